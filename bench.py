@@ -1,0 +1,166 @@
+"""Benchmark: voxels/s of the full gradient-domain pass (anisotropic diffusion
+of the stack, Eq. (1), then the per-slice screened Poisson, Eq. (2)), each
+solved to 1e-6 canonical relative residual on one MI355X.
+
+One step = AD + SP of the whole stack, inputs already resident in HBM.
+Prints one JSON line (rank 0).  The dominant kernel is the finest-level
+red-black relaxation; its HIP-event time inside the timed steps gives the
+achieved algorithmic HBM bandwidth (read x and b, write x per voxel).
+The CPU baseline is the FP64 oracle (conjugate gradients on the same
+systems) timed on the host on a crop of the same stack.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+WORKLOADS = {
+    # name: (spec key, storage, fp64_refine, description)
+    "stack1k": ("stack1k", "f32", 0, "1024x1024x128 stack, FP32 storage + arithmetic, plain V-cycles"),
+    "stack4k-f16": ("stack4k", "f16", 1, "4096x4096x256 stack, FP16 storage, FP32 relaxation, FP64 refinement"),
+    "stack4k-bf16": ("stack4k", "bf16", 1, "4096x4096x256 stack, BF16 storage, FP32 relaxation, FP64 refinement"),
+    "stack4k-f32": ("stack4k", "f32", 0, "4096x4096x256 stack, FP32 storage + arithmetic, plain V-cycles"),
+}
+BETA = (1.0, 1.0, 4.0)
+ALPHA = 0.01
+TOL = 1e-6
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="stack1k", choices=sorted(WORKLOADS))
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-crop", default="32,128,128", help="nz,ny,nx of the oracle's crop")
+    p.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                          "profiles", "traffic.json"))
+    return p.parse_args()
+
+
+def cpu_baseline(I0_host, crop):
+    """The FP64 oracle (CG on the AD system, then CG on the SP system) on a
+    crop of the same stack, solved as its own problem."""
+    from oracle import solvers
+
+    nz, ny, nx = crop
+    sub = np.ascontiguousarray(I0_host[:nz, :ny, :nx], dtype=np.float64)
+    t0 = time.perf_counter()
+    I1 = solvers.ad_solve(sub, BETA, method="cg", rtol=TOL)
+    solvers.sp_solve(sub, I1, ALPHA, method="cg", rtol=TOL)
+    dt = time.perf_counter() - t0
+    return {
+        "value": sub.size / dt,
+        "unit": "voxels/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"crop [0:{nz},0:{ny},0:{nx}] of the same stack ({sub.size} voxels), AD then SP by "
+                  f"plain conjugate gradients to {TOL:g}, numpy FP64 (single-threaded elementwise), {dt:.1f} s",
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1310_0041_amd as gd
+    import synth
+
+    gd.load()
+    spec_key, storage, refine, desc = WORKLOADS[a.workload]
+    spec = synth.CONFIGS[spec_key]
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[storage]
+    sdt = {"f32": gd.F32, "f16": gd.F16, "bf16": gd.BF16}[storage]
+    dev = torch.device("cuda:0")
+
+    t0 = time.perf_counter()
+    I0 = synth.make_stack(spec, device=dev, dtype=tdt)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    nvox = I0.numel()
+    out_dtype = torch.float32 if storage == "f32" else tdt
+    opts = dict(storage=sdt, fp64_refine=refine, rel_tol=TOL)
+
+    def step(timing):
+        I1, r1 = gd.smooth_z(I0, BETA, out_dtype=out_dtype, timing=timing, **opts)
+        I2, r2, per = gd.screened_poisson_stack(I0, I1.to(I0.dtype), ALPHA, timing=timing, **opts)
+        return r1, r2
+
+    for _ in range(a.warmup):
+        step(0)
+    torch.cuda.synchronize()
+    gd.reset_kernel_time()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(a.steps):
+        reps.append(step(1))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    ms, launches, bytes_per = gd.kernel_time()
+    # the timed launches mix the AD stack and the SP slices; both finest
+    # levels have the same voxel count and storage, so the same bytes
+    avg_ms = ms / max(launches, 1)
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+
+    traffic = None
+    if os.path.exists(a.traffic_json):
+        try:
+            t = json.load(open(a.traffic_json))
+            if t.get("workload") == a.workload:
+                traffic = t.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    r1, r2 = reps[-1]
+    line = {
+        "metric": "voxels/s to 1e-6 rel. residual (AD + per-slice SP)",
+        "value": nvox / dt,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16+f64", "bf16": "bf16+f64"}[storage],
+        "data": "synthetic",
+        "config": {
+            "workload": f"{a.workload}: {desc}; beta=(1,1,4), alpha={ALPHA}, Neumann, tol {TOL:g}",
+            "nx": spec.nx, "ny": spec.ny, "nz": spec.nz, "voxels": nvox,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_rb_sweep (finest level)",
+            "launches": launches,
+            "avg_launch_ms": avg_ms,
+            "algorithmic_bytes_per_launch": bytes_per,
+        },
+        "ad": {"cycles": r1["cycles"], "refine_steps": r1["refine_steps"], "rel_residual": r1["rel_residual"],
+               "levels": r1["levels"]},
+        "sp": {"cycles": r2["cycles"], "refine_steps": r2["refine_steps"], "rel_residual": r2["rel_residual"]},
+        "generate_s": gen_s,
+    }
+    if not a.no_cpu_baseline:
+        crop = tuple(int(v) for v in a.cpu_crop.split(","))
+        line["cpu_baseline"] = cpu_baseline(I0[: crop[0], : crop[1], : crop[2]].double().cpu().numpy(), crop)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * gd.h -- C ABI of the MI355X (gfx950) gradient-domain stack solver.
+ *
+ * Solves the screened anisotropic Poisson systems of Kazhdan et al.,
+ * "Gradient-Domain Processing for Large EM Image Stacks":
+ *
+ *   general (Sec. 4):   (alpha - div W grad) x = alpha V - div W G,
+ *                       W = Diag(beta_x, beta_y, beta_z)
+ *   anisotropic diffusion, Eq. (1) (Sec. 3.1.1):
+ *                       alpha = 0, G = (dI0/dx, dI0/dy, 0)
+ *   per-slice screened Poisson, Eq. (2) (Sec. 3.1.2):
+ *                       W = Diag(beta_x, beta_y, 0), V = I1, G = grad_xy I0
+ *
+ * with the 7-point ("Constant", Sec. 4.2) discretisation on a regular voxel
+ * grid of unit spacing and natural (Neumann) boundaries: the operator is
+ * alpha*Id + sum_a beta_a * L_a, L_a the 3-point second difference along a
+ * with no neighbours outside the grid.  The solver is multigrid (Sec. 4.1):
+ * red-black Gauss-Seidel, residual restriction, a 1-cell coarsest level and
+ * prolongation of the correction, all on the GPU.
+ *
+ * Conventions (every entry point):
+ *  - Volumes are contiguous [nz][ny][nx] arrays, x fastest, unless a slice
+ *    descriptor gives an offset and row pitch.  Sizes are int64.
+ *  - Data pointers are DEVICE pointers owned by the caller; the library never
+ *    frees them.  Outputs must not alias inputs.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call
+ *    enqueues its work on `stream` and returns after the result is complete
+ *    on that stream (residual norms are read back to the host).
+ *  - Workspace (multigrid levels, scratch) is allocated by the library with
+ *    hipMalloc and cached per problem shape until gd_release_workspace().
+ *  - No C++ exception crosses the ABI.  Every call returns a gd_status; on a
+ *    status other than GD_OK, gd_last_error() gives a message (thread-local).
+ *  - A solve that does not reach opts->rel_tol within opts->max_cycles still
+ *    writes its best iterate and returns GD_ERR_NOT_CONVERGED.  A NaN or Inf
+ *    residual norm returns GD_ERR_NUMERIC.
+ */
+#ifndef GD_H
+#define GD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { GD_F64 = 0, GD_F32 = 1, GD_F16 = 2, GD_BF16 = 3 } gd_dtype;
+
+typedef enum {
+  GD_OK = 0,
+  GD_ERR_INVALID = -1,        /* bad argument (null pointer, size, weight, dtype) */
+  GD_ERR_NOMEM = -2,          /* device allocation failed */
+  GD_ERR_HIP = -3,            /* a HIP runtime call or kernel launch failed */
+  GD_ERR_NOT_CONVERGED = -4,  /* tolerance not reached within max_cycles */
+  GD_ERR_NUMERIC = -5,        /* NaN/Inf in a residual norm */
+  GD_ERR_UNSUPPORTED = -6     /* valid request this build does not implement */
+} gd_status;
+
+/* Solver options.  Obtain defaults with gd_default_opts() and edit. */
+typedef struct {
+  double rel_tol;       /* stop when ||b - A x||_2 / ||b||_2 <= rel_tol (canonical
+                           system, x0 = 0 convention of the Table 1 caption)   */
+  int max_cycles;       /* V-cycles (plain) or refinement steps (mixed)        */
+  int pre_smooth;       /* red-black GS sweeps before restriction              */
+  int post_smooth;      /* red-black GS sweeps after prolongation              */
+  gd_dtype storage;     /* storage of the multigrid arrays: F64/F32 (plain) or
+                           F16/BF16/F32 (with fp64_refine)                      */
+  int fp64_refine;      /* 1: FP64 outer iterative refinement around V-cycles
+                           in `storage`; 0: plain V-cycles in `storage`        */
+  int inner_cycles;     /* V-cycles per refinement step (fp64_refine = 1)      */
+  int prolong;          /* 0: cell-centred trilinear, 1: piecewise constant    */
+  int timing;           /* 1: time the finest-level relaxation launches with
+                           HIP events (gd_get_kernel_time)                     */
+} gd_solve_opts;
+
+/* Filled by the solve calls when the pointer is non-NULL. */
+typedef struct {
+  int cycles;             /* V-cycles run (all refinement steps included)       */
+  int refine_steps;       /* FP64 refinement steps (0 for plain solves)         */
+  double rel_residual;    /* final canonical relative residual, FP64 on the GPU */
+  double b_norm;          /* ||b||_2 of the canonical system                    */
+  double seconds;         /* wall time of the call, host clock                  */
+  int levels;             /* multigrid levels (finest = level 0)                */
+} gd_solve_report;
+
+/* One slice of a batched screened-Poisson call (Eq. (2) per slice). */
+typedef struct {
+  int64_t offset;  /* element offset of pixel (0,0) in the I0/I1/I2 arrays */
+  int32_t nx, ny;  /* slice width and height                               */
+  int32_t pitch;   /* elements between rows (>= nx)                        */
+  float alpha;     /* screening weight of this slice (> 0)                 */
+} gd_slice_desc;
+
+void gd_default_opts(gd_solve_opts* opts);
+const char* gd_last_error(void);
+const char* gd_version(void);
+
+/* Anisotropic diffusion of a whole stack, Eq. (1) (Sec. 3.1.1):
+ *   (beta_x L_x + beta_y L_y + beta_z L_z) I1 = (beta_x L_x + beta_y L_y) I0
+ * with the gauge mean(I1) = mean(I0) (the zero frequency keeps gain 1).
+ * I0: nz*ny*nx values of in_t; I1: same count of out_t.  beta_x, beta_y >= 0,
+ * beta_z > 0.  The plain path stores the correction I1 - I0 in opts->storage
+ * (F32/F64) and iterates to rel_tol; with fp64_refine the iterate is FP64
+ * and the V-cycles run in opts->storage (F16/BF16/F32). */
+gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
+                      int64_t nx, int64_t ny, int64_t nz,
+                      double beta_x, double beta_y, double beta_z,
+                      const gd_solve_opts* opts, gd_solve_report* rep, void* stream);
+
+/* Per-slice screened Poisson, Eq. (2) (Sec. 3.1.2), for a batch of
+ * independent 2-D slices of any sizes:
+ *   (alpha_i + beta_x L_x + beta_y L_y) I2_i = alpha_i I1_i + (beta_x L_x + beta_y L_y) I0_i.
+ * I0, I1, I2 share dtype t and the slice layout `slices` (host array of
+ * nslices descriptors; slices must not overlap).  Every slice is iterated
+ * until its own relative residual <= rel_tol.  per_slice (host array of
+ * nslices, or NULL) receives each slice's final report; rep (or NULL) the
+ * batch summary with rel_residual = the largest slice residual. */
+gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, gd_dtype t,
+                                     const gd_slice_desc* slices, int64_t nslices,
+                                     double beta_x, double beta_y,
+                                     const gd_solve_opts* opts, gd_solve_report* rep,
+                                     gd_solve_report* per_slice, void* stream);
+
+/* ---- general system (Sec. 4) through an explicit hierarchy ---------------- */
+typedef struct gd_hierarchy gd_hierarchy;
+
+/* Multigrid levels for (alpha + sum_a beta_a L_a) on an nx*ny*nz grid, arrays
+ * in `storage` (F64/F32/F16/BF16, arithmetic in FP32, FP64 for F64).
+ * alpha >= 0, beta_a >= 0, not all zero. */
+gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t nz,
+                              double alpha, double beta_x, double beta_y, double beta_z,
+                              gd_dtype storage, const gd_solve_opts* opts, void* stream);
+gd_status gd_hierarchy_destroy(gd_hierarchy* h);
+/* Number of levels and the size of level `level` (finest = 0). */
+gd_status gd_hierarchy_info(const gd_hierarchy* h, int level, int* nlevels,
+                            int64_t dims[3], double coef[4] /* alpha, w_x, w_y, w_z */);
+
+/* b = alpha V + sum_a beta_a D_a^T G_a (the discrete alpha V - div W G).
+ * V: nx*ny*nz values (ignored when alpha == 0; may be NULL then).
+ * Gx/Gy/Gz: face fields of the volume's shape; G_a[v] is the target of the
+ * face between v and v + e_a, entries on the last plane along a are ignored;
+ * NULL = zero field.  All in the hierarchy's storage dtype; b likewise. */
+gd_status gd_rhs_general(gd_hierarchy* h, const void* V, const void* Gx, const void* Gy,
+                         const void* Gz, void* b, void* stream);
+
+/* ncycles V-cycles on A x = b (x in/out, b in; both in the storage dtype).
+ * rel_residual_out (may be NULL) receives ||b - A x|| / ||b|| after the
+ * last cycle (FP64 accumulation).  ncycles <= 0 only evaluates it. */
+gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles,
+                    double* rel_residual_out, void* stream);
+
+/* ---- single multigrid steps (Sec. 4.1), for kernel-level checks ------------
+ * All arrays are nx*ny*nz of dtype s; the operator is
+ * alpha*Id + w_x L_x + w_y L_y + w_z L_z (one level's coefficients). */
+
+/* One red-black Gauss-Seidel sweep: red voxels ((i+j+k) even) then black,
+ * each set to zero its own residual.  x_out must not alias x_in. */
+gd_status gd_rb_sweep(const void* x_in, void* x_out, const void* b, gd_dtype s,
+                      int64_t nx, int64_t ny, int64_t nz,
+                      double alpha, double w_x, double w_y, double w_z, void* stream);
+
+/* r = b - A x restricted to the coarse grid of size ceil(n_a / c_a), each
+ * coarse cell the sum of its children (c_a in {1, 2}).  norm2_out (host, may
+ * be NULL) receives sum r^2 over the fine grid (FP64). */
+gd_status gd_residual_restrict(const void* x, const void* b, void* b_coarse, gd_dtype s,
+                               int64_t nx, int64_t ny, int64_t nz,
+                               int c_x, int c_y, int c_z,
+                               double alpha, double w_x, double w_y, double w_z,
+                               double* norm2_out, void* stream);
+
+/* x += P e: up-sample a coarse correction (prolong 0: cell-centred
+ * trilinear, 1: piecewise constant) onto the fine grid and add it. */
+gd_status gd_prolong_add(const void* e_coarse, void* x, gd_dtype s,
+                         int64_t nx, int64_t ny, int64_t nz,
+                         int c_x, int c_y, int c_z, int prolong, void* stream);
+
+/* ---- instrumentation -------------------------------------------------------- */
+/* Total HIP-event time (ms) and launch count of the finest-level relaxation
+ * kernel since the last reset, recorded by solves run with opts->timing = 1.
+ * bytes_per_launch: algorithmic bytes of the last timed launch (read x and b,
+ * write x: 3 * storage bytes per voxel). */
+gd_status gd_get_kernel_time(double* total_ms, int64_t* launches, double* bytes_per_launch);
+void gd_reset_kernel_time(void);
+
+/* Free every cached workspace (all devices). */
+gd_status gd_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GD_H */

@@ -1,0 +1,319 @@
+"""Python binding of the gfx950 gradient-domain stack solver (``libgd.so``).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch provides device memory and the current stream.  The binding refuses
+to run when the HIP library is missing; there is no CPU fallback.
+
+Entry points follow ``include/gd.h``:
+
+* :func:`smooth_z`                  anisotropic diffusion of a stack, Eq. (1)
+* :func:`screened_poisson_slices`   per-slice screened Poisson, Eq. (2),
+                                    for a batch of slices of any sizes
+* :func:`screened_poisson_stack`    the same for the slices of one stack
+* :class:`Hierarchy`                the general Sec. 4 system: rhs + V-cycles
+* :func:`rb_sweep`, :func:`residual_restrict`, :func:`prolong_add`
+                                    single multigrid steps (Sec. 4.1)
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgd.so")
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_NOT_CONVERGED, ERR_NUMERIC, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+
+class GDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gd status {status}: {msg}")
+        self.status = status
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("rel_tol", ctypes.c_double),
+        ("max_cycles", ctypes.c_int),
+        ("pre_smooth", ctypes.c_int),
+        ("post_smooth", ctypes.c_int),
+        ("storage", ctypes.c_int),
+        ("fp64_refine", ctypes.c_int),
+        ("inner_cycles", ctypes.c_int),
+        ("prolong", ctypes.c_int),
+        ("timing", ctypes.c_int),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("cycles", ctypes.c_int),
+        ("refine_steps", ctypes.c_int),
+        ("rel_residual", ctypes.c_double),
+        ("b_norm", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("levels", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SliceDesc(ctypes.Structure):
+    _fields_ = [
+        ("offset", ctypes.c_int64),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("pitch", ctypes.c_int32),
+        ("alpha", ctypes.c_float),
+    ]
+
+
+_lib = None
+_vp, _i64, _d, _i = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+
+_SIGS = {
+    "gd_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
+    "gd_last_error": (ctypes.c_char_p, []),
+    "gd_version": (ctypes.c_char_p, []),
+    "gd_smooth_z": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, ctypes.POINTER(SolveOpts),
+                         ctypes.POINTER(Report), _vp]),
+    "gd_screened_poisson_slices": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(SliceDesc), _i64, _d, _d,
+                                        ctypes.POINTER(SolveOpts), ctypes.POINTER(Report),
+                                        ctypes.POINTER(Report), _vp]),
+    "gd_hierarchy_create": (_i, [ctypes.POINTER(_vp), _i64, _i64, _i64, _d, _d, _d, _d, _i,
+                                 ctypes.POINTER(SolveOpts), _vp]),
+    "gd_hierarchy_destroy": (_i, [_vp]),
+    "gd_hierarchy_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
+    "gd_rhs_general": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gd_vcycle": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
+    "gd_rb_sweep": (_i, [_vp, _vp, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _d, _vp]),
+    "gd_residual_restrict": (_i, [_vp, _vp, _vp, _i, _i64, _i64, _i64, _i, _i, _i, _d, _d, _d, _d,
+                                  ctypes.POINTER(_d), _vp]),
+    "gd_prolong_add": (_i, [_vp, _vp, _i, _i64, _i64, _i64, _i, _i, _i, _i, _vp]),
+    "gd_get_kernel_time": (_i, [ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
+    "gd_reset_kernel_time": (None, []),
+    "gd_release_workspace": (_i, []),
+}
+
+
+def exported_symbols():
+    """Names every C-ABI entry point must export (as declared in gd.h)."""
+    return sorted(_SIGS)
+
+
+def load(path=LIB_PATH):
+    """Load libgd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run python -m paper_1310_0041_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, allow=()):
+    if status != OK and status not in allow:
+        raise GDError(status, _lib.gd_last_error().decode())
+    return status
+
+
+def default_opts(**kw):
+    o = SolveOpts()
+    load().gd_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def gd_dtype(t):
+    torch = _torch()
+    m = {torch.float64: F64, torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+    if t not in m:
+        raise TypeError(f"unsupported dtype {t}")
+    return m[t]
+
+
+def torch_dtype(code):
+    torch = _torch()
+    return {F64: torch.float64, F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}[code]
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def smooth_z(I0, beta=(1.0, 1.0, 4.0), out_dtype=None, opts=None, check=True, **kw):
+    """Anisotropic diffusion of the [nz][ny][nx] stack I0 (Eq. (1)).
+    Returns (I1, report dict)."""
+    lib = load()
+    nz, ny, nx = I0.shape
+    out = _torch().empty_like(I0, dtype=out_dtype or I0.dtype)
+    o = opts or default_opts(**kw)
+    rep = Report()
+    st = lib.gd_smooth_z(_ptr(I0), gd_dtype(I0.dtype), _ptr(out), gd_dtype(out.dtype), nx, ny, nz,
+                         float(beta[0]), float(beta[1]), float(beta[2]), ctypes.byref(o), ctypes.byref(rep),
+                         _stream())
+    if check:
+        _check(st)
+    return out, dict(rep.as_dict(), status=st)
+
+
+def make_slice_descs(offsets, nx, ny, alpha, pitch=None):
+    n = len(offsets)
+    arr = (SliceDesc * n)()
+    nx = np.broadcast_to(np.asarray(nx), (n,))
+    ny = np.broadcast_to(np.asarray(ny), (n,))
+    alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (n,))
+    pitch = nx if pitch is None else np.broadcast_to(np.asarray(pitch), (n,))
+    for i in range(n):
+        arr[i] = SliceDesc(int(offsets[i]), int(nx[i]), int(ny[i]), int(pitch[i]), float(alpha[i]))
+    return arr
+
+
+def screened_poisson_slices(I0, I1, descs, beta_xy=(1.0, 1.0), opts=None, out=None, check=True, **kw):
+    """Per-slice screened Poisson (Eq. (2)) for a batch of slices described by
+    ``descs`` (from :func:`make_slice_descs`).  Returns (I2, report, per-slice reports)."""
+    lib = load()
+    if I0.dtype != I1.dtype or I0.shape != I1.shape:
+        raise ValueError("I0 and I1 must share dtype and shape")
+    out = _torch().empty_like(I0) if out is None else out
+    n = len(descs)
+    o = opts or default_opts(**kw)
+    rep = Report()
+    per = (Report * n)()
+    st = lib.gd_screened_poisson_slices(_ptr(I0), _ptr(I1), _ptr(out), gd_dtype(I0.dtype), descs, n,
+                                        float(beta_xy[0]), float(beta_xy[1]), ctypes.byref(o),
+                                        ctypes.byref(rep), per, _stream())
+    if check:
+        _check(st)
+    return out, dict(rep.as_dict(), status=st), [p.as_dict() for p in per]
+
+
+def screened_poisson_stack(I0, I1, alpha=0.01, beta_xy=(1.0, 1.0), opts=None, check=True, **kw):
+    """Eq. (2) for every slice of a [nz][ny][nx] stack."""
+    nz, ny, nx = I0.shape
+    descs = make_slice_descs(np.arange(nz) * nx * ny, nx, ny, alpha)
+    return screened_poisson_slices(I0, I1, descs, beta_xy, opts=opts, check=check, **kw)
+
+
+class Hierarchy:
+    """Multigrid hierarchy of the general Sec. 4 system
+    (alpha + sum_a beta_a L_a) x = alpha V + sum_a beta_a D_a^T G_a."""
+
+    def __init__(self, shape, alpha, beta, dtype, opts=None, **kw):
+        lib = load()
+        nz, ny, nx = shape
+        self.shape = tuple(shape)
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        o = opts or default_opts(**kw)
+        _check(lib.gd_hierarchy_create(ctypes.byref(self._h), nx, ny, nz, float(alpha), float(beta[0]),
+                                       float(beta[1]), float(beta[2]), gd_dtype(dtype), ctypes.byref(o),
+                                       _stream()))
+
+    def info(self, level=-1):
+        n = ctypes.c_int()
+        dims = (ctypes.c_int64 * 3)()
+        coef = (ctypes.c_double * 4)()
+        if level < 0:
+            _check(_lib.gd_hierarchy_info(self._h, -1, ctypes.byref(n), None, None))
+            return n.value
+        _check(_lib.gd_hierarchy_info(self._h, level, ctypes.byref(n), dims, coef))
+        return (dims[2], dims[1], dims[0]), tuple(coef)
+
+    def rhs(self, V=None, Gx=None, Gy=None, Gz=None):
+        b = _torch().empty(self.shape, dtype=self.dtype, device="cuda")
+        _check(_lib.gd_rhs_general(self._h, _ptr(V), _ptr(Gx), _ptr(Gy), _ptr(Gz), _ptr(b), _stream()))
+        return b
+
+    def vcycle(self, x, b, ncycles=1):
+        rr = ctypes.c_double()
+        _check(_lib.gd_vcycle(self._h, _ptr(x), _ptr(b), int(ncycles), ctypes.byref(rr), _stream()))
+        return rr.value
+
+    def close(self):
+        if self._h:
+            _lib.gd_hierarchy_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rb_sweep(x, b, alpha, w):
+    """One red-black Gauss-Seidel sweep (returns the new x)."""
+    lib = load()
+    nz, ny, nx = x.shape
+    out = _torch().empty_like(x)
+    _check(lib.gd_rb_sweep(_ptr(x), _ptr(out), _ptr(b), gd_dtype(x.dtype), nx, ny, nz, float(alpha),
+                           float(w[0]), float(w[1]), float(w[2]), _stream()))
+    return out
+
+
+def residual_restrict(x, b, alpha, w, c):
+    """Residual restricted by summing children; returns (b_coarse, sum r^2)."""
+    lib = load()
+    nz, ny, nx = x.shape
+    cs = (-(-nz // c[2]), -(-ny // c[1]), -(-nx // c[0]))
+    bc = _torch().empty(cs, dtype=x.dtype, device=x.device)
+    n2 = ctypes.c_double()
+    _check(lib.gd_residual_restrict(_ptr(x), _ptr(b), _ptr(bc), gd_dtype(x.dtype), nx, ny, nz, int(c[0]),
+                                    int(c[1]), int(c[2]), float(alpha), float(w[0]), float(w[1]), float(w[2]),
+                                    ctypes.byref(n2), _stream()))
+    return bc, n2.value
+
+
+def prolong_add(e_coarse, x, c, mode=0):
+    """x += P e_coarse in place (mode 0 trilinear, 1 constant); returns x."""
+    lib = load()
+    nz, ny, nx = x.shape
+    _check(lib.gd_prolong_add(_ptr(e_coarse), _ptr(x), gd_dtype(x.dtype), nx, ny, nz, int(c[0]), int(c[1]),
+                              int(c[2]), int(mode), _stream()))
+    return x
+
+
+def kernel_time():
+    lib = load()
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    by = ctypes.c_double()
+    lib.gd_get_kernel_time(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by))
+    return ms.value, n.value, by.value
+
+
+def reset_kernel_time():
+    load().gd_reset_kernel_time()
+
+
+def release_workspace():
+    _check(load().gd_release_workspace())

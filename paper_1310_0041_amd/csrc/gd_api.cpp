@@ -1,0 +1,960 @@
+// Host orchestration and C ABI of the gradient-domain multigrid solver
+// (Kazhdan et al., "Gradient-Domain Processing for Large EM Image Stacks").
+//
+// The hierarchy: a level holds one grid (3-D stack, anisotropic diffusion)
+// or many (independent 2-D slices, screened Poisson).  Each grid is coarsened
+// on its own: an axis is halved when it still has more than one cell and its
+// coupling weight is at least half of the strongest remaining one, so a
+// strongly coupled axis (beta_z = 4 > beta_x = beta_y) is coarsened first and
+// the coarse operators become isotropic.  A coarse operator re-discretises
+// the fine one on the doubled cells: with cell-volume ratio V = prod f_a,
+// alpha_c = V alpha and w_a,c = V / f_a^2 * w_a (face area over length).
+// Grids end at one cell, whose relaxation is an exact solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gd.h"
+#include "gd_launch.h"
+
+namespace gd {
+
+static thread_local std::string t_err;
+
+static gd_status fail(gd_status s, const std::string& msg) {
+  t_err = msg;
+  return s;
+}
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIP_TRY(call)                                         \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) throw HipFail{e_, #call};           \
+  } while (0)
+
+static size_t dsize(gd_dtype t) {
+  switch (t) {
+    case GD_F64: return 8;
+    case GD_F32: return 4;
+    case GD_F16: return 2;
+    case GD_BF16: return 2;
+  }
+  return 0;
+}
+
+static bool valid_dtype(int t) { return t >= GD_F64 && t <= GD_BF16; }
+
+// ------------------------------------------------------------- timing
+
+struct KernelTimer {
+  std::mutex mu;
+  double total_ms = 0.0;
+  int64_t launches = 0;
+  double bytes = 0.0;
+};
+static KernelTimer g_timer;
+
+// --------------------------------------------------------------- hierarchy
+
+struct GridSpec {  // finest-level grid as the caller describes it
+  int64_t nx, ny, nz;
+  double alpha, wx, wy, wz;
+  int64_t ioff, ipy, ipz;
+};
+
+struct Tab {  // launch geometry of one kernel family on one level
+  int64_t* d_b0 = nullptr;
+  std::vector<int64_t> h_b0;
+  int zlen = 1;
+  Geom geom(const GridDesc* d_grids, int ngrids) const {
+    Geom g;
+    g.grids = d_grids;
+    g.block0 = d_b0;
+    g.ngrids = ngrids;
+    g.nblocks = h_b0.back();
+    g.zlen = zlen;
+    return g;
+  }
+};
+
+struct Level {
+  std::vector<GridDesc> h;
+  GridDesc* d = nullptr;
+  int64_t total = 0;
+  Tab sw, ew, rc;  // relaxation tiles, per-voxel tiles, child-cell tiles
+  void* x = nullptr;
+  void* xt = nullptr;
+  void* b = nullptr;
+};
+
+struct Hier {
+  int device = 0;
+  gd_dtype s = GD_F32;
+  int ngrids = 0;
+  std::vector<Level> lv;
+  std::vector<void*> allocs;
+  double* partials = nullptr;
+  double* dred = nullptr;    // ngrids * 2
+  double* dscal = nullptr;   // ngrids * 4: scale, inv_scale, shift, spare
+  double* hpin = nullptr;    // pinned host, ngrids * 4
+  double* x64 = nullptr;     // FP64 iterate of the refinement path
+  std::vector<int64_t> cells;  // finest cells per grid
+
+  ~Hier() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (hpin) (void)hipHostFree(hpin);
+  }
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+    allocs.push_back(p);
+    return p;
+  }
+  Geom g_sw(int l) const { return lv[l].sw.geom(lv[l].d, ngrids); }
+  Geom g_ew(int l) const { return lv[l].ew.geom(lv[l].d, ngrids); }
+  Geom g_rc(int l) const { return lv[l].rc.geom(lv[l].d, ngrids); }
+};
+
+static void coarsen_factors(const GridDesc& g, int f[3]) {
+  const int64_t n[3] = {g.nx, g.ny, g.nz};
+  const double w[3] = {g.wx, g.wy, g.wz};
+  double wmax = 0.0;
+  for (int a = 0; a < 3; ++a)
+    if (n[a] > 1 && w[a] > 0.0) wmax = std::max(wmax, w[a]);
+  for (int a = 0; a < 3; ++a) f[a] = (n[a] > 1 && w[a] > 0.0 && w[a] >= 0.5 * wmax) ? 2 : 1;
+}
+
+static void build_tab(Tab& t, const std::vector<GridDesc>& grids, int TX, int TY, bool child, int64_t target) {
+  int64_t nzmax = 1, tiles_sum = 0;
+  for (const auto& g : grids) {
+    const int64_t nx = child ? g.cnx : g.nx, ny = child ? g.cny : g.ny, nz = child ? g.cnz : g.nz;
+    nzmax = std::max(nzmax, nz);
+    tiles_sum += ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
+  }
+  int64_t chunks = std::max<int64_t>(1, (target + tiles_sum - 1) / std::max<int64_t>(tiles_sum, 1));
+  chunks = std::min(chunks, nzmax);
+  t.zlen = (int)((nzmax + chunks - 1) / chunks);
+  t.h_b0.assign(1, 0);
+  for (const auto& g : grids) {
+    const int64_t nx = child ? g.cnx : g.nx, ny = child ? g.cny : g.ny, nz = child ? g.cnz : g.nz;
+    const int64_t nb = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + t.zlen - 1) / t.zlen);
+    t.h_b0.push_back(t.h_b0.back() + nb);
+  }
+}
+
+static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
+                                        hipStream_t st) {
+  auto H = std::make_unique<Hier>();
+  HIP_TRY(hipGetDevice(&H->device));
+  H->s = s;
+  H->ngrids = (int)specs.size();
+  // level descriptors
+  std::vector<GridDesc> cur(specs.size());
+  for (size_t i = 0; i < specs.size(); ++i) {
+    GridDesc g{};
+    g.nx = (int32_t)specs[i].nx;
+    g.ny = (int32_t)specs[i].ny;
+    g.nz = (int32_t)specs[i].nz;
+    g.alpha = specs[i].alpha;
+    g.wx = specs[i].wx;
+    g.wy = specs[i].wy;
+    g.wz = specs[i].wz;
+    g.ioff = specs[i].ioff;
+    g.ipy = specs[i].ipy;
+    g.ipz = specs[i].ipz;
+    cur[i] = g;
+    H->cells.push_back(specs[i].nx * specs[i].ny * specs[i].nz);
+  }
+  for (;;) {
+    Level L;
+    int64_t off = 0;
+    bool more = false;
+    for (auto& g : cur) {
+      g.off = off;
+      off += (int64_t)g.nx * g.ny * g.nz;
+      int f[3];
+      coarsen_factors(g, f);
+      g.fx = f[0]; g.fy = f[1]; g.fz = f[2];
+      g.cnx = (g.nx + f[0] - 1) / f[0];
+      g.cny = (g.ny + f[1] - 1) / f[1];
+      g.cnz = (g.nz + f[2] - 1) / f[2];
+      if (f[0] * f[1] * f[2] > 1) more = true;
+    }
+    L.h = cur;
+    L.total = off;
+    H->lv.push_back(std::move(L));
+    if (!more) break;
+    std::vector<GridDesc> nxt(cur.size());
+    int64_t coff = 0;
+    for (size_t i = 0; i < cur.size(); ++i) {
+      GridDesc& g = H->lv.back().h[i];
+      g.coff = coff;
+      GridDesc c{};
+      c.nx = g.cnx; c.ny = g.cny; c.nz = g.cnz;
+      const double V = (double)g.fx * g.fy * g.fz;
+      c.alpha = g.alpha * V;
+      c.wx = g.wx * V / (g.fx * g.fx);
+      c.wy = g.wy * V / (g.fy * g.fy);
+      c.wz = g.wz * V / (g.fz * g.fz);
+      nxt[i] = c;
+      coff += (int64_t)c.nx * c.ny * c.nz;
+    }
+    cur = nxt;
+  }
+  // last level: no child
+  for (auto& g : H->lv.back().h) { g.cnx = g.nx; g.cny = g.ny; g.cnz = g.nz; g.fx = g.fy = g.fz = 1; g.coff = 0; }
+
+  // launch tables, device copies, arrays
+  const size_t es = dsize(s);
+  int64_t maxblocks = 1;
+  std::vector<char> stage;
+  for (auto& L : H->lv) {
+    build_tab(L.sw, L.h, SW_TX, SW_TY, false, 2048);
+    build_tab(L.ew, L.h, EW_TX, EW_TY, false, 8192);
+    build_tab(L.rc, L.h, EW_TX, EW_TY, true, 8192);
+    maxblocks = std::max({maxblocks, L.sw.h_b0.back(), L.ew.h_b0.back(), L.rc.h_b0.back()});
+    const size_t nb = (size_t)H->ngrids + 1;
+    const size_t bytes = L.h.size() * sizeof(GridDesc) + 3 * nb * sizeof(int64_t);
+    char* dev = (char*)H->alloc(bytes);
+    L.d = (GridDesc*)dev;
+    L.sw.d_b0 = (int64_t*)(dev + L.h.size() * sizeof(GridDesc));
+    L.ew.d_b0 = L.sw.d_b0 + nb;
+    L.rc.d_b0 = L.ew.d_b0 + nb;
+    stage.resize(bytes);
+    std::memcpy(stage.data(), L.h.data(), L.h.size() * sizeof(GridDesc));
+    std::memcpy(stage.data() + L.h.size() * sizeof(GridDesc), L.sw.h_b0.data(), nb * sizeof(int64_t));
+    std::memcpy(stage.data() + L.h.size() * sizeof(GridDesc) + nb * sizeof(int64_t), L.ew.h_b0.data(),
+                nb * sizeof(int64_t));
+    std::memcpy(stage.data() + L.h.size() * sizeof(GridDesc) + 2 * nb * sizeof(int64_t), L.rc.h_b0.data(),
+                nb * sizeof(int64_t));
+    HIP_TRY(hipMemcpy(dev, stage.data(), bytes, hipMemcpyHostToDevice));
+    L.x = H->alloc(L.total * es);
+    L.xt = H->alloc(L.total * es);
+    L.b = H->alloc(L.total * es);
+  }
+  H->partials = (double*)H->alloc(maxblocks * 2 * sizeof(double));
+  H->dred = (double*)H->alloc(H->ngrids * 2 * sizeof(double));
+  H->dscal = (double*)H->alloc(H->ngrids * 4 * sizeof(double));
+  HIP_TRY(hipHostMalloc((void**)&H->hpin, H->ngrids * 4 * sizeof(double), hipHostMallocDefault));
+  if (mixed) H->x64 = (double*)H->alloc(H->lv[0].total * sizeof(double));
+  (void)st;
+  return H;
+}
+
+// -------------------------------------------------------------- workspace
+
+static std::mutex g_cache_mu;
+static std::map<std::string, std::unique_ptr<Hier>> g_cache;
+
+static uint64_t fnv(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+static Hier* get_hier(const char* kind, const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
+                      hipStream_t st) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  // the descriptors minus the caller's I/O layout decide the hierarchy
+  std::vector<double> sig;
+  for (const auto& g : specs) {
+    sig.insert(sig.end(), {(double)g.nx, (double)g.ny, (double)g.nz, g.alpha, g.wx, g.wy, g.wz});
+  }
+  char key[256];
+  std::snprintf(key, sizeof key, "%s|d%d|s%d|m%d|n%zu|h%016llx", kind, dev, (int)s, (int)mixed, specs.size(),
+                (unsigned long long)fnv(sig.data(), sig.size() * sizeof(double)));
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(key);
+  if (it == g_cache.end()) {
+    it = g_cache.emplace(key, build_hier(specs, s, mixed, st)).first;
+  }
+  Hier* H = it->second.get();
+  // the caller's layout may differ between calls of the same shape
+  auto& L0 = H->lv[0];
+  bool changed = false;
+  for (size_t i = 0; i < specs.size(); ++i) {
+    if (L0.h[i].ioff != specs[i].ioff || L0.h[i].ipy != specs[i].ipy || L0.h[i].ipz != specs[i].ipz) {
+      L0.h[i].ioff = specs[i].ioff;
+      L0.h[i].ipy = specs[i].ipy;
+      L0.h[i].ipz = specs[i].ipz;
+      changed = true;
+    }
+  }
+  if (changed) {
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(L0.d, L0.h.data(), L0.h.size() * sizeof(GridDesc), hipMemcpyHostToDevice));
+  }
+  return H;
+}
+
+// --------------------------------------------------------------- V-cycle
+
+struct Cycler {
+  Hier& H;
+  hipStream_t st;
+  int pre, post, pmode;
+  bool timing;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t ev_used = 0;
+
+  Cycler(Hier& h, hipStream_t s, const gd_solve_opts& o)
+      : H(h), st(s), pre(o.pre_smooth), post(o.post_smooth), pmode(o.prolong), timing(o.timing != 0) {}
+  ~Cycler() {
+    for (auto& p : ev) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  }
+
+  void sweep(int l, const void* ec) {
+    Level& L = H.lv[l];
+    const bool t = timing && l == 0;
+    if (t) {
+      if (ev_used == ev.size()) {
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        ev.push_back({a, b});
+      }
+      HIP_TRY(hipEventRecord(ev[ev_used].first, st));
+    }
+    HIP_TRY(launch_rb_sweep(H.s, H.g_sw(l), L.x, L.xt, L.b, ec, pmode, st));
+    if (t) HIP_TRY(hipEventRecord(ev[ev_used++].second, st));
+    std::swap(L.x, L.xt);
+  }
+  void smooth(int l, int n, const void* ec = nullptr) {
+    for (int i = 0; i < n; ++i) sweep(l, i == 0 ? ec : nullptr);
+  }
+  // residual of level l restricted into level l + 1 (its x zeroed);
+  // with `norm`, per-grid sum r^2 lands in H.dred
+  void restrict_to(int l, bool norm) {
+    Level& L = H.lv[l];
+    Level& C = H.lv[l + 1];
+    HIP_TRY(launch_residual_restrict(H.s, H.g_rc(l), L.x, L.b, C.b, C.x, norm ? H.partials : nullptr, st));
+    if (norm) HIP_TRY(launch_reduce(H.partials, L.rc.d_b0, H.ngrids, 1, H.dred, st));
+  }
+  // coarse-grid correction of level l (levels l+1 .. bottom), then post-smoothing
+  void correct(int l) {
+    below(l + 1);
+    Level& C = H.lv[l + 1];
+    if (post > 0) {
+      smooth(l, post, C.x);  // prolongation fused into the first sweep
+    } else {
+      HIP_TRY(launch_prolong_add(H.s, H.g_ew(l), C.x, H.lv[l].x, pmode, st));
+    }
+  }
+  void below(int l) {
+    const int last = (int)H.lv.size() - 1;
+    if (l == last) {
+      smooth(l, 1);  // one-cell grids: one relaxation is the exact solve
+      return;
+    }
+    smooth(l, pre);
+    restrict_to(l, false);
+    correct(l);
+  }
+  void full(int l) {  // one V-cycle from level l
+    if (l == (int)H.lv.size() - 1) { smooth(l, 1); return; }
+    smooth(l, pre);
+    restrict_to(l, false);
+    correct(l);
+  }
+  // collect HIP-event times of finest-level sweeps (after a stream sync)
+  void harvest() {
+    if (!timing || ev_used == 0) return;
+    double tot = 0.0;
+    for (size_t i = 0; i < ev_used; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ev[i].first, ev[i].second));
+      tot += ms;
+    }
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    g_timer.total_ms += tot;
+    g_timer.launches += (int64_t)ev_used;
+    g_timer.bytes = 3.0 * (double)dsize(H.s) * (double)H.lv[0].total;
+    ev_used = 0;
+  }
+};
+
+static void read_dred(Hier& H, int ncomp, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(H.hpin, H.dred, H.ngrids * ncomp * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------- AD / SP solves
+
+struct Problem {
+  const void* I0;
+  const void* I1;  // SP value target (NULL for AD)
+  void* out;
+  gd_dtype tin, tout;
+  bool gauge;  // AD: mean(x) = mean(I0)
+};
+
+struct Outcome {
+  int cycles = 0, steps = 0;
+  std::vector<double> rel, bnorm;
+  bool converged = false, numeric = false;
+};
+
+// ||b|| of the canonical system per grid (and the correction-form rhs when b_out)
+static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero, std::vector<double>& bn,
+                            hipStream_t st) {
+  HIP_TRY(launch_rhs_corr(P.tin, H.s, H.g_ew(0), P.I0, P.I1, b_out, x_zero, H.partials, st));
+  HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, H.ngrids, 1, H.dred, st));
+  read_dred(H, 1, st);
+  bn.resize(H.ngrids);
+  for (int g = 0; g < H.ngrids; ++g) bn[g] = std::sqrt(H.hpin[g]);
+}
+
+static std::vector<double> canon_residual(Hier& H, const Problem& P, int mode, void* rout, hipStream_t st) {
+  HIP_TRY(launch_canon_residual(P.tin, H.s, mode, H.g_ew(0), P.I0, P.I1, H.lv[0].x, H.x64, rout, H.dscal + H.ngrids,
+                                H.partials, st));
+  HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, H.ngrids, 1, H.dred, st));
+  read_dred(H, 1, st);
+  std::vector<double> r(H.ngrids);
+  for (int g = 0; g < H.ngrids; ++g) r[g] = std::sqrt(H.hpin[g]);
+  return r;
+}
+
+static double denom(double bn) { return bn > 0.0 ? bn : 1.0; }
+
+static void finish(Hier& H, const Problem& P, int mode, hipStream_t st) {
+  const double* shift = nullptr;
+  if (P.gauge) {
+    HIP_TRY(launch_sum_shift(P.tin, H.s, mode, H.g_ew(0), P.I0, H.lv[0].x, H.x64, H.partials, st));
+    HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, H.ngrids, 1, H.dred, st));
+    read_dred(H, 1, st);
+    for (int g = 0; g < H.ngrids; ++g) H.hpin[g] = H.hpin[g] / (double)H.cells[g];
+    HIP_TRY(hipMemcpyAsync(H.dscal + 2 * H.ngrids, H.hpin, H.ngrids * sizeof(double), hipMemcpyHostToDevice, st));
+    shift = H.dscal + 2 * H.ngrids;
+  }
+  HIP_TRY(launch_finalize(P.tin, H.s, P.tout, mode, H.g_ew(0), P.I0, H.lv[0].x, H.x64, shift, P.out, st));
+  HIP_TRY(hipStreamSynchronize(st));
+}
+
+static bool all_below(const std::vector<double>& r, const std::vector<double>& bn, double tol, bool& bad) {
+  bool ok = true;
+  for (size_t g = 0; g < r.size(); ++g) {
+    if (!std::isfinite(r[g])) bad = true;
+    if (!(r[g] <= tol * denom(bn[g]))) ok = false;
+  }
+  return ok;
+}
+
+// Plain path: V-cycles on the correction E = x - I0 in the storage type.
+// The convergence test after each pre-smoothing uses the storage-precision
+// residual against half the tolerance; a pass is confirmed with the FP64
+// canonical residual of x = I0 + E before returning.  The storage precision
+// bounds how small the residual of a stored E can be (its rounding error
+// times the operator); when three successive cycles gain less than 30 %, the
+// solve stops there and reports the FP64 residual it reached.
+static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
+  Outcome R;
+  canonical_norms(H, P, H.lv[0].b, H.lv[0].x, R.bnorm, st);
+  Cycler cy(H, st, o);
+  const bool single = H.lv.size() == 1;
+  double inner = 0.5;
+  std::vector<double> rr(H.ngrids), best(H.ngrids, INFINITY);
+  int stall = 0;
+  for (;;) {
+    if (single) {
+      cy.smooth(0, 1);
+      R.cycles++;
+    } else {
+      cy.smooth(0, o.pre_smooth);
+    }
+    bool check_final = R.cycles >= o.max_cycles || single;
+    bool stop_after = check_final;
+    if (!single) {
+      cy.restrict_to(0, true);
+      read_dred(H, 1, st);
+      bool bad = false;
+      bool gained = false;
+      for (int g = 0; g < H.ngrids; ++g) {
+        rr[g] = std::sqrt(H.hpin[g]);
+        if (rr[g] < 0.7 * best[g]) gained = true;
+        best[g] = std::min(best[g], rr[g]);
+      }
+      if (all_below(rr, R.bnorm, inner * o.rel_tol, bad)) check_final = true;
+      if (bad) { R.numeric = true; break; }
+      stall = gained ? 0 : stall + 1;
+      if (stall >= 3) check_final = stop_after = true;
+    }
+    if (check_final) {
+      std::vector<double> c = canon_residual(H, P, 0, nullptr, st);
+      bool bad = false;
+      R.converged = all_below(c, R.bnorm, o.rel_tol, bad);
+      R.rel.resize(H.ngrids);
+      for (int g = 0; g < H.ngrids; ++g) R.rel[g] = c[g] / denom(R.bnorm[g]);
+      if (bad) { R.numeric = true; break; }
+      if (R.converged || stop_after) break;
+      inner *= 0.25;
+    }
+    cy.correct(0);
+    R.cycles++;
+  }
+  cy.harvest();
+  finish(H, P, 0, st);
+  cy.harvest();
+  return R;
+}
+
+// Mixed path: FP64 iterate x64; each refinement step solves A e = r / s for
+// the scaled FP64 residual (s = RMS of r per grid) with V-cycles in the
+// storage type, then x64 += s e.
+static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
+  Outcome R;
+  canonical_norms(H, P, nullptr, nullptr, R.bnorm, st);
+  HIP_TRY(launch_refine_init(P.tin, H.g_ew(0), P.I0, H.x64, st));
+  Cycler cy(H, st, o);
+  const size_t es = dsize(H.s);
+  for (;;) {
+    std::vector<double> r = canon_residual(H, P, 1, nullptr, st);
+    bool bad = false;
+    R.converged = all_below(r, R.bnorm, o.rel_tol, bad);
+    R.rel.resize(H.ngrids);
+    for (int g = 0; g < H.ngrids; ++g) R.rel[g] = r[g] / denom(R.bnorm[g]);
+    if (bad) { R.numeric = true; break; }
+    if (R.converged || R.steps >= o.max_cycles) break;
+    for (int g = 0; g < H.ngrids; ++g) {
+      double s = r[g] / std::sqrt((double)H.cells[g]);
+      if (!(s > 0.0)) s = 1.0;
+      H.hpin[g] = s;
+      H.hpin[H.ngrids + g] = 1.0 / s;
+    }
+    HIP_TRY(hipMemcpyAsync(H.dscal, H.hpin, 2 * H.ngrids * sizeof(double), hipMemcpyHostToDevice, st));
+    // scaled residual -> finest b; e = 0
+    (void)canon_residual(H, P, 1, H.lv[0].b, st);
+    HIP_TRY(hipMemsetAsync(H.lv[0].x, 0, H.lv[0].total * es, st));
+    for (int c = 0; c < o.inner_cycles; ++c) {
+      cy.full(0);
+      R.cycles++;
+    }
+    HIP_TRY(launch_refine_update(H.s, H.g_ew(0), H.x64, H.lv[0].x, H.dscal, st));
+    R.steps++;
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  cy.harvest();
+  finish(H, P, 1, st);
+  return R;
+}
+
+static void fill_report(gd_solve_report* rep, const Outcome& R, int g, double secs, int levels) {
+  rep->cycles = R.cycles;
+  rep->refine_steps = R.steps;
+  rep->rel_residual = R.rel.empty() ? 0.0 : R.rel[g];
+  rep->b_norm = R.bnorm.empty() ? 0.0 : R.bnorm[g];
+  rep->seconds = secs;
+  rep->levels = levels;
+}
+
+// Standalone single steps: a one-grid level description in a small cached
+// device buffer.
+struct StepBuf {
+  int device = -1;
+  char* dev = nullptr;
+  size_t cap = 0;
+  double* part = nullptr;
+  size_t pcap = 0;
+};
+static std::mutex g_step_mu;
+static std::map<int, StepBuf> g_step;
+
+static gd_status run_guarded(const std::function<gd_status()>& f) {
+  try {
+    return f();
+  } catch (const HipFail& e) {
+    if (e.e == hipErrorOutOfMemory) return fail(GD_ERR_NOMEM, std::string("out of device memory in ") + e.what);
+    return fail(GD_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    return fail(GD_ERR_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(GD_ERR_HIP, e.what());
+  }
+}
+
+}  // namespace gd
+
+using namespace gd;
+
+// =================================================================== C ABI
+
+extern "C" {
+
+void gd_default_opts(gd_solve_opts* o) {
+  if (!o) return;
+  o->rel_tol = 1e-6;
+  o->max_cycles = 50;
+  o->pre_smooth = 2;
+  o->post_smooth = 2;
+  o->storage = GD_F32;
+  o->fp64_refine = 0;
+  o->inner_cycles = 1;
+  o->prolong = 0;
+  o->timing = 0;
+}
+
+const char* gd_last_error(void) { return t_err.c_str(); }
+const char* gd_version(void) { return "gdstack 0.1 gfx950"; }
+
+static gd_status check_opts(const gd_solve_opts& o) {
+  if (!(o.rel_tol > 0.0) || o.max_cycles < 0 || o.pre_smooth < 0 || o.post_smooth < 0 ||
+      o.pre_smooth + o.post_smooth < 1 || !valid_dtype(o.storage) || o.inner_cycles < 1 ||
+      (o.prolong != 0 && o.prolong != 1))
+    return fail(GD_ERR_INVALID, "invalid solver options");
+  if (!o.fp64_refine && (o.storage == GD_F16 || o.storage == GD_BF16))
+    return fail(GD_ERR_UNSUPPORTED, "16-bit storage needs fp64_refine = 1 (its rounding floor is far above 1e-6)");
+  return GD_OK;
+}
+
+gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, int64_t nx, int64_t ny, int64_t nz,
+                      double bx, double by, double bz, const gd_solve_opts* opts, gd_solve_report* rep,
+                      void* stream) {
+  if (!I0 || !I1) return fail(GD_ERR_INVALID, "gd_smooth_z: null pointer");
+  if ((const void*)I0 == (const void*)I1) return fail(GD_ERR_INVALID, "gd_smooth_z: output aliases input");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
+    return fail(GD_ERR_INVALID, "gd_smooth_z: bad size");
+  if (!valid_dtype(in_t) || !valid_dtype(out_t)) return fail(GD_ERR_INVALID, "gd_smooth_z: bad dtype");
+  if (!(bx >= 0.0) || !(by >= 0.0) || !(bz > 0.0) || !std::isfinite(bx) || !std::isfinite(by) || !std::isfinite(bz))
+    return fail(GD_ERR_INVALID, "gd_smooth_z: need beta_x, beta_y >= 0 and beta_z > 0");
+  gd_solve_opts o;
+  gd_default_opts(&o);
+  if (opts) o = *opts;
+  gd_status s = check_opts(o);
+  if (s != GD_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<GridSpec> g{{nx, ny, nz, 0.0, bx, by, bz, 0, nx, nx * ny}};
+    Hier* H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st);
+    Problem P{I0, nullptr, I1, in_t, out_t, true};
+    Outcome R = o.fp64_refine ? solve_mixed(*H, P, o, st) : solve_plain(*H, P, o, st);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) fill_report(rep, R, 0, secs, (int)H->lv.size());
+    if (R.numeric) return fail(GD_ERR_NUMERIC, "gd_smooth_z: non-finite residual");
+    if (!R.converged) return fail(GD_ERR_NOT_CONVERGED, "gd_smooth_z: tolerance not reached");
+    return GD_OK;
+  });
+}
+
+gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, gd_dtype t, const gd_slice_desc* sl,
+                                     int64_t n, double bx, double by, const gd_solve_opts* opts, gd_solve_report* rep,
+                                     gd_solve_report* per, void* stream) {
+  if (!I0 || !I1 || !I2 || !sl) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: null pointer");
+  if (I2 == I0 || I2 == I1) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: output aliases input");
+  if (n <= 0 || n > (1 << 24)) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad slice count");
+  if (!valid_dtype(t)) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad dtype");
+  if (!(bx >= 0.0) || !(by >= 0.0) || !std::isfinite(bx) || !std::isfinite(by))
+    return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad beta");
+  std::vector<GridSpec> g;
+  g.reserve(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const gd_slice_desc& d = sl[i];
+    if (d.nx <= 0 || d.ny <= 0 || d.pitch < d.nx || d.offset < 0 || !(d.alpha > 0.0) || !std::isfinite(d.alpha))
+      return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad slice descriptor " + std::to_string(i));
+    g.push_back({d.nx, d.ny, 1, (double)d.alpha, bx, by, 0.0, d.offset, d.pitch, (int64_t)d.pitch * d.ny});
+  }
+  // slices must not overlap (compare row spans of slices sorted by offset)
+  {
+    std::vector<std::pair<int64_t, int64_t>> span;
+    for (int64_t i = 0; i < n; ++i)
+      span.push_back({sl[i].offset, sl[i].offset + (int64_t)sl[i].pitch * (sl[i].ny - 1) + sl[i].nx});
+    std::sort(span.begin(), span.end());
+    for (size_t i = 1; i < span.size(); ++i)
+      if (span[i].first < span[i - 1].second)
+        return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: slices overlap");
+  }
+  gd_solve_opts o;
+  gd_default_opts(&o);
+  if (opts) o = *opts;
+  gd_status s = check_opts(o);
+  if (s != GD_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    Hier* H = get_hier("sp", g, o.storage, o.fp64_refine != 0, st);
+    Problem P{I0, I1, I2, t, t, false};
+    Outcome R = o.fp64_refine ? solve_mixed(*H, P, o, st) : solve_plain(*H, P, o, st);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (per)
+      for (int64_t i = 0; i < n; ++i) fill_report(&per[i], R, (int)i, secs, (int)H->lv.size());
+    if (rep) {
+      fill_report(rep, R, 0, secs, (int)H->lv.size());
+      double worst = 0.0;
+      for (double r : R.rel) worst = std::max(worst, r);
+      rep->rel_residual = worst;
+    }
+    if (R.numeric) return fail(GD_ERR_NUMERIC, "gd_screened_poisson_slices: non-finite residual");
+    if (!R.converged) return fail(GD_ERR_NOT_CONVERGED, "gd_screened_poisson_slices: tolerance not reached");
+    return GD_OK;
+  });
+}
+
+// ------------------------------------------------------------ hierarchy API
+
+struct gd_hierarchy {
+  std::unique_ptr<Hier> H;
+  gd_solve_opts o;
+};
+
+gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t nz, double alpha, double bx, double by,
+                              double bz, gd_dtype s, const gd_solve_opts* opts, void* stream) {
+  if (!h) return fail(GD_ERR_INVALID, "gd_hierarchy_create: null handle pointer");
+  *h = nullptr;
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
+    return fail(GD_ERR_INVALID, "gd_hierarchy_create: bad size");
+  if (!valid_dtype(s)) return fail(GD_ERR_INVALID, "gd_hierarchy_create: bad dtype");
+  if (!(alpha >= 0.0) || !(bx >= 0.0) || !(by >= 0.0) || !(bz >= 0.0) || !std::isfinite(alpha) ||
+      !std::isfinite(bx) || !std::isfinite(by) || !std::isfinite(bz) || (alpha == 0.0 && bx == 0.0 && by == 0.0 && bz == 0.0))
+    return fail(GD_ERR_INVALID, "gd_hierarchy_create: weights must be >= 0 and not all zero");
+  gd_solve_opts o;
+  gd_default_opts(&o);
+  if (opts) o = *opts;
+  o.storage = s;
+  o.fp64_refine = 0;
+  if (!(o.rel_tol > 0.0) || o.pre_smooth < 0 || o.post_smooth < 0 || o.pre_smooth + o.post_smooth < 1 ||
+      (o.prolong != 0 && o.prolong != 1))
+    return fail(GD_ERR_INVALID, "gd_hierarchy_create: invalid options");
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    auto hh = std::make_unique<gd_hierarchy>();
+    hh->o = o;
+    hh->H = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st);
+    *h = hh.release();
+    return GD_OK;
+  });
+}
+
+gd_status gd_hierarchy_destroy(gd_hierarchy* h) {
+  if (!h) return GD_OK;
+  delete h;
+  return GD_OK;
+}
+
+gd_status gd_hierarchy_info(const gd_hierarchy* h, int level, int* nlevels, int64_t dims[3], double coef[4]) {
+  if (!h) return fail(GD_ERR_INVALID, "gd_hierarchy_info: null handle");
+  const Hier& H = *h->H;
+  if (nlevels) *nlevels = (int)H.lv.size();
+  if (level < 0 || level >= (int)H.lv.size()) {
+    if (dims || coef) return fail(GD_ERR_INVALID, "gd_hierarchy_info: level out of range");
+    return GD_OK;
+  }
+  const GridDesc& g = H.lv[level].h[0];
+  if (dims) { dims[0] = g.nx; dims[1] = g.ny; dims[2] = g.nz; }
+  if (coef) { coef[0] = g.alpha; coef[1] = g.wx; coef[2] = g.wy; coef[3] = g.wz; }
+  return GD_OK;
+}
+
+gd_status gd_rhs_general(gd_hierarchy* h, const void* V, const void* Gx, const void* Gy, const void* Gz, void* b,
+                         void* stream) {
+  if (!h || !b) return fail(GD_ERR_INVALID, "gd_rhs_general: null pointer");
+  Hier& H = *h->H;
+  if (H.lv[0].h[0].alpha != 0.0 && !V) return fail(GD_ERR_INVALID, "gd_rhs_general: V is required when alpha > 0");
+  if (b == V || b == Gx || b == Gy || b == Gz) return fail(GD_ERR_INVALID, "gd_rhs_general: output aliases input");
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    HIP_TRY(launch_rhs_general(H.s, H.g_ew(0), V, Gx, Gy, Gz, b, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+  });
+}
+
+gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles, double* relres, void* stream) {
+  if (!h || !x || !b) return fail(GD_ERR_INVALID, "gd_vcycle: null pointer");
+  if (x == b) return fail(GD_ERR_INVALID, "gd_vcycle: x aliases b");
+  Hier& H = *h->H;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    const size_t bytes = H.lv[0].total * dsize(H.s);
+    Level& L0 = H.lv[0];
+    Cycler cy(H, st, h->o);
+    if (ncycles > 0) {
+      HIP_TRY(hipMemcpyAsync(L0.x, x, bytes, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(L0.b, b, bytes, hipMemcpyDeviceToDevice, st));
+      for (int c = 0; c < ncycles; ++c) cy.full(0);
+      HIP_TRY(hipMemcpyAsync(x, L0.x, bytes, hipMemcpyDeviceToDevice, st));
+    }
+    if (relres) {
+      HIP_TRY(launch_general_residual(H.s, H.g_ew(0), x, b, H.partials, st));
+      HIP_TRY(launch_reduce(H.partials, L0.ew.d_b0, 1, 2, H.dred, st));
+      read_dred(H, 2, st);
+      const double rr = std::sqrt(H.hpin[0]), bb = std::sqrt(H.hpin[1]);
+      *relres = bb > 0.0 ? rr / bb : rr;
+      if (!std::isfinite(*relres)) return fail(GD_ERR_NUMERIC, "gd_vcycle: non-finite residual");
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    cy.harvest();
+    return GD_OK;
+  });
+}
+
+// --------------------------------------------------------- single steps
+
+static gd_status one_grid(GridDesc& g, int64_t nx, int64_t ny, int64_t nz, int cx, int cy, int cz, double alpha,
+                          double wx, double wy, double wz) {
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
+    return fail(GD_ERR_INVALID, "bad size");
+  if ((cx != 1 && cx != 2) || (cy != 1 && cy != 2) || (cz != 1 && cz != 2))
+    return fail(GD_ERR_INVALID, "coarsening factors must be 1 or 2");
+  if (!(alpha >= 0.0) || !(wx >= 0.0) || !(wy >= 0.0) || !(wz >= 0.0))
+    return fail(GD_ERR_INVALID, "weights must be >= 0");
+  std::memset(&g, 0, sizeof g);
+  g.nx = (int32_t)nx; g.ny = (int32_t)ny; g.nz = (int32_t)nz;
+  g.fx = cx; g.fy = cy; g.fz = cz;
+  g.cnx = (g.nx + cx - 1) / cx; g.cny = (g.ny + cy - 1) / cy; g.cnz = (g.nz + cz - 1) / cz;
+  g.alpha = alpha; g.wx = wx; g.wy = wy; g.wz = wz;
+  g.ipy = nx; g.ipz = nx * ny;
+  return GD_OK;
+}
+
+// upload one grid + its table for kernel family (TX, TY, child) and return the geometry
+static Geom step_geom(const GridDesc& g, int TX, int TY, bool child, int64_t target, int64_t& nblocks,
+                      double** part, hipStream_t st) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_step_mu);
+  StepBuf& sb = g_step[dev];
+  Tab t;
+  build_tab(t, {g}, TX, TY, child, target);
+  nblocks = t.h_b0.back();
+  const size_t bytes = sizeof(GridDesc) + 2 * sizeof(int64_t);
+  if (sb.cap < bytes) {
+    if (sb.dev) HIP_TRY(hipFree(sb.dev));
+    HIP_TRY(hipMalloc((void**)&sb.dev, 256));
+    sb.cap = 256;
+  }
+  if (sb.pcap < (size_t)nblocks * 2 + 2) {
+    if (sb.part) HIP_TRY(hipFree(sb.part));
+    sb.pcap = (size_t)nblocks * 2 + 2;
+    HIP_TRY(hipMalloc((void**)&sb.part, sb.pcap * sizeof(double)));
+  }
+  char host[256];
+  std::memcpy(host, &g, sizeof(GridDesc));
+  std::memcpy(host + sizeof(GridDesc), t.h_b0.data(), 2 * sizeof(int64_t));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(sb.dev, host, bytes, hipMemcpyHostToDevice));
+  Geom geo;
+  geo.grids = (const GridDesc*)sb.dev;
+  geo.block0 = (const int64_t*)(sb.dev + sizeof(GridDesc));
+  geo.ngrids = 1;
+  geo.nblocks = nblocks;
+  geo.zlen = t.zlen;
+  *part = sb.part;
+  return geo;
+}
+
+gd_status gd_rb_sweep(const void* xin, void* xout, const void* b, gd_dtype s, int64_t nx, int64_t ny, int64_t nz,
+                      double alpha, double wx, double wy, double wz, void* stream) {
+  if (!xin || !xout || !b) return fail(GD_ERR_INVALID, "gd_rb_sweep: null pointer");
+  if (xin == xout || xout == b) return fail(GD_ERR_INVALID, "gd_rb_sweep: output aliases input");
+  if (!valid_dtype(s)) return fail(GD_ERR_INVALID, "gd_rb_sweep: bad dtype");
+  GridDesc g;
+  gd_status r = one_grid(g, nx, ny, nz, 1, 1, 1, alpha, wx, wy, wz);
+  if (r != GD_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    int64_t nb;
+    double* part;
+    Geom geo = step_geom(g, SW_TX, SW_TY, false, 2048, nb, &part, st);
+    HIP_TRY(launch_rb_sweep(s, geo, xin, xout, b, nullptr, 0, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+  });
+}
+
+gd_status gd_residual_restrict(const void* x, const void* b, void* bc, gd_dtype s, int64_t nx, int64_t ny, int64_t nz,
+                               int cx, int cy, int cz, double alpha, double wx, double wy, double wz, double* norm2,
+                               void* stream) {
+  if (!x || !b || !bc) return fail(GD_ERR_INVALID, "gd_residual_restrict: null pointer");
+  if (bc == x || bc == b) return fail(GD_ERR_INVALID, "gd_residual_restrict: output aliases input");
+  if (!valid_dtype(s)) return fail(GD_ERR_INVALID, "gd_residual_restrict: bad dtype");
+  GridDesc g;
+  gd_status r = one_grid(g, nx, ny, nz, cx, cy, cz, alpha, wx, wy, wz);
+  if (r != GD_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    int64_t nb;
+    double* part;
+    Geom geo = step_geom(g, EW_TX, EW_TY, true, 8192, nb, &part, st);
+    HIP_TRY(launch_residual_restrict(s, geo, x, b, bc, nullptr, part, st));
+    if (norm2) {
+      std::vector<double> h(nb);
+      HIP_TRY(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      double t = 0.0;
+      for (double v : h) t += v;
+      *norm2 = t;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+  });
+}
+
+gd_status gd_prolong_add(const void* ec, void* x, gd_dtype s, int64_t nx, int64_t ny, int64_t nz, int cx, int cy,
+                         int cz, int prolong, void* stream) {
+  if (!ec || !x) return fail(GD_ERR_INVALID, "gd_prolong_add: null pointer");
+  if (ec == x) return fail(GD_ERR_INVALID, "gd_prolong_add: output aliases input");
+  if (!valid_dtype(s)) return fail(GD_ERR_INVALID, "gd_prolong_add: bad dtype");
+  if (prolong != 0 && prolong != 1) return fail(GD_ERR_INVALID, "gd_prolong_add: prolong must be 0 or 1");
+  GridDesc g;
+  gd_status r = one_grid(g, nx, ny, nz, cx, cy, cz, 0.0, 0.0, 0.0, 0.0);
+  if (r != GD_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    int64_t nb;
+    double* part;
+    Geom geo = step_geom(g, EW_TX, EW_TY, false, 8192, nb, &part, st);
+    HIP_TRY(launch_prolong_add(s, geo, ec, x, prolong, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+  });
+}
+
+gd_status gd_get_kernel_time(double* total_ms, int64_t* launches, double* bytes) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  if (total_ms) *total_ms = g_timer.total_ms;
+  if (launches) *launches = g_timer.launches;
+  if (bytes) *bytes = g_timer.bytes;
+  return GD_OK;
+}
+
+void gd_reset_kernel_time(void) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  g_timer.total_ms = 0.0;
+  g_timer.launches = 0;
+}
+
+gd_status gd_release_workspace(void) {
+  return run_guarded([&]() -> gd_status {
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      g_cache.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_step_mu);
+    for (auto& kv : g_step) {
+      if (kv.second.dev) HIP_TRY(hipFree(kv.second.dev));
+      if (kv.second.part) HIP_TRY(hipFree(kv.second.part));
+    }
+    g_step.clear();
+    return GD_OK;
+  });
+}
+
+}  // extern "C"
+

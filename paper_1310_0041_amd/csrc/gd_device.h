@@ -1,0 +1,64 @@
+// Device-side types shared by the gfx950 kernels and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace gd {
+
+// One grid of one multigrid level.  A level holds one grid (a 3-D stack) or
+// many (a batch of independent 2-D slices); every array of a level is the
+// concatenation of its grids' [nz][ny][nx] blocks.
+struct GridDesc {
+  int64_t off;    // first element of this grid in the level's arrays
+  int64_t coff;   // first element of its child grid in the next level's arrays
+  int64_t ioff;   // first element in the caller's arrays (finest level I/O)
+  int64_t ipy;    // caller's row pitch (elements)
+  int64_t ipz;    // caller's plane pitch (elements)
+  int32_t nx, ny, nz;
+  int32_t cnx, cny, cnz;  // child grid size
+  int32_t fx, fy, fz;     // coarsening factor per axis (1 or 2)
+  int32_t pad_;
+  double alpha, wx, wy, wz;  // operator alpha*Id + sum_a w_a L_a of this level
+};
+
+// Storage-type traits: load to / store from the arithmetic type.
+template <typename S> struct Ty;
+template <> struct Ty<double> {
+  using C = double;
+  static __device__ __forceinline__ double ld(const double* p) { return *p; }
+  static __device__ __forceinline__ void st(double* p, double v) { *p = v; }
+};
+template <> struct Ty<float> {
+  using C = float;
+  static __device__ __forceinline__ float ld(const float* p) { return *p; }
+  static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
+};
+template <> struct Ty<__half> {
+  using C = float;
+  static __device__ __forceinline__ float ld(const __half* p) { return __half2float(*p); }
+  static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
+};
+template <> struct Ty<__hip_bfloat16> {
+  using C = float;
+  static __device__ __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+  static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+};
+
+// Exact upcast to double (every storage type embeds in binary64).
+template <typename T> __device__ __forceinline__ double ld64(const T* p) { return (double)Ty<T>::ld(p); }
+template <typename T> __device__ __forceinline__ void st64(T* p, double v) { Ty<T>::st(p, (typename Ty<T>::C)v); }
+
+// Block index -> grid: largest g with block0[g] <= bid (block0 has n+1 entries).
+__device__ __forceinline__ int find_grid(const int64_t* __restrict__ block0, int n, int64_t bid) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (block0[mid] <= bid) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace gd

@@ -1,0 +1,63 @@
+// Host-side launchers of the gfx950 kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gd.h"
+#include "gd_device.h"
+
+namespace gd {
+
+// Tile shapes of the kernel families.
+constexpr int SW_TX = 64, SW_TY = 8;   // relaxation: interior tile, 256 threads
+constexpr int EW_TX = 64, EW_TY = 4;   // per-voxel kernels: 256 threads
+
+// A launch over the grids of one level: blocks [block0[g], block0[g+1])
+// belong to grid g; each block covers one (x, y) tile and `zlen` planes.
+struct Geom {
+  const GridDesc* grids = nullptr;  // device array
+  const int64_t* block0 = nullptr;  // device array, ngrids + 1 entries
+  int ngrids = 0;
+  int64_t nblocks = 0;
+  int zlen = 1;
+};
+
+hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
+                           const void* e_coarse, int prolong_mode, hipStream_t st);
+hipError_t launch_residual_restrict(gd_dtype s, const Geom& gc, const void* x, const void* b,
+                                    void* b_coarse, void* x_coarse, double* partials, hipStream_t st);
+hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* e_coarse, void* x, int mode,
+                              hipStream_t st);
+// Finest level of the AD/SP systems in correction form: b = alpha (I1 - I0)
+// - w_z L_z I0 (written when b != NULL, x zeroed when x != NULL) and the
+// FP64 squares of the canonical right-hand side alpha I1 + (w_x L_x + w_y L_y) I0.
+hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, const void* I1,
+                           void* b, void* x, double* partials, hipStream_t st);
+// FP64 canonical residual r = b - A x of the AD/SP system for x = I0 + E
+// (mode 0, E packed in `s`) or x = x64 (mode 1).  Per block: sum r^2.  When
+// r_out != NULL also writes r * inv_scale[g] packed in `s`.
+hipError_t launch_canon_residual(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
+                                 const void* I1, const void* E, const double* x64, void* r_out,
+                                 const double* inv_scale, double* partials, hipStream_t st);
+// Per block: sum (x - I0) for x = I0 + E (mode 0) or x64 (mode 1).
+hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
+                            const void* E, const double* x64, double* partials, hipStream_t st);
+// out = x - shift[g] in the caller's layout, x = I0 + E (mode 0) or x64 (mode 1).
+hipError_t launch_finalize(gd_dtype tin, gd_dtype s, gd_dtype tout, int mode, const Geom& g,
+                           const void* I0, const void* E, const double* x64, const double* shift,
+                           void* out, hipStream_t st);
+hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, double* x64, hipStream_t st);
+hipError_t launch_refine_update(gd_dtype s, const Geom& g, double* x64, const void* e,
+                                const double* scale, hipStream_t st);
+// Generic system: b = alpha V + sum_a w_a D_a^T G_a.
+hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const void* Gx,
+                              const void* Gy, const void* Gz, void* b, hipStream_t st);
+// Generic system: per block (sum (b - A x)^2, sum b^2) in FP64.
+hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b,
+                                   double* partials, hipStream_t st);
+// out[g * ncomp + c] = sum of partials[b * ncomp + c] over the blocks of grid g.
+hipError_t launch_reduce(const double* partials, const int64_t* block0, int ngrids, int ncomp,
+                         double* out, hipStream_t st);
+
+}  // namespace gd

@@ -1,0 +1,96 @@
+"""The C-ABI library loads and exports every entry point gd.h declares; its
+argument checks run on the host (no GPU call is made here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1310_0041_amd as gd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "gd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gd_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return gd.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(gd.exported_symbols())
+
+
+def test_defaults(lib):
+    o = gd.default_opts()
+    assert o.rel_tol == 1e-6 and o.pre_smooth == 2 and o.post_smooth == 2 and o.storage == gd.F32
+    assert lib.gd_version().startswith(b"gdstack")
+
+
+P = ctypes.c_void_p
+
+
+@pytest.mark.parametrize(
+    "args,status",
+    [
+        ((None, 1, P(64), 1, 4, 4, 4, 1.0, 1.0, 4.0), gd.ERR_INVALID),          # null input
+        ((P(64), 1, P(64), 1, 4, 4, 4, 1.0, 1.0, 4.0), gd.ERR_INVALID),         # aliasing
+        ((P(64), 1, P(128), 1, 0, 4, 4, 1.0, 1.0, 4.0), gd.ERR_INVALID),        # empty
+        ((P(64), 1, P(128), 1, 4, 4, 4, 1.0, 1.0, 0.0), gd.ERR_INVALID),        # beta_z = 0
+        ((P(64), 1, P(128), 1, 4, 4, 4, -1.0, 1.0, 4.0), gd.ERR_INVALID),       # negative beta
+        ((P(64), 1, P(128), 1, 4, 4, 4, float("nan"), 1.0, 4.0), gd.ERR_INVALID),
+        ((P(64), 7, P(128), 1, 4, 4, 4, 1.0, 1.0, 4.0), gd.ERR_INVALID),        # bad dtype
+        ((P(64), 1, P(128), 1, 4, 4, 2**31, 1.0, 1.0, 4.0), gd.ERR_INVALID),    # too long
+    ],
+)
+def test_smooth_z_argument_checks(lib, args, status):
+    assert lib.gd_smooth_z(*args, None, None, None) == status
+    assert lib.gd_last_error()
+
+
+def test_option_checks(lib):
+    base = (P(64), 1, P(128), 1, 4, 4, 4, 1.0, 1.0, 4.0)
+    for kw, st in [
+        (dict(storage=gd.F16), gd.ERR_UNSUPPORTED),
+        (dict(storage=gd.BF16), gd.ERR_UNSUPPORTED),
+        (dict(rel_tol=0.0), gd.ERR_INVALID),
+        (dict(pre_smooth=0, post_smooth=0), gd.ERR_INVALID),
+        (dict(prolong=3), gd.ERR_INVALID),
+        (dict(storage=9), gd.ERR_INVALID),
+    ]:
+        o = gd.default_opts(**kw)
+        assert lib.gd_smooth_z(*base, ctypes.byref(o), None, None) == st, kw
+
+
+def test_slice_argument_checks(lib):
+    d = gd.make_slice_descs([0, 50], 10, 10, 0.01)
+    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, 2, 1.0, 1.0, None, None, None,
+                                          None) == gd.ERR_INVALID  # slices overlap
+    d = gd.make_slice_descs([0, 100], 10, 10, 0.0)
+    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, 2, 1.0, 1.0, None, None, None,
+                                          None) == gd.ERR_INVALID  # alpha must be > 0
+    d = gd.make_slice_descs([0], 10, 10, 0.01, pitch=[5])
+    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, 1, 1.0, 1.0, None, None, None,
+                                          None) == gd.ERR_INVALID  # pitch < nx
+    assert lib.gd_screened_poisson_slices(P(64), P(128), P(64), 1, d, 1, 1.0, 1.0, None, None, None,
+                                          None) == gd.ERR_INVALID  # aliasing
+
+
+def test_step_argument_checks(lib):
+    assert lib.gd_rb_sweep(P(64), P(64), P(128), 1, 4, 4, 4, 0.0, 1.0, 1.0, 1.0, None) == gd.ERR_INVALID
+    assert lib.gd_residual_restrict(P(64), P(128), P(256), 1, 4, 4, 4, 3, 1, 1, 0.0, 1.0, 1.0, 1.0, None,
+                                    None) == gd.ERR_INVALID
+    assert lib.gd_prolong_add(P(64), P(128), 1, 4, 4, 4, 2, 2, 2, 5, None) == gd.ERR_INVALID
+    h = ctypes.c_void_p()
+    assert lib.gd_hierarchy_create(ctypes.byref(h), 4, 4, 4, 0.0, 0.0, 0.0, 0.0, 1, None, None) == gd.ERR_INVALID
+    assert lib.gd_hierarchy_create(ctypes.byref(h), 4, 4, 4, -1.0, 1.0, 0.0, 0.0, 1, None, None) == gd.ERR_INVALID

@@ -1,0 +1,285 @@
+"""HIP path vs the FP64 oracle, element by element, on the same seeded inputs.
+
+Kernel-level steps (one red-black sweep, residual + restriction,
+prolongation) are compared to the oracle's definitions of the same step;
+whole solves are compared to the oracle's solution of the paper's systems.
+Tolerances: FP64 steps 1e-12 relative, FP32 steps 2e-6 relative (a handful
+of roundings of values of similar magnitude); solves to 1e-6 (FP64 iterate)
+or 1e-5 (plain FP32) relative L2, the bars stated for this path.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import grid as og
+from oracle import mgsteps as om
+from oracle import solvers as osv
+
+pytestmark = pytest.mark.gpu
+
+BETA = (1.0, 1.0, 4.0)
+TD = {np.float64: torch.float64, np.float32: torch.float32}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+STEP_SHAPES = [(9, 17, 130), (1, 33, 200), (40, 3, 5), (3, 8, 64), (1, 1, 1), (5, 1, 7), (2, 70, 1)]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", STEP_SHAPES)
+@pytest.mark.parametrize("alpha,w", [(0.0, BETA), (0.01, (1.0, 1.0, 0.0)), (0.7, (2.0, 0.5, 3.0))])
+def test_rb_sweep_step(gd, dt, shape, alpha, w):
+    say("rb_sweep", shape, dt, alpha, w)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(shape) * 10
+    b = rng.standard_normal(shape)
+    xq, bq = host(dev(x, dt)), host(dev(b, dt))
+    ref = om.rb_sweep(xq, bq, alpha, w)
+    out = host(gd.rb_sweep(dev(x, dt), dev(b, dt), alpha, w))
+    tol = 1e-12 if dt == torch.float64 else 2e-6
+    assert np.abs(out - ref).max() <= tol * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", STEP_SHAPES)
+@pytest.mark.parametrize("c", [(2, 2, 2), (1, 1, 2), (2, 2, 1)])
+def test_residual_restrict_step(gd, dt, shape, c):
+    say("residual_restrict", shape, dt, c)
+    rng = np.random.default_rng(2)
+    alpha, w = 0.3, (1.0, 2.0, 4.0)
+    x = rng.standard_normal(shape) * 10
+    b = rng.standard_normal(shape)
+    xq, bq = host(dev(x, dt)), host(dev(b, dt))
+    r = om.residual(xq, bq, alpha, w)
+    ref = om.restrict_sum(r, c)
+    bc, n2 = gd.residual_restrict(dev(x, dt), dev(b, dt), alpha, w, c)
+    tol = 1e-12 if dt == torch.float64 else 2e-6
+    scale = max(1.0, np.abs(xq).max() * 24)
+    assert np.abs(host(bc) - ref).max() <= tol * scale * 8
+    assert abs(n2 - float((r * r).sum())) <= 1e-5 * float((r * r).sum()) + 1e-12
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", STEP_SHAPES)
+@pytest.mark.parametrize("c", [(2, 2, 2), (1, 1, 2), (2, 2, 1)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_prolong_step(gd, dt, shape, c, mode):
+    say("prolong", shape, dt, c, mode)
+    rng = np.random.default_rng(3)
+    cs = om.coarse_shape(shape, c)
+    e = rng.standard_normal(cs)
+    x = rng.standard_normal(shape)
+    eq, xq = host(dev(e, dt)), host(dev(x, dt))
+    P = om.prolong_trilinear if mode == 0 else om.prolong_constant
+    ref = xq + P(eq, shape, c)
+    out = host(gd.prolong_add(dev(e, dt), dev(x, dt), c, mode))
+    tol = 1e-13 if dt == torch.float64 else 1e-6
+    assert np.abs(out - ref).max() <= tol * max(1.0, np.abs(ref).max())
+
+
+# ----------------------------------------------------------------- solves
+
+
+def stack(spec, dt):
+    I0 = synth.make_stack(spec).numpy()
+    return host(dev(I0, dt))  # the quantised input both sides see
+
+
+def test_ad_then_sp_fp64_stack64(gd):
+    """64x64x16, FP64, V-cycles to 1e-8 (the FP64 plain configuration)."""
+    say("AD+SP f64 64x64x16")
+    I0 = stack(synth.CONFIGS["stack64"], torch.float64)
+    I1, rep = gd.smooth_z(dev(I0, torch.float64), BETA, storage=gd.F64, rel_tol=1e-8)
+    assert rep["rel_residual"] <= 1e-8
+    ref1 = osv.ad_dct(I0, BETA)
+    assert rel(host(I1), ref1) <= 1e-6
+    # residual recomputed by the oracle on the returned FP64 output
+    b = og.rhs_ad(I0, BETA)
+    assert om.relative_residual(host(I1), b, 0.0, BETA) <= 1.01e-8
+    I2, rep2, per = gd.screened_poisson_stack(dev(I0, torch.float64), I1, 0.01, storage=gd.F64, rel_tol=1e-8)
+    assert rep2["rel_residual"] <= 1e-8
+    ref2 = osv.sp_dct(I0, host(I1), 0.01)
+    assert rel(host(I2), ref2) <= 1e-6
+    assert rel(host(I2), osv.sp_dct(I0, ref1, 0.01)) <= 1e-6
+
+
+def fp32_floor(I0, ref, b):
+    """Relative residual of the exact answer when its correction I1 - I0 is
+    stored in FP32: no plain FP32 iterate can do much better."""
+    E = (ref - I0).astype(np.float32).astype(np.float64)
+    return om.relative_residual(I0 + E, b, 0.0, BETA)
+
+
+@pytest.mark.parametrize("shape", [(32, 256, 256), (7, 45, 99), (1, 40, 33), (16, 1, 64), (3, 2, 1), (16, 64, 64)])
+def test_ad_plain_fp32(gd, shape):
+    say("AD f32 plain", shape)
+    nz, ny, nx = shape
+    spec = synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100412)
+    I0 = stack(spec, torch.float32)
+    ref = osv.ad_dct(I0, BETA)
+    b = og.rhs_ad(I0, BETA)
+    tol = 1e-6
+    if np.linalg.norm(b) > 0:
+        tol = max(1e-6, 3.0 * fp32_floor(I0, ref, b))
+    I1, rep = gd.smooth_z(dev(I0), BETA, out_dtype=torch.float64, rel_tol=tol)
+    assert rep["status"] == 0 and rep["rel_residual"] <= tol
+    assert rel(host(I1), ref) <= 1e-5
+    if np.linalg.norm(b) > 0:
+        assert om.relative_residual(host(I1), b, 0.0, BETA) <= 1.01 * tol
+    # gauge: mean preserved
+    assert abs(host(I1).mean() - I0.mean()) <= 1e-9 * max(1.0, abs(I0.mean()))
+
+
+def test_plain_fp32_stops_at_its_floor(gd):
+    """Smooth slices with strong slice-to-slice jumps: the FP32 correction
+    cannot represent an answer at 1e-9; the solve stops on stagnation and
+    says so, with a finite best iterate close to the oracle."""
+    say("AD f32 floor")
+    spec = synth.StackSpec(64, 64, 16, (4.0, 40.0), False, 13100411)
+    I0 = stack(spec, torch.float32)
+    I1, rep = gd.smooth_z(dev(I0), BETA, out_dtype=torch.float64, rel_tol=1e-9, check=False)
+    assert rep["status"] == gd.ERR_NOT_CONVERGED
+    assert rep["cycles"] < 40
+    assert rel(host(I1), osv.ad_dct(I0, BETA)) <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16", "f32"])
+def test_ad_mixed_refinement(gd, storage):
+    say("AD mixed", storage)
+    st = {"f16": gd.F16, "bf16": gd.BF16, "f32": gd.F32}[storage]
+    tin = {"f16": torch.float16, "bf16": torch.bfloat16, "f32": torch.float32}[storage]
+    spec = synth.StackSpec(96, 80, 24, (4.0, 40.0), True, 13100413)
+    I0f = synth.make_stack(spec)
+    I0 = I0f.to(tin).double().numpy()
+    ref = osv.ad_dct(I0, BETA)
+    I1, rep = gd.smooth_z(I0f.to(tin).cuda(), BETA, out_dtype=torch.float64, storage=st, fp64_refine=1)
+    assert rep["rel_residual"] <= 1e-6 and rep["refine_steps"] >= 1
+    assert rel(host(I1), ref) <= 1e-5
+    # the error bar of 1e-6 vs the oracle needs a residual below it (the
+    # smoothest modes have eigenvalues ~1e-3): the FP64 iterate gets there
+    I1, rep = gd.smooth_z(I0f.to(tin).cuda(), BETA, out_dtype=torch.float64, storage=st, fp64_refine=1,
+                          rel_tol=2e-7)
+    assert rep["rel_residual"] <= 2e-7
+    assert rel(host(I1), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("shape", [(8, 256, 256), (3, 37, 130), (2, 1, 1)])
+def test_sp_stack_plain_fp32(gd, shape):
+    say("SP stack f32", shape)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(4)
+    I0 = host(dev(rng.uniform(0, 255, shape)))
+    I1 = host(dev(I0 + rng.uniform(-20, 20, (nz, 1, 1)) + rng.standard_normal(shape)))
+    I2, rep, per = gd.screened_poisson_stack(dev(I0), dev(I1), 0.01)
+    assert rep["rel_residual"] <= 1e-6
+    assert all(p["rel_residual"] <= 1e-6 for p in per)
+    assert rel(host(I2), osv.sp_dct(I0, I1, 0.01)) <= 1e-5
+
+
+def test_sp_batched_uneven_slices(gd):
+    """Independent slices of uneven sizes and per-slice alpha in one call."""
+    say("SP batch uneven")
+    meta = synth.make_slice_batch(nslices=24, lo=16, hi=300, seed=77, dtype=torch.float32)
+    I0 = meta["I0"].cuda()
+    I1 = meta["I1"].cuda()
+    descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
+    I2, rep, per = gd.screened_poisson_slices(I0, I1, descs)
+    assert rep["rel_residual"] <= 1e-6
+    out = host(I2)
+    a0 = meta["I0"].double().numpy()
+    a1 = meta["I1"].double().numpy()
+    for i in range(24):
+        o, w, h = meta["offset"][i], meta["w"][i], meta["h"][i]
+        s0 = a0[o:o + w * h].reshape(1, h, w)
+        s1 = a1[o:o + w * h].reshape(1, h, w)
+        alpha = float(np.float32(meta["alpha"][i]))
+        ref = osv.sp_dct(s0, s1, alpha)
+        assert rel(out[o:o + w * h].reshape(1, h, w), ref) <= 1e-5, i
+        assert per[i]["rel_residual"] <= 1e-6
+
+
+def test_sp_batched_mixed_bf16(gd):
+    say("SP batch mixed bf16")
+    meta = synth.make_slice_batch(nslices=8, lo=30, hi=200, seed=78, dtype=torch.bfloat16)
+    descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
+    I2, rep, per = gd.screened_poisson_slices(meta["I0"].cuda(), meta["I1"].cuda(), descs, storage=gd.BF16,
+                                              fp64_refine=1)
+    assert rep["rel_residual"] <= 1e-6
+    a0 = meta["I0"].double().numpy()
+    a1 = meta["I1"].double().numpy()
+    out = host(I2)
+    for i in range(8):
+        o, w, h = meta["offset"][i], meta["w"][i], meta["h"][i]
+        ref = osv.sp_dct(a0[o:o + w * h].reshape(1, h, w), a1[o:o + w * h].reshape(1, h, w),
+                         float(np.float32(meta["alpha"][i])))
+        # output rounded to bf16 (8-bit mantissa)
+        assert rel(out[o:o + w * h].reshape(1, h, w), ref) <= 4e-3
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_general_system_hierarchy(gd, dt):
+    say("general hierarchy", dt)
+    shape = (12, 50, 70)
+    alpha, beta = 0.05, (1.0, 0.5, 2.0)
+    rng = np.random.default_rng(5)
+    V = rng.standard_normal(shape)
+    G = [rng.standard_normal(shape) for _ in range(3)]
+    Vq = host(dev(V, dt))
+    Gq = [host(dev(g, dt)) for g in G]
+    faces = (Gq[0][:, :, :-1], Gq[1][:, :-1, :], Gq[2][:-1, :, :])
+    ref = osv.general_solve(Vq, faces, alpha, beta, method="dct")
+    h = gd.Hierarchy(shape, alpha, beta, dt)
+    b = h.rhs(dev(V, dt), *[dev(g, dt) for g in G])
+    bref = og.rhs_general(Vq, faces, alpha, beta)
+    assert np.abs(host(b) - bref).max() <= (1e-13 if dt == torch.float64 else 1e-6) * np.abs(bref).max()
+    x = torch.zeros(shape, dtype=dt, device="cuda")
+    rr = 1.0
+    for _ in range(30):
+        rr = h.vcycle(x, b, 1)
+        if rr < (1e-10 if dt == torch.float64 else 1e-6):
+            break
+    assert rr < (1e-10 if dt == torch.float64 else 1e-6)
+    # the oracle's own FP64 residual of the returned x
+    ores = om.relative_residual(host(x), host(b), alpha, beta)
+    assert ores <= (1.01e-10 if dt == torch.float64 else 2e-6)
+    # error bar: residual times the condition number (white-noise targets
+    # excite every mode; kappa = lambda_max / alpha here)
+    kappa = (alpha + 4 * sum(beta)) / alpha
+    assert rel(host(x), osv.dct_solve(host(b), alpha, beta)) <= kappa * ores * 1.01
+    tol_ref = 1e-8 if dt == torch.float64 else 1e-5
+    assert rel(host(b), bref) <= tol_ref
+    assert rel(osv.dct_solve(bref, alpha, beta), ref) <= 1e-12
+    h.close()
+
+
+def test_not_converged_status(gd):
+    say("not converged")
+    I0 = dev(np.random.default_rng(6).uniform(0, 255, (8, 64, 64)))
+    I1, rep = gd.smooth_z(I0, BETA, check=False, max_cycles=1, rel_tol=1e-12)
+    assert rep["status"] == gd.ERR_NOT_CONVERGED
+    assert torch.isfinite(I1).all()
+
+
+def test_deterministic(gd):
+    say("determinism")
+    I0 = dev(np.random.default_rng(7).uniform(0, 255, (16, 100, 90)))
+    a, _ = gd.smooth_z(I0, BETA)
+    b, _ = gd.smooth_z(I0, BETA)
+    assert torch.equal(a, b)
