@@ -39,6 +39,7 @@ def parse():
     p.add_argument("--workload", default="stack1k", choices=sorted(WORKLOADS))
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-crop", default="32,128,128", help="nz,ny,nx of the oracle's crop")
+    p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
     p.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                           "profiles", "traffic.json"))
     return p.parse_args()
@@ -89,7 +90,8 @@ def main():
     gen_s = time.perf_counter() - t0
     nvox = I0.numel()
     out_dtype = torch.float32 if storage == "f32" else tdt
-    opts = dict(storage=sdt, fp64_refine=refine, rel_tol=TOL)
+    pre, post = (int(v) for v in a.smooth.split(","))
+    opts = dict(storage=sdt, fp64_refine=refine, rel_tol=TOL, pre_smooth=pre, post_smooth=post)
 
     def step(timing):
         I1, r1 = gd.smooth_z(I0, BETA, out_dtype=out_dtype, timing=timing, **opts)
@@ -137,7 +139,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{a.workload}: {desc}; beta=(1,1,4), alpha={ALPHA}, Neumann, tol {TOL:g}",
-            "nx": spec.nx, "ny": spec.ny, "nz": spec.nz, "voxels": nvox,
+            "nx": spec.nx, "ny": spec.ny, "nz": spec.nz, "voxels": nvox, "smooth": [pre, post],
         },
         "roofline": {
             "bound": "hbm",

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -71,23 +72,28 @@ static KernelTimer g_timer;
 
 // --------------------------------------------------------------- hierarchy
 
-struct GridSpec {  // finest-level grid as the caller describes it
+struct GridSpec {  // finest-level grid in the kernels' view
   int64_t nx, ny, nz;
   double alpha, wx, wy, wz;
   int64_t ioff, ipy, ipz;
+  int zin = 0;  // a 2-D slice seen as nz rows of one line
 };
+
+static int32_t pitch_of(int64_t nx) { return (int32_t)((nx + 3) & ~(int64_t)3); }
 
 struct Tab {  // launch geometry of one kernel family on one level
   int64_t* d_b0 = nullptr;
   std::vector<int64_t> h_b0;
   int zlen = 1;
-  Geom geom(const GridDesc* d_grids, int ngrids) const {
+  Geom geom(const GridDesc* d_grids, int ngrids, bool row) const {
     Geom g;
     g.grids = d_grids;
     g.block0 = d_b0;
     g.ngrids = ngrids;
     g.nblocks = h_b0.back();
     g.zlen = zlen;
+    g.etx = row ? EWR_TX : EW_TX;
+    g.row = row;
     return g;
   }
 };
@@ -96,7 +102,8 @@ struct Level {
   std::vector<GridDesc> h;
   GridDesc* d = nullptr;
   int64_t total = 0;
-  Tab sw, ew, rc;  // relaxation tiles, per-voxel tiles, child-cell tiles
+  bool row = false;  // every grid has ny == 1
+  Tab sw, ew, rc, rz;  // relaxation, per-voxel, child-cell and z-marching restriction tiles
   void* x = nullptr;
   void* xt = nullptr;
   void* b = nullptr;
@@ -127,9 +134,10 @@ struct Hier {
     allocs.push_back(p);
     return p;
   }
-  Geom g_sw(int l) const { return lv[l].sw.geom(lv[l].d, ngrids); }
-  Geom g_ew(int l) const { return lv[l].ew.geom(lv[l].d, ngrids); }
-  Geom g_rc(int l) const { return lv[l].rc.geom(lv[l].d, ngrids); }
+  Geom g_sw(int l) const { return lv[l].sw.geom(lv[l].d, ngrids, lv[l].row); }
+  Geom g_ew(int l) const { return lv[l].ew.geom(lv[l].d, ngrids, lv[l].row); }
+  Geom g_rc(int l) const { return lv[l].rc.geom(lv[l].d, ngrids, lv[l].row); }
+  Geom g_rz(int l) const { return lv[l].rz.geom(lv[l].d, ngrids, lv[l].row); }
 };
 
 static void coarsen_factors(const GridDesc& g, int f[3]) {
@@ -141,7 +149,8 @@ static void coarsen_factors(const GridDesc& g, int f[3]) {
   for (int a = 0; a < 3; ++a) f[a] = (n[a] > 1 && w[a] > 0.0 && w[a] >= 0.5 * wmax) ? 2 : 1;
 }
 
-static void build_tab(Tab& t, const std::vector<GridDesc>& grids, int TX, int TY, bool child, int64_t target) {
+static void build_tab(Tab& t, const std::vector<GridDesc>& grids, int TX, int TY, bool child, int64_t target,
+                      bool even = false) {
   int64_t nzmax = 1, tiles_sum = 0;
   for (const auto& g : grids) {
     const int64_t nx = child ? g.cnx : g.nx, ny = child ? g.cny : g.ny, nz = child ? g.cnz : g.nz;
@@ -151,12 +160,22 @@ static void build_tab(Tab& t, const std::vector<GridDesc>& grids, int TX, int TY
   int64_t chunks = std::max<int64_t>(1, (target + tiles_sum - 1) / std::max<int64_t>(tiles_sum, 1));
   chunks = std::min(chunks, nzmax);
   t.zlen = (int)((nzmax + chunks - 1) / chunks);
+  if (even && (t.zlen & 1)) t.zlen += 1;
   t.h_b0.assign(1, 0);
   for (const auto& g : grids) {
     const int64_t nx = child ? g.cnx : g.nx, ny = child ? g.cny : g.ny, nz = child ? g.cnz : g.nz;
     const int64_t nb = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + t.zlen - 1) / t.zlen);
     t.h_b0.push_back(t.h_b0.back() + nb);
   }
+}
+
+// Blocks a relaxation launch aims for (z-chunks are cut until reached).
+static int64_t sweep_target() {
+  static int64_t v = [] {
+    const char* e = std::getenv("GD_SWEEP_BLOCKS");
+    return e ? std::max<int64_t>(1, std::atoll(e)) : (int64_t)8192;
+  }();
+  return v;
 }
 
 static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
@@ -179,6 +198,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     g.ioff = specs[i].ioff;
     g.ipy = specs[i].ipy;
     g.ipz = specs[i].ipz;
+    g.zin = specs[i].zin;
     cur[i] = g;
     H->cells.push_back(specs[i].nx * specs[i].ny * specs[i].nz);
   }
@@ -186,15 +206,19 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     Level L;
     int64_t off = 0;
     bool more = false;
+    L.row = true;
     for (auto& g : cur) {
       g.off = off;
-      off += (int64_t)g.nx * g.ny * g.nz;
+      g.px = pitch_of(g.nx);
+      off += (int64_t)g.px * g.ny * g.nz;
+      if (g.ny != 1) L.row = false;
       int f[3];
       coarsen_factors(g, f);
       g.fx = f[0]; g.fy = f[1]; g.fz = f[2];
       g.cnx = (g.nx + f[0] - 1) / f[0];
       g.cny = (g.ny + f[1] - 1) / f[1];
       g.cnz = (g.nz + f[2] - 1) / f[2];
+      g.cpx = pitch_of(g.cnx);
       if (f[0] * f[1] * f[2] > 1) more = true;
     }
     L.h = cur;
@@ -214,36 +238,46 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
       c.wy = g.wy * V / (g.fy * g.fy);
       c.wz = g.wz * V / (g.fz * g.fz);
       nxt[i] = c;
-      coff += (int64_t)c.nx * c.ny * c.nz;
+      coff += (int64_t)pitch_of(c.nx) * c.ny * c.nz;
     }
     cur = nxt;
   }
   // last level: no child
-  for (auto& g : H->lv.back().h) { g.cnx = g.nx; g.cny = g.ny; g.cnz = g.nz; g.fx = g.fy = g.fz = 1; g.coff = 0; }
+  for (auto& g : H->lv.back().h) {
+    g.cnx = g.nx; g.cny = g.ny; g.cnz = g.nz; g.cpx = g.px; g.fx = g.fy = g.fz = 1; g.coff = 0;
+  }
 
   // launch tables, device copies, arrays
   const size_t es = dsize(s);
   int64_t maxblocks = 1;
   std::vector<char> stage;
   for (auto& L : H->lv) {
-    build_tab(L.sw, L.h, SW_TX, SW_TY, false, 2048);
-    build_tab(L.ew, L.h, EW_TX, EW_TY, false, 8192);
-    build_tab(L.rc, L.h, EW_TX, EW_TY, true, 8192);
-    maxblocks = std::max({maxblocks, L.sw.h_b0.back(), L.ew.h_b0.back(), L.rc.h_b0.back()});
+    if (L.row) {
+      build_tab(L.sw, L.h, SWR_TX, 1, false, sweep_target());
+      build_tab(L.ew, L.h, EWR_TX, 1, false, 8192);
+      build_tab(L.rc, L.h, EWR_TX, 1, true, 8192);
+      build_tab(L.rz, L.h, SWR_TX, 1, false, 4096, true);
+    } else {
+      build_tab(L.sw, L.h, SW_TX, SW_TY, false, sweep_target());
+      build_tab(L.ew, L.h, EW_TX, EW_TY, false, 8192);
+      build_tab(L.rc, L.h, EW_TX, EW_TY, true, 8192);
+      build_tab(L.rz, L.h, SW_TX, SW_TY, false, 2048, true);
+    }
+    maxblocks = std::max({maxblocks, L.sw.h_b0.back(), L.ew.h_b0.back(), L.rc.h_b0.back(), L.rz.h_b0.back()});
     const size_t nb = (size_t)H->ngrids + 1;
-    const size_t bytes = L.h.size() * sizeof(GridDesc) + 3 * nb * sizeof(int64_t);
+    const size_t gbytes = L.h.size() * sizeof(GridDesc);
+    const size_t bytes = gbytes + 4 * nb * sizeof(int64_t);
     char* dev = (char*)H->alloc(bytes);
     L.d = (GridDesc*)dev;
-    L.sw.d_b0 = (int64_t*)(dev + L.h.size() * sizeof(GridDesc));
+    L.sw.d_b0 = (int64_t*)(dev + gbytes);
     L.ew.d_b0 = L.sw.d_b0 + nb;
     L.rc.d_b0 = L.ew.d_b0 + nb;
+    L.rz.d_b0 = L.rc.d_b0 + nb;
     stage.resize(bytes);
-    std::memcpy(stage.data(), L.h.data(), L.h.size() * sizeof(GridDesc));
-    std::memcpy(stage.data() + L.h.size() * sizeof(GridDesc), L.sw.h_b0.data(), nb * sizeof(int64_t));
-    std::memcpy(stage.data() + L.h.size() * sizeof(GridDesc) + nb * sizeof(int64_t), L.ew.h_b0.data(),
-                nb * sizeof(int64_t));
-    std::memcpy(stage.data() + L.h.size() * sizeof(GridDesc) + 2 * nb * sizeof(int64_t), L.rc.h_b0.data(),
-                nb * sizeof(int64_t));
+    std::memcpy(stage.data(), L.h.data(), gbytes);
+    const Tab* tabs[4] = {&L.sw, &L.ew, &L.rc, &L.rz};
+    for (int k = 0; k < 4; ++k)
+      std::memcpy(stage.data() + gbytes + k * nb * sizeof(int64_t), tabs[k]->h_b0.data(), nb * sizeof(int64_t));
     HIP_TRY(hipMemcpy(dev, stage.data(), bytes, hipMemcpyHostToDevice));
     L.x = H->alloc(L.total * es);
     L.xt = H->alloc(L.total * es);
@@ -345,8 +379,8 @@ struct Cycler {
   void restrict_to(int l, bool norm) {
     Level& L = H.lv[l];
     Level& C = H.lv[l + 1];
-    HIP_TRY(launch_residual_restrict(H.s, H.g_rc(l), L.x, L.b, C.b, C.x, norm ? H.partials : nullptr, st));
-    if (norm) HIP_TRY(launch_reduce(H.partials, L.rc.d_b0, H.ngrids, 1, H.dred, st));
+    HIP_TRY(launch_restrict_z(H.s, H.g_rz(l), L.x, L.b, C.b, C.x, norm ? H.partials : nullptr, st));
+    if (norm) HIP_TRY(launch_reduce(H.partials, L.rz.d_b0, H.ngrids, 1, H.dred, st));
   }
   // coarse-grid correction of level l (levels l+1 .. bottom), then post-smoothing
   void correct(int l) {
@@ -386,7 +420,9 @@ struct Cycler {
     std::lock_guard<std::mutex> lk(g_timer.mu);
     g_timer.total_ms += tot;
     g_timer.launches += (int64_t)ev_used;
-    g_timer.bytes = 3.0 * (double)dsize(H.s) * (double)H.lv[0].total;
+    double cells = 0.0;
+    for (int64_t c : H.cells) cells += (double)c;
+    g_timer.bytes = 3.0 * (double)dsize(H.s) * cells;
     ev_used = 0;
   }
 };
@@ -668,7 +704,10 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
     const gd_slice_desc& d = sl[i];
     if (d.nx <= 0 || d.ny <= 0 || d.pitch < d.nx || d.offset < 0 || !(d.alpha > 0.0) || !std::isfinite(d.alpha))
       return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad slice descriptor " + std::to_string(i));
-    g.push_back({d.nx, d.ny, 1, (double)d.alpha, bx, by, 0.0, d.offset, d.pitch, (int64_t)d.pitch * d.ny});
+    // the slice's rows become the grid's z axis (one line per plane)
+    GridSpec sp{d.nx, 1, d.ny, (double)d.alpha, bx, 0.0, by, d.offset, d.pitch, d.pitch};
+    sp.zin = 1;
+    g.push_back(sp);
   }
   // slices must not overlap (compare row spans of slices sorted by offset)
   {
@@ -781,14 +820,16 @@ gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles, double
   Hier& H = *h->H;
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
-    const size_t bytes = H.lv[0].total * dsize(H.s);
     Level& L0 = H.lv[0];
+    const GridDesc& g0 = L0.h[0];
+    const size_t es = dsize(H.s);
+    const size_t wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es, rows = (size_t)g0.ny * g0.nz;
     Cycler cy(H, st, h->o);
     if (ncycles > 0) {
-      HIP_TRY(hipMemcpyAsync(L0.x, x, bytes, hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipMemcpyAsync(L0.b, b, bytes, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpy2DAsync(L0.x, pb, x, wb, wb, rows, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpy2DAsync(L0.b, pb, b, wb, wb, rows, hipMemcpyDeviceToDevice, st));
       for (int c = 0; c < ncycles; ++c) cy.full(0);
-      HIP_TRY(hipMemcpyAsync(x, L0.x, bytes, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpy2DAsync(x, wb, L0.x, pb, wb, rows, hipMemcpyDeviceToDevice, st));
     }
     if (relres) {
       HIP_TRY(launch_general_residual(H.s, H.g_ew(0), x, b, H.partials, st));
@@ -820,18 +861,19 @@ static gd_status one_grid(GridDesc& g, int64_t nx, int64_t ny, int64_t nz, int c
   g.cnx = (g.nx + cx - 1) / cx; g.cny = (g.ny + cy - 1) / cy; g.cnz = (g.nz + cz - 1) / cz;
   g.alpha = alpha; g.wx = wx; g.wy = wy; g.wz = wz;
   g.ipy = nx; g.ipz = nx * ny;
+  g.px = (int32_t)nx; g.cpx = g.cnx;  // the caller's arrays are unpadded
   return GD_OK;
 }
 
 // upload one grid + its table for kernel family (TX, TY, child) and return the geometry
 static Geom step_geom(const GridDesc& g, int TX, int TY, bool child, int64_t target, int64_t& nblocks,
-                      double** part, hipStream_t st) {
+                      double** part, hipStream_t st, bool even = false) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_step_mu);
   StepBuf& sb = g_step[dev];
   Tab t;
-  build_tab(t, {g}, TX, TY, child, target);
+  build_tab(t, {g}, TX, TY, child, target, even);
   nblocks = t.h_b0.back();
   const size_t bytes = sizeof(GridDesc) + 2 * sizeof(int64_t);
   if (sb.cap < bytes) {
@@ -855,6 +897,7 @@ static Geom step_geom(const GridDesc& g, int TX, int TY, bool child, int64_t tar
   geo.ngrids = 1;
   geo.nblocks = nblocks;
   geo.zlen = t.zlen;
+  geo.vec = (g.px % 2) == 0;
   *part = sb.part;
   return geo;
 }
@@ -865,13 +908,18 @@ gd_status gd_rb_sweep(const void* xin, void* xout, const void* b, gd_dtype s, in
   if (xin == xout || xout == b) return fail(GD_ERR_INVALID, "gd_rb_sweep: output aliases input");
   if (!valid_dtype(s)) return fail(GD_ERR_INVALID, "gd_rb_sweep: bad dtype");
   GridDesc g;
-  gd_status r = one_grid(g, nx, ny, nz, 1, 1, 1, alpha, wx, wy, wz);
+  // a single slice (nz == 1) runs in the one-line form: its rows become z
+  const bool slice = nz == 1 && ny > 1;
+  gd_status r = slice ? one_grid(g, nx, 1, ny, 1, 1, 1, alpha, wx, 0.0, wy)
+                      : one_grid(g, nx, ny, nz, 1, 1, 1, alpha, wx, wy, wz);
   if (r != GD_OK) return r;
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     int64_t nb;
     double* part;
-    Geom geo = step_geom(g, SW_TX, SW_TY, false, 2048, nb, &part, st);
+    Geom geo = slice ? step_geom(g, SWR_TX, 1, false, sweep_target(), nb, &part, st)
+                     : step_geom(g, SW_TX, SW_TY, false, sweep_target(), nb, &part, st);
+    geo.row = slice;
     HIP_TRY(launch_rb_sweep(s, geo, xin, xout, b, nullptr, 0, st));
     HIP_TRY(hipStreamSynchronize(st));
     return GD_OK;
@@ -885,14 +933,18 @@ gd_status gd_residual_restrict(const void* x, const void* b, void* bc, gd_dtype 
   if (bc == x || bc == b) return fail(GD_ERR_INVALID, "gd_residual_restrict: output aliases input");
   if (!valid_dtype(s)) return fail(GD_ERR_INVALID, "gd_residual_restrict: bad dtype");
   GridDesc g;
-  gd_status r = one_grid(g, nx, ny, nz, cx, cy, cz, alpha, wx, wy, wz);
+  const bool slice = nz == 1 && ny > 1;  // one-line form, rows as z
+  gd_status r = slice ? one_grid(g, nx, 1, ny, cx, 1, cy, alpha, wx, 0.0, wy)
+                      : one_grid(g, nx, ny, nz, cx, cy, cz, alpha, wx, wy, wz);
   if (r != GD_OK) return r;
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     int64_t nb;
     double* part;
-    Geom geo = step_geom(g, EW_TX, EW_TY, true, 8192, nb, &part, st);
-    HIP_TRY(launch_residual_restrict(s, geo, x, b, bc, nullptr, part, st));
+    Geom geo = slice ? step_geom(g, SWR_TX, 1, false, 4096, nb, &part, st, true)
+                     : step_geom(g, SW_TX, SW_TY, false, 2048, nb, &part, st, true);
+    geo.row = slice;
+    HIP_TRY(launch_restrict_z(s, geo, x, b, bc, nullptr, part, st));
     if (norm2) {
       std::vector<double> h(nb);
       HIP_TRY(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st));

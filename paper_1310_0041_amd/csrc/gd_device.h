@@ -20,7 +20,9 @@ struct GridDesc {
   int32_t nx, ny, nz;
   int32_t cnx, cny, cnz;  // child grid size
   int32_t fx, fy, fz;     // coarsening factor per axis (1 or 2)
-  int32_t pad_;
+  int32_t px;             // x pitch of this level's arrays (>= nx)
+  int32_t cpx;            // x pitch of the child grid's arrays
+  int32_t zin;            // 1: a 2-D slice seen as nz rows of one line (z is in-slice)
   double alpha, wx, wy, wz;  // operator alpha*Id + sum_a w_a L_a of this level
 };
 
@@ -46,6 +48,53 @@ template <> struct Ty<__hip_bfloat16> {
   static __device__ __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
   static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
 };
+
+// Two consecutive values (p aligned to two elements when vec).
+template <typename S>
+__device__ __forceinline__ void ld2(const S* p, bool vec, bool second, typename Ty<S>::C& a,
+                                    typename Ty<S>::C& b) {
+  using C = typename Ty<S>::C;
+  if (vec) {
+    if constexpr (sizeof(S) == 8) {
+      const double2 v = *reinterpret_cast<const double2*>(p);
+      a = (C)v.x; b = (C)v.y;
+    } else if constexpr (sizeof(S) == 4) {
+      const float2 v = *reinterpret_cast<const float2*>(p);
+      a = (C)v.x; b = (C)v.y;
+    } else {
+      const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+      S lo, hi;
+      const uint16_t l16 = (uint16_t)(v & 0xffffu), h16 = (uint16_t)(v >> 16);
+      __builtin_memcpy(&lo, &l16, 2);
+      __builtin_memcpy(&hi, &h16, 2);
+      a = Ty<S>::ld(&lo); b = Ty<S>::ld(&hi);
+    }
+  } else {
+    a = Ty<S>::ld(p);
+    b = second ? Ty<S>::ld(p + 1) : (C)0;
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void st2(S* p, bool vec, bool second, typename Ty<S>::C a, typename Ty<S>::C b) {
+  if (vec) {
+    if constexpr (sizeof(S) == 8) {
+      *reinterpret_cast<double2*>(p) = make_double2((double)a, (double)b);
+    } else if constexpr (sizeof(S) == 4) {
+      *reinterpret_cast<float2*>(p) = make_float2((float)a, (float)b);
+    } else {
+      S lo, hi;
+      Ty<S>::st(&lo, a); Ty<S>::st(&hi, b);
+      uint16_t l16, h16;
+      __builtin_memcpy(&l16, &lo, 2);
+      __builtin_memcpy(&h16, &hi, 2);
+      *reinterpret_cast<uint32_t*>(p) = (uint32_t)l16 | ((uint32_t)h16 << 16);
+    }
+  } else {
+    Ty<S>::st(p, a);
+    if (second) Ty<S>::st(p + 1, b);
+  }
+}
 
 // Exact upcast to double (every storage type embeds in binary64).
 template <typename T> __device__ __forceinline__ double ld64(const T* p) { return (double)Ty<T>::ld(p); }

@@ -10,8 +10,10 @@
 namespace gd {
 
 // Tile shapes of the kernel families.
-constexpr int SW_TX = 64, SW_TY = 8;   // relaxation: interior tile, 256 threads
-constexpr int EW_TX = 64, EW_TY = 4;   // per-voxel kernels: 256 threads
+constexpr int SW_TX = 64, SW_TY = 8;   // relaxation tile of 3-D grids, 256 threads (one x-pair each)
+constexpr int SWR_TX = 256;            // relaxation tile of one-line grids (2-D slices), 128 threads
+constexpr int EW_TX = 64, EW_TY = 4;   // per-voxel kernels on 3-D grids: 256 threads
+constexpr int EWR_TX = 256;            // per-voxel kernels on one-line grids
 
 // A launch over the grids of one level: blocks [block0[g], block0[g+1])
 // belong to grid g; each block covers one (x, y) tile and `zlen` planes.
@@ -21,12 +23,17 @@ struct Geom {
   int ngrids = 0;
   int64_t nblocks = 0;
   int zlen = 1;
+  int etx = EW_TX;   // per-voxel kernels: tile etx x (256 / etx)
+  bool row = false;  // relaxation: one-line (slice) tiles
+  bool vec = true;   // every grid's pitch and offset are even (x pairs aligned)
 };
 
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
                            const void* e_coarse, int prolong_mode, hipStream_t st);
-hipError_t launch_residual_restrict(gd_dtype s, const Geom& gc, const void* x, const void* b,
-                                    void* b_coarse, void* x_coarse, double* partials, hipStream_t st);
+// Residual + restriction (tiles as the relaxation, zlen even); per-block
+// sum r^2 into partials when non-NULL, coarse x zeroed when non-NULL.
+hipError_t launch_restrict_z(gd_dtype s, const Geom& g, const void* x, const void* b, void* b_coarse,
+                             void* x_coarse, double* partials, hipStream_t st);
 hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* e_coarse, void* x, int mode,
                               hipStream_t st);
 // Finest level of the AD/SP systems in correction form: b = alpha (I1 - I0)

@@ -4,6 +4,11 @@
 // stencil).  Every level operator is alpha*Id + sum_a w_a L_a, L_a the
 // 3-point Neumann second difference along axis a (no faces outside the grid).
 //
+// Layout: a grid's array is [nz][ny][px] with x pitch px >= nx (the library's
+// own arrays pad px to a multiple of 4 so that x pairs are aligned; arrays
+// given by a caller use px = nx).  A 2-D slice is described as nz = its rows,
+// ny = 1, so that every kernel marches along the slowest axis.
+//
 // All stencils are evaluated in difference form, sum_nb w (x_nb - x_c), which
 // keeps the rounding error proportional to the local variation instead of
 // the magnitude of x.
@@ -32,261 +37,614 @@ struct Tile {
   int g, x0, y0, z0, z1;
 };
 
-// Decode blockIdx.x into (grid, tile, z-range) for TX x TY tiles over the
+// Decode blockIdx.x into (grid, tile, z-range) for tx x ty tiles over the
 // grid's own size (coarse = false) or its child's size (coarse = true).
-template <int TX, int TY>
-__device__ __forceinline__ Tile decode_tile(const GridDesc* __restrict__ grids,
-                                            const int64_t* __restrict__ block0, int ngrids,
-                                            int zlen, bool coarse) {
+__device__ __forceinline__ Tile decode_tile(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0,
+                                            int ngrids, int zlen, int tx_, int ty_, bool coarse) {
   Tile t;
   const int64_t bid = blockIdx.x;
   t.g = find_grid(block0, ngrids, bid);
   const GridDesc& G = grids[t.g];
   const int nx = coarse ? G.cnx : G.nx, ny = coarse ? G.cny : G.ny, nz = coarse ? G.cnz : G.nz;
   const int64_t local = bid - block0[t.g];
-  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  const int tx = (nx + tx_ - 1) / tx_, ty = (ny + ty_ - 1) / ty_;
   const int64_t txy = (int64_t)tx * ty;
   const int zc = (int)(local / txy);
   const int r = (int)(local - (int64_t)zc * txy);
-  t.x0 = (r % tx) * TX;
-  t.y0 = (r / tx) * TY;
+  t.x0 = (r % tx) * tx_;
+  t.y0 = (r / tx) * ty_;
   t.z0 = zc * zlen;
   t.z1 = min(t.z0 + zlen, nz);
   return t;
 }
 
-// Cell-centred linear up-sampling weights along one axis: the fine cell i of
-// a halved axis takes 3/4 of its parent i/2 and 1/4 of the nearer coarse
-// neighbour, the parent itself standing in for a neighbour outside the grid;
-// a kept axis (f == 1) maps i to i.
-__device__ __forceinline__ void lin_idx(int i, int f, int nc, int& a, int& b) {
-  if (f == 1) { a = b = i; return; }
+// Cell-centred linear up-sampling along one axis: the fine cell i of a
+// halved axis takes 3/4 of its parent i/2 and 1/4 of the nearer coarse
+// neighbour; where that neighbour is outside the grid the parent takes weight
+// 1 (mirror boundary).  A kept axis (f == 1) maps i to i with weight 1.
+// two == false means the single index a carries weight 1.
+__device__ __forceinline__ bool lin_idx(int i, int f, int nc, int& a, int& b) {
+  if (f == 1) { a = b = i; return false; }
   a = i >> 1;
   b = (i & 1) ? a + 1 : a - 1;
-  if (b < 0 || b >= nc) b = a;
+  if (b < 0 || b >= nc) { b = a; return false; }
+  return true;
 }
 
-// Value of the up-sampled coarse correction at fine cell (i, j, k) of grid G.
+template <typename C>
+__device__ __forceinline__ C lin_mix(bool two, C va, C vb) {
+  return two ? (C)0.75 * va + (C)0.25 * vb : va;
+}
+
+// Value of the up-sampled coarse correction at fine cell (i, j, k) of grid G:
+// x first, then y, then z (prolong_pair evaluates the same expression).
 template <typename S>
 __device__ __forceinline__ typename Ty<S>::C prolong_value(const S* __restrict__ ec, const GridDesc& G,
                                                           int i, int j, int k, int mode) {
   using C = typename Ty<S>::C;
   const S* e = ec + G.coff;
-  const int64_t cpl = (int64_t)G.cnx * G.cny;
+  const int64_t cpl = (int64_t)G.cpx * G.cny;
   if (mode == 1) {
-    return Ty<S>::ld(e + (int64_t)(k / G.fz) * cpl + (int64_t)(j / G.fy) * G.cnx + (i / G.fx));
+    return Ty<S>::ld(e + (int64_t)(k / G.fz) * cpl + (int64_t)(j / G.fy) * G.cpx + (i / G.fx));
   }
   int ia, ib, ja, jb, ka, kb;
-  lin_idx(i, G.fx, G.cnx, ia, ib);
-  lin_idx(j, G.fy, G.cny, ja, jb);
-  lin_idx(k, G.fz, G.cnz, ka, kb);
-  const C wa = (C)0.75, wb = (C)0.25;
-  const S* pa = e + (int64_t)ka * cpl;
-  const S* pb = e + (int64_t)kb * cpl;
-  auto row = [&](const S* p, int jj) {
-    const S* q = p + (int64_t)jj * G.cnx;
-    return wa * Ty<S>::ld(q + ia) + wb * Ty<S>::ld(q + ib);
+  const bool tx = lin_idx(i, G.fx, G.cnx, ia, ib);
+  const bool ty = lin_idx(j, G.fy, G.cny, ja, jb);
+  const bool tz = lin_idx(k, G.fz, G.cnz, ka, kb);
+  auto row = [&](int kk, int jj) {
+    const S* q = e + (int64_t)kk * cpl + (int64_t)jj * G.cpx;
+    return lin_mix<C>(tx, Ty<S>::ld(q + ia), tx ? Ty<S>::ld(q + ib) : (C)0);
   };
-  const C za = wa * row(pa, ja) + wb * row(pa, jb);
-  const C zb = wa * row(pb, ja) + wb * row(pb, jb);
-  return wa * za + wb * zb;
+  auto plane = [&](int kk) { return lin_mix<C>(ty, row(kk, ja), ty ? row(kk, jb) : (C)0); };
+  return lin_mix<C>(tz, plane(ka), tz ? plane(kb) : (C)0);
+}
+
+// The same for the x-pair (i, i + 1), i even, of the library's arrays (child
+// pitch a multiple of 4): the pair shares its coarse rows.
+template <typename S>
+__device__ __forceinline__ void prolong_pair(const S* __restrict__ ec, const GridDesc& G, int i, int j, int k,
+                                             int mode, typename Ty<S>::C& va, typename Ty<S>::C& vb) {
+  using C = typename Ty<S>::C;
+  const S* e = ec + G.coff;
+  const int64_t cpl = (int64_t)G.cpx * G.cny;
+  if (mode == 1) {
+    const S* r = e + (int64_t)(k / G.fz) * cpl + (int64_t)(j / G.fy) * G.cpx;
+    va = Ty<S>::ld(r + i / G.fx);
+    vb = Ty<S>::ld(r + (i + 1) / G.fx);
+    return;
+  }
+  int ja, jb, ka, kb;
+  const bool ty = lin_idx(j, G.fy, G.cny, ja, jb);
+  const bool tz = lin_idx(k, G.fz, G.cnz, ka, kb);
+  int iaA, ibA, iaB, ibB;
+  const bool txA = lin_idx(i, G.fx, G.cnx, iaA, ibA);
+  const bool txB = lin_idx(i + 1, G.fx, G.cnx, iaB, ibB);
+  auto rows = [&](int kk, int jj, C& ra, C& rb) {
+    const S* q = e + (int64_t)kk * cpl + (int64_t)jj * G.cpx;
+    if (G.fx == 1) {
+      ld2(q + i, true, true, ra, rb);  // kept axis: weight 1 on i and i + 1
+    } else {
+      const C c0 = Ty<S>::ld(q + iaA);  // the pair's common parent
+      ra = lin_mix<C>(txA, c0, txA ? Ty<S>::ld(q + ibA) : (C)0);
+      rb = lin_mix<C>(txB, c0, txB ? Ty<S>::ld(q + ibB) : (C)0);
+    }
+  };
+  auto planes = [&](int kk, C& pa, C& pb) {
+    C a0, b0, a1 = 0, b1 = 0;
+    rows(kk, ja, a0, b0);
+    if (ty) rows(kk, jb, a1, b1);
+    pa = lin_mix<C>(ty, a0, a1);
+    pb = lin_mix<C>(ty, b0, b1);
+  };
+  C a0, b0, a1 = 0, b1 = 0;
+  planes(ka, a0, b0);
+  if (tz) planes(kb, a1, b1);
+  va = lin_mix<C>(tz, a0, a1);
+  vb = lin_mix<C>(tz, b0, b1);
 }
 
 // ------------------------------------------------------- red-black sweep
 //
 // One complete red-black Gauss-Seidel sweep (Sec. 4.1, multi-coloured GS),
 // out of place: reads x_in, writes x_out.  A block owns a TX x TY column of
-// the grid and marches along z, keeping four planes of x (with a 2-cell
-// in-plane halo) and four planes of b (1-cell halo) in LDS:
-//   step p:  red voxels of plane p on the tile plus a 1-cell ring (from
-//            old black values), then black voxels of plane p - 1 on the tile
-//            (from the new red values of planes p-2..p), then plane p - 1 is
-//            written and plane p + 2 enters the ring.
+// the grid and marches along z.  Thread t owns the x-pair (x0 + 2 (t mod
+// TX/2), y0 + t / (TX/2)) and its two neighbours along x: in every plane one
+// of the pair is red and the other black, and the z-neighbours of a cell are
+// cells of the same column, so each thread keeps its column of planes
+// p-2 .. p+2 in registers and only the in-plane neighbours go through LDS
+// (four planes, with a 2-cell halo ring loaded by the threads in turn).
+//   step p:  red cells of plane p (own pair and the 1-cell ring around the
+//            tile, from old black values) | barrier | black cells of plane
+//            p - 1 (from the new red values of planes p-2..p), plane p - 1
+//            written, plane p + 2 enters LDS | barrier
 // Recomputing the red ring makes every tile independent of its neighbours,
 // so blocks never exchange data and the sweep equals the sequential
-// definition exactly.  When e_coarse != NULL the prolongated coarse
-// correction is added to x while it is loaded (fused up-sampling).
+// definition exactly.  When e_coarse != NULL the up-sampled coarse
+// correction is added to x while it is loaded (fused prolongation).
+// TY == 1 is the row form for grids with ny == 1 (2-D slices).
 
-template <typename S>
-__global__ void __launch_bounds__(256)
-k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids,
-           int zlen, const S* __restrict__ xin, S* __restrict__ xout, const S* __restrict__ bin,
+template <int TX, int TY>
+struct SweepShape {
+  static constexpr bool ROW = (TY == 1);
+  static constexpr int NT = TX * TY / 2;                 // threads: one x-pair each
+  static constexpr int YO = ROW ? 0 : 2;                 // tile row 0 inside the LDS plane
+  static constexpr int HX = TX + 4, HY = ROW ? 1 : TY + 4;
+  static constexpr int NHALO = HX * HY - TX * TY;        // halo cells per plane
+  static constexpr int NHR = (NHALO + NT - 1) / NT;      // halo cells per thread
+  static constexpr int NRING = ROW ? 1 : (TX + 2) + TY;  // red ring-1 cells per plane
+};
+
+// LDS coordinates of halo cell h (everything of the HY x HX plane outside the tile)
+template <int TX, int TY>
+__device__ __forceinline__ void halo_cell(int h, int& hy, int& hx) {
+  using SS = SweepShape<TX, TY>;
+  if constexpr (SS::ROW) {
+    hy = 0;
+    hx = (h < 2) ? h : TX + h;  // 0, 1, TX + 2, TX + 3
+  } else {
+    constexpr int HX = SS::HX;
+    if (h < 2 * HX) { hy = h / HX; hx = h - hy * HX; return; }
+    h -= 2 * HX;
+    if (h < 2 * HX) { hy = TY + 2 + h / HX; hx = h - (h / HX) * HX; return; }
+    h -= 2 * HX;
+    hy = 2 + (h >> 2);
+    const int c = h & 3;
+    hx = (c < 2) ? c : TX + c;  // 0, 1, TX + 2, TX + 3
+  }
+}
+
+// LDS coordinates of the m-th red cell of the 1-cell ring at plane p
+template <int TX, int TY>
+__device__ __forceinline__ void ring_red_cell(int m, int x0, int y0, int p, int& hy, int& hx) {
+  using SS = SweepShape<TX, TY>;
+  if constexpr (SS::ROW) {
+    // cells x0 - 1 and x0 + TX of the single row; exactly one is red
+    hy = 0;
+    hx = ((x0 - 1 + p) & 1) == 0 ? 1 : TX + 2;
+    (void)m; (void)y0;
+  } else {
+    constexpr int HALF = (TX + 2) / 2;
+    if (m < 2 * HALF) {  // top (hy = 1) or bottom (hy = TY + 2) row, hx in 1 .. TX + 2
+      hy = (m < HALF) ? 1 : TY + 2;
+      const int k = (m < HALF) ? m : m - HALF;
+      const int s = (x0 + y0 - 2 + hy + p) & 1;  // parity hx must have
+      hx = (s ? 1 : 2) + 2 * k;
+    } else {  // left (hx = 1) or right (hx = TX + 2) column, hy in 2 .. TY + 1
+      const int k = m - 2 * HALF;
+      const int HC = TY / 2;
+      hx = (k < HC) ? 1 : TX + 2;
+      const int kk = (k < HC) ? k : k - HC;
+      const int s = (x0 - 2 + hx + y0 - 2 + p) & 1;
+      hy = 2 + s + 2 * kk;
+    }
+  }
+}
+
+// Work split of the 1-cell ring and the halo over the waves of a block, so
+// that every wave gets the same share.
+template <int N, int NT>
+struct WaveSplit {
+  static constexpr int NW = NT / 64;
+  static constexpr int PER = (N + NW - 1) / NW;  // items per wave (<= 64 by construction)
+  static __device__ __forceinline__ int item(int tid) {  // -1: none
+    const int w = tid >> 6, l = tid & 63;
+    const int m = w * PER + l;
+    return (l < PER && m < N) ? m : -1;
+  }
+};
+
+template <typename S, int TX, int TY, bool FP, bool VEC>
+__global__ void __launch_bounds__(TX * TY / 2)
+k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+           const S* __restrict__ xin, S* __restrict__ xout, const S* __restrict__ bin,
            const S* __restrict__ ec, int pmode) {
   using C = typename Ty<S>::C;
-  constexpr int TX = SW_TX, TY = SW_TY;
-  constexpr int HX = TX + 4, HY = TY + 4;   // x tile with 2-cell halo
-  constexpr int BX = TX + 2, BY = TY + 2;   // b tile with 1-cell halo
-  constexpr int NXL = (HX * HY + 255) / 256;
-  constexpr int NBL = (BX * BY + 255) / 256;
-  __shared__ C X[4][HY][HX];
-  __shared__ C B[4][BY][BX];
+  using SS = SweepShape<TX, TY>;
+  constexpr int NT = SS::NT, YO = SS::YO, HX = SS::HX, HY = SS::HY, NHR = SS::NHR;
+  constexpr int PLANE = HX * HY;
+  constexpr bool ROW = SS::ROW;
+  using Ring = WaveSplit<SS::NRING, NT>;
+  static_assert(Ring::PER <= 64, "ring share per wave");
+  __shared__ C X[4 * PLANE];
 
-  const Tile t = decode_tile<TX, TY>(grids, block0, ngrids, zlen, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
-  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
-  const int64_t pl = (int64_t)nx * ny;
+  const int64_t pl = (int64_t)px * ny;
   const S* xg = xin + G.off;
   const S* bg = bin + G.off;
   S* xo = xout + G.off;
   const int tid = threadIdx.x;
   const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
 
-  C rx[NXL], rb[NBL];
-  auto fetch = [&](int q) {  // global -> registers, plane q (x) and q - 1 (b)
+  // ---- own pair (gx, gx + 1) of row gy
+  const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
+  const int gx = x0 + 2 * pxl, gy = y0 + tyl;
+  const bool rowok = gy < ny;
+  const bool vA = rowok && gx < nx, vB = rowok && gx + 1 < nx;
+  const int lo = (YO + tyl) * HX + 2 + 2 * pxl;  // LDS index of gx inside a plane
+  const int own = gy * px + gx;                 // element offset inside a plane (< 2^31)
+  const C wU = (gy > 0) ? wy : (C)0, wD = (gy + 1 < ny) ? wy : (C)0;
+  // per plane parity par = p & 1 the red cell of the pair is at position cp = (gy + par) & 1
+  int offO[2], offY[2];
+  C wO[2], wP[2], invI[2], dxy[2];
+  bool vR[2];
 #pragma unroll
-    for (int k = 0; k < NXL; ++k) {
-      const int i = tid + 256 * k;
-      const int hy = i / HX, hx = i - hy * HX;
-      const int gx = x0 - 2 + hx, gy = y0 - 2 + hy;
-      C v = (C)0;
-      if (i < HX * HY && q >= 0 && q < nz && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-        v = Ty<S>::ld(xg + q * pl + (int64_t)gy * nx + gx);
-        if (ec) v += prolong_value<S>(ec, G, gx, gy, q, pmode);
+  for (int par = 0; par < 2; ++par) {
+    const int cp = (gy + par) & 1;
+    offO[par] = cp ? lo + 2 : lo - 1;
+    offY[par] = lo + cp;
+    wO[par] = (cp ? (gx + 2 < nx) : (gx > 0)) ? wx : (C)0;
+    wP[par] = (cp ? true : vB) ? wx : (C)0;
+    vR[par] = cp ? vB : vA;  // the red cell of plane p (and black cell of plane p - 1) exists
+    dxy[par] = alpha + wO[par] + wP[par] + wU + wD;
+    const C di = dxy[par] + (nz > 1 ? 2 * wz : (C)0);
+    invI[par] = di > (C)0 ? (C)1 / di : (C)0;
+  }
+
+  // ---- halo cells of this thread (loaded every plane)
+  int hoff[NHR], hg[NHR];
+  bool hv[NHR], hs[NHR];
+#pragma unroll
+  for (int k = 0; k < NHR; ++k) {
+    int h;
+    if (k < NHR - 1) {
+      h = tid + NT * k;
+    } else {  // last round: spread the remainder over the waves
+      const int m = WaveSplit<SS::NHALO - NT * (NHR - 1), NT>::item(tid);
+      h = m < 0 ? -1 : NT * k + m;
+    }
+    int hy = 0, hx = 0;
+    if (h >= 0) halo_cell<TX, TY>(h, hy, hx);
+    const int cx = x0 - 2 + hx, cy = y0 - YO + hy;
+    hs[k] = h >= 0;
+    hv[k] = h >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    hoff[k] = hy * HX + hx;
+    hg[k] = hv[k] ? cy * px + cx : 0;
+  }
+
+  // ---- ring red cell of this thread, for each plane parity
+  const int rm = Ring::item(tid);
+  int ro[2], rg[2];
+  bool rv[2];
+  C rwl[2], rwr[2], rwu[2], rwd[2], rdxy[2];
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    int hy = 0, hx = 0;
+    if (rm >= 0) ring_red_cell<TX, TY>(rm, x0, y0, par, hy, hx);
+    const int cx = x0 - 2 + hx, cy = y0 - YO + hy;
+    rv[par] = rm >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    ro[par] = hy * HX + hx;
+    rg[par] = rv[par] ? cy * px + cx : 0;
+    rwl[par] = cx > 0 ? wx : (C)0;
+    rwr[par] = cx < nx - 1 ? wx : (C)0;
+    rwu[par] = cy > 0 ? wy : (C)0;
+    rwd[par] = cy < ny - 1 ? wy : (C)0;
+    rdxy[par] = alpha + rwl[par] + rwr[par] + rwu[par] + rwd[par];
+  }
+
+  // ---- plane loads: x pair + halo (registers), b pair, ring b.  Two planes
+  // of x and b are in flight while a plane is relaxed; a loaded value is
+  // first touched one or two planes later, so the loads overlap the updates.
+  struct XSet { C a, b, h[NHR]; };
+  auto fetch_x = [&](int q, XSet& o) {
+    o.a = o.b = (C)0;
+#pragma unroll
+    for (int k = 0; k < NHR; ++k) o.h[k] = (C)0;
+    if (q >= 0 && q < nz) {
+      const S* P = xg + (int64_t)q * pl;
+      if (vA) {
+        ld2(P + own, VEC, vB, o.a, o.b);
+        if (FP) {
+          C pa, pb;
+          prolong_pair<S>(ec, G, gx, gy, q, pmode, pa, pb);
+          o.a += pa;
+          o.b += pb;
+        }
       }
-      rx[k] = v;
-    }
-    const int qb = q - 1;
 #pragma unroll
-    for (int k = 0; k < NBL; ++k) {
-      const int i = tid + 256 * k;
-      const int by = i / BX, bx = i - by * BX;
-      const int gx = x0 - 1 + bx, gy = y0 - 1 + by;
-      C v = (C)0;
-      if (i < BX * BY && qb >= 0 && qb < nz && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-        v = Ty<S>::ld(bg + qb * pl + (int64_t)gy * nx + gx);
-      rb[k] = v;
+      for (int k = 0; k < NHR; ++k) {
+        if (hv[k]) {
+          C v = Ty<S>::ld(P + hg[k]);
+          if (FP) v += prolong_value<S>(ec, G, x0 - 2 + hoff[k] % HX, y0 - YO + hoff[k] / HX, q, pmode);
+          o.h[k] = v;
+        }
+      }
     }
   };
-  auto stash = [&](int q) {  // registers -> LDS slots of planes q (x), q - 1 (b)
-    const int sx = q & 3, sb = (q - 1) & 3;
+  auto stash = [&](int q, const XSet& o) {
+    C* P = X + (q & 3) * PLANE;
+    P[lo] = o.a;
+    P[lo + 1] = vB ? o.b : (C)0;
 #pragma unroll
-    for (int k = 0; k < NXL; ++k) {
-      const int i = tid + 256 * k;
-      if (i < HX * HY) (&X[sx][0][0])[i] = rx[k];
-    }
-#pragma unroll
-    for (int k = 0; k < NBL; ++k) {
-      const int i = tid + 256 * k;
-      if (i < BX * BY) (&B[sb][0][0])[i] = rb[k];
-    }
+    for (int k = 0; k < NHR; ++k)
+      if (hs[k]) P[hoff[k]] = o.h[k];
   };
-  // zero-residual update of the voxel at LDS x coords (hy, hx), plane p
-  auto relax = [&](int p, int hy, int hx, int by, int bx, int gx, int gy) {
-    const int s0 = p & 3;
-    const C xc = X[s0][hy][hx];
-    C r = B[s0][by][bx] - alpha * xc;
-    C d = alpha;
-    if (gx > 0) { r += wx * (X[s0][hy][hx - 1] - xc); d += wx; }
-    if (gx < nx - 1) { r += wx * (X[s0][hy][hx + 1] - xc); d += wx; }
-    if (gy > 0) { r += wy * (X[s0][hy - 1][hx] - xc); d += wy; }
-    if (gy < ny - 1) { r += wy * (X[s0][hy + 1][hx] - xc); d += wy; }
-    if (p > 0) { r += wz * (X[(p - 1) & 3][hy][hx] - xc); d += wz; }
-    if (p < nz - 1) { r += wz * (X[(p + 1) & 3][hy][hx] - xc); d += wz; }
-    X[s0][hy][hx] = d > (C)0 ? xc + r / d : (C)0;
+  // b pair of plane q (memory order, raw)
+  auto fetch_b = [&](int q, C& a, C& b) {
+    a = b = (C)0;
+    if (q >= 0 && q < nz && vA) ld2(bg + (int64_t)q * pl + own, VEC, vB, a, b);
+  };
+  auto ring_b = [&](int q) -> C {
+    const int par = q & 1;
+    if (q < 0 || q >= nz || !rv[par]) return (C)0;
+    return Ty<S>::ld(bg + (int64_t)q * pl + rg[par]);
+  };
+  // pair (in memory order) -> (red, black) of plane q
+  auto split = [&](int q, C a, C b, C& r, C& k) {
+    const bool cp = ((gy + q) & 1) != 0;
+    b = vB ? b : (C)0;
+    r = cp ? b : a;
+    k = cp ? a : b;
   };
 
+  // column registers (red R / black K of planes p-2 .. p+1), b of planes p-1, p
+  C Rm2 = 0, Km2 = 0, Rm1, Km1, R0, K0, Rp1, Kp1;
+  C bRm1, bKm1, bR0, bK0, ba0, bb0, ba1, bb1, rb, rb1, rb2;
+  XSet n0, n1;
   const int pfirst = max(q0 - 1, 0);
   const int plast = (q1 < nz) ? q1 : nz;  // p == nz: black of the last plane only
-  // prologue: x planes pfirst-1 .. pfirst+1 and b plane pfirst
-  fetch(pfirst - 1); stash(pfirst - 1);
-  fetch(pfirst);     stash(pfirst);
-  fetch(pfirst + 1); stash(pfirst + 1);
-  fetch(pfirst + 2);  // in flight: x plane pfirst+2, b plane pfirst+1
+  fetch_x(pfirst - 1, n0); stash(pfirst - 1, n0); split(pfirst - 1, n0.a, n0.b, Rm1, Km1);
+  fetch_x(pfirst, n0);     stash(pfirst, n0);     split(pfirst, n0.a, n0.b, R0, K0);
+  fetch_x(pfirst + 1, n0); stash(pfirst + 1, n0); split(pfirst + 1, n0.a, n0.b, Rp1, Kp1);
+  fetch_b(pfirst - 1, ba0, bb0); split(pfirst - 1, ba0, bb0, bRm1, bKm1);
+  fetch_b(pfirst, ba0, bb0);     split(pfirst, ba0, bb0, bR0, bK0);
+  rb = ring_b(pfirst);
+  fetch_x(pfirst + 2, n0);
+  fetch_x(pfirst + 3, n1);
+  fetch_b(pfirst + 1, ba0, bb0);
+  fetch_b(pfirst + 2, ba1, bb1);
+  rb1 = ring_b(pfirst + 1);
+  rb2 = ring_b(pfirst + 2);
 
   for (int p = pfirst; p <= plast; ++p) {
     __syncthreads();
-    if (p < nz) {  // red voxels of plane p on the tile and its 1-cell ring
-      for (int i = tid; i < BY * (BX / 2); i += 256) {
-        const int ry = i / (BX / 2), m = i - ry * (BX / 2);
-        const int gy = y0 - 1 + ry;
-        const int rxx = 2 * m + ((x0 - 1 + gy + p) & 1);
-        const int gx = x0 - 1 + rxx;
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) relax(p, ry + 1, rxx + 1, ry, rxx, gx, gy);
+    const int par = p & 1;
+    if (p < nz) {
+      // ---- red cells of plane p
+      C* P = X + (p & 3) * PLANE;
+      const C wzm = p > 0 ? wz : (C)0, wzp = p < nz - 1 ? wz : (C)0;
+      if (vR[par]) {
+        const C xc = R0;
+        C r = bR0 - alpha * xc;
+        r += wP[par] * (K0 - xc);
+        r += wO[par] * (P[offO[par]] - xc);
+        if (!ROW) {
+          r += wU * (P[offY[par] - HX] - xc);
+          r += wD * (P[offY[par] + HX] - xc);
+        }
+        r += wzm * (Km1 - xc);
+        r += wzp * (Kp1 - xc);
+        C inv = invI[par];
+        if (p == 0 || p == nz - 1) {
+          const C d = dxy[par] + wzm + wzp;
+          inv = d > (C)0 ? (C)1 / d : (C)0;
+        }
+        const C nv = inv != (C)0 ? xc + r * inv : (C)0;
+        R0 = nv;
+        P[offY[par]] = nv;
+      }
+      if (rv[par]) {  // red cell of the 1-cell ring
+        const int o = ro[par];
+        const C xc = P[o];
+        C r = rb - alpha * xc;
+        r += rwl[par] * (P[o - 1] - xc);
+        r += rwr[par] * (P[o + 1] - xc);
+        if (!ROW) {
+          r += rwu[par] * (P[o - HX] - xc);
+          r += rwd[par] * (P[o + HX] - xc);
+        }
+        if (p > 0) r += wz * (X[((p - 1) & 3) * PLANE + o] - xc);
+        if (p < nz - 1) r += wz * (X[((p + 1) & 3) * PLANE + o] - xc);
+        const C d = rdxy[par] + wzm + wzp;
+        P[o] = d > (C)0 ? xc + r / d : (C)0;
       }
     }
     __syncthreads();
-    const int q = p - 1;  // black voxels of plane q on the tile
-    const bool outq = q >= q0 && q < q1;
-    if (outq) {
-      for (int i = tid; i < TY * (TX / 2); i += 256) {
-        const int ty = i / (TX / 2), m = i - ty * (TX / 2);
-        const int gy = y0 + ty;
-        const int txx = 2 * m + ((x0 + gy + q + 1) & 1);
-        const int gx = x0 + txx;
-        if (gx < nx && gy < ny) relax(q, ty + 2, txx + 2, ty + 1, txx + 1, gx, gy);
+    const int q = p - 1;
+    if (q >= q0 && q < q1) {
+      // ---- black cells of plane q = p - 1 (same position as the red cell of plane p)
+      if (vR[par]) {
+        const C* P = X + (q & 3) * PLANE;
+        const C wzm = q > 0 ? wz : (C)0, wzp = q < nz - 1 ? wz : (C)0;
+        const C xc = Km1;
+        C r = bKm1 - alpha * xc;
+        r += wP[par] * (Rm1 - xc);
+        r += wO[par] * (P[offO[par]] - xc);
+        if (!ROW) {
+          r += wU * (P[offY[par] - HX] - xc);
+          r += wD * (P[offY[par] + HX] - xc);
+        }
+        r += wzm * (Rm2 - xc);
+        r += wzp * (R0 - xc);
+        C inv = invI[par];
+        if (q == 0 || q == nz - 1) {
+          const C d = dxy[par] + wzm + wzp;
+          inv = d > (C)0 ? (C)1 / d : (C)0;
+        }
+        Km1 = inv != (C)0 ? xc + r * inv : (C)0;
+      }
+      if (vA) {
+        const bool cq = ((gy + q) & 1) != 0;  // red position of plane q
+        st2(xo + (int64_t)q * pl + own, VEC, vB, cq ? Km1 : Rm1, cq ? Rm1 : Km1);
       }
     }
-    __syncthreads();
-    if (outq) {
-      for (int i = tid; i < TY * TX; i += 256) {
-        const int ty = i / TX, tx = i - ty * TX;
-        const int gx = x0 + tx, gy = y0 + ty;
-        if (gx < nx && gy < ny) Ty<S>::st(xo + q * pl + (int64_t)gy * nx + gx, X[q & 3][ty + 2][tx + 2]);
-      }
+    // ---- advance: plane p + 2 enters LDS, loads for p + 4 (x) and p + 3 (b) go out
+    stash(p + 2, n0);
+    Rm2 = Rm1; Km2 = Km1; Rm1 = R0; Km1 = K0; R0 = Rp1; K0 = Kp1;
+    split(p + 2, n0.a, n0.b, Rp1, Kp1);
+    bRm1 = bR0; bKm1 = bK0;
+    split(p + 1, ba0, bb0, bR0, bK0);
+    rb = rb1; rb1 = rb2;
+    n0 = n1;
+    ba0 = ba1; bb0 = bb1;
+    if (p + 2 <= plast) {
+      fetch_x(p + 4, n1);
+      fetch_b(p + 3, ba1, bb1);
+      rb2 = ring_b(p + 3);
     }
-    stash(p + 2);
-    if (p + 1 <= plast) fetch(p + 3);
   }
 }
 
-// ------------------------------------------- residual + restriction (gather)
+// ------------------------------------------------ residual + restriction
 //
-// One thread per coarse cell: the residual of each of its (up to 8) children
-// is evaluated and summed into the coarse right-hand side (the transpose of
-// piecewise-constant up-sampling), and the coarse unknown is zeroed.  The
-// per-block FP64 sum of r^2 over the fine cells feeds the residual norm.
-template <typename S>
-__global__ void __launch_bounds__(256)
-k_residual_restrict(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids,
-                    int zlen, const S* __restrict__ xin, const S* __restrict__ bin, S* __restrict__ bc,
-                    S* __restrict__ xc, double* __restrict__ partials) {
+// r = b - A x on the fine grid, summed into the coarse right-hand side (each
+// coarse cell the sum of its children: the transpose of piecewise-constant
+// up-sampling), the coarse unknown zeroed, and the per-block FP64 sum of r^2
+// over the fine cells for the residual norm.
+// A block owns a TX x TY fine tile and marches along z; thread t owns an
+// x-pair.  The pair's column (planes k-1, k, k+1) stays in registers and the
+// in-plane neighbours come from LDS (three planes, 1-cell halo ring).  The
+// residuals of the children are summed in the pair (f_x = 2), across the two
+// rows of a wave (f_y = 2, lanes l and l + 32) and over two planes (f_z = 2)
+// before the owner of the coarse cell writes it.  zlen is even.
+template <typename S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY / 2)
+k_restrict_z(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+             const S* __restrict__ xin, const S* __restrict__ bin, S* __restrict__ bc, S* __restrict__ xc,
+             double* __restrict__ partials) {
   using C = typename Ty<S>::C;
-  __shared__ double red[4];
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, true);
+  constexpr bool ROW = (TY == 1);
+  constexpr int NT = TX * TY / 2;
+  constexpr int YO = ROW ? 0 : 1;
+  constexpr int HX = TX + 2, HY = ROW ? 1 : TY + 2;
+  constexpr int NHALO = HX * HY - TX * TY;
+  constexpr int NHR = (NHALO + NT - 1) / NT;
+  static_assert(ROW || TX == 64, "row pairs of a wave: TX/2 == 32 lanes per row");
+  __shared__ C X[3][HY][HX];
+  __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
-  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
-  const int64_t pl = (int64_t)nx * ny;
-  const int64_t cpl = (int64_t)G.cnx * G.cny;
-  const S* x = xin + G.off;
-  const S* b = bin + G.off;
-  const int I = t.x0 + (threadIdx.x & 63), J = t.y0 + (threadIdx.x >> 6);
+  const int64_t pl = (int64_t)px * ny;
+  const int64_t cpl = (int64_t)G.cpx * G.cny;
+  const S* xg = xin + G.off;
+  const S* bg = bin + G.off;
+  const bool vec = ((px | G.off) & 1) == 0, cvec = ((G.cpx | G.coff) & 1) == 0;
+  const int tid = threadIdx.x;
+  const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
+  const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
+  const int gx = x0 + 2 * pxl, gy = y0 + tyl;
+  const bool rowok = gy < ny;
+  const bool vA = rowok && gx < nx, vB = rowok && gx + 1 < nx;
+  const int lx = 1 + 2 * pxl, ly = YO + tyl;
+  const int64_t own = (int64_t)gy * px + gx;
+  const bool up = gy > 0, dn = gy + 1 < ny, o0 = gx > 0, o1 = gx + 2 < nx;
+
+  int hoff[NHR];
+  int64_t hg[NHR];
+  bool hv[NHR];
+#pragma unroll
+  for (int k = 0; k < NHR; ++k) {
+    const int h = tid + NT * k;
+    int hy = 0, hx = 0;
+    if (ROW) {
+      hx = (h == 0) ? 0 : HX - 1;
+    } else if (h < HX) {
+      hy = 0; hx = h;
+    } else if (h < 2 * HX) {
+      hy = HY - 1; hx = h - HX;
+    } else {
+      const int m = h - 2 * HX;
+      hy = 1 + (m >> 1);
+      hx = (m & 1) ? HX - 1 : 0;
+    }
+    const int cx = x0 - 1 + hx, cy = y0 - YO + hy;
+    hv[k] = h < NHALO && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    hoff[k] = hy * HX + hx;
+    hg[k] = hv[k] ? (int64_t)cy * px + cx : 0;
+  }
+  C na = 0, nb = 0, nh[NHR];
+  auto fetch = [&](int q) {
+    na = nb = (C)0;
+    const bool okq = q >= 0 && q < nz;
+    if (okq && vA) ld2(xg + q * pl + own, vec, vB, na, nb);
+#pragma unroll
+    for (int k = 0; k < NHR; ++k) nh[k] = (okq && hv[k]) ? Ty<S>::ld(xg + q * pl + hg[k]) : (C)0;
+  };
+  auto stash = [&](int q) {
+    C* P = &X[((q % 3) + 3) % 3][0][0];
+    P[ly * HX + lx] = na;
+    P[ly * HX + lx + 1] = nb;
+#pragma unroll
+    for (int k = 0; k < NHR; ++k)
+      if (tid + NT * k < NHALO) P[hoff[k]] = nh[k];
+  };
+  auto fetch_b = [&](int q, C& a, C& b) {
+    a = b = (C)0;
+    if (q >= 0 && q < nz && vA) ld2(bg + q * pl + own, vec, vB, a, b);
+  };
+
+  C ma, mb, ca, cb, pa, pb, ba, bb, bna, bnb;
+  fetch(q0 - 1); ma = na; mb = nb;
+  fetch(q0); stash(q0); ca = na; cb = nb;
+  fetch_b(q0, ba, bb);
+  fetch(q0 + 1);
+  fetch_b(q0 + 1, bna, bnb);
   double nrm = 0.0;
-  if (I < G.cnx && J < G.cny) {
-    for (int K = t.z0; K < t.z1; ++K) {
-      C sum = (C)0;
-      for (int dz = 0; dz < G.fz; ++dz) {
-        const int k = K * G.fz + dz;
-        if (k >= nz) break;
-        for (int dy = 0; dy < G.fy; ++dy) {
-          const int j = J * G.fy + dy;
-          if (j >= ny) break;
-          for (int dx = 0; dx < G.fx; ++dx) {
-            const int i = I * G.fx + dx;
-            if (i >= nx) break;
-            const int64_t v = k * pl + (int64_t)j * nx + i;
-            const C xv = Ty<S>::ld(x + v);
-            C r = Ty<S>::ld(b + v) - alpha * xv;
-            if (i > 0) r += wx * (Ty<S>::ld(x + v - 1) - xv);
-            if (i < nx - 1) r += wx * (Ty<S>::ld(x + v + 1) - xv);
-            if (j > 0) r += wy * (Ty<S>::ld(x + v - nx) - xv);
-            if (j < ny - 1) r += wy * (Ty<S>::ld(x + v + nx) - xv);
-            if (k > 0) r += wz * (Ty<S>::ld(x + v - pl) - xv);
-            if (k < nz - 1) r += wz * (Ty<S>::ld(x + v + pl) - xv);
-            sum += r;
-            nrm += (double)r * (double)r;
-          }
+  C s0 = 0, s1 = 0;
+  for (int k = q0; k < q1; ++k) {
+    stash(k + 1);
+    pa = na; pb = nb;
+    fetch(k + 2);
+    __syncthreads();
+    const C* P = &X[k % 3][0][0];
+    const bool zm = k > 0, zp = k < nz - 1;
+    C ra = 0, rb = 0;
+    if (vA) {
+      const C xa = ca;
+      C r = ba - alpha * xa;
+      r += vB ? wx * (cb - xa) : (C)0;
+      r += o0 ? wx * (P[ly * HX + lx - 1] - xa) : (C)0;
+      r += up ? wy * (P[(ly - 1 + (ROW ? 1 : 0)) * HX + lx] - xa) : (C)0;
+      r += dn ? wy * (P[(ly + 1 - (ROW ? 1 : 0)) * HX + lx] - xa) : (C)0;
+      r += zm ? wz * (ma - xa) : (C)0;
+      r += zp ? wz * (pa - xa) : (C)0;
+      ra = r;
+    }
+    if (vB) {
+      const C xb = cb;
+      C r = bb - alpha * xb;
+      r += wx * (ca - xb);
+      r += o1 ? wx * (P[ly * HX + lx + 2] - xb) : (C)0;
+      r += up ? wy * (P[(ly - 1 + (ROW ? 1 : 0)) * HX + lx + 1] - xb) : (C)0;
+      r += dn ? wy * (P[(ly + 1 - (ROW ? 1 : 0)) * HX + lx + 1] - xb) : (C)0;
+      r += zm ? wz * (mb - xb) : (C)0;
+      r += zp ? wz * (pb - xb) : (C)0;
+      rb = r;
+    }
+    nrm += (double)ra * (double)ra + (double)rb * (double)rb;
+    if (G.fx == 2) s0 += ra + rb; else { s0 += ra; s1 += rb; }
+    if (G.fz == 1 || (k & 1) || k == nz - 1) {
+      // rows 2J and 2J + 1 sit in lanes l and l + 32 of one wave
+      if (!ROW && G.fy == 2) {
+        s0 += __shfl_down(s0, 32, 64);
+        s1 += __shfl_down(s1, 32, 64);
+      }
+      const bool owner = ROW || G.fy == 1 || (tyl & 1) == 0;
+      if (owner && vA) {
+        const int I = gx / G.fx, J = gy / G.fy, K = k / G.fz;
+        const int64_t cv = G.coff + K * cpl + (int64_t)J * G.cpx + I;
+        if (G.fx == 2) {
+          Ty<S>::st(bc + cv, s0);
+          if (xc) Ty<S>::st(xc + cv, (C)0);
+        } else {
+          st2(bc + cv, cvec, vB, s0, s1);
+          if (xc) st2(xc + cv, cvec, vB, (C)0, (C)0);
         }
       }
-      const int64_t cv = G.coff + K * cpl + (int64_t)J * G.cnx + I;
-      Ty<S>::st(bc + cv, sum);
-      if (xc) Ty<S>::st(xc + cv, (C)0);
+      s0 = s1 = (C)0;
     }
+    ma = ca; mb = cb; ca = pa; cb = pb;
+    ba = bna; bb = bnb;
+    fetch_b(k + 2, bna, bnb);
   }
   if (partials) {
-    const double s = block_sum(nrm, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    const double sm = block_sum(nrm, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = sm;
   }
 }
 
@@ -294,15 +652,15 @@ k_residual_restrict(const GridDesc* __restrict__ grids, const int64_t* __restric
 template <typename S>
 __global__ void __launch_bounds__(256)
 k_prolong_add(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
-              const S* __restrict__ ec, S* __restrict__ xio, int mode) {
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+              int etx, const S* __restrict__ ec, S* __restrict__ xio, int mode) {
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   if (i >= G.nx || j >= G.ny) return;
-  const int64_t pl = (int64_t)G.nx * G.ny;
+  const int64_t pl = (int64_t)G.px * G.ny;
   S* x = xio + G.off;
   for (int k = t.z0; k < t.z1; ++k) {
-    const int64_t v = k * pl + (int64_t)j * G.nx + i;
+    const int64_t v = k * pl + (int64_t)j * G.px + i;
     Ty<S>::st(x + v, Ty<S>::ld(x + v) + prolong_value<S>(ec, G, i, j, k, mode));
   }
 }
@@ -310,46 +668,52 @@ k_prolong_add(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 // ------------------------------------------- finest level of AD / SP (Eq. 1, 2)
 //
 // Canonical system of both phases: A = alpha + w_x L_x + w_y L_y + w_z L_z,
-// b = alpha I1 + (w_x L_x + w_y L_y) I0 (AD: alpha = 0; SP: w_z = 0).  The
-// plain solver iterates on the correction E = x - I0, whose right-hand side
-// is b - A I0 = alpha (I1 - I0) - w_z L_z I0.
+// b = alpha I1 + (w_x L_x + w_y L_y) I0 (AD: alpha = 0; SP: w_z = 0).  In
+// the grid description the caller's y axis is the grid's y axis for a stack
+// and its z axis for a slice (ny = 1); the in-slice weights are then w_x and
+// w_z.  GridDesc::zin flags the slice form.
+// The plain solver iterates on the correction E = x - I0, whose right-hand
+// side is b - A I0 = alpha (I1 - I0) - (cross-slice part of A) I0.
 
 template <typename Tin>
 __device__ __forceinline__ double in_at(const Tin* p, int64_t v) { return ld64(p + v); }
 
 template <typename Tin, typename S>
 __global__ void __launch_bounds__(256)
-k_rhs_corr(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+k_rhs_corr(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
            const Tin* __restrict__ I0, const Tin* __restrict__ I1, S* __restrict__ bout,
            S* __restrict__ xout, double* __restrict__ partials) {
   __shared__ double red[4];
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
   const int nx = G.nx, ny = G.ny, nz = G.nz;
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const bool slice = G.zin != 0;  // 2-D slice form
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   double nrm = 0.0;
   if (i < nx && j < ny) {
-    const int64_t pl = (int64_t)nx * ny;
+    const int64_t pl = (int64_t)G.px * ny;
     for (int k = t.z0; k < t.z1; ++k) {
       const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
       const double c = in_at(I0, u);
-      double lxy = 0.0, lz = 0.0;
-      if (i > 0) lxy += G.wx * (c - in_at(I0, u - 1));
-      if (i < nx - 1) lxy += G.wx * (c - in_at(I0, u + 1));
-      if (j > 0) lxy += G.wy * (c - in_at(I0, u - G.ipy));
-      if (j < ny - 1) lxy += G.wy * (c - in_at(I0, u + G.ipy));
+      double lin = 0.0, lcross = 0.0;  // in-slice and cross-slice second differences
+      if (i > 0) lin += G.wx * (c - in_at(I0, u - 1));
+      if (i < nx - 1) lin += G.wx * (c - in_at(I0, u + 1));
+      if (j > 0) lin += G.wy * (c - in_at(I0, u - G.ipy));
+      if (j < ny - 1) lin += G.wy * (c - in_at(I0, u + G.ipy));
       if (G.wz != 0.0) {
-        if (k > 0) lz += in_at(I0, u - G.ipz) - c;
-        if (k < nz - 1) lz += in_at(I0, u + G.ipz) - c;
+        double lz = 0.0;
+        if (k > 0) lz += c - in_at(I0, u - G.ipz);
+        if (k < nz - 1) lz += c - in_at(I0, u + G.ipz);
+        if (slice) lin += G.wz * lz; else lcross += G.wz * lz;
       }
-      double bcan = lxy, bcorr = G.wz * lz;
+      double bcan = lin, bcorr = -lcross;
       if (G.alpha != 0.0) {
         const double v1 = in_at(I1, u);
         bcan += G.alpha * v1;
         bcorr += G.alpha * (v1 - c);
       }
       nrm += bcan * bcan;
-      const int64_t v = G.off + k * pl + (int64_t)j * nx + i;
+      const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
       if (bout) st64(bout + v, bcorr);
       if (xout) st64(xout + v, 0.0);
     }
@@ -370,33 +734,38 @@ __device__ __forceinline__ double xval(const Tin* I0, const S* E, const double* 
 template <typename Tin, typename S, int MODE>
 __global__ void __launch_bounds__(256)
 k_canon_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids,
-                 int zlen, const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
+                 int zlen, int etx, const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
                  const double* __restrict__ x64, S* __restrict__ rout, const double* __restrict__ inv_scale,
                  double* __restrict__ partials) {
   __shared__ double red[4];
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
-  const int nx = G.nx, ny = G.ny, nz = G.nz;
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
+  const bool slice = G.zin != 0;
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   const S* Eg = (MODE == 0) ? E + G.off : E;
   const double* xg = (MODE == 1) ? x64 + G.off : x64;
   double nrm = 0.0;
   if (i < nx && j < ny) {
-    const int64_t pl = (int64_t)nx * ny;
+    const int64_t pl = (int64_t)px * ny;
     for (int k = t.z0; k < t.z1; ++k) {
       const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
-      const int64_t v = k * pl + (int64_t)j * nx + i;
+      const int64_t v = k * pl + (int64_t)j * px + i;
       const double c0 = in_at(I0, u);
       const double xc = xval<Tin, S, MODE>(I0, Eg, xg, u, v);
       double r = -G.alpha * xc;  // b - A x, difference form
       if (G.alpha != 0.0) r += G.alpha * in_at(I1, u);
       if (i > 0) r += G.wx * ((c0 - in_at(I0, u - 1)) + (xval<Tin, S, MODE>(I0, Eg, xg, u - 1, v - 1) - xc));
       if (i < nx - 1) r += G.wx * ((c0 - in_at(I0, u + 1)) + (xval<Tin, S, MODE>(I0, Eg, xg, u + 1, v + 1) - xc));
-      if (j > 0) r += G.wy * ((c0 - in_at(I0, u - G.ipy)) + (xval<Tin, S, MODE>(I0, Eg, xg, u - G.ipy, v - nx) - xc));
-      if (j < ny - 1) r += G.wy * ((c0 - in_at(I0, u + G.ipy)) + (xval<Tin, S, MODE>(I0, Eg, xg, u + G.ipy, v + nx) - xc));
+      if (j > 0) r += G.wy * ((c0 - in_at(I0, u - G.ipy)) + (xval<Tin, S, MODE>(I0, Eg, xg, u - G.ipy, v - px) - xc));
+      if (j < ny - 1)
+        r += G.wy * ((c0 - in_at(I0, u + G.ipy)) + (xval<Tin, S, MODE>(I0, Eg, xg, u + G.ipy, v + px) - xc));
       if (G.wz != 0.0) {
-        if (k > 0) r += G.wz * (xval<Tin, S, MODE>(I0, Eg, xg, u - G.ipz, v - pl) - xc);
-        if (k < nz - 1) r += G.wz * (xval<Tin, S, MODE>(I0, Eg, xg, u + G.ipz, v + pl) - xc);
+        const double sl = slice ? 1.0 : 0.0;  // in-slice z (slice form) also carries the I0 term
+        if (k > 0)
+          r += G.wz * (sl * (c0 - in_at(I0, u - G.ipz)) + (xval<Tin, S, MODE>(I0, Eg, xg, u - G.ipz, v - pl) - xc));
+        if (k < nz - 1)
+          r += G.wz * (sl * (c0 - in_at(I0, u + G.ipz)) + (xval<Tin, S, MODE>(I0, Eg, xg, u + G.ipz, v + pl) - xc));
       }
       nrm += r * r;
       if (rout) st64(rout + G.off + v, r * inv_scale[t.g]);
@@ -408,18 +777,18 @@ k_canon_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict__
 
 template <typename Tin, typename S, int MODE>
 __global__ void __launch_bounds__(256)
-k_sum_shift(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+k_sum_shift(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
             const Tin* __restrict__ I0, const S* __restrict__ E, const double* __restrict__ x64,
             double* __restrict__ partials) {
   __shared__ double red[4];
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   double s = 0.0;
   if (i < G.nx && j < G.ny) {
-    const int64_t pl = (int64_t)G.nx * G.ny;
+    const int64_t pl = (int64_t)G.px * G.ny;
     for (int k = t.z0; k < t.z1; ++k) {
-      const int64_t v = G.off + k * pl + (int64_t)j * G.nx + i;
+      const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
       if (MODE == 0) {
         s += ld64(E + v);
       } else {
@@ -434,18 +803,18 @@ k_sum_shift(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
 
 template <typename Tin, typename S, typename Tout, int MODE>
 __global__ void __launch_bounds__(256)
-k_finalize(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+k_finalize(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
            const Tin* __restrict__ I0, const S* __restrict__ E, const double* __restrict__ x64,
            const double* __restrict__ shift, Tout* __restrict__ out) {
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   if (i >= G.nx || j >= G.ny) return;
-  const int64_t pl = (int64_t)G.nx * G.ny;
+  const int64_t pl = (int64_t)G.px * G.ny;
   const double sh = shift ? shift[t.g] : 0.0;
   for (int k = t.z0; k < t.z1; ++k) {
     const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
-    const int64_t v = G.off + k * pl + (int64_t)j * G.nx + i;
+    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
     const double x = (MODE == 0) ? in_at(I0, u) + ld64(E + v) : x64[v];
     st64(out + u, x - sh);
   }
@@ -453,49 +822,50 @@ k_finalize(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
 
 template <typename Tin>
 __global__ void __launch_bounds__(256)
-k_refine_init(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+k_refine_init(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
               const Tin* __restrict__ I0, double* __restrict__ x64) {
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   if (i >= G.nx || j >= G.ny) return;
-  const int64_t pl = (int64_t)G.nx * G.ny;
+  const int64_t pl = (int64_t)G.px * G.ny;
   for (int k = t.z0; k < t.z1; ++k) {
     const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
-    x64[G.off + k * pl + (int64_t)j * G.nx + i] = in_at(I0, u);
+    x64[G.off + k * pl + (int64_t)j * G.px + i] = in_at(I0, u);
   }
 }
 
 template <typename S>
 __global__ void __launch_bounds__(256)
 k_refine_update(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
-                double* __restrict__ x64, const S* __restrict__ e, const double* __restrict__ scale) {
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+                int etx, double* __restrict__ x64, const S* __restrict__ e, const double* __restrict__ scale) {
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   if (i >= G.nx || j >= G.ny) return;
-  const int64_t pl = (int64_t)G.nx * G.ny;
+  const int64_t pl = (int64_t)G.px * G.ny;
   const double s = scale[t.g];
   for (int k = t.z0; k < t.z1; ++k) {
-    const int64_t v = G.off + k * pl + (int64_t)j * G.nx + i;
+    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
     x64[v] += s * ld64(e + v);
   }
 }
 
 // -------------------------------------------------- general system (Sec. 4)
+// (caller's arrays, pitch px = nx)
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_rhs_general(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+k_rhs_general(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
               const S* __restrict__ V, const S* __restrict__ Gx, const S* __restrict__ Gy,
               const S* __restrict__ Gz, S* __restrict__ bout) {
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
   const int nx = G.nx, ny = G.ny, nz = G.nz;
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   if (i >= nx || j >= ny) return;
-  const int64_t pl = (int64_t)nx * ny;
+  const int64_t pl = (int64_t)G.ipz;
   for (int k = t.z0; k < t.z1; ++k) {
-    const int64_t v = G.off + k * pl + (int64_t)j * nx + i;
+    const int64_t v = G.ioff + k * pl + (int64_t)j * G.ipy + i;
     double b = 0.0;
     if (G.alpha != 0.0) b += G.alpha * ld64(V + v);
     // (D_a^T g)_v = g[v - e_a] - g[v]; faces outside the grid carry nothing
@@ -507,7 +877,7 @@ k_rhs_general(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
     }
     if (Gy && G.wy != 0.0) {
       double d = 0.0;
-      if (j > 0) d += ld64(Gy + v - nx);
+      if (j > 0) d += ld64(Gy + v - G.ipy);
       if (j < ny - 1) d -= ld64(Gy + v);
       b += G.wy * d;
     }
@@ -524,27 +894,26 @@ k_rhs_general(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 template <typename S>
 __global__ void __launch_bounds__(256)
 k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids,
-                   int zlen, const S* __restrict__ xin, const S* __restrict__ bin, double* __restrict__ partials) {
+                   int zlen, int etx, const S* __restrict__ xin, const S* __restrict__ bin,
+                   double* __restrict__ partials) {
   __shared__ double red[4];
-  const Tile t = decode_tile<EW_TX, EW_TY>(grids, block0, ngrids, zlen, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
   const int nx = G.nx, ny = G.ny, nz = G.nz;
-  const int i = t.x0 + (threadIdx.x & 63), j = t.y0 + (threadIdx.x >> 6);
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   double rr = 0.0, bb = 0.0;
   if (i < nx && j < ny) {
-    const int64_t pl = (int64_t)nx * ny;
-    const S* x = xin + G.off;
-    const S* b = bin + G.off;
+    const int64_t pl = G.ipz, py = G.ipy;
     for (int k = t.z0; k < t.z1; ++k) {
-      const int64_t v = k * pl + (int64_t)j * nx + i;
-      const double xc = ld64(x + v), bv = ld64(b + v);
+      const int64_t v = G.ioff + k * pl + (int64_t)j * py + i;
+      const double xc = ld64(xin + v), bv = ld64(bin + v);
       double r = bv - G.alpha * xc;
-      if (i > 0) r += G.wx * (ld64(x + v - 1) - xc);
-      if (i < nx - 1) r += G.wx * (ld64(x + v + 1) - xc);
-      if (j > 0) r += G.wy * (ld64(x + v - nx) - xc);
-      if (j < ny - 1) r += G.wy * (ld64(x + v + nx) - xc);
-      if (k > 0) r += G.wz * (ld64(x + v - pl) - xc);
-      if (k < nz - 1) r += G.wz * (ld64(x + v + pl) - xc);
+      if (i > 0) r += G.wx * (ld64(xin + v - 1) - xc);
+      if (i < nx - 1) r += G.wx * (ld64(xin + v + 1) - xc);
+      if (j > 0) r += G.wy * (ld64(xin + v - py) - xc);
+      if (j < ny - 1) r += G.wy * (ld64(xin + v + py) - xc);
+      if (k > 0) r += G.wz * (ld64(xin + v - pl) - xc);
+      if (k < nz - 1) r += G.wz * (ld64(xin + v + pl) - xc);
       rr += r * r;
       bb += bv * bv;
     }
@@ -575,7 +944,7 @@ k_reduce(const double* __restrict__ partials, const int64_t* __restrict__ block0
 
 // ============================================================ launchers
 
-#define GD_ARGS(geom) dim3((unsigned)(geom).nblocks), dim3(256), 0, st, (geom).grids, (geom).block0, (geom).ngrids, (geom).zlen
+#define GD_ARGS(geom) dim3((unsigned)(geom).nblocks), dim3(256), 0, st, (geom).grids, (geom).block0, (geom).ngrids, (geom).zlen, (geom).etx
 
 #define GD_DISPATCH_S(s, MACRO)                        \
   switch (s) {                                         \
@@ -597,19 +966,53 @@ k_reduce(const double* __restrict__ partials, const int64_t* __restrict__ block0
 
 static hipError_t last() { return hipGetLastError(); }
 
+template <typename T, bool FP, bool VEC>
+static void sweep_launch3(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
+                          hipStream_t st) {
+  if (g.row) {
+    hipLaunchKernelGGL((k_rb_sweep<T, SWR_TX, 1, FP, VEC>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st,
+                       g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec,
+                       pmode);
+  } else {
+    hipLaunchKernelGGL((k_rb_sweep<T, SW_TX, SW_TY, FP, VEC>), dim3((unsigned)g.nblocks), dim3(SW_TX * SW_TY / 2), 0,
+                       st, g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec,
+                       pmode);
+  }
+}
+
+template <typename T>
+static void sweep_launch(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
+                         hipStream_t st) {
+  // the library's arrays are pair-aligned (g.vec); a caller's odd-width arrays are not
+  if (ec) sweep_launch3<T, true, true>(g, xin, xout, b, ec, pmode, st);
+  else if (g.vec) sweep_launch3<T, false, true>(g, xin, xout, b, ec, pmode, st);
+  else sweep_launch3<T, false, false>(g, xin, xout, b, ec, pmode, st);
+}
+
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
                            const void* ec, int pmode, hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
-#define L(T) hipLaunchKernelGGL(k_rb_sweep<T>, GD_ARGS(g), (const T*)xin, (T*)xout, (const T*)b, (const T*)ec, pmode)
+#define L(T) sweep_launch<T>(g, xin, xout, b, ec, pmode, st)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();
 }
 
-hipError_t launch_residual_restrict(gd_dtype s, const Geom& g, const void* x, const void* b, void* bc,
-                                    void* xc, double* partials, hipStream_t st) {
+template <typename T>
+static void restrict_z_launch(const Geom& g, const void* x, const void* b, void* bc, void* xc, double* partials,
+                              hipStream_t st) {
+  if (g.row)
+    hipLaunchKernelGGL((k_restrict_z<T, SWR_TX, 1>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st, g.grids,
+                       g.block0, g.ngrids, g.zlen, (const T*)x, (const T*)b, (T*)bc, (T*)xc, partials);
+  else
+    hipLaunchKernelGGL((k_restrict_z<T, SW_TX, SW_TY>), dim3((unsigned)g.nblocks), dim3(SW_TX * SW_TY / 2), 0, st,
+                       g.grids, g.block0, g.ngrids, g.zlen, (const T*)x, (const T*)b, (T*)bc, (T*)xc, partials);
+}
+
+hipError_t launch_restrict_z(gd_dtype s, const Geom& g, const void* x, const void* b, void* bc, void* xc,
+                             double* partials, hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
-#define L(T) hipLaunchKernelGGL(k_residual_restrict<T>, GD_ARGS(g), (const T*)x, (const T*)b, (T*)bc, (T*)xc, partials)
+#define L(T) restrict_z_launch<T>(g, x, b, bc, xc, partials, st)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();

@@ -39,7 +39,8 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-STEP_SHAPES = [(9, 17, 130), (1, 33, 200), (40, 3, 5), (3, 8, 64), (1, 1, 1), (5, 1, 7), (2, 70, 1)]
+STEP_SHAPES = [(9, 17, 130), (1, 33, 200), (40, 3, 5), (3, 8, 64), (1, 1, 1), (5, 1, 7), (2, 70, 1), (1, 300, 517),
+               (1, 7, 1), (6, 21, 67)]
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
