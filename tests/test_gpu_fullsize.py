@@ -1,0 +1,100 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+* 1024x1024x128 FP32 stack: the whole answer against the FP64 DCT oracle.
+* 4096x4096x256 FP16/BF16 stack with FP64 refinement: the 512x512x32 crop
+  solved as its own problem against the oracle; the full stack through
+  properties that hold at any size (slice means of the answer equal the
+  global input mean; the oracle's own residual on sampled slabs).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import grid as og
+from oracle import solvers as osv
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+BETA = (1.0, 1.0, 4.0)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_stack1k_full_against_dct(gd):
+    say("stack1k full AD+SP vs DCT")
+    spec = synth.CONFIGS["stack1k"]
+    I0 = synth.make_stack(spec, device="cuda", dtype=torch.float32)
+    # error <= 1e-5 needs the residual a little below 1e-6 here (the smoothest
+    # modes amplify it ~13x); 4e-7 is above this stack's FP32 floor (~2.6e-7)
+    opts = dict(pre_smooth=1, post_smooth=2, rel_tol=4e-7, check=False)
+    I1, r1 = gd.smooth_z(I0, BETA, out_dtype=torch.float64, **opts)
+    print("AD", r1, flush=True)
+    assert r1["rel_residual"] <= 1e-6
+    I2, r2, per = gd.screened_poisson_stack(I0, I1.float(), 0.01, **opts)
+    print("SP", r2, flush=True)
+    assert r2["rel_residual"] <= 1e-6
+    a0 = I0.double().cpu().numpy()
+    ref1 = osv.ad_dct(a0, BETA)
+    assert rel(I1.cpu().numpy(), ref1) <= 1e-5
+    # the SP phase as run: value target = the FP32 AD output the GPU used
+    ref2 = osv.sp_dct(a0, I1.float().double().cpu().numpy(), 0.01)
+    assert rel(I2.double().cpu().numpy(), ref2) <= 1e-5
+
+
+@pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
+def test_stack4k_crop_mixed(gd, dt):
+    """The 512x512x32 crop of the 4096x4096x256 stack, solved as its own
+    problem with 16-bit storage and FP64 refinement."""
+    say("stack4k crop mixed", dt)
+    spec = synth.CONFIGS["stack4k"]
+    full = synth.make_stack(spec, device="cuda", z_range=(0, 32))
+    crop = full[:, :512, :512].to(dt).contiguous()
+    del full
+    st = gd.F16 if dt == torch.float16 else gd.BF16
+    I1, r1 = gd.smooth_z(crop, BETA, out_dtype=torch.float64, storage=st, fp64_refine=1, rel_tol=5e-8)
+    a0 = crop.double().cpu().numpy()
+    ref1 = osv.ad_dct(a0, BETA)
+    assert r1["rel_residual"] <= 5e-8
+    assert rel(I1.cpu().numpy(), ref1) <= 1e-6
+    I1q = I1.to(dt)
+    I2, r2, _ = gd.screened_poisson_stack(crop, I1q, 0.01, storage=st, fp64_refine=1, rel_tol=5e-8)
+    ref2 = osv.sp_dct(a0, I1q.double().cpu().numpy(), 0.01)
+    # I2 is returned in the 16-bit input type: compare at its resolution
+    tol = 2e-3 if dt == torch.float16 else 8e-3
+    assert rel(I2.double().cpu().numpy(), ref2) <= tol
+    gd.release_workspace()
+
+
+@pytest.mark.parametrize("dt", [torch.float16])
+def test_stack4k_full_properties(gd, dt):
+    say("stack4k full mixed", dt)
+    spec = synth.CONFIGS["stack4k"]
+    I0 = synth.make_stack(spec, device="cuda", dtype=dt)
+    I1, r1 = gd.smooth_z(I0, BETA, out_dtype=torch.float32, storage=gd.F16, fp64_refine=1)
+    assert r1["rel_residual"] <= 1e-6
+    # slice means of the answer equal the global mean of the input
+    gm = I0.double().mean().item()
+    sm = I1.double().mean(dim=(1, 2)).cpu().numpy()
+    assert np.abs(sm - gm).max() <= 1e-5 * max(1.0, abs(gm)) + 1e-3
+    # the oracle's residual on sampled slabs (interior planes k0 .. k0+7,
+    # with their z-neighbours for the stencil)
+    rng = np.random.default_rng(0)
+    for k0 in rng.choice(np.arange(1, 256 - 9), 2, replace=False):
+        sl = slice(int(k0) - 1, int(k0) + 9)
+        x = I1[sl].double().cpu().numpy()
+        i0 = I0[sl].double().cpu().numpy()
+        r = og.rhs_ad(i0, BETA) - og.apply_A(x, 0.0, BETA)
+        b = og.rhs_ad(i0, BETA)
+        inner = slice(1, -1)
+        # FP32 output rounding floor: ~3e-6 of ||b|| per slab; the solve itself is at 1e-6
+        assert np.linalg.norm(r[inner]) <= 2e-5 * np.linalg.norm(b[inner])
+    del I0, I1
+    gd.release_workspace()
+    torch.cuda.empty_cache()
