@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-crop", default="32,128,128", help="nz,ny,nx of the oracle's crop")
     p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only copy a 1 GiB buffer 3 times (reference for HBM byte counters)")
     p.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                           "profiles", "traffic.json"))
     return p.parse_args()
@@ -89,7 +91,7 @@ def bench_slices(a, gd, synth, torch, desc):
         _, rep, per = gd.screened_poisson_slices(I0, I1, descs, out=out, timing=1, **opts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
-    ms, launches, bytes_per = gd.kernel_time()
+    ms, launches, bytes_per = gd.kernel_time(gd.SWEEP_SLICE)
     avg_ms = ms / max(launches, 1)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     line = {
@@ -100,7 +102,7 @@ def bench_slices(a, gd, synth, torch, desc):
         "config": {"workload": f"{a.workload}: {desc}; beta=(1,1), tol {TOL:g} per slice", "slices": len(descs),
                    "pixels": npx, "smooth": [pre, post]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rb_sweep (finest level)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rb_sweep<f32,256,1,false,true> finest level",
                      "launches": launches, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per},
         "sp": {"cycles": rep["cycles"], "max_slice_rel_residual": rep["rel_residual"], "levels": rep["levels"]},
         "generate_s": gen_s,
@@ -119,6 +121,14 @@ def main():
     import paper_1310_0041_amd as gd
     import synth
 
+    if a.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": src.numel() * 4, "copies": 3}))
+        return
     gd.load()
     spec_key, storage, refine, desc = WORKLOADS[a.workload]
     spec = synth.CONFIGS.get(spec_key)
@@ -152,10 +162,16 @@ def main():
         reps.append(step(1))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
-    ms, launches, bytes_per = gd.kernel_time()
-    # the timed launches mix the AD stack and the SP slices; both finest
-    # levels have the same voxel count and storage, so the same bytes
+    # dominant kernel: the finest-level relaxation of the stack (AD phase),
+    # k_rb_sweep<S, 64, 8, false, true> at the finest level's launch shape
+    ms, launches, bytes_per = gd.kernel_time(gd.SWEEP_STACK)
     avg_ms = ms / max(launches, 1)
+    others = {}
+    for name, v in (("stack_fused_prolong", gd.SWEEP_STACK_PROLONG), ("slice", gd.SWEEP_SLICE),
+                    ("slice_fused_prolong", gd.SWEEP_SLICE_PROLONG)):
+        m2, n2, b2 = gd.kernel_time(v)
+        if n2:
+            others[name] = {"launches": n2, "avg_launch_ms": m2 / n2, "GB/s": b2 / (m2 / n2 * 1e-3) / 1e9}
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if launches else 0.0
 
     traffic = None
@@ -192,10 +208,11 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_rb_sweep (finest level)",
+            "kernel": "k_rb_sweep<%s,64,8,false,true> finest level" % storage,
             "launches": launches,
             "avg_launch_ms": avg_ms,
             "algorithmic_bytes_per_launch": bytes_per,
+            "other_finest_sweeps": others,
         },
         "ad": {"cycles": r1["cycles"], "refine_steps": r1["refine_steps"], "rel_residual": r1["rel_residual"],
                "levels": r1["levels"]},

@@ -70,6 +70,8 @@ typedef struct {
   int prolong;          /* 0: cell-centred trilinear, 1: piecewise constant    */
   int timing;           /* 1: time the finest-level relaxation launches with
                            HIP events (gd_get_kernel_time)                     */
+  int fuse_prolong;     /* 1: add the up-sampled correction inside the first
+                           post-smoothing sweep instead of a separate pass    */
 } gd_solve_opts;
 
 /* Filled by the solve calls when the pointer is non-NULL. */
@@ -175,10 +177,12 @@ gd_status gd_prolong_add(const void* e_coarse, void* x, gd_dtype s,
 
 /* ---- instrumentation -------------------------------------------------------- */
 /* Total HIP-event time (ms) and launch count of the finest-level relaxation
- * kernel since the last reset, recorded by solves run with opts->timing = 1.
- * bytes_per_launch: algorithmic bytes of the last timed launch (read x and b,
- * write x: 3 * storage bytes per voxel). */
-gd_status gd_get_kernel_time(double* total_ms, int64_t* launches, double* bytes_per_launch);
+ * launches of one variant since the last reset, recorded by solves run with
+ * opts->timing = 1.  variant: 0 stack grid, 1 stack grid with the coarse
+ * correction added on load, 2 slice (one-line) grids, 3 slice grids with the
+ * correction.  bytes_per_launch: algorithmic bytes of one launch (read x and
+ * b, write x: 3 * storage bytes per voxel of the finest level). */
+gd_status gd_get_kernel_time(int variant, double* total_ms, int64_t* launches, double* bytes_per_launch);
 void gd_reset_kernel_time(void);
 
 /* Free every cached workspace (all devices). */

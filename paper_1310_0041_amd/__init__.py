@@ -44,6 +44,7 @@ class SolveOpts(ctypes.Structure):
         ("inner_cycles", ctypes.c_int),
         ("prolong", ctypes.c_int),
         ("timing", ctypes.c_int),
+        ("fuse_prolong", ctypes.c_int),
     ]
 
 
@@ -93,7 +94,7 @@ _SIGS = {
     "gd_residual_restrict": (_i, [_vp, _vp, _vp, _i, _i64, _i64, _i64, _i, _i, _i, _d, _d, _d, _d,
                                   ctypes.POINTER(_d), _vp]),
     "gd_prolong_add": (_i, [_vp, _vp, _i, _i64, _i64, _i64, _i, _i, _i, _i, _vp]),
-    "gd_get_kernel_time": (_i, [ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
+    "gd_get_kernel_time": (_i, [_i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "gd_reset_kernel_time": (None, []),
     "gd_release_workspace": (_i, []),
 }
@@ -302,12 +303,17 @@ def prolong_add(e_coarse, x, c, mode=0):
     return x
 
 
-def kernel_time():
+SWEEP_STACK, SWEEP_STACK_PROLONG, SWEEP_SLICE, SWEEP_SLICE_PROLONG = 0, 1, 2, 3
+
+
+def kernel_time(variant=SWEEP_STACK):
+    """(total ms, launches, algorithmic bytes per launch) of the finest-level
+    relaxation launches of one variant recorded with opts.timing = 1."""
     lib = load()
     ms = ctypes.c_double()
     n = ctypes.c_int64()
     by = ctypes.c_double()
-    lib.gd_get_kernel_time(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by))
+    _check(lib.gd_get_kernel_time(int(variant), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
     return ms.value, n.value, by.value
 
 

@@ -64,9 +64,9 @@ static bool valid_dtype(int t) { return t >= GD_F64 && t <= GD_BF16; }
 
 struct KernelTimer {
   std::mutex mu;
-  double total_ms = 0.0;
-  int64_t launches = 0;
-  double bytes = 0.0;
+  double total_ms[4] = {0, 0, 0, 0};
+  int64_t launches[4] = {0, 0, 0, 0};
+  double bytes[4] = {0, 0, 0, 0};
 };
 static KernelTimer g_timer;
 
@@ -251,14 +251,18 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
   const size_t es = dsize(s);
   int64_t maxblocks = 1;
   std::vector<char> stage;
-  for (auto& L : H->lv) {
+  for (size_t li = 0; li < H->lv.size(); ++li) {
+    Level& L = H->lv[li];
+    // the finest level aims for more blocks than the coarser ones (its
+    // launches are then told apart by their grid size in kernel traces)
+    const int64_t tgt = li == 0 ? sweep_target() : std::max<int64_t>(1, sweep_target() / 2);
     if (L.row) {
-      build_tab(L.sw, L.h, SWR_TX, 1, false, sweep_target());
+      build_tab(L.sw, L.h, SWR_TX, 1, false, tgt);
       build_tab(L.ew, L.h, EWR_TX, 1, false, 8192);
       build_tab(L.rc, L.h, EWR_TX, 1, true, 8192);
       build_tab(L.rz, L.h, SWR_TX, 1, false, 4096, true);
     } else {
-      build_tab(L.sw, L.h, SW_TX, SW_TY, false, sweep_target());
+      build_tab(L.sw, L.h, SW_TX, SW_TY, false, tgt);
       build_tab(L.ew, L.h, EW_TX, EW_TY, false, 8192);
       build_tab(L.rc, L.h, EW_TX, EW_TY, true, 8192);
       build_tab(L.rz, L.h, SW_TX, SW_TY, false, 2048, true);
@@ -347,10 +351,13 @@ struct Cycler {
   int pre, post, pmode;
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<int> ev_kind;
   size_t ev_used = 0;
 
+  bool fuse;
   Cycler(Hier& h, hipStream_t s, const gd_solve_opts& o)
-      : H(h), st(s), pre(o.pre_smooth), post(o.post_smooth), pmode(o.prolong), timing(o.timing != 0) {}
+      : H(h), st(s), pre(o.pre_smooth), post(o.post_smooth), pmode(o.prolong), timing(o.timing != 0),
+        fuse(o.fuse_prolong != 0) {}
   ~Cycler() {
     for (auto& p : ev) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   }
@@ -366,6 +373,8 @@ struct Cycler {
         ev.push_back({a, b});
       }
       HIP_TRY(hipEventRecord(ev[ev_used].first, st));
+      if (ev_kind.size() < ev.size()) ev_kind.resize(ev.size());
+      ev_kind[ev_used] = (L.row ? 2 : 0) + (ec ? 1 : 0);
     }
     HIP_TRY(launch_rb_sweep(H.s, H.g_sw(l), L.x, L.xt, L.b, ec, pmode, st));
     if (t) HIP_TRY(hipEventRecord(ev[ev_used++].second, st));
@@ -386,10 +395,11 @@ struct Cycler {
   void correct(int l) {
     below(l + 1);
     Level& C = H.lv[l + 1];
-    if (post > 0) {
-      smooth(l, post, C.x);  // prolongation fused into the first sweep
+    if (fuse && post > 0) {
+      smooth(l, post, C.x);  // prolongation fused into the first sweep's loads
     } else {
-      HIP_TRY(launch_prolong_add(H.s, H.g_ew(l), C.x, H.lv[l].x, pmode, st));
+      HIP_TRY(launch_prolong_pair(H.s, H.g_sw(l), C.x, H.lv[l].x, pmode, st));
+      smooth(l, post);
     }
   }
   void below(int l) {
@@ -411,18 +421,23 @@ struct Cycler {
   // collect HIP-event times of finest-level sweeps (after a stream sync)
   void harvest() {
     if (!timing || ev_used == 0) return;
-    double tot = 0.0;
+    double tot[4] = {0, 0, 0, 0};
+    int64_t cnt[4] = {0, 0, 0, 0};
     for (size_t i = 0; i < ev_used; ++i) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ev[i].first, ev[i].second));
-      tot += ms;
+      tot[ev_kind[i]] += ms;
+      cnt[ev_kind[i]] += 1;
     }
-    std::lock_guard<std::mutex> lk(g_timer.mu);
-    g_timer.total_ms += tot;
-    g_timer.launches += (int64_t)ev_used;
     double cells = 0.0;
     for (int64_t c : H.cells) cells += (double)c;
-    g_timer.bytes = 3.0 * (double)dsize(H.s) * cells;
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    for (int k = 0; k < 4; ++k) {
+      if (!cnt[k]) continue;
+      g_timer.total_ms[k] += tot[k];
+      g_timer.launches[k] += cnt[k];
+      g_timer.bytes[k] = 3.0 * (double)dsize(H.s) * cells;
+    }
     ev_used = 0;
   }
 };
@@ -644,6 +659,7 @@ void gd_default_opts(gd_solve_opts* o) {
   o->inner_cycles = 1;
   o->prolong = 0;
   o->timing = 0;
+  o->fuse_prolong = 0;
 }
 
 const char* gd_last_error(void) { return t_err.c_str(); }
@@ -978,18 +994,21 @@ gd_status gd_prolong_add(const void* ec, void* x, gd_dtype s, int64_t nx, int64_
   });
 }
 
-gd_status gd_get_kernel_time(double* total_ms, int64_t* launches, double* bytes) {
+gd_status gd_get_kernel_time(int variant, double* total_ms, int64_t* launches, double* bytes) {
+  if (variant < 0 || variant > 3) return fail(GD_ERR_INVALID, "gd_get_kernel_time: variant must be 0..3");
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  if (total_ms) *total_ms = g_timer.total_ms;
-  if (launches) *launches = g_timer.launches;
-  if (bytes) *bytes = g_timer.bytes;
+  if (total_ms) *total_ms = g_timer.total_ms[variant];
+  if (launches) *launches = g_timer.launches[variant];
+  if (bytes) *bytes = g_timer.bytes[variant];
   return GD_OK;
 }
 
 void gd_reset_kernel_time(void) {
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  g_timer.total_ms = 0.0;
-  g_timer.launches = 0;
+  for (int k = 0; k < 4; ++k) {
+    g_timer.total_ms[k] = 0.0;
+    g_timer.launches[k] = 0;
+  }
 }
 
 gd_status gd_release_workspace(void) {

@@ -665,6 +665,32 @@ k_prolong_add(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
   }
 }
 
+// Pair form for the library's arrays (tiles of the relaxation, one x-pair per
+// thread); the loads of a pair do not depend on each other, so many are in
+// flight without any LDS or barrier.
+template <typename S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY / 2)
+k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+               const S* __restrict__ ec, S* __restrict__ xio, int mode) {
+  using C = typename Ty<S>::C;
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
+  const GridDesc& G = grids[t.g];
+  const int tid = threadIdx.x;
+  const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
+  const int gx = t.x0 + 2 * pxl, gy = t.y0 + tyl;
+  if (gy >= G.ny || gx >= G.nx) return;
+  const bool vB = gx + 1 < G.nx;
+  const int64_t pl = (int64_t)G.px * G.ny;
+  S* x = xio + G.off + (int64_t)gy * G.px + gx;
+#pragma unroll 2
+  for (int k = t.z0; k < t.z1; ++k) {
+    C a, b, pa, pb;
+    ld2(x + k * pl, true, vB, a, b);
+    prolong_pair<S>(ec, G, gx, gy, k, mode, pa, pb);
+    st2(x + k * pl, true, vB, a + pa, b + pb);
+  }
+}
+
 // ------------------------------------------- finest level of AD / SP (Eq. 1, 2)
 //
 // Canonical system of both phases: A = alpha + w_x L_x + w_y L_y + w_z L_z,
@@ -1013,6 +1039,24 @@ hipError_t launch_restrict_z(gd_dtype s, const Geom& g, const void* x, const voi
                              double* partials, hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
 #define L(T) restrict_z_launch<T>(g, x, b, bc, xc, partials, st)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+template <typename T>
+static void prolong_pair_launch(const Geom& g, const void* ec, void* x, int mode, hipStream_t st) {
+  if (g.row)
+    hipLaunchKernelGGL((k_prolong_pair<T, SWR_TX, 1>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st, g.grids,
+                       g.block0, g.ngrids, g.zlen, (const T*)ec, (T*)x, mode);
+  else
+    hipLaunchKernelGGL((k_prolong_pair<T, SW_TX, SW_TY>), dim3((unsigned)g.nblocks), dim3(SW_TX * SW_TY / 2), 0, st,
+                       g.grids, g.block0, g.ngrids, g.zlen, (const T*)ec, (T*)x, mode);
+}
+
+hipError_t launch_prolong_pair(gd_dtype s, const Geom& g, const void* ec, void* x, int mode, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L(T) prolong_pair_launch<T>(g, ec, x, mode, st)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();

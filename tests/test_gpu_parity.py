@@ -148,6 +148,22 @@ def test_ad_plain_fp32(gd, shape):
     assert abs(host(I1).mean() - I0.mean()) <= 1e-9 * max(1.0, abs(I0.mean()))
 
 
+@pytest.mark.parametrize("fuse", [0, 1])
+def test_prolongation_fused_or_separate(gd, fuse):
+    """The coarse correction added in its own pass or inside the first
+    post-smoothing sweep's loads gives the same answer."""
+    say("AD fuse_prolong", fuse)
+    spec = synth.StackSpec(70, 50, 12, (4.0, 40.0), True, 13100412)
+    I0 = stack(spec, torch.float64)
+    I1, rep = gd.smooth_z(dev(I0, torch.float64), BETA, storage=gd.F64, rel_tol=1e-10, fuse_prolong=fuse)
+    assert rep["rel_residual"] <= 1e-10
+    assert rel(host(I1), osv.ad_dct(I0, BETA)) <= 1e-8
+    for p in (0, 1):  # trilinear and piecewise-constant up-sampling
+        I1, rep = gd.smooth_z(dev(I0, torch.float64), BETA, storage=gd.F64, rel_tol=1e-10, fuse_prolong=fuse,
+                              prolong=p)
+        assert rep["rel_residual"] <= 1e-10
+
+
 def test_plain_fp32_stops_at_its_floor(gd):
     """Smooth slices with strong slice-to-slice jumps: the FP32 correction
     cannot represent an answer at 1e-9; the solve stops on stagnation and
