@@ -150,6 +150,48 @@ gd_status gd_rhs_general(gd_hierarchy* h, const void* V, const void* Gx, const v
 gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles,
                     double* rel_residual_out, void* stream);
 
+/* Residual-to-error pairs from multigrid itself, for training a learned
+ * preconditioner: x_k = `cycles` V-cycles from zero on A x = b; r_out = b - A x_k,
+ * e_out = x_star - x_k (x_star: the converged solution, from gd_vcycle).
+ * All arrays nx*ny*nz in the hierarchy's storage dtype. */
+gd_status gd_mg_error_pairs(gd_hierarchy* h, const void* b, const void* x_star, int cycles,
+                            void* r_out, void* e_out, void* stream);
+
+/* ---- learned preconditioner (not in the paper) --------------------------------
+ * A 3-level U-Net of 3x3 convolutions (16/32/64 channels, BF16 weights and
+ * activations, FP32 accumulation on the matrix cores, FP32 master weights)
+ * mapping a residual image to an error estimate: z = N(r / s) * s with s the
+ * RMS of r per image.  Images: nx % 256 == 0, ny % 4 == 0, nx, ny <= 16384,
+ * nx*ny <= 2^26, FP32, batch of `batch` images of ny*nx pixels (a
+ * [batch][ny][nx] array); training batches hold at most 2^28 pixels.  The
+ * forward pass runs in groups of images of at most 2^25 pixels (about 10 GB
+ * of activations).  Errors: GD_ERR_INVALID for other shapes. */
+typedef struct gd_net gd_net;
+gd_status gd_net_create(gd_net** n, uint64_t seed);          /* He-normal init from seed */
+gd_status gd_net_destroy(gd_net* n);
+int64_t gd_net_num_params(const gd_net* n);
+gd_status gd_net_get_params(gd_net* n, float* host, int64_t count);   /* FP32 master weights */
+gd_status gd_net_set_params(gd_net* n, const float* host, int64_t count);
+const char* gd_net_last_error(void);
+gd_status gd_net_forward(gd_net* n, const float* r, float* z, int64_t nx, int64_t ny, int64_t batch,
+                         void* stream);
+/* loss = mean over pixels of (N(r/s) - e/s)^2; gradients (FP32, master-weight
+ * layout, host array of gd_net_num_params) without updating the weights */
+gd_status gd_net_gradients(gd_net* n, const float* r, const float* e, int64_t nx, int64_t ny, int64_t batch,
+                           float* grad_host, double* loss_out, void* stream);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the same loss */
+gd_status gd_net_train_step(gd_net* n, const float* r, const float* e, int64_t nx, int64_t ny, int64_t batch,
+                            float lr, double* loss_out, void* stream);
+
+/* Flexible conjugate gradients on the hierarchy's system (FP32 storage) with
+ * preconditioner 0: one V-cycle, 1: the net, 2: a V-cycle then the net on
+ * its remaining residual.  x in/out, b in (caller's layout).  When the net
+ * fails or stops reducing the residual the iteration restarts with the
+ * V-cycle preconditioner (rep->refine_steps = 1 then).  rep->cycles =
+ * iterations, rep->rel_residual = the final true relative residual. */
+gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int precond, double rel_tol,
+                       int max_iter, gd_solve_report* rep, void* stream);
+
 /* ---- single multigrid steps (Sec. 4.1), for kernel-level checks ------------
  * All arrays are nx*ny*nz of dtype s; the operator is
  * alpha*Id + w_x L_x + w_y L_y + w_z L_z (one level's coefficients). */

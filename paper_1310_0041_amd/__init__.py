@@ -97,6 +97,17 @@ _SIGS = {
     "gd_get_kernel_time": (_i, [_i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "gd_reset_kernel_time": (None, []),
     "gd_release_workspace": (_i, []),
+    "gd_mg_error_pairs": (_i, [_vp, _vp, _vp, _i, _vp, _vp, _vp]),
+    "gd_net_create": (_i, [ctypes.POINTER(_vp), ctypes.c_uint64]),
+    "gd_net_destroy": (_i, [_vp]),
+    "gd_net_num_params": (_i64, [_vp]),
+    "gd_net_get_params": (_i, [_vp, _vp, _i64]),
+    "gd_net_set_params": (_i, [_vp, _vp, _i64]),
+    "gd_net_last_error": (ctypes.c_char_p, []),
+    "gd_net_forward": (_i, [_vp, _vp, _vp, _i64, _i64, _i64, _vp]),
+    "gd_net_gradients": (_i, [_vp, _vp, _vp, _i64, _i64, _i64, _vp, ctypes.POINTER(_d), _vp]),
+    "gd_net_train_step": (_i, [_vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, ctypes.POINTER(_d), _vp]),
+    "gd_fcg_solve": (_i, [_vp, _vp, _vp, _vp, _i, _d, _i, ctypes.POINTER(Report), _vp]),
 }
 
 
@@ -121,9 +132,10 @@ def load(path=LIB_PATH):
     return lib
 
 
-def _check(status, allow=()):
+def _check(status, allow=(), net=False):
     if status != OK and status not in allow:
-        raise GDError(status, _lib.gd_last_error().decode())
+        msg = (_lib.gd_net_last_error() if net else _lib.gd_last_error()).decode()
+        raise GDError(status, msg)
     return status
 
 
@@ -259,10 +271,85 @@ class Hierarchy:
         _check(_lib.gd_vcycle(self._h, _ptr(x), _ptr(b), int(ncycles), ctypes.byref(rr), _stream()))
         return rr.value
 
+    def error_pairs(self, b, x_star, cycles):
+        """(r_k, e_k) after `cycles` V-cycles from zero: b - A x_k and x_star - x_k."""
+        r = _torch().empty_like(b)
+        e = _torch().empty_like(b)
+        _check(_lib.gd_mg_error_pairs(self._h, _ptr(b), _ptr(x_star), int(cycles), _ptr(r), _ptr(e), _stream()))
+        return r, e
+
+    def fcg(self, x, b, net=None, precond=0, rel_tol=1e-6, max_iter=200, check=True):
+        """Flexible CG (x in/out); precond 0 V-cycle, 1 net, 2 V-cycle then net."""
+        rep = Report()
+        st = _lib.gd_fcg_solve(self._h, net._n if net is not None else None, _ptr(x), _ptr(b), int(precond),
+                               float(rel_tol), int(max_iter), ctypes.byref(rep), _stream())
+        if check:
+            _check(st)
+        d = rep.as_dict()
+        d["iterations"] = d["cycles"]
+        d["fallback_used"] = d["refine_steps"]
+        d["status"] = st
+        return d
+
     def close(self):
         if self._h:
             _lib.gd_hierarchy_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """The learned preconditioner (BF16 U-Net run by the library's kernels)."""
+
+    def __init__(self, seed=0):
+        lib = load()
+        self._n = ctypes.c_void_p()
+        _check(lib.gd_net_create(ctypes.byref(self._n), int(seed)), net=True)
+
+    @property
+    def num_params(self):
+        return int(_lib.gd_net_num_params(self._n))
+
+    def get_params(self):
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(_lib.gd_net_get_params(self._n, out.ctypes.data_as(ctypes.c_void_p), out.size), net=True)
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(_lib.gd_net_set_params(self._n, p.ctypes.data_as(ctypes.c_void_p), p.size), net=True)
+
+    def forward(self, r):
+        """r: [batch][ny][nx] FP32 on the GPU -> z of the same shape."""
+        b, ny, nx = r.shape
+        z = _torch().empty_like(r)
+        _check(_lib.gd_net_forward(self._n, _ptr(r), _ptr(z), nx, ny, b, _stream()), net=True)
+        return z
+
+    def gradients(self, r, e):
+        b, ny, nx = r.shape
+        g = np.empty(self.num_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(_lib.gd_net_gradients(self._n, _ptr(r), _ptr(e), nx, ny, b, g.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.byref(loss), _stream()), net=True)
+        return g, loss.value
+
+    def train_step(self, r, e, lr=1e-3):
+        b, ny, nx = r.shape
+        loss = ctypes.c_double()
+        _check(_lib.gd_net_train_step(self._n, _ptr(r), _ptr(e), nx, ny, b, float(lr), ctypes.byref(loss),
+                                      _stream()), net=True)
+        return loss.value
+
+    def close(self):
+        if self._n:
+            _lib.gd_net_destroy(self._n)
+            self._n = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -766,7 +766,41 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
 struct gd_hierarchy {
   std::unique_ptr<Hier> H;
   gd_solve_opts o;
+  void* kv[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // Krylov vectors r, z, p, q, t, u
+  ~gd_hierarchy() {
+    for (void* p : kv)
+      if (p) (void)hipFree(p);
+  }
 };
+
+namespace gd {
+// one V-cycle from a zero guess on A z = r (caller's layout, storage dtype)
+static void mg_apply(gd_hierarchy* h, const void* r, void* z, hipStream_t st) {
+  Hier& H = *h->H;
+  Level& L0 = H.lv[0];
+  const GridDesc& g0 = L0.h[0];
+  const size_t es = dsize(H.s);
+  const size_t wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es, rows = (size_t)g0.ny * g0.nz;
+  HIP_TRY(hipMemcpy2DAsync(L0.b, pb, r, wb, wb, rows, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * es, st));
+  Cycler cy(H, st, h->o);
+  cy.full(0);
+  HIP_TRY(hipMemcpy2DAsync(z, wb, L0.x, pb, wb, rows, hipMemcpyDeviceToDevice, st));
+}
+
+static double reduce1(Hier& H, hipStream_t st) {
+  HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, 1, 1, H.dred, st));
+  read_dred(H, 1, st);
+  return H.hpin[0];
+}
+
+static void set_coef(Hier& H, double a, double b, hipStream_t st) {
+  HIP_TRY(hipStreamSynchronize(st));
+  H.hpin[2] = a;
+  H.hpin[3] = b;
+  HIP_TRY(hipMemcpyAsync(H.dscal, H.hpin + 2, 2 * sizeof(double), hipMemcpyHostToDevice, st));
+}
+}  // namespace gd
 
 gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t nz, double alpha, double bx, double by,
                               double bz, gd_dtype s, const gd_solve_opts* opts, void* stream) {
@@ -848,7 +882,7 @@ gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles, double
       HIP_TRY(hipMemcpy2DAsync(x, wb, L0.x, pb, wb, rows, hipMemcpyDeviceToDevice, st));
     }
     if (relres) {
-      HIP_TRY(launch_general_residual(H.s, H.g_ew(0), x, b, H.partials, st));
+      HIP_TRY(launch_general_residual(H.s, H.g_ew(0), x, b, nullptr, H.partials, st));
       HIP_TRY(launch_reduce(H.partials, L0.ew.d_b0, 1, 2, H.dred, st));
       read_dred(H, 2, st);
       const double rr = std::sqrt(H.hpin[0]), bb = std::sqrt(H.hpin[1]);
@@ -857,6 +891,133 @@ gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles, double
     }
     HIP_TRY(hipStreamSynchronize(st));
     cy.harvest();
+    return GD_OK;
+  });
+}
+
+// ---------------------------------------------------- flexible CG + pairs
+
+gd_status gd_mg_error_pairs(gd_hierarchy* h, const void* b, const void* x_star, int cycles, void* r_out, void* e_out,
+                            void* stream) {
+  if (!h || !b || !x_star || !r_out || !e_out) return fail(GD_ERR_INVALID, "gd_mg_error_pairs: null pointer");
+  if (cycles < 0) return fail(GD_ERR_INVALID, "gd_mg_error_pairs: cycles < 0");
+  Hier& H = *h->H;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    Level& L0 = H.lv[0];
+    const GridDesc& g0 = L0.h[0];
+    const size_t es = dsize(H.s);
+    const size_t wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es, rows = (size_t)g0.ny * g0.nz;
+    // x_k: k V-cycles from zero, left in e_out for the moment
+    HIP_TRY(hipMemcpy2DAsync(L0.b, pb, b, wb, wb, rows, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * es, st));
+    Cycler cy(H, st, h->o);
+    for (int c = 0; c < cycles; ++c) cy.full(0);
+    HIP_TRY(hipMemcpy2DAsync(e_out, wb, L0.x, pb, wb, rows, hipMemcpyDeviceToDevice, st));
+    // r_k = b - A x_k; e_k = x* - x_k
+    HIP_TRY(launch_general_residual(H.s, H.g_ew(0), e_out, b, r_out, H.partials, st));
+    set_coef(H, 1.0, -1.0, st);
+    HIP_TRY(launch_axpby(H.s, H.g_ew(0), H.dscal, x_star, e_out, e_out, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+  });
+}
+
+gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int precond, double rel_tol,
+                       int max_iter, gd_solve_report* rep, void* stream) {
+  if (!h || !x || !b) return fail(GD_ERR_INVALID, "gd_fcg_solve: null pointer");
+  if (x == b) return fail(GD_ERR_INVALID, "gd_fcg_solve: x aliases b");
+  if (precond < 0 || precond > 2 || (precond > 0 && !net))
+    return fail(GD_ERR_INVALID, "gd_fcg_solve: precond 0 (V-cycle), 1 (net) or 2 (V-cycle then net) with a net");
+  if (!(rel_tol > 0.0) || max_iter < 0) return fail(GD_ERR_INVALID, "gd_fcg_solve: bad tolerance or max_iter");
+  Hier& H = *h->H;
+  if (H.s != GD_F32) return fail(GD_ERR_UNSUPPORTED, "gd_fcg_solve: FP32 hierarchies only");
+  const GridDesc& g0 = H.lv[0].h[0];
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t n = (size_t)g0.nx * g0.ny * g0.nz, bytes = n * 4;
+    for (auto& p : h->kv)
+      if (!p) HIP_TRY(hipMalloc(&p, bytes));
+    void *r = h->kv[0], *z = h->kv[1], *p = h->kv[2], *q = h->kv[3], *t = h->kv[4], *u = h->kv[5];
+    const Geom g = H.g_ew(0);
+    int mode = precond, fallback = 0, it = 0;
+    double bn = 0.0, rn = 0.0;
+    auto residual = [&]() {  // r = b - A x, returns ||r||, sets ||b||
+      HIP_TRY(launch_general_residual(H.s, g, x, b, r, H.partials, st));
+      HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, 1, 2, H.dred, st));
+      read_dred(H, 2, st);
+      bn = std::sqrt(H.hpin[1]);
+      return std::sqrt(H.hpin[0]);
+    };
+    auto precondition = [&](int m) -> bool {  // z = M(r); false if the net failed
+      if (m == 0 || m == 2) mg_apply(h, r, z, st);
+      if (m == 1) {
+        if (gd_net_forward(net, (const float*)r, (float*)z, g0.nx, g0.ny, g0.nz, st) != GD_OK) return false;
+      } else if (m == 2) {
+        // z += net(r - A z); q still holds A p of this iteration and must survive
+        HIP_TRY(launch_general_residual(H.s, g, z, r, t, H.partials, st));
+        if (gd_net_forward(net, (const float*)t, (float*)u, g0.nx, g0.ny, g0.nz, st) != GD_OK) return false;
+        set_coef(H, 1.0, 1.0, st);
+        HIP_TRY(launch_axpby(H.s, g, H.dscal, u, z, z, st));
+      }
+      return true;
+    };
+    rn = residual();
+    const double den = bn > 0.0 ? bn : 1.0;
+    double best = rn;
+    int stall = 0, replaced = 0;
+    bool restart = true;
+    while (it < max_iter) {
+      if (rn <= rel_tol * den) {
+        // the recurrence says converged: check against b - A x and, if
+        // rounding has let the two drift apart, restart from the true residual
+        rn = residual();
+        if (rn <= rel_tol * den || ++replaced > 4) break;
+        restart = true;
+      }
+      if (restart) {
+        if (!precondition(mode)) { mode = 0; fallback = 1; precondition(0); }
+        HIP_TRY(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, st));
+        restart = false;
+      }
+      HIP_TRY(launch_apply_dot(H.s, g, p, q, H.partials, st));
+      const double pq = reduce1(H, st);
+      HIP_TRY(launch_dot(H.s, g, p, r, H.partials, st));
+      const double pr = reduce1(H, st);
+      if (!(pq > 0.0) || !std::isfinite(pr)) {  // preconditioner broke A-conjugacy: restart plainly
+        if (mode != 0) { mode = 0; fallback = 1; restart = true; continue; }
+        return fail(GD_ERR_NUMERIC, "gd_fcg_solve: breakdown (p.Ap <= 0)");
+      }
+      const double a = pr / pq;
+      set_coef(H, a, 0.0, st);
+      HIP_TRY(launch_cg_update(H.s, g, H.dscal, x, r, p, q, H.partials, st));
+      rn = std::sqrt(reduce1(H, st));
+      ++it;
+      if (!std::isfinite(rn)) return fail(GD_ERR_NUMERIC, "gd_fcg_solve: non-finite residual");
+      if (rn < 0.9 * best) { best = rn; stall = 0; } else if (++stall >= 5 && mode != 0) {
+        mode = 0; fallback = 1; restart = true;  // the learned preconditioner stopped helping
+        rn = residual();
+        continue;
+      }
+      if (rn <= rel_tol * den) continue;
+      if (!precondition(mode)) { mode = 0; fallback = 1; restart = true; continue; }
+      HIP_TRY(launch_dot(H.s, g, z, q, H.partials, st));
+      const double zq = reduce1(H, st);
+      set_coef(H, 1.0, -zq / pq, st);
+      HIP_TRY(launch_axpby(H.s, g, H.dscal, z, p, p, st));  // p = z + beta p
+    }
+    const double rtrue = residual();
+    HIP_TRY(hipStreamSynchronize(st));
+    if (rep) {
+      rep->cycles = it;
+      rep->refine_steps = fallback;
+      rep->rel_residual = rtrue / den;
+      rep->b_norm = bn;
+      rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      rep->levels = (int)H.lv.size();
+    }
+    if (!(rtrue <= rel_tol * den)) return fail(GD_ERR_NOT_CONVERGED, "gd_fcg_solve: tolerance not reached");
     return GD_OK;
   });
 }

@@ -62,9 +62,18 @@ hipError_t launch_refine_update(gd_dtype s, const Geom& g, double* x64, const vo
 // Generic system: b = alpha V + sum_a w_a D_a^T G_a.
 hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const void* Gx,
                               const void* Gy, const void* Gz, void* b, hipStream_t st);
-// Generic system: per block (sum (b - A x)^2, sum b^2) in FP64.
-hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b,
+// Generic system: per block (sum (b - A x)^2, sum b^2) in FP64; r_out
+// (may be NULL) receives b - A x.
+hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b, void* r_out,
                                    double* partials, hipStream_t st);
+// Krylov vectors (caller's layout): q = A p with per-block p.q; per-block a.b;
+// x += c0 p, r -= c0 q with per-block r.r; out = c0 X + c1 Y.
+hipError_t launch_apply_dot(gd_dtype s, const Geom& g, const void* p, void* q, double* partials, hipStream_t st);
+hipError_t launch_dot(gd_dtype s, const Geom& g, const void* a, const void* b, double* partials, hipStream_t st);
+hipError_t launch_cg_update(gd_dtype s, const Geom& g, const double* coef, void* x, void* r, const void* p,
+                            const void* q, double* partials, hipStream_t st);
+hipError_t launch_axpby(gd_dtype s, const Geom& g, const double* coef, const void* X, const void* Y, void* out,
+                        hipStream_t st);
 // out[g * ncomp + c] = sum of partials[b * ncomp + c] over the blocks of grid g.
 hipError_t launch_reduce(const double* partials, const int64_t* block0, int ngrids, int ncomp,
                          double* out, hipStream_t st);

@@ -920,7 +920,7 @@ k_rhs_general(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 template <typename S>
 __global__ void __launch_bounds__(256)
 k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids,
-                   int zlen, int etx, const S* __restrict__ xin, const S* __restrict__ bin,
+                   int zlen, int etx, const S* __restrict__ xin, const S* __restrict__ bin, S* __restrict__ rout,
                    double* __restrict__ partials) {
   __shared__ double red[4];
   const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
@@ -940,6 +940,7 @@ k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict
       if (j < ny - 1) r += G.wy * (ld64(xin + v + py) - xc);
       if (k > 0) r += G.wz * (ld64(xin + v - pl) - xc);
       if (k < nz - 1) r += G.wz * (ld64(xin + v + pl) - xc);
+      if (rout) st64(rout + v, r);
       rr += r * r;
       bb += bv * bv;
     }
@@ -949,6 +950,97 @@ k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = s1;
     partials[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+// ------------------------------------------------- Krylov vector kernels
+// (caller's layout, one grid).  q = A p with the per-block FP64 sum of p.q.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_apply_dot(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+            const S* __restrict__ pin, S* __restrict__ qout, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  double pq = 0.0;
+  if (i < nx && j < ny) {
+    const int64_t pl = G.ipz, py = G.ipy;
+    for (int k = t.z0; k < t.z1; ++k) {
+      const int64_t v = G.ioff + k * pl + (int64_t)j * py + i;
+      const double pc = ld64(pin + v);
+      double q = G.alpha * pc;
+      if (i > 0) q += G.wx * (pc - ld64(pin + v - 1));
+      if (i < nx - 1) q += G.wx * (pc - ld64(pin + v + 1));
+      if (j > 0) q += G.wy * (pc - ld64(pin + v - py));
+      if (j < ny - 1) q += G.wy * (pc - ld64(pin + v + py));
+      if (k > 0) q += G.wz * (pc - ld64(pin + v - pl));
+      if (k < nz - 1) q += G.wz * (pc - ld64(pin + v + pl));
+      st64(qout + v, q);
+      pq += pc * q;
+    }
+  }
+  const double s = block_sum(pq, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// per-block FP64 sum of a.b
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_dot(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+      const S* __restrict__ a, const S* __restrict__ b, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  double s = 0.0;
+  if (i < G.nx && j < G.ny)
+    for (int k = t.z0; k < t.z1; ++k) {
+      const int64_t v = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
+      s += ld64(a + v) * ld64(b + v);
+    }
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// x += alpha p, r -= alpha q, per-block FP64 sum of r^2 (alpha = coef[0])
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_cg_update(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+            const double* __restrict__ coef, S* __restrict__ x, S* __restrict__ r, const S* __restrict__ p,
+            const S* __restrict__ q, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  const double a = coef[0];
+  double s = 0.0;
+  if (i < G.nx && j < G.ny)
+    for (int k = t.z0; k < t.z1; ++k) {
+      const int64_t v = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
+      st64(x + v, ld64(x + v) + a * ld64(p + v));
+      const double rn = ld64(r + v) - a * ld64(q + v);
+      st64(r + v, rn);
+      s += rn * rn;
+    }
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// out = a X + b Y (coef[0], coef[1]); Y may alias out
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_axpby(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+        const double* __restrict__ coef, const S* X, const S* Y, S* out) {
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  if (i >= G.nx || j >= G.ny) return;
+  const double a = coef[0], b = coef[1];
+  for (int k = t.z0; k < t.z1; ++k) {
+    const int64_t v = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
+    st64(out + v, a * ld64(X + v) + b * ld64(Y + v));
   }
 }
 
@@ -1166,10 +1258,44 @@ hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const vo
   return last();
 }
 
-hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b, double* partials,
-                                   hipStream_t st) {
+hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b, void* r_out,
+                                   double* partials, hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
-#define L(T) hipLaunchKernelGGL(k_general_residual<T>, GD_ARGS(g), (const T*)x, (const T*)b, partials)
+#define L(T) hipLaunchKernelGGL(k_general_residual<T>, GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, partials)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+hipError_t launch_apply_dot(gd_dtype s, const Geom& g, const void* p, void* q, double* partials, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L(T) hipLaunchKernelGGL(k_apply_dot<T>, GD_ARGS(g), (const T*)p, (T*)q, partials)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+hipError_t launch_dot(gd_dtype s, const Geom& g, const void* a, const void* b, double* partials, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L(T) hipLaunchKernelGGL(k_dot<T>, GD_ARGS(g), (const T*)a, (const T*)b, partials)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+hipError_t launch_cg_update(gd_dtype s, const Geom& g, const double* coef, void* x, void* r, const void* p,
+                            const void* q, double* partials, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L(T) hipLaunchKernelGGL(k_cg_update<T>, GD_ARGS(g), coef, (T*)x, (T*)r, (const T*)p, (const T*)q, partials)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+hipError_t launch_axpby(gd_dtype s, const Geom& g, const double* coef, const void* X, const void* Y, void* out,
+                        hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L(T) hipLaunchKernelGGL(k_axpby<T>, GD_ARGS(g), coef, (const T*)X, (const T*)Y, (T*)out)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();

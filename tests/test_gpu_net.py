@@ -1,0 +1,264 @@
+"""Learned preconditioner on the GPU: network forward and gradients against
+the FP64 reference, training on multigrid error pairs, flexible CG with the
+net and its fallback to the V-cycle preconditioner.
+
+The network is not part of the paper; what it gains is not pinned by it.
+The solves it takes part in are judged by the canonical residual and by the
+DCT oracle's solution."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import netref, solvers
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(p):
+    return torch.from_numpy(np.asarray(p, dtype=np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
+
+
+def gpu_params_as_oracle(net):
+    """The GPU's weights as its kernels see them (BF16), biases in FP32."""
+    p = net.get_params().astype(np.float64)
+    nw = sum(ci * co * 9 for ci, co in netref.LAYERS)
+    p[:nw] = bf16_round(p[:nw])
+    return p
+
+
+def smooth_images(b, h, w, seed):
+    """Residual-like test images: noise plus smooth structure."""
+    g = torch.Generator().manual_seed(seed)
+    x = torch.randn(b, h, w, generator=g, dtype=torch.float64)
+    yy, xx = torch.meshgrid(torch.linspace(0, 1, h, dtype=torch.float64), torch.linspace(0, 1, w, dtype=torch.float64),
+                            indexing="ij")
+    return x + 3.0 * torch.sin(6 * xx + 4 * yy)[None] * torch.rand(b, 1, 1, generator=g, dtype=torch.float64)
+
+
+@pytest.fixture(scope="module")
+def net(gd):
+    n = gd.Net(seed=11)
+    yield n
+    n.close()
+
+
+def test_params_roundtrip(gd, net):
+    p = np.random.default_rng(0).standard_normal(net.num_params).astype(np.float32)
+    old = net.get_params()
+    net.set_params(p)
+    np.testing.assert_array_equal(net.get_params(), p)
+    net.set_params(old)
+    assert net.num_params == sum(ci * co * 9 + co for ci, co in netref.LAYERS)
+
+
+@pytest.mark.parametrize("shape", [(2, 8, 256), (1, 12, 512), (3, 4, 256)])
+def test_forward_matches_oracle(gd, net, shape):
+    r = smooth_images(*shape, seed=sum(shape))
+    z = net.forward(r.float().cuda()).double().cpu().numpy()
+    ref = netref.forward(gpu_params_as_oracle(net), r.float().double().numpy())
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    # BF16 activations (8-bit significand) through nine layers
+    assert err < 2e-2, err
+
+
+def test_forward_batch_independent(gd, net):
+    r = smooth_images(3, 8, 256, seed=5).float().cuda()
+    z = net.forward(r)
+    for i in range(3):
+        torch.testing.assert_close(net.forward(r[i:i + 1].contiguous()), z[i:i + 1], rtol=0, atol=0)
+
+
+def test_forward_zero_residual(gd, net):
+    z = net.forward(torch.zeros(1, 4, 256, device="cuda"))
+    ref = netref.forward(gpu_params_as_oracle(net), np.zeros((1, 4, 256)))
+    np.testing.assert_allclose(z.double().cpu().numpy(), ref, rtol=2e-2, atol=1e-3 * np.abs(ref).max() + 1e-6)
+
+
+def test_forward_rejects_bad_shape(gd, net):
+    with pytest.raises(gd.GDError):
+        net.forward(torch.zeros(1, 8, 200, device="cuda"))
+    with pytest.raises(gd.GDError):
+        net.forward(torch.zeros(1, 6, 256, device="cuda"))
+
+
+@pytest.mark.parametrize("shape", [(2, 8, 256), (1, 16, 512)])
+def test_gradients_match_oracle(gd, net, shape):
+    r = smooth_images(*shape, seed=17 + shape[1])
+    e = smooth_images(*shape, seed=23 + shape[1]) * 0.3
+    g, L = net.gradients(r.float().cuda(), e.float().cuda())
+    Lref, gref = netref.gradients(gpu_params_as_oracle(net), r.float().double().numpy(), e.float().double().numpy())
+    assert abs(L - Lref) <= 1e-2 * Lref, (L, Lref)
+    Ws, bs = netref.unflatten(np.arange(net.num_params))
+    g = g.astype(np.float64)
+    report = []
+    for l in range(9):
+        for name, ix in (("W", Ws[l].ravel().astype(np.int64)), ("b", bs[l].astype(np.int64))):
+            a, b = g[ix], gref[ix]
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            cos = a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
+            report.append((l, name, rel, cos))
+    print("layer, param, rel. error, cosine:", report)
+    # BF16 activations and back-propagated gradients (unit round-off 2^-9)
+    # feed sums over all pixels that cancel strongly; FP32 accumulation
+    for l, name, rel, cos in report:
+        assert rel < 4e-2 and cos > 0.999, (l, name, rel, cos)
+    assert np.linalg.norm(g - gref) / np.linalg.norm(gref) < 2e-2
+
+
+def test_gradients_deterministic(gd, net):
+    r = smooth_images(2, 8, 256, seed=3).float().cuda()
+    e = smooth_images(2, 8, 256, seed=4).float().cuda()
+    g1, l1 = net.gradients(r, e)
+    g2, l2 = net.gradients(r, e)
+    np.testing.assert_array_equal(g1, g2)
+    assert l1 == l2
+
+
+def test_train_step_is_adam(gd):
+    net = gd.Net(seed=3)
+    r = smooth_images(1, 8, 256, seed=8).float().cuda()
+    e = smooth_images(1, 8, 256, seed=9).float().cuda()
+    p0 = net.get_params().astype(np.float64)
+    g, _ = net.gradients(r, e)
+    net.train_step(r, e, lr=1e-3)
+    p1 = net.get_params().astype(np.float64)
+    # first Adam step: m/(1-b1) = g, v/(1-b2) = g^2, step = lr * g / (|g| + eps)
+    g = g.astype(np.float64)
+    expect = p0 - 1e-3 * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(p1, expect, rtol=0, atol=2e-6)
+    net.close()
+
+
+# ----------------------------------------------------------- solving with it
+
+ALPHA = 0.01
+
+
+def make_pairs(gd, h, b, ncycles=(1, 2)):
+    """(r_k, e_k) from k V-cycles on A x = b (slices as a batch)."""
+    xs = torch.zeros_like(b)
+    h.vcycle(xs, b, 30)
+    rs, es = [], []
+    for k in ncycles:
+        r, e = h.error_pairs(b, xs, k)
+        rs.append(r)
+        es.append(e)
+    return torch.cat(rs), torch.cat(es)
+
+
+@pytest.fixture(scope="module")
+def trained(gd):
+    """A net trained on multigrid error pairs of 256^2 slices."""
+    from oracle import grid
+
+    nz, n = 16, 256
+    h = gd.Hierarchy((nz, n, n), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+    spec = synth.StackSpec(n, n, nz, (4.0, 40.0), True, 13100416)
+    I0 = synth.make_stack(spec).to(torch.float64).numpy()
+    b = torch.from_numpy(grid.rhs_sp(I0, I0.mean(axis=0, keepdims=True).repeat(nz, 0), ALPHA)).float().cuda()
+    r, e = make_pairs(gd, h, b)
+    net = gd.Net(seed=1)
+    losses = []
+    for step in range(300):
+        i = (step * 8) % r.shape[0]
+        losses.append(net.train_step(r[i:i + 8].contiguous(), e[i:i + 8].contiguous(), lr=2e-3))
+    yield net, h, losses
+    net.close()
+    h.close()
+
+
+def held_out(gd, n=256, nz=8, seed=13100417):
+    from oracle import grid
+
+    spec = synth.StackSpec(n, n, nz, (4.0, 40.0), True, seed)
+    I0 = synth.make_stack(spec).to(torch.float64).numpy()
+    return grid.rhs_sp(I0, np.roll(I0, 1, axis=0), ALPHA)
+
+
+def test_training_reduces_loss(gd, trained):
+    net, h, losses = trained
+    assert np.isfinite(losses).all()
+    assert np.mean(losses[-20:]) < 0.7 * np.mean(losses[:5]), (losses[:5], losses[-20:])
+
+
+def test_net_corrects_multigrid_error(gd, trained):
+    """On held-out slices, e_1 - N(r_1) is smaller than e_1 (the one-cycle
+    multigrid error); parity-unpinned by the paper."""
+    net, _, _ = trained
+    b = torch.from_numpy(held_out(gd)).float().cuda()
+    h = gd.Hierarchy(tuple(b.shape), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+    r, e = make_pairs(gd, h, b, ncycles=(1,))
+    z = net.forward(r)
+    gain = (torch.linalg.norm(e - z) / torch.linalg.norm(e)).item()
+    h.close()
+    assert gain < 0.9, gain
+
+
+@pytest.mark.parametrize("precond", [0, 1, 2])
+def test_fcg_solution_matches_oracle(gd, trained, precond):
+    net, _, _ = trained
+    bnp = held_out(gd, seed=13100418)
+    b = torch.from_numpy(bnp).float().cuda()
+    h = gd.Hierarchy(tuple(b.shape), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+    x = torch.zeros_like(b)
+    rep = h.fcg(x, b, net=net, precond=precond, rel_tol=1e-6, max_iter=300, check=False)
+    h.close()
+    assert rep["status"] == 0 and rep["rel_residual"] <= 1e-6, rep
+    ref = solvers.dct_solve(bnp, ALPHA, (1.0, 1.0, 0.0))
+    err = np.linalg.norm(x.double().cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err < 2e-5, err
+
+
+def test_fcg_with_net_needs_fewer_iterations(gd, trained):
+    """V-cycle + net preconditioning against the V-cycle alone (same FCG)."""
+    net, _, _ = trained
+    b = torch.from_numpy(held_out(gd, seed=13100419)).float().cuda()
+    h = gd.Hierarchy(tuple(b.shape), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+    it = {}
+    for m in (0, 2):
+        x = torch.zeros_like(b)
+        rep = h.fcg(x, b, net=net, precond=m, rel_tol=1e-6, max_iter=300, check=False)
+        assert rep["status"] == 0 and rep["fallback_used"] == 0, rep
+        it[m] = rep["iterations"]
+    h.close()
+    assert it[2] <= it[0], it
+
+
+@pytest.mark.parametrize("broken", ["nan", "zero"])
+def test_fcg_falls_back_to_multigrid(gd, broken):
+    net = gd.Net(seed=2)
+    p = net.get_params()
+    net.set_params(np.full_like(p, np.nan) if broken == "nan" else np.zeros_like(p))
+    b = torch.from_numpy(held_out(gd, nz=4, seed=13100420)).float().cuda()
+    h = gd.Hierarchy(tuple(b.shape), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+    for m in (1, 2):
+        x = torch.zeros_like(b)
+        rep = h.fcg(x, b, net=net, precond=m, rel_tol=1e-6, max_iter=300, check=False)
+        assert rep["status"] == 0 and rep["rel_residual"] <= 1e-6, rep
+        if m == 1 or broken == "nan":
+            assert rep["fallback_used"] == 1
+    h.close()
+    net.close()
+
+
+def test_fcg_falls_back_on_unsupported_shape(gd, trained):
+    net, _, _ = trained
+    b = torch.from_numpy(held_out(gd, n=200, nz=2, seed=13100421)).float().cuda()
+    h = gd.Hierarchy(tuple(b.shape), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+    x = torch.zeros_like(b)
+    rep = h.fcg(x, b, net=net, precond=1, rel_tol=1e-6, max_iter=300, check=False)
+    h.close()
+    assert rep["status"] == 0, rep
+    assert rep["fallback_used"] == 1 and rep["rel_residual"] <= 1e-6
+
+
+def test_fcg_rejects_bad_arguments(gd):
+    h = gd.Hierarchy((2, 8, 256), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+    b = torch.ones(2, 8, 256, device="cuda")
+    with pytest.raises(gd.GDError):
+        h.fcg(torch.zeros_like(b), b, net=None, precond=1)
+    with pytest.raises(gd.GDError):
+        h.fcg(torch.zeros_like(b), b, precond=3)
+    h.close()
