@@ -24,6 +24,9 @@ WORKLOADS = {
     "stack4k-f16": ("stack4k", "f16", 1, "4096x4096x256 stack, FP16 storage, FP32 relaxation, FP64 refinement"),
     "stack4k-bf16": ("stack4k", "bf16", 1, "4096x4096x256 stack, BF16 storage, FP32 relaxation, FP64 refinement"),
     "stack4k-f32": ("stack4k", "f32", 0, "4096x4096x256 stack, FP32 storage + arithmetic, plain V-cycles"),
+    "learned2k": ("learned", "f32", 0, "2048x2048x64 stack, per-slice screened Poisson (alpha 0.01), flexible CG "
+                  "preconditioned by a V-cycle then the BF16 U-Net, net trained on multigrid error pairs of "
+                  "1024x1024 slices"),
     "slices2048": ("slices", "f32", 0, "2048 independent slices, sides log-uniform in [256, 2048], alpha U(0.001, 0.1), "
                    "per-slice screened Poisson, FP32, plain V-cycles, one batched launch per level step"),
 }
@@ -110,6 +113,119 @@ def bench_slices(a, gd, synth, torch, desc):
     print(json.dumps(line), flush=True)
 
 
+def bench_learned(a, gd, synth, torch, desc):
+    """Learned preconditioner: train on multigrid (residual, error) pairs of
+    1024^2 slices (untimed), then solve the per-slice screened Poisson system
+    of a 2048^2 x 64 stack by flexible CG with the V-cycle + net
+    preconditioner; plain V-cycles and V-cycle-preconditioned FCG on the
+    same system are timed beside it."""
+    dev = torch.device("cuda:0")
+
+    def sp_rhs(I0, I1):
+        # alpha I1 + (D_x^T D_x + D_y^T D_y) I0 per slice (Eq. (2)); input preparation
+        b = ALPHA * I1.double()
+        for ax in (2, 1):
+            d = torch.diff(I0.double(), dim=ax)
+            n = I0.shape[ax]
+            b.narrow(ax, 0, n - 1).sub_(d)
+            b.narrow(ax, 1, n - 1).add_(d)
+        return b.float().contiguous()
+
+    def stack(n, nz, seed):
+        spec = synth.StackSpec(n, n, nz, (4.0, 40.0), True, seed)
+        I0 = synth.make_stack(spec, device=dev, dtype=torch.float32)
+        I1, _ = gd.smooth_z(I0, BETA, out_dtype=torch.float32, rel_tol=TOL)
+        return sp_rhs(I0, I1)
+
+    t0 = time.perf_counter()
+    btr = stack(1024, 16, 13100430)
+    h = gd.Hierarchy(tuple(btr.shape), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+    xs = torch.zeros_like(btr)
+    h.vcycle(xs, btr, 30)
+    pairs = [h.error_pairs(btr, xs, k) for k in (1, 2, 3)]
+    h.close()
+    r = torch.cat([p[0] for p in pairs])
+    e = torch.cat([p[1] for p in pairs])
+    del pairs, xs, btr
+    net = gd.Net(seed=1)
+    g = torch.Generator().manual_seed(0)
+    nsteps, bs, lr = 300, 4, 2e-3
+    perm = torch.randperm(r.shape[0], generator=g)
+    losses = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(nsteps):
+        i = (s * bs) % r.shape[0]
+        idx = perm[i:i + bs] if i + bs <= r.shape[0] else perm[:bs]
+        losses.append(net.train_step(r[idx].contiguous(), e[idx].contiguous(), lr=lr if s < 0.7 * nsteps else 0.2 * lr))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    sc = torch.sqrt((r.double() ** 2).mean(dim=(1, 2)))
+    zero_loss = ((e.double() / sc[:, None, None]) ** 2).mean().item()
+    del r, e
+    b = stack(2048, 64, 13100431)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    nvox = b.numel()
+    h = gd.Hierarchy(tuple(b.shape), ALPHA, (1.0, 1.0, 0.0), torch.float32)
+
+    def solve(mode):
+        x = torch.zeros_like(b)
+        if mode == "mg":
+            for c in range(1, 100):
+                rr = h.vcycle(x, b, 1)
+                if rr <= TOL:
+                    return {"iterations": c, "rel_residual": rr}
+            raise RuntimeError("plain V-cycles did not converge")
+        rep = h.fcg(x, b, net=net, precond=mode, rel_tol=TOL, max_iter=100)
+        return rep
+
+    results = {}
+    for mode, name in (("mg", "plain_vcycles"), (0, "fcg_vcycle"), (2, "fcg_vcycle_net")):
+        for _ in range(a.warmup):
+            solve(mode)
+        torch.cuda.synchronize()
+        if mode == 2:
+            net.set_timing(True)
+        t2 = time.perf_counter()
+        for _ in range(a.steps):
+            rep = solve(mode)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t2) / a.steps
+        results[name] = {"ms_per_solve": dt * 1e3, "iterations": rep["iterations"],
+                         "rel_residual": rep["rel_residual"], "voxels_per_s": nvox / dt}
+        if mode == 2:
+            results[name]["fallback_used"] = rep["fallback_used"]
+    layers = []
+    for l in range(9):
+        ms, n, fl = net.kernel_time(l)
+        layers.append({"layer": l, "launches": n, "avg_launch_ms": ms / max(n, 1),
+                       "TFLOP/s": fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0})
+    net.set_timing(False)
+    dom = max(range(9), key=lambda l: layers[l]["avg_launch_ms"] * layers[l]["launches"])
+    peak = 2500.0  # dense BF16 MFMA, TFLOP/s
+    learned = results["fcg_vcycle_net"]
+    line = {
+        "metric": "voxels/s to 1e-6 rel. residual (per-slice SP, learned-preconditioned FCG)",
+        "value": learned["voxels_per_s"], "unit": "voxels/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": learned["ms_per_solve"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {desc}; tol {TOL:g}", "nx": 2048, "ny": 2048, "nz": 64,
+                   "voxels": nvox},
+        "roofline": {"bound": "mfma", "achieved": layers[dom]["TFLOP/s"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": layers[dom]["TFLOP/s"] / peak, "traffic": None,
+                     "kernel": f"k_conv3x3 forward, layer {dom}", "layers": layers},
+        "solvers": results,
+        "training": {"pairs": "48 (r_k, e_k), k = 1, 2, 3 V-cycles on 16 slices of 1024^2", "steps": nsteps,
+                     "batch": bs, "seconds": train_s, "loss_first": losses[0], "loss_last": losses[-1],
+                     "loss_zero_net": zero_loss},
+        "setup_s": setup_s,
+    }
+    h.close()
+    net.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -138,6 +254,8 @@ def main():
 
     if spec_key == "slices":
         return bench_slices(a, gd, synth, torch, desc)
+    if spec_key == "learned":
+        return bench_learned(a, gd, synth, torch, desc)
     t0 = time.perf_counter()
     I0 = synth.make_stack(spec, device=dev, dtype=tdt)
     torch.cuda.synchronize()

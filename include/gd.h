@@ -183,6 +183,13 @@ gd_status gd_net_gradients(gd_net* n, const float* r, const float* e, int64_t nx
 gd_status gd_net_train_step(gd_net* n, const float* r, const float* e, int64_t nx, int64_t ny, int64_t batch,
                             float lr, double* loss_out, void* stream);
 
+/* Timing of the forward convolutions (HIP events on the caller's stream).
+ * set_timing(on) also clears the totals.  kernel_time: total ms, launches
+ * and algorithmic FLOPs (2 * 9 * cin * cout per output pixel, real channel
+ * counts) of layer 0..8 since then. */
+gd_status gd_net_set_timing(gd_net* n, int on);
+gd_status gd_net_kernel_time(const gd_net* n, int layer, double* ms, int64_t* launches, double* flops);
+
 /* Flexible conjugate gradients on the hierarchy's system (FP32 storage) with
  * preconditioner 0: one V-cycle, 1: the net, 2: a V-cycle then the net on
  * its remaining residual.  x in/out, b in (caller's layout).  When the net

@@ -107,6 +107,8 @@ _SIGS = {
     "gd_net_forward": (_i, [_vp, _vp, _vp, _i64, _i64, _i64, _vp]),
     "gd_net_gradients": (_i, [_vp, _vp, _vp, _i64, _i64, _i64, _vp, ctypes.POINTER(_d), _vp]),
     "gd_net_train_step": (_i, [_vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, ctypes.POINTER(_d), _vp]),
+    "gd_net_set_timing": (_i, [_vp, _i]),
+    "gd_net_kernel_time": (_i, [_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "gd_fcg_solve": (_i, [_vp, _vp, _vp, _vp, _i, _d, _i, ctypes.POINTER(Report), _vp]),
 }
 
@@ -345,6 +347,16 @@ class Net:
         _check(_lib.gd_net_train_step(self._n, _ptr(r), _ptr(e), nx, ny, b, float(lr), ctypes.byref(loss),
                                       _stream()), net=True)
         return loss.value
+
+    def set_timing(self, on=True):
+        _check(_lib.gd_net_set_timing(self._n, int(bool(on))), net=True)
+
+    def kernel_time(self, layer):
+        """(total ms, launches, algorithmic FLOPs) of one layer's forward convolutions."""
+        ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(_lib.gd_net_kernel_time(self._n, int(layer), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)),
+               net=True)
+        return ms.value, n.value, fl.value
 
     def close(self):
         if self._n:

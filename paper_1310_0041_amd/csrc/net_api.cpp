@@ -91,6 +91,30 @@ struct gd_net {
   Buf dY, dA5, dC1, dA4, dC2, dA3b, dA3, dP2, dA2, dP1, dA1;
   Buf part, bpart, gpk, scale, lpart;
   std::vector<double> hl;
+  // optional HIP-event timing of the forward convolutions, per layer
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<int> ev_layer;
+  std::vector<double> ev_flops;
+  size_t ev_used = 0;
+  double t_ms[9] = {}, t_flops[9] = {};
+  int64_t t_cnt[9] = {};
+  ~gd_net() {
+    for (auto& p : ev) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+  }
+  void harvest() {  // after the stream has been synchronised
+    for (size_t i = 0; i < ev_used; ++i) {
+      float ms = 0.f;
+      NT_TRY(hipEventElapsedTime(&ms, ev[i].first, ev[i].second));
+      t_ms[ev_layer[i]] += ms;
+      t_flops[ev_layer[i]] += ev_flops[i];
+      t_cnt[ev_layer[i]] += 1;
+    }
+    ev_used = 0;
+  }
 
   void layout() {
     size_t o = 0;
@@ -153,8 +177,22 @@ void conv_fwd(gd_net& N, int l, const bf* in, int in_s, int in_o, bf* out, int o
               hipStream_t st, float* out_f = nullptr) {
   const LayerSpec& L = kLayers[l];
   const float* bias = N.master.as<float>() + N.boff[l];
+  if (N.timing) {
+    if (N.ev_used == N.ev.size()) {
+      hipEvent_t a, b;
+      NT_TRY(hipEventCreate(&a));
+      NT_TRY(hipEventCreate(&b));
+      N.ev.push_back({a, b});
+      N.ev_layer.push_back(0);
+      N.ev_flops.push_back(0.0);
+    }
+    N.ev_layer[N.ev_used] = l;
+    N.ev_flops[N.ev_used] = 2.0 * 9.0 * L.cin * L.cout * (double)N.B * h * w;  // real channels, not padding
+    NT_TRY(hipEventRecord(N.ev[N.ev_used].first, st));
+  }
   NT_TRY(conv(L.cinp, L.coutp, in, in_s, in_o, N.wpk[l].as<bf>(), bias, l != 8, out, out_f, out_s, out_o,
               L.cout, nullptr, 0, 0, N.B, h, w, st));
+  if (N.timing) NT_TRY(hipEventRecord(N.ev[N.ev_used++].second, st));
 }
 
 // weight and bias gradients of layer l into N.grad
@@ -393,6 +431,7 @@ gd_status gd_net_forward(gd_net* n, const float* r, float* z, int64_t nx, int64_
       NT_TRY(unpack_output(n->Y.as<float>(), 1, z + b0 * npix, n->scale.as<float>(), npix, (int)nbat, st));
     }
     NT_TRY(hipStreamSynchronize(st));
+    n->harvest();
     return GD_OK;
   });
 }
@@ -407,6 +446,7 @@ gd_status gd_net_gradients(gd_net* n, const float* r, const float* e, int64_t nx
     n->shape((int)batch, (int)ny, (int)nx);
     forward(*n, r, st);
     const double L = backward(*n, e, st);
+    n->harvest();
     if (loss_out) *loss_out = L;
     if (grad_host) NT_TRY(hipMemcpy(grad_host, n->grad.p, n->nparam * 4, hipMemcpyDeviceToHost));
     return GD_OK;
@@ -424,6 +464,7 @@ gd_status gd_net_train_step(gd_net* n, const float* r, const float* e, int64_t n
     n->shape((int)batch, (int)ny, (int)nx);
     forward(*n, r, st);
     const double L = backward(*n, e, st);
+    n->harvest();
     if (loss_out) *loss_out = L;
     if (!std::isfinite(L)) return nfail(GD_ERR_NUMERIC, "gd_net_train_step: non-finite loss");
     n->step += 1;
@@ -435,6 +476,26 @@ gd_status gd_net_train_step(gd_net* n, const float* r, const float* e, int64_t n
     NT_TRY(hipStreamSynchronize(st));
     return GD_OK;
   });
+}
+
+gd_status gd_net_set_timing(gd_net* n, int on) {
+  if (!n) return nfail(GD_ERR_INVALID, "gd_net_set_timing: null handle");
+  n->timing = on != 0;
+  n->ev_used = 0;
+  for (int l = 0; l < 9; ++l) {
+    n->t_ms[l] = 0.0;
+    n->t_flops[l] = 0.0;
+    n->t_cnt[l] = 0;
+  }
+  return GD_OK;
+}
+
+gd_status gd_net_kernel_time(const gd_net* n, int layer, double* ms, int64_t* launches, double* flops) {
+  if (!n || layer < 0 || layer >= 9) return nfail(GD_ERR_INVALID, "gd_net_kernel_time: bad handle or layer");
+  if (ms) *ms = n->t_ms[layer];
+  if (launches) *launches = n->t_cnt[layer];
+  if (flops) *flops = n->t_flops[layer];
+  return GD_OK;
 }
 
 }  // extern "C"

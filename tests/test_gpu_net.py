@@ -262,3 +262,19 @@ def test_fcg_rejects_bad_arguments(gd):
     with pytest.raises(gd.GDError):
         h.fcg(torch.zeros_like(b), b, precond=3)
     h.close()
+
+
+def test_conv_timing_counts(gd):
+    net = gd.Net(seed=4)
+    net.set_timing(True)
+    r = smooth_images(3, 16, 512, seed=12).float().cuda()
+    net.forward(r)
+    net.forward(r)
+    for l, (ci, co) in enumerate(netref.LAYERS):
+        ms, n, fl = net.kernel_time(l)
+        level = {0: 0, 1: 0, 2: 1, 3: 1, 4: 2, 5: 2, 6: 1, 7: 0, 8: 0}[l]
+        assert n == 2 and ms > 0.0
+        assert fl == 2 * 2 * 9 * ci * co * 3 * 16 * 512 / 4 ** level
+    net.set_timing(False)
+    assert net.kernel_time(0)[1] == 0
+    net.close()
