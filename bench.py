@@ -34,6 +34,13 @@ BETA = (1.0, 1.0, 4.0)
 ALPHA = 0.01
 TOL = 1e-6
 HBM_PEAK_GBS = 8000.0
+# relaxation tile variants of 3-D grids (GD_SWEEP_TILE; the library's default is 2)
+SWEEP_TILES = {0: (64, 8), 1: (128, 8), 2: (64, 16), 3: (128, 16)}
+
+
+def sweep_tile():
+    t = int(os.environ.get("GD_SWEEP_TILE", "2"))
+    return t if t in SWEEP_TILES else 2
 
 
 def parse():
@@ -326,7 +333,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_rb_sweep<%s,64,8,false,true> finest level" % storage,
+            "kernel": "k_rb_sweep<%s,%d,%d,false,true> finest level" % ((storage,) + SWEEP_TILES[sweep_tile()]),
             "launches": launches,
             "avg_launch_ms": avg_ms,
             "algorithmic_bytes_per_launch": bytes_per,

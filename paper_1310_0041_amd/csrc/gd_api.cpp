@@ -85,6 +85,7 @@ struct Tab {  // launch geometry of one kernel family on one level
   int64_t* d_b0 = nullptr;
   std::vector<int64_t> h_b0;
   int zlen = 1;
+  int tile = 0;  // relaxation tile variant (3-D grids)
   Geom geom(const GridDesc* d_grids, int ngrids, bool row) const {
     Geom g;
     g.grids = d_grids;
@@ -94,6 +95,7 @@ struct Tab {  // launch geometry of one kernel family on one level
     g.zlen = zlen;
     g.etx = row ? EWR_TX : EW_TX;
     g.row = row;
+    g.tile = tile;
     return g;
   }
 };
@@ -103,7 +105,7 @@ struct Level {
   GridDesc* d = nullptr;
   int64_t total = 0;
   bool row = false;  // every grid has ny == 1
-  Tab sw, ew, rc, rz;  // relaxation, per-voxel, child-cell and z-marching restriction tiles
+  Tab sw, ew, rc, rz, pp;  // relaxation, per-voxel, child-cell, z-marching restriction, prolongation tiles
   void* x = nullptr;
   void* xt = nullptr;
   void* b = nullptr;
@@ -138,6 +140,7 @@ struct Hier {
   Geom g_ew(int l) const { return lv[l].ew.geom(lv[l].d, ngrids, lv[l].row); }
   Geom g_rc(int l) const { return lv[l].rc.geom(lv[l].d, ngrids, lv[l].row); }
   Geom g_rz(int l) const { return lv[l].rz.geom(lv[l].d, ngrids, lv[l].row); }
+  Geom g_pp(int l) const { return lv[l].pp.geom(lv[l].d, ngrids, lv[l].row); }
 };
 
 static void coarsen_factors(const GridDesc& g, int f[3]) {
@@ -169,13 +172,27 @@ static void build_tab(Tab& t, const std::vector<GridDesc>& grids, int TX, int TY
   }
 }
 
-// Blocks a relaxation launch aims for (z-chunks are cut until reached).
-static int64_t sweep_target() {
-  static int64_t v = [] {
-    const char* e = std::getenv("GD_SWEEP_BLOCKS");
-    return e ? std::max<int64_t>(1, std::atoll(e)) : (int64_t)8192;
+// Relaxation tile variant of 3-D grids (GD_SWEEP_TILE, 0..3; 64 x 16 by
+// default, the fastest of the four on MI355X for 1024^2 x 128 FP32 stacks).
+static int sweep_tile() {
+  static int v = [] {
+    const char* e = std::getenv("GD_SWEEP_TILE");
+    const int t = e ? std::atoi(e) : 2;
+    return (t >= 0 && t < 4) ? t : 2;
   }();
   return v;
+}
+
+// Blocks a finest-level relaxation launch aims for (z-chunks are cut until
+// reached): GD_SWEEP_BLOCKS for 3-D grids (default 4096), GD_SWEEP_BLOCKS_ROW
+// for one-line grids (2-D slices, default 8192).
+static int64_t env_blocks(const char* name, int64_t dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::max<int64_t>(1, std::atoll(e)) : dflt;
+}
+static int64_t sweep_target(bool row = false) {
+  static int64_t v3 = env_blocks("GD_SWEEP_BLOCKS", 4096), vr = env_blocks("GD_SWEEP_BLOCKS_ROW", 8192);
+  return row ? vr : v3;
 }
 
 static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
@@ -255,32 +272,38 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     Level& L = H->lv[li];
     // the finest level aims for more blocks than the coarser ones (its
     // launches are then told apart by their grid size in kernel traces)
-    const int64_t tgt = li == 0 ? sweep_target() : std::max<int64_t>(1, sweep_target() / 2);
+    const int64_t tgt = li == 0 ? sweep_target(L.row) : std::max<int64_t>(1, sweep_target(L.row) / 2);
     if (L.row) {
       build_tab(L.sw, L.h, SWR_TX, 1, false, tgt);
       build_tab(L.ew, L.h, EWR_TX, 1, false, 8192);
       build_tab(L.rc, L.h, EWR_TX, 1, true, 8192);
       build_tab(L.rz, L.h, SWR_TX, 1, false, 4096, true);
+      build_tab(L.pp, L.h, SWR_TX, 1, false, tgt);
     } else {
-      build_tab(L.sw, L.h, SW_TX, SW_TY, false, tgt);
+      const int v = sweep_tile();
+      build_tab(L.sw, L.h, SWEEP_TILE_TX[v], SWEEP_TILE_TY[v], false, tgt);
+      L.sw.tile = v;
       build_tab(L.ew, L.h, EW_TX, EW_TY, false, 8192);
       build_tab(L.rc, L.h, EW_TX, EW_TY, true, 8192);
       build_tab(L.rz, L.h, SW_TX, SW_TY, false, 2048, true);
+      build_tab(L.pp, L.h, SW_TX, SW_TY, false, tgt);
     }
-    maxblocks = std::max({maxblocks, L.sw.h_b0.back(), L.ew.h_b0.back(), L.rc.h_b0.back(), L.rz.h_b0.back()});
+    maxblocks = std::max({maxblocks, L.sw.h_b0.back(), L.ew.h_b0.back(), L.rc.h_b0.back(), L.rz.h_b0.back(),
+                          L.pp.h_b0.back()});
     const size_t nb = (size_t)H->ngrids + 1;
     const size_t gbytes = L.h.size() * sizeof(GridDesc);
-    const size_t bytes = gbytes + 4 * nb * sizeof(int64_t);
+    const size_t bytes = gbytes + 5 * nb * sizeof(int64_t);
     char* dev = (char*)H->alloc(bytes);
     L.d = (GridDesc*)dev;
     L.sw.d_b0 = (int64_t*)(dev + gbytes);
     L.ew.d_b0 = L.sw.d_b0 + nb;
     L.rc.d_b0 = L.ew.d_b0 + nb;
     L.rz.d_b0 = L.rc.d_b0 + nb;
+    L.pp.d_b0 = L.rz.d_b0 + nb;
     stage.resize(bytes);
     std::memcpy(stage.data(), L.h.data(), gbytes);
-    const Tab* tabs[4] = {&L.sw, &L.ew, &L.rc, &L.rz};
-    for (int k = 0; k < 4; ++k)
+    const Tab* tabs[5] = {&L.sw, &L.ew, &L.rc, &L.rz, &L.pp};
+    for (int k = 0; k < 5; ++k)
       std::memcpy(stage.data() + gbytes + k * nb * sizeof(int64_t), tabs[k]->h_b0.data(), nb * sizeof(int64_t));
     HIP_TRY(hipMemcpy(dev, stage.data(), bytes, hipMemcpyHostToDevice));
     L.x = H->alloc(L.total * es);
@@ -395,10 +418,10 @@ struct Cycler {
   void correct(int l) {
     below(l + 1);
     Level& C = H.lv[l + 1];
-    if (fuse && post > 0) {
+    if (fuse && post > 0 && H.lv[l].sw.tile == 0) {
       smooth(l, post, C.x);  // prolongation fused into the first sweep's loads
     } else {
-      HIP_TRY(launch_prolong_pair(H.s, H.g_sw(l), C.x, H.lv[l].x, pmode, st));
+      HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), C.x, H.lv[l].x, pmode, st));
       smooth(l, post);
     }
   }
@@ -466,17 +489,17 @@ struct Outcome {
 // ||b|| of the canonical system per grid (and the correction-form rhs when b_out)
 static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero, std::vector<double>& bn,
                             hipStream_t st) {
-  HIP_TRY(launch_rhs_corr(P.tin, H.s, H.g_ew(0), P.I0, P.I1, b_out, x_zero, H.partials, st));
-  HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, H.ngrids, 1, H.dred, st));
+  HIP_TRY(launch_rhs_corr(P.tin, H.s, H.g_rz(0), P.I0, P.I1, b_out, x_zero, H.partials, st));
+  HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, H.ngrids, 1, H.dred, st));
   read_dred(H, 1, st);
   bn.resize(H.ngrids);
   for (int g = 0; g < H.ngrids; ++g) bn[g] = std::sqrt(H.hpin[g]);
 }
 
 static std::vector<double> canon_residual(Hier& H, const Problem& P, int mode, void* rout, hipStream_t st) {
-  HIP_TRY(launch_canon_residual(P.tin, H.s, mode, H.g_ew(0), P.I0, P.I1, H.lv[0].x, H.x64, rout, H.dscal + H.ngrids,
+  HIP_TRY(launch_canon_residual(P.tin, H.s, mode, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, rout, H.dscal + H.ngrids,
                                 H.partials, st));
-  HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, H.ngrids, 1, H.dred, st));
+  HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, H.ngrids, 1, H.dred, st));
   read_dred(H, 1, st);
   std::vector<double> r(H.ngrids);
   for (int g = 0; g < H.ngrids; ++g) r[g] = std::sqrt(H.hpin[g]);
@@ -1094,7 +1117,7 @@ gd_status gd_rb_sweep(const void* xin, void* xout, const void* b, gd_dtype s, in
   return run_guarded([&]() -> gd_status {
     int64_t nb;
     double* part;
-    Geom geo = slice ? step_geom(g, SWR_TX, 1, false, sweep_target(), nb, &part, st)
+    Geom geo = slice ? step_geom(g, SWR_TX, 1, false, sweep_target(true), nb, &part, st)
                      : step_geom(g, SW_TX, SW_TY, false, sweep_target(), nb, &part, st);
     geo.row = slice;
     HIP_TRY(launch_rb_sweep(s, geo, xin, xout, b, nullptr, 0, st));

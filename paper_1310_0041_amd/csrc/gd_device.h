@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 #include <stdint.h>
@@ -94,6 +95,74 @@ __device__ __forceinline__ void st2(S* p, bool vec, bool second, typename Ty<S>:
     Ty<S>::st(p, a);
     if (second) Ty<S>::st(p + 1, b);
   }
+}
+
+// Raw (unconverted) values: a load whose result is converted at once makes
+// the wave wait for it right there; kept raw, the wait moves to the first
+// use and the load stays in flight meanwhile.
+template <typename S> struct Raw {
+  using W = std::conditional_t<sizeof(S) == 8, double, std::conditional_t<sizeof(S) == 4, float, uint32_t>>;
+  W w = 0;
+};
+template <typename S> struct Raw2 {  // two consecutive values
+  using W = std::conditional_t<sizeof(S) == 8, double2, std::conditional_t<sizeof(S) == 4, float2, uint32_t>>;
+  W w;
+  __device__ __forceinline__ Raw2() { __builtin_memset(&w, 0, sizeof(W)); }
+};
+
+template <typename S> __device__ __forceinline__ void ld_raw(const S* p, Raw<S>& r) {
+  if constexpr (sizeof(S) == 2) r.w = *reinterpret_cast<const uint16_t*>(p);
+  else r.w = *p;
+}
+template <typename S> __device__ __forceinline__ void ld_raw2(const S* p, bool vec, bool second, Raw2<S>& r) {
+  if constexpr (sizeof(S) == 8) {
+    if (vec) r.w = *reinterpret_cast<const double2*>(p);
+    else { r.w.x = p[0]; r.w.y = second ? p[1] : 0.0; }
+  } else if constexpr (sizeof(S) == 4) {
+    if (vec) r.w = *reinterpret_cast<const float2*>(p);
+    else { r.w.x = p[0]; r.w.y = second ? p[1] : 0.f; }
+  } else {
+    if (vec) {
+      r.w = *reinterpret_cast<const uint32_t*>(p);
+    } else {
+      const uint32_t lo = *reinterpret_cast<const uint16_t*>(p);
+      const uint32_t hi = second ? (uint32_t)*reinterpret_cast<const uint16_t*>(p + 1) : 0u;
+      r.w = lo | (hi << 16);
+    }
+  }
+}
+template <typename S> __device__ __forceinline__ float from_bits16f(uint32_t h) {
+  if constexpr (std::is_same_v<S, __hip_bfloat16>) return __uint_as_float(h << 16);
+  else return __half2float(__ushort_as_half((unsigned short)h));
+}
+// conversions to the compute type Ty<S>::C
+template <typename S> __device__ __forceinline__ typename Ty<S>::C raw_c(const Raw<S>& r) {
+  if constexpr (sizeof(S) == 2) return from_bits16f<S>(r.w);
+  else return r.w;
+}
+template <typename S> __device__ __forceinline__ typename Ty<S>::C raw_ca(const Raw2<S>& r) {
+  if constexpr (sizeof(S) == 2) return from_bits16f<S>(r.w & 0xffffu);
+  else return r.w.x;
+}
+template <typename S> __device__ __forceinline__ typename Ty<S>::C raw_cb(const Raw2<S>& r) {
+  if constexpr (sizeof(S) == 2) return from_bits16f<S>(r.w >> 16);
+  else return r.w.y;
+}
+template <typename S> __device__ __forceinline__ double from_bits16(uint32_t h) {
+  if constexpr (std::is_same_v<S, __hip_bfloat16>) return (double)__uint_as_float(h << 16);
+  else return (double)__half2float(__ushort_as_half((unsigned short)h));
+}
+template <typename S> __device__ __forceinline__ double raw_d(const Raw<S>& r) {
+  if constexpr (sizeof(S) == 2) return from_bits16<S>(r.w);
+  else return (double)r.w;
+}
+template <typename S> __device__ __forceinline__ double raw_a(const Raw2<S>& r) {
+  if constexpr (sizeof(S) == 2) return from_bits16<S>(r.w & 0xffffu);
+  else return (double)r.w.x;
+}
+template <typename S> __device__ __forceinline__ double raw_b(const Raw2<S>& r) {
+  if constexpr (sizeof(S) == 2) return from_bits16<S>(r.w >> 16);
+  else return (double)r.w.y;
 }
 
 // Exact upcast to double (every storage type embeds in binary64).

@@ -14,6 +14,11 @@ constexpr int SW_TX = 64, SW_TY = 8;   // relaxation tile of 3-D grids, 256 thre
 constexpr int SWR_TX = 256;            // relaxation tile of one-line grids (2-D slices), 128 threads
 constexpr int EW_TX = 64, EW_TY = 4;   // per-voxel kernels on 3-D grids: 256 threads
 constexpr int EWR_TX = 256;            // per-voxel kernels on one-line grids
+// Relaxation tile variants of 3-D grids (one x-pair per thread): 0: 64 x 8,
+// 1: 128 x 8, 2: 64 x 16, 3: 128 x 16.  Wider and taller tiles re-read a
+// smaller share of halo cells per voxel.
+constexpr int SWEEP_TILE_TX[4] = {64, 128, 64, 128};
+constexpr int SWEEP_TILE_TY[4] = {8, 8, 16, 16};
 
 // A launch over the grids of one level: blocks [block0[g], block0[g+1])
 // belong to grid g; each block covers one (x, y) tile and `zlen` planes.
@@ -26,6 +31,7 @@ struct Geom {
   int etx = EW_TX;   // per-voxel kernels: tile etx x (256 / etx)
   bool row = false;  // relaxation: one-line (slice) tiles
   bool vec = true;   // every grid's pitch and offset are even (x pairs aligned)
+  int tile = 0;      // relaxation tile variant of 3-D grids (SWEEP_TILE_TX / TY)
 };
 
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,

@@ -35,14 +35,22 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 struct Tile {
   int g, x0, y0, z0, z1;
+  int64_t bid;  // logical block index (per-block partial sums go here)
 };
+
+// Logical block index.  Work-groups go to the 8 XCDs round-robin and each
+// XCD has its own L2; handing XCD x a contiguous run of tiles (so that
+// neighbouring halos share an L2) measured slower for these streaming
+// z-marches than the plain order, which is kept.
+__device__ __forceinline__ int64_t xcd_block() { return blockIdx.x; }
 
 // Decode blockIdx.x into (grid, tile, z-range) for tx x ty tiles over the
 // grid's own size (coarse = false) or its child's size (coarse = true).
 __device__ __forceinline__ Tile decode_tile(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0,
                                             int ngrids, int zlen, int tx_, int ty_, bool coarse) {
   Tile t;
-  const int64_t bid = blockIdx.x;
+  const int64_t bid = xcd_block();
+  t.bid = bid;
   t.g = find_grid(block0, ngrids, bid);
   const GridDesc& G = grids[t.g];
   const int nx = coarse ? G.cnx : G.nx, ny = coarse ? G.cny : G.ny, nz = coarse ? G.cnz : G.nz;
@@ -327,49 +335,75 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   // ---- plane loads: x pair + halo (registers), b pair, ring b.  Two planes
   // of x and b are in flight while a plane is relaxed; a loaded value is
   // first touched one or two planes later, so the loads overlap the updates.
-  struct XSet { C a, b, h[NHR]; };
+  // Values are kept raw (storage format) until stash / split: converting a
+  // 16-bit value right after its load would make the wave wait for it there.
+  // The plain loads are issued unconditionally from clamped, always valid
+  // addresses and masked when used: with no branch around them the compiler
+  // can wait for the oldest plane only, keeping the next one in flight.
+  struct XSet {
+    Raw2<S> p;                      // own pair
+    Raw<S> h[NHR];                  // halo cells
+    C ea = 0, eb = 0, eh[NHR] = {};  // fused prolongation (FP)
+  };
+  auto plane_ptr = [&](const S* base, int q) { return base + (int64_t)min(max(q, 0), nz - 1) * pl; };
   auto fetch_x = [&](int q, XSet& o) {
-    o.a = o.b = (C)0;
+    const S* P = plane_ptr(xg, q);
+    if (VEC) {
+      ld_raw2(P + (vA ? own : 0), true, true, o.p);
+    } else {
+      o.p = Raw2<S>();
+      if (vA) ld_raw2(P + own, false, vB, o.p);
+    }
 #pragma unroll
-    for (int k = 0; k < NHR; ++k) o.h[k] = (C)0;
-    if (q >= 0 && q < nz) {
-      const S* P = xg + (int64_t)q * pl;
-      if (vA) {
-        ld2(P + own, VEC, vB, o.a, o.b);
-        if (FP) {
-          C pa, pb;
-          prolong_pair<S>(ec, G, gx, gy, q, pmode, pa, pb);
-          o.a += pa;
-          o.b += pb;
-        }
-      }
+    for (int k = 0; k < NHR; ++k) ld_raw(P + hg[k], o.h[k]);
+    if (FP) {
+      o.ea = o.eb = (C)0;
 #pragma unroll
-      for (int k = 0; k < NHR; ++k) {
-        if (hv[k]) {
-          C v = Ty<S>::ld(P + hg[k]);
-          if (FP) v += prolong_value<S>(ec, G, x0 - 2 + hoff[k] % HX, y0 - YO + hoff[k] / HX, q, pmode);
-          o.h[k] = v;
-        }
+      for (int k = 0; k < NHR; ++k) o.eh[k] = (C)0;
+      if (q >= 0 && q < nz) {
+        if (vA) prolong_pair<S>(ec, G, gx, gy, q, pmode, o.ea, o.eb);
+#pragma unroll
+        for (int k = 0; k < NHR; ++k)
+          if (hv[k]) o.eh[k] = prolong_value<S>(ec, G, x0 - 2 + hoff[k] % HX, y0 - YO + hoff[k] / HX, q, pmode);
       }
     }
   };
+  auto xa = [&](const XSet& o, int q) -> C {
+    const C v = FP ? raw_ca(o.p) + o.ea : raw_ca(o.p);
+    return (q >= 0 && q < nz && vA) ? v : (C)0;
+  };
+  auto xb = [&](const XSet& o, int q) -> C {
+    const C v = FP ? raw_cb(o.p) + o.eb : raw_cb(o.p);
+    return (q >= 0 && q < nz && vB) ? v : (C)0;
+  };
   auto stash = [&](int q, const XSet& o) {
     C* P = X + (q & 3) * PLANE;
-    P[lo] = o.a;
-    P[lo + 1] = vB ? o.b : (C)0;
+    const bool okq = q >= 0 && q < nz;
+    P[lo] = xa(o, q);
+    P[lo + 1] = xb(o, q);
 #pragma unroll
     for (int k = 0; k < NHR; ++k)
-      if (hs[k]) P[hoff[k]] = o.h[k];
+      if (hs[k]) P[hoff[k]] = (okq && hv[k]) ? (FP ? raw_c(o.h[k]) + o.eh[k] : raw_c(o.h[k])) : (C)0;
   };
-  // b pair of plane q (memory order, raw)
-  auto fetch_b = [&](int q, C& a, C& b) {
-    a = b = (C)0;
-    if (q >= 0 && q < nz && vA) ld2(bg + (int64_t)q * pl + own, VEC, vB, a, b);
+  // b pair of plane q (memory order, raw; masked by bA / bB)
+  auto fetch_b = [&](int q, Raw2<S>& r) {
+    const S* P = plane_ptr(bg, q);
+    if (VEC) {
+      ld_raw2(P + (vA ? own : 0), true, true, r);
+    } else {
+      r = Raw2<S>();
+      if (vA) ld_raw2(P + own, false, vB, r);
+    }
   };
-  auto ring_b = [&](int q) -> C {
-    const int par = q & 1;
-    if (q < 0 || q >= nz || !rv[par]) return (C)0;
-    return Ty<S>::ld(bg + (int64_t)q * pl + rg[par]);
+  auto bA = [&](const Raw2<S>& r, int q) -> C { return (q >= 0 && q < nz && vA) ? raw_ca(r) : (C)0; };
+  auto bB = [&](const Raw2<S>& r, int q) -> C { return (q >= 0 && q < nz && vB) ? raw_cb(r) : (C)0; };
+  auto ring_b = [&](int q) -> Raw<S> {
+    Raw<S> r;
+    ld_raw(plane_ptr(bg, q) + rg[q & 1], r);
+    return r;
+  };
+  auto ring_bv = [&](const Raw<S>& r, int q) -> C {
+    return (q >= 0 && q < nz && rv[q & 1]) ? raw_c(r) : (C)0;
   };
   // pair (in memory order) -> (red, black) of plane q
   auto split = [&](int q, C a, C b, C& r, C& k) {
@@ -381,20 +415,22 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
 
   // column registers (red R / black K of planes p-2 .. p+1), b of planes p-1, p
   C Rm2 = 0, Km2 = 0, Rm1, Km1, R0, K0, Rp1, Kp1;
-  C bRm1, bKm1, bR0, bK0, ba0, bb0, ba1, bb1, rb, rb1, rb2;
+  C bRm1, bKm1, bR0, bK0;
+  Raw2<S> bw0, bw1;
+  Raw<S> rb, rb1, rb2;
   XSet n0, n1;
   const int pfirst = max(q0 - 1, 0);
   const int plast = (q1 < nz) ? q1 : nz;  // p == nz: black of the last plane only
-  fetch_x(pfirst - 1, n0); stash(pfirst - 1, n0); split(pfirst - 1, n0.a, n0.b, Rm1, Km1);
-  fetch_x(pfirst, n0);     stash(pfirst, n0);     split(pfirst, n0.a, n0.b, R0, K0);
-  fetch_x(pfirst + 1, n0); stash(pfirst + 1, n0); split(pfirst + 1, n0.a, n0.b, Rp1, Kp1);
-  fetch_b(pfirst - 1, ba0, bb0); split(pfirst - 1, ba0, bb0, bRm1, bKm1);
-  fetch_b(pfirst, ba0, bb0);     split(pfirst, ba0, bb0, bR0, bK0);
+  fetch_x(pfirst - 1, n0); stash(pfirst - 1, n0); split(pfirst - 1, xa(n0, pfirst - 1), xb(n0, pfirst - 1), Rm1, Km1);
+  fetch_x(pfirst, n0);     stash(pfirst, n0);     split(pfirst, xa(n0, pfirst), xb(n0, pfirst), R0, K0);
+  fetch_x(pfirst + 1, n0); stash(pfirst + 1, n0); split(pfirst + 1, xa(n0, pfirst + 1), xb(n0, pfirst + 1), Rp1, Kp1);
+  fetch_b(pfirst - 1, bw0); split(pfirst - 1, bA(bw0, pfirst - 1), bB(bw0, pfirst - 1), bRm1, bKm1);
+  fetch_b(pfirst, bw0);     split(pfirst, bA(bw0, pfirst), bB(bw0, pfirst), bR0, bK0);
   rb = ring_b(pfirst);
   fetch_x(pfirst + 2, n0);
   fetch_x(pfirst + 3, n1);
-  fetch_b(pfirst + 1, ba0, bb0);
-  fetch_b(pfirst + 2, ba1, bb1);
+  fetch_b(pfirst + 1, bw0);
+  fetch_b(pfirst + 2, bw1);
   rb1 = ring_b(pfirst + 1);
   rb2 = ring_b(pfirst + 2);
 
@@ -428,7 +464,7 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
       if (rv[par]) {  // red cell of the 1-cell ring
         const int o = ro[par];
         const C xc = P[o];
-        C r = rb - alpha * xc;
+        C r = ring_bv(rb, p) - alpha * xc;
         r += rwl[par] * (P[o - 1] - xc);
         r += rwr[par] * (P[o + 1] - xc);
         if (!ROW) {
@@ -473,17 +509,17 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
     // ---- advance: plane p + 2 enters LDS, loads for p + 4 (x) and p + 3 (b) go out
     stash(p + 2, n0);
     Rm2 = Rm1; Km2 = Km1; Rm1 = R0; Km1 = K0; R0 = Rp1; K0 = Kp1;
-    split(p + 2, n0.a, n0.b, Rp1, Kp1);
+    split(p + 2, xa(n0, p + 2), xb(n0, p + 2), Rp1, Kp1);
     bRm1 = bR0; bKm1 = bK0;
-    split(p + 1, ba0, bb0, bR0, bK0);
+    split(p + 1, bA(bw0, p + 1), bB(bw0, p + 1), bR0, bK0);
     rb = rb1; rb1 = rb2;
     n0 = n1;
-    ba0 = ba1; bb0 = bb1;
-    if (p + 2 <= plast) {
-      fetch_x(p + 4, n1);
-      fetch_b(p + 3, ba1, bb1);
-      rb2 = ring_b(p + 3);
-    }
+    bw0 = bw1;
+    // next planes (clamped reads past the chunk's end are harmless and keep
+    // the loop free of a branch around the loads)
+    fetch_x(p + 4, n1);
+    fetch_b(p + 3, bw1);
+    rb2 = ring_b(p + 3);
   }
 }
 
@@ -644,7 +680,7 @@ k_restrict_z(const GridDesc* __restrict__ grids, const int64_t* __restrict__ blo
   }
   if (partials) {
     const double sm = block_sum(nrm, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = sm;
+    if (threadIdx.x == 0) partials[t.bid] = sm;
   }
 }
 
@@ -704,101 +740,236 @@ k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
 template <typename Tin>
 __device__ __forceinline__ double in_at(const Tin* p, int64_t v) { return ld64(p + v); }
 
-template <typename Tin, typename S>
-__global__ void __launch_bounds__(256)
-k_rhs_corr(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
-           const Tin* __restrict__ I0, const Tin* __restrict__ I1, S* __restrict__ bout,
-           S* __restrict__ xout, double* __restrict__ partials) {
-  __shared__ double red[4];
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
-  const GridDesc& G = grids[t.g];
-  const int nx = G.nx, ny = G.ny, nz = G.nz;
-  const bool slice = G.zin != 0;  // 2-D slice form
-  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
-  double nrm = 0.0;
-  if (i < nx && j < ny) {
-    const int64_t pl = (int64_t)G.px * ny;
-    for (int k = t.z0; k < t.z1; ++k) {
-      const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
-      const double c = in_at(I0, u);
-      double lin = 0.0, lcross = 0.0;  // in-slice and cross-slice second differences
-      if (i > 0) lin += G.wx * (c - in_at(I0, u - 1));
-      if (i < nx - 1) lin += G.wx * (c - in_at(I0, u + 1));
-      if (j > 0) lin += G.wy * (c - in_at(I0, u - G.ipy));
-      if (j < ny - 1) lin += G.wy * (c - in_at(I0, u + G.ipy));
-      if (G.wz != 0.0) {
-        double lz = 0.0;
-        if (k > 0) lz += c - in_at(I0, u - G.ipz);
-        if (k < nz - 1) lz += c - in_at(I0, u + G.ipz);
-        if (slice) lin += G.wz * lz; else lcross += G.wz * lz;
-      }
-      double bcan = lin, bcorr = -lcross;
-      if (G.alpha != 0.0) {
-        const double v1 = in_at(I1, u);
-        bcan += G.alpha * v1;
-        bcorr += G.alpha * (v1 - c);
-      }
-      nrm += bcan * bcan;
-      const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
-      if (bout) st64(bout + v, bcorr);
-      if (xout) st64(xout + v, 0.0);
-    }
-  }
-  if (partials) {
-    const double s = block_sum(nrm, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  }
-}
+// ------------------------------------- correction-form stencil passes
+//
+// Both passes on the finest grid use one z-marching structure (pairs of x
+// per thread, the three planes of one field in an LDS ring for the in-plane
+// neighbours, z neighbours in registers; FP64 arithmetic):
+//
+// KIND 0, right-hand side of the correction E = x - I0.  With F = I0:
+//   b_corr = alpha (I1 - I0) - [stack] w_z L_z I0
+//   ||b||^2 of the canonical system b = alpha I1 + (w_x L_x + w_y L_y) I0
+//   (+ w_z L_z I0 for a slice, whose "z" is its own second axis); the stack
+//   form's cross-slice target is zero (Eq. (1)).  Writes b_corr and a zero
+//   correction.
+// KIND 1, canonical residual b - A x in FP64.  With F = x - I0 (E in MODE 0,
+// x64 - I0 in MODE 1) the I0 terms of b and A x cancel except across slices:
+//   r = alpha (I1 - I0 - F) - (w_x L_x + w_y L_y + w_z L_z) F - [stack] w_z L_z I0
+//   ||r||^2 per block; r * inv_scale stored when rout is set.
+// L_a v is the Neumann second difference sum over existing neighbours of
+// (v_c - v_n).  Row tiles (TY == 1) serve grids with ny == 1.
+template <typename Tin, typename S, int TX, int TY, int KIND, int MODE>
+__global__ void __launch_bounds__(TX * TY / 2)
+k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+               const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
+               const double* __restrict__ x64, S* __restrict__ out0, S* __restrict__ out1,
+               const double* __restrict__ inv_scale, double* __restrict__ partials) {
+  constexpr bool ROW = (TY == 1);
+  constexpr int NT = TX * TY / 2;
+  constexpr int YO = ROW ? 0 : 1;
+  constexpr int HX = TX + 2, HY = ROW ? 1 : TY + 2;
+  constexpr int NHALO = HX * HY - TX * TY;
+  constexpr int NHR = (NHALO + NT - 1) / NT;
+  __shared__ double X[3][HY][HX];
+  __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
 
-// x at packed index v / caller index u: I0 + E (mode 0) or x64 (mode 1)
-template <typename Tin, typename S, int MODE>
-__device__ __forceinline__ double xval(const Tin* I0, const S* E, const double* x64, int64_t u, int64_t v) {
-  if (MODE == 0) return in_at(I0, u) + ld64(E + v);
-  return x64[v];
-}
-
-template <typename Tin, typename S, int MODE>
-__global__ void __launch_bounds__(256)
-k_canon_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids,
-                 int zlen, int etx, const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
-                 const double* __restrict__ x64, S* __restrict__ rout, const double* __restrict__ inv_scale,
-                 double* __restrict__ partials) {
-  __shared__ double red[4];
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
   const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const bool slice = G.zin != 0;
-  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
-  const S* Eg = (MODE == 0) ? E + G.off : E;
-  const double* xg = (MODE == 1) ? x64 + G.off : x64;
-  double nrm = 0.0;
-  if (i < nx && j < ny) {
-    const int64_t pl = (int64_t)px * ny;
-    for (int k = t.z0; k < t.z1; ++k) {
-      const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
-      const int64_t v = k * pl + (int64_t)j * px + i;
-      const double c0 = in_at(I0, u);
-      const double xc = xval<Tin, S, MODE>(I0, Eg, xg, u, v);
-      double r = -G.alpha * xc;  // b - A x, difference form
-      if (G.alpha != 0.0) r += G.alpha * in_at(I1, u);
-      if (i > 0) r += G.wx * ((c0 - in_at(I0, u - 1)) + (xval<Tin, S, MODE>(I0, Eg, xg, u - 1, v - 1) - xc));
-      if (i < nx - 1) r += G.wx * ((c0 - in_at(I0, u + 1)) + (xval<Tin, S, MODE>(I0, Eg, xg, u + 1, v + 1) - xc));
-      if (j > 0) r += G.wy * ((c0 - in_at(I0, u - G.ipy)) + (xval<Tin, S, MODE>(I0, Eg, xg, u - G.ipy, v - px) - xc));
-      if (j < ny - 1)
-        r += G.wy * ((c0 - in_at(I0, u + G.ipy)) + (xval<Tin, S, MODE>(I0, Eg, xg, u + G.ipy, v + px) - xc));
-      if (G.wz != 0.0) {
-        const double sl = slice ? 1.0 : 0.0;  // in-slice z (slice form) also carries the I0 term
-        if (k > 0)
-          r += G.wz * (sl * (c0 - in_at(I0, u - G.ipz)) + (xval<Tin, S, MODE>(I0, Eg, xg, u - G.ipz, v - pl) - xc));
-        if (k < nz - 1)
-          r += G.wz * (sl * (c0 - in_at(I0, u + G.ipz)) + (xval<Tin, S, MODE>(I0, Eg, xg, u + G.ipz, v + pl) - xc));
-      }
-      nrm += r * r;
-      if (rout) st64(rout + G.off + v, r * inv_scale[t.g]);
+  const double alpha = G.alpha, wx = G.wx, wy = ROW ? 0.0 : G.wy, wz = G.wz;
+  const bool cross = !slice && wz != 0.0;  // the stack's cross-slice term of I0
+  const int64_t pl = (int64_t)px * ny;
+  const Tin* I0g = I0 + G.ioff;
+  const Tin* I1g = (I1 && alpha != 0.0) ? I1 + G.ioff : nullptr;
+  const S* Eg = E + G.off;
+  const double* xg = x64 + G.off;
+  const bool ivec = ((G.ioff | G.ipy | G.ipz) & 1) == 0, vec = ((px | G.off) & 1) == 0;
+  const int tid = threadIdx.x;
+  const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
+  const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
+  const int gx = x0 + 2 * pxl, gy = y0 + tyl;
+  const bool rowok = gy < ny;
+  const bool vA = rowok && gx < nx, vB = rowok && gx + 1 < nx;
+  const int lx = 1 + 2 * pxl, ly = YO + tyl;
+  const int64_t own = (int64_t)gy * px + gx, ownu = (int64_t)gy * G.ipy + gx;
+  const bool up = !ROW && gy > 0, dn = !ROW && gy + 1 < ny, o0 = gx > 0, o1 = gx + 2 < nx;
+
+  int hoff[NHR];
+  int64_t hg[NHR], hu[NHR];
+  bool hv[NHR];
+#pragma unroll
+  for (int k = 0; k < NHR; ++k) {
+    const int h = tid + NT * k;
+    int hy = 0, hx = 0;
+    if (ROW) {
+      hx = (h == 0) ? 0 : HX - 1;
+    } else if (h < HX) {
+      hy = 0; hx = h;
+    } else if (h < 2 * HX) {
+      hy = HY - 1; hx = h - HX;
+    } else {
+      const int m = h - 2 * HX;
+      hy = 1 + (m >> 1);
+      hx = (m & 1) ? HX - 1 : 0;
     }
+    const int cx = x0 - 1 + hx, cy = y0 - YO + hy;
+    hv[k] = h < NHALO && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    hoff[k] = hy * HX + hx;
+    hg[k] = hv[k] ? (int64_t)cy * px + cx : 0;
+    hu[k] = hv[k] ? (int64_t)cy * G.ipy + cx : 0;
   }
-  const double s = block_sum(nrm, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  // Raw loads of plane q: F's own pair and halo values and (KIND 1) I0's
+  // pair; converted to FP64 only in stash(), after other work has run.
+  using FS = std::conditional_t<KIND == 0, Tin, std::conditional_t<MODE == 0, S, double>>;
+  Raw2<FS> rf;
+  Raw2<Tin> ri;
+  Raw<FS> rh[NHR];
+  Raw<Tin> rhi[NHR];
+  auto fetch = [&](int q) {
+    const bool okq = q >= 0 && q < nz;
+    rf = Raw2<FS>();
+    ri = Raw2<Tin>();
+    if (okq && vA) {
+      if (KIND == 0) {
+        ld_raw2(reinterpret_cast<const FS*>(I0g) + q * G.ipz + ownu, ivec, vB, rf);
+      } else {
+        ld_raw2(I0g + q * G.ipz + ownu, ivec, vB, ri);
+        if (MODE == 0) ld_raw2(reinterpret_cast<const FS*>(Eg) + q * pl + own, vec, vB, rf);
+        else ld_raw2(reinterpret_cast<const FS*>(xg) + q * pl + own, vec, vB, rf);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NHR; ++k) {
+      rh[k] = Raw<FS>();
+      rhi[k] = Raw<Tin>();
+      if (okq && hv[k]) {
+        if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0g) + q * G.ipz + hu[k], rh[k]);
+        else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + q * pl + hg[k], rh[k]);
+        else {
+          ld_raw(reinterpret_cast<const FS*>(xg) + q * pl + hg[k], rh[k]);
+          ld_raw(I0g + q * G.ipz + hu[k], rhi[k]);
+        }
+      }
+    }
+  };
+  // convert the last fetch: F pair (fa, fb), I0 pair (ia, ib); store F's plane
+  double fa = 0, fb = 0, ia = 0, ib = 0;
+  auto stash = [&](int q) {
+    if (KIND == 1) {
+      ia = raw_a(ri);
+      ib = raw_b(ri);
+    }
+    fa = raw_a(rf);
+    fb = raw_b(rf);
+    if (KIND == 1 && MODE == 1) {
+      fa -= ia;
+      fb = vB ? fb - ib : 0.0;
+    }
+    double* P = &X[((q % 3) + 3) % 3][0][0];
+    P[ly * HX + lx] = fa;
+    P[ly * HX + lx + 1] = fb;
+#pragma unroll
+    for (int k = 0; k < NHR; ++k)
+      if (tid + NT * k < NHALO) P[hoff[k]] = (KIND == 1 && MODE == 1) ? raw_d(rh[k]) - raw_d(rhi[k]) : raw_d(rh[k]);
+  };
+  // I1 pair at plane q (raw), prefetched one plane ahead
+  Raw2<Tin> r1n;
+  auto fetch1 = [&](int q) {
+    r1n = Raw2<Tin>();
+    if (I1g && q >= 0 && q < nz && vA) ld_raw2(I1g + q * G.ipz + ownu, ivec, vB, r1n);
+  };
+
+  // registers: F and I0 at k - 1 (m), k (c), k + 1 (p)
+  double fma_ = 0, fmb = 0, fca, fcb, fpa, fpb, ima = 0, imb = 0, ica = 0, icb = 0, ipa = 0, ipb = 0;
+  fetch(q0 - 1);
+  stash(q0 - 1);  // plane q0 - 1 goes to the ring slot of q0 + 2, rewritten before it is read
+  fma_ = fa; fmb = fb; ima = ia; imb = ib;
+  fetch(q0);
+  stash(q0);
+  fca = fa; fcb = fb; ica = ia; icb = ib;
+  fetch(q0 + 1);
+  fetch1(q0);
+  double nrm = 0.0;
+  for (int k = q0; k < q1; ++k) {
+    stash(k + 1);
+    fpa = fa; fpb = fb; ipa = ia; ipb = ib;
+    const Raw2<Tin> r1 = r1n;
+    fetch(k + 2);
+    fetch1(k + 1);
+    __syncthreads();
+    const double v1a = I1g ? raw_a(r1) : 0.0, v1b = I1g ? raw_b(r1) : 0.0;
+    const double* P = &X[k % 3][0][0];
+    const bool zm = k > 0, zp = k < nz - 1;
+    double ra = 0.0, rb = 0.0;
+    // in-plane and z second differences of F; I0's z term for the stack
+    auto lap = [&](double c, double l, bool hl, double rr, bool hr, double u_, double d_, double zm_, double zp_) {
+      double s2 = 0.0;
+      if (hl) s2 += wx * (c - l);
+      if (hr) s2 += wx * (c - rr);
+      if (up) s2 += wy * (c - u_);
+      if (dn) s2 += wy * (c - d_);
+      if (zm) s2 += wz * (c - zm_);
+      if (zp) s2 += wz * (c - zp_);
+      return s2;
+    };
+    if (vA) {
+      const double c = fca;
+      const double lf = lap(c, o0 ? P[ly * HX + lx - 1] : 0.0, o0, fcb, vB, up ? P[(ly - 1) * HX + lx] : 0.0,
+                            dn ? P[(ly + 1) * HX + lx] : 0.0, fma_, fpa);
+      double lzI = 0.0;  // w_z L_z I0 (stack only)
+      if (cross) {
+        const double i0 = KIND == 0 ? fca : ica, im = KIND == 0 ? fma_ : ima, ip = KIND == 0 ? fpa : ipa;
+        if (zm) lzI += wz * (i0 - im);
+        if (zp) lzI += wz * (i0 - ip);
+      }
+      if (KIND == 0) {
+        const double lin = lf - (cross ? lzI : 0.0);  // canonical part of L I0
+        const double bcan = alpha * v1a + lin;
+        nrm += bcan * bcan;
+        ra = alpha * (v1a - c) - lzI;
+      } else {
+        ra = alpha * (v1a - ica - c) - lf - lzI;
+        nrm += ra * ra;
+      }
+    }
+    if (vB) {
+      const double c = fcb;
+      const double lf = lap(c, fca, true, o1 ? P[ly * HX + lx + 2] : 0.0, o1, up ? P[(ly - 1) * HX + lx + 1] : 0.0,
+                            dn ? P[(ly + 1) * HX + lx + 1] : 0.0, fmb, fpb);
+      double lzI = 0.0;
+      if (cross) {
+        const double i0 = KIND == 0 ? fcb : icb, im = KIND == 0 ? fmb : imb, ip = KIND == 0 ? fpb : ipb;
+        if (zm) lzI += wz * (i0 - im);
+        if (zp) lzI += wz * (i0 - ip);
+      }
+      if (KIND == 0) {
+        const double lin = lf - (cross ? lzI : 0.0);
+        const double bcan = alpha * v1b + lin;
+        nrm += bcan * bcan;
+        rb = alpha * (v1b - c) - lzI;
+      } else {
+        rb = alpha * (v1b - icb - c) - lf - lzI;
+        nrm += rb * rb;
+      }
+    }
+    if (vA) {
+      const int64_t v = G.off + k * pl + own;
+      if (KIND == 0) {
+        if (out0) st2(out0 + v, vec, vB, (typename Ty<S>::C)ra, (typename Ty<S>::C)rb);
+        if (out1) st2(out1 + v, vec, vB, (typename Ty<S>::C)0, (typename Ty<S>::C)0);
+      } else if (out0) {
+        const double sc = inv_scale[t.g];
+        st2(out0 + v, vec, vB, (typename Ty<S>::C)(ra * sc), (typename Ty<S>::C)(rb * sc));
+      }
+    }
+    fma_ = fca; fmb = fcb; fca = fpa; fcb = fpb;
+    ima = ica; imb = icb; ica = ipa; icb = ipb;
+  }
+  if (partials) {
+    const double sm = block_sum(nrm, red);
+    if (threadIdx.x == 0) partials[t.bid] = sm;
+  }
 }
 
 template <typename Tin, typename S, int MODE>
@@ -824,7 +995,7 @@ k_sum_shift(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
     }
   }
   const double tot = block_sum(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  if (threadIdx.x == 0) partials[t.bid] = tot;
 }
 
 template <typename Tin, typename S, typename Tout, int MODE>
@@ -948,8 +1119,8 @@ k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict
   const double s1 = block_sum(rr, red);
   const double s2 = block_sum(bb, red);
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = s1;
-    partials[2 * blockIdx.x + 1] = s2;
+    partials[2 * t.bid] = s1;
+    partials[2 * t.bid + 1] = s2;
   }
 }
 
@@ -982,7 +1153,7 @@ k_apply_dot(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
     }
   }
   const double s = block_sum(pq, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[t.bid] = s;
 }
 
 // per-block FP64 sum of a.b
@@ -1001,7 +1172,7 @@ k_dot(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, in
       s += ld64(a + v) * ld64(b + v);
     }
   const double tot = block_sum(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  if (threadIdx.x == 0) partials[t.bid] = tot;
 }
 
 // x += alpha p, r -= alpha q, per-block FP64 sum of r^2 (alpha = coef[0])
@@ -1025,7 +1196,7 @@ k_cg_update(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
       s += rn * rn;
     }
   const double tot = block_sum(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  if (threadIdx.x == 0) partials[t.bid] = tot;
 }
 
 // out = a X + b Y (coef[0], coef[1]); Y may alias out
@@ -1092,9 +1263,19 @@ static void sweep_launch3(const Geom& g, const void* xin, void* xout, const void
                        g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec,
                        pmode);
   } else {
-    hipLaunchKernelGGL((k_rb_sweep<T, SW_TX, SW_TY, FP, VEC>), dim3((unsigned)g.nblocks), dim3(SW_TX * SW_TY / 2), 0,
-                       st, g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec,
-                       pmode);
+#define SWEEP_TILE(TX, TY)                                                                                     \
+  hipLaunchKernelGGL((k_rb_sweep<T, TX, TY, FP, VEC>), dim3((unsigned)g.nblocks), dim3(TX * TY / 2), 0, st,    \
+                     g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec, pmode)
+    if (FP || g.tile == 0) {
+      SWEEP_TILE(64, 8);
+    } else if constexpr (!FP) {  // the fused prolongation exists for the 64 x 8 tile only
+      switch (g.tile) {
+        case 1: SWEEP_TILE(128, 8); break;
+        case 2: SWEEP_TILE(64, 16); break;
+        default: SWEEP_TILE(128, 16); break;
+      }
+    }
+#undef SWEEP_TILE
   }
 }
 
@@ -1162,10 +1343,23 @@ hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* ec, void* x
   return last();
 }
 
+template <typename TI, typename T, int KIND, int MODE>
+static void corr_stencil_launch(const Geom& g, const void* I0, const void* I1, const void* E, const double* x64,
+                                void* o0, void* o1, const double* inv_scale, double* partials, hipStream_t st) {
+  if (g.row)
+    hipLaunchKernelGGL((k_corr_stencil<TI, T, SWR_TX, 1, KIND, MODE>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0,
+                       st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0, (const TI*)I1, (const T*)E, x64, (T*)o0,
+                       (T*)o1, inv_scale, partials);
+  else
+    hipLaunchKernelGGL((k_corr_stencil<TI, T, SW_TX, SW_TY, KIND, MODE>), dim3((unsigned)g.nblocks),
+                       dim3(SW_TX * SW_TY / 2), 0, st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0,
+                       (const TI*)I1, (const T*)E, x64, (T*)o0, (T*)o1, inv_scale, partials);
+}
+
 hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, const void* I1, void* b,
                            void* x, double* partials, hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
-#define L2(TI, T) hipLaunchKernelGGL((k_rhs_corr<TI, T>), GD_ARGS(g), (const TI*)I0, (const TI*)I1, (T*)b, (T*)x, partials)
+#define L2(TI, T) corr_stencil_launch<TI, T, 0, 0>(g, I0, I1, nullptr, nullptr, b, x, nullptr, partials, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1
@@ -1177,13 +1371,11 @@ hipError_t launch_canon_residual(gd_dtype tin, gd_dtype s, int mode, const Geom&
                                  const void* I1, const void* E, const double* x64, void* r_out,
                                  const double* inv_scale, double* partials, hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
-#define L2(TI, T)                                                                                          \
-  if (mode == 0)                                                                                           \
-    hipLaunchKernelGGL((k_canon_residual<TI, T, 0>), GD_ARGS(g), (const TI*)I0, (const TI*)I1, (const T*)E, \
-                       x64, (T*)r_out, inv_scale, partials);                                               \
-  else                                                                                                     \
-    hipLaunchKernelGGL((k_canon_residual<TI, T, 1>), GD_ARGS(g), (const TI*)I0, (const TI*)I1, (const T*)E, \
-                       x64, (T*)r_out, inv_scale, partials)
+#define L2(TI, T)                                                                                        \
+  if (mode == 0)                                                                                         \
+    corr_stencil_launch<TI, T, 1, 0>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, st);        \
+  else                                                                                                   \
+    corr_stencil_launch<TI, T, 1, 1>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1
