@@ -52,6 +52,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-crop", default="32,128,128", help="nz,ny,nx of the oracle's crop")
     p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
+    p.add_argument("--inner-cycles", type=int, default=None,
+                   help="V-cycles per FP64 refinement step (mixed storage; library default if omitted)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only copy a 1 GiB buffer 3 times (reference for HBM byte counters)")
     p.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -271,6 +273,8 @@ def main():
     out_dtype = torch.float32 if storage == "f32" else tdt
     pre, post = (int(v) for v in a.smooth.split(","))
     opts = dict(storage=sdt, fp64_refine=refine, rel_tol=TOL, pre_smooth=pre, post_smooth=post)
+    if a.inner_cycles is not None:
+        opts["inner_cycles"] = a.inner_cycles
 
     def step(timing):
         I1, r1 = gd.smooth_z(I0, BETA, out_dtype=out_dtype, timing=timing, **opts)

@@ -122,6 +122,7 @@ struct Hier {
   double* dscal = nullptr;   // ngrids * 4: scale, inv_scale, shift, spare
   double* hpin = nullptr;    // pinned host, ngrids * 4
   double* x64 = nullptr;     // FP64 iterate of the refinement path
+  double* x64b = nullptr;    // its next value (the fused update writes here)
   std::vector<int64_t> cells;  // finest cells per grid
 
   ~Hier() {
@@ -314,7 +315,10 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
   H->dred = (double*)H->alloc(H->ngrids * 2 * sizeof(double));
   H->dscal = (double*)H->alloc(H->ngrids * 4 * sizeof(double));
   HIP_TRY(hipHostMalloc((void**)&H->hpin, H->ngrids * 4 * sizeof(double), hipHostMallocDefault));
-  if (mixed) H->x64 = (double*)H->alloc(H->lv[0].total * sizeof(double));
+  if (mixed) {
+    H->x64 = (double*)H->alloc(H->lv[0].total * sizeof(double));
+    H->x64b = (double*)H->alloc(H->lv[0].total * sizeof(double));
+  }
   (void)st;
   return H;
 }
@@ -592,35 +596,60 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
 // Mixed path: FP64 iterate x64; each refinement step solves A e = r / s for
 // the scaled FP64 residual (s = RMS of r per grid) with V-cycles in the
 // storage type, then x64 += s e.
+// Mixed path: FP64 iterate x64 (starting at I0), V-cycles in the storage
+// type on the residual scaled to unit RMS.  One fused pass per refinement
+// step applies the update x64 + s e (into the second FP64 buffer), computes
+// the FP64 canonical residual of the result and writes it, scaled by the
+// RMS of the residual before it (so that it is of order one), as the next
+// right-hand side.
 static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
   Outcome R;
   canonical_norms(H, P, nullptr, nullptr, R.bnorm, st);
   HIP_TRY(launch_refine_init(P.tin, H.g_ew(0), P.I0, H.x64, st));
   Cycler cy(H, st, o);
   const size_t es = dsize(H.s);
+  const int n = H.ngrids;
+  std::vector<double> r = canon_residual(H, P, 1, nullptr, st);
+  std::vector<double> scale(n, 1.0);  // scale of the right-hand side in L0.b
+  auto rms = [&](int g, const std::vector<double>& v) {
+    const double q = v[g] / std::sqrt((double)H.cells[g]);
+    return q > 0.0 ? q : 1.0;
+  };
+  bool first = true;
   for (;;) {
-    std::vector<double> r = canon_residual(H, P, 1, nullptr, st);
     bool bad = false;
     R.converged = all_below(r, R.bnorm, o.rel_tol, bad);
-    R.rel.resize(H.ngrids);
-    for (int g = 0; g < H.ngrids; ++g) R.rel[g] = r[g] / denom(R.bnorm[g]);
+    R.rel.resize(n);
+    for (int g = 0; g < n; ++g) R.rel[g] = r[g] / denom(R.bnorm[g]);
     if (bad) { R.numeric = true; break; }
     if (R.converged || R.steps >= o.max_cycles) break;
-    for (int g = 0; g < H.ngrids; ++g) {
-      double s = r[g] / std::sqrt((double)H.cells[g]);
-      if (!(s > 0.0)) s = 1.0;
-      H.hpin[g] = s;
-      H.hpin[H.ngrids + g] = 1.0 / s;
+    if (first) {  // scaled copy of the initial residual
+      for (int g = 0; g < n; ++g) {
+        scale[g] = rms(g, r);
+        H.hpin[n + g] = 1.0 / scale[g];
+      }
+      HIP_TRY(hipMemcpyAsync(H.dscal + n, H.hpin + n, n * sizeof(double), hipMemcpyHostToDevice, st));
+      (void)canon_residual(H, P, 1, H.lv[0].b, st);
+      first = false;
     }
-    HIP_TRY(hipMemcpyAsync(H.dscal, H.hpin, 2 * H.ngrids * sizeof(double), hipMemcpyHostToDevice, st));
-    // scaled residual -> finest b; e = 0
-    (void)canon_residual(H, P, 1, H.lv[0].b, st);
     HIP_TRY(hipMemsetAsync(H.lv[0].x, 0, H.lv[0].total * es, st));
     for (int c = 0; c < o.inner_cycles; ++c) {
       cy.full(0);
       R.cycles++;
     }
-    HIP_TRY(launch_refine_update(H.s, H.g_ew(0), H.x64, H.lv[0].x, H.dscal, st));
+    // x64' = x64 + scale e; r = b - A x64'; L0.b = r / rms(previous r)
+    for (int g = 0; g < n; ++g) {
+      H.hpin[g] = scale[g];
+      scale[g] = rms(g, r);
+      H.hpin[n + g] = 1.0 / scale[g];
+    }
+    HIP_TRY(hipMemcpyAsync(H.dscal, H.hpin, 2 * n * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_canon_residual(P.tin, H.s, 2, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, H.lv[0].b, H.dscal + n,
+                                  H.partials, st, H.x64b, H.dscal));
+    HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, n, 1, H.dred, st));
+    read_dred(H, 1, st);
+    for (int g = 0; g < n; ++g) r[g] = std::sqrt(H.hpin[g]);
+    std::swap(H.x64, H.x64b);
     R.steps++;
   }
   HIP_TRY(hipStreamSynchronize(st));

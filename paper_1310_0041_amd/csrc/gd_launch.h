@@ -50,11 +50,14 @@ hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* e_coarse, v
 hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, const void* I1,
                            void* b, void* x, double* partials, hipStream_t st);
 // FP64 canonical residual r = b - A x of the AD/SP system for x = I0 + E
-// (mode 0, E packed in `s`) or x = x64 (mode 1).  Per block: sum r^2.  When
-// r_out != NULL also writes r * inv_scale[g] packed in `s`.
+// (mode 0, E packed in `s`), x = x64 (mode 1) or x = x64 + e_scale[g] E
+// (mode 2, the refinement update, also written to x64_out, which must not
+// alias x64).  Per block: sum r^2.  When r_out != NULL also writes
+// r * inv_scale[g] packed in `s`.
 hipError_t launch_canon_residual(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
                                  const void* I1, const void* E, const double* x64, void* r_out,
-                                 const double* inv_scale, double* partials, hipStream_t st);
+                                 const double* inv_scale, double* partials, hipStream_t st,
+                                 double* x64_out = nullptr, const double* e_scale = nullptr);
 // Per block: sum (x - I0) for x = I0 + E (mode 0) or x64 (mode 1).
 hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
                             const void* E, const double* x64, double* partials, hipStream_t st);
@@ -63,8 +66,6 @@ hipError_t launch_finalize(gd_dtype tin, gd_dtype s, gd_dtype tout, int mode, co
                            const void* I0, const void* E, const double* x64, const double* shift,
                            void* out, hipStream_t st);
 hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, double* x64, hipStream_t st);
-hipError_t launch_refine_update(gd_dtype s, const Geom& g, double* x64, const void* e,
-                                const double* scale, hipStream_t st);
 // Generic system: b = alpha V + sum_a w_a D_a^T G_a.
 hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const void* Gx,
                               const void* Gy, const void* Gz, void* b, hipStream_t st);

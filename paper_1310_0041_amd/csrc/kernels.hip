@@ -753,7 +753,9 @@ __device__ __forceinline__ double in_at(const Tin* p, int64_t v) { return ld64(p
 //   form's cross-slice target is zero (Eq. (1)).  Writes b_corr and a zero
 //   correction.
 // KIND 1, canonical residual b - A x in FP64.  With F = x - I0 (E in MODE 0,
-// x64 - I0 in MODE 1) the I0 terms of b and A x cancel except across slices:
+// x64 - I0 in MODE 1, x64 + s e - I0 in MODE 2, where the refinement's
+// update x64 + s e is also written to x64_out, s = e_scale[grid]) the I0
+// terms of b and A x cancel except across slices:
 //   r = alpha (I1 - I0 - F) - (w_x L_x + w_y L_y + w_z L_z) F - [stack] w_z L_z I0
 //   ||r||^2 per block; r * inv_scale stored when rout is set.
 // L_a v is the Neumann second difference sum over existing neighbours of
@@ -763,13 +765,15 @@ __global__ void __launch_bounds__(TX * TY / 2)
 k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
                const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
                const double* __restrict__ x64, S* __restrict__ out0, S* __restrict__ out1,
-               const double* __restrict__ inv_scale, double* __restrict__ partials) {
+               const double* __restrict__ inv_scale, double* __restrict__ partials,
+               double* __restrict__ x64_out, const double* __restrict__ e_scale) {
   constexpr bool ROW = (TY == 1);
   constexpr int NT = TX * TY / 2;
   constexpr int YO = ROW ? 0 : 1;
   constexpr int HX = TX + 2, HY = ROW ? 1 : TY + 2;
   constexpr int NHALO = HX * HY - TX * TY;
   constexpr int NHR = (NHALO + NT - 1) / NT;
+  static_assert(MODE < 2 || KIND == 1, "the refinement update belongs to the residual pass");
   __shared__ double X[3][HY][HX];
   __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
 
@@ -824,31 +828,41 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   using FS = std::conditional_t<KIND == 0, Tin, std::conditional_t<MODE == 0, S, double>>;
   Raw2<FS> rf;
   Raw2<Tin> ri;
+  Raw2<S> re;  // MODE 2: the correction e
   Raw<FS> rh[NHR];
   Raw<Tin> rhi[NHR];
+  Raw<S> rhe[NHR];
+  const double es = (MODE == 2) ? e_scale[t.g] : 0.0;
   auto fetch = [&](int q) {
     const bool okq = q >= 0 && q < nz;
     rf = Raw2<FS>();
     ri = Raw2<Tin>();
+    re = Raw2<S>();
     if (okq && vA) {
       if (KIND == 0) {
         ld_raw2(reinterpret_cast<const FS*>(I0g) + q * G.ipz + ownu, ivec, vB, rf);
       } else {
         ld_raw2(I0g + q * G.ipz + ownu, ivec, vB, ri);
-        if (MODE == 0) ld_raw2(reinterpret_cast<const FS*>(Eg) + q * pl + own, vec, vB, rf);
-        else ld_raw2(reinterpret_cast<const FS*>(xg) + q * pl + own, vec, vB, rf);
+        if (MODE == 0) {
+          ld_raw2(reinterpret_cast<const FS*>(Eg) + q * pl + own, vec, vB, rf);
+        } else {
+          ld_raw2(reinterpret_cast<const FS*>(xg) + q * pl + own, vec, vB, rf);
+          if (MODE == 2) ld_raw2(Eg + q * pl + own, vec, vB, re);
+        }
       }
     }
 #pragma unroll
     for (int k = 0; k < NHR; ++k) {
       rh[k] = Raw<FS>();
       rhi[k] = Raw<Tin>();
+      rhe[k] = Raw<S>();
       if (okq && hv[k]) {
         if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0g) + q * G.ipz + hu[k], rh[k]);
         else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + q * pl + hg[k], rh[k]);
         else {
           ld_raw(reinterpret_cast<const FS*>(xg) + q * pl + hg[k], rh[k]);
           ld_raw(I0g + q * G.ipz + hu[k], rhi[k]);
+          if (MODE == 2) ld_raw(Eg + q * pl + hg[k], rhe[k]);
         }
       }
     }
@@ -862,7 +876,12 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     }
     fa = raw_a(rf);
     fb = raw_b(rf);
-    if (KIND == 1 && MODE == 1) {
+    if (KIND == 1 && MODE == 2) {  // refinement update x64 + s e, written by the cell's owner
+      fa += es * raw_a(re);
+      fb += es * raw_b(re);
+      if (vA && q >= q0 && q < q1) st2(x64_out + G.off + q * pl + own, vec, vB, fa, fb);
+    }
+    if (KIND == 1 && MODE >= 1) {
       fa -= ia;
       fb = vB ? fb - ib : 0.0;
     }
@@ -871,7 +890,12 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     P[ly * HX + lx + 1] = fb;
 #pragma unroll
     for (int k = 0; k < NHR; ++k)
-      if (tid + NT * k < NHALO) P[hoff[k]] = (KIND == 1 && MODE == 1) ? raw_d(rh[k]) - raw_d(rhi[k]) : raw_d(rh[k]);
+      if (tid + NT * k < NHALO) {
+        double v = raw_d(rh[k]);
+        if (KIND == 1 && MODE == 2) v += es * raw_d(rhe[k]);
+        if (KIND == 1 && MODE >= 1) v -= raw_d(rhi[k]);
+        P[hoff[k]] = v;
+      }
   };
   // I1 pair at plane q (raw), prefetched one plane ahead
   Raw2<Tin> r1n;
@@ -1032,21 +1056,6 @@ k_refine_init(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
   }
 }
 
-template <typename S>
-__global__ void __launch_bounds__(256)
-k_refine_update(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
-                int etx, double* __restrict__ x64, const S* __restrict__ e, const double* __restrict__ scale) {
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
-  const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
-  if (i >= G.nx || j >= G.ny) return;
-  const int64_t pl = (int64_t)G.px * G.ny;
-  const double s = scale[t.g];
-  for (int k = t.z0; k < t.z1; ++k) {
-    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
-    x64[v] += s * ld64(e + v);
-  }
-}
 
 // -------------------------------------------------- general system (Sec. 4)
 // (caller's arrays, pitch px = nx)
@@ -1345,21 +1354,23 @@ hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* ec, void* x
 
 template <typename TI, typename T, int KIND, int MODE>
 static void corr_stencil_launch(const Geom& g, const void* I0, const void* I1, const void* E, const double* x64,
-                                void* o0, void* o1, const double* inv_scale, double* partials, hipStream_t st) {
+                                void* o0, void* o1, const double* inv_scale, double* partials, double* x64o,
+                                const double* escale, hipStream_t st) {
   if (g.row)
     hipLaunchKernelGGL((k_corr_stencil<TI, T, SWR_TX, 1, KIND, MODE>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0,
                        st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0, (const TI*)I1, (const T*)E, x64, (T*)o0,
-                       (T*)o1, inv_scale, partials);
+                       (T*)o1, inv_scale, partials, x64o, escale);
   else
     hipLaunchKernelGGL((k_corr_stencil<TI, T, SW_TX, SW_TY, KIND, MODE>), dim3((unsigned)g.nblocks),
                        dim3(SW_TX * SW_TY / 2), 0, st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0,
-                       (const TI*)I1, (const T*)E, x64, (T*)o0, (T*)o1, inv_scale, partials);
+                       (const TI*)I1, (const T*)E, x64, (T*)o0, (T*)o1, inv_scale, partials, x64o, escale);
 }
 
 hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, const void* I1, void* b,
                            void* x, double* partials, hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
-#define L2(TI, T) corr_stencil_launch<TI, T, 0, 0>(g, I0, I1, nullptr, nullptr, b, x, nullptr, partials, st)
+#define L2(TI, T) \
+  corr_stencil_launch<TI, T, 0, 0>(g, I0, I1, nullptr, nullptr, b, x, nullptr, partials, nullptr, nullptr, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1
@@ -1369,13 +1380,16 @@ hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* 
 
 hipError_t launch_canon_residual(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
                                  const void* I1, const void* E, const double* x64, void* r_out,
-                                 const double* inv_scale, double* partials, hipStream_t st) {
+                                 const double* inv_scale, double* partials, hipStream_t st, double* x64_out,
+                                 const double* e_scale) {
   if (g.nblocks == 0) return hipSuccess;
-#define L2(TI, T)                                                                                        \
-  if (mode == 0)                                                                                         \
-    corr_stencil_launch<TI, T, 1, 0>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, st);        \
-  else                                                                                                   \
-    corr_stencil_launch<TI, T, 1, 1>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, st)
+#define L2(TI, T)                                                                                              \
+  if (mode == 0)                                                                                               \
+    corr_stencil_launch<TI, T, 1, 0>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, nullptr, st); \
+  else if (mode == 1)                                                                                          \
+    corr_stencil_launch<TI, T, 1, 1>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, nullptr, st); \
+  else                                                                                                         \
+    corr_stencil_launch<TI, T, 1, 2>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, x64_out, e_scale, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1
@@ -1432,14 +1446,6 @@ hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, doubl
   return last();
 }
 
-hipError_t launch_refine_update(gd_dtype s, const Geom& g, double* x64, const void* e, const double* scale,
-                                hipStream_t st) {
-  if (g.nblocks == 0) return hipSuccess;
-#define L(T) hipLaunchKernelGGL(k_refine_update<T>, GD_ARGS(g), x64, (const T*)e, scale)
-  GD_DISPATCH_S(s, L)
-#undef L
-  return last();
-}
 
 hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const void* Gx, const void* Gy,
                               const void* Gz, void* b, hipStream_t st) {
