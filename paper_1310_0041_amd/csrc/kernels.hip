@@ -593,33 +593,43 @@ k_restrict_z(const GridDesc* __restrict__ grids, const int64_t* __restrict__ blo
     hoff[k] = hy * HX + hx;
     hg[k] = hv[k] ? (int64_t)cy * px + cx : 0;
   }
-  C na = 0, nb = 0, nh[NHR];
+  // x of plane q: raw loads from clamped addresses (no branch around them),
+  // converted and masked in stash(); b pairs likewise, one plane ahead
+  Raw2<S> rx;
+  Raw<S> rh[NHR];
+  C na = 0, nb = 0;
+  auto plane_off = [&](int q) { return (int64_t)min(max(q, 0), nz - 1) * pl; };
   auto fetch = [&](int q) {
-    na = nb = (C)0;
-    const bool okq = q >= 0 && q < nz;
-    if (okq && vA) ld2(xg + q * pl + own, vec, vB, na, nb);
+    const S* P = xg + plane_off(q);
+    ld_raw2(P + (vA ? own : 0), vec, true, rx);
 #pragma unroll
-    for (int k = 0; k < NHR; ++k) nh[k] = (okq && hv[k]) ? Ty<S>::ld(xg + q * pl + hg[k]) : (C)0;
+    for (int k = 0; k < NHR; ++k) ld_raw(P + hg[k], rh[k]);
   };
-  auto stash = [&](int q) {
+  auto stash = [&](int q) {  // converts the last fetch into na, nb and LDS
+    const bool okq = q >= 0 && q < nz;
+    na = (okq && vA) ? raw_ca(rx) : (C)0;
+    nb = (okq && vB) ? raw_cb(rx) : (C)0;
     C* P = &X[((q % 3) + 3) % 3][0][0];
     P[ly * HX + lx] = na;
     P[ly * HX + lx + 1] = nb;
 #pragma unroll
     for (int k = 0; k < NHR; ++k)
-      if (tid + NT * k < NHALO) P[hoff[k]] = nh[k];
+      if (tid + NT * k < NHALO) P[hoff[k]] = (okq && hv[k]) ? raw_c(rh[k]) : (C)0;
   };
-  auto fetch_b = [&](int q, C& a, C& b) {
-    a = b = (C)0;
-    if (q >= 0 && q < nz && vA) ld2(bg + q * pl + own, vec, vB, a, b);
+  Raw2<S> rbn;
+  auto fetch_b = [&](int q) { ld_raw2(bg + plane_off(q) + (vA ? own : 0), vec, true, rbn); };
+  auto conv_b = [&](int q, C& a, C& b) {
+    const bool okq = q >= 0 && q < nz;
+    a = (okq && vA) ? raw_ca(rbn) : (C)0;
+    b = (okq && vB) ? raw_cb(rbn) : (C)0;
   };
 
-  C ma, mb, ca, cb, pa, pb, ba, bb, bna, bnb;
-  fetch(q0 - 1); ma = na; mb = nb;
+  C ma, mb, ca, cb, pa, pb, ba, bb;
+  fetch(q0 - 1); stash(q0 - 1); ma = na; mb = nb;  // (the ring slot of q0 - 1 is rewritten before it is read)
   fetch(q0); stash(q0); ca = na; cb = nb;
-  fetch_b(q0, ba, bb);
+  fetch_b(q0); conv_b(q0, ba, bb);
   fetch(q0 + 1);
-  fetch_b(q0 + 1, bna, bnb);
+  fetch_b(q0 + 1);
   double nrm = 0.0;
   C s0 = 0, s1 = 0;
   for (int k = q0; k < q1; ++k) {
@@ -675,8 +685,8 @@ k_restrict_z(const GridDesc* __restrict__ grids, const int64_t* __restrict__ blo
       s0 = s1 = (C)0;
     }
     ma = ca; mb = cb; ca = pa; cb = pb;
-    ba = bna; bb = bnb;
-    fetch_b(k + 2, bna, bnb);
+    conv_b(k + 1, ba, bb);
+    fetch_b(k + 2);
   }
   if (partials) {
     const double sm = block_sum(nrm, red);
@@ -702,8 +712,14 @@ k_prolong_add(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 }
 
 // Pair form for the library's arrays (tiles of the relaxation, one x-pair per
-// thread); the loads of a pair do not depend on each other, so many are in
-// flight without any LDS or barrier.
+// thread), marching along z.  The x and y interpolation of a thread is the
+// same on every plane: each coarse plane reduces to one value per fine cell
+// of the pair, kept in a window of three coarse planes (K - 1, K, K + 1)
+// that advances with the fine plane's parent K, so a coarse plane is loaded
+// once per block column.  Fine values are read raw two planes ahead and
+// coarse planes one advance ahead, from clamped addresses without branches.
+// Every weight and index is that of prolong_value (cell-centred trilinear,
+// weight 1 on kept axes and at mirror edges; mode 1 piecewise constant).
 template <typename S, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY / 2)
 k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
@@ -714,16 +730,97 @@ k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   const int tid = threadIdx.x;
   const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
   const int gx = t.x0 + 2 * pxl, gy = t.y0 + tyl;
-  if (gy >= G.ny || gx >= G.nx) return;
+  const bool ok = gy < G.ny && gx < G.nx;
   const bool vB = gx + 1 < G.nx;
   const int64_t pl = (int64_t)G.px * G.ny;
-  S* x = xio + G.off + (int64_t)gy * G.px + gx;
-#pragma unroll 2
-  for (int k = t.z0; k < t.z1; ++k) {
-    C a, b, pa, pb;
-    ld2(x + k * pl, true, vB, a, b);
-    prolong_pair<S>(ec, G, gx, gy, k, mode, pa, pb);
-    st2(x + k * pl, true, vB, a + pa, b + pb);
+  S* x = xio + G.off + (ok ? (int64_t)gy * G.px + gx : 0);
+  const int nz = G.nz, cnz = G.cnz, fz = G.fz;
+  const S* e = ec + G.coff;
+  const int64_t cpl = (int64_t)G.cpx * G.cny;
+
+  // x: vA = a0 v(i0) + a1 v(i1), vB = b0 v(i0) + b2 v(i2) on a coarse row
+  int i0 = 0, i1 = 0, i2 = 0;
+  C a0 = 1, a1 = 0, b0 = 0, b2 = 0;
+  // y: rows ja (weight ya) and jb (weight yb)
+  int ja = 0, jb = 0;
+  C ya = 1, yb = 0;
+  if (ok) {
+    if (G.fx == 1) {
+      i0 = gx; i2 = vB ? gx + 1 : gx; i1 = i0;
+      b2 = 1;
+    } else if (mode == 1) {
+      i0 = i1 = i2 = gx / 2;
+      b0 = 1;
+    } else {
+      int pa, qa, pb, qb;
+      const bool tA = lin_idx(gx, 2, G.cnx, pa, qa);
+      const bool tB = lin_idx(gx + 1, 2, G.cnx, pb, qb);
+      i0 = pa;  // the pair's common parent
+      i1 = tA ? qa : pa;
+      i2 = tB ? qb : pa;
+      a0 = tA ? (C)0.75 : (C)1; a1 = tA ? (C)0.25 : (C)0;
+      b0 = tB ? (C)0.75 : (C)1; b2 = tB ? (C)0.25 : (C)0;
+    }
+    if (G.fy == 1) {
+      ja = jb = gy;
+    } else if (mode == 1) {
+      ja = jb = gy / 2;
+    } else {
+      const bool ty = lin_idx(gy, 2, G.cny, ja, jb);
+      if (ty) { ya = (C)0.75; yb = (C)0.25; } else { jb = ja; }
+    }
+  }
+  const S* ra = e + (int64_t)ja * G.cpx;
+  const S* rb = e + (int64_t)jb * G.cpx;
+  struct CRaw { Raw<S> v[6]; };
+  auto cload = [&](int K, CRaw& r) {  // coarse plane K (clamped)
+    const int64_t o = (int64_t)min(max(K, 0), cnz - 1) * cpl;
+    ld_raw(ra + o + i0, r.v[0]); ld_raw(ra + o + i1, r.v[1]); ld_raw(ra + o + i2, r.v[2]);
+    ld_raw(rb + o + i0, r.v[3]); ld_raw(rb + o + i1, r.v[4]); ld_raw(rb + o + i2, r.v[5]);
+  };
+  auto cval = [&](const CRaw& r, C& va, C& vb) {
+    const C u0 = raw_c(r.v[0]), u1 = raw_c(r.v[1]), u2 = raw_c(r.v[2]);
+    const C w0 = raw_c(r.v[3]), w1 = raw_c(r.v[4]), w2 = raw_c(r.v[5]);
+    va = ya * (a0 * u0 + a1 * u1) + yb * (a0 * w0 + a1 * w1);
+    vb = ya * (b0 * u0 + b2 * u2) + yb * (b0 * w0 + b2 * w2);
+  };
+  auto fplane = [&](int k) { return x + (int64_t)min(max(k, 0), nz - 1) * pl; };
+
+  const int k0 = t.z0, k1 = t.z1;
+  int Kc = k0 / fz;
+  C vma, vmb, v0a, v0b, vpa, vpb;
+  CRaw cr;
+  cload(Kc - 1, cr); cval(cr, vma, vmb);
+  cload(Kc, cr);     cval(cr, v0a, v0b);
+  cload(Kc + 1, cr); cval(cr, vpa, vpb);
+  cload(Kc + 2, cr);
+  Raw2<S> f0, f1, fn;
+  ld_raw2(fplane(k0), true, true, f0);
+  ld_raw2(fplane(k0 + 1), true, true, f1);
+  for (int k = k0; k < k1; ++k) {
+    ld_raw2(fplane(k + 2), true, true, fn);
+    const int K = k / fz;
+    if (K > Kc) {  // advance the window (uniform over the block)
+      vma = v0a; vmb = v0b; v0a = vpa; v0b = vpb;
+      cval(cr, vpa, vpb);
+      Kc = K;
+    }
+    cload(Kc + 2, cr);
+    // z weights: parent K and its neighbour on the fine cell's side
+    C za, zb;
+    if (mode == 0 && fz == 2) {
+      const int Kn = (k & 1) ? K + 1 : K - 1;
+      const bool two = Kn >= 0 && Kn < cnz;
+      const C w1 = two ? (C)0.75 : (C)1, w2 = two ? (C)0.25 : (C)0;
+      za = w1 * v0a + w2 * ((k & 1) ? vpa : vma);
+      zb = w1 * v0b + w2 * ((k & 1) ? vpb : vmb);
+    } else {
+      za = v0a;
+      zb = v0b;
+    }
+    if (ok) st2(x + (int64_t)k * pl, true, vB, raw_ca(f0) + za, raw_cb(f0) + zb);
+    f0 = f1;
+    f1 = fn;
   }
 }
 
@@ -833,52 +930,47 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   Raw<Tin> rhi[NHR];
   Raw<S> rhe[NHR];
   const double es = (MODE == 2) ? e_scale[t.g] : 0.0;
+  // loads from clamped addresses without branches around them (masked in stash)
   auto fetch = [&](int q) {
-    const bool okq = q >= 0 && q < nz;
-    rf = Raw2<FS>();
-    ri = Raw2<Tin>();
-    re = Raw2<S>();
-    if (okq && vA) {
-      if (KIND == 0) {
-        ld_raw2(reinterpret_cast<const FS*>(I0g) + q * G.ipz + ownu, ivec, vB, rf);
+    const int qc = min(max(q, 0), nz - 1);
+    const Tin* I0q = I0g + qc * G.ipz;
+    const int64_t po = qc * pl;
+    const int64_t oo = vA ? own : 0, ou = vA ? ownu : 0;
+    if (KIND == 0) {
+      ld_raw2(reinterpret_cast<const FS*>(I0q) + ou, ivec, vB, rf);
+    } else {
+      ld_raw2(I0q + ou, ivec, vB, ri);
+      if (MODE == 0) {
+        ld_raw2(reinterpret_cast<const FS*>(Eg) + po + oo, true, true, rf);
       } else {
-        ld_raw2(I0g + q * G.ipz + ownu, ivec, vB, ri);
-        if (MODE == 0) {
-          ld_raw2(reinterpret_cast<const FS*>(Eg) + q * pl + own, vec, vB, rf);
-        } else {
-          ld_raw2(reinterpret_cast<const FS*>(xg) + q * pl + own, vec, vB, rf);
-          if (MODE == 2) ld_raw2(Eg + q * pl + own, vec, vB, re);
-        }
+        ld_raw2(reinterpret_cast<const FS*>(xg) + po + oo, true, true, rf);
+        if (MODE == 2) ld_raw2(Eg + po + oo, true, true, re);
       }
     }
 #pragma unroll
     for (int k = 0; k < NHR; ++k) {
-      rh[k] = Raw<FS>();
-      rhi[k] = Raw<Tin>();
-      rhe[k] = Raw<S>();
-      if (okq && hv[k]) {
-        if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0g) + q * G.ipz + hu[k], rh[k]);
-        else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + q * pl + hg[k], rh[k]);
-        else {
-          ld_raw(reinterpret_cast<const FS*>(xg) + q * pl + hg[k], rh[k]);
-          ld_raw(I0g + q * G.ipz + hu[k], rhi[k]);
-          if (MODE == 2) ld_raw(Eg + q * pl + hg[k], rhe[k]);
-        }
+      if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0q) + hu[k], rh[k]);
+      else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + po + hg[k], rh[k]);
+      else {
+        ld_raw(reinterpret_cast<const FS*>(xg) + po + hg[k], rh[k]);
+        ld_raw(I0q + hu[k], rhi[k]);
+        if (MODE == 2) ld_raw(Eg + po + hg[k], rhe[k]);
       }
     }
   };
   // convert the last fetch: F pair (fa, fb), I0 pair (ia, ib); store F's plane
   double fa = 0, fb = 0, ia = 0, ib = 0;
   auto stash = [&](int q) {
+    const bool okq = q >= 0 && q < nz, mA = okq && vA, mB = okq && vB;
     if (KIND == 1) {
-      ia = raw_a(ri);
-      ib = raw_b(ri);
+      ia = mA ? raw_a(ri) : 0.0;
+      ib = mB ? raw_b(ri) : 0.0;
     }
-    fa = raw_a(rf);
-    fb = raw_b(rf);
+    fa = mA ? raw_a(rf) : 0.0;
+    fb = mB ? raw_b(rf) : 0.0;
     if (KIND == 1 && MODE == 2) {  // refinement update x64 + s e, written by the cell's owner
-      fa += es * raw_a(re);
-      fb += es * raw_b(re);
+      fa += mA ? es * raw_a(re) : 0.0;
+      fb += mB ? es * raw_b(re) : 0.0;
       if (vA && q >= q0 && q < q1) st2(x64_out + G.off + q * pl + own, vec, vB, fa, fb);
     }
     if (KIND == 1 && MODE >= 1) {
@@ -894,14 +986,13 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
         double v = raw_d(rh[k]);
         if (KIND == 1 && MODE == 2) v += es * raw_d(rhe[k]);
         if (KIND == 1 && MODE >= 1) v -= raw_d(rhi[k]);
-        P[hoff[k]] = v;
+        P[hoff[k]] = (okq && hv[k]) ? v : 0.0;
       }
   };
   // I1 pair at plane q (raw), prefetched one plane ahead
   Raw2<Tin> r1n;
-  auto fetch1 = [&](int q) {
-    r1n = Raw2<Tin>();
-    if (I1g && q >= 0 && q < nz && vA) ld_raw2(I1g + q * G.ipz + ownu, ivec, vB, r1n);
+  auto fetch1 = [&](int q) {  // raw, clamped; used only for k in [q0, q1) with vA / vB
+    if (I1g) ld_raw2(I1g + min(max(q, 0), nz - 1) * G.ipz + (vA ? ownu : 0), ivec, vB, r1n);
   };
 
   // registers: F and I0 at k - 1 (m), k (c), k + 1 (p)
