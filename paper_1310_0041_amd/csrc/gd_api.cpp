@@ -105,6 +105,7 @@ struct Level {
   GridDesc* d = nullptr;
   int64_t total = 0;
   bool row = false;  // every grid has ny == 1
+  bool keep_x = false;  // every grid keeps x on the way to the next level (f_x == 1)
   Tab sw, ew, rc, rz, pp;  // relaxation, per-voxel, child-cell, z-marching restriction, prolongation tiles
   void* x = nullptr;
   void* xt = nullptr;
@@ -225,6 +226,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     int64_t off = 0;
     bool more = false;
     L.row = true;
+    L.keep_x = true;
     for (auto& g : cur) {
       g.off = off;
       g.px = pitch_of(g.nx);
@@ -233,6 +235,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
       int f[3];
       coarsen_factors(g, f);
       g.fx = f[0]; g.fy = f[1]; g.fz = f[2];
+      if (g.fx != 1) L.keep_x = false;
       g.cnx = (g.nx + f[0] - 1) / f[0];
       g.cny = (g.ny + f[1] - 1) / f[1];
       g.cnz = (g.nz + f[2] - 1) / f[2];
@@ -425,7 +428,7 @@ struct Cycler {
     if (fuse && post > 0 && H.lv[l].sw.tile == 0) {
       smooth(l, post, C.x);  // prolongation fused into the first sweep's loads
     } else {
-      HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), C.x, H.lv[l].x, pmode, st));
+      HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), C.x, H.lv[l].x, pmode, H.lv[l].keep_x, st));
       smooth(l, post);
     }
   }

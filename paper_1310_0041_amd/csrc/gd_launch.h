@@ -41,7 +41,9 @@ hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xou
 hipError_t launch_restrict_z(gd_dtype s, const Geom& g, const void* x, const void* b, void* b_coarse,
                              void* x_coarse, double* partials, hipStream_t st);
 // x += P e for the library's arrays, relaxation tiles (one x-pair per thread).
-hipError_t launch_prolong_pair(gd_dtype s, const Geom& g, const void* e_coarse, void* x, int mode, hipStream_t st);
+// keep_x: every grid of the level keeps x (f_x == 1).
+hipError_t launch_prolong_pair(gd_dtype s, const Geom& g, const void* e_coarse, void* x, int mode, bool keep_x,
+                               hipStream_t st);
 hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* e_coarse, void* x, int mode,
                               hipStream_t st);
 // Finest level of the AD/SP systems in correction form: b = alpha (I1 - I0)

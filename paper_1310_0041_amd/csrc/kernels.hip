@@ -720,10 +720,11 @@ k_prolong_add(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 // coarse planes one advance ahead, from clamped addresses without branches.
 // Every weight and index is that of prolong_value (cell-centred trilinear,
 // weight 1 on kept axes and at mirror edges; mode 1 piecewise constant).
-template <typename S, int TX, int TY>
+template <typename S, int TX, int TY, bool KEEPX>
 __global__ void __launch_bounds__(TX * TY / 2)
 k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
                const S* __restrict__ ec, S* __restrict__ xio, int mode) {
+  // KEEPX: the level keeps x (f_x == 1), so a coarse row holds the pair itself
   using C = typename Ty<S>::C;
   const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
@@ -745,8 +746,9 @@ k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   int ja = 0, jb = 0;
   C ya = 1, yb = 0;
   if (ok) {
-    if (G.fx == 1) {
-      i0 = gx; i2 = vB ? gx + 1 : gx; i1 = i0;
+    if (G.fx == 1) {  // the pair (gx, gx + 1) of the coarse row (KEEPX loads it from i0 at once)
+      i0 = i1 = gx;
+      i2 = vB ? gx + 1 : gx;
       b2 = 1;
     } else if (mode == 1) {
       i0 = i1 = i2 = gx / 2;
@@ -772,17 +774,27 @@ k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   }
   const S* ra = e + (int64_t)ja * G.cpx;
   const S* rb = e + (int64_t)jb * G.cpx;
-  struct CRaw { Raw<S> v[6]; };
+  struct CRaw { Raw<S> v[6]; Raw2<S> p[2]; };
   auto cload = [&](int K, CRaw& r) {  // coarse plane K (clamped)
     const int64_t o = (int64_t)min(max(K, 0), cnz - 1) * cpl;
-    ld_raw(ra + o + i0, r.v[0]); ld_raw(ra + o + i1, r.v[1]); ld_raw(ra + o + i2, r.v[2]);
-    ld_raw(rb + o + i0, r.v[3]); ld_raw(rb + o + i1, r.v[4]); ld_raw(rb + o + i2, r.v[5]);
+    if (KEEPX) {
+      ld_raw2(ra + o + i0, true, true, r.p[0]);
+      ld_raw2(rb + o + i0, true, true, r.p[1]);
+    } else {
+      ld_raw(ra + o + i0, r.v[0]); ld_raw(ra + o + i1, r.v[1]); ld_raw(ra + o + i2, r.v[2]);
+      ld_raw(rb + o + i0, r.v[3]); ld_raw(rb + o + i1, r.v[4]); ld_raw(rb + o + i2, r.v[5]);
+    }
   };
   auto cval = [&](const CRaw& r, C& va, C& vb) {
-    const C u0 = raw_c(r.v[0]), u1 = raw_c(r.v[1]), u2 = raw_c(r.v[2]);
-    const C w0 = raw_c(r.v[3]), w1 = raw_c(r.v[4]), w2 = raw_c(r.v[5]);
-    va = ya * (a0 * u0 + a1 * u1) + yb * (a0 * w0 + a1 * w1);
-    vb = ya * (b0 * u0 + b2 * u2) + yb * (b0 * w0 + b2 * w2);
+    if (KEEPX) {
+      va = ya * raw_ca(r.p[0]) + yb * raw_ca(r.p[1]);
+      vb = ya * raw_cb(r.p[0]) + yb * raw_cb(r.p[1]);
+    } else {
+      const C u0 = raw_c(r.v[0]), u1 = raw_c(r.v[1]), u2 = raw_c(r.v[2]);
+      const C w0 = raw_c(r.v[3]), w1 = raw_c(r.v[4]), w2 = raw_c(r.v[5]);
+      va = ya * (a0 * u0 + a1 * u1) + yb * (a0 * w0 + a1 * w1);
+      vb = ya * (b0 * u0 + b2 * u2) + yb * (b0 * w0 + b2 * w2);
+    }
   };
   auto fplane = [&](int k) { return x + (int64_t)min(max(k, 0), nz - 1) * pl; };
 
@@ -1417,19 +1429,20 @@ hipError_t launch_restrict_z(gd_dtype s, const Geom& g, const void* x, const voi
   return last();
 }
 
-template <typename T>
+template <typename T, bool KEEPX>
 static void prolong_pair_launch(const Geom& g, const void* ec, void* x, int mode, hipStream_t st) {
   if (g.row)
-    hipLaunchKernelGGL((k_prolong_pair<T, SWR_TX, 1>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st, g.grids,
-                       g.block0, g.ngrids, g.zlen, (const T*)ec, (T*)x, mode);
-  else
-    hipLaunchKernelGGL((k_prolong_pair<T, SW_TX, SW_TY>), dim3((unsigned)g.nblocks), dim3(SW_TX * SW_TY / 2), 0, st,
+    hipLaunchKernelGGL((k_prolong_pair<T, SWR_TX, 1, KEEPX>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st,
                        g.grids, g.block0, g.ngrids, g.zlen, (const T*)ec, (T*)x, mode);
+  else
+    hipLaunchKernelGGL((k_prolong_pair<T, SW_TX, SW_TY, KEEPX>), dim3((unsigned)g.nblocks), dim3(SW_TX * SW_TY / 2),
+                       0, st, g.grids, g.block0, g.ngrids, g.zlen, (const T*)ec, (T*)x, mode);
 }
 
-hipError_t launch_prolong_pair(gd_dtype s, const Geom& g, const void* ec, void* x, int mode, hipStream_t st) {
+hipError_t launch_prolong_pair(gd_dtype s, const Geom& g, const void* ec, void* x, int mode, bool keep_x,
+                               hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
-#define L(T) prolong_pair_launch<T>(g, ec, x, mode, st)
+#define L(T) keep_x ? prolong_pair_launch<T, true>(g, ec, x, mode, st) : prolong_pair_launch<T, false>(g, ec, x, mode, st)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();
