@@ -416,25 +416,34 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   // column registers (red R / black K of planes p-2 .. p+1), b of planes p-1, p
   C Rm2 = 0, Km2 = 0, Rm1, Km1, R0, K0, Rp1, Kp1;
   C bRm1, bKm1, bR0, bK0;
-  Raw2<S> bw0, bw1;
-  Raw<S> rb, rb1, rb2;
-  XSet n0, n1;
+  // Loads in flight sit in two slots each (plane r in slot (r - pfirst) & 1)
+  // and the loop is unrolled by two, so that no in-flight register is ever
+  // copied: a copy would make the wave wait for the newest loads.
+  XSet S0, S1;
+  Raw2<S> B0, B1;
+  Raw<S> RB0, RB1;
   const int pfirst = max(q0 - 1, 0);
   const int plast = (q1 < nz) ? q1 : nz;  // p == nz: black of the last plane only
-  fetch_x(pfirst - 1, n0); stash(pfirst - 1, n0); split(pfirst - 1, xa(n0, pfirst - 1), xb(n0, pfirst - 1), Rm1, Km1);
-  fetch_x(pfirst, n0);     stash(pfirst, n0);     split(pfirst, xa(n0, pfirst), xb(n0, pfirst), R0, K0);
-  fetch_x(pfirst + 1, n0); stash(pfirst + 1, n0); split(pfirst + 1, xa(n0, pfirst + 1), xb(n0, pfirst + 1), Rp1, Kp1);
-  fetch_b(pfirst - 1, bw0); split(pfirst - 1, bA(bw0, pfirst - 1), bB(bw0, pfirst - 1), bRm1, bKm1);
-  fetch_b(pfirst, bw0);     split(pfirst, bA(bw0, pfirst), bB(bw0, pfirst), bR0, bK0);
-  rb = ring_b(pfirst);
-  fetch_x(pfirst + 2, n0);
-  fetch_x(pfirst + 3, n1);
-  fetch_b(pfirst + 1, bw0);
-  fetch_b(pfirst + 2, bw1);
-  rb1 = ring_b(pfirst + 1);
-  rb2 = ring_b(pfirst + 2);
+  {
+    XSet t0;
+    Raw2<S> tb;
+    fetch_x(pfirst - 1, t0); stash(pfirst - 1, t0); split(pfirst - 1, xa(t0, pfirst - 1), xb(t0, pfirst - 1), Rm1, Km1);
+    fetch_x(pfirst, t0);     stash(pfirst, t0);     split(pfirst, xa(t0, pfirst), xb(t0, pfirst), R0, K0);
+    fetch_x(pfirst + 1, t0); stash(pfirst + 1, t0); split(pfirst + 1, xa(t0, pfirst + 1), xb(t0, pfirst + 1), Rp1, Kp1);
+    fetch_b(pfirst - 1, tb); split(pfirst - 1, bA(tb, pfirst - 1), bB(tb, pfirst - 1), bRm1, bKm1);
+    fetch_b(pfirst, tb);     split(pfirst, bA(tb, pfirst), bB(tb, pfirst), bR0, bK0);
+  }
+  RB0 = ring_b(pfirst);
+  RB1 = ring_b(pfirst + 1);
+  fetch_x(pfirst + 2, S0);
+  fetch_x(pfirst + 3, S1);
+  fetch_b(pfirst + 1, B1);
+  fetch_b(pfirst + 2, B0);
 
-  for (int p = pfirst; p <= plast; ++p) {
+  // one plane step: red of plane p, black of plane p - 1, then plane p + 2
+  // enters LDS and the loads of planes p + 4 (x), p + 3 (b), p + 2 (ring b)
+  // go out into the slots just consumed
+  auto step = [&](int p, XSet& XS, Raw2<S>& BS, Raw<S>& RBS) {
     __syncthreads();
     const int par = p & 1;
     if (p < nz) {
@@ -464,7 +473,7 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
       if (rv[par]) {  // red cell of the 1-cell ring
         const int o = ro[par];
         const C xc = P[o];
-        C r = ring_bv(rb, p) - alpha * xc;
+        C r = ring_bv(RBS, p) - alpha * xc;
         r += rwl[par] * (P[o - 1] - xc);
         r += rwr[par] * (P[o + 1] - xc);
         if (!ROW) {
@@ -506,21 +515,23 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
         st2(xo + (int64_t)q * pl + own, VEC, vB, cq ? Km1 : Rm1, cq ? Rm1 : Km1);
       }
     }
-    // ---- advance: plane p + 2 enters LDS, loads for p + 4 (x) and p + 3 (b) go out
-    stash(p + 2, n0);
+    stash(p + 2, XS);
     Rm2 = Rm1; Km2 = Km1; Rm1 = R0; Km1 = K0; R0 = Rp1; K0 = Kp1;
-    split(p + 2, xa(n0, p + 2), xb(n0, p + 2), Rp1, Kp1);
+    split(p + 2, xa(XS, p + 2), xb(XS, p + 2), Rp1, Kp1);
     bRm1 = bR0; bKm1 = bK0;
-    split(p + 1, bA(bw0, p + 1), bB(bw0, p + 1), bR0, bK0);
-    rb = rb1; rb1 = rb2;
-    n0 = n1;
-    bw0 = bw1;
+    split(p + 1, bA(BS, p + 1), bB(BS, p + 1), bR0, bK0);
     // next planes (clamped reads past the chunk's end are harmless and keep
     // the loop free of a branch around the loads)
-    fetch_x(p + 4, n1);
-    fetch_b(p + 3, bw1);
-    rb2 = ring_b(p + 3);
+    fetch_x(p + 4, XS);
+    fetch_b(p + 3, BS);
+    RBS = ring_b(p + 2);
+  };
+  int p = pfirst;
+  for (; p + 1 <= plast; p += 2) {
+    step(p, S0, B1, RB0);
+    step(p + 1, S1, B0, RB1);
   }
+  if (p <= plast) step(p, S0, B1, RB0);
 }
 
 // ------------------------------------------------ residual + restriction
