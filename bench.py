@@ -34,13 +34,6 @@ BETA = (1.0, 1.0, 4.0)
 ALPHA = 0.01
 TOL = 1e-6
 HBM_PEAK_GBS = 8000.0
-# relaxation tile variants of 3-D grids (GD_SWEEP_TILE; the library's default is 2)
-SWEEP_TILES = {0: (64, 8), 1: (128, 8), 2: (64, 16), 3: (128, 16)}
-
-
-def sweep_tile():
-    t = int(os.environ.get("GD_SWEEP_TILE", "2"))
-    return t if t in SWEEP_TILES else 2
 
 
 def parse():
@@ -50,7 +43,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="stack1k", choices=sorted(WORKLOADS))
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-crop", default="32,128,128", help="nz,ny,nx of the oracle's crop")
+    p.add_argument("--cpu-crop", default="32,192,192", help="nz,ny,nx of the oracle's crop")
     p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
     p.add_argument("--inner-cycles", type=int, default=None,
                    help="V-cycles per FP64 refinement step (mixed storage; library default if omitted)")
@@ -302,12 +295,14 @@ def main():
         if n2:
             others[name] = {"launches": n2, "avg_launch_ms": m2 / n2, "GB/s": b2 / (m2 / n2 * 1e-3) / 1e9}
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    cfg = gd.sweep_config((spec.nz, spec.ny, spec.nx), tdt)
 
     traffic = None
     if os.path.exists(a.traffic_json):
         try:
             t = json.load(open(a.traffic_json))
-            if t.get("workload") == a.workload:
+            # counters of this workload's finest relaxation, taken with the same tile
+            if t.get("workload") == a.workload and list(t.get("tile", [])) == list(cfg["tile"]):
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -337,7 +332,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_rb_sweep<%s,%d,%d,false,true> finest level" % ((storage,) + SWEEP_TILES[sweep_tile()]),
+            "kernel": "k_rb_sweep<%s,%d,%d,false,true> finest level" % ((storage,) + tuple(cfg["tile"])),
+            "sweep_config": cfg,
             "launches": launches,
             "avg_launch_ms": avg_ms,
             "algorithmic_bytes_per_launch": bytes_per,

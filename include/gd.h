@@ -72,6 +72,9 @@ typedef struct {
                            HIP events (gd_get_kernel_time)                     */
   int fuse_prolong;     /* 1: add the up-sampled correction inside the first
                            post-smoothing sweep instead of a separate pass    */
+  int sweep_tile;       /* relaxation tile of 3-D grids: -1 automatic (the
+                           autotuned or default choice), 0: 64x8, 1: 128x8,
+                           2: 64x16, 3: 128x16.  Results do not depend on it. */
 } gd_solve_opts;
 
 /* Filled by the solve calls when the pointer is non-NULL. */
@@ -233,6 +236,16 @@ gd_status gd_prolong_add(const void* e_coarse, void* x, gd_dtype s,
  * b, write x: 3 * storage bytes per voxel of the finest level). */
 gd_status gd_get_kernel_time(int variant, double* total_ms, int64_t* launches, double* bytes_per_launch);
 void gd_reset_kernel_time(void);
+
+/* Relaxation launch of the finest level of an nx*ny*nz 3-D grid in storage
+ * type s: tile (tile_tx x tile_ty cells) and block target, and whether they
+ * come from the autotuner (tuned = 1, ms = the measured time of one sweep)
+ * or from the fixed default.  The autotuner runs once per size and type
+ * when a workspace of at least 2^22 cells is first built (GD_AUTOTUNE=0, or
+ * GD_SWEEP_TILE / GD_SWEEP_BLOCKS, keep the fixed choice); any tile computes
+ * the same values.  Output pointers may be NULL. */
+gd_status gd_sweep_config(int64_t nx, int64_t ny, int64_t nz, gd_dtype s, int* tile_tx, int* tile_ty,
+                          int64_t* blocks_target, int* tuned, double* ms);
 
 /* Free every cached workspace (all devices). */
 gd_status gd_release_workspace(void);

@@ -45,6 +45,7 @@ class SolveOpts(ctypes.Structure):
         ("prolong", ctypes.c_int),
         ("timing", ctypes.c_int),
         ("fuse_prolong", ctypes.c_int),
+        ("sweep_tile", ctypes.c_int),
     ]
 
 
@@ -97,6 +98,8 @@ _SIGS = {
     "gd_get_kernel_time": (_i, [_i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "gd_reset_kernel_time": (None, []),
     "gd_release_workspace": (_i, []),
+    "gd_sweep_config": (_i, [_i64, _i64, _i64, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i64),
+                             ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "gd_mg_error_pairs": (_i, [_vp, _vp, _vp, _i, _vp, _vp, _vp]),
     "gd_net_create": (_i, [ctypes.POINTER(_vp), ctypes.c_uint64]),
     "gd_net_destroy": (_i, [_vp]),
@@ -418,6 +421,18 @@ def kernel_time(variant=SWEEP_STACK):
 
 def reset_kernel_time():
     load().gd_reset_kernel_time()
+
+
+def sweep_config(shape, dtype):
+    """Relaxation launch of the finest level of a (nz, ny, nx) grid: dict of
+    tile, blocks target, tuned flag and measured ms per sweep."""
+    nz, ny, nx = shape
+    tx, ty, tuned = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    blocks, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(load().gd_sweep_config(nx, ny, nz, gd_dtype(dtype), ctypes.byref(tx), ctypes.byref(ty),
+                                  ctypes.byref(blocks), ctypes.byref(tuned), ctypes.byref(ms)))
+    return {"tile": (tx.value, ty.value), "blocks_target": blocks.value, "tuned": bool(tuned.value),
+            "ms": ms.value}
 
 
 def release_workspace():

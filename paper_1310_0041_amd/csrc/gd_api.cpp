@@ -198,7 +198,7 @@ static int64_t sweep_target(bool row = false) {
 }
 
 static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
-                                        hipStream_t st) {
+                                        hipStream_t st, int tile_force = -1) {
   auto H = std::make_unique<Hier>();
   HIP_TRY(hipGetDevice(&H->device));
   H->s = s;
@@ -282,15 +282,15 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
       build_tab(L.ew, L.h, EWR_TX, 1, false, 8192);
       build_tab(L.rc, L.h, EWR_TX, 1, true, 8192);
       build_tab(L.rz, L.h, SWR_TX, 1, false, 4096, true);
-      build_tab(L.pp, L.h, SWR_TX, 1, false, tgt);
+      build_tab(L.pp, L.h, SWR_TX, 1, false, li == 0 ? 8192 : 4096);
     } else {
-      const int v = sweep_tile();
+      const int v = tile_force >= 0 ? tile_force : sweep_tile();
       build_tab(L.sw, L.h, SWEEP_TILE_TX[v], SWEEP_TILE_TY[v], false, tgt);
       L.sw.tile = v;
       build_tab(L.ew, L.h, EW_TX, EW_TY, false, 8192);
       build_tab(L.rc, L.h, EW_TX, EW_TY, true, 8192);
       build_tab(L.rz, L.h, SW_TX, SW_TY, false, 2048, true);
-      build_tab(L.pp, L.h, SW_TX, SW_TY, false, tgt);
+      build_tab(L.pp, L.h, SW_TX, SW_TY, false, li == 0 ? 4096 : 2048);
     }
     maxblocks = std::max({maxblocks, L.sw.h_b0.back(), L.ew.h_b0.back(), L.rc.h_b0.back(), L.rz.h_b0.back(),
                           L.pp.h_b0.back()});
@@ -326,6 +326,103 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
   return H;
 }
 
+// ------------------------------------------------------------ autotuning
+//
+// The relaxation of a large finest 3-D level is timed once per (size,
+// storage type) for every tile variant and block target; the fastest is
+// kept for this and later hierarchies of that size.  Any tile computes the
+// same values (each cell's update depends on its neighbours only), so the
+// choice changes time, not results.  GD_AUTOTUNE=0, or a GD_SWEEP_TILE /
+// GD_SWEEP_BLOCKS setting, keeps the fixed choice.
+struct TuneChoice {
+  int tile = 2;
+  int64_t target = 4096;
+  double ms = 0.0;
+  bool tuned = false;
+};
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int64_t, int64_t, int64_t, int>, TuneChoice> g_tune;
+
+static bool autotune_on() {
+  static bool v = [] {
+    const char* e = std::getenv("GD_AUTOTUNE");
+    if (e && std::atoi(e) == 0) return false;
+    return !std::getenv("GD_SWEEP_TILE") && !std::getenv("GD_SWEEP_BLOCKS");
+  }();
+  return v;
+}
+
+static void set_sweep_tabs(Hier& H, int tile, int64_t target) {
+  for (size_t li = 0; li < H.lv.size(); ++li) {
+    Level& L = H.lv[li];
+    if (L.row) continue;
+    const int64_t tgt = li == 0 ? target : std::max<int64_t>(1, target / 2);
+    int64_t* d = L.sw.d_b0;
+    build_tab(L.sw, L.h, SWEEP_TILE_TX[tile], SWEEP_TILE_TY[tile], false, tgt);
+    L.sw.d_b0 = d;
+    L.sw.tile = tile;
+    HIP_TRY(hipMemcpy(d, L.sw.h_b0.data(), L.sw.h_b0.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  }
+}
+
+static void autotune(Hier& H, hipStream_t st) {
+  Level& L = H.lv[0];
+  if (L.row || H.ngrids != 1 || !autotune_on()) return;
+  const GridDesc& g = L.h[0];
+  if ((int64_t)g.nx * g.ny * g.nz < ((int64_t)1 << 22)) return;
+  const auto key = std::make_tuple((int64_t)g.nx, (int64_t)g.ny, (int64_t)g.nz, (int)H.s);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      set_sweep_tabs(H, it->second.tile, it->second.target);
+      return;
+    }
+  }
+  const size_t es = dsize(H.s);
+  HIP_TRY(hipMemsetAsync(L.x, 0, L.total * es, st));
+  HIP_TRY(hipMemsetAsync(L.b, 0, L.total * es, st));
+  int64_t* d_b0 = nullptr;
+  HIP_TRY(hipMalloc(&d_b0, 2 * sizeof(int64_t)));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  TuneChoice best;
+  best.ms = 1e30;
+  const int64_t targets[4] = {1024, 2048, 4096, 8192};
+  for (int tile = 0; tile < 4; ++tile) {
+    for (int64_t target : targets) {
+      Tab t;
+      build_tab(t, L.h, SWEEP_TILE_TX[tile], SWEEP_TILE_TY[tile], false, target);
+      t.tile = tile;
+      HIP_TRY(hipMemcpyAsync(d_b0, t.h_b0.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice, st));
+      t.d_b0 = d_b0;
+      const Geom geo = t.geom(L.d, 1, false);
+      HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));  // warm-up
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms / 3.0 < best.ms) {
+        best.ms = ms / 3.0;
+        best.tile = tile;
+        best.target = target;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_b0);
+  best.tuned = true;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+  }
+  set_sweep_tabs(H, best.tile, best.target);
+}
+
 // -------------------------------------------------------------- workspace
 
 static std::mutex g_cache_mu;
@@ -338,7 +435,7 @@ static uint64_t fnv(const void* p, size_t n, uint64_t h = 1469598103934665603ull
 }
 
 static Hier* get_hier(const char* kind, const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
-                      hipStream_t st) {
+                      hipStream_t st, int tile_force) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   // the descriptors minus the caller's I/O layout decide the hierarchy
@@ -347,12 +444,14 @@ static Hier* get_hier(const char* kind, const std::vector<GridSpec>& specs, gd_d
     sig.insert(sig.end(), {(double)g.nx, (double)g.ny, (double)g.nz, g.alpha, g.wx, g.wy, g.wz});
   }
   char key[256];
-  std::snprintf(key, sizeof key, "%s|d%d|s%d|m%d|n%zu|h%016llx", kind, dev, (int)s, (int)mixed, specs.size(),
-                (unsigned long long)fnv(sig.data(), sig.size() * sizeof(double)));
+  std::snprintf(key, sizeof key, "%s|d%d|s%d|m%d|t%d|n%zu|h%016llx", kind, dev, (int)s, (int)mixed, tile_force,
+                specs.size(), (unsigned long long)fnv(sig.data(), sig.size() * sizeof(double)));
   std::lock_guard<std::mutex> lk(g_cache_mu);
   auto it = g_cache.find(key);
   if (it == g_cache.end()) {
-    it = g_cache.emplace(key, build_hier(specs, s, mixed, st)).first;
+    auto H = build_hier(specs, s, mixed, st, tile_force);
+    if (tile_force < 0) autotune(*H, st);
+    it = g_cache.emplace(key, std::move(H)).first;
   }
   Hier* H = it->second.get();
   // the caller's layout may differ between calls of the same shape
@@ -715,6 +814,7 @@ void gd_default_opts(gd_solve_opts* o) {
   o->prolong = 0;
   o->timing = 0;
   o->fuse_prolong = 0;
+  o->sweep_tile = -1;
 }
 
 const char* gd_last_error(void) { return t_err.c_str(); }
@@ -723,7 +823,7 @@ const char* gd_version(void) { return "gdstack 0.1 gfx950"; }
 static gd_status check_opts(const gd_solve_opts& o) {
   if (!(o.rel_tol > 0.0) || o.max_cycles < 0 || o.pre_smooth < 0 || o.post_smooth < 0 ||
       o.pre_smooth + o.post_smooth < 1 || !valid_dtype(o.storage) || o.inner_cycles < 1 ||
-      (o.prolong != 0 && o.prolong != 1))
+      (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3)
     return fail(GD_ERR_INVALID, "invalid solver options");
   if (!o.fp64_refine && (o.storage == GD_F16 || o.storage == GD_BF16))
     return fail(GD_ERR_UNSUPPORTED, "16-bit storage needs fp64_refine = 1 (its rounding floor is far above 1e-6)");
@@ -749,7 +849,7 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, i
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<GridSpec> g{{nx, ny, nz, 0.0, bx, by, bz, 0, nx, nx * ny}};
-    Hier* H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st);
+    Hier* H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
     Problem P{I0, nullptr, I1, in_t, out_t, true};
     Outcome R = o.fp64_refine ? solve_mixed(*H, P, o, st) : solve_plain(*H, P, o, st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -798,7 +898,7 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
-    Hier* H = get_hier("sp", g, o.storage, o.fp64_refine != 0, st);
+    Hier* H = get_hier("sp", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
     Problem P{I0, I1, I2, t, t, false};
     Outcome R = o.fp64_refine ? solve_mixed(*H, P, o, st) : solve_plain(*H, P, o, st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -873,13 +973,13 @@ gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t 
   o.storage = s;
   o.fp64_refine = 0;
   if (!(o.rel_tol > 0.0) || o.pre_smooth < 0 || o.post_smooth < 0 || o.pre_smooth + o.post_smooth < 1 ||
-      (o.prolong != 0 && o.prolong != 1))
+      (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3)
     return fail(GD_ERR_INVALID, "gd_hierarchy_create: invalid options");
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     auto hh = std::make_unique<gd_hierarchy>();
     hh->o = o;
-    hh->H = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st);
+    hh->H = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, o.sweep_tile);
     *h = hh.release();
     return GD_OK;
   });
@@ -1225,6 +1325,30 @@ void gd_reset_kernel_time(void) {
     g_timer.total_ms[k] = 0.0;
     g_timer.launches[k] = 0;
   }
+}
+
+gd_status gd_sweep_config(int64_t nx, int64_t ny, int64_t nz, gd_dtype s, int* tile_tx, int* tile_ty,
+                          int64_t* blocks_target, int* tuned, double* ms) {
+  int tile = sweep_tile();
+  int64_t target = sweep_target(false);
+  int t = 0;
+  double m = 0.0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(nx, ny, nz, (int)s));
+    if (it != g_tune.end()) {
+      tile = it->second.tile;
+      target = it->second.target;
+      t = 1;
+      m = it->second.ms;
+    }
+  }
+  if (tile_tx) *tile_tx = SWEEP_TILE_TX[tile];
+  if (tile_ty) *tile_ty = SWEEP_TILE_TY[tile];
+  if (blocks_target) *blocks_target = target;
+  if (tuned) *tuned = t;
+  if (ms) *ms = m;
+  return GD_OK;
 }
 
 gd_status gd_release_workspace(void) {

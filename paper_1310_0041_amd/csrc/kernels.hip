@@ -276,7 +276,7 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   const C wU = (gy > 0) ? wy : (C)0, wD = (gy + 1 < ny) ? wy : (C)0;
   // per plane parity par = p & 1 the red cell of the pair is at position cp = (gy + par) & 1
   int offO[2], offY[2];
-  C wO[2], wP[2], invI[2], dxy[2];
+  C wO[2], wP[2], wL[2], wR[2], invI[2], dxy[2];
   bool vR[2];
 #pragma unroll
   for (int par = 0; par < 2; ++par) {
@@ -286,8 +286,14 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
     wO[par] = (cp ? (gx + 2 < nx) : (gx > 0)) ? wx : (C)0;
     wP[par] = (cp ? true : vB) ? wx : (C)0;
     vR[par] = cp ? vB : vA;  // the red cell of plane p (and black cell of plane p - 1) exists
-    dxy[par] = alpha + wO[par] + wP[par] + wU + wD;
-    const C di = dxy[par] + (nz > 1 ? 2 * wz : (C)0);
+    // left, right, up, down, then z: the order the 1-cell ring uses too, so
+    // that a ring cell and its owner round alike and every tile shape gives
+    // the same values
+    wL[par] = cp ? wP[par] : wO[par];  // left neighbour: the pair partner when the cell is gx + 1
+    wR[par] = cp ? wO[par] : wP[par];
+    dxy[par] = alpha + wL[par] + wR[par] + wU + wD;
+    const C wz1 = nz > 1 ? wz : (C)0;
+    const C di = (dxy[par] + wz1) + wz1;
     invI[par] = di > (C)0 ? (C)1 / di : (C)0;
   }
 
@@ -453,8 +459,12 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
       if (vR[par]) {
         const C xc = R0;
         C r = bR0 - alpha * xc;
-        r += wP[par] * (K0 - xc);
-        r += wO[par] * (P[offO[par]] - xc);
+        {
+          const bool cp = ((gy + p) & 1) != 0;  // red cell on the pair's right
+          const C vo = P[offO[par]];
+          r += wL[par] * ((cp ? K0 : vo) - xc);  // left neighbour first
+          r += wR[par] * ((cp ? vo : K0) - xc);
+        }
         if (!ROW) {
           r += wU * (P[offY[par] - HX] - xc);
           r += wD * (P[offY[par] + HX] - xc);
@@ -482,8 +492,9 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
         }
         if (p > 0) r += wz * (X[((p - 1) & 3) * PLANE + o] - xc);
         if (p < nz - 1) r += wz * (X[((p + 1) & 3) * PLANE + o] - xc);
-        const C d = rdxy[par] + wzm + wzp;
-        P[o] = d > (C)0 ? xc + r / d : (C)0;
+        const C d = (rdxy[par] + wzm) + wzp;
+        const C inv = d > (C)0 ? (C)1 / d : (C)0;
+        P[o] = inv != (C)0 ? xc + r * inv : (C)0;
       }
     }
     __syncthreads();

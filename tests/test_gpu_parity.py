@@ -8,6 +8,8 @@ of roundings of values of similar magnitude); solves to 1e-6 (FP64 iterate)
 or 1e-5 (plain FP32) relative L2, the bars stated for this path.
 """
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -300,3 +302,43 @@ def test_deterministic(gd):
     a, _ = gd.smooth_z(I0, BETA)
     b, _ = gd.smooth_z(I0, BETA)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_sweep_tiles_identical(gd, storage):
+    """Every relaxation tile computes the same values: the AD and SP results
+    agree bit for bit across the four tile variants (odd sizes, several
+    z-chunks and ragged tile edges)."""
+    import synth
+
+    spec = synth.StackSpec(203, 77, 37, (4.0, 40.0), True, 13100422)
+    I0 = synth.make_stack(spec).to(torch.float32).cuda()
+    # a fixed number of cycles (the FP32 rounding floor of this stack is near 1e-6)
+    kw = dict(rel_tol=1e-9, max_cycles=5, check=False)
+    if storage == "f16":
+        kw.update(storage=gd.F16, fp64_refine=1)
+    outs = []
+    for tile in range(4):
+        I1, r1 = gd.smooth_z(I0, (1.0, 1.0, 4.0), out_dtype=torch.float32, sweep_tile=tile, **kw)
+        I2, r2, _ = gd.screened_poisson_stack(I0, I1, 0.01, sweep_tile=tile, **kw)
+        outs.append((I1, I2, r1["cycles"], r2["cycles"]))
+    for I1, I2, c1, c2 in outs[1:]:
+        assert (c1, c2) == outs[0][2:]
+        assert torch.equal(I1, outs[0][0]) and torch.equal(I2, outs[0][1])
+
+
+def test_autotune_choice(gd):
+    """A workspace of 2^22 cells is autotuned once; the choice is reported
+    and changes nothing in the result."""
+    import synth
+
+    spec = synth.StackSpec(256, 256, 64, (4.0, 40.0), True, 13100423)
+    I0 = synth.make_stack(spec).to(torch.float32).cuda()
+    I1, r1 = gd.smooth_z(I0, (1.0, 1.0, 4.0), out_dtype=torch.float32, rel_tol=1e-6)
+    cfg = gd.sweep_config(tuple(I0.shape), torch.float32)
+    if os.environ.get("GD_AUTOTUNE", "1") != "0" and "GD_SWEEP_TILE" not in os.environ \
+            and "GD_SWEEP_BLOCKS" not in os.environ:
+        assert cfg["tuned"] and cfg["ms"] > 0.0
+    assert cfg["tile"] in [(64, 8), (128, 8), (64, 16), (128, 16)]
+    J1, s1 = gd.smooth_z(I0, (1.0, 1.0, 4.0), out_dtype=torch.float32, rel_tol=1e-6, sweep_tile=0)
+    assert r1["cycles"] == s1["cycles"] and torch.equal(I1, J1)
