@@ -347,7 +347,7 @@ static bool autotune_on() {
   static bool v = [] {
     const char* e = std::getenv("GD_AUTOTUNE");
     if (e && std::atoi(e) == 0) return false;
-    return !std::getenv("GD_SWEEP_TILE") && !std::getenv("GD_SWEEP_BLOCKS");
+    return !std::getenv("GD_SWEEP_TILE") && !std::getenv("GD_SWEEP_BLOCKS") && !std::getenv("GD_SWEEP_BLOCKS_ROW");
   }();
   return v;
 }
@@ -365,9 +365,84 @@ static void set_sweep_tabs(Hier& H, int tile, int64_t target) {
   }
 }
 
+static void set_row_tabs(Hier& H, int64_t target) {
+  for (size_t li = 0; li < H.lv.size(); ++li) {
+    Level& L = H.lv[li];
+    if (!L.row) continue;
+    const int64_t tgt = li == 0 ? target : std::max<int64_t>(1, target / 2);
+    int64_t* d = L.sw.d_b0;
+    build_tab(L.sw, L.h, SWR_TX, 1, false, tgt);
+    L.sw.d_b0 = d;
+    HIP_TRY(hipMemcpy(d, L.sw.h_b0.data(), L.sw.h_b0.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  }
+}
+
+// One-line grids (2-D slices): the row tile is fixed; the block target of the
+// finest level is timed at 2048 .. 16384 and the fastest kept, per set of
+// slice sizes (total cells and count; tile -1 in the cache key).
+static void autotune_rows(Hier& H, hipStream_t st) {
+  Level& L = H.lv[0];
+  int64_t cells = 0;
+  for (const auto& g : L.h) cells += (int64_t)g.nx * g.ny * g.nz;
+  if (cells < ((int64_t)1 << 22)) return;
+  const auto key = std::make_tuple(cells, (int64_t)H.ngrids, (int64_t)-1, (int)H.s);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      set_row_tabs(H, it->second.target);
+      return;
+    }
+  }
+  const size_t es = dsize(H.s);
+  HIP_TRY(hipMemsetAsync(L.x, 0, L.total * es, st));
+  HIP_TRY(hipMemsetAsync(L.b, 0, L.total * es, st));
+  const size_t nb = (size_t)H.ngrids + 1;
+  int64_t* d_b0 = nullptr;
+  HIP_TRY(hipMalloc(&d_b0, nb * sizeof(int64_t)));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  TuneChoice best;
+  best.ms = 1e30;
+  best.tile = -1;
+  for (int64_t target : {2048, 4096, 8192, 16384}) {
+    Tab t;
+    build_tab(t, L.h, SWR_TX, 1, false, target);
+    HIP_TRY(hipMemcpyAsync(d_b0, t.h_b0.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    t.d_b0 = d_b0;
+    const Geom geo = t.geom(L.d, H.ngrids, true);
+    HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));
+    HIP_TRY(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms / 3.0 < best.ms) {
+      best.ms = ms / 3.0;
+      best.target = target;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_b0);
+  best.tuned = true;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+  }
+  set_row_tabs(H, best.target);
+}
+
 static void autotune(Hier& H, hipStream_t st) {
   Level& L = H.lv[0];
-  if (L.row || H.ngrids != 1 || !autotune_on()) return;
+  if (!autotune_on()) return;
+  if (L.row) {
+    autotune_rows(H, st);
+    return;
+  }
+  if (H.ngrids != 1) return;
   const GridDesc& g = L.h[0];
   if ((int64_t)g.nx * g.ny * g.nz < ((int64_t)1 << 22)) return;
   const auto key = std::make_tuple((int64_t)g.nx, (int64_t)g.ny, (int64_t)g.nz, (int)H.s);
