@@ -44,12 +44,19 @@ __device__ __forceinline__ bf f2b(float v) { return __float2bfloat16(v); }
 
 // ------------------------------------------------------------ convolution
 //
-// Block: one image row segment of 64 pixels, all output channels.  The three
-// input rows it touches (66 pixels, all channels) are staged in LDS; wave w
-// computes pixels 16w .. 16w + 15 for every 16-channel output tile.
+// Block: a 64-pixel segment of CONV_RB consecutive rows of one image, all
+// output channels, marching down the rows.  The three input rows a row
+// needs (66 pixels, all channels) sit in an LDS ring; each new row is read
+// into registers while the current one is computed and enters LDS after.
+// The 4 waves split the work into WP pixel groups x WM output-channel groups
+// (WP * WM = 4); a wave keeps its weight fragments (A operands) for all
+// k-steps in registers for the whole block and reads only activations (B
+// operands) from LDS.
 // in: pixel stride in_s, channel offset in_o; out likewise (bf16 or fp32);
 // mask (optional, bf16 view): the result is zeroed where mask <= 0 (ReLU'
 // of the layer that produced this layer's input, for the data gradient).
+constexpr int CONV_RB = 16;
+
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256)
 k_conv3x3(const bf* __restrict__ in, int in_s, int in_o, const bf* __restrict__ W, const float* __restrict__ bias,
@@ -57,66 +64,113 @@ k_conv3x3(const bf* __restrict__ in, int in_s, int in_o, const bf* __restrict__ 
           const bf* __restrict__ mask, int mask_s, int mask_o, int H, int Wd) {
   constexpr int K = 9 * CIN;
   constexpr int KPAD = (K + 31) / 32 * 32;
+  constexpr int KS = KPAD / 32;
   constexpr int MT = COUT / 16;
+  constexpr int WM = (MT % 4 == 0) ? 4 : (MT % 2 == 0) ? 2 : 1;  // output-channel groups
+  constexpr int WP = 4 / WM;                                      // pixel groups
+  constexpr int NPT = 4 / WP;                                     // 16-pixel tiles per wave
+  constexpr int MTW = MT / WM;                                    // 16-channel tiles per wave
+  constexpr int CH = CIN / 8;                                     // 16-byte chunks per pixel
+  constexpr int NCH = (66 * CH + 255) / 256;                      // chunks of a row per thread
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel padding");
   __shared__ __attribute__((aligned(16))) bf T[3][66][CIN];
 
   const int segs = Wd / 64;
+  const int rblk = (H + CONV_RB - 1) / CONV_RB;
   const int seg = blockIdx.x % segs;
-  const int y = (blockIdx.x / segs) % H;
-  const int b = blockIdx.x / (segs * H);
+  const int y0 = ((blockIdx.x / segs) % rblk) * CONV_RB;
+  const int b = blockIdx.x / (segs * rblk);
   const int x0 = seg * 64;
   const int tid = threadIdx.x;
-  // stage: 16-byte chunks (8 channels of one pixel)
-  constexpr int CH = CIN / 8;
-  for (int i = tid; i < 3 * 66 * CH; i += 256) {
-    const int c8 = i % CH, px = (i / CH) % 66, r = i / (CH * 66);
-    const int yy = y + r - 1, xx = x0 + px - 1;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (yy >= 0 && yy < H && xx >= 0 && xx < Wd)
-      v = *reinterpret_cast<const uint4*>(in + ((int64_t)(b * H + yy) * Wd + xx) * in_s + in_o + 8 * c8);
-    *reinterpret_cast<uint4*>(&T[r][px][8 * c8]) = v;
-  }
-  __syncthreads();
-  const int w = tid >> 6, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
   const int j = l & 15, kg = l >> 4;
-  v4f acc[MT];
+  const int wp = w % WP, wm = w / WP;
+
+  // weight fragments of this wave: rows 16 (wm MTW + mt) + j, k = 32 s + 8 kg
+  v8bf A[MTW][KS];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int kk = 0; kk < KPAD; kk += 32) {
-    const int k = kk + 8 * kg;
-    v8bf bv;
-    if (k < K) {
+  for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      A[mt][s] = *reinterpret_cast<const v8bf*>(W + (int64_t)(16 * (wm * MTW + mt) + j) * KPAD + 32 * s + 8 * kg);
+
+  // row staging: chunk c of a row = pixel c / CH (x0 - 1 + pixel), channels 8 (c % CH)
+  uint4 R[NCH];
+  auto fetch_row = [&](int yy) {
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+      const int c = tid + 256 * q;
+      const int px = c / CH, c8 = c - px * CH, xx = x0 + px - 1;
+      R[q] = make_uint4(0, 0, 0, 0);
+      if (c < 66 * CH && yy >= 0 && yy < H && xx >= 0 && xx < Wd)
+        R[q] = *reinterpret_cast<const uint4*>(in + ((int64_t)(b * H + yy) * Wd + xx) * in_s + in_o + 8 * c8);
+    }
+  };
+  auto store_row = [&](int yy) {
+    bf* P = &T[(yy + 3) % 3][0][0];
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+      const int c = tid + 256 * q;
+      if (c < 66 * CH) *reinterpret_cast<uint4*>(P + 8 * c) = R[q];
+    }
+  };
+  fetch_row(y0 - 1);
+  store_row(y0 - 1);
+  fetch_row(y0);
+  store_row(y0);
+  fetch_row(y0 + 1);
+
+  const int yend = min(y0 + CONV_RB, H);
+  for (int y = y0; y < yend; ++y) {
+    store_row(y + 1);
+    __syncthreads();
+    if (y + 2 < yend + 1) fetch_row(y + 2);  // uniform: the next row's input, in flight during the products
+    v4f acc[NPT][MTW];
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt) acc[t][mt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = 32 * s + 8 * kg;
       const int tap = k / CIN, ci = k - tap * CIN;
       const int dy = tap / 3, dx = tap - 3 * dy;
-      bv = *reinterpret_cast<const v8bf*>(&T[dy][16 * w + j + dx][ci]);
-    } else {
-      bv = v8bf{0, 0, 0, 0, 0, 0, 0, 0};
+      const bool kin = k < K;
+#pragma unroll
+      for (int t = 0; t < NPT; ++t) {
+        const int px = 16 * (wp * NPT + t) + j;
+        v8bf bv = v8bf{0, 0, 0, 0, 0, 0, 0, 0};
+        if (kin) bv = *reinterpret_cast<const v8bf*>(&T[(y - 1 + dy + 3) % 3][px + dx][ci]);
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) acc[t][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt][s], bv, acc[t][mt], 0, 0, 0);
+      }
     }
+    // the last product issued finishes last: drain it, and keep every read
+    // of the other accumulators behind the drain
+    mfma_drain(acc[NPT - 1][MTW - 1]);
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const v8bf av = *reinterpret_cast<const v8bf*>(W + (int64_t)(16 * m + j) * KPAD + k);
-      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[m], 0, 0, 0);
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt) asm volatile("" : "+a"(acc[t][mt]));
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+      const int x = x0 + 16 * (wp * NPT + t) + j;
+      const int64_t pix = (int64_t)(b * H + y) * Wd + x;
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int co = 16 * (wm * MTW + mt) + 4 * kg + e;
+          if (co >= cstore) continue;
+          float v = acc[t][mt][e] + (bias ? bias[co] : 0.f);
+          if (relu) v = fmaxf(v, 0.f);
+          if (mask) v = (b2f(mask[pix * mask_s + mask_o + co]) > 0.f) ? v : 0.f;
+          if (out_f) out_f[pix * out_s + out_o + co] = v;
+          else out_b[pix * out_s + out_o + co] = f2b(v);
+        }
+      }
     }
-  }
-  mfma_drain(acc[MT - 1]);
-#pragma unroll
-  for (int m = 0; m < MT - 1; ++m) asm volatile("" : "+a"(acc[m]));
-  const int x = x0 + 16 * w + j;
-  const int64_t pix = (int64_t)(b * H + y) * Wd + x;
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int co = 16 * m + 4 * kg + e;
-      if (co >= cstore) continue;
-      float v = acc[m][e] + (bias ? bias[co] : 0.f);
-      if (relu) v = fmaxf(v, 0.f);
-      if (mask) v = (b2f(mask[pix * mask_s + mask_o + co]) > 0.f) ? v : 0.f;
-      if (out_f) out_f[pix * out_s + out_o + co] = v;
-      else out_b[pix * out_s + out_o + co] = f2b(v);
-    }
+    __syncthreads();  // the ring slot of row y - 1 is rewritten next
   }
 }
 
@@ -246,44 +300,83 @@ k_bias_grad(const bf* __restrict__ dout, int d_s, int d_o, int cout, int64_t npi
 
 // ------------------------------------------------------------- glue
 
+// Channels move in groups of 8 (16 bytes): every channel count, stride and
+// offset of these views is a multiple of 8.
+struct V8 {
+  float v[8];
+};
+__device__ __forceinline__ V8 ld8(const bf* p) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+  V8 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r.v[2 * i] = __uint_as_float(w[i] << 16);
+    r.v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+  return r;
+}
+__device__ __forceinline__ void st8(bf* p, const V8& r) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t lo = __builtin_bit_cast(uint16_t, f2b(r.v[2 * i]));
+    const uint32_t hi = __builtin_bit_cast(uint16_t, f2b(r.v[2 * i + 1]));
+    w[i] = lo | (hi << 16);
+  }
+  *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // average pool 2x2: out (H/2 x W/2) from in (H x W), C channels
 __global__ void k_pool(const bf* __restrict__ in, int in_s, int in_o, bf* __restrict__ out, int out_s, int out_o,
                        int C, int B, int H, int Wd) {
-  const int h = H / 2, w = Wd / 2;
-  GRID_STRIDE(i, (int64_t)B * h * w * C) {
-    const int c = i % C;
-    const int64_t q = i / C;
+  const int h = H / 2, w = Wd / 2, G = C / 8;
+  GRID_STRIDE(i, (int64_t)B * h * w * G) {
+    const int c = (int)(i % G) * 8;
+    const int64_t q = i / G;
     const int x = q % w, y = (q / w) % h, b = q / ((int64_t)w * h);
-    float s = 0.f;
+    V8 s;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s.v[e] = 0.f;
     for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx)
-        s += b2f(in[((int64_t)(b * H + 2 * y + dy) * Wd + 2 * x + dx) * in_s + in_o + c]);
-    out[((int64_t)(b * h + y) * w + x) * out_s + out_o + c] = f2b(0.25f * s);
+      for (int dx = 0; dx < 2; ++dx) {
+        const V8 t = ld8(in + ((int64_t)(b * H + 2 * y + dy) * Wd + 2 * x + dx) * in_s + in_o + c);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s.v[e] += t.v[e];
+      }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s.v[e] *= 0.25f;
+    st8(out + ((int64_t)(b * h + y) * w + x) * out_s + out_o + c, s);
   }
 }
 
 // pool backward, accumulated: din(2y+dy, 2x+dx) += dout(y, x) / 4
 __global__ void k_pool_bwd_acc(const bf* __restrict__ dout, int d_s, int d_o, bf* __restrict__ din, int i_s, int i_o,
                                int C, int B, int H, int Wd) {
-  GRID_STRIDE(i, (int64_t)B * H * Wd * C) {
-    const int c = i % C;
-    const int64_t q = i / C;
+  const int G = C / 8;
+  GRID_STRIDE(i, (int64_t)B * H * Wd * G) {
+    const int c = (int)(i % G) * 8;
+    const int64_t q = i / G;
     const int x = q % Wd, y = (q / Wd) % H, b = q / ((int64_t)Wd * H);
-    const float g = b2f(dout[((int64_t)(b * (H / 2) + y / 2) * (Wd / 2) + x / 2) * d_s + d_o + c]);
+    const V8 g = ld8(dout + ((int64_t)(b * (H / 2) + y / 2) * (Wd / 2) + x / 2) * d_s + d_o + c);
     bf* p = din + ((int64_t)(b * H + y) * Wd + x) * i_s + i_o + c;
-    *p = f2b(b2f(*p) + 0.25f * g);
+    V8 t = ld8(p);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t.v[e] += 0.25f * g.v[e];
+    st8(p, t);
   }
 }
 
 // nearest up-sampling x2: out (H x W) from in (H/2 x W/2)
 __global__ void k_up(const bf* __restrict__ in, int in_s, int in_o, bf* __restrict__ out, int out_s, int out_o, int C,
                      int B, int H, int Wd) {
-  GRID_STRIDE(i, (int64_t)B * H * Wd * C) {
-    const int c = i % C;
-    const int64_t q = i / C;
+  const int G = C / 8;
+  GRID_STRIDE(i, (int64_t)B * H * Wd * G) {
+    const int c = (int)(i % G) * 8;
+    const int64_t q = i / G;
     const int x = q % Wd, y = (q / Wd) % H, b = q / ((int64_t)Wd * H);
-    out[((int64_t)(b * H + y) * Wd + x) * out_s + out_o + c] =
-        in[((int64_t)(b * (H / 2) + y / 2) * (Wd / 2) + x / 2) * in_s + in_o + c];
+    *reinterpret_cast<uint4*>(out + ((int64_t)(b * H + y) * Wd + x) * out_s + out_o + c) =
+        *reinterpret_cast<const uint4*>(in + ((int64_t)(b * (H / 2) + y / 2) * (Wd / 2) + x / 2) * in_s + in_o + c);
   }
 }
 
@@ -291,39 +384,53 @@ __global__ void k_up(const bf* __restrict__ in, int in_s, int in_o, bf* __restri
 // ReLU' mask of the up-sampled activation's producer (mask view, may be NULL)
 __global__ void k_up_bwd(const bf* __restrict__ dout, int d_s, int d_o, bf* __restrict__ din, int i_s, int i_o,
                          const bf* __restrict__ mask, int m_s, int m_o, int C, int B, int H, int Wd) {
-  const int h = H / 2, w = Wd / 2;
-  GRID_STRIDE(i, (int64_t)B * h * w * C) {
-    const int c = i % C;
-    const int64_t q = i / C;
+  const int h = H / 2, w = Wd / 2, G = C / 8;
+  GRID_STRIDE(i, (int64_t)B * h * w * G) {
+    const int c = (int)(i % G) * 8;
+    const int64_t q = i / G;
     const int x = q % w, y = (q / w) % h, b = q / ((int64_t)w * h);
-    float s = 0.f;
+    V8 s;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s.v[e] = 0.f;
     for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx)
-        s += b2f(dout[((int64_t)(b * H + 2 * y + dy) * Wd + 2 * x + dx) * d_s + d_o + c]);
+      for (int dx = 0; dx < 2; ++dx) {
+        const V8 t = ld8(dout + ((int64_t)(b * H + 2 * y + dy) * Wd + 2 * x + dx) * d_s + d_o + c);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s.v[e] += t.v[e];
+      }
     const int64_t pix = (int64_t)(b * h + y) * w + x;
-    if (mask && !(b2f(mask[pix * m_s + m_o + c]) > 0.f)) s = 0.f;
-    din[pix * i_s + i_o + c] = f2b(s);
+    if (mask) {
+      const V8 m = ld8(mask + pix * m_s + m_o + c);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s.v[e] = (m.v[e] > 0.f) ? s.v[e] : 0.f;
+    }
+    st8(din + pix * i_s + i_o + c, s);
   }
 }
 
 // g *= (act > 0) in place
 __global__ void k_relu_mask(bf* __restrict__ g, int g_s, int g_o, const bf* __restrict__ act, int a_s, int a_o, int C,
                             int64_t npix) {
-  GRID_STRIDE(i, npix * C) {
-    const int c = i % C;
-    const int64_t p = i / C;
-    if (!(b2f(act[p * a_s + a_o + c]) > 0.f)) g[p * g_s + g_o + c] = f2b(0.f);
+  const int G = C / 8;
+  GRID_STRIDE(i, npix * G) {
+    const int c = (int)(i % G) * 8;
+    const int64_t p = i / G;
+    bf* gp = g + p * g_s + g_o + c;
+    V8 t = ld8(gp);
+    const V8 m = ld8(act + p * a_s + a_o + c);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t.v[e] = (m.v[e] > 0.f) ? t.v[e] : 0.f;
+    st8(gp, t);
   }
 }
 
-// input: channel 0 = r * inv_scale[b], channels 1..C-1 = 0
+// input: channel 0 = r * inv_scale[b], channels 1..7 = 0 (C == 8)
 __global__ void k_pack_input(const float* __restrict__ r, const float* __restrict__ inv_scale, bf* __restrict__ out,
                              int C, int64_t npix_img, int B) {
-  GRID_STRIDE(i, npix_img * B * C) {
-    const int c = i % C;
-    const int64_t p = i / C;
+  GRID_STRIDE(p, npix_img * B) {
     const int b = (int)(p / npix_img);
-    out[i] = f2b(c == 0 ? r[p] * inv_scale[b] : 0.f);
+    const uint32_t lo = __builtin_bit_cast(uint16_t, f2b(r[p] * inv_scale[b]));
+    *reinterpret_cast<uint4*>(out + p * C) = make_uint4(lo, 0u, 0u, 0u);
   }
 }
 
@@ -410,7 +517,7 @@ hipError_t conv(int cin, int cout, const bf* in, int in_s, int in_o, const bf* W
                 bf* out_b, float* out_f, int out_s, int out_o, int cstore, const bf* mask, int mask_s, int mask_o,
                 int B, int H, int Wd, hipStream_t st) {
   if (Wd % 64) return hipErrorInvalidValue;
-  const unsigned grid = (unsigned)((int64_t)B * H * (Wd / 64));
+  const unsigned grid = (unsigned)((int64_t)B * ((H + CONV_RB - 1) / CONV_RB) * (Wd / 64));
 #define X(CI, CO)                                                                                              \
   if (cin == CI && cout == CO) {                                                                               \
     hipLaunchKernelGGL((k_conv3x3<CI, CO>), dim3(grid), dim3(256), 0, st, in, in_s, in_o, W, bias, relu, out_b, \
@@ -454,35 +561,36 @@ hipError_t bias_grad(const bf* dout, int d_s, int d_o, int cout, int64_t npix, f
 }
 hipError_t pool(const bf* in, int in_s, int in_o, bf* out, int out_s, int out_o, int C, int B, int H, int Wd,
                 hipStream_t st) {
-  hipLaunchKernelGGL(k_pool, dim3(nb((int64_t)B * (H / 2) * (Wd / 2) * C)), dim3(256), 0, st, in, in_s, in_o, out,
+  hipLaunchKernelGGL(k_pool, dim3(nb((int64_t)B * (H / 2) * (Wd / 2) * (C / 8))), dim3(256), 0, st, in, in_s, in_o, out,
                      out_s, out_o, C, B, H, Wd);
   return hipGetLastError();
 }
 hipError_t pool_bwd_acc(const bf* dout, int d_s, int d_o, bf* din, int i_s, int i_o, int C, int B, int H, int Wd,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_pool_bwd_acc, dim3(nb((int64_t)B * H * Wd * C)), dim3(256), 0, st, dout, d_s, d_o, din, i_s,
+  hipLaunchKernelGGL(k_pool_bwd_acc, dim3(nb((int64_t)B * H * Wd * (C / 8))), dim3(256), 0, st, dout, d_s, d_o, din, i_s,
                      i_o, C, B, H, Wd);
   return hipGetLastError();
 }
 hipError_t up(const bf* in, int in_s, int in_o, bf* out, int out_s, int out_o, int C, int B, int H, int Wd,
               hipStream_t st) {
-  hipLaunchKernelGGL(k_up, dim3(nb((int64_t)B * H * Wd * C)), dim3(256), 0, st, in, in_s, in_o, out, out_s, out_o, C,
+  hipLaunchKernelGGL(k_up, dim3(nb((int64_t)B * H * Wd * (C / 8))), dim3(256), 0, st, in, in_s, in_o, out, out_s, out_o, C,
                      B, H, Wd);
   return hipGetLastError();
 }
 hipError_t up_bwd(const bf* dout, int d_s, int d_o, bf* din, int i_s, int i_o, const bf* mask, int m_s, int m_o, int C,
                   int B, int H, int Wd, hipStream_t st) {
-  hipLaunchKernelGGL(k_up_bwd, dim3(nb((int64_t)B * (H / 2) * (Wd / 2) * C)), dim3(256), 0, st, dout, d_s, d_o, din,
+  hipLaunchKernelGGL(k_up_bwd, dim3(nb((int64_t)B * (H / 2) * (Wd / 2) * (C / 8))), dim3(256), 0, st, dout, d_s, d_o, din,
                      i_s, i_o, mask, m_s, m_o, C, B, H, Wd);
   return hipGetLastError();
 }
 hipError_t relu_mask(bf* g, int g_s, int g_o, const bf* act, int a_s, int a_o, int C, int64_t npix, hipStream_t st) {
-  hipLaunchKernelGGL(k_relu_mask, dim3(nb(npix * C)), dim3(256), 0, st, g, g_s, g_o, act, a_s, a_o, C, npix);
+  hipLaunchKernelGGL(k_relu_mask, dim3(nb(npix * (C / 8))), dim3(256), 0, st, g, g_s, g_o, act, a_s, a_o, C, npix);
   return hipGetLastError();
 }
 hipError_t pack_input(const float* r, const float* inv_scale, bf* out, int C, int64_t npix_img, int B,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_input, dim3(nb(npix_img * B * C)), dim3(256), 0, st, r, inv_scale, out, C, npix_img, B);
+  if (C != 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack_input, dim3(nb(npix_img * B)), dim3(256), 0, st, r, inv_scale, out, C, npix_img, B);
   return hipGetLastError();
 }
 hipError_t unpack_output(const float* net_out, int s, float* z, const float* scale, int64_t npix_img, int B,
