@@ -55,13 +55,18 @@ __device__ __forceinline__ bf f2b(float v) { return __float2bfloat16(v); }
 // in: pixel stride in_s, channel offset in_o; out likewise (bf16 or fp32);
 // mask (optional, bf16 view): the result is zeroed where mask <= 0 (ReLU'
 // of the layer that produced this layer's input, for the data gradient).
+// With in2 set, the input is a concatenation read in place: channels
+// [0, cup) are `in` at half resolution, nearest up-sampled (pixel (y, x)
+// reads (y / 2, x / 2) of an H/2 x W/2 image), and [cup, CIN) are in2
+// (stride in2_s, offset in2_o) at full resolution.
 constexpr int CONV_RB = 16;
 
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256)
 k_conv3x3(const bf* __restrict__ in, int in_s, int in_o, const bf* __restrict__ W, const float* __restrict__ bias,
           int relu, bf* __restrict__ out_b, float* __restrict__ out_f, int out_s, int out_o, int cstore,
-          const bf* __restrict__ mask, int mask_s, int mask_o, int H, int Wd) {
+          const bf* __restrict__ mask, int mask_s, int mask_o, int H, int Wd, const bf* __restrict__ in2,
+          int in2_s, int in2_o, int cup) {
   constexpr int K = 9 * CIN;
   constexpr int KPAD = (K + 31) / 32 * 32;
   constexpr int KS = KPAD / 32;
@@ -102,8 +107,13 @@ k_conv3x3(const bf* __restrict__ in, int in_s, int in_o, const bf* __restrict__ 
       const int c = tid + 256 * q;
       const int px = c / CH, c8 = c - px * CH, xx = x0 + px - 1;
       R[q] = make_uint4(0, 0, 0, 0);
-      if (c < 66 * CH && yy >= 0 && yy < H && xx >= 0 && xx < Wd)
-        R[q] = *reinterpret_cast<const uint4*>(in + ((int64_t)(b * H + yy) * Wd + xx) * in_s + in_o + 8 * c8);
+      if (c < 66 * CH && yy >= 0 && yy < H && xx >= 0 && xx < Wd) {
+        const bf* src;
+        if (!in2) src = in + ((int64_t)(b * H + yy) * Wd + xx) * in_s + in_o + 8 * c8;
+        else if (8 * c8 < cup) src = in + ((int64_t)(b * (H / 2) + yy / 2) * (Wd / 2) + xx / 2) * in_s + in_o + 8 * c8;
+        else src = in2 + ((int64_t)(b * H + yy) * Wd + xx) * in2_s + in2_o + 8 * c8 - cup;
+        R[q] = *reinterpret_cast<const uint4*>(src);
+      }
     }
   };
   auto store_row = [&](int yy) {
@@ -152,21 +162,46 @@ k_conv3x3(const bf* __restrict__ in, int in_s, int in_o, const bf* __restrict__ 
     for (int t = 0; t < NPT; ++t)
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt) asm volatile("" : "+a"(acc[t][mt]));
+    // a lane holds 4 consecutive output channels of one pixel: written (and
+    // masked) 8 bytes at a time when all four are stored
 #pragma unroll
     for (int t = 0; t < NPT; ++t) {
       const int x = x0 + 16 * (wp * NPT + t) + j;
       const int64_t pix = (int64_t)(b * H + y) * Wd + x;
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt) {
+        const int co0 = 16 * (wm * MTW + mt) + 4 * kg;
+        float v[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int co = 16 * (wm * MTW + mt) + 4 * kg + e;
-          if (co >= cstore) continue;
-          float v = acc[t][mt][e] + (bias ? bias[co] : 0.f);
-          if (relu) v = fmaxf(v, 0.f);
-          if (mask) v = (b2f(mask[pix * mask_s + mask_o + co]) > 0.f) ? v : 0.f;
-          if (out_f) out_f[pix * out_s + out_o + co] = v;
-          else out_b[pix * out_s + out_o + co] = f2b(v);
+          v[e] = acc[t][mt][e] + ((bias && co0 + e < cstore) ? bias[co0 + e] : 0.f);  // bias has cstore entries
+          if (relu) v[e] = fmaxf(v[e], 0.f);
+        }
+        if (co0 + 3 < cstore && !out_f) {
+          if (mask) {
+            const uint2 m = *reinterpret_cast<const uint2*>(mask + pix * mask_s + mask_o + co0);
+            const uint32_t mw[2] = {m.x, m.y};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const uint32_t bits = (e & 1) ? (mw[e >> 1] & 0xffff0000u) : (mw[e >> 1] << 16);
+              v[e] = (__uint_as_float(bits) > 0.f) ? v[e] : 0.f;
+            }
+          }
+          const uint32_t w0 = (uint32_t)__builtin_bit_cast(uint16_t, f2b(v[0])) |
+                              ((uint32_t)__builtin_bit_cast(uint16_t, f2b(v[1])) << 16);
+          const uint32_t w1 = (uint32_t)__builtin_bit_cast(uint16_t, f2b(v[2])) |
+                              ((uint32_t)__builtin_bit_cast(uint16_t, f2b(v[3])) << 16);
+          *reinterpret_cast<uint2*>(out_b + pix * out_s + out_o + co0) = make_uint2(w0, w1);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int co = co0 + e;
+            if (co >= cstore) continue;
+            float u = v[e];
+            if (mask) u = (b2f(mask[pix * mask_s + mask_o + co]) > 0.f) ? u : 0.f;
+            if (out_f) out_f[pix * out_s + out_o + co] = u;
+            else out_b[pix * out_s + out_o + co] = f2b(u);
+          }
         }
       }
     }
@@ -515,13 +550,13 @@ static inline unsigned nb(int64_t n) { return (unsigned)std::min<int64_t>((n + 2
 
 hipError_t conv(int cin, int cout, const bf* in, int in_s, int in_o, const bf* W, const float* bias, int relu,
                 bf* out_b, float* out_f, int out_s, int out_o, int cstore, const bf* mask, int mask_s, int mask_o,
-                int B, int H, int Wd, hipStream_t st) {
-  if (Wd % 64) return hipErrorInvalidValue;
+                int B, int H, int Wd, hipStream_t st, const bf* in2, int in2_s, int in2_o, int cup) {
+  if (Wd % 64 || (in2 && (cup % 8 || cup <= 0 || cup >= cin || H % 2))) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((int64_t)B * ((H + CONV_RB - 1) / CONV_RB) * (Wd / 64));
 #define X(CI, CO)                                                                                              \
   if (cin == CI && cout == CO) {                                                                               \
     hipLaunchKernelGGL((k_conv3x3<CI, CO>), dim3(grid), dim3(256), 0, st, in, in_s, in_o, W, bias, relu, out_b, \
-                       out_f, out_s, out_o, cstore, mask, mask_s, mask_o, H, Wd);                              \
+                       out_f, out_s, out_o, cstore, mask, mask_s, mask_o, H, Wd, in2, in2_s, in2_o, cup);      \
     return hipGetLastError();                                                                                  \
   }
   CONV_CASES(X)
