@@ -17,7 +17,8 @@ typedef __hip_bfloat16 bf;
 hipError_t conv(int cin, int cout, const bf* in, int in_s, int in_o, const bf* W, const float* bias, int relu,
                 bf* out_b, float* out_f, int out_s, int out_o, int cstore, const bf* mask, int mask_s, int mask_o,
                 int B, int H, int Wd, hipStream_t st, const bf* in2 = nullptr, int in2_s = 0, int in2_o = 0,
-                int cup = 0);
+                int cup = 0, const float* rin = nullptr, const float* rscale = nullptr,
+                const float* oscale = nullptr);
 int wgrad_groups(int cin, int cout);
 hipError_t wgrad(int cin, int cout, const bf* in, int in_s, int in_o, const bf* dout, int d_s, int d_o,
                  float* partial, int B, int H, int Wd, int R, hipStream_t st);

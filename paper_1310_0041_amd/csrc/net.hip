@@ -61,12 +61,16 @@ __device__ __forceinline__ bf f2b(float v) { return __float2bfloat16(v); }
 // (stride in2_s, offset in2_o) at full resolution.
 constexpr int CONV_RB = 16;
 
-template <int CIN, int COUT>
+template <int CIN, int COUT, bool RIN>
 __global__ void __launch_bounds__(256)
 k_conv3x3(const bf* __restrict__ in, int in_s, int in_o, const bf* __restrict__ W, const float* __restrict__ bias,
           int relu, bf* __restrict__ out_b, float* __restrict__ out_f, int out_s, int out_o, int cstore,
           const bf* __restrict__ mask, int mask_s, int mask_o, int H, int Wd, const bf* __restrict__ in2,
-          int in2_s, int in2_o, int cup) {
+          int in2_s, int in2_o, int cup, const float* __restrict__ rin, const float* __restrict__ rscale,
+          const float* __restrict__ oscale) {
+  // rin (CIN == 8): the input is the FP32 residual image itself, channel 0 =
+  // rin * rscale[image], channels 1..7 = 0.  oscale (FP32 output): the stored
+  // value is multiplied by oscale[image].
   constexpr int K = 9 * CIN;
   constexpr int KPAD = (K + 31) / 32 * 32;
   constexpr int KS = KPAD / 32;
@@ -107,7 +111,12 @@ k_conv3x3(const bf* __restrict__ in, int in_s, int in_o, const bf* __restrict__ 
       const int c = tid + 256 * q;
       const int px = c / CH, c8 = c - px * CH, xx = x0 + px - 1;
       R[q] = make_uint4(0, 0, 0, 0);
-      if (c < 66 * CH && yy >= 0 && yy < H && xx >= 0 && xx < Wd) {
+      if constexpr (RIN) {  // CH == 1: one chunk per pixel
+        if (c < 66 && yy >= 0 && yy < H && xx >= 0 && xx < Wd) {
+          const float v = rin[(int64_t)(b * H + yy) * Wd + xx] * rscale[b];
+          R[q].x = (uint32_t)__builtin_bit_cast(uint16_t, f2b(v));
+        }
+      } else if (c < 66 * CH && yy >= 0 && yy < H && xx >= 0 && xx < Wd) {
         const bf* src;
         if (!in2) src = in + ((int64_t)(b * H + yy) * Wd + xx) * in_s + in_o + 8 * c8;
         else if (8 * c8 < cup) src = in + ((int64_t)(b * (H / 2) + yy / 2) * (Wd / 2) + xx / 2) * in_s + in_o + 8 * c8;
@@ -199,7 +208,7 @@ k_conv3x3(const bf* __restrict__ in, int in_s, int in_o, const bf* __restrict__ 
             if (co >= cstore) continue;
             float u = v[e];
             if (mask) u = (b2f(mask[pix * mask_s + mask_o + co]) > 0.f) ? u : 0.f;
-            if (out_f) out_f[pix * out_s + out_o + co] = u;
+            if (out_f) out_f[pix * out_s + out_o + co] = oscale ? u * oscale[b] : u;
             else out_b[pix * out_s + out_o + co] = f2b(u);
           }
         }
@@ -550,13 +559,23 @@ static inline unsigned nb(int64_t n) { return (unsigned)std::min<int64_t>((n + 2
 
 hipError_t conv(int cin, int cout, const bf* in, int in_s, int in_o, const bf* W, const float* bias, int relu,
                 bf* out_b, float* out_f, int out_s, int out_o, int cstore, const bf* mask, int mask_s, int mask_o,
-                int B, int H, int Wd, hipStream_t st, const bf* in2, int in2_s, int in2_o, int cup) {
-  if (Wd % 64 || (in2 && (cup % 8 || cup <= 0 || cup >= cin || H % 2))) return hipErrorInvalidValue;
+                int B, int H, int Wd, hipStream_t st, const bf* in2, int in2_s, int in2_o, int cup,
+                const float* rin, const float* rscale, const float* oscale) {
+  if (Wd % 64 || (in2 && (cup % 8 || cup <= 0 || cup >= cin || H % 2)) || (rin && (cin != 8 || !rscale)))
+    return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((int64_t)B * ((H + CONV_RB - 1) / CONV_RB) * (Wd / 64));
+  if (rin) {
+    if (cin != 8 || cout != 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_conv3x3<8, 16, true>), dim3(grid), dim3(256), 0, st, in, in_s, in_o, W, bias, relu, out_b,
+                       out_f, out_s, out_o, cstore, mask, mask_s, mask_o, H, Wd, in2, in2_s, in2_o, cup, rin, rscale,
+                       oscale);
+    return hipGetLastError();
+  }
 #define X(CI, CO)                                                                                              \
   if (cin == CI && cout == CO) {                                                                               \
-    hipLaunchKernelGGL((k_conv3x3<CI, CO>), dim3(grid), dim3(256), 0, st, in, in_s, in_o, W, bias, relu, out_b, \
-                       out_f, out_s, out_o, cstore, mask, mask_s, mask_o, H, Wd, in2, in2_s, in2_o, cup);      \
+    hipLaunchKernelGGL((k_conv3x3<CI, CO, false>), dim3(grid), dim3(256), 0, st, in, in_s, in_o, W, bias, relu, \
+                       out_b, out_f, out_s, out_o, cstore, mask, mask_s, mask_o, H, Wd, in2, in2_s, in2_o, cup,  \
+                       rin, rscale, oscale);                                                                   \
     return hipGetLastError();                                                                                  \
   }
   CONV_CASES(X)

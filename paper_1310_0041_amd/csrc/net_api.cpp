@@ -176,7 +176,8 @@ using namespace gd::net;
 int wgrad_rows(int B, int h) { return std::max(1, (B * h + 127) / 128); }
 
 void conv_fwd(gd_net& N, int l, const bf* in, int in_s, int in_o, bf* out, int out_s, int out_o, int h, int w,
-              hipStream_t st, float* out_f = nullptr, const bf* in2 = nullptr, int in2_s = 0, int cup = 0) {
+              hipStream_t st, float* out_f = nullptr, const bf* in2 = nullptr, int in2_s = 0, int cup = 0,
+              const float* rin = nullptr, const float* rscale = nullptr, const float* oscale = nullptr) {
   const LayerSpec& L = kLayers[l];
   const float* bias = N.master.as<float>() + N.boff[l];
   if (N.timing) {
@@ -193,7 +194,7 @@ void conv_fwd(gd_net& N, int l, const bf* in, int in_s, int in_o, bf* out, int o
     NT_TRY(hipEventRecord(N.ev[N.ev_used].first, st));
   }
   NT_TRY(conv(L.cinp, L.coutp, in, in_s, in_o, N.wpk[l].as<bf>(), bias, l != 8, out, out_f, out_s, out_o,
-              L.cout, nullptr, 0, 0, N.B, h, w, st, in2, in2_s, 0, cup));
+              L.cout, nullptr, 0, 0, N.B, h, w, st, in2, in2_s, 0, cup, rin, rscale, oscale));
   if (N.timing) NT_TRY(hipEventRecord(N.ev[N.ev_used++].second, st));
 }
 
@@ -229,16 +230,19 @@ void conv_dgrad(gd_net& N, int l, const bf* dout, int d_s, int d_o, bf* din, int
 // per-image RMS of r -> scale (s) and inverse (1/s) on the device
 void image_scale(gd_net& N, const float* r, hipStream_t st);
 
-void forward(gd_net& N, const float* r, hipStream_t st, bool train = true) {
+// train: the activations back-propagation needs are kept and the output
+// is the net's FP32 value; otherwise z = net * scale is written to z_out
+void forward(gd_net& N, const float* r, hipStream_t st, bool train = true, float* z_out = nullptr) {
   const int H = N.H, W = N.W, h1 = H / 2, w1 = W / 2, h2 = H / 4, w2 = W / 4;
   const int64_t npix = (int64_t)H * W;
   image_scale(N, r, st);
-  NT_TRY(pack_input(r, N.scale.as<float>() + N.B, N.X0.as<bf>(), 8, npix, N.B, st));
   if (!train) {
-    // forward only: the skip activations stay contiguous and the decoder
-    // convolutions read their concatenated inputs in place, up-sampling on
-    // the fly (nothing of the concatenation is written)
-    conv_fwd(N, 0, N.X0.as<bf>(), 8, 0, N.A1.as<bf>(), 16, 0, H, W, st);
+    // forward only: the first convolution reads the residual itself, the
+    // skip activations stay contiguous, the decoder convolutions read their
+    // concatenated inputs in place, up-sampling on the fly, and the last one
+    // writes z scaled back
+    conv_fwd(N, 0, nullptr, 8, 0, N.A1.as<bf>(), 16, 0, H, W, st, nullptr, nullptr, 0, 0, r,
+             N.scale.as<float>() + N.B);
     conv_fwd(N, 1, N.A1.as<bf>(), 16, 0, N.S1.as<bf>(), 16, 0, H, W, st);
     NT_TRY(pool(N.S1.as<bf>(), 16, 0, N.P1.as<bf>(), 16, 0, 16, N.B, H, W, st));
     conv_fwd(N, 2, N.P1.as<bf>(), 16, 0, N.A2.as<bf>(), 32, 0, h1, w1, st);
@@ -248,9 +252,11 @@ void forward(gd_net& N, const float* r, hipStream_t st, bool train = true) {
     conv_fwd(N, 5, N.A3.as<bf>(), 64, 0, N.A3b.as<bf>(), 64, 0, h2, w2, st);
     conv_fwd(N, 6, N.A3b.as<bf>(), 64, 0, N.A4.as<bf>(), 32, 0, h1, w1, st, nullptr, N.S2.as<bf>(), 32, 64);
     conv_fwd(N, 7, N.A4.as<bf>(), 32, 0, N.A5.as<bf>(), 16, 0, H, W, st, nullptr, N.S1.as<bf>(), 16, 32);
-    conv_fwd(N, 8, N.A5.as<bf>(), 16, 0, nullptr, 1, 0, H, W, st, N.Y.as<float>());
+    conv_fwd(N, 8, N.A5.as<bf>(), 16, 0, nullptr, 1, 0, H, W, st, z_out, nullptr, 0, 0, nullptr, nullptr,
+             N.scale.as<float>());
     return;
   }
+  NT_TRY(pack_input(r, N.scale.as<float>() + N.B, N.X0.as<bf>(), 8, npix, N.B, st));
   conv_fwd(N, 0, N.X0.as<bf>(), 8, 0, N.A1.as<bf>(), 16, 0, H, W, st);
   conv_fwd(N, 1, N.A1.as<bf>(), 16, 0, N.C1.as<bf>(), 48, 32, H, W, st);
   NT_TRY(pool(N.C1.as<bf>(), 48, 32, N.P1.as<bf>(), 16, 0, 16, N.B, H, W, st));
@@ -446,8 +452,7 @@ gd_status gd_net_forward(gd_net* n, const float* r, float* z, int64_t nx, int64_
     for (int64_t b0 = 0; b0 < batch; b0 += bc) {
       const int64_t nbat = std::min(bc, batch - b0);
       n->shape((int)nbat, (int)ny, (int)nx);
-      forward(*n, r + b0 * npix, st, false);
-      NT_TRY(unpack_output(n->Y.as<float>(), 1, z + b0 * npix, n->scale.as<float>(), npix, (int)nbat, st));
+      forward(*n, r + b0 * npix, st, false, z + b0 * npix);
     }
     NT_TRY(hipStreamSynchronize(st));
     n->harvest();
