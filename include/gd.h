@@ -75,6 +75,10 @@ typedef struct {
   int sweep_tile;       /* relaxation tile of 3-D grids: -1 automatic (the
                            autotuned or default choice), 0: 64x8, 1: 128x8,
                            2: 64x16, 3: 128x16.  Results do not depend on it. */
+  int use_graph;        /* 1 (default): the repeated part of each V-cycle is
+                           captured once into a HIP graph and replayed; 0:
+                           plain launches.  Same results either way; timing = 1
+                           uses plain launches. */
 } gd_solve_opts;
 
 /* Filled by the solve calls when the pointer is non-NULL. */

@@ -46,6 +46,7 @@ class SolveOpts(ctypes.Structure):
         ("timing", ctypes.c_int),
         ("fuse_prolong", ctypes.c_int),
         ("sweep_tile", ctypes.c_int),
+        ("use_graph", ctypes.c_int),
     ]
 
 

@@ -126,9 +126,30 @@ struct Hier {
   double* x64b = nullptr;    // its next value (the fused update writes here)
   std::vector<int64_t> cells;  // finest cells per grid
 
+  // Captured V-cycle segments (see CycleGraphs): two executables that map
+  // the level buffers' ping-pong state A -> B and B -> A.
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::pair<void*, void*>> from, to;  // (x, xt) of every level before / after
+  };
+  hipStream_t cap = nullptr;  // private capture stream (default priority)
+  std::map<std::string, std::vector<Graph>> graphs;
+
   ~Hier() {
+    for (auto& kv : graphs)
+      for (auto& g : kv.second)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (cap) (void)hipStreamDestroy(cap);
     for (void* p : allocs) (void)hipFree(p);
     if (hpin) (void)hipHostFree(hpin);
+  }
+  std::vector<std::pair<void*, void*>> xstate() const {
+    std::vector<std::pair<void*, void*>> v;
+    for (const auto& L : lv) v.push_back({L.x, L.xt});
+    return v;
+  }
+  void set_xstate(const std::vector<std::pair<void*, void*>>& v) {
+    for (size_t i = 0; i < lv.size(); ++i) { lv[i].x = v[i].first; lv[i].xt = v[i].second; }
   }
   void* alloc(size_t bytes) {
     void* p = nullptr;
@@ -646,6 +667,57 @@ struct Cycler {
   }
 };
 
+// A repeated piece of the solve (e.g. "coarse-grid correction of level 0,
+// post-smoothing, next pre-smoothing, restriction with norm") captured once
+// into a HIP graph per buffer state and replayed: the launch sequence and
+// every argument are fixed by the hierarchy and the options, except which of
+// a level's two x buffers is current, so one graph is kept per state.  The
+// host's view of the buffers is set to the state the replayed graph leaves.
+// No memset or host synchronisation is inside a captured piece.
+struct CycleGraphs {
+  Hier& H;
+  std::string key;
+  CycleGraphs(Hier& h, const std::string& k) : H(h), key(k) {}
+  // run `piece` (which launches on the stream it is given) on st, through a graph
+  template <typename F>
+  void run(hipStream_t st, F&& piece) {
+    auto& gs = H.graphs[key];
+    const auto now = H.xstate();
+    for (auto& g : gs) {
+      if (g.from == now) {
+        HIP_TRY(hipGraphLaunch(g.exec, st));
+        H.set_xstate(g.to);
+        return;
+      }
+    }
+    if (!H.cap) HIP_TRY(hipStreamCreateWithFlags(&H.cap, hipStreamNonBlocking));
+    // order the capture stream after the caller's work, capture, then launch
+    HIP_TRY(hipStreamSynchronize(st));
+    Hier::Graph g;
+    g.from = now;
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(H.cap, hipStreamCaptureModeThreadLocal));
+    piece(H.cap);
+    HIP_TRY(hipStreamEndCapture(H.cap, &graph));
+    g.to = H.xstate();
+    hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(e);
+    H.set_xstate(g.from);
+    HIP_TRY(hipGraphLaunch(g.exec, st));
+    H.set_xstate(g.to);
+    gs.push_back(std::move(g));
+  }
+};
+
+static bool graphs_on(const gd_solve_opts& o) { return o.use_graph != 0 && o.timing == 0; }
+
+static std::string graph_key(const char* what, const gd_solve_opts& o) {
+  char k[128];
+  std::snprintf(k, sizeof k, "%s|%d|%d|%d|%d", what, o.pre_smooth, o.post_smooth, o.prolong, o.fuse_prolong);
+  return k;
+}
+
 static void read_dred(Hier& H, int ncomp, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(H.hpin, H.dred, H.ngrids * ncomp * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -727,17 +799,19 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
   double inner = 0.5;
   std::vector<double> rr(H.ngrids), best(H.ngrids, INFINITY);
   int stall = 0;
+  bool pre_done = false;  // the graph has already run this cycle's pre-smoothing and restriction
   for (;;) {
     if (single) {
       cy.smooth(0, 1);
       R.cycles++;
-    } else {
+    } else if (!pre_done) {
       cy.smooth(0, o.pre_smooth);
     }
     bool check_final = R.cycles >= o.max_cycles || single;
     bool stop_after = check_final;
     if (!single) {
-      cy.restrict_to(0, true);
+      if (!pre_done) cy.restrict_to(0, true);
+      pre_done = false;
       read_dred(H, 1, st);
       bool bad = false;
       bool gained = false;
@@ -761,8 +835,21 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
       if (R.converged || stop_after) break;
       inner *= 0.25;
     }
-    cy.correct(0);
-    R.cycles++;
+    if (graphs_on(o) && !single) {
+      // the correction of this cycle and the next cycle's pre-smoothing and
+      // restriction (with its norm), replayed as one graph
+      CycleGraphs(H, graph_key("plain", o)).run(st, [&](hipStream_t cs) {
+        Cycler c(H, cs, o);
+        c.correct(0);
+        c.smooth(0, o.pre_smooth);
+        c.restrict_to(0, true);
+      });
+      R.cycles++;
+      pre_done = true;
+    } else {
+      cy.correct(0);
+      R.cycles++;
+    }
   }
   cy.harvest();
   finish(H, P, 0, st);
@@ -770,9 +857,6 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
   return R;
 }
 
-// Mixed path: FP64 iterate x64; each refinement step solves A e = r / s for
-// the scaled FP64 residual (s = RMS of r per grid) with V-cycles in the
-// storage type, then x64 += s e.
 // Mixed path: FP64 iterate x64 (starting at I0), V-cycles in the storage
 // type on the residual scaled to unit RMS.  One fused pass per refinement
 // step applies the update x64 + s e (into the second FP64 buffer), computes
@@ -811,7 +895,10 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
     }
     HIP_TRY(hipMemsetAsync(H.lv[0].x, 0, H.lv[0].total * es, st));
     for (int c = 0; c < o.inner_cycles; ++c) {
-      cy.full(0);
+      if (graphs_on(o))
+        CycleGraphs(H, graph_key("full", o)).run(st, [&](hipStream_t cs) { Cycler(H, cs, o).full(0); });
+      else
+        cy.full(0);
       R.cycles++;
     }
     // x64' = x64 + scale e; r = b - A x64'; L0.b = r / rms(previous r)
@@ -890,6 +977,7 @@ void gd_default_opts(gd_solve_opts* o) {
   o->timing = 0;
   o->fuse_prolong = 0;
   o->sweep_tile = -1;
+  o->use_graph = 1;
 }
 
 const char* gd_last_error(void) { return t_err.c_str(); }
