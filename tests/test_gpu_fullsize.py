@@ -98,3 +98,76 @@ def test_stack4k_full_properties(gd, dt):
     del I0, I1
     gd.release_workspace()
     torch.cuda.empty_cache()
+
+
+def test_slices2048_full_sampled(gd):
+    """The 2048 uneven slices of the batched workload, solved as bench.py
+    solves them (one batched solve, FP32, 1e-6 per slice); sampled slices —
+    the smallest, the largest, the most and least screened and a few random
+    ones — against the FP64 DCT oracle of their own systems, and every
+    slice's residual against its own right-hand side."""
+    say("slices2048 full batch, sampled slices vs DCT")
+    meta = synth.make_slice_batch(device="cuda", dtype=torch.float32)
+    descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
+    I2, rep, per = gd.screened_poisson_slices(meta["I0"], meta["I1"], descs, rel_tol=1e-6, pre_smooth=1,
+                                              post_smooth=2)
+    print("batch", rep, flush=True)
+    assert max(p["rel_residual"] for p in per) <= 1e-6
+    w, h, a, off = meta["w"], meta["h"], meta["alpha"], meta["offset"]
+    area = w * h
+    rng = np.random.default_rng(5)
+    pick = {int(np.argmin(area)), int(np.argmax(area)), int(np.argmin(a)), int(np.argmax(a))}
+    pick |= set(int(i) for i in rng.choice(len(w), 4, replace=False))
+    for i in sorted(pick):
+        n = int(area[i])
+        s0 = meta["I0"][off[i]:off[i] + n].double().cpu().numpy().reshape(1, h[i], w[i])
+        s1 = meta["I1"][off[i]:off[i] + n].double().cpu().numpy().reshape(1, h[i], w[i])
+        got = I2[off[i]:off[i] + n].double().cpu().numpy().reshape(1, h[i], w[i])
+        ref = osv.sp_dct(s0, s1, float(np.float32(a[i])))
+        err = rel(got, ref)
+        say(f"slice {i} {w[i]}x{h[i]} alpha {a[i]:.4f}: rel err {err:.2e}")
+        # relative residual 1e-6 with the SP operator's condition (alpha >= 0.001)
+        assert err <= 2e-5
+
+
+def test_learned2k_full_sampled(gd):
+    """The learned workload's solve (2048x2048x64 per-slice SP, alpha 0.01)
+    by flexible CG with the V-cycle + net preconditioner, as bench.py runs it
+    after training: the true residual reaches 1e-6 and sampled slices agree
+    with the FP64 DCT oracle."""
+    say("learned2k full solve, sampled slices vs DCT")
+    n, nz, alpha = 2048, 64, 0.01
+    spec = synth.StackSpec(n, n, nz, (4.0, 40.0), True, 13100431)
+    I0 = synth.make_stack(spec, device="cuda", dtype=torch.float32)
+    I1 = torch.roll(I0, 1, 0).contiguous()
+    b = torch.zeros_like(I0, dtype=torch.float64)
+    b += alpha * I1.double()
+    for ax in (2, 1):
+        d = torch.diff(I0.double(), dim=ax)
+        m = I0.shape[ax]
+        b.narrow(ax, 0, m - 1).sub_(d)
+        b.narrow(ax, 1, m - 1).add_(d)
+    b = b.float().contiguous()
+    # a briefly trained net (the pairs of a 1024^2 stack, as bench.py)
+    tb = b[:16, :1024, :1024].contiguous()
+    ht = gd.Hierarchy(tuple(tb.shape), alpha, (1.0, 1.0, 0.0), torch.float32)
+    xs = torch.zeros_like(tb)
+    ht.vcycle(xs, tb, 30)
+    r, e = ht.error_pairs(tb, xs, 1)
+    ht.close()
+    net = gd.Net(seed=1)
+    for s in range(100):
+        i = (4 * s) % 16
+        net.train_step(r[i:i + 4].contiguous(), e[i:i + 4].contiguous(), lr=2e-3)
+    h = gd.Hierarchy(tuple(b.shape), alpha, (1.0, 1.0, 0.0), torch.float32)
+    x = torch.zeros_like(b)
+    rep = h.fcg(x, b, net=net, precond=2, rel_tol=1e-6, max_iter=100)
+    h.close()
+    net.close()
+    print("fcg", rep, flush=True)
+    assert rep["rel_residual"] <= 1e-6
+    for z in (0, 31, 63):
+        ref = osv.dct_solve(b[z:z + 1].double().cpu().numpy(), alpha, (1.0, 1.0, 0.0))
+        err = rel(x[z:z + 1].double().cpu().numpy(), ref)
+        say(f"slice {z}: rel err {err:.2e}")
+        assert err <= 2e-5
