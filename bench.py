@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-crop", default="32,192,192", help="nz,ny,nx of the oracle's crop")
     p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
+    p.add_argument("--fmg", type=int, default=None, help="1: full-multigrid start of the plain solves")
     p.add_argument("--inner-cycles", type=int, default=None,
                    help="V-cycles per FP64 refinement step (mixed storage; library default if omitted)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -268,6 +269,8 @@ def main():
     opts = dict(storage=sdt, fp64_refine=refine, rel_tol=TOL, pre_smooth=pre, post_smooth=post)
     if a.inner_cycles is not None:
         opts["inner_cycles"] = a.inner_cycles
+    if a.fmg is not None:
+        opts["fmg"] = a.fmg
 
     def step(timing):
         I1, r1 = gd.smooth_z(I0, BETA, out_dtype=out_dtype, timing=timing, **opts)

@@ -79,6 +79,10 @@ typedef struct {
                            captured once into a HIP graph and replayed; 0:
                            plain launches.  Same results either way; timing = 1
                            uses plain launches. */
+  int fmg;              /* 1: start the plain solve with a full-multigrid pass
+                           (right-hand side restricted to every level, coarse
+                           solutions interpolated up, one V-cycle per level);
+                           0 (default): start from zero */
 } gd_solve_opts;
 
 /* Filled by the solve calls when the pointer is non-NULL. */

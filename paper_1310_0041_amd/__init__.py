@@ -47,6 +47,7 @@ class SolveOpts(ctypes.Structure):
         ("fuse_prolong", ctypes.c_int),
         ("sweep_tile", ctypes.c_int),
         ("use_graph", ctypes.c_int),
+        ("fmg", ctypes.c_int),
     ]
 
 

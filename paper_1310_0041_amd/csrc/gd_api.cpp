@@ -637,6 +637,18 @@ struct Cycler {
     restrict_to(l, false);
     correct(l);
   }
+  // full multigrid start (x of level 0 is zero): the right-hand side
+  // restricted to every level, the coarsest solved, then level by level the
+  // coarse solution interpolated as the initial guess and one V-cycle run
+  void fmg() {
+    const int last = (int)H.lv.size() - 1;
+    for (int l = 0; l < last; ++l) restrict_to(l, false);  // x = 0: r = b
+    smooth(last, 1);
+    for (int l = last - 1; l >= 0; --l) {
+      HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), H.lv[l + 1].x, H.lv[l].x, pmode, H.lv[l].keep_x, st));
+      full(l);
+    }
+  }
   void full(int l) {  // one V-cycle from level l
     if (l == (int)H.lv.size() - 1) { smooth(l, 1); return; }
     smooth(l, pre);
@@ -800,6 +812,10 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
   std::vector<double> rr(H.ngrids), best(H.ngrids, INFINITY);
   int stall = 0;
   bool pre_done = false;  // the graph has already run this cycle's pre-smoothing and restriction
+  if (o.fmg && !single) {
+    cy.fmg();
+    R.cycles++;
+  }
   for (;;) {
     if (single) {
       cy.smooth(0, 1);
@@ -978,6 +994,7 @@ void gd_default_opts(gd_solve_opts* o) {
   o->fuse_prolong = 0;
   o->sweep_tile = -1;
   o->use_graph = 1;
+  o->fmg = 0;
 }
 
 const char* gd_last_error(void) { return t_err.c_str(); }

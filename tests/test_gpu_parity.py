@@ -365,3 +365,16 @@ def test_graph_replays_match_eager(gd, storage):
         torch.cuda.synchronize()
         assert r1["cycles"] == rep1["cycles"] and r2["cycles"] == rep2["cycles"]
         assert torch.equal(a1, ref1) and torch.equal(a2, ref2)
+
+
+def test_fmg_start(gd):
+    """The full-multigrid start reaches the same answer (DCT oracle)."""
+    import synth
+
+    spec = synth.StackSpec(96, 64, 16, (4.0, 40.0), True, 13100425)
+    I0 = synth.make_stack(spec).to(torch.float64)
+    I1, r1 = gd.smooth_z(I0.cuda(), (1.0, 1.0, 4.0), out_dtype=torch.float64, storage=gd.F64, rel_tol=1e-10,
+                         fmg=1)
+    assert r1["rel_residual"] <= 1e-10
+    ref = osv.ad_dct(I0.numpy(), (1.0, 1.0, 4.0))
+    assert np.linalg.norm(I1.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-8
