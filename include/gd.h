@@ -126,7 +126,9 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
  * nslices descriptors; slices must not overlap).  Every slice is iterated
  * until its own relative residual <= rel_tol.  per_slice (host array of
  * nslices, or NULL) receives each slice's final report; rep (or NULL) the
- * batch summary with rel_residual = the largest slice residual. */
+ * batch summary with rel_residual = the largest slice residual.  nslices = 0
+ * is an empty batch (GD_OK, nothing touched); nslices < 0, zero-sized
+ * slices or alpha <= 0 are GD_ERR_INVALID. */
 gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, gd_dtype t,
                                      const gd_slice_desc* slices, int64_t nslices,
                                      double beta_x, double beta_y,

@@ -1043,9 +1043,13 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, i
 gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, gd_dtype t, const gd_slice_desc* sl,
                                      int64_t n, double bx, double by, const gd_solve_opts* opts, gd_solve_report* rep,
                                      gd_solve_report* per, void* stream) {
+  if (n == 0) {  // an empty batch: nothing to solve
+    if (rep) std::memset(rep, 0, sizeof *rep);
+    return GD_OK;
+  }
   if (!I0 || !I1 || !I2 || !sl) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: null pointer");
   if (I2 == I0 || I2 == I1) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: output aliases input");
-  if (n <= 0 || n > (1 << 24)) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad slice count");
+  if (n < 0 || n > (1 << 24)) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad slice count");
   if (!valid_dtype(t)) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad dtype");
   if (!(bx >= 0.0) || !(by >= 0.0) || !std::isfinite(bx) || !std::isfinite(by))
     return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad beta");

@@ -36,8 +36,6 @@ hipError_t up_bwd(const bf* dout, int d_s, int d_o, bf* din, int i_s, int i_o, c
 hipError_t relu_mask(bf* g, int g_s, int g_o, const bf* act, int a_s, int a_o, int C, int64_t npix, hipStream_t st);
 hipError_t pack_input(const float* r, const float* inv_scale, bf* out, int C, int64_t npix_img, int B,
                       hipStream_t st);
-hipError_t unpack_output(const float* net_out, int s, float* z, const float* scale, int64_t npix_img, int B,
-                         hipStream_t st);
 hipError_t loss(const float* y, int y_s, const float* e, const float* inv_scale, bf* dy, int d_s, int C,
                 int64_t npix_img, int B, double* partial, int* nblocks, hipStream_t st);
 hipError_t adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps, float c1,

@@ -478,11 +478,6 @@ __global__ void k_pack_input(const float* __restrict__ r, const float* __restric
   }
 }
 
-// output: z[p] = net[p][0] * scale[b]
-__global__ void k_unpack_output(const float* __restrict__ net_out, int s, float* __restrict__ z,
-                                const float* __restrict__ scale, int64_t npix_img, int B) {
-  GRID_STRIDE(p, npix_img * B) z[p] = net_out[p * s] * scale[(int)(p / npix_img)];
-}
 
 // loss = mean (y - e * inv_scale)^2 over pixels; dy = 2 (y - t) / npix into a
 // bf16 gradient view (channel 0; the other channels are zeroed)
@@ -645,11 +640,6 @@ hipError_t pack_input(const float* r, const float* inv_scale, bf* out, int C, in
                       hipStream_t st) {
   if (C != 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pack_input, dim3(nb(npix_img * B)), dim3(256), 0, st, r, inv_scale, out, C, npix_img, B);
-  return hipGetLastError();
-}
-hipError_t unpack_output(const float* net_out, int s, float* z, const float* scale, int64_t npix_img, int B,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack_output, dim3(nb(npix_img * B)), dim3(256), 0, st, net_out, s, z, scale, npix_img, B);
   return hipGetLastError();
 }
 hipError_t loss(const float* y, int y_s, const float* e, const float* inv_scale, bf* dy, int d_s, int C,

@@ -84,6 +84,13 @@ def test_slice_argument_checks(lib):
                                           None) == gd.ERR_INVALID  # pitch < nx
     assert lib.gd_screened_poisson_slices(P(64), P(128), P(64), 1, d, 1, 1.0, 1.0, None, None, None,
                                           None) == gd.ERR_INVALID  # aliasing
+    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, -1, 1.0, 1.0, None, None, None,
+                                          None) == gd.ERR_INVALID  # negative count
+    rep = gd.Report()
+    rep.cycles = 7
+    assert lib.gd_screened_poisson_slices(None, None, None, 1, None, 0, 1.0, 1.0, None, ctypes.byref(rep),
+                                          None, None) == gd.OK  # an empty batch touches nothing
+    assert rep.cycles == 0
 
 
 def test_step_argument_checks(lib):
