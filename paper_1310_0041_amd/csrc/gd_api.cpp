@@ -81,11 +81,24 @@ struct GridSpec {  // finest-level grid in the kernels' view
 
 static int32_t pitch_of(int64_t nx) { return (int32_t)((nx + 3) & ~(int64_t)3); }
 
+// Block order of relaxation launches (0 plain, 1 a contiguous run of tiles
+// per XCD): GD_SWEEP_ORDER=0/1 fixes it, otherwise -1 here and the slice
+// autotuner times both (3-D grids keep the plain order).
+static int sweep_order_env() {
+  static const int v = [] {
+    const char* e = std::getenv("GD_SWEEP_ORDER");
+    const int o = e ? std::atoi(e) : -1;
+    return o == 0 || o == 1 ? o : -1;
+  }();
+  return v;
+}
+
 struct Tab {  // launch geometry of one kernel family on one level
   int64_t* d_b0 = nullptr;
   std::vector<int64_t> h_b0;
   int zlen = 1;
-  int tile = 0;  // relaxation tile variant (3-D grids)
+  int tile = 0;   // relaxation tile variant (3-D grids)
+  int order = 0;  // relaxation block order (see xcd_block)
   Geom geom(const GridDesc* d_grids, int ngrids, bool row) const {
     Geom g;
     g.grids = d_grids;
@@ -96,6 +109,7 @@ struct Tab {  // launch geometry of one kernel family on one level
     g.etx = row ? EWR_TX : EW_TX;
     g.row = row;
     g.tile = tile;
+    g.order = order;
     return g;
   }
 };
@@ -300,6 +314,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     const int64_t tgt = li == 0 ? sweep_target(L.row) : std::max<int64_t>(1, sweep_target(L.row) / 2);
     if (L.row) {
       build_tab(L.sw, L.h, SWR_TX, 1, false, tgt);
+      L.sw.order = sweep_order_env() == 1 ? 1 : 0;
       build_tab(L.ew, L.h, EWR_TX, 1, false, 8192);
       build_tab(L.rc, L.h, EWR_TX, 1, true, 8192);
       build_tab(L.rz, L.h, SWR_TX, 1, false, 4096, true);
@@ -357,6 +372,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
 // GD_SWEEP_BLOCKS setting, keeps the fixed choice.
 struct TuneChoice {
   int tile = 2;
+  int order = 0;
   int64_t target = 4096;
   double ms = 0.0;
   bool tuned = false;
@@ -386,7 +402,7 @@ static void set_sweep_tabs(Hier& H, int tile, int64_t target) {
   }
 }
 
-static void set_row_tabs(Hier& H, int64_t target) {
+static void set_row_tabs(Hier& H, int64_t target, int order) {
   for (size_t li = 0; li < H.lv.size(); ++li) {
     Level& L = H.lv[li];
     if (!L.row) continue;
@@ -394,13 +410,16 @@ static void set_row_tabs(Hier& H, int64_t target) {
     int64_t* d = L.sw.d_b0;
     build_tab(L.sw, L.h, SWR_TX, 1, false, tgt);
     L.sw.d_b0 = d;
+    L.sw.order = order;
     HIP_TRY(hipMemcpy(d, L.sw.h_b0.data(), L.sw.h_b0.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   }
 }
 
 // One-line grids (2-D slices): the row tile is fixed; the block target of the
-// finest level is timed at 2048 .. 16384 and the fastest kept, per set of
-// slice sizes (total cells and count; tile -1 in the cache key).
+// finest level (2048 .. 16384) and the block order (plain, or a contiguous
+// run per XCD: faster for some batches, slower for others) are timed and
+// the fastest kept, per set of slice sizes (total cells and count; tile -1
+// in the cache key).
 static void autotune_rows(Hier& H, hipStream_t st) {
   Level& L = H.lv[0];
   int64_t cells = 0;
@@ -411,7 +430,7 @@ static void autotune_rows(Hier& H, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
-      set_row_tabs(H, it->second.target);
+      set_row_tabs(H, it->second.target, it->second.order);
       return;
     }
   }
@@ -427,22 +446,27 @@ static void autotune_rows(Hier& H, hipStream_t st) {
   TuneChoice best;
   best.ms = 1e30;
   best.tile = -1;
-  for (int64_t target : {2048, 4096, 8192, 16384}) {
-    Tab t;
-    build_tab(t, L.h, SWR_TX, 1, false, target);
-    HIP_TRY(hipMemcpyAsync(d_b0, t.h_b0.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    t.d_b0 = d_b0;
-    const Geom geo = t.geom(L.d, H.ngrids, true);
-    HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));
-    HIP_TRY(hipEventRecord(e0, st));
-    for (int r = 0; r < 3; ++r) HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (ms / 3.0 < best.ms) {
-      best.ms = ms / 3.0;
-      best.target = target;
+  for (int order = 0; order < 2; ++order) {
+    if (sweep_order_env() >= 0 && order != sweep_order_env()) continue;
+    for (int64_t target : {2048, 4096, 8192, 16384}) {
+      Tab t;
+      build_tab(t, L.h, SWR_TX, 1, false, target);
+      HIP_TRY(hipMemcpyAsync(d_b0, t.h_b0.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, st));
+      t.d_b0 = d_b0;
+      t.order = order;
+      const Geom geo = t.geom(L.d, H.ngrids, true);
+      HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms / 3.0 < best.ms) {
+        best.ms = ms / 3.0;
+        best.target = target;
+        best.order = order;
+      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -453,7 +477,7 @@ static void autotune_rows(Hier& H, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = best;
   }
-  set_row_tabs(H, best.target);
+  set_row_tabs(H, best.target, best.order);
 }
 
 static void autotune(Hier& H, hipStream_t st) {

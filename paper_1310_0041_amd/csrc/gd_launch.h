@@ -32,6 +32,7 @@ struct Geom {
   bool row = false;  // relaxation: one-line (slice) tiles
   bool vec = true;   // every grid's pitch and offset are even (x pairs aligned)
   int tile = 0;      // relaxation tile variant of 3-D grids (SWEEP_TILE_TX / TY)
+  int order = 0;     // relaxation block order: 0 plain, 1 contiguous runs per XCD
 };
 
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,

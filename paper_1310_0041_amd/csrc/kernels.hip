@@ -12,6 +12,8 @@
 // All stencils are evaluated in difference form, sum_nb w (x_nb - x_c), which
 // keeps the rounding error proportional to the local variation instead of
 // the magnitude of x.
+#include <cstdlib>
+#include <type_traits>
 #include "gd_launch.h"
 
 namespace gd {
@@ -39,17 +41,25 @@ struct Tile {
 };
 
 // Logical block index.  Work-groups go to the 8 XCDs round-robin and each
-// XCD has its own L2; handing XCD x a contiguous run of tiles (so that
-// neighbouring halos share an L2) measured slower for these streaming
-// z-marches than the plain order, which is kept.
-__device__ __forceinline__ int64_t xcd_block() { return blockIdx.x; }
+// XCD has its own L2.  Order 1 hands XCD x a contiguous run of tiles, so
+// that the halos of neighbouring tiles are fetched into one L2 (used by the
+// relaxation of slice batches); order 0 is the plain order.
+__device__ __forceinline__ int64_t xcd_block(int order = 0) {
+  if (order != 1) return blockIdx.x;
+  // XCD x = b mod 8 takes the contiguous run [x q + min(x, r), ...) of
+  // logical blocks (q = n / 8, r = n mod 8): a bijection of [0, n)
+  const int64_t b = blockIdx.x, n = gridDim.x;
+  const int64_t q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
 
 // Decode blockIdx.x into (grid, tile, z-range) for tx x ty tiles over the
 // grid's own size (coarse = false) or its child's size (coarse = true).
 __device__ __forceinline__ Tile decode_tile(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0,
-                                            int ngrids, int zlen, int tx_, int ty_, bool coarse) {
+                                            int ngrids, int zlen, int tx_, int ty_, bool coarse,
+                                            int order = 0) {
   Tile t;
-  const int64_t bid = xcd_block();
+  const int64_t bid = xcd_block(order);
   t.bid = bid;
   t.g = find_grid(block0, ngrids, bid);
   const GridDesc& G = grids[t.g];
@@ -167,8 +177,13 @@ __device__ __forceinline__ void prolong_pair(const S* __restrict__ ec, const Gri
 //            written, plane p + 2 enters LDS | barrier
 // Recomputing the red ring makes every tile independent of its neighbours,
 // so blocks never exchange data and the sweep equals the sequential
-// definition exactly.  When e_coarse != NULL the up-sampled coarse
-// correction is added to x while it is loaded (fused prolongation).
+// definition exactly.  Every thread relaxes its red cell and a ring cell in
+// each plane (a thread without a ring cell relaxes a stand-in and writes it
+// to a slot of its own), so that the LDS reads of both issue together, and
+// the plane parity is a compile-time argument of the unrolled step: the
+// per-parity weights and inverse diagonals stay in registers.  When
+// e_coarse != NULL the up-sampled coarse correction is added to x while it
+// is loaded (fused prolongation).
 // TY == 1 is the row form for grids with ny == 1 (2-D slices).
 
 template <int TX, int TY>
@@ -241,11 +256,37 @@ struct WaveSplit {
   }
 };
 
+// Gauss-Seidel value of one cell in correction form, x + (b - A x) / d:
+// the residual is accumulated from neighbour differences (exact for close
+// values), which keeps the FP32 rounding floor low when x is much larger
+// than b (small alpha).  Neighbours are taken left, right, up, down, z-1,
+// z+1 with explicit fused multiply-adds, so that a ring cell and its owner
+// compute it alike.  inv == 0 (no diagonal) gives 0.
+template <typename C>
+__device__ __forceinline__ C fmac(C a, C b, C c) {
+  if constexpr (sizeof(C) == 8) return __builtin_fma(a, b, c);
+  else return __builtin_fmaf(a, b, c);
+}
+template <typename C, bool ROW>
+__device__ __forceinline__ C relax(C x, C b, C alpha, C wl, C nl, C wr, C nr, C wu, C nu, C wd, C nd, C wzm, C nzm,
+                                   C wzp, C nzp, C inv) {
+  C r = fmac(-alpha, x, b);
+  r = fmac(wl, nl - x, r);
+  r = fmac(wr, nr - x, r);
+  if (!ROW) {
+    r = fmac(wu, nu - x, r);
+    r = fmac(wd, nd - x, r);
+  }
+  r = fmac(wzm, nzm - x, r);
+  r = fmac(wzp, nzp - x, r);
+  return inv != (C)0 ? fmac(r, inv, x) : (C)0;
+}
+
 template <typename S, int TX, int TY, bool FP, bool VEC>
 __global__ void __launch_bounds__(TX * TY / 2)
 k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
            const S* __restrict__ xin, S* __restrict__ xout, const S* __restrict__ bin,
-           const S* __restrict__ ec, int pmode) {
+           const S* __restrict__ ec, int pmode, int order) {
   using C = typename Ty<S>::C;
   using SS = SweepShape<TX, TY>;
   constexpr int NT = SS::NT, YO = SS::YO, HX = SS::HX, HY = SS::HY, NHR = SS::NHR;
@@ -253,9 +294,11 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   constexpr bool ROW = SS::ROW;
   using Ring = WaveSplit<SS::NRING, NT>;
   static_assert(Ring::PER <= 64, "ring share per wave");
-  __shared__ C X[4 * PLANE];
+  // four planes, then one slot per thread that takes the masked writes of
+  // threads without a ring cell
+  __shared__ C X[4 * PLANE + NT];
 
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false, order);
   const GridDesc& G = grids[t.g];
   const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
@@ -276,7 +319,7 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   const C wU = (gy > 0) ? wy : (C)0, wD = (gy + 1 < ny) ? wy : (C)0;
   // per plane parity par = p & 1 the red cell of the pair is at position cp = (gy + par) & 1
   int offO[2], offY[2];
-  C wO[2], wP[2], wL[2], wR[2], invI[2], dxy[2];
+  C wO[2], wP[2], wL[2], wR[2], invI[2], invE[2];
   bool vR[2];
 #pragma unroll
   for (int par = 0; par < 2; ++par) {
@@ -291,10 +334,12 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
     // the same values
     wL[par] = cp ? wP[par] : wO[par];  // left neighbour: the pair partner when the cell is gx + 1
     wR[par] = cp ? wO[par] : wP[par];
-    dxy[par] = alpha + wL[par] + wR[par] + wU + wD;
+    const C dxy = alpha + wL[par] + wR[par] + wU + wD;
+    // diagonal inside the z-range and on its first or last plane
     const C wz1 = nz > 1 ? wz : (C)0;
-    const C di = (dxy[par] + wz1) + wz1;
+    const C di = (dxy + wz1) + wz1, de = dxy + wz1;
     invI[par] = di > (C)0 ? (C)1 / di : (C)0;
+    invE[par] = de > (C)0 ? (C)1 / de : (C)0;
   }
 
   // ---- halo cells of this thread (loaded every plane)
@@ -322,20 +367,27 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   const int rm = Ring::item(tid);
   int ro[2], rg[2];
   bool rv[2];
-  C rwl[2], rwr[2], rwu[2], rwd[2], rdxy[2];
+  C rwl[2], rwr[2], rwu[2], rwd[2], rinvI[2], rinvE[2];
 #pragma unroll
   for (int par = 0; par < 2; ++par) {
     int hy = 0, hx = 0;
     if (rm >= 0) ring_red_cell<TX, TY>(rm, x0, y0, par, hy, hx);
     const int cx = x0 - 2 + hx, cy = y0 - YO + hy;
     rv[par] = rm >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
-    ro[par] = hy * HX + hx;
+    // a thread without a ring cell relaxes its own cell's position as a
+    // stand-in (in-plane neighbours inside the LDS plane) and writes the
+    // result to its dummy slot
+    ro[par] = rm >= 0 ? hy * HX + hx : lo;
     rg[par] = rv[par] ? cy * px + cx : 0;
     rwl[par] = cx > 0 ? wx : (C)0;
     rwr[par] = cx < nx - 1 ? wx : (C)0;
     rwu[par] = cy > 0 ? wy : (C)0;
     rwd[par] = cy < ny - 1 ? wy : (C)0;
-    rdxy[par] = alpha + rwl[par] + rwr[par] + rwu[par] + rwd[par];
+    const C dxy = alpha + rwl[par] + rwr[par] + rwu[par] + rwd[par];
+    const C wz1 = nz > 1 ? wz : (C)0;
+    const C di = (dxy + wz1) + wz1, de = dxy + wz1;
+    rinvI[par] = di > (C)0 ? (C)1 / di : (C)0;
+    rinvE[par] = de > (C)0 ? (C)1 / de : (C)0;
   }
 
   // ---- plane loads: x pair + halo (registers), b pair, ring b.  Two planes
@@ -408,9 +460,6 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
     ld_raw(plane_ptr(bg, q) + rg[q & 1], r);
     return r;
   };
-  auto ring_bv = [&](const Raw<S>& r, int q) -> C {
-    return (q >= 0 && q < nz && rv[q & 1]) ? raw_c(r) : (C)0;
-  };
   // pair (in memory order) -> (red, black) of plane q
   auto split = [&](int q, C a, C b, C& r, C& k) {
     const bool cp = ((gy + q) & 1) != 0;
@@ -449,82 +498,49 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   // one plane step: red of plane p, black of plane p - 1, then plane p + 2
   // enters LDS and the loads of planes p + 4 (x), p + 3 (b), p + 2 (ring b)
   // go out into the slots just consumed
-  auto step = [&](int p, XSet& XS, Raw2<S>& BS, Raw<S>& RBS) {
+  auto step = [&](auto PC, int p, XSet& XS, Raw2<S>& BS, Raw<S>& RBS) {
+    constexpr int par = decltype(PC)::value;  // p & 1, fixed per unrolled step
     __syncthreads();
-    const int par = p & 1;
     if (p < nz) {
-      // ---- red cells of plane p
+      // ---- red cells of plane p: the pair's red cell and the ring cell,
+      // both computed by every thread (masked), so that their LDS reads
+      // issue together
       C* P = X + (p & 3) * PLANE;
+      const C* Pm = X + ((p - 1) & 3) * PLANE;
+      const C* Pp = X + ((p + 1) & 3) * PLANE;
       const C wzm = p > 0 ? wz : (C)0, wzp = p < nz - 1 ? wz : (C)0;
-      if (vR[par]) {
-        const C xc = R0;
-        C r = bR0 - alpha * xc;
-        {
-          const bool cp = ((gy + p) & 1) != 0;  // red cell on the pair's right
-          const C vo = P[offO[par]];
-          r += wL[par] * ((cp ? K0 : vo) - xc);  // left neighbour first
-          r += wR[par] * ((cp ? vo : K0) - xc);
-        }
-        if (!ROW) {
-          r += wU * (P[offY[par] - HX] - xc);
-          r += wD * (P[offY[par] + HX] - xc);
-        }
-        r += wzm * (Km1 - xc);
-        r += wzp * (Kp1 - xc);
-        C inv = invI[par];
-        if (p == 0 || p == nz - 1) {
-          const C d = dxy[par] + wzm + wzp;
-          inv = d > (C)0 ? (C)1 / d : (C)0;
-        }
-        const C nv = inv != (C)0 ? xc + r * inv : (C)0;
-        R0 = nv;
-        P[offY[par]] = nv;
-      }
-      if (rv[par]) {  // red cell of the 1-cell ring
-        const int o = ro[par];
-        const C xc = P[o];
-        C r = ring_bv(RBS, p) - alpha * xc;
-        r += rwl[par] * (P[o - 1] - xc);
-        r += rwr[par] * (P[o + 1] - xc);
-        if (!ROW) {
-          r += rwu[par] * (P[o - HX] - xc);
-          r += rwd[par] * (P[o + HX] - xc);
-        }
-        if (p > 0) r += wz * (X[((p - 1) & 3) * PLANE + o] - xc);
-        if (p < nz - 1) r += wz * (X[((p + 1) & 3) * PLANE + o] - xc);
-        const C d = (rdxy[par] + wzm) + wzp;
-        const C inv = d > (C)0 ? (C)1 / d : (C)0;
-        P[o] = inv != (C)0 ? xc + r * inv : (C)0;
-      }
+      const bool edge = p == 0 || p == nz - 1;
+      const bool cp = ((gy + p) & 1) != 0;  // red cell on the pair's right
+      const C vo = P[offO[par]];
+      const C up = ROW ? (C)0 : P[offY[par] - HX], dn = ROW ? (C)0 : P[offY[par] + HX];
+      const int o = ro[par];
+      const C rx = P[o], rl = P[o - 1], rr = P[o + 1];
+      const C ru = ROW ? (C)0 : P[o - HX], rd = ROW ? (C)0 : P[o + HX];
+      const C rzm = Pm[o], rzp = Pp[o];
+      const C nv = relax<C, ROW>(R0, bR0, alpha, wL[par], cp ? K0 : vo, wR[par], cp ? vo : K0, wU, up, wD, dn, wzm, Km1,
+                                 wzp, Kp1, edge ? invE[par] : invI[par]);
+      R0 = vR[par] ? nv : (C)0;
+      P[offY[par]] = R0;
+      const C rb = (p >= 0 && rv[par]) ? raw_c(RBS) : (C)0;
+      const C rn = relax<C, ROW>(rx, rb, alpha, rwl[par], rl, rwr[par], rr, rwu[par], ru, rwd[par], rd, wzm, rzm,
+                                 wzp, rzp, edge ? rinvE[par] : rinvI[par]);
+      *(rv[par] ? P + o : X + 4 * PLANE + tid) = rn;
     }
     __syncthreads();
     const int q = p - 1;
     if (q >= q0 && q < q1) {
       // ---- black cells of plane q = p - 1 (same position as the red cell of plane p)
-      if (vR[par]) {
-        const C* P = X + (q & 3) * PLANE;
-        const C wzm = q > 0 ? wz : (C)0, wzp = q < nz - 1 ? wz : (C)0;
-        const C xc = Km1;
-        C r = bKm1 - alpha * xc;
-        r += wP[par] * (Rm1 - xc);
-        r += wO[par] * (P[offO[par]] - xc);
-        if (!ROW) {
-          r += wU * (P[offY[par] - HX] - xc);
-          r += wD * (P[offY[par] + HX] - xc);
-        }
-        r += wzm * (Rm2 - xc);
-        r += wzp * (R0 - xc);
-        C inv = invI[par];
-        if (q == 0 || q == nz - 1) {
-          const C d = dxy[par] + wzm + wzp;
-          inv = d > (C)0 ? (C)1 / d : (C)0;
-        }
-        Km1 = inv != (C)0 ? xc + r * inv : (C)0;
-      }
-      if (vA) {
-        const bool cq = ((gy + q) & 1) != 0;  // red position of plane q
-        st2(xo + (int64_t)q * pl + own, VEC, vB, cq ? Km1 : Rm1, cq ? Rm1 : Km1);
-      }
+      const C* P = X + (q & 3) * PLANE;
+      const C wzm = q > 0 ? wz : (C)0, wzp = q < nz - 1 ? wz : (C)0;
+      const bool edge = q == 0 || q == nz - 1;
+      const bool cq = ((gy + q) & 1) != 0;  // red position of plane q
+      // the black cell sits on the pair's right when the red one is on its left
+      const C vo = P[offO[par]];
+      const C up = ROW ? (C)0 : P[offY[par] - HX], dn = ROW ? (C)0 : P[offY[par] + HX];
+      const C nv = relax<C, ROW>(Km1, bKm1, alpha, wL[par], cq ? vo : Rm1, wR[par], cq ? Rm1 : vo, wU, up, wD, dn, wzm,
+                                 Rm2, wzp, R0, edge ? invE[par] : invI[par]);
+      Km1 = vR[par] ? nv : (C)0;
+      if (vA) st2(xo + (int64_t)q * pl + own, VEC, vB, cq ? Km1 : Rm1, cq ? Rm1 : Km1);
     }
     stash(p + 2, XS);
     Rm2 = Rm1; Km2 = Km1; Rm1 = R0; Km1 = K0; R0 = Rp1; K0 = Kp1;
@@ -535,14 +551,24 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
     // the loop free of a branch around the loads)
     fetch_x(p + 4, XS);
     fetch_b(p + 3, BS);
-    RBS = ring_b(p + 2);
+    ld_raw(plane_ptr(bg, p + 2) + rg[par], RBS);  // ring b of plane p + 2 (same parity)
   };
+  using E0 = std::integral_constant<int, 0>;
+  using E1 = std::integral_constant<int, 1>;
   int p = pfirst;
-  for (; p + 1 <= plast; p += 2) {
-    step(p, S0, B1, RB0);
-    step(p + 1, S1, B0, RB1);
+  if ((pfirst & 1) == 0) {
+    for (; p + 1 <= plast; p += 2) {
+      step(E0{}, p, S0, B1, RB0);
+      step(E1{}, p + 1, S1, B0, RB1);
+    }
+    if (p <= plast) step(E0{}, p, S0, B1, RB0);
+  } else {
+    for (; p + 1 <= plast; p += 2) {
+      step(E1{}, p, S0, B1, RB0);
+      step(E0{}, p + 1, S1, B0, RB1);
+    }
+    if (p <= plast) step(E1{}, p, S0, B1, RB0);
   }
-  if (p <= plast) step(p, S0, B1, RB0);
 }
 
 // ------------------------------------------------ residual + restriction
@@ -1395,11 +1421,12 @@ static void sweep_launch3(const Geom& g, const void* xin, void* xout, const void
   if (g.row) {
     hipLaunchKernelGGL((k_rb_sweep<T, SWR_TX, 1, FP, VEC>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st,
                        g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec,
-                       pmode);
+                       pmode, g.order);
   } else {
 #define SWEEP_TILE(TX, TY)                                                                                     \
   hipLaunchKernelGGL((k_rb_sweep<T, TX, TY, FP, VEC>), dim3((unsigned)g.nblocks), dim3(TX * TY / 2), 0, st,    \
-                     g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec, pmode)
+                     g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec, pmode, \
+                     g.order)
     if (FP || g.tile == 0) {
       SWEEP_TILE(64, 8);
     } else if constexpr (!FP) {  // the fused prolongation exists for the 64 x 8 tile only
