@@ -171,10 +171,15 @@ __device__ __forceinline__ void prolong_pair(const S* __restrict__ ec, const Gri
 // cells of the same column, so each thread keeps its column of planes
 // p-2 .. p+2 in registers and only the in-plane neighbours go through LDS
 // (four planes, with a 2-cell halo ring loaded by the threads in turn).
-//   step p:  red cells of plane p (own pair and the 1-cell ring around the
-//            tile, from old black values) | barrier | black cells of plane
-//            p - 1 (from the new red values of planes p-2..p), plane p - 1
-//            written, plane p + 2 enters LDS | barrier
+//   step p:  barrier | red cells of plane p (own pair and the 1-cell ring
+//            around the tile, from old black values), written to plane p's
+//            LDS buffer | black cells of plane p - 1 (from the new red values
+//            of planes p-2..p: in-plane ones from plane p - 1's buffer,
+//            written in the previous step), plane p - 1 written to memory,
+//            plane p + 2 enters LDS (the buffer plane p - 2 used)
+// One barrier per plane suffices: within a step no buffer is both written
+// and read (red cells of plane p are written, only black cells of plane p
+// and planes p +- 1 are read; plane p - 1 is read; plane p + 2 is written).
 // Recomputing the red ring makes every tile independent of its neighbours,
 // so blocks never exchange data and the sweep equals the sequential
 // definition exactly.  Every thread relaxes its red cell and a ring cell in
@@ -526,7 +531,8 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
                                  wzp, rzp, edge ? rinvE[par] : rinvI[par]);
       *(rv[par] ? P + o : X + 4 * PLANE + tid) = rn;
     }
-    __syncthreads();
+    // no barrier here: the black cells of plane p - 1 read only plane
+    // p - 1's buffer, whose red cells were written in the previous step
     const int q = p - 1;
     if (q >= q0 && q < q1) {
       // ---- black cells of plane q = p - 1 (same position as the red cell of plane p)
