@@ -20,7 +20,9 @@
  *
  * Conventions (every entry point):
  *  - Volumes are contiguous [nz][ny][nx] arrays, x fastest, unless a slice
- *    descriptor gives an offset and row pitch.  Sizes are int64.
+ *    descriptor gives an offset and row pitch.  Sizes are int64; an x-y
+ *    plane (a slice row's pitch) may hold at most 2^28 cells (16384^2),
+ *    larger ones return GD_ERR_UNSUPPORTED.
  *  - Data pointers are DEVICE pointers owned by the caller; the library never
  *    frees them.  Outputs must not alias inputs.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Every call

@@ -983,6 +983,10 @@ struct StepBuf {
 static std::mutex g_step_mu;
 static std::map<int, StepBuf> g_step;
 
+// Kernels address a cell inside one x-y plane with a 32-bit offset (bytes,
+// up to 8 per value): planes are limited to 2^28 cells (16384^2).
+constexpr int64_t MAX_PLANE = (int64_t)1 << 28;
+
 static gd_status run_guarded(const std::function<gd_status()>& f) {
   try {
     return f();
@@ -1041,6 +1045,7 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, i
   if ((const void*)I0 == (const void*)I1) return fail(GD_ERR_INVALID, "gd_smooth_z: output aliases input");
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
     return fail(GD_ERR_INVALID, "gd_smooth_z: bad size");
+  if (nx * ny > MAX_PLANE) return fail(GD_ERR_UNSUPPORTED, "gd_smooth_z: x-y plane above 2^28 cells");
   if (!valid_dtype(in_t) || !valid_dtype(out_t)) return fail(GD_ERR_INVALID, "gd_smooth_z: bad dtype");
   if (!(bx >= 0.0) || !(by >= 0.0) || !(bz > 0.0) || !std::isfinite(bx) || !std::isfinite(by) || !std::isfinite(bz))
     return fail(GD_ERR_INVALID, "gd_smooth_z: need beta_x, beta_y >= 0 and beta_z > 0");
@@ -1083,6 +1088,8 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
     const gd_slice_desc& d = sl[i];
     if (d.nx <= 0 || d.ny <= 0 || d.pitch < d.nx || d.offset < 0 || !(d.alpha > 0.0) || !std::isfinite(d.alpha))
       return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad slice descriptor " + std::to_string(i));
+    if (d.pitch > MAX_PLANE)
+      return fail(GD_ERR_UNSUPPORTED, "gd_screened_poisson_slices: row pitch above 2^28 in slice " + std::to_string(i));
     // the slice's rows become the grid's z axis (one line per plane)
     GridSpec sp{d.nx, 1, d.ny, (double)d.alpha, bx, 0.0, by, d.offset, d.pitch, d.pitch};
     sp.zin = 1;
@@ -1171,6 +1178,7 @@ gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t 
   *h = nullptr;
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
     return fail(GD_ERR_INVALID, "gd_hierarchy_create: bad size");
+  if (nx * ny > MAX_PLANE) return fail(GD_ERR_UNSUPPORTED, "gd_hierarchy_create: x-y plane above 2^28 cells");
   if (!valid_dtype(s)) return fail(GD_ERR_INVALID, "gd_hierarchy_create: bad dtype");
   if (!(alpha >= 0.0) || !(bx >= 0.0) || !(by >= 0.0) || !(bz >= 0.0) || !std::isfinite(alpha) ||
       !std::isfinite(bx) || !std::isfinite(by) || !std::isfinite(bz) || (alpha == 0.0 && bx == 0.0 && by == 0.0 && bz == 0.0))
@@ -1391,6 +1399,7 @@ static gd_status one_grid(GridDesc& g, int64_t nx, int64_t ny, int64_t nz, int c
                           double wx, double wy, double wz) {
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
     return fail(GD_ERR_INVALID, "bad size");
+  if (nx * ny > MAX_PLANE) return fail(GD_ERR_UNSUPPORTED, "x-y plane above 2^28 cells");
   if ((cx != 1 && cx != 2) || (cy != 1 && cy != 2) || (cz != 1 && cz != 2))
     return fail(GD_ERR_INVALID, "coarsening factors must be 1 or 2");
   if (!(alpha >= 0.0) || !(wx >= 0.0) || !(wy >= 0.0) || !(wz >= 0.0))

@@ -320,7 +320,7 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   const bool rowok = gy < ny;
   const bool vA = rowok && gx < nx, vB = rowok && gx + 1 < nx;
   const int lo = (YO + tyl) * HX + 2 + 2 * pxl;  // LDS index of gx inside a plane
-  const int own = gy * px + gx;                 // element offset inside a plane (< 2^31)
+  const int own = gy * px + gx;                 // element offset inside a plane (< 2^28)
   const C wU = (gy > 0) ? wy : (C)0, wD = (gy + 1 < ny) ? wy : (C)0;
   // per plane parity par = p & 1 the red cell of the pair is at position cp = (gy + par) & 1
   int offO[2], offY[2];

@@ -93,6 +93,18 @@ def test_slice_argument_checks(lib):
     assert rep.cycles == 0
 
 
+def test_plane_size_limit(lib):
+    # an x-y plane above 2^28 cells is refused on the host, before any GPU call
+    h = ctypes.c_void_p()
+    assert lib.gd_hierarchy_create(ctypes.byref(h), 1 << 15, 1 << 14, 1, 0.1, 1.0, 1.0, 1.0, 1, None,
+                                   None) == gd.ERR_UNSUPPORTED
+    assert lib.gd_smooth_z(P(64), 1, P(128), 1, 1 << 15, 1 << 14, 2, 1.0, 1.0, 4.0, None, None,
+                           None) == gd.ERR_UNSUPPORTED
+    d = gd.make_slice_descs([0], 10, 10, 0.01, pitch=[(1 << 28) + 1])
+    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, 1, 1.0, 1.0, None, None, None,
+                                          None) == gd.ERR_UNSUPPORTED
+
+
 def test_step_argument_checks(lib):
     assert lib.gd_rb_sweep(P(64), P(64), P(128), 1, 4, 4, 4, 0.0, 1.0, 1.0, 1.0, None) == gd.ERR_INVALID
     assert lib.gd_residual_restrict(P(64), P(128), P(256), 1, 4, 4, 4, 3, 1, 1, 0.0, 1.0, 1.0, 1.0, None,
