@@ -184,7 +184,7 @@ def bench_learned(a, gd, synth, torch, desc):
         return rep
 
     results = {}
-    for mode, name in (("mg", "plain_vcycles"), (0, "fcg_vcycle"), (2, "fcg_vcycle_net")):
+    for mode, name in (("mg", "plain_vcycles"), (0, "fcg_vcycle"), (3, "fcg_net_smoother"), (2, "fcg_vcycle_net")):
         for _ in range(a.warmup):
             solve(mode)
         torch.cuda.synchronize()
@@ -197,7 +197,7 @@ def bench_learned(a, gd, synth, torch, desc):
         dt = (time.perf_counter() - t2) / a.steps
         results[name] = {"ms_per_solve": dt * 1e3, "iterations": rep["iterations"],
                          "rel_residual": rep["rel_residual"], "voxels_per_s": nvox / dt}
-        if mode == 2:
+        if mode in (2, 3):
             results[name]["fallback_used"] = rep["fallback_used"]
     layers = []
     for l in range(9):
@@ -233,7 +233,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+              "sharding across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
 

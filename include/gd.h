@@ -207,7 +207,9 @@ gd_status gd_net_kernel_time(const gd_net* n, int layer, double* ms, int64_t* la
 
 /* Flexible conjugate gradients on the hierarchy's system (FP32 storage) with
  * preconditioner 0: one V-cycle, 1: the net, 2: a V-cycle then the net on
- * its remaining residual.  x in/out, b in (caller's layout).  When the net
+ * its remaining residual, 3: the net as the finest level's post-smoother (a
+ * V-cycle without the finest post-smoothing sweeps, then the net on its
+ * remaining residual).  x in/out, b in (caller's layout).  When the net
  * fails or stops reducing the residual the iteration restarts with the
  * V-cycle preconditioner (rep->refine_steps = 1 then).  rep->cycles =
  * iterations, rep->rel_residual = the final true relative residual. */

@@ -286,7 +286,8 @@ class Hierarchy:
         return r, e
 
     def fcg(self, x, b, net=None, precond=0, rel_tol=1e-6, max_iter=200, check=True):
-        """Flexible CG (x in/out); precond 0 V-cycle, 1 net, 2 V-cycle then net."""
+        """Flexible CG (x in/out); precond 0 V-cycle, 1 net, 2 V-cycle then net,
+        3 net in place of the finest level's post-smoothing."""
         rep = Report()
         st = _lib.gd_fcg_solve(self._h, net._n if net is not None else None, _ptr(x), _ptr(b), int(precond),
                                float(rel_tol), int(max_iter), ctypes.byref(rep), _stream())

@@ -598,6 +598,7 @@ struct Cycler {
   Hier& H;
   hipStream_t st;
   int pre, post, pmode;
+  int post0 = -1;  // post-smoothing sweeps of the finest level (-1: as the others)
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   std::vector<int> ev_kind;
@@ -644,11 +645,12 @@ struct Cycler {
   void correct(int l) {
     below(l + 1);
     Level& C = H.lv[l + 1];
-    if (fuse && post > 0 && H.lv[l].sw.tile == 0) {
-      smooth(l, post, C.x);  // prolongation fused into the first sweep's loads
+    const int np = (l == 0 && post0 >= 0) ? post0 : post;
+    if (fuse && np > 0 && H.lv[l].sw.tile == 0) {
+      smooth(l, np, C.x);  // prolongation fused into the first sweep's loads
     } else {
       HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), C.x, H.lv[l].x, pmode, H.lv[l].keep_x, st));
-      smooth(l, post);
+      smooth(l, np);
     }
   }
   void below(int l) {
@@ -1145,7 +1147,9 @@ struct gd_hierarchy {
 
 namespace gd {
 // one V-cycle from a zero guess on A z = r (caller's layout, storage dtype)
-static void mg_apply(gd_hierarchy* h, const void* r, void* z, hipStream_t st) {
+// z = one V-cycle on A z = r from z = 0; no_post: without the finest
+// level's post-smoothing (the learned smoother takes its place)
+static void mg_apply(gd_hierarchy* h, const void* r, void* z, hipStream_t st, bool no_post = false) {
   Hier& H = *h->H;
   Level& L0 = H.lv[0];
   const GridDesc& g0 = L0.h[0];
@@ -1154,6 +1158,7 @@ static void mg_apply(gd_hierarchy* h, const void* r, void* z, hipStream_t st) {
   HIP_TRY(hipMemcpy2DAsync(L0.b, pb, r, wb, wb, rows, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * es, st));
   Cycler cy(H, st, h->o);
+  if (no_post) cy.post0 = 0;
   cy.full(0);
   HIP_TRY(hipMemcpy2DAsync(z, wb, L0.x, pb, wb, rows, hipMemcpyDeviceToDevice, st));
 }
@@ -1298,8 +1303,10 @@ gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int
                        int max_iter, gd_solve_report* rep, void* stream) {
   if (!h || !x || !b) return fail(GD_ERR_INVALID, "gd_fcg_solve: null pointer");
   if (x == b) return fail(GD_ERR_INVALID, "gd_fcg_solve: x aliases b");
-  if (precond < 0 || precond > 2 || (precond > 0 && !net))
-    return fail(GD_ERR_INVALID, "gd_fcg_solve: precond 0 (V-cycle), 1 (net) or 2 (V-cycle then net) with a net");
+  if (precond < 0 || precond > 3 || (precond > 0 && !net))
+    return fail(GD_ERR_INVALID,
+                "gd_fcg_solve: precond 0 (V-cycle), 1 (net), 2 (V-cycle then net) or 3 (net as the finest "
+                "post-smoother) with a net");
   if (!(rel_tol > 0.0) || max_iter < 0) return fail(GD_ERR_INVALID, "gd_fcg_solve: bad tolerance or max_iter");
   Hier& H = *h->H;
   if (H.s != GD_F32) return fail(GD_ERR_UNSUPPORTED, "gd_fcg_solve: FP32 hierarchies only");
@@ -1323,9 +1330,10 @@ gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int
     };
     auto precondition = [&](int m) -> bool {  // z = M(r); false if the net failed
       if (m == 0 || m == 2) mg_apply(h, r, z, st);
+      if (m == 3) mg_apply(h, r, z, st, true);
       if (m == 1) {
         if (gd_net_forward(net, (const float*)r, (float*)z, g0.nx, g0.ny, g0.nz, st) != GD_OK) return false;
-      } else if (m == 2) {
+      } else if (m == 2 || m == 3) {
         // z += net(r - A z); q still holds A p of this iteration and must survive
         HIP_TRY(launch_general_residual(H.s, g, z, r, t, H.partials, st));
         if (gd_net_forward(net, (const float*)t, (float*)u, g0.nx, g0.ny, g0.nz, st) != GD_OK) return false;

@@ -196,7 +196,7 @@ def test_net_corrects_multigrid_error(gd, trained):
     assert gain < 0.9, gain
 
 
-@pytest.mark.parametrize("precond", [0, 1, 2])
+@pytest.mark.parametrize("precond", [0, 1, 2, 3])
 def test_fcg_solution_matches_oracle(gd, trained, precond):
     net, _, _ = trained
     bnp = held_out(gd, seed=13100418)
@@ -242,7 +242,7 @@ def test_fcg_falls_back_to_multigrid(gd, broken):
     net.set_params(np.full_like(p, np.nan) if broken == "nan" else np.zeros_like(p))
     b = torch.from_numpy(held_out(gd, nz=4, seed=13100420)).float().cuda()
     h = gd.Hierarchy(tuple(b.shape), ALPHA, (1.0, 1.0, 0.0), torch.float32)
-    for m in (1, 2):
+    for m in (1, 2, 3):
         x = torch.zeros_like(b)
         rep = h.fcg(x, b, net=net, precond=m, rel_tol=1e-6, max_iter=300, check=False)
         assert rep["status"] == 0 and rep["rel_residual"] <= 1e-6, rep
@@ -270,6 +270,10 @@ def test_fcg_rejects_bad_arguments(gd):
         h.fcg(torch.zeros_like(b), b, net=None, precond=1)
     with pytest.raises(gd.GDError):
         h.fcg(torch.zeros_like(b), b, precond=3)
+    net = gd.Net(seed=3)
+    with pytest.raises(gd.GDError):
+        h.fcg(torch.zeros_like(b), b, net=net, precond=4)
+    net.close()
     h.close()
 
 
