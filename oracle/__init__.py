@@ -18,6 +18,9 @@ Image Stacks"):
                    grids), conjugate gradients on the matrix-free operator, and
                    the exact DCT-II diagonalisation that is the discrete form of
                    the frequency-space analysis of Sec. 3.2.
+* ``npr``       -- the gradient-modulation filter of Sec. 6 (the general
+                   system with the input's gradients scaled by
+                   lambda (1 - exp(-|grad|^2 / 2 sigma^2))), its limits and energy.
 * ``mgsteps``   -- single multigrid steps (Sec. 4.1): one red-black
                    Gauss-Seidel sweep, the residual, restriction by summing
                    children, constant and cell-centred trilinear prolongation,
