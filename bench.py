@@ -27,6 +27,8 @@ WORKLOADS = {
     "learned2k": ("learned", "f32", 0, "2048x2048x64 stack, per-slice screened Poisson (alpha 0.01), flexible CG "
                   "preconditioned by a V-cycle then the BF16 U-Net, net trained on multigrid error pairs of "
                   "1024x1024 slices"),
+    "npr-video": ("npr", "f32", 0, "1920x1080x742 grey-level video volume, gradient-modulation filter of Sec. 6 "
+                  "(alpha 0.001, W = diag(1, 1, 0.1), lambda 1.25, sigma 5), FP32 storage, plain V-cycles"),
     "slices2048": ("slices", "f32", 0, "2048 independent slices, sides log-uniform in [256, 2048], alpha U(0.001, 0.1), "
                    "per-slice screened Poisson, FP32, plain V-cycles, one batched launch per level step"),
 }
@@ -229,6 +231,69 @@ def bench_learned(a, gd, synth, torch, desc):
     print(json.dumps(line), flush=True)
 
 
+NPR = dict(alpha=0.001, beta=(1.0, 1.0, 0.1), lam=1.25, sigma=5.0)
+
+
+def bench_npr(a, gd, synth, torch, desc):
+    """Gradient-modulation filter (Sec. 6) of a synthetic 1920x1080x742 video
+    volume: one step = the modulated right-hand side, V-cycles to 1e-6 and
+    the output, inputs resident in HBM."""
+    spec = synth.VIDEO_CONFIGS["video1080"]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    I0 = synth.make_video(spec, device=dev, dtype=torch.float32)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    nvox = I0.numel()
+    pre, post = (int(v) for v in a.smooth.split(","))
+    opts = dict(rel_tol=TOL, pre_smooth=pre, post_smooth=post)
+
+    def step(timing):
+        return gd.npr_filter(I0, NPR["alpha"], NPR["beta"], NPR["lam"], NPR["sigma"], timing=timing, **opts)[1]
+
+    for _ in range(a.warmup):
+        step(0)
+    torch.cuda.synchronize()
+    gd.reset_kernel_time()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        rep = step(1)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    ms, launches, bytes_per = gd.kernel_time(gd.SWEEP_STACK)
+    avg_ms = ms / max(launches, 1)
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    cfg = gd.sweep_config((spec.nt, spec.ny, spec.nx), torch.float32)
+    line = {
+        "metric": "voxels/s to 1e-6 rel. residual (gradient-modulation filter)",
+        "value": nvox / dt, "unit": "voxels/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {desc}; Neumann, tol {TOL:g}", "nx": spec.nx, "ny": spec.ny,
+                   "nz": spec.nt, "voxels": nvox, "smooth": [pre, post]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rb_sweep<f32,%d,%d,false,true> finest level" % tuple(cfg["tile"]),
+                     "sweep_config": cfg, "launches": launches, "avg_launch_ms": avg_ms,
+                     "algorithmic_bytes_per_launch": bytes_per},
+        "solve": {"cycles": rep["cycles"], "rel_residual": rep["rel_residual"], "levels": rep["levels"]},
+        "generate_s": gen_s,
+    }
+    if not a.no_cpu_baseline:
+        from oracle import npr
+
+        nz, ny, nx = (int(v) for v in a.cpu_crop.split(","))
+        sub = I0[:nz, :ny, :nx].double().cpu().numpy()
+        t1 = time.perf_counter()
+        npr.npr_filter(sub, NPR["alpha"], NPR["beta"], NPR["lam"], NPR["sigma"], method="cg", rtol=TOL)
+        cdt = time.perf_counter() - t1
+        line["cpu_baseline"] = {
+            "value": sub.size / cdt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+            "sample": f"crop [0:{nz},0:{ny},0:{nx}] of the same video ({sub.size} voxels), modulated field and "
+                      f"right-hand side, then conjugate gradients to {TOL:g}, numpy FP64, {cdt:.1f} s"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -259,6 +324,8 @@ def main():
         return bench_slices(a, gd, synth, torch, desc)
     if spec_key == "learned":
         return bench_learned(a, gd, synth, torch, desc)
+    if spec_key == "npr":
+        return bench_npr(a, gd, synth, torch, desc)
     t0 = time.perf_counter()
     I0 = synth.make_stack(spec, device=dev, dtype=tdt)
     torch.cuda.synchronize()

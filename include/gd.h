@@ -137,6 +137,24 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
                                      const gd_solve_opts* opts, gd_solve_report* rep,
                                      gd_solve_report* per_slice, void* stream);
 
+/* Gradient-modulation ("non-photorealistic") filter of Sec. 6, the general
+ * system of Sec. 4 applied to a volume (the paper filters a video,
+ * x, y = frame, z = time):
+ *   I1 = argmin alpha |I - I0|^2 + sum_a beta_a |D_a I - V_a|^2,
+ *   V  = lambda (1 - exp(-|g|^2 / (2 sigma^2))) g,
+ * g the forward-difference gradient of I0 at each voxel (a component is 0
+ * where its face leaves the grid), its face v -> v + e_a carrying V_a(v).
+ * The paper uses alpha = 0.001, beta = (1, 1, 0.1), lambda = 1.25, sigma = 5
+ * on grey values in [0, 256).  I0 (in_t) and I1 (out_t) are contiguous
+ * [nz][ny][nx]; the V-cycles run in opts->storage on the correction I1 - I0
+ * until ||b - A I1|| <= rel_tol ||b|| (canonical b, FP64 accumulation).
+ * alpha <= 0, beta < 0, sigma <= 0 or a non-finite lambda are
+ * GD_ERR_INVALID; opts->fp64_refine is GD_ERR_UNSUPPORTED. */
+gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
+                        int64_t nx, int64_t ny, int64_t nz, double alpha,
+                        double beta_x, double beta_y, double beta_z, double lambda, double sigma,
+                        const gd_solve_opts* opts, gd_solve_report* rep, void* stream);
+
 /* ---- general system (Sec. 4) through an explicit hierarchy ---------------- */
 typedef struct gd_hierarchy gd_hierarchy;
 

@@ -87,10 +87,12 @@ def rhs(I0, alpha, beta, lam, sigma):
     return grid.rhs_general(I0, modulate(I0, lam, sigma), alpha, beta, shape=I0.shape)
 
 
-def npr_filter(I0, alpha=0.001, beta=(1.0, 1.0, 0.1), lam=1.25, sigma=5.0, method="dct"):
-    """The filtered volume: the minimiser of the energy above (alpha > 0)."""
+def npr_filter(I0, alpha=0.001, beta=(1.0, 1.0, 0.1), lam=1.25, sigma=5.0, method="dct", rtol=1e-13):
+    """The filtered volume: the minimiser of the energy above (alpha > 0).
+    method 'dct' (exact), 'dense' (tiny grids) or 'cg' (to relative residual rtol)."""
     I0 = grid.as3d(I0)
-    return solvers.general_solve(I0, modulate(I0, lam, sigma), alpha, beta, method=method, shape=I0.shape)
+    return solvers.general_solve(I0, modulate(I0, lam, sigma), alpha, beta, method=method, shape=I0.shape,
+                                 rtol=rtol)
 
 
 def energy(I, I0, alpha, beta, lam, sigma):

@@ -87,6 +87,8 @@ _SIGS = {
     "gd_screened_poisson_slices": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(SliceDesc), _i64, _d, _d,
                                         ctypes.POINTER(SolveOpts), ctypes.POINTER(Report),
                                         ctypes.POINTER(Report), _vp]),
+    "gd_npr_filter": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _d, _d, _d, ctypes.POINTER(SolveOpts),
+                           ctypes.POINTER(Report), _vp]),
     "gd_hierarchy_create": (_i, [ctypes.POINTER(_vp), _i64, _i64, _i64, _d, _d, _d, _d, _i,
                                  ctypes.POINTER(SolveOpts), _vp]),
     "gd_hierarchy_destroy": (_i, [_vp]),
@@ -200,6 +202,23 @@ def smooth_z(I0, beta=(1.0, 1.0, 4.0), out_dtype=None, opts=None, check=True, **
     st = lib.gd_smooth_z(_ptr(I0), gd_dtype(I0.dtype), _ptr(out), gd_dtype(out.dtype), nx, ny, nz,
                          float(beta[0]), float(beta[1]), float(beta[2]), ctypes.byref(o), ctypes.byref(rep),
                          _stream())
+    if check:
+        _check(st)
+    return out, dict(rep.as_dict(), status=st)
+
+
+def npr_filter(I0, alpha=0.001, beta=(1.0, 1.0, 0.1), lam=1.25, sigma=5.0, out_dtype=None, opts=None, check=True,
+               **kw):
+    """Gradient-modulation filter of the [nz][ny][nx] volume I0 (Sec. 6).
+    Returns (I1, report dict)."""
+    lib = load()
+    nz, ny, nx = I0.shape
+    out = _torch().empty_like(I0, dtype=out_dtype or I0.dtype)
+    o = opts or default_opts(**kw)
+    rep = Report()
+    st = lib.gd_npr_filter(_ptr(I0), gd_dtype(I0.dtype), _ptr(out), gd_dtype(out.dtype), nx, ny, nz, float(alpha),
+                           float(beta[0]), float(beta[1]), float(beta[2]), float(lam), float(sigma), ctypes.byref(o),
+                           ctypes.byref(rep), _stream())
     if check:
         _check(st)
     return out, dict(rep.as_dict(), status=st)

@@ -964,6 +964,58 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
   return R;
 }
 
+// Gradient-modulation filter (Sec. 6): plain V-cycles on the correction
+// system A E = b (b from launch_npr_rhs, E = 0 at the start) until the
+// residual, accumulated in FP64, is at most rel_tol times the canonical
+// ||b||.  The residual of E equals the canonical residual of I0 + E.
+static Outcome solve_npr(Hier& H, const gd_solve_opts& o, double bnorm, hipStream_t st) {
+  Outcome R;
+  R.bnorm = {bnorm};
+  Cycler cy(H, st, o);
+  const bool single = H.lv.size() == 1;
+  const double den = denom(bnorm);
+  double best = INFINITY, inner = 0.5;
+  int stall = 0;
+  auto full_residual = [&]() {
+    HIP_TRY(launch_general_residual(H.s, H.g_ew(0), H.lv[0].x, H.lv[0].b, nullptr, H.partials, st, true));
+    HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, 1, 2, H.dred, st));
+    read_dred(H, 2, st);
+    return std::sqrt(H.hpin[0]);
+  };
+  for (;;) {
+    bool check_final = R.cycles >= o.max_cycles || single, stop_after = check_final;
+    if (single) {
+      cy.smooth(0, 1);
+      R.cycles++;
+    } else {
+      cy.smooth(0, o.pre_smooth);
+      cy.restrict_to(0, true);
+      read_dred(H, 1, st);
+      const double rr = std::sqrt(H.hpin[0]);
+      if (!std::isfinite(rr)) { R.numeric = true; break; }
+      stall = rr < 0.7 * best ? 0 : stall + 1;
+      best = std::min(best, rr);
+      if (rr <= inner * o.rel_tol * den) check_final = true;
+      if (stall >= 3) check_final = stop_after = true;
+    }
+    if (check_final) {
+      const double rr = full_residual();
+      R.rel = {rr / den};
+      if (!std::isfinite(rr)) { R.numeric = true; break; }
+      R.converged = rr <= o.rel_tol * den;
+      if (R.converged || stop_after) break;
+      inner *= 0.25;
+    }
+    if (!single) {
+      cy.correct(0);
+      R.cycles++;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  cy.harvest();
+  return R;
+}
+
 static void fill_report(gd_solve_report* rep, const Outcome& R, int g, double secs, int levels) {
   rep->cycles = R.cycles;
   rep->refine_steps = R.steps;
@@ -1067,6 +1119,48 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, i
     if (rep) fill_report(rep, R, 0, secs, (int)H->lv.size());
     if (R.numeric) return fail(GD_ERR_NUMERIC, "gd_smooth_z: non-finite residual");
     if (!R.converged) return fail(GD_ERR_NOT_CONVERGED, "gd_smooth_z: tolerance not reached");
+    return GD_OK;
+  });
+}
+
+gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, int64_t nx, int64_t ny, int64_t nz,
+                        double alpha, double bx, double by, double bz, double lambda, double sigma,
+                        const gd_solve_opts* opts, gd_solve_report* rep, void* stream) {
+  if (!I0 || !I1) return fail(GD_ERR_INVALID, "gd_npr_filter: null pointer");
+  if ((const void*)I0 == (const void*)I1) return fail(GD_ERR_INVALID, "gd_npr_filter: output aliases input");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
+    return fail(GD_ERR_INVALID, "gd_npr_filter: bad size");
+  if (nx * ny > MAX_PLANE) return fail(GD_ERR_UNSUPPORTED, "gd_npr_filter: x-y plane above 2^28 cells");
+  if (!valid_dtype(in_t) || !valid_dtype(out_t)) return fail(GD_ERR_INVALID, "gd_npr_filter: bad dtype");
+  if (!(alpha > 0.0) || !std::isfinite(alpha) || !(bx >= 0.0) || !(by >= 0.0) || !(bz >= 0.0) ||
+      !std::isfinite(bx) || !std::isfinite(by) || !std::isfinite(bz))
+    return fail(GD_ERR_INVALID, "gd_npr_filter: need alpha > 0 and beta >= 0");
+  if (!std::isfinite(lambda) || !(sigma > 0.0) || !std::isfinite(sigma))
+    return fail(GD_ERR_INVALID, "gd_npr_filter: need a finite lambda and sigma > 0");
+  gd_solve_opts o;
+  gd_default_opts(&o);
+  if (opts) o = *opts;
+  gd_status s = check_opts(o);
+  if (s != GD_OK) return s;
+  if (o.fp64_refine) return fail(GD_ERR_UNSUPPORTED, "gd_npr_filter: FP64 refinement is not built for this filter");
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<GridSpec> g{{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}};
+    Hier* H = get_hier("npr", g, o.storage, false, st, o.sweep_tile);
+    Level& L0 = H->lv[0];
+    HIP_TRY(launch_npr_rhs(in_t, H->s, H->g_ew(0), I0, lambda, sigma, L0.b, H->partials, st));
+    HIP_TRY(launch_reduce(H->partials, L0.ew.d_b0, 1, 2, H->dred, st));
+    read_dred(*H, 2, st);
+    const double bnorm = std::sqrt(H->hpin[0]);
+    HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * dsize(H->s), st));
+    Outcome R = solve_npr(*H, o, bnorm, st);
+    HIP_TRY(launch_finalize(in_t, H->s, out_t, 0, H->g_ew(0), I0, L0.x, nullptr, nullptr, I1, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) fill_report(rep, R, 0, secs, (int)H->lv.size());
+    if (R.numeric) return fail(GD_ERR_NUMERIC, "gd_npr_filter: non-finite residual");
+    if (!R.converged) return fail(GD_ERR_NOT_CONVERGED, "gd_npr_filter: tolerance not reached");
     return GD_OK;
   });
 }

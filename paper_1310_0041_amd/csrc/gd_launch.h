@@ -73,9 +73,15 @@ hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, doubl
 hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const void* Gx,
                               const void* Gy, const void* Gz, void* b, hipStream_t st);
 // Generic system: per block (sum (b - A x)^2, sum b^2) in FP64; r_out
-// (may be NULL) receives b - A x.
+// (may be NULL) receives b - A x.  lib_layout: x, b, r are a hierarchy level
+// (offset off, pitch px) instead of the caller's arrays.
 hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b, void* r_out,
-                                   double* partials, hipStream_t st);
+                                   double* partials, hipStream_t st, bool lib_layout = false);
+// Gradient-modulation filter (Sec. 6): the correction-form right-hand side
+// from I0 (caller's layout, dtype tin) into b (finest level, dtype s); per
+// block FP64 (sum of the canonical rhs squared, sum of b squared).
+hipError_t launch_npr_rhs(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, double lam, double sigma,
+                          void* b, double* partials, hipStream_t st);
 // Krylov vectors (caller's layout): q = A p with per-block p.q; per-block a.b;
 // x += c0 p, r -= c0 q with per-block r.r; out = c0 X + c1 Y.
 hipError_t launch_apply_dot(gd_dtype s, const Geom& g, const void* p, void* q, double* partials, hipStream_t st);

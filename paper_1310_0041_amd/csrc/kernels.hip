@@ -1254,7 +1254,9 @@ k_rhs_general(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
   }
 }
 
-template <typename S>
+// LIB: the arrays are a level of the library's hierarchy (offset off, row
+// pitch px) instead of the caller's layout.
+template <typename S, bool LIB>
 __global__ void __launch_bounds__(256)
 k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids,
                    int zlen, int etx, const S* __restrict__ xin, const S* __restrict__ bin, S* __restrict__ rout,
@@ -1266,9 +1268,10 @@ k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict
   const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   double rr = 0.0, bb = 0.0;
   if (i < nx && j < ny) {
-    const int64_t pl = G.ipz, py = G.ipy;
+    const int64_t pl = LIB ? (int64_t)G.px * ny : G.ipz, py = LIB ? (int64_t)G.px : G.ipy;
+    const int64_t base = LIB ? G.off : G.ioff;
     for (int k = t.z0; k < t.z1; ++k) {
-      const int64_t v = G.ioff + k * pl + (int64_t)j * py + i;
+      const int64_t v = base + k * pl + (int64_t)j * py + i;
       const double xc = ld64(xin + v), bv = ld64(bin + v);
       double r = bv - G.alpha * xc;
       if (i > 0) r += G.wx * (ld64(xin + v - 1) - xc);
@@ -1284,6 +1287,81 @@ k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict
   }
   const double s1 = block_sum(rr, red);
   const double s2 = block_sum(bb, red);
+  if (threadIdx.x == 0) {
+    partials[2 * t.bid] = s1;
+    partials[2 * t.bid + 1] = s2;
+  }
+}
+
+// ------------------------------------------- gradient-modulation filter (Sec. 6)
+//
+// Right-hand side of the filter in correction form.  The target gradient on
+// the face v -> v + e_a is V = f(v) g_a(v): g(v) the forward-difference
+// gradient of I0 at v (a component is 0 where its face leaves the grid) and
+// f(v) = lambda (1 - exp(-|g(v)|^2 / (2 sigma^2))).  The canonical system is
+// (alpha + sum_a w_a D_a^T D_a) I = alpha I0 + sum_a w_a D_a^T V_a; for
+// I = I0 + E it becomes A E = sum_a w_a D_a^T ((f - 1) g_a), written to b in
+// the library's layout.  (D_a^T h)(v) = h(v - e_a) - h(v), so a voxel needs
+// f and g of itself and of its three lower neighbours.  Per block: FP64
+// sums of the canonical right-hand side squared and of b squared.
+template <typename Tin, typename S>
+__global__ void __launch_bounds__(256)
+k_npr_rhs(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+          const Tin* __restrict__ I0, double lam, double inv2s2, S* __restrict__ bout,
+          double* __restrict__ partials) {
+  __shared__ double red[4];
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  double sb = 0.0, se = 0.0;
+  if (i < nx && j < ny) {
+    const int64_t pl = (int64_t)G.px * ny;
+    const double w[3] = {G.wx, G.wy, G.wz};
+    for (int k = t.z0; k < t.z1; ++k) {
+      // value of I0 at (i + di, j + dj, k + dk), inside the grid by construction
+      auto I = [&](int di, int dj, int dk) -> double {
+        return in_at(I0, G.ioff + (int64_t)(k + dk) * G.ipz + (int64_t)(j + dj) * G.ipy + (i + di));
+      };
+      // forward gradient of voxel (i + di, j + dj, k + dk) (value c there)
+      auto fwd = [&](int di, int dj, int dk, double c, double g[3]) {
+        g[0] = (i + di + 1 < nx) ? I(di + 1, dj, dk) - c : 0.0;
+        g[1] = (j + dj + 1 < ny) ? I(di, dj + 1, dk) - c : 0.0;
+        g[2] = (k + dk + 1 < nz) ? I(di, dj, dk + 1) - c : 0.0;
+      };
+      auto factor = [&](const double g[3]) {
+        return lam * (1.0 - exp(-(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * inv2s2));
+      };
+      const double c = I(0, 0, 0);
+      double gv[3];
+      fwd(0, 0, 0, c, gv);
+      const double fv = factor(gv);
+      double bc = G.alpha * c, be = 0.0;
+      const bool lower[3] = {i > 0, j > 0, k > 0};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (w[a] == 0.0) continue;
+        // the face this voxel owns
+        bc -= w[a] * fv * gv[a];
+        be -= w[a] * (fv - 1.0) * gv[a];
+        // the face owned by the lower neighbour along a
+        if (lower[a]) {
+          const int di = a == 0 ? -1 : 0, dj = a == 1 ? -1 : 0, dk = a == 2 ? -1 : 0;
+          const double cu = I(di, dj, dk);
+          double gu[3];
+          fwd(di, dj, dk, cu, gu);
+          const double fu = factor(gu);
+          bc += w[a] * fu * gu[a];
+          be += w[a] * (fu - 1.0) * gu[a];
+        }
+      }
+      st64(bout + G.off + k * pl + (int64_t)j * G.px + i, be);
+      sb += bc * bc;
+      se += be * be;
+    }
+  }
+  const double s1 = block_sum(sb, red);
+  const double s2 = block_sum(se, red);
   if (threadIdx.x == 0) {
     partials[2 * t.bid] = s1;
     partials[2 * t.bid + 1] = s2;
@@ -1616,10 +1694,38 @@ hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const vo
 }
 
 hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b, void* r_out,
-                                   double* partials, hipStream_t st) {
+                                   double* partials, hipStream_t st, bool lib_layout) {
   if (g.nblocks == 0) return hipSuccess;
-#define L(T) hipLaunchKernelGGL(k_general_residual<T>, GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, partials)
+#define L(T)                                                                                                      \
+  if (lib_layout)                                                                                                 \
+    hipLaunchKernelGGL((k_general_residual<T, true>), GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, partials); \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_general_residual<T, false>), GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, partials)
   GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+template <typename TI>
+static void npr_rhs_launch(gd_dtype s, const Geom& g, const void* I0, double lam, double inv2s2, void* b,
+                           double* partials, hipStream_t st) {
+#define L(T) hipLaunchKernelGGL((k_npr_rhs<TI, T>), GD_ARGS(g), (const TI*)I0, lam, inv2s2, (T*)b, partials)
+  switch (s) {
+    case GD_F64: L(double); break;
+    case GD_F32: L(float); break;
+    case GD_F16: L(__half); break;
+    case GD_BF16: L(__hip_bfloat16); break;
+    default: break;
+  }
+#undef L
+}
+
+hipError_t launch_npr_rhs(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, double lam, double sigma,
+                          void* b, double* partials, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+  const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+#define L(TI) npr_rhs_launch<TI>(s, g, I0, lam, inv2s2, b, partials, st)
+  GD_DISPATCH_S(tin, L)
 #undef L
   return last();
 }

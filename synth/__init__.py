@@ -5,7 +5,9 @@ both the HIP path and the FP64 oracle consume.  The paper's Mouse S1 stack and
 its video example are not available, so these stacks stand in for them:
 Gaussian blobs shared across slices with sub-pixel jitter, a jittered-lattice
 Voronoi membrane pattern, a per-slice gain and offset (the slice-to-slice
-discontinuities the method removes) and additive Gaussian noise.
+discontinuities the method removes) and additive Gaussian noise.  A
+grey-level video volume (moving blobs plus noise) stands in for the video
+of the paper's gradient-modulation example.
 """
 
 from .stack import (  # noqa: F401
@@ -16,3 +18,4 @@ from .stack import (  # noqa: F401
     quantize,
     counter_normal,
 )
+from .video import VideoSpec, VIDEO_CONFIGS, make_video  # noqa: F401

@@ -93,6 +93,21 @@ def test_slice_argument_checks(lib):
     assert rep.cycles == 0
 
 
+def test_npr_argument_checks(lib):
+    def call(alpha=0.001, beta=(1.0, 1.0, 0.1), lam=1.25, sigma=5.0, opts=None, out=P(128)):
+        return lib.gd_npr_filter(P(64), 1, out, 1, 8, 8, 4, alpha, beta[0], beta[1], beta[2], lam, sigma, opts,
+                                 None, None)
+    assert call(alpha=0.0) == gd.ERR_INVALID
+    assert call(beta=(1.0, -1.0, 0.1)) == gd.ERR_INVALID
+    assert call(sigma=0.0) == gd.ERR_INVALID
+    assert call(lam=float("nan")) == gd.ERR_INVALID
+    assert call(out=P(64)) == gd.ERR_INVALID  # aliasing
+    o = gd.default_opts(fp64_refine=1)
+    assert call(opts=ctypes.byref(o)) == gd.ERR_UNSUPPORTED
+    assert lib.gd_npr_filter(P(64), 1, P(128), 1, 1 << 15, 1 << 14, 1, 0.001, 1.0, 1.0, 0.1, 1.25, 5.0, None, None,
+                             None) == gd.ERR_UNSUPPORTED
+
+
 def test_plane_size_limit(lib):
     # an x-y plane above 2^28 cells is refused on the host, before any GPU call
     h = ctypes.c_void_p()
