@@ -21,6 +21,9 @@ Image Stacks"):
 * ``npr``       -- the gradient-modulation filter of Sec. 6 (the general
                    system with the input's gradients scaled by
                    lambda (1 - exp(-|grad|^2 / 2 sigma^2))), its limits and energy.
+* ``hybrid``    -- the steps of the "Hybrid" discretisation of Sec. 4.2:
+                   B-spline prolongation (1/2, 1, 1/2), its transpose, Galerkin
+                   coarse operators from per-axis 1-D tables, 8-colour GS.
 * ``mgsteps``   -- single multigrid steps (Sec. 4.1): one red-black
                    Gauss-Seidel sweep, the residual, restriction by summing
                    children, constant and cell-centred trilinear prolongation,
