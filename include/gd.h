@@ -85,6 +85,13 @@ typedef struct {
                            (right-hand side restricted to every level, coarse
                            solutions interpolated up, one V-cycle per level);
                            0 (default): start from zero */
+  int discretization;   /* Sec. 4.2: 0 (default) "Constant" transfers with
+                           rediscretised 7-point coarse operators; 1 "Hybrid":
+                           7-point finest level, B-spline (1/2, 1, 1/2)
+                           prolongation, its transpose as restriction and
+                           Galerkin 27-point coarse operators relaxed by
+                           8-colour Gauss-Seidel.  Same answer; single-grid
+                           solves only (slice batches: GD_ERR_UNSUPPORTED). */
 } gd_solve_opts;
 
 /* Filled by the solve calls when the pointer is non-NULL. */

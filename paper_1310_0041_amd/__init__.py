@@ -48,6 +48,7 @@ class SolveOpts(ctypes.Structure):
         ("sweep_tile", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("fmg", ctypes.c_int),
+        ("discretization", ctypes.c_int),
     ]
 
 

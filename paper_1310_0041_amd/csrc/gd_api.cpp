@@ -139,6 +139,9 @@ struct Hier {
   double* x64 = nullptr;     // FP64 iterate of the refinement path
   double* x64b = nullptr;    // its next value (the fused update writes here)
   std::vector<int64_t> cells;  // finest cells per grid
+  // Hybrid discretisation: per-level table blocks (levels >= 1) on the device
+  std::vector<HybTables> hyb;
+  double* hyb_dev = nullptr;
 
   // Captured V-cycle segments (see CycleGraphs): two executables that map
   // the level buffers' ping-pong state A -> B and B -> A.
@@ -594,6 +597,102 @@ static Hier* get_hier(const char* kind, const std::vector<GridSpec>& specs, gd_d
 
 // --------------------------------------------------------------- V-cycle
 
+// A valid request this library does not build (reported as GD_ERR_UNSUPPORTED).
+struct Unsupported : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+// Hybrid discretisation (Sec. 4.2): per-axis Galerkin tables of every level
+// >= 1.  Along one axis the finest level has M_0 = Id and K_0 = L (Neumann
+// 3-point); M_{l+1} = P^T M_l P, K_{l+1} = P^T K_l P with P the B-spline
+// nesting of the axis (identity when the axis is kept), all tridiagonal.
+struct Tri {
+  std::vector<double> lo, di, up;  // T[i][i-1], T[i][i], T[i][i+1]
+};
+
+static Tri galerkin_1d(const Tri& T, int n, bool halved) {
+  const int nc = halved ? (n + 1) / 2 : n;
+  Tri C{std::vector<double>(nc, 0.0), std::vector<double>(nc, 0.0), std::vector<double>(nc, 0.0)};
+  auto parents = [&](int f, int* c, double* w) -> int {
+    if (!halved) { c[0] = f; w[0] = 1.0; return 1; }
+    if ((f & 1) == 0) { c[0] = f / 2; w[0] = 1.0; return 1; }
+    const int lo = (f - 1) / 2, hi = (f + 1) / 2;
+    if (hi < nc) { c[0] = lo; w[0] = 0.5; c[1] = hi; w[1] = 0.5; return 2; }
+    c[0] = lo; w[0] = 1.0;
+    return 1;
+  };
+  for (int f = 0; f < n; ++f) {
+    int pc[2], qc[2];
+    double pw[2], qw[2];
+    const int np = parents(f, pc, pw);
+    for (int d = -1; d <= 1; ++d) {
+      const int g = f + d;
+      if (g < 0 || g >= n) continue;
+      const double t = d < 0 ? T.lo[f] : (d == 0 ? T.di[f] : T.up[f]);
+      if (t == 0.0) continue;
+      const int nq = parents(g, qc, qw);
+      for (int a = 0; a < np; ++a)
+        for (int b = 0; b < nq; ++b) {
+          const double v = pw[a] * t * qw[b];
+          const int dc = qc[b] - pc[a];
+          if (dc == -1) C.lo[pc[a]] += v;
+          else if (dc == 0) C.di[pc[a]] += v;
+          else if (dc == 1) C.up[pc[a]] += v;
+          else throw std::logic_error("Galerkin product left the tridiagonal band");
+        }
+    }
+  }
+  return C;
+}
+
+static void ensure_hybrid(Hier& H) {
+  if (!H.hyb.empty()) return;
+  if (H.ngrids != 1) throw Unsupported("the Hybrid discretisation is built for single-grid solves only");
+  const int nl = (int)H.lv.size();
+  const GridDesc& g0 = H.lv[0].h[0];
+  // level 0 along each axis
+  Tri M[3], K[3];
+  const int n0[3] = {g0.nx, g0.ny, g0.nz};
+  for (int a = 0; a < 3; ++a) {
+    const int n = n0[a];
+    M[a] = Tri{std::vector<double>(n, 0.0), std::vector<double>(n, 1.0), std::vector<double>(n, 0.0)};
+    K[a] = Tri{std::vector<double>(n, 0.0), std::vector<double>(n, 0.0), std::vector<double>(n, 0.0)};
+    for (int i = 0; i < n; ++i) {
+      if (i > 0) { K[a].lo[i] = -1.0; K[a].di[i] += 1.0; }
+      if (i + 1 < n) { K[a].up[i] = -1.0; K[a].di[i] += 1.0; }
+    }
+  }
+  std::vector<double> host;
+  std::vector<size_t> at(3 * nl, 0);
+  for (int l = 1; l < nl; ++l) {
+    const GridDesc& p = H.lv[l - 1].h[0];
+    const GridDesc& g = H.lv[l].h[0];
+    const int fa[3] = {p.fx, p.fy, p.fz}, np_[3] = {p.nx, p.ny, p.nz}, nn[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+      M[a] = galerkin_1d(M[a], np_[a], fa[a] == 2);
+      K[a] = galerkin_1d(K[a], np_[a], fa[a] == 2);
+      if ((int)M[a].di.size() != nn[a]) throw std::logic_error("Hybrid tables: level size mismatch");
+      at[3 * l + a] = host.size();
+      for (const auto* v : {&M[a].lo, &M[a].di, &M[a].up, &K[a].lo, &K[a].di, &K[a].up})
+        host.insert(host.end(), v->begin(), v->end());
+    }
+  }
+  double* dev = (double*)H.alloc(std::max<size_t>(host.size(), 1) * sizeof(double));
+  if (!host.empty()) HIP_TRY(hipMemcpy(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+  H.hyb_dev = dev;
+  H.hyb.assign(nl, HybTables{});
+  for (int l = 0; l < nl; ++l) {
+    HybTables& T = H.hyb[l];
+    T.alpha = g0.alpha;
+    T.w[0] = g0.wx; T.w[1] = g0.wy; T.w[2] = g0.wz;
+    for (int a = 0; a < 3; ++a) T.t[a] = l == 0 ? nullptr : dev + at[3 * l + a];
+  }
+}
+
+static void prep(Hier& H, const gd_solve_opts& o) {
+  if (o.discretization == 1) ensure_hybrid(H);
+}
+
 struct Cycler {
   Hier& H;
   hipStream_t st;
@@ -605,15 +704,22 @@ struct Cycler {
   size_t ev_used = 0;
 
   bool fuse;
+  bool hyb;  // Hybrid discretisation: table levels >= 1, B-spline transfers
   Cycler(Hier& h, hipStream_t s, const gd_solve_opts& o)
       : H(h), st(s), pre(o.pre_smooth), post(o.post_smooth), pmode(o.prolong), timing(o.timing != 0),
-        fuse(o.fuse_prolong != 0) {}
+        fuse(o.fuse_prolong != 0), hyb(o.discretization == 1) {
+    if (hyb && H.hyb.empty()) throw std::logic_error("Hybrid tables not built before the cycle");
+  }
   ~Cycler() {
     for (auto& p : ev) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   }
 
   void sweep(int l, const void* ec) {
     Level& L = H.lv[l];
+    if (hyb && l > 0) {  // 27-point Galerkin level: 8-colour Gauss-Seidel in place
+      for (int c = 0; c < 8; ++c) HIP_TRY(launch_hyb_gs8(H.s, L.h[0], H.hyb[l], c, L.x, L.b, st));
+      return;
+    }
     const bool t = timing && l == 0;
     if (t) {
       if (ev_used == ev.size()) {
@@ -638,6 +744,16 @@ struct Cycler {
   void restrict_to(int l, bool norm) {
     Level& L = H.lv[l];
     Level& C = H.lv[l + 1];
+    if (hyb) {  // residual into the level's spare buffer, then P^T
+      if (l == 0) {
+        HIP_TRY(launch_general_residual(H.s, H.g_ew(0), L.x, L.b, L.xt, H.partials, st, true));
+        if (norm) HIP_TRY(launch_reduce(H.partials, L.ew.d_b0, 1, 2, H.dred, st));
+      } else {
+        HIP_TRY(launch_hyb_residual(H.s, L.h[0], H.hyb[l], L.x, L.b, L.xt, st));
+      }
+      HIP_TRY(launch_hyb_restrict(H.s, L.h[0], L.xt, C.b, C.x, st));
+      return;
+    }
     HIP_TRY(launch_restrict_z(H.s, H.g_rz(l), L.x, L.b, C.b, C.x, norm ? H.partials : nullptr, st));
     if (norm) HIP_TRY(launch_reduce(H.partials, L.rz.d_b0, H.ngrids, 1, H.dred, st));
   }
@@ -646,7 +762,10 @@ struct Cycler {
     below(l + 1);
     Level& C = H.lv[l + 1];
     const int np = (l == 0 && post0 >= 0) ? post0 : post;
-    if (fuse && np > 0 && H.lv[l].sw.tile == 0) {
+    if (hyb) {
+      HIP_TRY(launch_hyb_prolong(H.s, H.lv[l].h[0], C.x, H.lv[l].x, st));
+      smooth(l, np);
+    } else if (fuse && np > 0 && H.lv[l].sw.tile == 0) {
       smooth(l, np, C.x);  // prolongation fused into the first sweep's loads
     } else {
       HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), C.x, H.lv[l].x, pmode, H.lv[l].keep_x, st));
@@ -671,7 +790,8 @@ struct Cycler {
     for (int l = 0; l < last; ++l) restrict_to(l, false);  // x = 0: r = b
     smooth(last, 1);
     for (int l = last - 1; l >= 0; --l) {
-      HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), H.lv[l + 1].x, H.lv[l].x, pmode, H.lv[l].keep_x, st));
+      if (hyb) HIP_TRY(launch_hyb_prolong(H.s, H.lv[l].h[0], H.lv[l + 1].x, H.lv[l].x, st));
+      else HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), H.lv[l + 1].x, H.lv[l].x, pmode, H.lv[l].keep_x, st));
       full(l);
     }
   }
@@ -752,7 +872,8 @@ static bool graphs_on(const gd_solve_opts& o) { return o.use_graph != 0 && o.tim
 
 static std::string graph_key(const char* what, const gd_solve_opts& o) {
   char k[128];
-  std::snprintf(k, sizeof k, "%s|%d|%d|%d|%d", what, o.pre_smooth, o.post_smooth, o.prolong, o.fuse_prolong);
+  std::snprintf(k, sizeof k, "%s|%d|%d|%d|%d|%d", what, o.pre_smooth, o.post_smooth, o.prolong, o.fuse_prolong,
+                o.discretization);
   return k;
 }
 
@@ -830,6 +951,7 @@ static bool all_below(const std::vector<double>& r, const std::vector<double>& b
 // times the operator); when three successive cycles gain less than 30 %, the
 // solve stops there and reports the FP64 residual it reached.
 static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
+  prep(H, o);
   Outcome R;
   canonical_norms(H, P, H.lv[0].b, H.lv[0].x, R.bnorm, st);
   Cycler cy(H, st, o);
@@ -906,6 +1028,7 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
 // RMS of the residual before it (so that it is of order one), as the next
 // right-hand side.
 static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
+  prep(H, o);
   Outcome R;
   canonical_norms(H, P, nullptr, nullptr, R.bnorm, st);
   HIP_TRY(launch_refine_init(P.tin, H.g_ew(0), P.I0, H.x64, st));
@@ -969,6 +1092,7 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
 // residual, accumulated in FP64, is at most rel_tol times the canonical
 // ||b||.  The residual of E equals the canonical residual of I0 + E.
 static Outcome solve_npr(Hier& H, const gd_solve_opts& o, double bnorm, hipStream_t st) {
+  prep(H, o);
   Outcome R;
   R.bnorm = {bnorm};
   Cycler cy(H, st, o);
@@ -1049,6 +1173,8 @@ static gd_status run_guarded(const std::function<gd_status()>& f) {
     return fail(GD_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
   } catch (const std::bad_alloc&) {
     return fail(GD_ERR_NOMEM, "host allocation failed");
+  } catch (const Unsupported& e) {
+    return fail(GD_ERR_UNSUPPORTED, e.what());
   } catch (const std::exception& e) {
     return fail(GD_ERR_HIP, e.what());
   }
@@ -1077,6 +1203,7 @@ void gd_default_opts(gd_solve_opts* o) {
   o->sweep_tile = -1;
   o->use_graph = 1;
   o->fmg = 0;
+  o->discretization = 0;
 }
 
 const char* gd_last_error(void) { return t_err.c_str(); }
@@ -1085,7 +1212,8 @@ const char* gd_version(void) { return "gdstack 0.1 gfx950"; }
 static gd_status check_opts(const gd_solve_opts& o) {
   if (!(o.rel_tol > 0.0) || o.max_cycles < 0 || o.pre_smooth < 0 || o.post_smooth < 0 ||
       o.pre_smooth + o.post_smooth < 1 || !valid_dtype(o.storage) || o.inner_cycles < 1 ||
-      (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3)
+      (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3 ||
+      (o.discretization != 0 && o.discretization != 1))
     return fail(GD_ERR_INVALID, "invalid solver options");
   if (!o.fp64_refine && (o.storage == GD_F16 || o.storage == GD_BF16))
     return fail(GD_ERR_UNSUPPORTED, "16-bit storage needs fp64_refine = 1 (its rounding floor is far above 1e-6)");
@@ -1251,6 +1379,7 @@ static void mg_apply(gd_hierarchy* h, const void* r, void* z, hipStream_t st, bo
   const size_t wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es, rows = (size_t)g0.ny * g0.nz;
   HIP_TRY(hipMemcpy2DAsync(L0.b, pb, r, wb, wb, rows, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * es, st));
+  prep(H, h->o);
   Cycler cy(H, st, h->o);
   if (no_post) cy.post0 = 0;
   cy.full(0);
@@ -1344,6 +1473,7 @@ gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles, double
     const GridDesc& g0 = L0.h[0];
     const size_t es = dsize(H.s);
     const size_t wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es, rows = (size_t)g0.ny * g0.nz;
+    prep(H, h->o);
     Cycler cy(H, st, h->o);
     if (ncycles > 0) {
       HIP_TRY(hipMemcpy2DAsync(L0.x, pb, x, wb, wb, rows, hipMemcpyDeviceToDevice, st));
@@ -1381,6 +1511,7 @@ gd_status gd_mg_error_pairs(gd_hierarchy* h, const void* b, const void* x_star, 
     // x_k: k V-cycles from zero, left in e_out for the moment
     HIP_TRY(hipMemcpy2DAsync(L0.b, pb, b, wb, wb, rows, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * es, st));
+    prep(H, h->o);
     Cycler cy(H, st, h->o);
     for (int c = 0; c < cycles; ++c) cy.full(0);
     HIP_TRY(hipMemcpy2DAsync(e_out, wb, L0.x, pb, wb, rows, hipMemcpyDeviceToDevice, st));

@@ -77,6 +77,25 @@ hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const vo
 // (offset off, pitch px) instead of the caller's arrays.
 hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b, void* r_out,
                                    double* partials, hipStream_t st, bool lib_layout = false);
+// Hybrid discretisation (Sec. 4.2): a table level's operator is
+// alpha Mx My Mz + w_x Kx My Mz + w_y Mx Ky Mz + w_z Mx My Kz, t[a] the device
+// table block of axis a (six rows of n_a doubles: M below/on/above the
+// diagonal, then K).  G: the level's descriptor (one grid; offset and pitch
+// of the level arrays, child sizes and factors for the transfers).
+struct HybTables {
+  const double* t[3];
+  double alpha, w[3];
+};
+// one colour (0..7) of an 8-colour Gauss-Seidel sweep of a table level, in place
+hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int colour, void* x, const void* b,
+                          hipStream_t st);
+// r = b - A x on a table level
+hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T, const void* x, const void* b,
+                               void* r, hipStream_t st);
+// child b = P^T r and child x = 0 (B-spline nesting along the halved axes of G)
+hipError_t launch_hyb_restrict(gd_dtype s, const GridDesc& G, const void* r, void* bc, void* xc, hipStream_t st);
+// x += P e, e the child correction
+hipError_t launch_hyb_prolong(gd_dtype s, const GridDesc& G, const void* e, void* x, hipStream_t st);
 // Gradient-modulation filter (Sec. 6): the correction-form right-hand side
 // from I0 (caller's layout, dtype tin) into b (finest level, dtype s); per
 // block FP64 (sum of the canonical rhs squared, sum of b squared).

@@ -1368,6 +1368,182 @@ k_npr_rhs(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0
   }
 }
 
+// ------------------------------------------------ Hybrid discretisation
+//
+// Sec. 4.2 "Hybrid": the finest level keeps the 7-point operator; levels are
+// linked by the B-spline nesting (1/2, 1, 1/2) per halved axis (coarse
+// sample c on fine sample 2c; an odd last fine sample with no coarse sample
+// to its right takes the last one alone) and every coarser operator is the
+// Galerkin product, held as per-axis tridiagonal tables: a level's operator
+// is alpha Mx My Mz + w_x Kx My Mz + w_y Mx Ky Mz + w_z Mx My Kz.  A table
+// block of axis a (n_a samples) is six rows of n_a doubles: M below, on and
+// above the diagonal, then K likewise.  These levels are one grid each and
+// are addressed with the level's own offset and pitch.
+
+struct HybAxes {
+  const double* t[3];  // table blocks of x, y, z
+  double alpha, w[3];
+};
+
+// weight P[f][c] of coarse sample c in fine sample f along one axis (n fine,
+// nc coarse samples, halved or kept); 0 when c is not a parent of f
+__device__ __forceinline__ double bsp_weight(int f, int c, int n, int nc, bool halved) {
+  if (!halved) return f == c ? 1.0 : 0.0;
+  if (f == 2 * c) return 1.0;
+  if (f == 2 * c - 1) return 0.5;
+  if (f == 2 * c + 1 && f < n) return (c + 1 < nc) ? 0.5 : 1.0;
+  return 0.0;
+}
+
+// sum over the 27 neighbours of (row of A at (i, j, k)) . x, and the diagonal
+template <typename S>
+__device__ __forceinline__ void hyb_row(const HybAxes& A, const GridDesc& G, const S* __restrict__ x, int i, int j,
+                                        int k, double& ax, double& diag) {
+  const int n[3] = {G.nx, G.ny, G.nz}, c[3] = {i, j, k};
+  double m[3][3], kk[3][3];  // [axis][offset + 1]
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double* T = A.t[a];
+    const int na = n[a], q = c[a];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      m[a][d] = T[d * na + q];
+      kk[a][d] = T[(3 + d) * na + q];
+    }
+  }
+  const int64_t pl = (int64_t)G.px * G.ny;
+  double s = 0.0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int z = k + dz;
+    if (z < 0 || z >= G.nz) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int y = j + dy;
+      if (y < 0 || y >= G.ny) continue;
+      const double myz = m[1][dy + 1] * m[2][dz + 1];
+      const double kyz = kk[1][dy + 1] * m[2][dz + 1], mkz = m[1][dy + 1] * kk[2][dz + 1];
+      const S* row = x + G.off + z * pl + (int64_t)y * G.px;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = i + dx;
+        if (xx < 0 || xx >= G.nx) continue;
+        const double coef = (A.alpha * m[0][dx + 1] + A.w[0] * kk[0][dx + 1]) * myz +
+                            m[0][dx + 1] * (A.w[1] * kyz + A.w[2] * mkz);
+        s += coef * ld64(row + xx);
+      }
+    }
+  }
+  ax = s;
+  diag = (A.alpha * m[0][1] + A.w[0] * kk[0][1]) * m[1][1] * m[2][1] +
+         m[0][1] * (A.w[1] * kk[1][1] * m[2][1] + A.w[2] * m[1][1] * kk[2][1]);
+}
+
+// one colour of an 8-colour Gauss-Seidel sweep, in place: sample (i, j, k)
+// has colour (i & 1) + 2 (j & 1) + 4 (k & 1); samples of a colour are not
+// coupled by the 27-point stencil
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_hyb_gs8(GridDesc G, HybAxes A, int colour, S* __restrict__ x, const S* __restrict__ b) {
+  const int ci = colour & 1, cj = (colour >> 1) & 1, ck = colour >> 2;
+  const int64_t mx = (G.nx - ci + 1) / 2, my = (G.ny - cj + 1) / 2, mz = (G.nz - ck + 1) / 2;
+  const int64_t total = mx * my * mz;
+  const int64_t pl = (int64_t)G.px * G.ny;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int i = 2 * (int)(q % mx) + ci;
+    const int j = 2 * (int)((q / mx) % my) + cj;
+    const int k = 2 * (int)(q / (mx * my)) + ck;
+    double ax, d;
+    hyb_row(A, G, x, i, j, k, ax, d);
+    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
+    const double xc = ld64(x + v);
+    st64(x + v, d != 0.0 ? xc + (ld64(b + v) - ax) / d : 0.0);
+  }
+}
+
+// r = b - A x on a table level (all samples)
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_hyb_residual(GridDesc G, HybAxes A, const S* __restrict__ x, const S* __restrict__ b, S* __restrict__ r) {
+  const int64_t total = (int64_t)G.nx * G.ny * G.nz;
+  const int64_t pl = (int64_t)G.px * G.ny;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q % G.nx), j = (int)((q / G.nx) % G.ny), k = (int)(q / ((int64_t)G.nx * G.ny));
+    double ax, d;
+    hyb_row(A, G, x, i, j, k, ax, d);
+    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
+    st64(r + v, ld64(b + v) - ax);
+  }
+}
+
+// coarse b = P^T r (gathered by each coarse sample), coarse x = 0
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_hyb_restrict(GridDesc G, const S* __restrict__ r, S* __restrict__ bc, S* __restrict__ xc) {
+  const int64_t total = (int64_t)G.cnx * G.cny * G.cnz;
+  const int64_t pl = (int64_t)G.px * G.ny, cpl = (int64_t)G.cpx * G.cny;
+  const bool hx = G.fx == 2, hy = G.fy == 2, hz = G.fz == 2;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q % G.cnx), j = (int)((q / G.cnx) % G.cny), k = (int)(q / ((int64_t)G.cnx * G.cny));
+    const int x0 = hx ? 2 * i : i, y0 = hy ? 2 * j : j, z0 = hz ? 2 * k : k;
+    double s = 0.0;
+    for (int dz = (hz ? -1 : 0); dz <= (hz ? 1 : 0); ++dz) {
+      const int f = z0 + dz;
+      if (f < 0 || f >= G.nz) continue;
+      const double wz = bsp_weight(f, k, G.nz, G.cnz, hz);
+      for (int dy = (hy ? -1 : 0); dy <= (hy ? 1 : 0); ++dy) {
+        const int g = y0 + dy;
+        if (g < 0 || g >= G.ny) continue;
+        const double wyz = wz * bsp_weight(g, j, G.ny, G.cny, hy);
+        for (int dx = (hx ? -1 : 0); dx <= (hx ? 1 : 0); ++dx) {
+          const int h = x0 + dx;
+          if (h < 0 || h >= G.nx) continue;
+          s += wyz * bsp_weight(h, i, G.nx, G.cnx, hx) * ld64(r + G.off + f * pl + (int64_t)g * G.px + h);
+        }
+      }
+    }
+    const int64_t v = G.coff + k * cpl + (int64_t)j * G.cpx + i;
+    st64(bc + v, s);
+    st64(xc + v, 0.0);
+  }
+}
+
+// x += P e (each fine sample gathers its coarse parents)
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_hyb_prolong(GridDesc G, const S* __restrict__ e, S* __restrict__ x) {
+  const int64_t total = (int64_t)G.nx * G.ny * G.nz;
+  const int64_t pl = (int64_t)G.px * G.ny, cpl = (int64_t)G.cpx * G.cny;
+  const bool hx = G.fx == 2, hy = G.fy == 2, hz = G.fz == 2;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q % G.nx), j = (int)((q / G.nx) % G.ny), k = (int)(q / ((int64_t)G.nx * G.ny));
+    // parents along each axis: (index, weight) x 2 (weight 0 when absent)
+    int pa[3][2];
+    double pw[3][2];
+    const int f[3] = {i, j, k}, n[3] = {G.nx, G.ny, G.nz}, nc[3] = {G.cnx, G.cny, G.cnz};
+    const bool hv[3] = {hx, hy, hz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!hv[a]) { pa[a][0] = pa[a][1] = f[a]; pw[a][0] = 1.0; pw[a][1] = 0.0; continue; }
+      if ((f[a] & 1) == 0) { pa[a][0] = pa[a][1] = f[a] / 2; pw[a][0] = 1.0; pw[a][1] = 0.0; continue; }
+      const int lo = (f[a] - 1) / 2, hi = (f[a] + 1) / 2;
+      if (hi < nc[a]) { pa[a][0] = lo; pa[a][1] = hi; pw[a][0] = pw[a][1] = 0.5; }
+      else { pa[a][0] = pa[a][1] = lo; pw[a][0] = 1.0; pw[a][1] = 0.0; }
+      (void)n;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          const double wgt = pw[0][cx] * pw[1][cy] * pw[2][cz];
+          if (wgt != 0.0)
+            s += wgt * ld64(e + G.coff + pa[2][cz] * cpl + (int64_t)pa[1][cy] * G.cpx + pa[0][cx]);
+        }
+    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
+    st64(x + v, ld64(x + v) + s);
+  }
+}
+
 // ------------------------------------------------- Krylov vector kernels
 // (caller's layout, one grid).  q = A p with the per-block FP64 sum of p.q.
 template <typename S>
@@ -1701,6 +1877,51 @@ hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, con
     hipLaunchKernelGGL((k_general_residual<T, true>), GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, partials); \
   else                                                                                                            \
     hipLaunchKernelGGL((k_general_residual<T, false>), GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, partials)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+static unsigned gs_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
+}
+
+hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int colour, void* x, const void* b,
+                          hipStream_t st) {
+  const int ci = colour & 1, cj = (colour >> 1) & 1, ck = colour >> 2;
+  const int64_t n = (int64_t)((G.nx - ci + 1) / 2) * ((G.ny - cj + 1) / 2) * ((G.nz - ck + 1) / 2);
+  if (n == 0) return hipSuccess;
+  HybAxes A{{T.t[0], T.t[1], T.t[2]}, T.alpha, {T.w[0], T.w[1], T.w[2]}};
+#define L(TT) hipLaunchKernelGGL(k_hyb_gs8<TT>, dim3(gs_blocks(n)), dim3(256), 0, st, G, A, colour, (TT*)x, (const TT*)b)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T, const void* x, const void* b,
+                               void* r, hipStream_t st) {
+  const int64_t n = (int64_t)G.nx * G.ny * G.nz;
+  HybAxes A{{T.t[0], T.t[1], T.t[2]}, T.alpha, {T.w[0], T.w[1], T.w[2]}};
+#define L(TT) hipLaunchKernelGGL(k_hyb_residual<TT>, dim3(gs_blocks(n)), dim3(256), 0, st, G, A, (const TT*)x, \
+                                 (const TT*)b, (TT*)r)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+hipError_t launch_hyb_restrict(gd_dtype s, const GridDesc& G, const void* r, void* bc, void* xc, hipStream_t st) {
+  const int64_t n = (int64_t)G.cnx * G.cny * G.cnz;
+#define L(TT) hipLaunchKernelGGL(k_hyb_restrict<TT>, dim3(gs_blocks(n)), dim3(256), 0, st, G, (const TT*)r, (TT*)bc, \
+                                 (TT*)xc)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+hipError_t launch_hyb_prolong(gd_dtype s, const GridDesc& G, const void* e, void* x, hipStream_t st) {
+  const int64_t n = (int64_t)G.nx * G.ny * G.nz;
+#define L(TT) hipLaunchKernelGGL(k_hyb_prolong<TT>, dim3(gs_blocks(n)), dim3(256), 0, st, G, (const TT*)e, (TT*)x)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();

@@ -1,0 +1,118 @@
+"""The Hybrid discretisation (Sec. 4.2) on the GPU.
+
+One V-cycle of the library (7-point red-black relaxation on the finest
+level, 8-colour Gauss-Seidel on the Galerkin levels, B-spline transfers) is
+compared element by element with the same cycle composed from the oracle's
+step functions on the library's own level sizes: 1e-11 relative in FP64,
+1e-5 in FP32.  Whole solves must reach the same answer as the "Constant"
+solver: the DCT oracle's solution of the finest-level system.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import grid as og
+from oracle import hybrid, mgsteps, solvers
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def oracle_vcycle(x, b, sizes, alpha, w, pre, post):
+    """One V-cycle composed from oracle steps on the level sizes `sizes`
+    ([nz][ny][nx] per level, finest first)."""
+    last = len(sizes) - 1
+    halv = [[sizes[l + 1][::-1][a] != sizes[l][::-1][a] for l in range(last)] for a in range(3)]  # per axis x, y, z
+    n0 = sizes[0][::-1]
+    tabs = [hybrid.level_tables(n0[a], halv[a]) for a in range(3)]
+    mats = [[tabs[a][l] for a in range(3)] for l in range(last + 1)]
+    P = [hybrid.transfer_mats(sizes[l], [halv[a][l] for a in range(3)]) for l in range(last)]
+
+    def smooth(l, x, b, n):
+        for _ in range(n):
+            x = mgsteps.rb_sweep(x, b, alpha, w) if l == 0 else hybrid.gs8_sweep(x, b, mats[l], alpha, w)
+        return x
+
+    def full(l, x, b):
+        if l == last:
+            return smooth(l, x, b, 1)
+        x = smooth(l, x, b, pre)
+        r = mgsteps.residual(x, b, alpha, w) if l == 0 else b - hybrid.apply(x, mats[l], alpha, w)
+        bc = hybrid.restrict(r, P[l])
+        xc = full(l + 1, np.zeros(bc.shape), bc)
+        return smooth(l, x + hybrid.prolong(xc, P[l]), b, post)
+
+    return full(0, og.as3d(x), og.as3d(b))
+
+
+SHAPES = [(9, 17, 30), (8, 8, 8), (5, 33, 20), (1, 12, 40), (16, 3, 5), (2, 2, 2), (1, 1, 1), (12, 1, 7)]
+SYSTEMS = [(0.0, (1.0, 1.0, 4.0)), (0.01, (1.0, 1.0, 0.0)), (0.001, (1.0, 1.0, 0.1))]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("alpha,w", SYSTEMS)
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_one_vcycle_matches_oracle_steps(gd, shape, alpha, w, dt):
+    say("hybrid vcycle", shape, alpha, w, dt)
+    rng = np.random.default_rng(7)
+    x0, b = rng.standard_normal(shape), rng.standard_normal(shape)
+    if alpha == 0.0:
+        b -= b.mean()
+    xq = torch.from_numpy(x0).to(dt).double().numpy()
+    bq = torch.from_numpy(b).to(dt).double().numpy()
+    h = gd.Hierarchy(shape, alpha, w, dt, discretization=1, pre_smooth=1, post_smooth=2)
+    sizes = [h.info(l)[0] for l in range(h.info())]
+    x = torch.from_numpy(xq).to(dt).cuda()
+    h.vcycle(x, torch.from_numpy(bq).to(dt).cuda(), 1)
+    h.close()
+    ref = oracle_vcycle(xq, bq, sizes, alpha, w, 1, 2)
+    tol = 1e-11 if dt == torch.float64 else 1e-5
+    assert np.abs(x.double().cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape", [(16, 64, 64), (7, 45, 99), (32, 128, 96)])
+def test_ad_solve_hybrid_same_answer(gd, shape):
+    say("hybrid AD", shape)
+    nz, ny, nx = shape
+    I0 = synth.make_stack(synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100422)).numpy()
+    ref = solvers.ad_dct(I0, (1.0, 1.0, 4.0))
+    out, rep = gd.smooth_z(torch.from_numpy(I0).cuda(), (1.0, 1.0, 4.0), storage=gd.F64, rel_tol=1e-10,
+                           discretization=1)
+    assert rep["status"] == 0 and rep["rel_residual"] <= 1e-10
+    assert np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
+    # the same system with the Constant transfers, for the cycle counts
+    _, rep0 = gd.smooth_z(torch.from_numpy(I0).cuda(), (1.0, 1.0, 4.0), storage=gd.F64, rel_tol=1e-10)
+    say("cycles hybrid", rep["cycles"], "constant", rep0["cycles"])
+
+
+def test_ad_mixed_fp16_hybrid(gd):
+    say("hybrid AD f16 + FP64 refinement")
+    I0t = synth.make_stack(synth.StackSpec(96, 80, 24, (4.0, 40.0), True, 13100423)).to(torch.float16)
+    I0 = I0t.double().numpy()
+    out, rep = gd.smooth_z(I0t.cuda(), (1.0, 1.0, 4.0), out_dtype=torch.float64, storage=gd.F16, fp64_refine=1,
+                           discretization=1)
+    assert rep["status"] == 0 and rep["rel_residual"] <= 1e-6
+    ref = solvers.ad_dct(I0, (1.0, 1.0, 4.0))
+    assert np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+def test_npr_hybrid(gd):
+    say("hybrid NPR")
+    from oracle import npr
+    I0 = synth.make_video(synth.VideoSpec(80, 48, 10)).numpy()
+    ref = npr.npr_filter(I0)
+    out, rep = gd.npr_filter(torch.from_numpy(I0).cuda(), storage=gd.F64, rel_tol=1e-11, discretization=1)
+    assert rep["status"] == 0
+    assert np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
+
+
+def test_slice_batch_hybrid_unsupported(gd):
+    I0 = torch.rand(3, 16, 32, device="cuda")
+    with pytest.raises(gd.GDError) as ei:
+        gd.screened_poisson_stack(I0, I0.clone(), 0.01, discretization=1)
+    assert ei.value.status == gd.ERR_UNSUPPORTED
