@@ -48,6 +48,11 @@ def parse():
     p.add_argument("--cpu-crop", default="32,192,192", help="nz,ny,nx of the oracle's crop")
     p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
     p.add_argument("--fmg", type=int, default=None, help="1: full-multigrid start of the plain solves")
+    p.add_argument("--discretization", default="constant", choices=["constant", "hybrid"],
+                   help="transfers and coarse operators of the AD solve (Sec. 4.2); the per-slice SP batch "
+                        "always uses the Constant scheme")
+    p.add_argument("--prolong", default="trilinear", choices=["trilinear", "constant"],
+                   help="up-sampling of the Constant scheme: cell-centred trilinear or replication")
     p.add_argument("--inner-cycles", type=int, default=None,
                    help="V-cycles per FP64 refinement step (mixed storage; library default if omitted)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -338,9 +343,11 @@ def main():
         opts["inner_cycles"] = a.inner_cycles
     if a.fmg is not None:
         opts["fmg"] = a.fmg
+    opts["prolong"] = 0 if a.prolong == "trilinear" else 1
+    ad_opts = dict(opts, discretization=1 if a.discretization == "hybrid" else 0)
 
     def step(timing):
-        I1, r1 = gd.smooth_z(I0, BETA, out_dtype=out_dtype, timing=timing, **opts)
+        I1, r1 = gd.smooth_z(I0, BETA, out_dtype=out_dtype, timing=timing, **ad_opts)
         I2, r2, per = gd.screened_poisson_stack(I0, I1.to(I0.dtype), ALPHA, timing=timing, **opts)
         return r1, r2
 
@@ -392,7 +399,9 @@ def main():
         "dtype": {"f32": "f32", "f16": "f16+f64", "bf16": "bf16+f64"}[storage],
         "data": "synthetic",
         "config": {
-            "workload": f"{a.workload}: {desc}; beta=(1,1,4), alpha={ALPHA}, Neumann, tol {TOL:g}",
+            "workload": f"{a.workload}: {desc}; beta=(1,1,4), alpha={ALPHA}, Neumann, tol {TOL:g}"
+                        + ("" if a.discretization == "constant" and a.prolong == "trilinear"
+                           else f"; AD {a.discretization} discretisation, {a.prolong} up-sampling"),
             "nx": spec.nx, "ny": spec.ny, "nz": spec.nz, "voxels": nvox, "smooth": [pre, post],
         },
         "roofline": {
@@ -410,8 +419,10 @@ def main():
             "other_finest_sweeps": others,
         },
         "ad": {"cycles": r1["cycles"], "refine_steps": r1["refine_steps"], "rel_residual": r1["rel_residual"],
-               "levels": r1["levels"]},
-        "sp": {"cycles": r2["cycles"], "refine_steps": r2["refine_steps"], "rel_residual": r2["rel_residual"]},
+               "levels": r1["levels"], "discretization": a.discretization, "prolong": a.prolong,
+               "factor_per_cycle": r1["rel_residual"] ** (1.0 / max(r1["cycles"], 1))},
+        "sp": {"cycles": r2["cycles"], "refine_steps": r2["refine_steps"], "rel_residual": r2["rel_residual"],
+               "factor_per_cycle": r2["rel_residual"] ** (1.0 / max(r2["cycles"], 1))},
         "generate_s": gen_s,
     }
     if not a.no_cpu_baseline:

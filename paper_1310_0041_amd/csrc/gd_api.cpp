@@ -142,6 +142,8 @@ struct Hier {
   // Hybrid discretisation: per-level table blocks (levels >= 1) on the device
   std::vector<HybTables> hyb;
   double* hyb_dev = nullptr;
+  double* hyb_part = nullptr;   // per-block r^2 of the finest Hybrid residual
+  int64_t* hyb_b0 = nullptr;    // {0, its block count}
 
   // Captured V-cycle segments (see CycleGraphs): two executables that map
   // the level buffers' ping-pong state A -> B and B -> A.
@@ -650,6 +652,8 @@ static void ensure_hybrid(Hier& H) {
   if (H.ngrids != 1) throw Unsupported("the Hybrid discretisation is built for single-grid solves only");
   const int nl = (int)H.lv.size();
   const GridDesc& g0 = H.lv[0].h[0];
+  if (g0.ny > 65535 * 4 || g0.nz > 65535 * 4)
+    throw Unsupported("the Hybrid discretisation needs ny and nz <= 262140");
   // level 0 along each axis
   Tri M[3], K[3];
   const int n0[3] = {g0.nx, g0.ny, g0.nz};
@@ -680,6 +684,11 @@ static void ensure_hybrid(Hier& H) {
   double* dev = (double*)H.alloc(std::max<size_t>(host.size(), 1) * sizeof(double));
   if (!host.empty()) HIP_TRY(hipMemcpy(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
   H.hyb_dev = dev;
+  const int64_t nb = hyb_residual7_blocks(g0);
+  H.hyb_part = (double*)H.alloc(nb * sizeof(double));
+  H.hyb_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
+  const int64_t b0[2] = {0, nb};
+  HIP_TRY(hipMemcpy(H.hyb_b0, b0, sizeof b0, hipMemcpyHostToDevice));
   H.hyb.assign(nl, HybTables{});
   for (int l = 0; l < nl; ++l) {
     HybTables& T = H.hyb[l];
@@ -746,8 +755,8 @@ struct Cycler {
     Level& C = H.lv[l + 1];
     if (hyb) {  // residual into the level's spare buffer, then P^T
       if (l == 0) {
-        HIP_TRY(launch_general_residual(H.s, H.g_ew(0), L.x, L.b, L.xt, H.partials, st, true));
-        if (norm) HIP_TRY(launch_reduce(H.partials, L.ew.d_b0, 1, 2, H.dred, st));
+        HIP_TRY(launch_hyb_residual7(H.s, L.h[0], L.x, L.b, L.xt, H.hyb_part, st));
+        if (norm) HIP_TRY(launch_reduce(H.hyb_part, H.hyb_b0, 1, 1, H.dred, st));
       } else {
         HIP_TRY(launch_hyb_residual(H.s, L.h[0], H.hyb[l], L.x, L.b, L.xt, st));
       }

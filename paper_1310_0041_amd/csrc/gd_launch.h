@@ -92,6 +92,11 @@ hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int
 // r = b - A x on a table level
 hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T, const void* x, const void* b,
                                void* r, hipStream_t st);
+// r = b - A x on the finest (7-point) level of a Hybrid hierarchy, with
+// per-block FP64 sums of r^2 in partials[0 .. hyb_residual7_blocks(G))
+int64_t hyb_residual7_blocks(const GridDesc& G);
+hipError_t launch_hyb_residual7(gd_dtype s, const GridDesc& G, const void* x, const void* b, void* r,
+                                double* partials, hipStream_t st);
 // child b = P^T r and child x = 0 (B-spline nesting along the halved axes of G)
 hipError_t launch_hyb_restrict(gd_dtype s, const GridDesc& G, const void* r, void* bc, void* xc, hipStream_t st);
 // x += P e, e the child correction

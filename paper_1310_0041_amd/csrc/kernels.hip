@@ -1395,61 +1395,65 @@ __device__ __forceinline__ double bsp_weight(int f, int c, int n, int nc, bool h
   return 0.0;
 }
 
-// sum over the 27 neighbours of (row of A at (i, j, k)) . x, and the diagonal
+// sum over the 27 neighbours of (row of A at (i, j, k)) . x, and the diagonal.
+// Branch-free: a neighbour outside the grid is read at a clamped index and
+// weighted by its table entry, which is 0 (the first sample has no lower and
+// the last no upper coupling on every level), so all 27 loads issue at once.
 template <typename S>
 __device__ __forceinline__ void hyb_row(const HybAxes& A, const GridDesc& G, const S* __restrict__ x, int i, int j,
                                         int k, double& ax, double& diag) {
   const int n[3] = {G.nx, G.ny, G.nz}, c[3] = {i, j, k};
   double m[3][3], kk[3][3];  // [axis][offset + 1]
+  int q[3][3];               // clamped neighbour index [axis][offset + 1]
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double* T = A.t[a];
-    const int na = n[a], q = c[a];
+    const int na = n[a], p = c[a];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      m[a][d] = T[d * na + q];
-      kk[a][d] = T[(3 + d) * na + q];
+      m[a][d] = T[d * na + p];
+      kk[a][d] = T[(3 + d) * na + p];
+      q[a][d] = min(max(p + d - 1, 0), na - 1);
     }
   }
   const int64_t pl = (int64_t)G.px * G.ny;
+  const S* base = x + G.off;
   double s = 0.0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int z = k + dz;
-    if (z < 0 || z >= G.nz) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int y = j + dy;
-      if (y < 0 || y >= G.ny) continue;
-      const double myz = m[1][dy + 1] * m[2][dz + 1];
-      const double kyz = kk[1][dy + 1] * m[2][dz + 1], mkz = m[1][dy + 1] * kk[2][dz + 1];
-      const S* row = x + G.off + z * pl + (int64_t)y * G.px;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xx = i + dx;
-        if (xx < 0 || xx >= G.nx) continue;
-        const double coef = (A.alpha * m[0][dx + 1] + A.w[0] * kk[0][dx + 1]) * myz +
-                            m[0][dx + 1] * (A.w[1] * kyz + A.w[2] * mkz);
-        s += coef * ld64(row + xx);
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const double myz = m[1][dy] * m[2][dz], kyz = kk[1][dy] * m[2][dz], mkz = m[1][dy] * kk[2][dz];
+      const S* row = base + q[2][dz] * pl + (int64_t)q[1][dy] * G.px;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const double coef = (A.alpha * m[0][dx] + A.w[0] * kk[0][dx]) * myz + m[0][dx] * (A.w[1] * kyz + A.w[2] * mkz);
+        s += coef * ld64(row + q[0][dx]);
       }
     }
-  }
   ax = s;
   diag = (A.alpha * m[0][1] + A.w[0] * kk[0][1]) * m[1][1] * m[2][1] +
          m[0][1] * (A.w[1] * kk[1][1] * m[2][1] + A.w[2] * m[1][1] * kk[2][1]);
 }
 
+// Table-level kernels run on a 3-D launch: a block is 64 x 4 samples of one
+// (x, y) tile, a thread HZ consecutive z-samples (no index division).
+constexpr int HBX = 64, HBY = 4, HZ = 4;
+
 // one colour of an 8-colour Gauss-Seidel sweep, in place: sample (i, j, k)
 // has colour (i & 1) + 2 (j & 1) + 4 (k & 1); samples of a colour are not
-// coupled by the 27-point stencil
+// coupled by the 27-point stencil.  The launch spans the colour's
+// sub-lattice (i = 2 ii + ci, ...).
 template <typename S>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(HBX * HBY)
 k_hyb_gs8(GridDesc G, HybAxes A, int colour, S* __restrict__ x, const S* __restrict__ b) {
   const int ci = colour & 1, cj = (colour >> 1) & 1, ck = colour >> 2;
-  const int64_t mx = (G.nx - ci + 1) / 2, my = (G.ny - cj + 1) / 2, mz = (G.nz - ck + 1) / 2;
-  const int64_t total = mx * my * mz;
+  const int i = 2 * (int)(blockIdx.x * HBX + threadIdx.x) + ci, j = 2 * (int)(blockIdx.y * HBY + threadIdx.y) + cj;
+  if (i >= G.nx || j >= G.ny) return;
   const int64_t pl = (int64_t)G.px * G.ny;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int i = 2 * (int)(q % mx) + ci;
-    const int j = 2 * (int)((q / mx) % my) + cj;
-    const int k = 2 * (int)(q / (mx * my)) + ck;
+  for (int kk = blockIdx.z * HZ; kk < (int)(blockIdx.z + 1) * HZ; ++kk) {
+    const int k = 2 * kk + ck;
+    if (k >= G.nz) break;
     double ax, d;
     hyb_row(A, G, x, i, j, k, ax, d);
     const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
@@ -1460,12 +1464,12 @@ k_hyb_gs8(GridDesc G, HybAxes A, int colour, S* __restrict__ x, const S* __restr
 
 // r = b - A x on a table level (all samples)
 template <typename S>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(HBX * HBY)
 k_hyb_residual(GridDesc G, HybAxes A, const S* __restrict__ x, const S* __restrict__ b, S* __restrict__ r) {
-  const int64_t total = (int64_t)G.nx * G.ny * G.nz;
+  const int i = blockIdx.x * HBX + threadIdx.x, j = blockIdx.y * HBY + threadIdx.y;
+  if (i >= G.nx || j >= G.ny) return;
   const int64_t pl = (int64_t)G.px * G.ny;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(q % G.nx), j = (int)((q / G.nx) % G.ny), k = (int)(q / ((int64_t)G.nx * G.ny));
+  for (int k = blockIdx.z * HZ; k < min((int)(blockIdx.z + 1) * HZ, G.nz); ++k) {
     double ax, d;
     hyb_row(A, G, x, i, j, k, ax, d);
     const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
@@ -1473,16 +1477,71 @@ k_hyb_residual(GridDesc G, HybAxes A, const S* __restrict__ x, const S* __restri
   }
 }
 
+// r = b - A x on the finest (7-point) level, with the FP64 sum of r^2 per
+// block (partials[block], block = x + gx (y + gy z)), summed in a fixed
+// order.  A thread takes HZ7 z-samples; a full chunk is unrolled so that its
+// loads issue together.
+constexpr int HZ7 = 8;
+
+template <typename S>
+__global__ void __launch_bounds__(HBX * HBY)
+k_hyb_residual7(GridDesc G, const S* __restrict__ x, const S* __restrict__ b, S* __restrict__ r,
+                double* __restrict__ partials) {
+  using C = typename Ty<S>::C;
+  __shared__ double red[HBY];
+  const int i = blockIdx.x * HBX + threadIdx.x, j = blockIdx.y * HBY + threadIdx.y;
+  double rr = 0.0;
+  if (i < G.nx && j < G.ny) {
+    const int64_t pl = (int64_t)G.px * G.ny, py = G.px;
+    const C alpha = (C)G.alpha;
+    const C wl = i > 0 ? (C)G.wx : (C)0, wr = i + 1 < G.nx ? (C)G.wx : (C)0;
+    const C wd = j > 0 ? (C)G.wy : (C)0, wu = j + 1 < G.ny ? (C)G.wy : (C)0;
+    const int64_t ol = i > 0 ? -1 : 0, orr = i + 1 < G.nx ? 1 : 0, od = j > 0 ? -py : 0, ou = j + 1 < G.ny ? py : 0;
+    auto one = [&](int k) {
+      const int64_t v = G.off + k * pl + (int64_t)j * py + i;
+      const C wb = k > 0 ? (C)G.wz : (C)0, wf = k + 1 < G.nz ? (C)G.wz : (C)0;
+      const int64_t ob = k > 0 ? -pl : 0, of = k + 1 < G.nz ? pl : 0;
+      const C xc = Ty<S>::ld(x + v);
+      C q = Ty<S>::ld(b + v) - alpha * xc;
+      q += wl * (Ty<S>::ld(x + v + ol) - xc);
+      q += wr * (Ty<S>::ld(x + v + orr) - xc);
+      q += wd * (Ty<S>::ld(x + v + od) - xc);
+      q += wu * (Ty<S>::ld(x + v + ou) - xc);
+      q += wb * (Ty<S>::ld(x + v + ob) - xc);
+      q += wf * (Ty<S>::ld(x + v + of) - xc);
+      Ty<S>::st(r + v, q);
+      rr += (double)q * (double)q;
+    };
+    const int k0 = blockIdx.z * HZ7;
+    if (k0 + HZ7 <= G.nz) {
+#pragma unroll
+      for (int t = 0; t < HZ7; ++t) one(k0 + t);
+    } else {
+      for (int k = k0; k < G.nz; ++k) one(k);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o, 64);
+  if (threadIdx.x == 0) red[threadIdx.y] = rr;
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    double t = 0.0;
+    for (int w = 0; w < HBY; ++w) t += red[w];
+    partials[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = t;
+  }
+}
+
 // coarse b = P^T r (gathered by each coarse sample), coarse x = 0
 template <typename S>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(HBX * HBY)
 k_hyb_restrict(GridDesc G, const S* __restrict__ r, S* __restrict__ bc, S* __restrict__ xc) {
-  const int64_t total = (int64_t)G.cnx * G.cny * G.cnz;
+  const int i = blockIdx.x * HBX + threadIdx.x, j = blockIdx.y * HBY + threadIdx.y;
+  if (i >= G.cnx || j >= G.cny) return;
   const int64_t pl = (int64_t)G.px * G.ny, cpl = (int64_t)G.cpx * G.cny;
   const bool hx = G.fx == 2, hy = G.fy == 2, hz = G.fz == 2;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(q % G.cnx), j = (int)((q / G.cnx) % G.cny), k = (int)(q / ((int64_t)G.cnx * G.cny));
-    const int x0 = hx ? 2 * i : i, y0 = hy ? 2 * j : j, z0 = hz ? 2 * k : k;
+  const int x0 = hx ? 2 * i : i, y0 = hy ? 2 * j : j;
+  for (int k = blockIdx.z * HZ; k < min((int)(blockIdx.z + 1) * HZ, G.cnz); ++k) {
+    const int z0 = hz ? 2 * k : k;
     double s = 0.0;
     for (int dz = (hz ? -1 : 0); dz <= (hz ? 1 : 0); ++dz) {
       const int f = z0 + dz;
@@ -1507,27 +1566,26 @@ k_hyb_restrict(GridDesc G, const S* __restrict__ r, S* __restrict__ bc, S* __res
 
 // x += P e (each fine sample gathers its coarse parents)
 template <typename S>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(HBX * HBY)
 k_hyb_prolong(GridDesc G, const S* __restrict__ e, S* __restrict__ x) {
-  const int64_t total = (int64_t)G.nx * G.ny * G.nz;
+  const int i = blockIdx.x * HBX + threadIdx.x, j = blockIdx.y * HBY + threadIdx.y;
+  if (i >= G.nx || j >= G.ny) return;
   const int64_t pl = (int64_t)G.px * G.ny, cpl = (int64_t)G.cpx * G.cny;
-  const bool hx = G.fx == 2, hy = G.fy == 2, hz = G.fz == 2;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(q % G.nx), j = (int)((q / G.nx) % G.ny), k = (int)(q / ((int64_t)G.nx * G.ny));
-    // parents along each axis: (index, weight) x 2 (weight 0 when absent)
-    int pa[3][2];
-    double pw[3][2];
-    const int f[3] = {i, j, k}, n[3] = {G.nx, G.ny, G.nz}, nc[3] = {G.cnx, G.cny, G.cnz};
-    const bool hv[3] = {hx, hy, hz};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (!hv[a]) { pa[a][0] = pa[a][1] = f[a]; pw[a][0] = 1.0; pw[a][1] = 0.0; continue; }
-      if ((f[a] & 1) == 0) { pa[a][0] = pa[a][1] = f[a] / 2; pw[a][0] = 1.0; pw[a][1] = 0.0; continue; }
-      const int lo = (f[a] - 1) / 2, hi = (f[a] + 1) / 2;
-      if (hi < nc[a]) { pa[a][0] = lo; pa[a][1] = hi; pw[a][0] = pw[a][1] = 0.5; }
-      else { pa[a][0] = pa[a][1] = lo; pw[a][0] = 1.0; pw[a][1] = 0.0; }
-      (void)n;
-    }
+  const bool hv[3] = {G.fx == 2, G.fy == 2, G.fz == 2};
+  const int nc[3] = {G.cnx, G.cny, G.cnz};
+  // parents along an axis: (index, weight) x 2, weight 0 when absent
+  auto parents = [&](int a, int f, int* pa, double* pw) {
+    if (!hv[a] || (f & 1) == 0) { pa[0] = pa[1] = hv[a] ? f / 2 : f; pw[0] = 1.0; pw[1] = 0.0; return; }
+    const int lo = (f - 1) / 2, hi = (f + 1) / 2;
+    if (hi < nc[a]) { pa[0] = lo; pa[1] = hi; pw[0] = pw[1] = 0.5; }
+    else { pa[0] = pa[1] = lo; pw[0] = 1.0; pw[1] = 0.0; }
+  };
+  int px_[2], py_[2], pz_[2];
+  double wx_[2], wy_[2], wz_[2];
+  parents(0, i, px_, wx_);
+  parents(1, j, py_, wy_);
+  for (int k = blockIdx.z * HZ; k < min((int)(blockIdx.z + 1) * HZ, G.nz); ++k) {
+    parents(2, k, pz_, wz_);
     double s = 0.0;
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz)
@@ -1535,9 +1593,8 @@ k_hyb_prolong(GridDesc G, const S* __restrict__ e, S* __restrict__ x) {
       for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
         for (int cx = 0; cx < 2; ++cx) {
-          const double wgt = pw[0][cx] * pw[1][cy] * pw[2][cz];
-          if (wgt != 0.0)
-            s += wgt * ld64(e + G.coff + pa[2][cz] * cpl + (int64_t)pa[1][cy] * G.cpx + pa[0][cx]);
+          const double wgt = wx_[cx] * wy_[cy] * wz_[cz];
+          if (wgt != 0.0) s += wgt * ld64(e + G.coff + pz_[cz] * cpl + (int64_t)py_[cy] * G.cpx + px_[cx]);
         }
     const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
     st64(x + v, ld64(x + v) + s);
@@ -1882,18 +1939,18 @@ hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, con
   return last();
 }
 
-static unsigned gs_blocks(int64_t n) {
-  const int64_t b = (n + 255) / 256;
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
+static dim3 hyb_grid(int64_t nx, int64_t ny, int64_t nz) {
+  return dim3((unsigned)((nx + HBX - 1) / HBX), (unsigned)((ny + HBY - 1) / HBY), (unsigned)((nz + HZ - 1) / HZ));
 }
 
 hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int colour, void* x, const void* b,
                           hipStream_t st) {
   const int ci = colour & 1, cj = (colour >> 1) & 1, ck = colour >> 2;
-  const int64_t n = (int64_t)((G.nx - ci + 1) / 2) * ((G.ny - cj + 1) / 2) * ((G.nz - ck + 1) / 2);
-  if (n == 0) return hipSuccess;
+  const int64_t mx = (G.nx - ci + 1) / 2, my = (G.ny - cj + 1) / 2, mz = (G.nz - ck + 1) / 2;
+  if (mx * my * mz == 0) return hipSuccess;
   HybAxes A{{T.t[0], T.t[1], T.t[2]}, T.alpha, {T.w[0], T.w[1], T.w[2]}};
-#define L(TT) hipLaunchKernelGGL(k_hyb_gs8<TT>, dim3(gs_blocks(n)), dim3(256), 0, st, G, A, colour, (TT*)x, (const TT*)b)
+#define L(TT) hipLaunchKernelGGL(k_hyb_gs8<TT>, hyb_grid(mx, my, mz), dim3(HBX, HBY), 0, st, G, A, colour, (TT*)x, \
+                                 (const TT*)b)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();
@@ -1901,27 +1958,44 @@ hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int
 
 hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T, const void* x, const void* b,
                                void* r, hipStream_t st) {
-  const int64_t n = (int64_t)G.nx * G.ny * G.nz;
   HybAxes A{{T.t[0], T.t[1], T.t[2]}, T.alpha, {T.w[0], T.w[1], T.w[2]}};
-#define L(TT) hipLaunchKernelGGL(k_hyb_residual<TT>, dim3(gs_blocks(n)), dim3(256), 0, st, G, A, (const TT*)x, \
-                                 (const TT*)b, (TT*)r)
+#define L(TT) hipLaunchKernelGGL(k_hyb_residual<TT>, hyb_grid(G.nx, G.ny, G.nz), dim3(HBX, HBY), 0, st, G, A, \
+                                 (const TT*)x, (const TT*)b, (TT*)r)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+static dim3 hyb7_grid(const GridDesc& G) {
+  return dim3((unsigned)((G.nx + HBX - 1) / HBX), (unsigned)((G.ny + HBY - 1) / HBY),
+              (unsigned)((G.nz + HZ7 - 1) / HZ7));
+}
+
+int64_t hyb_residual7_blocks(const GridDesc& G) {
+  const dim3 g = hyb7_grid(G);
+  return (int64_t)g.x * g.y * g.z;
+}
+
+hipError_t launch_hyb_residual7(gd_dtype s, const GridDesc& G, const void* x, const void* b, void* r,
+                                double* partials, hipStream_t st) {
+#define L(TT) hipLaunchKernelGGL(k_hyb_residual7<TT>, hyb7_grid(G), dim3(HBX, HBY), 0, st, G, \
+                                 (const TT*)x, (const TT*)b, (TT*)r, partials)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();
 }
 
 hipError_t launch_hyb_restrict(gd_dtype s, const GridDesc& G, const void* r, void* bc, void* xc, hipStream_t st) {
-  const int64_t n = (int64_t)G.cnx * G.cny * G.cnz;
-#define L(TT) hipLaunchKernelGGL(k_hyb_restrict<TT>, dim3(gs_blocks(n)), dim3(256), 0, st, G, (const TT*)r, (TT*)bc, \
-                                 (TT*)xc)
+#define L(TT) hipLaunchKernelGGL(k_hyb_restrict<TT>, hyb_grid(G.cnx, G.cny, G.cnz), dim3(HBX, HBY), 0, st, G, \
+                                 (const TT*)r, (TT*)bc, (TT*)xc)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();
 }
 
 hipError_t launch_hyb_prolong(gd_dtype s, const GridDesc& G, const void* e, void* x, hipStream_t st) {
-  const int64_t n = (int64_t)G.nx * G.ny * G.nz;
-#define L(TT) hipLaunchKernelGGL(k_hyb_prolong<TT>, dim3(gs_blocks(n)), dim3(256), 0, st, G, (const TT*)e, (TT*)x)
+#define L(TT) hipLaunchKernelGGL(k_hyb_prolong<TT>, hyb_grid(G.nx, G.ny, G.nz), dim3(HBX, HBY), 0, st, G, \
+                                 (const TT*)e, (TT*)x)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();
