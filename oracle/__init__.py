@@ -24,6 +24,9 @@ Image Stacks"):
 * ``hybrid``    -- the steps of the "Hybrid" discretisation of Sec. 4.2:
                    B-spline prolongation (1/2, 1, 1/2), its transpose, Galerkin
                    coarse operators from per-axis 1-D tables, 8-colour GS.
+* ``linear``    -- the "Linear" discretisation of Sec. 4.2 (trilinear B-spline
+                   finite elements): mass/stiffness tables, the AD right-hand
+                   side and its solution (a different answer from the 7-point one).
 * ``mgsteps``   -- single multigrid steps (Sec. 4.1): one red-black
                    Gauss-Seidel sweep, the residual, restriction by summing
                    children, constant and cell-centred trilinear prolongation,
