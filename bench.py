@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--cpu-crop", default="32,192,192", help="nz,ny,nx of the oracle's crop")
     p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
     p.add_argument("--fmg", type=int, default=None, help="1: full-multigrid start of the plain solves")
-    p.add_argument("--discretization", default="constant", choices=["constant", "hybrid"],
+    p.add_argument("--discretization", default="constant", choices=["constant", "hybrid", "linear"],
                    help="transfers and coarse operators of the AD solve (Sec. 4.2); the per-slice SP batch "
                         "always uses the Constant scheme")
     p.add_argument("--prolong", default="trilinear", choices=["trilinear", "constant"],
@@ -344,7 +344,7 @@ def main():
     if a.fmg is not None:
         opts["fmg"] = a.fmg
     opts["prolong"] = 0 if a.prolong == "trilinear" else 1
-    ad_opts = dict(opts, discretization=1 if a.discretization == "hybrid" else 0)
+    ad_opts = dict(opts, discretization={"constant": 0, "hybrid": 1, "linear": 2}[a.discretization])
 
     def step(timing):
         I1, r1 = gd.smooth_z(I0, BETA, out_dtype=out_dtype, timing=timing, **ad_opts)

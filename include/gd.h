@@ -90,8 +90,12 @@ typedef struct {
                            7-point finest level, B-spline (1/2, 1, 1/2)
                            prolongation, its transpose as restriction and
                            Galerkin 27-point coarse operators relaxed by
-                           8-colour Gauss-Seidel.  Same answer; single-grid
-                           solves only (slice batches: GD_ERR_UNSUPPORTED). */
+                           8-colour Gauss-Seidel (same answer); 2 "Linear":
+                           trilinear B-spline finite elements on every level
+                           (27-point, a different discrete answer; AD and the
+                           hierarchy calls only, no FP64 refinement).  1 and 2
+                           take single-grid solves only (slice batches:
+                           GD_ERR_UNSUPPORTED). */
 } gd_solve_opts;
 
 /* Filled by the solve calls when the pointer is non-NULL. */

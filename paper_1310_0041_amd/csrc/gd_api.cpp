@@ -140,10 +140,12 @@ struct Hier {
   double* x64b = nullptr;    // its next value (the fused update writes here)
   std::vector<int64_t> cells;  // finest cells per grid
   // Hybrid discretisation: per-level table blocks (levels >= 1) on the device
-  std::vector<HybTables> hyb;
-  double* hyb_dev = nullptr;
-  double* hyb_part = nullptr;   // per-block r^2 of the finest Hybrid residual
-  int64_t* hyb_b0 = nullptr;    // {0, its block count}
+  // Hybrid (hyb) and Linear (lin) discretisations: per-level table blocks on
+  // the device (Hybrid: levels >= 1; Linear: every level)
+  std::vector<HybTables> hyb, lin;
+  double* hyb_part = nullptr;   // per-block r^2 of a finest-level residual
+  int64_t* hyb_b0 = nullptr;    // {0, block count} of the 7-point residual
+  int64_t* tab_b0 = nullptr;    // {0, block count} of the table residual
 
   // Captured V-cycle segments (see CycleGraphs): two executables that map
   // the level buffers' ping-pong state A -> B and B -> A.
@@ -647,14 +649,18 @@ static Tri galerkin_1d(const Tri& T, int n, bool halved) {
   return C;
 }
 
-static void ensure_hybrid(Hier& H) {
-  if (!H.hyb.empty()) return;
-  if (H.ngrids != 1) throw Unsupported("the Hybrid discretisation is built for single-grid solves only");
+// Tables of the Hybrid (disc 1) or Linear (disc 2) discretisation.  Along
+// one axis level 0 has K_0 = L (Neumann 3-point, also the B-spline stiffness
+// matrix) and M_0 = Id (Hybrid: the 7-point finest operator) or the B-spline
+// mass matrix (1/6, 4/6, 1/6; ends 2/6, 1/6) (Linear).
+static void ensure_tables(Hier& H, int disc) {
+  std::vector<HybTables>& out = disc == 2 ? H.lin : H.hyb;
+  if (!out.empty()) return;
+  if (H.ngrids != 1) throw Unsupported("the Hybrid and Linear discretisations are built for single-grid solves only");
   const int nl = (int)H.lv.size();
   const GridDesc& g0 = H.lv[0].h[0];
   if (g0.ny > 65535 * 4 || g0.nz > 65535 * 4)
-    throw Unsupported("the Hybrid discretisation needs ny and nz <= 262140");
-  // level 0 along each axis
+    throw Unsupported("the Hybrid and Linear discretisations need ny and nz <= 262140");
   Tri M[3], K[3];
   const int n0[3] = {g0.nx, g0.ny, g0.nz};
   for (int a = 0; a < 3; ++a) {
@@ -665,9 +671,23 @@ static void ensure_hybrid(Hier& H) {
       if (i > 0) { K[a].lo[i] = -1.0; K[a].di[i] += 1.0; }
       if (i + 1 < n) { K[a].up[i] = -1.0; K[a].di[i] += 1.0; }
     }
+    if (disc == 2 && n > 1)
+      for (int i = 0; i < n; ++i) {
+        M[a].lo[i] = i > 0 ? 1.0 / 6.0 : 0.0;
+        M[a].up[i] = i + 1 < n ? 1.0 / 6.0 : 0.0;
+        M[a].di[i] = (i > 0 ? 2.0 / 6.0 : 0.0) + (i + 1 < n ? 2.0 / 6.0 : 0.0);
+      }
   }
   std::vector<double> host;
   std::vector<size_t> at(3 * nl, 0);
+  auto push = [&](int l) {
+    for (int a = 0; a < 3; ++a) {
+      at[3 * l + a] = host.size();
+      for (const auto* v : {&M[a].lo, &M[a].di, &M[a].up, &K[a].lo, &K[a].di, &K[a].up})
+        host.insert(host.end(), v->begin(), v->end());
+    }
+  };
+  if (disc == 2) push(0);
   for (int l = 1; l < nl; ++l) {
     const GridDesc& p = H.lv[l - 1].h[0];
     const GridDesc& g = H.lv[l].h[0];
@@ -675,32 +695,36 @@ static void ensure_hybrid(Hier& H) {
     for (int a = 0; a < 3; ++a) {
       M[a] = galerkin_1d(M[a], np_[a], fa[a] == 2);
       K[a] = galerkin_1d(K[a], np_[a], fa[a] == 2);
-      if ((int)M[a].di.size() != nn[a]) throw std::logic_error("Hybrid tables: level size mismatch");
-      at[3 * l + a] = host.size();
-      for (const auto* v : {&M[a].lo, &M[a].di, &M[a].up, &K[a].lo, &K[a].di, &K[a].up})
-        host.insert(host.end(), v->begin(), v->end());
+      if ((int)M[a].di.size() != nn[a]) throw std::logic_error("discretisation tables: level size mismatch");
     }
+    push(l);
   }
   double* dev = (double*)H.alloc(std::max<size_t>(host.size(), 1) * sizeof(double));
   if (!host.empty()) HIP_TRY(hipMemcpy(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
-  H.hyb_dev = dev;
-  const int64_t nb = hyb_residual7_blocks(g0);
-  H.hyb_part = (double*)H.alloc(nb * sizeof(double));
-  H.hyb_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
-  const int64_t b0[2] = {0, nb};
-  HIP_TRY(hipMemcpy(H.hyb_b0, b0, sizeof b0, hipMemcpyHostToDevice));
-  H.hyb.assign(nl, HybTables{});
+  if (!H.hyb_part) {
+    const int64_t n7 = hyb_residual7_blocks(g0), nt = hyb_residual_blocks(g0);
+    H.hyb_part = (double*)H.alloc(std::max(n7, nt) * sizeof(double));
+    H.hyb_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
+    H.tab_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
+    const int64_t b7[2] = {0, n7}, bt[2] = {0, nt};
+    HIP_TRY(hipMemcpy(H.hyb_b0, b7, sizeof b7, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(H.tab_b0, bt, sizeof bt, hipMemcpyHostToDevice));
+  }
+  out.assign(nl, HybTables{});
   for (int l = 0; l < nl; ++l) {
-    HybTables& T = H.hyb[l];
+    HybTables& T = out[l];
     T.alpha = g0.alpha;
     T.w[0] = g0.wx; T.w[1] = g0.wy; T.w[2] = g0.wz;
-    for (int a = 0; a < 3; ++a) T.t[a] = l == 0 ? nullptr : dev + at[3 * l + a];
+    const bool has = disc == 2 || l > 0;
+    for (int a = 0; a < 3; ++a) T.t[a] = has ? dev + at[3 * l + a] : nullptr;
   }
 }
 
 static void prep(Hier& H, const gd_solve_opts& o) {
-  if (o.discretization == 1) ensure_hybrid(H);
+  if (o.discretization == 1 || o.discretization == 2) ensure_tables(H, o.discretization);
 }
+
+static void read_dred(Hier& H, int ncomp, hipStream_t st);
 
 struct Cycler {
   Hier& H;
@@ -713,11 +737,31 @@ struct Cycler {
   size_t ev_used = 0;
 
   bool fuse;
-  bool hyb;  // Hybrid discretisation: table levels >= 1, B-spline transfers
+  int disc;  // 0 Constant; 1 Hybrid (table levels >= 1), 2 Linear (all table levels); B-spline transfers
+  bool hyb;  // disc != 0
+  const std::vector<HybTables>* T = nullptr;
   Cycler(Hier& h, hipStream_t s, const gd_solve_opts& o)
       : H(h), st(s), pre(o.pre_smooth), post(o.post_smooth), pmode(o.prolong), timing(o.timing != 0),
-        fuse(o.fuse_prolong != 0), hyb(o.discretization == 1) {
-    if (hyb && H.hyb.empty()) throw std::logic_error("Hybrid tables not built before the cycle");
+        fuse(o.fuse_prolong != 0), disc(o.discretization), hyb(o.discretization != 0) {
+    if (hyb) {
+      T = disc == 2 ? &H.lin : &H.hyb;
+      if (T->empty()) throw std::logic_error("discretisation tables not built before the cycle");
+    }
+  }
+  bool table_level(int l) const { return disc == 2 || (disc == 1 && l > 0); }
+  // ||b - A x|| of level 0 (FP64 accumulation), r left in the level's spare buffer
+  double level0_residual() {
+    Level& L = H.lv[0];
+    if (table_level(0)) {
+      HIP_TRY(launch_hyb_residual(H.s, L.h[0], (*T)[0], L.x, L.b, L.xt, st, H.hyb_part));
+      HIP_TRY(launch_reduce(H.hyb_part, H.tab_b0, 1, 1, H.dred, st));
+      read_dred(H, 1, st);
+    } else {
+      HIP_TRY(launch_general_residual(H.s, H.g_ew(0), L.x, L.b, L.xt, H.partials, st, true));
+      HIP_TRY(launch_reduce(H.partials, L.ew.d_b0, 1, 2, H.dred, st));
+      read_dred(H, 2, st);
+    }
+    return std::sqrt(H.hpin[0]);
   }
   ~Cycler() {
     for (auto& p : ev) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
@@ -725,8 +769,8 @@ struct Cycler {
 
   void sweep(int l, const void* ec) {
     Level& L = H.lv[l];
-    if (hyb && l > 0) {  // 27-point Galerkin level: 8-colour Gauss-Seidel in place
-      for (int c = 0; c < 8; ++c) HIP_TRY(launch_hyb_gs8(H.s, L.h[0], H.hyb[l], c, L.x, L.b, st));
+    if (hyb && table_level(l)) {  // 27-point level: 8-colour Gauss-Seidel in place
+      for (int c = 0; c < 8; ++c) HIP_TRY(launch_hyb_gs8(H.s, L.h[0], (*T)[l], c, L.x, L.b, st));
       return;
     }
     const bool t = timing && l == 0;
@@ -754,11 +798,12 @@ struct Cycler {
     Level& L = H.lv[l];
     Level& C = H.lv[l + 1];
     if (hyb) {  // residual into the level's spare buffer, then P^T
-      if (l == 0) {
+      if (!table_level(l)) {
         HIP_TRY(launch_hyb_residual7(H.s, L.h[0], L.x, L.b, L.xt, H.hyb_part, st));
         if (norm) HIP_TRY(launch_reduce(H.hyb_part, H.hyb_b0, 1, 1, H.dred, st));
       } else {
-        HIP_TRY(launch_hyb_residual(H.s, L.h[0], H.hyb[l], L.x, L.b, L.xt, st));
+        HIP_TRY(launch_hyb_residual(H.s, L.h[0], (*T)[l], L.x, L.b, L.xt, st, norm ? H.hyb_part : nullptr));
+        if (norm) HIP_TRY(launch_reduce(H.hyb_part, H.tab_b0, 1, 1, H.dred, st));
       }
       HIP_TRY(launch_hyb_restrict(H.s, L.h[0], L.xt, C.b, C.x, st));
       return;
@@ -1096,11 +1141,12 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
   return R;
 }
 
-// Gradient-modulation filter (Sec. 6): plain V-cycles on the correction
-// system A E = b (b from launch_npr_rhs, E = 0 at the start) until the
-// residual, accumulated in FP64, is at most rel_tol times the canonical
-// ||b||.  The residual of E equals the canonical residual of I0 + E.
-static Outcome solve_npr(Hier& H, const gd_solve_opts& o, double bnorm, hipStream_t st) {
+// Plain V-cycles on a correction system A E = b already in level 0 (E = 0
+// at the start; the gradient-modulation filter and the Linear AD solve)
+// until the residual, accumulated in FP64, is at most rel_tol times the
+// canonical ||b||.  The residual of E equals the canonical residual of
+// I0 + E.
+static Outcome solve_corr(Hier& H, const gd_solve_opts& o, double bnorm, hipStream_t st) {
   prep(H, o);
   Outcome R;
   R.bnorm = {bnorm};
@@ -1109,12 +1155,7 @@ static Outcome solve_npr(Hier& H, const gd_solve_opts& o, double bnorm, hipStrea
   const double den = denom(bnorm);
   double best = INFINITY, inner = 0.5;
   int stall = 0;
-  auto full_residual = [&]() {
-    HIP_TRY(launch_general_residual(H.s, H.g_ew(0), H.lv[0].x, H.lv[0].b, nullptr, H.partials, st, true));
-    HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, 1, 2, H.dred, st));
-    read_dred(H, 2, st);
-    return std::sqrt(H.hpin[0]);
-  };
+  auto full_residual = [&]() { return cy.level0_residual(); };
   for (;;) {
     bool check_final = R.cycles >= o.max_cycles || single, stop_after = check_final;
     if (single) {
@@ -1146,6 +1187,36 @@ static Outcome solve_npr(Hier& H, const gd_solve_opts& o, double bnorm, hipStrea
   }
   HIP_TRY(hipStreamSynchronize(st));
   cy.harvest();
+  return R;
+}
+
+// AD (Eq. (1)) with the Linear discretisation: b = (b_x Kx My Mz + b_y Mx Ky
+// Mz) I0 (canonical, its norm only); in correction form E = I1 - I0 the
+// system is A E = -b_z Mx My Kz I0.  Both come from the table residual
+// against a zero right-hand side, with I0 loaded into level 0.  Then plain
+// V-cycles on every table level, and the output I0 + E shifted to the mean
+// of I0 (the constants are the null space).
+static Outcome solve_linear_ad(Hier& H, const Problem& P, const gd_solve_opts& o, double bx, double by, double bz,
+                               hipStream_t st) {
+  prep(H, o);
+  Level& L0 = H.lv[0];
+  const GridDesc& g0 = L0.h[0];
+  const size_t es = dsize(H.s);
+  HIP_TRY(launch_load_input(P.tin, H.s, g0, P.I0, L0.x, st));
+  HIP_TRY(hipMemsetAsync(L0.b, 0, L0.total * es, st));
+  HybTables Tb = H.lin[0], Tz = H.lin[0];
+  Tb.alpha = 0.0; Tb.w[0] = bx; Tb.w[1] = by; Tb.w[2] = 0.0;
+  Tz.alpha = 0.0; Tz.w[0] = 0.0; Tz.w[1] = 0.0; Tz.w[2] = bz;
+  HIP_TRY(launch_hyb_residual(H.s, g0, Tb, L0.x, L0.b, L0.xt, st, H.hyb_part));  // -b
+  HIP_TRY(launch_reduce(H.hyb_part, H.tab_b0, 1, 1, H.dred, st));
+  read_dred(H, 1, st);
+  const double bnorm = std::sqrt(H.hpin[0]);
+  HIP_TRY(launch_hyb_residual(H.s, g0, Tz, L0.x, L0.b, L0.xt, st));  // -b_z Mx My Kz I0
+  HIP_TRY(hipMemcpyAsync(L0.b, L0.xt, L0.total * es, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * es, st));
+  Outcome R = solve_corr(H, o, bnorm, st);
+  finish(H, P, 0, st);
+  HIP_TRY(hipStreamSynchronize(st));
   return R;
 }
 
@@ -1222,7 +1293,7 @@ static gd_status check_opts(const gd_solve_opts& o) {
   if (!(o.rel_tol > 0.0) || o.max_cycles < 0 || o.pre_smooth < 0 || o.post_smooth < 0 ||
       o.pre_smooth + o.post_smooth < 1 || !valid_dtype(o.storage) || o.inner_cycles < 1 ||
       (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3 ||
-      (o.discretization != 0 && o.discretization != 1))
+      o.discretization < 0 || o.discretization > 2)
     return fail(GD_ERR_INVALID, "invalid solver options");
   if (!o.fp64_refine && (o.storage == GD_F16 || o.storage == GD_BF16))
     return fail(GD_ERR_UNSUPPORTED, "16-bit storage needs fp64_refine = 1 (its rounding floor is far above 1e-6)");
@@ -1245,13 +1316,17 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, i
   if (opts) o = *opts;
   gd_status s = check_opts(o);
   if (s != GD_OK) return s;
+  if (o.discretization == 2 && o.fp64_refine)
+    return fail(GD_ERR_UNSUPPORTED, "gd_smooth_z: FP64 refinement is not built for the Linear discretisation");
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<GridSpec> g{{nx, ny, nz, 0.0, bx, by, bz, 0, nx, nx * ny}};
     Hier* H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
     Problem P{I0, nullptr, I1, in_t, out_t, true};
-    Outcome R = o.fp64_refine ? solve_mixed(*H, P, o, st) : solve_plain(*H, P, o, st);
+    Outcome R = o.discretization == 2 ? solve_linear_ad(*H, P, o, bx, by, bz, st)
+                : o.fp64_refine       ? solve_mixed(*H, P, o, st)
+                                      : solve_plain(*H, P, o, st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rep) fill_report(rep, R, 0, secs, (int)H->lv.size());
     if (R.numeric) return fail(GD_ERR_NUMERIC, "gd_smooth_z: non-finite residual");
@@ -1280,6 +1355,8 @@ gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
   gd_status s = check_opts(o);
   if (s != GD_OK) return s;
   if (o.fp64_refine) return fail(GD_ERR_UNSUPPORTED, "gd_npr_filter: FP64 refinement is not built for this filter");
+  if (o.discretization == 2)
+    return fail(GD_ERR_UNSUPPORTED, "gd_npr_filter: the Linear discretisation is built for the AD solve only");
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1291,7 +1368,7 @@ gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
     read_dred(*H, 2, st);
     const double bnorm = std::sqrt(H->hpin[0]);
     HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * dsize(H->s), st));
-    Outcome R = solve_npr(*H, o, bnorm, st);
+    Outcome R = solve_corr(*H, o, bnorm, st);
     HIP_TRY(launch_finalize(in_t, H->s, out_t, 0, H->g_ew(0), I0, L0.x, nullptr, nullptr, I1, st));
     HIP_TRY(hipStreamSynchronize(st));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1343,6 +1420,8 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
   if (opts) o = *opts;
   gd_status s = check_opts(o);
   if (s != GD_OK) return s;
+  if (o.discretization == 2)
+    return fail(GD_ERR_UNSUPPORTED, "gd_screened_poisson_slices: the Linear discretisation is built for the AD solve only");
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1426,7 +1505,8 @@ gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t 
   o.storage = s;
   o.fp64_refine = 0;
   if (!(o.rel_tol > 0.0) || o.pre_smooth < 0 || o.post_smooth < 0 || o.pre_smooth + o.post_smooth < 1 ||
-      (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3)
+      (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3 || o.discretization < 0 ||
+      o.discretization > 2)
     return fail(GD_ERR_INVALID, "gd_hierarchy_create: invalid options");
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {

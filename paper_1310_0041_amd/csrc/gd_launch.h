@@ -89,9 +89,13 @@ struct HybTables {
 // one colour (0..7) of an 8-colour Gauss-Seidel sweep of a table level, in place
 hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int colour, void* x, const void* b,
                           hipStream_t st);
-// r = b - A x on a table level
+// r = b - A x on a table level; with partials, per-block FP64 sums of r^2
+// in partials[0 .. hyb_residual_blocks(G))
+int64_t hyb_residual_blocks(const GridDesc& G);
 hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T, const void* x, const void* b,
-                               void* r, hipStream_t st);
+                               void* r, hipStream_t st, double* partials = nullptr);
+// the caller's input I0 (dtype tin, layout ioff / ipy / ipz of G) into a level array of dtype s
+hipError_t launch_load_input(gd_dtype tin, gd_dtype s, const GridDesc& G, const void* in, void* out, hipStream_t st);
 // r = b - A x on the finest (7-point) level of a Hybrid hierarchy, with
 // per-block FP64 sums of r^2 in partials[0 .. hyb_residual7_blocks(G))
 int64_t hyb_residual7_blocks(const GridDesc& G);

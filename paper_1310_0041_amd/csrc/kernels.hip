@@ -1462,19 +1462,47 @@ k_hyb_gs8(GridDesc G, HybAxes A, int colour, S* __restrict__ x, const S* __restr
   }
 }
 
-// r = b - A x on a table level (all samples)
+// r = b - A x on a table level (all samples); with partials, the FP64 sum
+// of r^2 per block (block = x + gx (y + gy z)), in a fixed order
 template <typename S>
 __global__ void __launch_bounds__(HBX * HBY)
-k_hyb_residual(GridDesc G, HybAxes A, const S* __restrict__ x, const S* __restrict__ b, S* __restrict__ r) {
+k_hyb_residual(GridDesc G, HybAxes A, const S* __restrict__ x, const S* __restrict__ b, S* __restrict__ r,
+               double* __restrict__ partials) {
+  __shared__ double red[HBY];
+  const int i = blockIdx.x * HBX + threadIdx.x, j = blockIdx.y * HBY + threadIdx.y;
+  double rr = 0.0;
+  if (i < G.nx && j < G.ny) {
+    const int64_t pl = (int64_t)G.px * G.ny;
+    for (int k = blockIdx.z * HZ; k < min((int)(blockIdx.z + 1) * HZ, G.nz); ++k) {
+      double ax, d;
+      hyb_row(A, G, x, i, j, k, ax, d);
+      const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
+      const double q = ld64(b + v) - ax;
+      st64(r + v, q);
+      rr += q * q;
+    }
+  }
+  if (!partials) return;  // uniform over the launch
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o, 64);
+  if (threadIdx.x == 0) red[threadIdx.y] = rr;
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    double t = 0.0;
+    for (int w = 0; w < HBY; ++w) t += red[w];
+    partials[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = t;
+  }
+}
+
+// the caller's input (caller layout, dtype Tin) copied into a level array
+template <typename Tin, typename S>
+__global__ void __launch_bounds__(HBX * HBY)
+k_load_input(GridDesc G, const Tin* __restrict__ in, S* __restrict__ out) {
   const int i = blockIdx.x * HBX + threadIdx.x, j = blockIdx.y * HBY + threadIdx.y;
   if (i >= G.nx || j >= G.ny) return;
   const int64_t pl = (int64_t)G.px * G.ny;
-  for (int k = blockIdx.z * HZ; k < min((int)(blockIdx.z + 1) * HZ, G.nz); ++k) {
-    double ax, d;
-    hyb_row(A, G, x, i, j, k, ax, d);
-    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
-    st64(r + v, ld64(b + v) - ax);
-  }
+  for (int k = blockIdx.z * HZ; k < min((int)(blockIdx.z + 1) * HZ, G.nz); ++k)
+    st64(out + G.off + k * pl + (int64_t)j * G.px + i, in_at(in, G.ioff + (int64_t)k * G.ipz + (int64_t)j * G.ipy + i));
 }
 
 // r = b - A x on the finest (7-point) level, with the FP64 sum of r^2 per
@@ -1956,12 +1984,38 @@ hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int
   return last();
 }
 
+int64_t hyb_residual_blocks(const GridDesc& G) {
+  const dim3 g = hyb_grid(G.nx, G.ny, G.nz);
+  return (int64_t)g.x * g.y * g.z;
+}
+
 hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T, const void* x, const void* b,
-                               void* r, hipStream_t st) {
+                               void* r, hipStream_t st, double* partials) {
   HybAxes A{{T.t[0], T.t[1], T.t[2]}, T.alpha, {T.w[0], T.w[1], T.w[2]}};
 #define L(TT) hipLaunchKernelGGL(k_hyb_residual<TT>, hyb_grid(G.nx, G.ny, G.nz), dim3(HBX, HBY), 0, st, G, A, \
-                                 (const TT*)x, (const TT*)b, (TT*)r)
+                                 (const TT*)x, (const TT*)b, (TT*)r, partials)
   GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+template <typename TI>
+static void load_input_launch(gd_dtype s, const GridDesc& G, const void* in, void* out, hipStream_t st) {
+#define L(TT) hipLaunchKernelGGL((k_load_input<TI, TT>), hyb_grid(G.nx, G.ny, G.nz), dim3(HBX, HBY), 0, st, G, \
+                                 (const TI*)in, (TT*)out)
+  switch (s) {
+    case GD_F64: L(double); break;
+    case GD_F32: L(float); break;
+    case GD_F16: L(__half); break;
+    case GD_BF16: L(__hip_bfloat16); break;
+    default: break;
+  }
+#undef L
+}
+
+hipError_t launch_load_input(gd_dtype tin, gd_dtype s, const GridDesc& G, const void* in, void* out, hipStream_t st) {
+#define L(TI) load_input_launch<TI>(s, G, in, out, st)
+  GD_DISPATCH_S(tin, L)
 #undef L
   return last();
 }

@@ -108,6 +108,18 @@ def test_npr_argument_checks(lib):
                              None) == gd.ERR_UNSUPPORTED
 
 
+def test_discretization_option_checked(lib):
+    h = ctypes.c_void_p()
+    o = gd.default_opts(discretization=3)
+    assert lib.gd_hierarchy_create(ctypes.byref(h), 4, 4, 4, 0.1, 1.0, 1.0, 1.0, 1, ctypes.byref(o),
+                                   None) == gd.ERR_INVALID
+    assert lib.gd_smooth_z(P(64), 1, P(128), 1, 4, 4, 4, 1.0, 1.0, 4.0, ctypes.byref(o), None,
+                           None) == gd.ERR_INVALID
+    o = gd.default_opts(discretization=2, fp64_refine=1, storage=gd.F16)
+    assert lib.gd_smooth_z(P(64), 1, P(128), 1, 4, 4, 4, 1.0, 1.0, 4.0, ctypes.byref(o), None,
+                           None) == gd.ERR_UNSUPPORTED
+
+
 def test_plane_size_limit(lib):
     # an x-y plane above 2^28 cells is refused on the host, before any GPU call
     h = ctypes.c_void_p()

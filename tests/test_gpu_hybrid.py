@@ -1,11 +1,13 @@
-"""The Hybrid discretisation (Sec. 4.2) on the GPU.
+"""The Hybrid and Linear discretisations (Sec. 4.2) on the GPU.
 
 One V-cycle of the library (7-point red-black relaxation on the finest
 level, 8-colour Gauss-Seidel on the Galerkin levels, B-spline transfers) is
 compared element by element with the same cycle composed from the oracle's
 step functions on the library's own level sizes: 1e-11 relative in FP64,
 1e-5 in FP32.  Whole solves must reach the same answer as the "Constant"
-solver: the DCT oracle's solution of the finest-level system.
+solver: the DCT oracle's solution of the finest-level system.  The Linear
+scheme (B-spline finite elements on every level, 8-colour Gauss-Seidel
+everywhere) is checked the same way against its own oracle.
 """
 
 import numpy as np
@@ -14,7 +16,7 @@ import torch
 
 import synth
 from oracle import grid as og
-from oracle import hybrid, mgsteps, solvers
+from oracle import hybrid, linear, mgsteps, solvers
 
 pytestmark = pytest.mark.gpu
 
@@ -23,26 +25,33 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
-def oracle_vcycle(x, b, sizes, alpha, w, pre, post):
+def oracle_vcycle(x, b, sizes, alpha, w, pre, post, fem=False):
     """One V-cycle composed from oracle steps on the level sizes `sizes`
-    ([nz][ny][nx] per level, finest first)."""
+    ([nz][ny][nx] per level, finest first).  fem: the Linear scheme (level 0
+    is the B-spline operator, relaxed by 8-colour GS like the others)."""
     last = len(sizes) - 1
     halv = [[sizes[l + 1][::-1][a] != sizes[l][::-1][a] for l in range(last)] for a in range(3)]  # per axis x, y, z
     n0 = sizes[0][::-1]
-    tabs = [hybrid.level_tables(n0[a], halv[a]) for a in range(3)]
-    mats = [[tabs[a][l] for a in range(3)] for l in range(last + 1)]
+    mats = [linear.tables(sizes[0]) if fem else [(np.eye(n), hybrid.laplace_1d(n)) for n in n0]]
+    for l in range(last):
+        nxt = []
+        for a in range(3):
+            Pa = hybrid.prolong_1d(mats[l][a][0].shape[0], halv[a][l])
+            nxt.append((Pa.T @ mats[l][a][0] @ Pa, Pa.T @ mats[l][a][1] @ Pa))
+        mats.append(nxt)
     P = [hybrid.transfer_mats(sizes[l], [halv[a][l] for a in range(3)]) for l in range(last)]
+    table = (lambda l: True) if fem else (lambda l: l > 0)
 
     def smooth(l, x, b, n):
         for _ in range(n):
-            x = mgsteps.rb_sweep(x, b, alpha, w) if l == 0 else hybrid.gs8_sweep(x, b, mats[l], alpha, w)
+            x = hybrid.gs8_sweep(x, b, mats[l], alpha, w) if table(l) else mgsteps.rb_sweep(x, b, alpha, w)
         return x
 
     def full(l, x, b):
         if l == last:
             return smooth(l, x, b, 1)
         x = smooth(l, x, b, pre)
-        r = mgsteps.residual(x, b, alpha, w) if l == 0 else b - hybrid.apply(x, mats[l], alpha, w)
+        r = b - hybrid.apply(x, mats[l], alpha, w) if table(l) else mgsteps.residual(x, b, alpha, w)
         bc = hybrid.restrict(r, P[l])
         xc = full(l + 1, np.zeros(bc.shape), bc)
         return smooth(l, x + hybrid.prolong(xc, P[l]), b, post)
@@ -115,4 +124,69 @@ def test_slice_batch_hybrid_unsupported(gd):
     I0 = torch.rand(3, 16, 32, device="cuda")
     with pytest.raises(gd.GDError) as ei:
         gd.screened_poisson_stack(I0, I0.clone(), 0.01, discretization=1)
+    assert ei.value.status == gd.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("shape", [(9, 17, 30), (5, 8, 8), (1, 12, 40), (16, 3, 5), (2, 2, 2), (1, 1, 1)])
+@pytest.mark.parametrize("alpha,w", SYSTEMS)
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_linear_one_vcycle_matches_oracle_steps(gd, shape, alpha, w, dt):
+    say("linear vcycle", shape, alpha, w, dt)
+    rng = np.random.default_rng(8)
+    x0, b = rng.standard_normal(shape), rng.standard_normal(shape)
+    if alpha == 0.0:
+        b -= b.mean()
+    xq = torch.from_numpy(x0).to(dt).double().numpy()
+    bq = torch.from_numpy(b).to(dt).double().numpy()
+    h = gd.Hierarchy(shape, alpha, w, dt, discretization=2, pre_smooth=1, post_smooth=2)
+    sizes = [h.info(l)[0] for l in range(h.info())]
+    x = torch.from_numpy(xq).to(dt).cuda()
+    h.vcycle(x, torch.from_numpy(bq).to(dt).cuda(), 1)
+    h.close()
+    ref = oracle_vcycle(xq, bq, sizes, alpha, w, 1, 2, fem=True)
+    tol = 1e-11 if dt == torch.float64 else 1e-5
+    assert np.abs(x.double().cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape", [(8, 32, 40), (5, 17, 23)])
+def test_linear_ad_solve_fp64(gd, shape):
+    say("linear AD f64", shape)
+    nz, ny, nx = shape
+    I0 = synth.make_stack(synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100424)).numpy()
+    ref = linear.ad_solve(I0, (1.0, 1.0, 4.0), method="cg")
+    out, rep = gd.smooth_z(torch.from_numpy(I0).cuda(), (1.0, 1.0, 4.0), storage=gd.F64, rel_tol=1e-10,
+                           discretization=2)
+    x = out.cpu().numpy()
+    assert rep["status"] == 0 and rep["rel_residual"] <= 1e-10, rep
+    assert linear.relative_residual(x, I0, (1.0, 1.0, 4.0)) <= 1.01e-10
+    assert abs(x.mean() - I0.mean()) <= 1e-9 * abs(I0.mean())
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 1e-8
+
+
+def test_linear_ad_solve_fp32(gd):
+    say("linear AD f32")
+    I0 = synth.make_stack(synth.StackSpec(96, 64, 12, (4.0, 40.0), True, 13100425)).float().double().numpy()
+    beta = (1.0, 1.0, 4.0)
+    ref = linear.ad_solve(I0, beta, method="cg")
+    E = (ref - I0).astype(np.float32).astype(np.float64)
+    tol = max(1e-6, 3.0 * linear.relative_residual(I0 + E, I0, beta))
+    out, rep = gd.smooth_z(torch.from_numpy(I0).float().cuda(), beta, out_dtype=torch.float64, rel_tol=tol,
+                           discretization=2)
+    x = out.cpu().numpy()
+    assert rep["status"] == 0 and linear.relative_residual(x, I0, beta) <= 1.01 * tol
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 1e-5
+    # and it is a different answer from the 7-point one
+    assert np.linalg.norm(ref - solvers.ad_dct(I0, beta)) > 1e-4 * np.linalg.norm(ref)
+
+
+def test_linear_unsupported_cases(gd):
+    I0 = torch.rand(3, 16, 32, device="cuda") * 100
+    with pytest.raises(gd.GDError) as ei:
+        gd.screened_poisson_stack(I0, I0.clone(), 0.01, discretization=2)
+    assert ei.value.status == gd.ERR_UNSUPPORTED
+    with pytest.raises(gd.GDError) as ei:
+        gd.npr_filter(I0, discretization=2)
+    assert ei.value.status == gd.ERR_UNSUPPORTED
+    with pytest.raises(gd.GDError) as ei:
+        gd.smooth_z(I0, (1.0, 1.0, 4.0), storage=gd.F16, fp64_refine=1, discretization=2)
     assert ei.value.status == gd.ERR_UNSUPPORTED
