@@ -166,6 +166,26 @@ gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
                         double beta_x, double beta_y, double beta_z, double lambda, double sigma,
                         const gd_solve_opts* opts, gd_solve_report* rep, void* stream);
 
+/* ---- spectral solver (Sec. 3.2): exact DCT-II diagonalisation -------------
+ * The constant-coefficient Neumann operator alpha + sum_a beta_a L_a is
+ * diagonal in the DCT-II basis cos(pi k (j + 1/2) / n) (eigenvalues
+ * alpha + sum_a beta_a (2 - 2 cos(pi k_a / n_a))), so these calls solve the
+ * same systems as the multigrid ones exactly (FP64 throughout, three
+ * forward and three inverse transforms): a competitor and a verifier.
+ * Contiguous [nz][ny][nx] arrays; every axis a power of two <= 4096, other
+ * sizes GD_ERR_UNSUPPORTED.  An FP64 workspace of nx*ny*nz values is kept per
+ * device until gd_release_workspace(). */
+
+/* x = (alpha + sum_a beta_a L_a)^-1 b; with alpha = 0 the mean-free solution
+ * (b should then have zero mean: its mean is dropped). */
+gd_status gd_dct_solve(const void* b, gd_dtype bt, void* x, gd_dtype xt, int64_t nx, int64_t ny, int64_t nz,
+                       double alpha, double beta_x, double beta_y, double beta_z, void* stream);
+/* Anisotropic diffusion, Eq. (1), in closed form (Sec. 3.2.1): every
+ * frequency scaled by (bx lx + by ly) / (bx lx + by ly + bz lz), the zero
+ * frequency kept (mean(I1) = mean(I0)). */
+gd_status gd_dct_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, int64_t nx, int64_t ny,
+                          int64_t nz, double beta_x, double beta_y, double beta_z, void* stream);
+
 /* ---- general system (Sec. 4) through an explicit hierarchy ---------------- */
 typedef struct gd_hierarchy gd_hierarchy;
 

@@ -88,6 +88,8 @@ _SIGS = {
     "gd_screened_poisson_slices": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(SliceDesc), _i64, _d, _d,
                                         ctypes.POINTER(SolveOpts), ctypes.POINTER(Report),
                                         ctypes.POINTER(Report), _vp]),
+    "gd_dct_solve": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _d, _vp]),
+    "gd_dct_smooth_z": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _vp]),
     "gd_npr_filter": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _d, _d, _d, ctypes.POINTER(SolveOpts),
                            ctypes.POINTER(Report), _vp]),
     "gd_hierarchy_create": (_i, [ctypes.POINTER(_vp), _i64, _i64, _i64, _d, _d, _d, _d, _i,
@@ -223,6 +225,30 @@ def npr_filter(I0, alpha=0.001, beta=(1.0, 1.0, 0.1), lam=1.25, sigma=5.0, out_d
     if check:
         _check(st)
     return out, dict(rep.as_dict(), status=st)
+
+
+def dct_solve(b, alpha, beta, out_dtype=None, check=True):
+    """Spectral solve of (alpha + sum beta_a L_a) x = b (power-of-two grid)."""
+    lib = load()
+    nz, ny, nx = b.shape
+    x = _torch().empty_like(b, dtype=out_dtype or b.dtype)
+    st = lib.gd_dct_solve(_ptr(b), gd_dtype(b.dtype), _ptr(x), gd_dtype(x.dtype), nx, ny, nz, float(alpha),
+                          float(beta[0]), float(beta[1]), float(beta[2]), _stream())
+    if check:
+        _check(st)
+    return x, st
+
+
+def dct_smooth_z(I0, beta=(1.0, 1.0, 4.0), out_dtype=None, check=True):
+    """Anisotropic diffusion of I0 (Eq. (1)) by the spectral solver."""
+    lib = load()
+    nz, ny, nx = I0.shape
+    out = _torch().empty_like(I0, dtype=out_dtype or I0.dtype)
+    st = lib.gd_dct_smooth_z(_ptr(I0), gd_dtype(I0.dtype), _ptr(out), gd_dtype(out.dtype), nx, ny, nz,
+                             float(beta[0]), float(beta[1]), float(beta[2]), _stream())
+    if check:
+        _check(st)
+    return out, st
 
 
 def make_slice_descs(offsets, nx, ny, alpha, pitch=None):

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgd.so")
 
-SOURCES = ["kernels.hip", "gd_api.cpp", "net.hip", "net_api.cpp"]
+SOURCES = ["kernels.hip", "gd_api.cpp", "net.hip", "net_api.cpp", "dct.hip", "dct_api.cpp"]
 
 # gfx950 only; packed FP32 instructions are disabled (the compiler still
 # vectorises ordinary float code with them otherwise).

@@ -36,6 +36,9 @@ static gd_status fail(gd_status s, const std::string& msg) {
   t_err = msg;
   return s;
 }
+// the same, for the library's other translation units
+gd_status set_error(gd_status s, const std::string& msg) { return fail(s, msg); }
+void dct_release();  // dct_api.cpp
 
 struct HipFail {
   hipError_t e;
@@ -1892,6 +1895,7 @@ gd_status gd_sweep_config(int64_t nx, int64_t ny, int64_t nz, gd_dtype s, int* t
 
 gd_status gd_release_workspace(void) {
   return run_guarded([&]() -> gd_status {
+    dct_release();
     {
       std::lock_guard<std::mutex> lk(g_cache_mu);
       g_cache.clear();

@@ -120,6 +120,15 @@ def test_discretization_option_checked(lib):
                            None) == gd.ERR_UNSUPPORTED
 
 
+def test_dct_argument_checks(lib):
+    assert lib.gd_dct_solve(None, 0, P(64), 0, 8, 8, 8, 0.1, 1.0, 1.0, 1.0, None) == gd.ERR_INVALID
+    assert lib.gd_dct_solve(P(64), 0, P(128), 0, 8, 8, 8, -0.1, 1.0, 1.0, 1.0, None) == gd.ERR_INVALID
+    assert lib.gd_dct_solve(P(64), 0, P(128), 0, 6, 8, 8, 0.1, 1.0, 1.0, 1.0, None) == gd.ERR_UNSUPPORTED
+    assert lib.gd_dct_solve(P(64), 0, P(128), 0, 8, 8, 8192, 0.1, 1.0, 1.0, 1.0, None) == gd.ERR_UNSUPPORTED
+    assert lib.gd_dct_smooth_z(P(64), 1, P(128), 0, 8, 8, 8, 1.0, 1.0, 0.0, None) == gd.ERR_INVALID
+    assert lib.gd_dct_smooth_z(P(64), 9, P(128), 0, 8, 8, 8, 1.0, 1.0, 4.0, None) == gd.ERR_INVALID
+
+
 def test_plane_size_limit(lib):
     # an x-y plane above 2^28 cells is refused on the host, before any GPU call
     h = ctypes.c_void_p()
