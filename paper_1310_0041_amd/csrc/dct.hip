@@ -256,9 +256,9 @@ hipError_t dct_pass(const DctPass& p, hipStream_t st) {
   d.logn = ilog2(d.n);
   d.adjacent = d.sf == 1;
   // about 2048 values per block (several blocks per CU), except long strided
-  // lines (n >= 512), which keep up to 4096 so that adjacent lines still form
-  // runs of 4 or more values in memory
-  d.lpb = ((d.adjacent || d.n <= 256) ? DCT_LDS / 2 : DCT_LDS) / d.n;
+  // lines (y or z, n >= 512), which keep up to 4096 so that the adjacent lines
+  // of a block still form runs of 4 or more values in memory
+  d.lpb = ((!d.adjacent || d.n <= 256) ? DCT_LDS / 2 : DCT_LDS) / d.n;
   if (d.lpb < 1) d.lpb = 1;
   if (d.lpb > 64) d.lpb = 64;
   if (d.lpb > d.nlines) d.lpb = (int)d.nlines;

@@ -652,6 +652,18 @@ static Tri galerkin_1d(const Tri& T, int n, bool halved) {
   return C;
 }
 
+// Per-block partial sums of the finest-level residual kernels (one grid).
+static void alloc_partials(Hier& H) {
+  const GridDesc& g0 = H.lv[0].h[0];
+  const int64_t n7 = hyb_residual7_blocks(g0), nt = hyb_residual_blocks(g0);
+  H.hyb_part = (double*)H.alloc(std::max(n7, nt) * sizeof(double));
+  H.hyb_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
+  H.tab_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
+  const int64_t b7[2] = {0, n7}, bt[2] = {0, nt};
+  HIP_TRY(hipMemcpy(H.hyb_b0, b7, sizeof b7, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(H.tab_b0, bt, sizeof bt, hipMemcpyHostToDevice));
+}
+
 // Tables of the Hybrid (disc 1) or Linear (disc 2) discretisation.  Along
 // one axis level 0 has K_0 = L (Neumann 3-point, also the B-spline stiffness
 // matrix) and M_0 = Id (Hybrid: the 7-point finest operator) or the B-spline
@@ -704,15 +716,7 @@ static void ensure_tables(Hier& H, int disc) {
   }
   double* dev = (double*)H.alloc(std::max<size_t>(host.size(), 1) * sizeof(double));
   if (!host.empty()) HIP_TRY(hipMemcpy(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
-  if (!H.hyb_part) {
-    const int64_t n7 = hyb_residual7_blocks(g0), nt = hyb_residual_blocks(g0);
-    H.hyb_part = (double*)H.alloc(std::max(n7, nt) * sizeof(double));
-    H.hyb_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
-    H.tab_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
-    const int64_t b7[2] = {0, n7}, bt[2] = {0, nt};
-    HIP_TRY(hipMemcpy(H.hyb_b0, b7, sizeof b7, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(H.tab_b0, bt, sizeof bt, hipMemcpyHostToDevice));
-  }
+  if (!H.hyb_part) alloc_partials(H);
   out.assign(nl, HybTables{});
   for (int l = 0; l < nl; ++l) {
     HybTables& T = out[l];
@@ -759,10 +763,11 @@ struct Cycler {
       HIP_TRY(launch_hyb_residual(H.s, L.h[0], (*T)[0], L.x, L.b, L.xt, st, H.hyb_part));
       HIP_TRY(launch_reduce(H.hyb_part, H.tab_b0, 1, 1, H.dred, st));
       read_dred(H, 1, st);
-    } else {
-      HIP_TRY(launch_general_residual(H.s, H.g_ew(0), L.x, L.b, L.xt, H.partials, st, true));
-      HIP_TRY(launch_reduce(H.partials, L.ew.d_b0, 1, 2, H.dred, st));
-      read_dred(H, 2, st);
+    } else {  // 7-point level (one grid): the fast residual with its own block partials
+      if (!H.hyb_part) alloc_partials(H);
+      HIP_TRY(launch_hyb_residual7(H.s, L.h[0], L.x, L.b, L.xt, H.hyb_part, st));
+      HIP_TRY(launch_reduce(H.hyb_part, H.hyb_b0, 1, 1, H.dred, st));
+      read_dred(H, 1, st);
     }
     return std::sqrt(H.hpin[0]);
   }

@@ -1309,6 +1309,9 @@ __global__ void __launch_bounds__(256)
 k_npr_rhs(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
           const Tin* __restrict__ I0, double lam, double inv2s2, S* __restrict__ bout,
           double* __restrict__ partials) {
+  // arithmetic in the storage's compute type (FP32 for FP32 storage, FP64
+  // for FP64); the z-march keeps the factor and gradient of the voxel below
+  using C = typename Ty<S>::C;
   __shared__ double red[4];
   const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
@@ -1317,47 +1320,57 @@ k_npr_rhs(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0
   double sb = 0.0, se = 0.0;
   if (i < nx && j < ny) {
     const int64_t pl = (int64_t)G.px * ny;
-    const double w[3] = {G.wx, G.wy, G.wz};
+    const C w[3] = {(C)G.wx, (C)G.wy, (C)G.wz};
+    const C lamc = (C)lam, i2 = (C)inv2s2, alpha = (C)G.alpha;
+    auto I = [&](int di, int dj, int k) -> C {
+      return (C)in_at(I0, G.ioff + (int64_t)k * G.ipz + (int64_t)(j + dj) * G.ipy + (i + di));
+    };
+    // forward gradient and factor of voxel (i + di, j + dj, k), value c there
+    auto fwd = [&](int di, int dj, int k, C c, C g[3]) -> C {
+      g[0] = (i + di + 1 < nx) ? I(di + 1, dj, k) - c : (C)0;
+      g[1] = (j + dj + 1 < ny) ? I(di, dj + 1, k) - c : (C)0;
+      g[2] = (k + 1 < nz) ? I(di, dj, k + 1) - c : (C)0;
+      return lamc * ((C)1 - exp(-(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * i2));
+    };
+    C fz = 0, gz = 0;  // factor and z-gradient of the voxel below (valid for k > t.z0)
+    if (t.z0 > 0) {
+      C g[3];
+      fz = fwd(0, 0, t.z0 - 1, I(0, 0, t.z0 - 1), g);
+      gz = g[2];
+    }
     for (int k = t.z0; k < t.z1; ++k) {
-      // value of I0 at (i + di, j + dj, k + dk), inside the grid by construction
-      auto I = [&](int di, int dj, int dk) -> double {
-        return in_at(I0, G.ioff + (int64_t)(k + dk) * G.ipz + (int64_t)(j + dj) * G.ipy + (i + di));
-      };
-      // forward gradient of voxel (i + di, j + dj, k + dk) (value c there)
-      auto fwd = [&](int di, int dj, int dk, double c, double g[3]) {
-        g[0] = (i + di + 1 < nx) ? I(di + 1, dj, dk) - c : 0.0;
-        g[1] = (j + dj + 1 < ny) ? I(di, dj + 1, dk) - c : 0.0;
-        g[2] = (k + dk + 1 < nz) ? I(di, dj, dk + 1) - c : 0.0;
-      };
-      auto factor = [&](const double g[3]) {
-        return lam * (1.0 - exp(-(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * inv2s2));
-      };
-      const double c = I(0, 0, 0);
-      double gv[3];
-      fwd(0, 0, 0, c, gv);
-      const double fv = factor(gv);
-      double bc = G.alpha * c, be = 0.0;
-      const bool lower[3] = {i > 0, j > 0, k > 0};
+      const C c = I(0, 0, k);
+      C gv[3];
+      const C fv = fwd(0, 0, k, c, gv);
+      C bc = alpha * c, be = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        if (w[a] == 0.0) continue;
-        // the face this voxel owns
-        bc -= w[a] * fv * gv[a];
-        be -= w[a] * (fv - 1.0) * gv[a];
-        // the face owned by the lower neighbour along a
-        if (lower[a]) {
-          const int di = a == 0 ? -1 : 0, dj = a == 1 ? -1 : 0, dk = a == 2 ? -1 : 0;
-          const double cu = I(di, dj, dk);
-          double gu[3];
-          fwd(di, dj, dk, cu, gu);
-          const double fu = factor(gu);
-          bc += w[a] * fu * gu[a];
-          be += w[a] * (fu - 1.0) * gu[a];
-        }
+        if (w[a] == (C)0) continue;
+        bc -= w[a] * fv * gv[a];  // the face this voxel owns
+        be -= w[a] * (fv - (C)1) * gv[a];
       }
-      st64(bout + G.off + k * pl + (int64_t)j * G.px + i, be);
-      sb += bc * bc;
-      se += be * be;
+      // faces owned by the lower neighbours along x, y (recomputed) and z (kept)
+      if (w[0] != (C)0 && i > 0) {
+        C g[3];
+        const C f = fwd(-1, 0, k, I(-1, 0, k), g);
+        bc += w[0] * f * g[0];
+        be += w[0] * (f - (C)1) * g[0];
+      }
+      if (w[1] != (C)0 && j > 0) {
+        C g[3];
+        const C f = fwd(0, -1, k, I(0, -1, k), g);
+        bc += w[1] * f * g[1];
+        be += w[1] * (f - (C)1) * g[1];
+      }
+      if (w[2] != (C)0 && k > 0) {
+        bc += w[2] * fz * gz;
+        be += w[2] * (fz - (C)1) * gz;
+      }
+      fz = fv;
+      gz = gv[2];
+      st64(bout + G.off + k * pl + (int64_t)j * G.px + i, (double)be);
+      sb += (double)bc * (double)bc;
+      se += (double)be * (double)be;
     }
   }
   const double s1 = block_sum(sb, red);
