@@ -37,13 +37,15 @@ __device__ __forceinline__ int bitrev(int v, int bits) {
 __device__ __forceinline__ int mk_pos(int j, int n) { return (j & 1) ? n - 1 - (j >> 1) : (j >> 1); }
 
 // lines along one axis of a contiguous [nz][ny][nx] array: element j of
-// line L is at (L mod nf) * sf + (L / nf) * ss + j * stride
+// line L is at (L mod nf) * sf + (L / nf) * ss + j * stride; every length
+// is a power of two, so the divisions are shifts
 struct DctLines {
   int n, logn;
   int64_t stride;
   int64_t nf, sf, ss;
+  int lognf;
   int64_t nlines;
-  int lpb;           // lines per block
+  int lpb, loglpb;   // lines per block
   bool adjacent;     // consecutive lines are consecutive in memory (sf == 1)
   // twiddles of this length: W[t] = exp(-2 pi i t / n), t < n / 2, and
   // Q[k] = exp(-i pi k / (2n)), k < n
@@ -85,57 +87,83 @@ __device__ __forceinline__ void st_any<__hip_bfloat16>(__hip_bfloat16* p, double
   *p = __float2bfloat16((float)v);
 }
 
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
 // one DCT-II (INV = false) or inverse pass along the lines of d, reading src
 // (type TI) and writing dst (type TO); src == dst for the FP64 work array
 // LDS (dynamic, sized by the launch): the block's lines as complex values,
-// then (inverse) their coefficients, read twice
+// then (inverse) their coefficients, read twice.
+// The FFT is decimation in time on bit-reversed input; two radix-2 stages
+// (half sizes h and 2h) are done at once as one radix-4 step on four values
+// h apart, so a length-2^m transform takes ceil(m / 2) barriers.
 template <bool INV, typename TI, typename TO>
 __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, DctLines d) {
   extern __shared__ double2 smem[];
-  const int n = d.n, lpb = d.lpb, tot = n * lpb;
+  const int n = d.n, logn = d.logn, lpb = d.lpb, tot = n << d.loglpb;
   double2* V = smem;
   double* X = reinterpret_cast<double*>(smem + tot);
-  const int64_t l0 = (int64_t)blockIdx.x * lpb;
+  const int64_t l0 = (int64_t)blockIdx.x << d.loglpb;
+  const int64_t fmask = d.nf - 1;
   auto base = [&](int l) -> int64_t {
     const int64_t L = l0 + l;
-    return (L % d.nf) * d.sf + (L / d.nf) * d.ss;
+    return (L & fmask) * d.sf + (L >> d.lognf) * d.ss;
   };
   auto split = [&](int e, int& l, int& j) {
-    if (d.adjacent) { l = e % lpb; j = e / lpb; }
-    else { l = e / n; j = e % n; }
+    if (d.adjacent) { l = e & (lpb - 1); j = e >> d.loglpb; }
+    else { l = e >> logn; j = e & (n - 1); }
   };
   for (int e = threadIdx.x; e < tot; e += DCT_NT) {
     int l, j;
     split(e, l, j);
     const double v = (l0 + l < d.nlines) ? ld_any(src + base(l) + j * d.stride) : 0.0;
-    if (!INV) V[l * n + bitrev(mk_pos(j, n), d.logn)] = make_double2(v, 0.0);
-    else X[l * n + j] = v;
+    if (!INV) V[(l << logn) + bitrev(mk_pos(j, n), logn)] = make_double2(v, 0.0);
+    else X[(l << logn) + j] = v;
   }
   __syncthreads();
   if (INV) {
     // V_k = exp(i pi k / 2n) (X_k - i X_{n-k}) = conj(Q_k) (X_k - i X_{n-k}), X_n = 0
     for (int e = threadIdx.x; e < tot; e += DCT_NT) {
-      const int l = e / n, k = e % n;
-      const double xk = X[l * n + k], xm = k == 0 ? 0.0 : X[l * n + n - k];
+      const int l = e >> logn, k = e & (n - 1);
+      const double xk = X[(l << logn) + k], xm = k == 0 ? 0.0 : X[(l << logn) + n - k];
       const double2 q = d.Q[k];
       const double ck = q.x, sk = -q.y;
-      V[l * n + bitrev(k, d.logn)] = make_double2(ck * xk + sk * xm, sk * xk - ck * xm);
+      V[(l << logn) + bitrev(k, logn)] = make_double2(ck * xk + sk * xm, sk * xk - ck * xm);
     }
     __syncthreads();
   }
-  // radix-2 FFT: stage with half-size h uses W[p n / (2h)] (conjugated for the inverse)
-  for (int st = 1; st <= d.logn; ++st) {
-    const int h = 1 << (st - 1), tw = n >> st;
-    for (int e = threadIdx.x; e < (n / 2) * lpb; e += DCT_NT) {
-      const int l = e / (n / 2), bfly = e % (n / 2);
-      const int grp = bfly / h, p = bfly % h;
-      const int i0 = l * n + grp * 2 * h + p, i1 = i0 + h;
-      const double2 w = d.W[p * tw];
-      const double cw = w.x, sw = INV ? -w.y : w.y;
-      const double2 u = V[i0], t = V[i1];
-      const double2 wt = make_double2(cw * t.x - sw * t.y, cw * t.y + sw * t.x);
-      V[i0] = make_double2(u.x + wt.x, u.y + wt.y);
-      V[i1] = make_double2(u.x - wt.x, u.y - wt.y);
+  int lh = 0;  // log2 of the half size of the next stage
+  if (logn & 1) {  // odd length exponent: one radix-2 stage of half size 1 (twiddle 1)
+    for (int e = threadIdx.x; e < (tot >> 1); e += DCT_NT) {
+      const double2 u = V[2 * e], t = V[2 * e + 1];
+      V[2 * e] = cadd(u, t);
+      V[2 * e + 1] = csub(u, t);
+    }
+    __syncthreads();
+    lh = 1;
+  }
+  for (; lh + 2 <= logn; lh += 2) {
+    // stages of half sizes h and 2h: twiddles W_{2h}^p = W[p n / 2h] and
+    // W_{4h}^p = W[p n / 4h]; the second stage's pair (p + h, p + 3h) takes
+    // W_{4h}^{p+h} = -i W_{4h}^p (+i for the inverse)
+    const int h = 1 << lh, t2 = logn - lh - 2;
+    for (int e = threadIdx.x; e < (tot >> 2); e += DCT_NT) {
+      const int l = e >> (logn - 2), q = e & ((n >> 2) - 1);
+      const int p = q & (h - 1);
+      const int i0 = (l << logn) + ((q >> lh) << (lh + 2)) + p;
+      double2 w1 = d.W[p << (t2 + 1)], w2 = d.W[p << t2];
+      if (INV) { w1.y = -w1.y; w2.y = -w2.y; }
+      const double2 a = V[i0], b = cmul(w1, V[i0 + h]), c = V[i0 + 2 * h], dd = cmul(w1, V[i0 + 3 * h]);
+      const double2 a1 = cadd(a, b), b1 = csub(a, b);
+      const double2 c1 = cmul(w2, cadd(c, dd)), d1 = cmul(w2, csub(c, dd));
+      const double2 jd = INV ? make_double2(-d1.y, d1.x) : make_double2(d1.y, -d1.x);
+      V[i0] = cadd(a1, c1);
+      V[i0 + h] = cadd(b1, jd);
+      V[i0 + 2 * h] = csub(a1, c1);
+      V[i0 + 3 * h] = csub(b1, jd);
     }
     __syncthreads();
   }
@@ -145,17 +173,17 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
     if (l0 + l >= d.nlines) continue;
     double out;
     if (!INV) {
-      const double2 q = d.Q[j], v = V[l * n + j];
+      const double2 q = d.Q[j], v = V[(l << logn) + j];
       out = q.x * v.x - q.y * v.y;  // Re(Q_j V_j)
       if (d.scale >= 0) {  // z-axis pass: line (i, jy), sample k = j
         const int64_t L = l0 + l;
-        const int i = (int)(L % d.nf), jy = (int)(L / d.nf);
+        const int i = (int)(L & fmask), jy = (int)(L >> d.lognf);
         out *= dct_factor(d.scale, d.lx[i], d.ly[jy], d.lz[j], i == 0 && jy == 0 && j == 0, d.alpha, d.wx, d.wy,
                           d.wz);
       }
     } else {
       const int m = (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
-      out = V[l * n + m].x / (double)n;
+      out = V[(l << logn) + m].x / (double)n;
     }
     st_any(dst + base(l) + j * d.stride, out);
   }
@@ -186,6 +214,32 @@ __global__ void k_dct_tables(int n, double2* W, double2* Q, double* lam) {
     Q[t] = make_double2(c, s);
     lam[t] = 2.0 - 2.0 * cospi((double)t / (double)n);
   }
+}
+
+// out[z][x][y] = in[z][y][x] for an [nz][ny][nx] FP64 array, through a
+// 32 x 32 LDS tile (one padding column against bank conflicts)
+__global__ void __launch_bounds__(256) k_transpose_xy(const double* __restrict__ in, double* __restrict__ out, int nx,
+                                                      int ny) {
+  __shared__ double T[32][33];
+  const int64_t z = blockIdx.z;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  const double* src = in + z * (int64_t)nx * ny;
+  double* dst = out + z * (int64_t)nx * ny;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int y = y0 + r, x = x0 + threadIdx.x;
+    if (x < nx && y < ny) T[r][threadIdx.x] = src[(int64_t)y * nx + x];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int x = x0 + r, y = y0 + threadIdx.x;
+    if (x < nx && y < ny) dst[(int64_t)x * ny + y] = T[threadIdx.x][r];
+  }
+}
+
+hipError_t dct_transpose_xy(const double* in, double* out, int nx, int ny, int nz, hipStream_t st) {
+  const dim3 grid((unsigned)((nx + 31) / 32), (unsigned)((ny + 31) / 32), (unsigned)nz);
+  hipLaunchKernelGGL(k_transpose_xy, grid, dim3(32, 8), 0, st, in, out, nx, ny);
+  return hipGetLastError();
 }
 
 // whole-array conversions (only for grids with every axis of length 1, where
@@ -262,6 +316,8 @@ hipError_t dct_pass(const DctPass& p, hipStream_t st) {
   if (d.lpb < 1) d.lpb = 1;
   if (d.lpb > 64) d.lpb = 64;
   if (d.lpb > d.nlines) d.lpb = (int)d.nlines;
+  d.loglpb = ilog2(d.lpb);
+  d.lognf = ilog2((int)d.nf);
   d.W = p.W; d.Q = p.Q;
   d.scale = p.scale;
   d.lx = p.lx; d.ly = p.ly; d.lz = p.lz;

@@ -76,36 +76,62 @@ hipError_t tables(int dev, int n, Tab* out, hipStream_t st) {
 }
 
 // forward DCT along x, y, z (the z pass also scales), inverse along z, y, x;
-// the first pass reads the caller's input and the last writes the output
+// the first pass reads the caller's input and the last writes the output.
+// Long y-lines (ny >= 512, nx > 1) are transposed into contiguous lines
+// first (a y pass over lines ny values apart reads short runs), and back
+// before the last x pass.
 gd_status spectral(const char* who, const void* in, gd_dtype it, void* out, gd_dtype ot, int64_t nx, int64_t ny,
                    int64_t nz, int mode, double alpha, double wx, double wy, double wz, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = nx * ny * nz;
+  const bool tr = ny >= 512 && nx > 1;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   double* w = nullptr;
   Tab tb[3];
   const int len[3] = {(int)nx, (int)ny, (int)nz};
   auto ok = [&](hipError_t r) { return r == hipSuccess; };
-  if (ok(e)) e = workspace(dev, n, &w);
+  if (ok(e)) e = workspace(dev, tr ? 2 * n : n, &w);
+  double* w2 = w + n;
   for (int a = 0; a < 3 && ok(e); ++a) e = tables(dev, len[a], &tb[a], st);
-  int axes[3], na = 0;
-  for (int a = 0; a < 3; ++a)
-    if (len[a] > 1) axes[na++] = a;
-  auto pass = [&](int a, bool inv, const void* src, gd_dtype ts, void* dst, gd_dtype td, int scale) {
-    gd::DctPass p{(int)nx, (int)ny, (int)nz, a, inv, src, ts, dst, td, tb[a].W, tb[a].Q, scale,
-                  tb[0].lam, tb[1].lam, tb[2].lam, alpha, wx, wy, wz};
+  // a pass over a volume of dims d[3] (x, y, z) along `axis`; tabs / weights
+  // of the volume's own x and y axes
+  auto pass = [&](const int d[3], const Tab* tx, const Tab* ty, double ax_w, double ay_w, int a, bool inv,
+                  const void* src, gd_dtype ts, void* dst, gd_dtype td, int scale) {
+    const Tab& ta = a == 0 ? *tx : (a == 1 ? *ty : tb[2]);
+    gd::DctPass p{d[0], d[1], d[2], a, inv, src, ts, dst, td, ta.W, ta.Q, scale, tx->lam, ty->lam, tb[2].lam,
+                  alpha, ax_w, ay_w, wz};
     return gd::dct_pass(p, st);
   };
-  const bool fused = na > 0 && axes[na - 1] == 2;  // the z pass exists and is the last forward pass
-  if (ok(e) && na == 0) e = gd::dct_convert(in, it, w, n, true, nullptr, st);
-  for (int q = 0; q < na && ok(e); ++q)
-    e = pass(axes[q], false, q == 0 ? in : w, q == 0 ? it : GD_F64, w, GD_F64, (fused && q == na - 1) ? mode : -1);
-  if (ok(e) && !fused)
-    e = gd::dct_scale(w, (int)nx, (int)ny, (int)nz, mode, tb[0].lam, tb[1].lam, tb[2].lam, alpha, wx, wy, wz, st);
-  for (int q = na - 1; q >= 0 && ok(e); --q)
-    e = pass(axes[q], true, w, GD_F64, q == 0 ? out : w, q == 0 ? ot : GD_F64, -1);
-  if (ok(e) && na == 0) e = gd::dct_convert(w, ot, nullptr, n, false, out, st);
+  if (tr) {
+    const int dn[3] = {(int)nx, (int)ny, (int)nz}, dt[3] = {(int)ny, (int)nx, (int)nz};
+    const bool zt = nz > 1;
+    if (ok(e)) e = pass(dn, &tb[0], &tb[1], wx, wy, 0, false, in, it, w, GD_F64, -1);
+    if (ok(e)) e = gd::dct_transpose_xy(w, w2, (int)nx, (int)ny, (int)nz, st);
+    if (ok(e)) e = pass(dt, &tb[1], &tb[0], wy, wx, 0, false, w2, GD_F64, w2, GD_F64, -1);
+    if (ok(e) && zt) e = pass(dt, &tb[1], &tb[0], wy, wx, 2, false, w2, GD_F64, w2, GD_F64, mode);
+    if (ok(e) && !zt)
+      e = gd::dct_scale(w2, (int)ny, (int)nx, (int)nz, mode, tb[1].lam, tb[0].lam, tb[2].lam, alpha, wy, wx, wz, st);
+    if (ok(e) && zt) e = pass(dt, &tb[1], &tb[0], wy, wx, 2, true, w2, GD_F64, w2, GD_F64, -1);
+    if (ok(e)) e = pass(dt, &tb[1], &tb[0], wy, wx, 0, true, w2, GD_F64, w2, GD_F64, -1);
+    if (ok(e)) e = gd::dct_transpose_xy(w2, w, (int)ny, (int)nx, (int)nz, st);
+    if (ok(e)) e = pass(dn, &tb[0], &tb[1], wx, wy, 0, true, w, GD_F64, out, ot, -1);
+  } else {
+    int axes[3], na = 0;
+    for (int a = 0; a < 3; ++a)
+      if (len[a] > 1) axes[na++] = a;
+    const int dn[3] = {(int)nx, (int)ny, (int)nz};
+    const bool fused = na > 0 && axes[na - 1] == 2;  // the z pass exists and is the last forward pass
+    if (ok(e) && na == 0) e = gd::dct_convert(in, it, w, n, true, nullptr, st);
+    for (int q = 0; q < na && ok(e); ++q)
+      e = pass(dn, &tb[0], &tb[1], wx, wy, axes[q], false, q == 0 ? in : w, q == 0 ? it : GD_F64, w, GD_F64,
+               (fused && q == na - 1) ? mode : -1);
+    if (ok(e) && !fused)
+      e = gd::dct_scale(w, (int)nx, (int)ny, (int)nz, mode, tb[0].lam, tb[1].lam, tb[2].lam, alpha, wx, wy, wz, st);
+    for (int q = na - 1; q >= 0 && ok(e); --q)
+      e = pass(dn, &tb[0], &tb[1], wx, wy, axes[q], true, w, GD_F64, q == 0 ? out : w, q == 0 ? ot : GD_F64, -1);
+    if (ok(e) && na == 0) e = gd::dct_convert(w, ot, nullptr, n, false, out, st);
+  }
   if (ok(e)) e = hipStreamSynchronize(st);
   if (e == hipErrorOutOfMemory) return gd::set_error(GD_ERR_NOMEM, std::string(who) + ": out of device memory");
   if (!ok(e)) return gd::set_error(GD_ERR_HIP, std::string(who) + ": " + hipGetErrorString(e));

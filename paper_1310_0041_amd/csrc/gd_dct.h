@@ -33,6 +33,8 @@ hipError_t dct_tables(int n, double2* W, double2* Q, double* lam, hipStream_t st
 // the scaling as its own pass over an FP64 array
 hipError_t dct_scale(double* c, int nx, int ny, int nz, int mode, const double* lx, const double* ly,
                      const double* lz, double alpha, double wx, double wy, double wz, hipStream_t st);
+// out[z][x][y] = in[z][y][x] of an [nz][ny][nx] FP64 array (out must not alias in)
+hipError_t dct_transpose_xy(const double* in, double* out, int nx, int ny, int nz, hipStream_t st);
 // dtype t -> FP64 (to64: in = caller array, out = FP64) or FP64 -> dtype t
 // (in = FP64 array, outp = caller array)
 hipError_t dct_convert(const void* in, gd_dtype t, double* out, int64_t n, bool to64, void* outp, hipStream_t st);

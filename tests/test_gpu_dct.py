@@ -15,8 +15,10 @@ from oracle import solvers
 
 pytestmark = pytest.mark.gpu
 
+# long y-lines (ny >= 512 with nx > 1) take the transposed path, with and
+# without a z axis
 SHAPES = [(8, 16, 32), (1, 1, 64), (4, 1, 8), (16, 64, 64), (2, 2, 2), (1, 1, 1), (32, 8, 4), (1, 4096, 2),
-          (2, 1, 4096)]
+          (2, 1, 4096), (4, 512, 64), (1, 512, 1024), (2, 1024, 1)]
 SYSTEMS = [(0.0, (1.0, 1.0, 4.0)), (0.01, (1.0, 1.0, 0.0)), (0.3, (2.0, 0.5, 1.0)), (0.001, (1.0, 1.0, 0.1))]
 
 
@@ -38,7 +40,7 @@ def test_dct_solve_matches_oracle(gd, shape, alpha, beta):
     assert np.abs(x - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("shape", [(16, 64, 64), (8, 128, 32), (1, 256, 256)])
+@pytest.mark.parametrize("shape", [(16, 64, 64), (8, 128, 32), (1, 256, 256), (4, 512, 32), (1, 1024, 64)])
 @pytest.mark.parametrize("tin", [torch.float32, torch.float16])
 def test_dct_ad_closed_form(gd, shape, tin):
     say("dct AD", shape, tin)
