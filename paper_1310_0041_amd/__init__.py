@@ -98,6 +98,10 @@ _SIGS = {
     "gd_hierarchy_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "gd_rhs_general": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gd_vcycle": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
+    "gd_hierarchy_create_streamed": (_i, [ctypes.POINTER(_vp), _i64, _i64, _i64, _d, _d, _d, _d, _i,
+                                          ctypes.POINTER(SolveOpts), _i64, _vp]),
+    "gd_vcycle_streamed": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
+    "gd_hierarchy_device_bytes": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "gd_rb_sweep": (_i, [_vp, _vp, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _d, _vp]),
     "gd_residual_restrict": (_i, [_vp, _vp, _vp, _i, _i64, _i64, _i64, _i, _i, _i, _d, _d, _d, _d,
                                   ctypes.POINTER(_d), _vp]),
@@ -345,6 +349,12 @@ class Hierarchy:
         d["status"] = st
         return d
 
+    def device_bytes(self):
+        """(device bytes held, planes of the largest window; 0 unless streamed)."""
+        b, w = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.gd_hierarchy_device_bytes(self._h, ctypes.byref(b), ctypes.byref(w)))
+        return b.value, w.value
+
     def close(self):
         if self._h:
             _lib.gd_hierarchy_destroy(self._h)
@@ -355,6 +365,41 @@ class Hierarchy:
             self.close()
         except Exception:
             pass
+
+
+def _host_ptr(t):
+    if t.is_cuda:
+        raise ValueError("a streamed hierarchy takes host (CPU) tensors")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class StreamedHierarchy(Hierarchy):
+    """A hierarchy whose finest level stays in host memory and is streamed
+    through HBM in z-slabs of `slab` planes (Sec. 4.1); the coarser levels
+    are resident.  vcycle takes CPU tensors (pinned ones let the copies
+    overlap the kernels)."""
+
+    def __init__(self, shape, alpha, beta, dtype, slab, opts=None, **kw):
+        lib = load()
+        nz, ny, nx = shape
+        self.shape = tuple(shape)
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        o = opts or default_opts(**kw)
+        _check(lib.gd_hierarchy_create_streamed(ctypes.byref(self._h), nx, ny, nz, float(alpha), float(beta[0]),
+                                                float(beta[1]), float(beta[2]), gd_dtype(dtype), ctypes.byref(o),
+                                                int(slab), _stream()))
+
+    def vcycle(self, x, b, ncycles=1, relres=True):
+        for t in (x, b):
+            if tuple(t.shape) != self.shape or t.dtype != self.dtype:
+                raise ValueError("x and b must have the hierarchy's shape and dtype")
+        rr = ctypes.c_double()
+        _check(_lib.gd_vcycle_streamed(self._h, _host_ptr(x), _host_ptr(b), int(ncycles),
+                                       ctypes.byref(rr) if relres else None, _stream()))
+        return rr.value if relres else None
 
 
 class Net:

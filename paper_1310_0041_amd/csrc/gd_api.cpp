@@ -135,6 +135,7 @@ struct Hier {
   int ngrids = 0;
   std::vector<Level> lv;
   std::vector<void*> allocs;
+  size_t bytes = 0;  // device bytes held through alloc()
   double* partials = nullptr;
   double* dred = nullptr;    // ngrids * 2
   double* dscal = nullptr;   // ngrids * 4: scale, inv_scale, shift, spare
@@ -181,6 +182,7 @@ struct Hier {
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
     allocs.push_back(p);
+    this->bytes += bytes;
     return p;
   }
   Geom g_sw(int l) const { return lv[l].sw.geom(lv[l].d, ngrids, lv[l].row); }
@@ -242,8 +244,11 @@ static int64_t sweep_target(bool row = false) {
   return row ? vr : v3;
 }
 
+// finest_arrays false: level 0 gets launch tables but no x / xt / b (its
+// data lives elsewhere); max_levels > 0 stops the hierarchy after that many.
 static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
-                                        hipStream_t st, int tile_force = -1) {
+                                        hipStream_t st, int tile_force = -1, bool finest_arrays = true,
+                                        int max_levels = 0) {
   auto H = std::make_unique<Hier>();
   HIP_TRY(hipGetDevice(&H->device));
   H->s = s;
@@ -290,7 +295,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     L.h = cur;
     L.total = off;
     H->lv.push_back(std::move(L));
-    if (!more) break;
+    if (!more || (max_levels > 0 && (int)H->lv.size() >= max_levels)) break;
     std::vector<GridDesc> nxt(cur.size());
     int64_t coff = 0;
     for (size_t i = 0; i < cur.size(); ++i) {
@@ -356,9 +361,11 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     for (int k = 0; k < 5; ++k)
       std::memcpy(stage.data() + gbytes + k * nb * sizeof(int64_t), tabs[k]->h_b0.data(), nb * sizeof(int64_t));
     HIP_TRY(hipMemcpy(dev, stage.data(), bytes, hipMemcpyHostToDevice));
-    L.x = H->alloc(L.total * es);
-    L.xt = H->alloc(L.total * es);
-    L.b = H->alloc(L.total * es);
+    if (li > 0 || finest_arrays) {
+      L.x = H->alloc(L.total * es);
+      L.xt = H->alloc(L.total * es);
+      L.b = H->alloc(L.total * es);
+    }
   }
   H->partials = (double*)H->alloc(maxblocks * 2 * sizeof(double));
   H->dred = (double*)H->alloc(H->ngrids * 2 * sizeof(double));
@@ -1453,8 +1460,52 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
 
 // ------------------------------------------------------------ hierarchy API
 
+// Finest level held in host memory (Sec. 4.1: every V-cycle is two
+// streaming passes through the data with a window over the slices).  The
+// z-axis is cut into slabs of `slab` planes; slab [z0, z1) is processed in a
+// window [a, e) = [z0 - halo, z1 + halo) clipped to the grid, with halo =
+// 2 max(pre, post) + 2 planes: a red-black sweep moves an error of the
+// window's cut faces two planes inwards, the residual one more and the
+// pairwise restriction stays within an even-aligned pair, so the planes
+// [z0, z1) come out as in a sweep of the whole grid.  Windows start on even
+// planes (slab and halo are even), which keeps the red-black colouring and
+// the pairing of planes by the restriction.  Two window buffer sets
+// alternate: the next window is uploaded and the previous one written back
+// on streams of their own while the current one is relaxed.
+struct Streamer {
+  struct Win {
+    int64_t a, e, z0, z1;
+  };
+  int64_t slab = 0, halo = 0;
+  std::vector<Win> wins;
+  std::map<int64_t, std::unique_ptr<Hier>> sets[2];  // window planes -> window hierarchy (levels 0 and 1)
+  hipStream_t up = nullptr, down = nullptr;
+  hipEvent_t loaded[2] = {}, computed[2] = {}, unloaded[2] = {}, start = nullptr, done_up = nullptr,
+             done_down = nullptr;
+  Hier& win(int k, int64_t planes) { return *sets[k].at(planes); }
+  size_t bytes() const {
+    size_t b = 0;
+    for (const auto& m : sets)
+      for (const auto& kv : m) b += kv.second->bytes;
+    return b;
+  }
+  ~Streamer() {
+    for (int k = 0; k < 2; ++k) {
+      if (loaded[k]) (void)hipEventDestroy(loaded[k]);
+      if (computed[k]) (void)hipEventDestroy(computed[k]);
+      if (unloaded[k]) (void)hipEventDestroy(unloaded[k]);
+    }
+    if (start) (void)hipEventDestroy(start);
+    if (done_up) (void)hipEventDestroy(done_up);
+    if (done_down) (void)hipEventDestroy(done_down);
+    if (up) (void)hipStreamDestroy(up);
+    if (down) (void)hipStreamDestroy(down);
+  }
+};
+
 struct gd_hierarchy {
   std::unique_ptr<Hier> H;
+  std::unique_ptr<Streamer> sm;  // set: the finest level is streamed from host memory
   gd_solve_opts o;
   void* kv[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // Krylov vectors r, z, p, q, t, u
   ~gd_hierarchy() {
@@ -1496,18 +1547,15 @@ static void set_coef(Hier& H, double a, double b, hipStream_t st) {
 }
 }  // namespace gd
 
-gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t nz, double alpha, double bx, double by,
-                              double bz, gd_dtype s, const gd_solve_opts* opts, void* stream) {
-  if (!h) return fail(GD_ERR_INVALID, "gd_hierarchy_create: null handle pointer");
-  *h = nullptr;
+static gd_status hier_args(const std::string& who, int64_t nx, int64_t ny, int64_t nz, double alpha, double bx,
+                           double by, double bz, gd_dtype s, const gd_solve_opts* opts, gd_solve_opts& o) {
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
-    return fail(GD_ERR_INVALID, "gd_hierarchy_create: bad size");
-  if (nx * ny > MAX_PLANE) return fail(GD_ERR_UNSUPPORTED, "gd_hierarchy_create: x-y plane above 2^28 cells");
-  if (!valid_dtype(s)) return fail(GD_ERR_INVALID, "gd_hierarchy_create: bad dtype");
+    return fail(GD_ERR_INVALID, who + ": bad size");
+  if (nx * ny > MAX_PLANE) return fail(GD_ERR_UNSUPPORTED, who + ": x-y plane above 2^28 cells");
+  if (!valid_dtype(s)) return fail(GD_ERR_INVALID, who + ": bad dtype");
   if (!(alpha >= 0.0) || !(bx >= 0.0) || !(by >= 0.0) || !(bz >= 0.0) || !std::isfinite(alpha) ||
       !std::isfinite(bx) || !std::isfinite(by) || !std::isfinite(bz) || (alpha == 0.0 && bx == 0.0 && by == 0.0 && bz == 0.0))
-    return fail(GD_ERR_INVALID, "gd_hierarchy_create: weights must be >= 0 and not all zero");
-  gd_solve_opts o;
+    return fail(GD_ERR_INVALID, who + ": weights must be >= 0 and not all zero");
   gd_default_opts(&o);
   if (opts) o = *opts;
   o.storage = s;
@@ -1515,7 +1563,17 @@ gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t 
   if (!(o.rel_tol > 0.0) || o.pre_smooth < 0 || o.post_smooth < 0 || o.pre_smooth + o.post_smooth < 1 ||
       (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3 || o.discretization < 0 ||
       o.discretization > 2)
-    return fail(GD_ERR_INVALID, "gd_hierarchy_create: invalid options");
+    return fail(GD_ERR_INVALID, who + ": invalid options");
+  return GD_OK;
+}
+
+gd_status gd_hierarchy_create(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t nz, double alpha, double bx, double by,
+                              double bz, gd_dtype s, const gd_solve_opts* opts, void* stream) {
+  if (!h) return fail(GD_ERR_INVALID, "gd_hierarchy_create: null handle pointer");
+  *h = nullptr;
+  gd_solve_opts o;
+  const gd_status a = hier_args("gd_hierarchy_create", nx, ny, nz, alpha, bx, by, bz, s, opts, o);
+  if (a != GD_OK) return a;
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     auto hh = std::make_unique<gd_hierarchy>();
@@ -1548,6 +1606,7 @@ gd_status gd_hierarchy_info(const gd_hierarchy* h, int level, int* nlevels, int6
 
 gd_status gd_rhs_general(gd_hierarchy* h, const void* V, const void* Gx, const void* Gy, const void* Gz, void* b,
                          void* stream) {
+  if (h && h->sm) return fail(GD_ERR_INVALID, "gd_rhs_general: the hierarchy streams its finest level (gd_vcycle_streamed)");
   if (!h || !b) return fail(GD_ERR_INVALID, "gd_rhs_general: null pointer");
   Hier& H = *h->H;
   if (H.lv[0].h[0].alpha != 0.0 && !V) return fail(GD_ERR_INVALID, "gd_rhs_general: V is required when alpha > 0");
@@ -1561,6 +1620,7 @@ gd_status gd_rhs_general(gd_hierarchy* h, const void* V, const void* Gx, const v
 }
 
 gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles, double* relres, void* stream) {
+  if (h && h->sm) return fail(GD_ERR_INVALID, "gd_vcycle: the hierarchy streams its finest level (gd_vcycle_streamed)");
   if (!h || !x || !b) return fail(GD_ERR_INVALID, "gd_vcycle: null pointer");
   if (x == b) return fail(GD_ERR_INVALID, "gd_vcycle: x aliases b");
   Hier& H = *h->H;
@@ -1592,10 +1652,188 @@ gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles, double
   });
 }
 
+// ------------------------------------------------ streamed finest level
+
+gd_status gd_hierarchy_create_streamed(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t nz, double alpha,
+                                       double bx, double by, double bz, gd_dtype s, const gd_solve_opts* opts,
+                                       int64_t slab, void* stream) {
+  const char* who = "gd_hierarchy_create_streamed";
+  if (!h) return fail(GD_ERR_INVALID, std::string(who) + ": null handle pointer");
+  *h = nullptr;
+  gd_solve_opts o;
+  const gd_status a = hier_args(who, nx, ny, nz, alpha, bx, by, bz, s, opts, o);
+  if (a != GD_OK) return a;
+  if (slab <= 0) return fail(GD_ERR_INVALID, std::string(who) + ": slab must be > 0");
+  if (o.discretization != 0)
+    return fail(GD_ERR_UNSUPPORTED, std::string(who) + ": only the Constant discretisation is streamed");
+  if (ny < 2) return fail(GD_ERR_UNSUPPORTED, std::string(who) + ": ny must be >= 2");
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    auto hh = std::make_unique<gd_hierarchy>();
+    hh->o = o;
+    hh->o.timing = 0;
+    hh->H = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, o.sweep_tile, false);
+    Hier& H = *hh->H;
+    if (H.lv.size() < 2) throw Unsupported("the grid has no coarser level to stream against");
+    auto sm = std::make_unique<Streamer>();
+    // slab even and at least the halo, so that only the next window reads
+    // planes of a slab (its halo) before they are written back
+    sm->halo = 2 * std::max(o.pre_smooth, o.post_smooth) + 2;
+    sm->slab = std::min<int64_t>(nz, std::max<int64_t>(slab + (slab & 1), sm->halo));
+    for (int64_t z0 = 0; z0 < nz; z0 += sm->slab) {
+      const int64_t z1 = std::min(nz, z0 + sm->slab);
+      sm->wins.push_back({std::max<int64_t>(0, z0 - sm->halo), std::min(nz, z1 + sm->halo), z0, z1});
+    }
+    const int tile = H.lv[0].sw.tile;
+    for (const auto& w : sm->wins)
+      for (int k = 0; k < 2; ++k)
+        if (!sm->sets[k].count(w.e - w.a))
+          sm->sets[k][w.e - w.a] =
+              build_hier({{nx, ny, w.e - w.a, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, tile, true, 2);
+    HIP_TRY(hipStreamCreateWithFlags(&sm->up, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&sm->down, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k) {
+      HIP_TRY(hipEventCreateWithFlags(&sm->loaded[k], hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&sm->computed[k], hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&sm->unloaded[k], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&sm->start, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&sm->done_up, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&sm->done_down, hipEventDisableTiming));
+    hh->sm = std::move(sm);
+    *h = hh.release();
+    return GD_OK;
+  });
+}
+
+// One streaming pass over the finest level.  down: pre-smoothing, then the
+// residual restricted into level 1 (whose iterate is zeroed); up: the level-1
+// correction interpolated and added, then post-smoothing.  x is written back
+// to host memory slab by slab.
+static void stream_pass(gd_hierarchy& h, bool down, void* xh, const void* bh, hipStream_t st) {
+  Hier& H = *h.H;
+  Streamer& S = *h.sm;
+  Level& C = H.lv[1];
+  const GridDesc& g0 = H.lv[0].h[0];
+  const size_t es = dsize(H.s);
+  const size_t wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es;
+  const size_t hplane = (size_t)g0.nx * g0.ny * es, dplane = (size_t)g0.px * g0.ny * es;
+  const size_t cplane = (size_t)g0.cpx * g0.cny * es;
+  const int64_t fz = g0.fz;
+  HIP_TRY(hipEventRecord(S.start, st));
+  HIP_TRY(hipStreamWaitEvent(S.up, S.start, 0));
+  HIP_TRY(hipStreamWaitEvent(S.down, S.start, 0));
+  if (down) HIP_TRY(hipMemsetAsync(C.x, 0, (size_t)C.total * es, st));
+  const size_t n = S.wins.size();
+  auto load = [&](size_t w) {
+    const Streamer::Win& W = S.wins[w];
+    const int k = (int)(w & 1);
+    Level& L = S.win(k, W.e - W.a).lv[0];
+    if (w >= 2) HIP_TRY(hipStreamWaitEvent(S.up, S.unloaded[k], 0));
+    const size_t rows = (size_t)g0.ny * (W.e - W.a);
+    HIP_TRY(hipMemcpy2DAsync(L.x, pb, (const char*)xh + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, S.up));
+    HIP_TRY(hipMemcpy2DAsync(L.b, pb, (const char*)bh + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, S.up));
+    HIP_TRY(hipEventRecord(S.loaded[k], S.up));
+  };
+  load(0);
+  for (size_t w = 0; w < n; ++w) {
+    if (w + 1 < n) load(w + 1);
+    const Streamer::Win& W = S.wins[w];
+    const int k = (int)(w & 1);
+    Hier& WH = S.win(k, W.e - W.a);
+    HIP_TRY(hipStreamWaitEvent(st, S.loaded[k], 0));
+    Cycler cy(WH, st, h.o);
+    if (down) {
+      cy.smooth(0, h.o.pre_smooth);
+      HIP_TRY(launch_restrict_z(WH.s, WH.g_rz(0), WH.lv[0].x, WH.lv[0].b, WH.lv[1].b, WH.lv[1].x, nullptr, st));
+      const int64_t c0 = W.z0 / fz, c1 = (W.z1 + fz - 1) / fz;  // coarse planes of [z0, z1)
+      HIP_TRY(hipMemcpyAsync((char*)C.b + c0 * cplane, (const char*)WH.lv[1].b + (c0 - W.a / fz) * cplane,
+                             (size_t)(c1 - c0) * cplane, hipMemcpyDeviceToDevice, st));
+    } else {
+      const void* ec = (const char*)C.x + (W.a / fz) * cplane;
+      if (h.o.fuse_prolong != 0 && h.o.post_smooth > 0 && WH.lv[0].sw.tile == 0) {
+        cy.smooth(0, h.o.post_smooth, ec);
+      } else {
+        HIP_TRY(launch_prolong_pair(WH.s, WH.g_pp(0), ec, WH.lv[0].x, h.o.prolong, WH.lv[0].keep_x, st));
+        cy.smooth(0, h.o.post_smooth);
+      }
+    }
+    HIP_TRY(hipEventRecord(S.computed[k], st));
+    HIP_TRY(hipStreamWaitEvent(S.down, S.computed[k], 0));
+    // the next window's halo holds this slab's last planes as they were
+    // before this pass: write back only after it has been read
+    if (w + 1 < n) HIP_TRY(hipStreamWaitEvent(S.down, S.loaded[(w + 1) & 1], 0));
+    HIP_TRY(hipMemcpy2DAsync((char*)xh + W.z0 * hplane, wb, (const char*)WH.lv[0].x + (W.z0 - W.a) * dplane, pb, wb,
+                             (size_t)g0.ny * (W.z1 - W.z0), hipMemcpyDeviceToHost, S.down));
+    HIP_TRY(hipEventRecord(S.unloaded[k], S.down));
+  }
+  HIP_TRY(hipEventRecord(S.done_up, S.up));
+  HIP_TRY(hipEventRecord(S.done_down, S.down));
+  HIP_TRY(hipStreamWaitEvent(st, S.done_up, 0));
+  HIP_TRY(hipStreamWaitEvent(st, S.done_down, 0));
+}
+
+gd_status gd_vcycle_streamed(gd_hierarchy* h, void* x, const void* b, int ncycles, double* relres, void* stream) {
+  if (!h || !x || !b) return fail(GD_ERR_INVALID, "gd_vcycle_streamed: null pointer");
+  if (!h->sm) return fail(GD_ERR_INVALID, "gd_vcycle_streamed: the hierarchy keeps its finest level in HBM (gd_vcycle)");
+  if (x == b) return fail(GD_ERR_INVALID, "gd_vcycle_streamed: x aliases b");
+  if (ncycles < 0) return fail(GD_ERR_INVALID, "gd_vcycle_streamed: ncycles < 0");
+  Hier& H = *h->H;
+  Streamer& S = *h->sm;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    Cycler cy(H, st, h->o);
+    for (int c = 0; c < ncycles; ++c) {
+      stream_pass(*h, true, x, b, st);
+      cy.below(1);
+      stream_pass(*h, false, x, b, st);
+    }
+    if (relres) {  // ||b - A x|| / ||b||, every window contributing its own slab's planes
+      const GridDesc& g0 = H.lv[0].h[0];
+      const size_t es = dsize(H.s), wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es;
+      const size_t hplane = (size_t)g0.nx * g0.ny * es;
+      double rr = 0.0, bb = 0.0;
+      for (const auto& W : S.wins) {
+        Hier& WH = S.win(0, W.e - W.a);
+        Level& L = WH.lv[0];
+        const size_t rows = (size_t)g0.ny * (W.e - W.a);
+        HIP_TRY(hipMemcpy2DAsync(L.x, pb, (const char*)x + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpy2DAsync(L.b, pb, (const char*)b + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_general_residual(WH.s, WH.g_ew(0), L.x, L.b, nullptr, WH.partials, st, true,
+                                        (int)(W.z0 - W.a), (int)(W.z1 - W.a)));
+        HIP_TRY(launch_reduce(WH.partials, L.ew.d_b0, 1, 2, WH.dred, st));
+        read_dred(WH, 2, st);
+        rr += WH.hpin[0];
+        bb += WH.hpin[1];
+      }
+      rr = std::sqrt(rr);
+      bb = std::sqrt(bb);
+      *relres = bb > 0.0 ? rr / bb : rr;
+      if (!std::isfinite(*relres)) return fail(GD_ERR_NUMERIC, "gd_vcycle_streamed: non-finite residual");
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+  });
+}
+
+gd_status gd_hierarchy_device_bytes(const gd_hierarchy* h, int64_t* bytes, int64_t* window_planes) {
+  if (!h || !bytes) return fail(GD_ERR_INVALID, "gd_hierarchy_device_bytes: null pointer");
+  size_t b = h->H->bytes;
+  int64_t wp = 0;
+  if (h->sm) {
+    b += h->sm->bytes();
+    for (const auto& W : h->sm->wins) wp = std::max(wp, W.e - W.a);
+  }
+  *bytes = (int64_t)b;
+  if (window_planes) *window_planes = wp;
+  return GD_OK;
+}
+
 // ---------------------------------------------------- flexible CG + pairs
 
 gd_status gd_mg_error_pairs(gd_hierarchy* h, const void* b, const void* x_star, int cycles, void* r_out, void* e_out,
                             void* stream) {
+  if (h && h->sm) return fail(GD_ERR_INVALID, "gd_mg_error_pairs: the hierarchy streams its finest level (gd_vcycle_streamed)");
   if (!h || !b || !x_star || !r_out || !e_out) return fail(GD_ERR_INVALID, "gd_mg_error_pairs: null pointer");
   if (cycles < 0) return fail(GD_ERR_INVALID, "gd_mg_error_pairs: cycles < 0");
   Hier& H = *h->H;
@@ -1623,6 +1861,7 @@ gd_status gd_mg_error_pairs(gd_hierarchy* h, const void* b, const void* x_star, 
 
 gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int precond, double rel_tol,
                        int max_iter, gd_solve_report* rep, void* stream) {
+  if (h && h->sm) return fail(GD_ERR_INVALID, "gd_fcg_solve: the hierarchy streams its finest level (gd_vcycle_streamed)");
   if (!h || !x || !b) return fail(GD_ERR_INVALID, "gd_fcg_solve: null pointer");
   if (x == b) return fail(GD_ERR_INVALID, "gd_fcg_solve: x aliases b");
   if (precond < 0 || precond > 3 || (precond > 0 && !net))

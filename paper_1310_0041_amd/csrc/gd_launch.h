@@ -74,9 +74,11 @@ hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const vo
                               const void* Gy, const void* Gz, void* b, hipStream_t st);
 // Generic system: per block (sum (b - A x)^2, sum b^2) in FP64; r_out
 // (may be NULL) receives b - A x.  lib_layout: x, b, r are a hierarchy level
-// (offset off, pitch px) instead of the caller's arrays.
+// (offset off, pitch px) instead of the caller's arrays.  Planes outside
+// [klo, khi) are skipped (neither summed nor written).
 hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b, void* r_out,
-                                   double* partials, hipStream_t st, bool lib_layout = false);
+                                   double* partials, hipStream_t st, bool lib_layout = false, int klo = 0,
+                                   int khi = 0x7fffffff);
 // Hybrid discretisation (Sec. 4.2): a table level's operator is
 // alpha Mx My Mz + w_x Kx My Mz + w_y Mx Ky Mz + w_z Mx My Kz, t[a] the device
 // table block of axis a (six rows of n_a doubles: M below/on/above the

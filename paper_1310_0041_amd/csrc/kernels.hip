@@ -1255,12 +1255,13 @@ k_rhs_general(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 }
 
 // LIB: the arrays are a level of the library's hierarchy (offset off, row
-// pitch px) instead of the caller's layout.
+// pitch px) instead of the caller's layout.  Only planes klo <= k < khi are
+// visited (a window whose outer planes are halo).
 template <typename S, bool LIB>
 __global__ void __launch_bounds__(256)
 k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids,
                    int zlen, int etx, const S* __restrict__ xin, const S* __restrict__ bin, S* __restrict__ rout,
-                   double* __restrict__ partials) {
+                   double* __restrict__ partials, int klo, int khi) {
   __shared__ double red[4];
   const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
@@ -1270,7 +1271,8 @@ k_general_residual(const GridDesc* __restrict__ grids, const int64_t* __restrict
   if (i < nx && j < ny) {
     const int64_t pl = LIB ? (int64_t)G.px * ny : G.ipz, py = LIB ? (int64_t)G.px : G.ipy;
     const int64_t base = LIB ? G.off : G.ioff;
-    for (int k = t.z0; k < t.z1; ++k) {
+    const int ka = t.z0 > klo ? t.z0 : klo, kb = t.z1 < khi ? t.z1 : khi;
+    for (int k = ka; k < kb; ++k) {
       const int64_t v = base + k * pl + (int64_t)j * py + i;
       const double xc = ld64(xin + v), bv = ld64(bin + v);
       double r = bv - G.alpha * xc;
@@ -1968,13 +1970,15 @@ hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const vo
 }
 
 hipError_t launch_general_residual(gd_dtype s, const Geom& g, const void* x, const void* b, void* r_out,
-                                   double* partials, hipStream_t st, bool lib_layout) {
+                                   double* partials, hipStream_t st, bool lib_layout, int klo, int khi) {
   if (g.nblocks == 0) return hipSuccess;
-#define L(T)                                                                                                      \
-  if (lib_layout)                                                                                                 \
-    hipLaunchKernelGGL((k_general_residual<T, true>), GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, partials); \
-  else                                                                                                            \
-    hipLaunchKernelGGL((k_general_residual<T, false>), GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, partials)
+#define L(T)                                                                                              \
+  if (lib_layout)                                                                                         \
+    hipLaunchKernelGGL((k_general_residual<T, true>), GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out,  \
+                       partials, klo, khi);                                                               \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_general_residual<T, false>), GD_ARGS(g), (const T*)x, (const T*)b, (T*)r_out, \
+                       partials, klo, khi)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();

@@ -1,0 +1,136 @@
+"""Finest level streamed from host memory (Sec. 4.1: each V-cycle is two
+streaming passes through the data with a window over the slices).
+
+The streamed cycle relaxes every slab inside a halo wide enough that its own
+planes come out as in a cycle over the whole grid, so it must agree with the
+in-core V-cycle bit for bit (same kernels, same per-voxel arithmetic).  It is
+also checked against the oracle: the FP64 residual of the iterate and the
+exact DCT solution of the same system.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mgsteps as om
+from oracle import solvers as osv
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# (shape [nz][ny][nx], slab, dtype, alpha, beta, pre/post): several windows
+# with a ragged last slab, odd nz, a slab below the halo (raised to it), one
+# window holding the whole grid, z kept at level 0 (beta_z small), FP16 and
+# FP64 storage, unequal pre- and post-smoothing
+CASES = [
+    ((40, 33, 47), 8, torch.float32, 0.0, (1.0, 1.0, 4.0), (2, 2)),
+    ((37, 16, 64), 10, torch.float32, 0.0, (1.0, 1.0, 4.0), (2, 2)),
+    ((45, 20, 24), 4, torch.float32, 0.02, (1.0, 1.0, 1.0), (2, 2)),
+    ((18, 20, 20), 64, torch.float32, 0.0, (1.0, 1.0, 4.0), (2, 2)),
+    ((48, 24, 30), 12, torch.float32, 0.01, (1.0, 1.0, 0.2), (2, 2)),
+    ((64, 24, 40), 16, torch.float16, 0.0, (1.0, 1.0, 4.0), (2, 2)),
+    ((33, 18, 22), 8, torch.float64, 0.05, (1.0, 0.5, 2.0), (2, 2)),
+    ((52, 16, 20), 10, torch.float32, 0.0, (1.0, 1.0, 4.0), (1, 3)),
+]
+
+
+def case_id(c):
+    return f"{c[0]}-slab{c[1]}-{str(c[2]).split('.')[-1]}-a{c[3]}-p{c[5]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=case_id)
+def test_streamed_cycles_equal_in_core(gd, case):
+    shape, slab, dt, alpha, beta, (pre, post) = case
+    say("streamed vs in-core", case_id(case))
+    rng = np.random.default_rng(11)
+    b = torch.from_numpy(rng.standard_normal(shape)).to(dt)
+    x0 = torch.from_numpy(rng.standard_normal(shape) * 0.5).to(dt)
+    hc = gd.Hierarchy(shape, alpha, beta, dt, pre_smooth=pre, post_smooth=post)
+    xd, bd = x0.cuda(), b.cuda()
+    rr_c = hc.vcycle(xd, bd, 2)
+    hs = gd.StreamedHierarchy(shape, alpha, beta, dt, slab, pre_smooth=pre, post_smooth=post)
+    assert hs.info() == hc.info()
+    xh = torch.empty(shape, dtype=dt, pin_memory=True)
+    xh.copy_(x0)
+    bh = torch.empty(shape, dtype=dt, pin_memory=True)
+    bh.copy_(b)
+    rr_s = hs.vcycle(xh, bh, 2)
+    assert torch.equal(xh, xd.cpu())
+    assert abs(rr_s - rr_c) <= 1e-9 * rr_c
+    _, planes = hs.device_bytes()
+    halo = 2 * max(pre, post) + 2
+    want = min(shape[0], max(slab + slab % 2, halo) + 2 * halo)
+    assert planes == want
+    hs.close()
+    hc.close()
+
+
+def test_pageable_host_memory(gd):
+    say("streamed pageable")
+    shape = (30, 16, 24)
+    rng = np.random.default_rng(12)
+    b = torch.from_numpy(rng.standard_normal(shape)).float()
+    hc = gd.Hierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32)
+    xd = torch.zeros(shape, device="cuda")
+    hc.vcycle(xd, b.cuda(), 3)
+    hs = gd.StreamedHierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32, 8)
+    xh = torch.zeros(shape)
+    hs.vcycle(xh, b.clone(), 3)
+    assert torch.equal(xh, xd.cpu())
+
+
+def test_streamed_solve_matches_oracle(gd):
+    """FP64 storage, cycles until the residual is at the FP64 level; the
+    oracle's own residual of the iterate and the exact DCT solution."""
+    say("streamed vs oracle")
+    shape = (41, 20, 26)
+    alpha, beta = 0.05, (1.0, 0.5, 2.0)
+    b = np.random.default_rng(13).standard_normal(shape)
+    hs = gd.StreamedHierarchy(shape, alpha, beta, torch.float64, 8)
+    xh = torch.zeros(shape, dtype=torch.float64, pin_memory=True)
+    bh = torch.from_numpy(b).pin_memory()
+    rr = 1.0
+    for _ in range(30):
+        rr = hs.vcycle(xh, bh, 1)
+        if rr < 1e-11:
+            break
+    assert rr < 1e-11
+    x = xh.numpy()
+    ores = om.relative_residual(x, b, alpha, beta)
+    assert ores <= 1.01e-11
+    kappa = (alpha + 4 * sum(beta)) / alpha
+    assert rel(x, osv.dct_solve(b, alpha, beta)) <= kappa * ores * 1.01
+
+
+def test_streamed_holds_less_device_memory(gd):
+    say("streamed device bytes")
+    shape = (512, 64, 64)
+    hc = gd.Hierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32)
+    hs = gd.StreamedHierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32, 16)
+    bc, _ = hc.device_bytes()
+    bs, planes = hs.device_bytes()
+    assert planes == 16 + 2 * 6
+    # in core: x, x', b of every level (about 3 x 1.57 finest arrays); streamed:
+    # the coarse levels (about 3 x 0.57) and two windows
+    assert bs < 0.6 * bc
+
+
+def test_in_core_calls_refuse_a_streamed_hierarchy(gd):
+    say("streamed refusals")
+    shape = (16, 8, 8)
+    hs = gd.StreamedHierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32, 8)
+    x = torch.zeros(shape, device="cuda")
+    with pytest.raises(RuntimeError):
+        gd.Hierarchy.vcycle(hs, x, x.clone(), 1)
+    with pytest.raises(RuntimeError):
+        hs.fcg(x, x.clone())
+    with pytest.raises(ValueError):
+        hs.vcycle(torch.zeros(4, 8, 8), torch.zeros(4, 8, 8))
