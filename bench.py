@@ -31,6 +31,10 @@ WORKLOADS = {
                  "solver (FP64 DCT-II diagonalisation, exact) beside the FP32 multigrid AD to 1e-6"),
     "npr-video": ("npr", "f32", 0, "1920x1080x742 grey-level video volume, gradient-modulation filter of Sec. 6 "
                   "(alpha 0.001, W = diag(1, 1, 0.1), lambda 1.25, sigma 5), FP32 storage, plain V-cycles"),
+    "stack1k-streamed": ("streamed:stack1k", "f32", 0, "1024x1024x128 stack, anisotropic-diffusion V-cycles (FP32) "
+                         "with the finest level's x and b in pinned host memory, streamed through HBM in halo-padded "
+                         "z-slabs (Sec. 4.1), coarse levels resident; the in-core V-cycles of the same system beside it"),
+    "stack4k-streamed": ("streamed:stack4k", "f32", 0, "4096x4096x256 stack, as stack1k-streamed"),
     "slices2048": ("slices", "f32", 0, "2048 independent slices, sides log-uniform in [256, 2048], alpha U(0.001, 0.1), "
                    "per-slice screened Poisson, FP32, plain V-cycles, one batched launch per level step"),
 }
@@ -57,6 +61,7 @@ def parse():
                    help="up-sampling of the Constant scheme: cell-centred trilinear or replication")
     p.add_argument("--inner-cycles", type=int, default=None,
                    help="V-cycles per FP64 refinement step (mixed storage; library default if omitted)")
+    p.add_argument("--slab", type=int, default=32, help="z-planes per slab of the streamed workload")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only copy a 1 GiB buffer 3 times (reference for HBM byte counters)")
     p.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -296,6 +301,96 @@ def bench_dct(a, gd, synth, torch, desc):
     print(json.dumps(line), flush=True)
 
 
+def bench_streamed(a, gd, synth, torch, desc):
+    """V-cycles of the AD system of the stack1k input with the finest level
+    in pinned host memory (gd_vcycle_streamed), as many as the in-core
+    cycles need to reach 1e-6 from zero; the in-core cycles are timed beside
+    them and must give the same iterate."""
+    spec = synth.CONFIGS[a.workload.split("-")[0]]
+    I0 = synth.make_stack(spec, device=torch.device("cuda:0"), dtype=torch.float32)
+    shape = tuple(I0.shape)
+    nvox = I0.numel()
+    pre, post = (int(v) for v in a.smooth.split(","))
+    kw = dict(pre_smooth=pre, post_smooth=post)
+    # right-hand side of Eq. (1): G = (d I0 / dx, d I0 / dy, 0) on the faces
+    gx = torch.zeros_like(I0)
+    gx[:, :, :-1] = I0[:, :, 1:] - I0[:, :, :-1]
+    gy = torch.zeros_like(I0)
+    gy[:, :-1, :] = I0[:, 1:, :] - I0[:, :-1, :]
+    hc = gd.Hierarchy(shape, 0.0, BETA, torch.float32, **kw)
+    b = hc.rhs(None, gx, gy, None)
+    del gx, gy, I0
+    xd = torch.zeros_like(b)
+    cycles, rr = 0, 1.0
+    while rr > TOL and cycles < 30:
+        rr = hc.vcycle(xd, b, 1)
+        cycles += 1
+    bh = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+    bh.copy_(b)
+    xh = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+    hs = gd.StreamedHierarchy(shape, 0.0, BETA, torch.float32, a.slab, **kw)
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / a.steps
+
+    def streamed():
+        xh.zero_()
+        hs.vcycle(xh, bh, cycles, relres=False)
+
+    def in_core():
+        xd.zero_()
+        hc.vcycle(xd, b, cycles)
+
+    dt = timed(streamed)
+    dt_c = timed(in_core)
+    same = bool(torch.equal(xh, xd.cpu()))
+    rr_s = hs.vcycle(xh, bh, 0)
+    dev_s, planes = hs.device_bytes()
+    dev_c, _ = hc.device_bytes()
+    # host-link bytes of one cycle: each pass uploads every window's x and b
+    # and writes back every slab's x
+    halo = 2 * max(pre, post) + 2
+    slab = min(spec.nz, max(a.slab + a.slab % 2, halo))
+    up_planes = 0
+    for z0 in range(0, spec.nz, slab):
+        z1 = min(spec.nz, z0 + slab)
+        up_planes += min(spec.nz, z1 + halo) - max(0, z0 - halo)
+    plane = spec.nx * spec.ny * 4
+    link = cycles * 2 * (2 * up_planes + spec.nz) * plane
+    # a plain pinned upload of 1 GiB, the link's practical rate
+    src = torch.empty(1 << 28, dtype=torch.float32, pin_memory=True)
+    dst = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    copy_gbs = 3 * src.numel() * 4 / (time.perf_counter() - t0) / 1e9
+    line = {
+        "metric": "voxels/s (anisotropic-diffusion V-cycles, finest level streamed from host memory)",
+        "value": nvox / dt, "unit": "voxels/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {desc}", "nx": spec.nx, "ny": spec.ny, "nz": spec.nz,
+                   "voxels": nvox, "cycles": cycles, "slab": slab, "halo": halo, "window_planes": planes},
+        "link": {"bytes_per_step": link, "achieved_gbs": link / dt / 1e9, "pinned_upload_gbs": copy_gbs,
+                 "note": "host<->device bytes of the streamed passes (uploads and write-backs, halos included)"},
+        "device_bytes": {"streamed": dev_s, "in_core": dev_c},
+        "in_core": {"ms": dt_c * 1e3, "voxels_per_s": nvox / dt_c, "same_iterate": same,
+                    "rel_residual": rr},
+        "rel_residual": rr_s,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_npr(a, gd, synth, torch, desc):
     """Gradient-modulation filter (Sec. 6) of a synthetic 1920x1080x742 video
     volume: one step = the modulated right-hand side, V-cycles to 1e-6 and
@@ -390,6 +485,8 @@ def main():
         return bench_npr(a, gd, synth, torch, desc)
     if spec_key == "dct":
         return bench_dct(a, gd, synth, torch, desc)
+    if spec_key.startswith("streamed"):
+        return bench_streamed(a, gd, synth, torch, desc)
     t0 = time.perf_counter()
     I0 = synth.make_stack(spec, device=dev, dtype=tdt)
     torch.cuda.synchronize()

@@ -224,7 +224,8 @@ gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles,
  * same values as gd_vcycle on the whole grid (halo planes are recomputed and
  * dropped).  Down pass: pre-smoothing and the restricted residual; up pass:
  * the interpolated coarse correction and post-smoothing.  Uploads, kernels
- * and write-backs of consecutive windows overlap on three streams.
+ * and write-backs of consecutive windows overlap on three streams (three
+ * window buffer sets rotate).
  *
  * gd_hierarchy_create_streamed: arguments as gd_hierarchy_create plus `slab`
  * (> 0).  Only the Constant discretisation (opts->discretization == 0),

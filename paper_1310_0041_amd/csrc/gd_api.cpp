@@ -244,10 +244,10 @@ static int64_t sweep_target(bool row = false) {
   return row ? vr : v3;
 }
 
-// finest_arrays false: level 0 gets launch tables but no x / xt / b (its
+// Levels below first_arrays get launch tables but no x / xt / b (their
 // data lives elsewhere); max_levels > 0 stops the hierarchy after that many.
 static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
-                                        hipStream_t st, int tile_force = -1, bool finest_arrays = true,
+                                        hipStream_t st, int tile_force = -1, int first_arrays = 0,
                                         int max_levels = 0) {
   auto H = std::make_unique<Hier>();
   HIP_TRY(hipGetDevice(&H->device));
@@ -361,7 +361,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     for (int k = 0; k < 5; ++k)
       std::memcpy(stage.data() + gbytes + k * nb * sizeof(int64_t), tabs[k]->h_b0.data(), nb * sizeof(int64_t));
     HIP_TRY(hipMemcpy(dev, stage.data(), bytes, hipMemcpyHostToDevice));
-    if (li > 0 || finest_arrays) {
+    if ((int)li >= first_arrays) {
       L.x = H->alloc(L.total * es);
       L.xt = H->alloc(L.total * es);
       L.b = H->alloc(L.total * es);
@@ -1469,28 +1469,37 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
 // pairwise restriction stays within an even-aligned pair, so the planes
 // [z0, z1) come out as in a sweep of the whole grid.  Windows start on even
 // planes (slab and halo are even), which keeps the red-black colouring and
-// the pairing of planes by the restriction.  Two window buffer sets
-// alternate: the next window is uploaded and the previous one written back
-// on streams of their own while the current one is relaxed.
+// the pairing of planes by the restriction.  Three window buffer sets
+// rotate: while one window is relaxed the next two are uploaded and the
+// previous one written back, on streams of their own (with two sets an
+// upload would wait for the write-back of the set it reuses, and the two
+// directions of the host link would take turns instead of overlapping).
 struct Streamer {
+  static constexpr int NS = 3;  // window buffer sets
   struct Win {
     int64_t a, e, z0, z1;
   };
   int64_t slab = 0, halo = 0;
   std::vector<Win> wins;
-  std::map<int64_t, std::unique_ptr<Hier>> sets[2];  // window planes -> window hierarchy (levels 0 and 1)
+  // window planes -> window hierarchy (levels 0 and 1, launch tables only);
+  // the windows of one set share that set's buffers, sized for the largest
+  std::map<int64_t, std::unique_ptr<Hier>> sets[NS];
+  void* pool[NS] = {};
+  size_t pool_bytes = 0;
   hipStream_t up = nullptr, down = nullptr;
-  hipEvent_t loaded[2] = {}, computed[2] = {}, unloaded[2] = {}, start = nullptr, done_up = nullptr,
+  hipEvent_t loaded[NS] = {}, computed[NS] = {}, unloaded[NS] = {}, start = nullptr, done_up = nullptr,
              done_down = nullptr;
   Hier& win(int k, int64_t planes) { return *sets[k].at(planes); }
   size_t bytes() const {
-    size_t b = 0;
+    size_t b = NS * pool_bytes;
     for (const auto& m : sets)
       for (const auto& kv : m) b += kv.second->bytes;
     return b;
   }
   ~Streamer() {
-    for (int k = 0; k < 2; ++k) {
+    for (void* p : pool)
+      if (p) (void)hipFree(p);
+    for (int k = 0; k < NS; ++k) {
       if (loaded[k]) (void)hipEventDestroy(loaded[k]);
       if (computed[k]) (void)hipEventDestroy(computed[k]);
       if (unloaded[k]) (void)hipEventDestroy(unloaded[k]);
@@ -1672,7 +1681,7 @@ gd_status gd_hierarchy_create_streamed(gd_hierarchy** h, int64_t nx, int64_t ny,
     auto hh = std::make_unique<gd_hierarchy>();
     hh->o = o;
     hh->o.timing = 0;
-    hh->H = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, o.sweep_tile, false);
+    hh->H = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, o.sweep_tile, 1);
     Hier& H = *hh->H;
     if (H.lv.size() < 2) throw Unsupported("the grid has no coarser level to stream against");
     auto sm = std::make_unique<Streamer>();
@@ -1685,14 +1694,38 @@ gd_status gd_hierarchy_create_streamed(gd_hierarchy** h, int64_t nx, int64_t ny,
       sm->wins.push_back({std::max<int64_t>(0, z0 - sm->halo), std::min(nz, z1 + sm->halo), z0, z1});
     }
     const int tile = H.lv[0].sw.tile;
-    for (const auto& w : sm->wins)
-      for (int k = 0; k < 2; ++k)
+    int64_t wmax = 0;
+    for (const auto& w : sm->wins) {
+      wmax = std::max(wmax, w.e - w.a);
+      for (int k = 0; k < Streamer::NS; ++k)
         if (!sm->sets[k].count(w.e - w.a))
           sm->sets[k][w.e - w.a] =
-              build_hier({{nx, ny, w.e - w.a, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, tile, true, 2);
+              build_hier({{nx, ny, w.e - w.a, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, tile, 2, 2);
+    }
+    // per set: level 0 x, x', b of wmax planes; level 1 b and x (the
+    // restriction's output; level 1 is not relaxed in a window)
+    const GridDesc& g0 = H.lv[0].h[0];
+    const size_t es = dsize(s);
+    const size_t fine = (size_t)g0.px * g0.ny * wmax * es;
+    const size_t coarse = (size_t)g0.cpx * g0.cny * ((wmax + g0.fz - 1) / g0.fz) * es;
+    const size_t f256 = (fine + 255) & ~(size_t)255, c256 = (coarse + 255) & ~(size_t)255;
+    sm->pool_bytes = 3 * f256 + 2 * c256;
+    for (int k = 0; k < Streamer::NS; ++k) {
+      HIP_TRY(hipMalloc(&sm->pool[k], sm->pool_bytes));
+      char* p = (char*)sm->pool[k];
+      for (auto& kv : sm->sets[k]) {
+        Hier& W = *kv.second;
+        W.lv[0].x = p;
+        W.lv[0].xt = p + f256;
+        W.lv[0].b = p + 2 * f256;
+        W.lv[1].b = p + 3 * f256;
+        W.lv[1].x = p + 3 * f256 + c256;
+        W.lv[1].xt = nullptr;
+      }
+    }
     HIP_TRY(hipStreamCreateWithFlags(&sm->up, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&sm->down, hipStreamNonBlocking));
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < Streamer::NS; ++k) {
       HIP_TRY(hipEventCreateWithFlags(&sm->loaded[k], hipEventDisableTiming));
       HIP_TRY(hipEventCreateWithFlags(&sm->computed[k], hipEventDisableTiming));
       HIP_TRY(hipEventCreateWithFlags(&sm->unloaded[k], hipEventDisableTiming));
@@ -1725,21 +1758,22 @@ static void stream_pass(gd_hierarchy& h, bool down, void* xh, const void* bh, hi
   HIP_TRY(hipStreamWaitEvent(S.down, S.start, 0));
   if (down) HIP_TRY(hipMemsetAsync(C.x, 0, (size_t)C.total * es, st));
   const size_t n = S.wins.size();
-  auto load = [&](size_t w) {
+  constexpr int NS = Streamer::NS;
+  auto load = [&](size_t w) {  // set w mod NS, last written back for window w - NS
     const Streamer::Win& W = S.wins[w];
-    const int k = (int)(w & 1);
+    const int k = (int)(w % NS);
     Level& L = S.win(k, W.e - W.a).lv[0];
-    if (w >= 2) HIP_TRY(hipStreamWaitEvent(S.up, S.unloaded[k], 0));
+    if (w >= (size_t)NS) HIP_TRY(hipStreamWaitEvent(S.up, S.unloaded[k], 0));
     const size_t rows = (size_t)g0.ny * (W.e - W.a);
     HIP_TRY(hipMemcpy2DAsync(L.x, pb, (const char*)xh + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, S.up));
     HIP_TRY(hipMemcpy2DAsync(L.b, pb, (const char*)bh + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, S.up));
     HIP_TRY(hipEventRecord(S.loaded[k], S.up));
   };
-  load(0);
+  for (size_t w = 0; w < std::min<size_t>(n, NS - 1); ++w) load(w);
   for (size_t w = 0; w < n; ++w) {
-    if (w + 1 < n) load(w + 1);
+    if (w + NS - 1 < n) load(w + NS - 1);
     const Streamer::Win& W = S.wins[w];
-    const int k = (int)(w & 1);
+    const int k = (int)(w % NS);
     Hier& WH = S.win(k, W.e - W.a);
     HIP_TRY(hipStreamWaitEvent(st, S.loaded[k], 0));
     Cycler cy(WH, st, h.o);
@@ -1762,7 +1796,7 @@ static void stream_pass(gd_hierarchy& h, bool down, void* xh, const void* bh, hi
     HIP_TRY(hipStreamWaitEvent(S.down, S.computed[k], 0));
     // the next window's halo holds this slab's last planes as they were
     // before this pass: write back only after it has been read
-    if (w + 1 < n) HIP_TRY(hipStreamWaitEvent(S.down, S.loaded[(w + 1) & 1], 0));
+    if (w + 1 < n) HIP_TRY(hipStreamWaitEvent(S.down, S.loaded[(w + 1) % NS], 0));
     HIP_TRY(hipMemcpy2DAsync((char*)xh + W.z0 * hplane, wb, (const char*)WH.lv[0].x + (W.z0 - W.a) * dplane, pb, wb,
                              (size_t)g0.ny * (W.z1 - W.z0), hipMemcpyDeviceToHost, S.down));
     HIP_TRY(hipEventRecord(S.unloaded[k], S.down));

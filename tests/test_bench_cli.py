@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused():
 def test_workloads_listed():
     r = run("--help")
     assert r.returncode == 0
-    for w in ("stack1k", "slices2048", "stack4k-f16", "learned2k", "npr-video", "ad1k-dct"):
+    for w in ("stack1k", "slices2048", "stack4k-f16", "learned2k", "npr-video", "ad1k-dct", "stack1k-streamed"):
         assert w in r.stdout
     for opt in ("--steps", "--warmup", "--discretization", "--prolong"):
         assert opt in r.stdout

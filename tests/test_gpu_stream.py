@@ -119,7 +119,7 @@ def test_streamed_holds_less_device_memory(gd):
     bs, planes = hs.device_bytes()
     assert planes == 16 + 2 * 6
     # in core: x, x', b of every level (about 3 x 1.57 finest arrays); streamed:
-    # the coarse levels (about 3 x 0.57) and two windows
+    # the coarse levels (about 3 x 0.57) and three windows
     assert bs < 0.6 * bc
 
 
