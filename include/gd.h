@@ -214,30 +214,37 @@ gd_status gd_rhs_general(gd_hierarchy* h, const void* V, const void* Gx, const v
 gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles,
                     double* rel_residual_out, void* stream);
 
-/* ---- finest level streamed from host memory (Sec. 4.1) -----------------------
+/* ---- levels streamed from host memory (Sec. 4.1) -----------------------------
  * The paper runs every V-cycle as two streaming passes through the data
  * with a window over the slices.  Here the finest level's x and b stay in
- * host memory and only a window of z-planes is in HBM; the coarser levels
- * are resident.  A pass cuts z into slabs of `slab` planes (raised to an even
- * count of at least the halo, 2 max(pre_smooth, post_smooth) + 2 planes) and
- * relaxes each slab with that halo on both sides, so every cycle gives the
- * same values as gd_vcycle on the whole grid (halo planes are recomputed and
- * dropped).  Down pass: pre-smoothing and the restricted residual; up pass:
- * the interpolated coarse correction and post-smoothing.  Uploads, kernels
- * and write-backs of consecutive windows overlap on three streams (three
- * window buffer sets rotate).
+ * host memory, and so may the next levels with more than an eighth of the
+ * finest level's cells (with z-first semi-coarsening the first coarse level
+ * has half; the library holds them in pinned host memory); only windows of
+ * z-planes of them are in HBM, the other levels are resident.  stream_levels
+ * = 0 streams such a coarser level only when its window buffers take less
+ * HBM than the level itself (long stacks); stream_levels = k > 0 streams at
+ * most k levels, the finest included (one level always stays resident).
+ * A pass over a streamed level cuts z into slabs of `slab` planes (raised to
+ * an even count of at least the halo, 2 max(pre_smooth, post_smooth) + 2
+ * planes) and relaxes each slab with that halo on both sides, so every cycle
+ * gives the same values as gd_vcycle on the whole grid (halo planes are
+ * recomputed and dropped).  Down pass: pre-smoothing and the restricted
+ * residual; up pass: the interpolated coarse correction and post-smoothing.
+ * Uploads, kernels and write-backs of consecutive windows overlap on three
+ * streams (three window buffer sets rotate per level).
  *
  * gd_hierarchy_create_streamed: arguments as gd_hierarchy_create plus `slab`
- * (> 0).  Only the Constant discretisation (opts->discretization == 0),
+ * (> 0) and `stream_levels` (>= 0).  Only the Constant discretisation (opts->discretization == 0),
  * ny >= 2 and grids with a coarser level; GD_ERR_UNSUPPORTED otherwise.  The
  * handle accepts gd_vcycle_streamed, gd_hierarchy_info,
- * gd_hierarchy_device_bytes and gd_hierarchy_destroy; the in-core calls
+ * gd_hierarchy_device_bytes, gd_hierarchy_streamed_levels and
+ * gd_hierarchy_destroy; the in-core calls
  * (gd_vcycle, gd_rhs_general, gd_mg_error_pairs, gd_fcg_solve) return
  * GD_ERR_INVALID. */
 gd_status gd_hierarchy_create_streamed(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t nz,
                                        double alpha, double beta_x, double beta_y, double beta_z,
                                        gd_dtype storage, const gd_solve_opts* opts, int64_t slab,
-                                       void* stream);
+                                       int stream_levels, void* stream);
 /* ncycles V-cycles on A x = b with x (in/out) and b (in) in HOST memory, dense
  * [nz][ny][nx] arrays of the storage dtype, owned by the caller.  Memory
  * from hipHostMalloc lets copies overlap the kernels; pageable memory works
@@ -249,6 +256,8 @@ gd_status gd_vcycle_streamed(gd_hierarchy* h, void* x, const void* b, int ncycle
 /* Device memory the hierarchy holds (levels, windows, launch tables) and,
  * for a streamed one, the planes of its largest window (0 otherwise). */
 gd_status gd_hierarchy_device_bytes(const gd_hierarchy* h, int64_t* bytes, int64_t* window_planes);
+/* Number of levels held in host memory (0 for an in-core hierarchy). */
+gd_status gd_hierarchy_streamed_levels(const gd_hierarchy* h, int* levels);
 
 /* Residual-to-error pairs from multigrid itself, for training a learned
  * preconditioner: x_k = `cycles` V-cycles from zero on A x = b; r_out = b - A x_k,

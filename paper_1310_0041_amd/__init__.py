@@ -99,9 +99,10 @@ _SIGS = {
     "gd_rhs_general": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gd_vcycle": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
     "gd_hierarchy_create_streamed": (_i, [ctypes.POINTER(_vp), _i64, _i64, _i64, _d, _d, _d, _d, _i,
-                                          ctypes.POINTER(SolveOpts), _i64, _vp]),
+                                          ctypes.POINTER(SolveOpts), _i64, _i, _vp]),
     "gd_vcycle_streamed": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
     "gd_hierarchy_device_bytes": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "gd_hierarchy_streamed_levels": (_i, [_vp, ctypes.POINTER(_i)]),
     "gd_rb_sweep": (_i, [_vp, _vp, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _d, _vp]),
     "gd_residual_restrict": (_i, [_vp, _vp, _vp, _i, _i64, _i64, _i64, _i, _i, _i, _d, _d, _d, _d,
                                   ctypes.POINTER(_d), _vp]),
@@ -355,6 +356,11 @@ class Hierarchy:
         _check(_lib.gd_hierarchy_device_bytes(self._h, ctypes.byref(b), ctypes.byref(w)))
         return b.value, w.value
 
+    def streamed_levels(self):
+        n = ctypes.c_int()
+        _check(_lib.gd_hierarchy_streamed_levels(self._h, ctypes.byref(n)))
+        return n.value
+
     def close(self):
         if self._h:
             _lib.gd_hierarchy_destroy(self._h)
@@ -376,12 +382,13 @@ def _host_ptr(t):
 
 
 class StreamedHierarchy(Hierarchy):
-    """A hierarchy whose finest level stays in host memory and is streamed
-    through HBM in z-slabs of `slab` planes (Sec. 4.1); the coarser levels
-    are resident.  vcycle takes CPU tensors (pinned ones let the copies
-    overlap the kernels)."""
+    """A hierarchy whose finest level (and possibly the next large ones, see
+    `levels`: 0 automatic, k > 0 at most k streamed levels) stays in host
+    memory and is streamed through HBM in z-slabs of `slab` planes
+    (Sec. 4.1); the other levels are resident.  vcycle takes CPU tensors
+    (pinned ones let the copies overlap the kernels)."""
 
-    def __init__(self, shape, alpha, beta, dtype, slab, opts=None, **kw):
+    def __init__(self, shape, alpha, beta, dtype, slab, levels=0, opts=None, **kw):
         lib = load()
         nz, ny, nx = shape
         self.shape = tuple(shape)
@@ -390,7 +397,7 @@ class StreamedHierarchy(Hierarchy):
         o = opts or default_opts(**kw)
         _check(lib.gd_hierarchy_create_streamed(ctypes.byref(self._h), nx, ny, nz, float(alpha), float(beta[0]),
                                                 float(beta[1]), float(beta[2]), gd_dtype(dtype), ctypes.byref(o),
-                                                int(slab), _stream()))
+                                                int(slab), int(levels), _stream()))
 
     def vcycle(self, x, b, ncycles=1, relres=True):
         for t in (x, b):

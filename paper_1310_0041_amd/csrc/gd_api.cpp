@@ -1460,47 +1460,66 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
 
 // ------------------------------------------------------------ hierarchy API
 
-// Finest level held in host memory (Sec. 4.1: every V-cycle is two
-// streaming passes through the data with a window over the slices).  The
-// z-axis is cut into slabs of `slab` planes; slab [z0, z1) is processed in a
-// window [a, e) = [z0 - halo, z1 + halo) clipped to the grid, with halo =
-// 2 max(pre, post) + 2 planes: a red-black sweep moves an error of the
-// window's cut faces two planes inwards, the residual one more and the
-// pairwise restriction stays within an even-aligned pair, so the planes
-// [z0, z1) come out as in a sweep of the whole grid.  Windows start on even
+// Levels held in host memory (Sec. 4.1: every V-cycle is two streaming
+// passes through the data with a window over the slices).  A streamed
+// level's z-axis is cut into slabs of `slab` planes; slab [z0, z1) is
+// processed in a window [a, e) = [z0 - halo, z1 + halo) clipped to the grid,
+// with halo = 2 max(pre, post) + 2 planes: a red-black sweep moves an error
+// of the window's cut faces two planes inwards, the residual one more and
+// the pairwise restriction stays within an even-aligned pair, so the planes
+// [z0, z1) come out as in a sweep of the whole level.  Windows start on even
 // planes (slab and halo are even), which keeps the red-black colouring and
 // the pairing of planes by the restriction.  Three window buffer sets
 // rotate: while one window is relaxed the next two are uploaded and the
 // previous one written back, on streams of their own (with two sets an
 // upload would wait for the write-back of the set it reuses, and the two
 // directions of the host link would take turns instead of overlapping).
+// A level is streamed when it has more than an eighth of the finest level's
+// cells (with z-first semi-coarsening the first coarse level has half); the
+// finest level's x and b are the caller's, a coarser streamed level's are
+// pinned host arrays of the library.  Smaller levels stay in HBM.
 struct Streamer {
-  static constexpr int NS = 3;  // window buffer sets
+  static constexpr int NS = 3;  // window buffer sets per level
   struct Win {
     int64_t a, e, z0, z1;
   };
-  int64_t slab = 0, halo = 0;
-  std::vector<Win> wins;
-  // window planes -> window hierarchy (levels 0 and 1, launch tables only);
-  // the windows of one set share that set's buffers, sized for the largest
-  std::map<int64_t, std::unique_ptr<Hier>> sets[NS];
-  void* pool[NS] = {};
-  size_t pool_bytes = 0;
+  struct Lvl {
+    int64_t slab = 0;
+    std::vector<Win> wins;
+    // window planes -> window hierarchy (levels 0 and 1, launch tables only);
+    // the windows of one set share that set's buffers, sized for the largest
+    std::map<int64_t, std::unique_ptr<Hier>> sets[NS];
+    void* pool[NS] = {};
+    size_t pool_bytes = 0;
+    void* hx = nullptr;  // pinned host x and b (levels > 0), dense [nz][ny][nx]
+    void* hb = nullptr;
+    Hier& win(int k, int64_t planes) { return *sets[k].at(planes); }
+  };
+  int64_t halo = 0;
+  std::vector<Lvl> lv;  // streamed levels 0 .. lv.size() - 1
   hipStream_t up = nullptr, down = nullptr;
-  hipEvent_t loaded[NS] = {}, computed[NS] = {}, unloaded[NS] = {}, start = nullptr, done_up = nullptr,
+  hipEvent_t loaded[NS] = {}, copied[NS] = {}, computed[NS] = {}, unloaded[NS] = {}, start = nullptr,
+             done_up = nullptr,
              done_down = nullptr;
-  Hier& win(int k, int64_t planes) { return *sets[k].at(planes); }
   size_t bytes() const {
-    size_t b = NS * pool_bytes;
-    for (const auto& m : sets)
-      for (const auto& kv : m) b += kv.second->bytes;
+    size_t b = 0;
+    for (const auto& L : lv) {
+      b += NS * L.pool_bytes;
+      for (const auto& m : L.sets)
+        for (const auto& kv : m) b += kv.second->bytes;
+    }
     return b;
   }
   ~Streamer() {
-    for (void* p : pool)
-      if (p) (void)hipFree(p);
+    for (auto& L : lv) {
+      for (void* p : L.pool)
+        if (p) (void)hipFree(p);
+      if (L.hx) (void)hipHostFree(L.hx);
+      if (L.hb) (void)hipHostFree(L.hb);
+    }
     for (int k = 0; k < NS; ++k) {
       if (loaded[k]) (void)hipEventDestroy(loaded[k]);
+      if (copied[k]) (void)hipEventDestroy(copied[k]);
       if (computed[k]) (void)hipEventDestroy(computed[k]);
       if (unloaded[k]) (void)hipEventDestroy(unloaded[k]);
     }
@@ -1661,11 +1680,11 @@ gd_status gd_vcycle(gd_hierarchy* h, void* x, const void* b, int ncycles, double
   });
 }
 
-// ------------------------------------------------ streamed finest level
+// ------------------------------------------------------- streamed levels
 
 gd_status gd_hierarchy_create_streamed(gd_hierarchy** h, int64_t nx, int64_t ny, int64_t nz, double alpha,
                                        double bx, double by, double bz, gd_dtype s, const gd_solve_opts* opts,
-                                       int64_t slab, void* stream) {
+                                       int64_t slab, int stream_levels, void* stream) {
   const char* who = "gd_hierarchy_create_streamed";
   if (!h) return fail(GD_ERR_INVALID, std::string(who) + ": null handle pointer");
   *h = nullptr;
@@ -1673,60 +1692,96 @@ gd_status gd_hierarchy_create_streamed(gd_hierarchy** h, int64_t nx, int64_t ny,
   const gd_status a = hier_args(who, nx, ny, nz, alpha, bx, by, bz, s, opts, o);
   if (a != GD_OK) return a;
   if (slab <= 0) return fail(GD_ERR_INVALID, std::string(who) + ": slab must be > 0");
+  if (stream_levels < 0) return fail(GD_ERR_INVALID, std::string(who) + ": stream_levels must be >= 0");
   if (o.discretization != 0)
     return fail(GD_ERR_UNSUPPORTED, std::string(who) + ": only the Constant discretisation is streamed");
   if (ny < 2) return fail(GD_ERR_UNSUPPORTED, std::string(who) + ": ny must be >= 2");
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
+    // levels to stream: the finest, then each next one with more than an
+    // eighth of its cells and ny >= 2, always leaving one level resident;
+    // stream_levels > 0 caps the count, 0 streams a coarser level only when
+    // its window buffers take less HBM than the level itself
+    const int64_t halo = 2 * std::max(o.pre_smooth, o.post_smooth) + 2;
+    const size_t es = dsize(s);
+    int ns = 1;
+    {
+      auto probe = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, o.sweep_tile, 99);
+      if (probe->lv.size() < 2) throw Unsupported("the grid has no coarser level to stream against");
+      const GridDesc& f = probe->lv[0].h[0];
+      const double cells0 = (double)f.nx * f.ny * f.nz;
+      while (ns + 1 < (int)probe->lv.size() && (stream_levels == 0 || ns < stream_levels)) {
+        const GridDesc& g = probe->lv[ns].h[0];
+        if (g.ny < 2 || 8.0 * g.nx * g.ny * g.nz <= cells0) break;
+        if (stream_levels == 0) {
+          const int64_t sl = std::min<int64_t>(g.nz, std::max<int64_t>(slab + (slab & 1), halo));
+          const int64_t w = std::min<int64_t>(g.nz, sl + 2 * halo);
+          const double fine = (double)g.px * g.ny * w * es;
+          const double coarse = (double)g.cpx * g.cny * ((w + g.fz - 1) / g.fz) * es;
+          const double resident = 3.0 * g.px * g.ny * g.nz * es;
+          if (Streamer::NS * (3.0 * fine + 2.0 * coarse) >= resident) break;
+        }
+        ++ns;
+      }
+    }
     auto hh = std::make_unique<gd_hierarchy>();
     hh->o = o;
     hh->o.timing = 0;
-    hh->H = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, o.sweep_tile, 1);
+    hh->H = build_hier({{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, o.sweep_tile, ns);
     Hier& H = *hh->H;
-    if (H.lv.size() < 2) throw Unsupported("the grid has no coarser level to stream against");
     auto sm = std::make_unique<Streamer>();
     // slab even and at least the halo, so that only the next window reads
     // planes of a slab (its halo) before they are written back
-    sm->halo = 2 * std::max(o.pre_smooth, o.post_smooth) + 2;
-    sm->slab = std::min<int64_t>(nz, std::max<int64_t>(slab + (slab & 1), sm->halo));
-    for (int64_t z0 = 0; z0 < nz; z0 += sm->slab) {
-      const int64_t z1 = std::min(nz, z0 + sm->slab);
-      sm->wins.push_back({std::max<int64_t>(0, z0 - sm->halo), std::min(nz, z1 + sm->halo), z0, z1});
-    }
-    const int tile = H.lv[0].sw.tile;
-    int64_t wmax = 0;
-    for (const auto& w : sm->wins) {
-      wmax = std::max(wmax, w.e - w.a);
-      for (int k = 0; k < Streamer::NS; ++k)
-        if (!sm->sets[k].count(w.e - w.a))
-          sm->sets[k][w.e - w.a] =
-              build_hier({{nx, ny, w.e - w.a, alpha, bx, by, bz, 0, nx, nx * ny}}, s, false, st, tile, 2, 2);
-    }
-    // per set: level 0 x, x', b of wmax planes; level 1 b and x (the
-    // restriction's output; level 1 is not relaxed in a window)
-    const GridDesc& g0 = H.lv[0].h[0];
-    const size_t es = dsize(s);
-    const size_t fine = (size_t)g0.px * g0.ny * wmax * es;
-    const size_t coarse = (size_t)g0.cpx * g0.cny * ((wmax + g0.fz - 1) / g0.fz) * es;
-    const size_t f256 = (fine + 255) & ~(size_t)255, c256 = (coarse + 255) & ~(size_t)255;
-    sm->pool_bytes = 3 * f256 + 2 * c256;
-    for (int k = 0; k < Streamer::NS; ++k) {
-      HIP_TRY(hipMalloc(&sm->pool[k], sm->pool_bytes));
-      char* p = (char*)sm->pool[k];
-      for (auto& kv : sm->sets[k]) {
-        Hier& W = *kv.second;
-        W.lv[0].x = p;
-        W.lv[0].xt = p + f256;
-        W.lv[0].b = p + 2 * f256;
-        W.lv[1].b = p + 3 * f256;
-        W.lv[1].x = p + 3 * f256 + c256;
-        W.lv[1].xt = nullptr;
+    sm->halo = halo;
+    sm->lv.resize(ns);
+    for (int l = 0; l < ns; ++l) {
+      Streamer::Lvl& SL = sm->lv[l];
+      const GridDesc& g = H.lv[l].h[0];
+      SL.slab = std::min<int64_t>(g.nz, std::max<int64_t>(slab + (slab & 1), sm->halo));
+      for (int64_t z0 = 0; z0 < g.nz; z0 += SL.slab) {
+        const int64_t z1 = std::min<int64_t>(g.nz, z0 + SL.slab);
+        SL.wins.push_back({std::max<int64_t>(0, z0 - sm->halo), std::min<int64_t>(g.nz, z1 + sm->halo), z0, z1});
+      }
+      const int tile = H.lv[l].sw.tile;
+      int64_t wmax = 0;
+      for (const auto& w : SL.wins) {
+        wmax = std::max(wmax, w.e - w.a);
+        for (int k = 0; k < Streamer::NS; ++k)
+          if (!SL.sets[k].count(w.e - w.a))
+            SL.sets[k][w.e - w.a] = build_hier({{g.nx, g.ny, w.e - w.a, g.alpha, g.wx, g.wy, g.wz, 0, g.nx,
+                                                 (int64_t)g.nx * g.ny}},
+                                               s, false, st, tile, 2, 2);
+      }
+      // per set: the window's x, x', b (wmax planes) and its coarse b and x
+      // (the restriction's output; in the up pass the coarse correction)
+      const size_t fine = (size_t)g.px * g.ny * wmax * es;
+      const size_t coarse = (size_t)g.cpx * g.cny * ((wmax + g.fz - 1) / g.fz) * es;
+      const size_t f256 = (fine + 255) & ~(size_t)255, c256 = (coarse + 255) & ~(size_t)255;
+      SL.pool_bytes = 3 * f256 + 2 * c256;
+      for (int k = 0; k < Streamer::NS; ++k) {
+        HIP_TRY(hipMalloc(&SL.pool[k], SL.pool_bytes));
+        char* p = (char*)SL.pool[k];
+        for (auto& kv : SL.sets[k]) {
+          Hier& W = *kv.second;
+          W.lv[0].x = p;
+          W.lv[0].xt = p + f256;
+          W.lv[0].b = p + 2 * f256;
+          W.lv[1].b = p + 3 * f256;
+          W.lv[1].x = p + 3 * f256 + c256;
+          W.lv[1].xt = nullptr;
+        }
+      }
+      if (l > 0) {
+        const size_t hbytes = (size_t)g.nx * g.ny * g.nz * es;
+        HIP_TRY(hipHostMalloc(&SL.hx, hbytes, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc(&SL.hb, hbytes, hipHostMallocDefault));
       }
     }
     HIP_TRY(hipStreamCreateWithFlags(&sm->up, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&sm->down, hipStreamNonBlocking));
     for (int k = 0; k < Streamer::NS; ++k) {
       HIP_TRY(hipEventCreateWithFlags(&sm->loaded[k], hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&sm->copied[k], hipEventDisableTiming));
       HIP_TRY(hipEventCreateWithFlags(&sm->computed[k], hipEventDisableTiming));
       HIP_TRY(hipEventCreateWithFlags(&sm->unloaded[k], hipEventDisableTiming));
     }
@@ -1739,52 +1794,91 @@ gd_status gd_hierarchy_create_streamed(gd_hierarchy** h, int64_t nx, int64_t ny,
   });
 }
 
-// One streaming pass over the finest level.  down: pre-smoothing, then the
-// residual restricted into level 1 (whose iterate is zeroed); up: the level-1
-// correction interpolated and added, then post-smoothing.  x is written back
-// to host memory slab by slab.
-static void stream_pass(gd_hierarchy& h, bool down, void* xh, const void* bh, hipStream_t st) {
+// One streaming pass over streamed level l (x and b in host memory).
+// down: pre-smoothing, then the residual restricted into level l + 1: into
+// HBM when that level is resident (its iterate zeroed), into its host b when
+// it is streamed too (its iterate then starts at zero in its own down pass,
+// so a coarser level's x is not uploaded there).  up: the correction of
+// level l + 1 interpolated and added (read in HBM, or uploaded plane range
+// by plane range with the window), then post-smoothing.  x is written back
+// slab by slab.
+static void stream_pass(gd_hierarchy& h, int l, bool down, void* xh, const void* bh, hipStream_t st) {
   Hier& H = *h.H;
   Streamer& S = *h.sm;
-  Level& C = H.lv[1];
-  const GridDesc& g0 = H.lv[0].h[0];
+  Streamer::Lvl& SL = S.lv[l];
+  const bool cs = l + 1 < (int)S.lv.size();  // level l + 1 is streamed too
+  Level& C = H.lv[l + 1];
+  const GridDesc& g = H.lv[l].h[0];
   const size_t es = dsize(H.s);
-  const size_t wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es;
-  const size_t hplane = (size_t)g0.nx * g0.ny * es, dplane = (size_t)g0.px * g0.ny * es;
-  const size_t cplane = (size_t)g0.cpx * g0.cny * es;
-  const int64_t fz = g0.fz;
+  const size_t wb = (size_t)g.nx * es, pb = (size_t)g.px * es;
+  const size_t hplane = (size_t)g.nx * g.ny * es, dplane = (size_t)g.px * g.ny * es;
+  const size_t cwb = (size_t)g.cnx * es, cpb = (size_t)g.cpx * es;
+  const size_t chplane = (size_t)g.cnx * g.cny * es, cplane = (size_t)g.cpx * g.cny * es;
+  const int64_t fz = g.fz;
+  const bool zero_x = down && l > 0;
   HIP_TRY(hipEventRecord(S.start, st));
   HIP_TRY(hipStreamWaitEvent(S.up, S.start, 0));
   HIP_TRY(hipStreamWaitEvent(S.down, S.start, 0));
-  if (down) HIP_TRY(hipMemsetAsync(C.x, 0, (size_t)C.total * es, st));
-  const size_t n = S.wins.size();
+  if (down && !cs) HIP_TRY(hipMemsetAsync(C.x, 0, (size_t)C.total * es, st));
+  const size_t n = SL.wins.size();
   constexpr int NS = Streamer::NS;
   auto load = [&](size_t w) {  // set w mod NS, last written back for window w - NS
-    const Streamer::Win& W = S.wins[w];
+    const Streamer::Win& W = SL.wins[w];
     const int k = (int)(w % NS);
-    Level& L = S.win(k, W.e - W.a).lv[0];
+    Hier& WH = SL.win(k, W.e - W.a);
+    Level& L = WH.lv[0];
     if (w >= (size_t)NS) HIP_TRY(hipStreamWaitEvent(S.up, S.unloaded[k], 0));
-    const size_t rows = (size_t)g0.ny * (W.e - W.a);
-    HIP_TRY(hipMemcpy2DAsync(L.x, pb, (const char*)xh + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, S.up));
-    HIP_TRY(hipMemcpy2DAsync(L.b, pb, (const char*)bh + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, S.up));
+    // planes [a, ov) are shared with the previous window, whose buffers still
+    // hold them as they were at the start of this pass (its kernels wait for
+    // this copy): copied on the device, so that every plane crosses the host
+    // link once per pass
+    int64_t ov = W.a;
+    if (w > 0) {
+      const Streamer::Win& P = SL.wins[w - 1];
+      Level& PL = SL.win((int)((w - 1) % NS), P.e - P.a).lv[0];
+      ov = std::max(W.a, std::min(P.e, W.e));
+      if (ov > W.a) {
+        const size_t bytes = (size_t)(ov - W.a) * dplane, off = (size_t)(W.a - P.a) * dplane;
+        if (!zero_x)
+          HIP_TRY(hipMemcpyAsync(L.x, (const char*)PL.x + off, bytes, hipMemcpyDeviceToDevice, S.up));
+        HIP_TRY(hipMemcpyAsync(L.b, (const char*)PL.b + off, bytes, hipMemcpyDeviceToDevice, S.up));
+      }
+      HIP_TRY(hipEventRecord(S.copied[(w - 1) % NS], S.up));
+    }
+    const size_t rows = (size_t)g.ny * (W.e - ov), dof = (size_t)(ov - W.a) * dplane;
+    if (zero_x) HIP_TRY(hipMemsetAsync(L.x, 0, dplane * (W.e - W.a), S.up));
+    else if (rows)
+      HIP_TRY(hipMemcpy2DAsync((char*)L.x + dof, pb, (const char*)xh + ov * hplane, wb, wb, rows,
+                               hipMemcpyHostToDevice, S.up));
+    if (rows)
+      HIP_TRY(hipMemcpy2DAsync((char*)L.b + dof, pb, (const char*)bh + ov * hplane, wb, wb, rows,
+                               hipMemcpyHostToDevice, S.up));
+    if (!down && cs) {  // the coarse correction under the window: planes [a / fz, a / fz + cnz)
+      const int64_t cn = WH.lv[0].h[0].cnz;
+      HIP_TRY(hipMemcpy2DAsync(WH.lv[1].x, cpb, (const char*)S.lv[l + 1].hx + (W.a / fz) * chplane, cwb, cwb,
+                               (size_t)g.cny * cn, hipMemcpyHostToDevice, S.up));
+    }
     HIP_TRY(hipEventRecord(S.loaded[k], S.up));
   };
   for (size_t w = 0; w < std::min<size_t>(n, NS - 1); ++w) load(w);
   for (size_t w = 0; w < n; ++w) {
     if (w + NS - 1 < n) load(w + NS - 1);
-    const Streamer::Win& W = S.wins[w];
+    const Streamer::Win& W = SL.wins[w];
     const int k = (int)(w % NS);
-    Hier& WH = S.win(k, W.e - W.a);
+    Hier& WH = SL.win(k, W.e - W.a);
     HIP_TRY(hipStreamWaitEvent(st, S.loaded[k], 0));
+    // the next window copies its shared planes out of this one first
+    if (w + 1 < n) HIP_TRY(hipStreamWaitEvent(st, S.copied[k], 0));
     Cycler cy(WH, st, h.o);
+    const int64_t c0 = W.z0 / fz, c1 = (W.z1 + fz - 1) / fz;  // coarse planes of [z0, z1)
     if (down) {
       cy.smooth(0, h.o.pre_smooth);
       HIP_TRY(launch_restrict_z(WH.s, WH.g_rz(0), WH.lv[0].x, WH.lv[0].b, WH.lv[1].b, WH.lv[1].x, nullptr, st));
-      const int64_t c0 = W.z0 / fz, c1 = (W.z1 + fz - 1) / fz;  // coarse planes of [z0, z1)
-      HIP_TRY(hipMemcpyAsync((char*)C.b + c0 * cplane, (const char*)WH.lv[1].b + (c0 - W.a / fz) * cplane,
-                             (size_t)(c1 - c0) * cplane, hipMemcpyDeviceToDevice, st));
+      if (!cs)
+        HIP_TRY(hipMemcpyAsync((char*)C.b + c0 * cplane, (const char*)WH.lv[1].b + (c0 - W.a / fz) * cplane,
+                               (size_t)(c1 - c0) * cplane, hipMemcpyDeviceToDevice, st));
     } else {
-      const void* ec = (const char*)C.x + (W.a / fz) * cplane;
+      const void* ec = cs ? WH.lv[1].x : (const void*)((const char*)C.x + (W.a / fz) * cplane);
       if (h.o.fuse_prolong != 0 && h.o.post_smooth > 0 && WH.lv[0].sw.tile == 0) {
         cy.smooth(0, h.o.post_smooth, ec);
       } else {
@@ -1798,7 +1892,11 @@ static void stream_pass(gd_hierarchy& h, bool down, void* xh, const void* bh, hi
     // before this pass: write back only after it has been read
     if (w + 1 < n) HIP_TRY(hipStreamWaitEvent(S.down, S.loaded[(w + 1) % NS], 0));
     HIP_TRY(hipMemcpy2DAsync((char*)xh + W.z0 * hplane, wb, (const char*)WH.lv[0].x + (W.z0 - W.a) * dplane, pb, wb,
-                             (size_t)g0.ny * (W.z1 - W.z0), hipMemcpyDeviceToHost, S.down));
+                             (size_t)g.ny * (W.z1 - W.z0), hipMemcpyDeviceToHost, S.down));
+    if (down && cs)
+      HIP_TRY(hipMemcpy2DAsync((char*)S.lv[l + 1].hb + c0 * chplane, cwb,
+                               (const char*)WH.lv[1].b + (c0 - W.a / fz) * cplane, cpb, cwb,
+                               (size_t)g.cny * (c1 - c0), hipMemcpyDeviceToHost, S.down));
     HIP_TRY(hipEventRecord(S.unloaded[k], S.down));
   }
   HIP_TRY(hipEventRecord(S.done_up, S.up));
@@ -1816,19 +1914,22 @@ gd_status gd_vcycle_streamed(gd_hierarchy* h, void* x, const void* b, int ncycle
   Streamer& S = *h->sm;
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
+    const int ns = (int)S.lv.size();
+    auto X = [&](int l) { return l == 0 ? x : S.lv[l].hx; };
+    auto B = [&](int l) { return l == 0 ? b : (const void*)S.lv[l].hb; };
     Cycler cy(H, st, h->o);
     for (int c = 0; c < ncycles; ++c) {
-      stream_pass(*h, true, x, b, st);
-      cy.below(1);
-      stream_pass(*h, false, x, b, st);
+      for (int l = 0; l < ns; ++l) stream_pass(*h, l, true, X(l), B(l), st);
+      cy.below(ns);
+      for (int l = ns - 1; l >= 0; --l) stream_pass(*h, l, false, X(l), B(l), st);
     }
     if (relres) {  // ||b - A x|| / ||b||, every window contributing its own slab's planes
       const GridDesc& g0 = H.lv[0].h[0];
       const size_t es = dsize(H.s), wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es;
       const size_t hplane = (size_t)g0.nx * g0.ny * es;
       double rr = 0.0, bb = 0.0;
-      for (const auto& W : S.wins) {
-        Hier& WH = S.win(0, W.e - W.a);
+      for (const auto& W : S.lv[0].wins) {
+        Hier& WH = S.lv[0].win(0, W.e - W.a);
         Level& L = WH.lv[0];
         const size_t rows = (size_t)g0.ny * (W.e - W.a);
         HIP_TRY(hipMemcpy2DAsync(L.x, pb, (const char*)x + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, st));
@@ -1856,10 +1957,16 @@ gd_status gd_hierarchy_device_bytes(const gd_hierarchy* h, int64_t* bytes, int64
   int64_t wp = 0;
   if (h->sm) {
     b += h->sm->bytes();
-    for (const auto& W : h->sm->wins) wp = std::max(wp, W.e - W.a);
+    for (const auto& W : h->sm->lv[0].wins) wp = std::max(wp, W.e - W.a);
   }
   *bytes = (int64_t)b;
   if (window_planes) *window_planes = wp;
+  return GD_OK;
+}
+
+gd_status gd_hierarchy_streamed_levels(const gd_hierarchy* h, int* levels) {
+  if (!h || !levels) return fail(GD_ERR_INVALID, "gd_hierarchy_streamed_levels: null pointer");
+  *levels = h->sm ? (int)h->sm->lv.size() : 0;
   return GD_OK;
 }
 

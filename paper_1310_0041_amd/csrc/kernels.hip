@@ -839,15 +839,18 @@ k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
       ld_raw(rb + o + i0, r.v[3]); ld_raw(rb + o + i1, r.v[4]); ld_raw(rb + o + i2, r.v[5]);
     }
   };
+  // explicit fused multiply-adds in one order: the window set-up and its
+  // advance compute a coarse plane's value alike, so a fine plane gets the
+  // same value whichever z-chunk it falls in
   auto cval = [&](const CRaw& r, C& va, C& vb) {
     if (KEEPX) {
-      va = ya * raw_ca(r.p[0]) + yb * raw_ca(r.p[1]);
-      vb = ya * raw_cb(r.p[0]) + yb * raw_cb(r.p[1]);
+      va = fmac(yb, raw_ca(r.p[1]), ya * raw_ca(r.p[0]));
+      vb = fmac(yb, raw_cb(r.p[1]), ya * raw_cb(r.p[0]));
     } else {
       const C u0 = raw_c(r.v[0]), u1 = raw_c(r.v[1]), u2 = raw_c(r.v[2]);
       const C w0 = raw_c(r.v[3]), w1 = raw_c(r.v[4]), w2 = raw_c(r.v[5]);
-      va = ya * (a0 * u0 + a1 * u1) + yb * (a0 * w0 + a1 * w1);
-      vb = ya * (b0 * u0 + b2 * u2) + yb * (b0 * w0 + b2 * w2);
+      va = fmac(yb, fmac(a1, w1, a0 * w0), ya * fmac(a1, u1, a0 * u0));
+      vb = fmac(yb, fmac(b2, w2, b0 * w0), ya * fmac(b2, u2, b0 * u0));
     }
   };
   auto fplane = [&](int k) { return x + (int64_t)min(max(k, 0), nz - 1) * pl; };
@@ -878,8 +881,8 @@ k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
       const int Kn = (k & 1) ? K + 1 : K - 1;
       const bool two = Kn >= 0 && Kn < cnz;
       const C w1 = two ? (C)0.75 : (C)1, w2 = two ? (C)0.25 : (C)0;
-      za = w1 * v0a + w2 * ((k & 1) ? vpa : vma);
-      zb = w1 * v0b + w2 * ((k & 1) ? vpb : vmb);
+      za = fmac(w2, (k & 1) ? vpa : vma, w1 * v0a);
+      zb = fmac(w2, (k & 1) ? vpb : vmb, w1 * v0b);
     } else {
       za = v0a;
       zb = v0b;

@@ -155,14 +155,16 @@ def test_streamed_hierarchy_argument_checks(lib):
     h = ctypes.c_void_p()
     o = gd.default_opts()
     create = lib.gd_hierarchy_create_streamed
-    assert create(None, 8, 8, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 4, None) == gd.ERR_INVALID
-    assert create(ctypes.byref(h), 8, 8, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 0, None) == gd.ERR_INVALID
-    assert create(ctypes.byref(h), 8, 8, 0, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 4, None) == gd.ERR_INVALID
-    assert create(ctypes.byref(h), 8, 8, 8, 0.0, 0.0, 0.0, 0.0, 1, ctypes.byref(o), 4, None) == gd.ERR_INVALID
-    assert create(ctypes.byref(h), 8, 1, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 4, None) == gd.ERR_UNSUPPORTED
+    assert create(None, 8, 8, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 4, 0, None) == gd.ERR_INVALID
+    assert create(ctypes.byref(h), 8, 8, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 0, 0, None) == gd.ERR_INVALID
+    assert create(ctypes.byref(h), 8, 8, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 4, -1, None) == gd.ERR_INVALID
+    assert create(ctypes.byref(h), 8, 8, 0, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 4, 0, None) == gd.ERR_INVALID
+    assert create(ctypes.byref(h), 8, 8, 8, 0.0, 0.0, 0.0, 0.0, 1, ctypes.byref(o), 4, 0, None) == gd.ERR_INVALID
+    assert create(ctypes.byref(h), 8, 1, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(o), 4, 0, None) == gd.ERR_UNSUPPORTED
     oh = gd.default_opts(discretization=1)
-    assert create(ctypes.byref(h), 8, 8, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(oh), 4, None) == gd.ERR_UNSUPPORTED
+    assert create(ctypes.byref(h), 8, 8, 8, 0.0, 1.0, 1.0, 4.0, 1, ctypes.byref(oh), 4, 0, None) == gd.ERR_UNSUPPORTED
     assert not h.value
     assert lib.gd_vcycle_streamed(None, P(64), P(128), 1, None, None) == gd.ERR_INVALID
     assert lib.gd_hierarchy_device_bytes(None, None, None) == gd.ERR_INVALID
+    assert lib.gd_hierarchy_streamed_levels(None, None) == gd.ERR_INVALID
     assert lib.gd_last_error()

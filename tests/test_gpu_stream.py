@@ -39,24 +39,39 @@ CASES = [
     ((64, 24, 40), 16, torch.float16, 0.0, (1.0, 1.0, 4.0), (2, 2)),
     ((33, 18, 22), 8, torch.float64, 0.05, (1.0, 0.5, 2.0), (2, 2)),
     ((52, 16, 20), 10, torch.float32, 0.0, (1.0, 1.0, 4.0), (1, 3)),
+    ((72, 12, 18), 8, torch.float32, 0.0, (1.0, 1.0, 16.0), (2, 2)),
+    ((66, 10, 14), 6, torch.float32, 0.001, (1.0, 1.0, 16.0), (1, 2)),
 ]
+
+
+def expected_streamed_levels(h):
+    """The finest level, then every next level with more than an eighth of
+    its cells and ny >= 2, leaving at least one level in HBM."""
+    n = h.info()
+    dims = [h.info(l)[0] for l in range(n)]
+    cells = [d[0] * d[1] * d[2] for d in dims]
+    k = 1
+    while k + 1 < n and dims[k][1] >= 2 and 8 * cells[k] > cells[0]:
+        k += 1
+    return k
 
 
 def case_id(c):
     return f"{c[0]}-slab{c[1]}-{str(c[2]).split('.')[-1]}-a{c[3]}-p{c[5]}"
 
 
+@pytest.mark.parametrize("levels", [1, 8])
 @pytest.mark.parametrize("case", CASES, ids=case_id)
-def test_streamed_cycles_equal_in_core(gd, case):
+def test_streamed_cycles_equal_in_core(gd, case, levels):
     shape, slab, dt, alpha, beta, (pre, post) = case
-    say("streamed vs in-core", case_id(case))
+    say("streamed vs in-core", case_id(case), "levels", levels)
     rng = np.random.default_rng(11)
     b = torch.from_numpy(rng.standard_normal(shape)).to(dt)
     x0 = torch.from_numpy(rng.standard_normal(shape) * 0.5).to(dt)
     hc = gd.Hierarchy(shape, alpha, beta, dt, pre_smooth=pre, post_smooth=post)
     xd, bd = x0.cuda(), b.cuda()
     rr_c = hc.vcycle(xd, bd, 2)
-    hs = gd.StreamedHierarchy(shape, alpha, beta, dt, slab, pre_smooth=pre, post_smooth=post)
+    hs = gd.StreamedHierarchy(shape, alpha, beta, dt, slab, levels, pre_smooth=pre, post_smooth=post)
     assert hs.info() == hc.info()
     xh = torch.empty(shape, dtype=dt, pin_memory=True)
     xh.copy_(x0)
@@ -65,6 +80,9 @@ def test_streamed_cycles_equal_in_core(gd, case):
     rr_s = hs.vcycle(xh, bh, 2)
     assert torch.equal(xh, xd.cpu())
     assert abs(rr_s - rr_c) <= 1e-9 * rr_c
+    assert hs.streamed_levels() == min(levels, expected_streamed_levels(hc))
+    if beta[2] == 16.0 and levels > 1:
+        assert hs.streamed_levels() == 3
     _, planes = hs.device_bytes()
     halo = 2 * max(pre, post) + 2
     want = min(shape[0], max(slab + slab % 2, halo) + 2 * halo)
@@ -94,7 +112,8 @@ def test_streamed_solve_matches_oracle(gd):
     shape = (41, 20, 26)
     alpha, beta = 0.05, (1.0, 0.5, 2.0)
     b = np.random.default_rng(13).standard_normal(shape)
-    hs = gd.StreamedHierarchy(shape, alpha, beta, torch.float64, 8)
+    hs = gd.StreamedHierarchy(shape, alpha, beta, torch.float64, 8, 8)
+    assert hs.streamed_levels() == 2
     xh = torch.zeros(shape, dtype=torch.float64, pin_memory=True)
     bh = torch.from_numpy(b).pin_memory()
     rr = 1.0
@@ -112,15 +131,17 @@ def test_streamed_solve_matches_oracle(gd):
 
 def test_streamed_holds_less_device_memory(gd):
     say("streamed device bytes")
-    shape = (512, 64, 64)
+    shape = (1024, 64, 64)
     hc = gd.Hierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32)
-    hs = gd.StreamedHierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32, 16)
+    hs = gd.StreamedHierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32, 16)  # levels chosen by HBM use
     bc, _ = hc.device_bytes()
     bs, planes = hs.device_bytes()
     assert planes == 16 + 2 * 6
     # in core: x, x', b of every level (about 3 x 1.57 finest arrays); streamed:
-    # the coarse levels (about 3 x 0.57) and three windows
-    assert bs < 0.6 * bc
+    # levels 2 and below (about 3 x 0.07) and three window buffer sets of
+    # levels 0 and 1 (28 planes each), which do not grow with nz
+    assert hs.streamed_levels() == 2
+    assert bs < 0.25 * bc
 
 
 def test_in_core_calls_refuse_a_streamed_hierarchy(gd):
@@ -134,3 +155,14 @@ def test_in_core_calls_refuse_a_streamed_hierarchy(gd):
         hs.fcg(x, x.clone())
     with pytest.raises(ValueError):
         hs.vcycle(torch.zeros(4, 8, 8), torch.zeros(4, 8, 8))
+
+
+def test_automatic_choice_keeps_short_coarse_levels_resident(gd):
+    """With stream_levels = 0 a coarser level is streamed only when its
+    window buffers take less HBM than the level: not on a short stack."""
+    say("streamed automatic levels")
+    hs = gd.StreamedHierarchy((40, 33, 47), 0.0, (1.0, 1.0, 4.0), torch.float32, 8)
+    assert hs.streamed_levels() == 1
+    hs2 = gd.StreamedHierarchy((40, 33, 47), 0.0, (1.0, 1.0, 4.0), torch.float32, 8, 8)
+    assert hs2.streamed_levels() == 2
+    assert hs.device_bytes()[0] < hs2.device_bytes()[0]
