@@ -93,6 +93,13 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
+// LDS position of complex value i of a block: the low four bits are XORed
+// with the XOR of the next three nibbles.  This permutes each aligned group
+// of 16 (no extra LDS), and spreads over the banks both the bit-reversed
+// scatter of the loads and the short strides of the first FFT steps, which
+// would otherwise fall on a few banks.
+__device__ __forceinline__ int swz(int i) { return i ^ (((i >> 4) ^ (i >> 8) ^ (i >> 12)) & 15); }
+
 // one DCT-II (INV = false) or inverse pass along the lines of d, reading src
 // (type TI) and writing dst (type TO); src == dst for the FP64 work array
 // LDS (dynamic, sized by the launch): the block's lines as complex values,
@@ -120,7 +127,7 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
     int l, j;
     split(e, l, j);
     const double v = (l0 + l < d.nlines) ? ld_any(src + base(l) + j * d.stride) : 0.0;
-    if (!INV) V[(l << logn) + bitrev(mk_pos(j, n), logn)] = make_double2(v, 0.0);
+    if (!INV) V[swz((l << logn) + bitrev(mk_pos(j, n), logn))] = make_double2(v, 0.0);
     else X[(l << logn) + j] = v;
   }
   __syncthreads();
@@ -131,16 +138,17 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
       const double xk = X[(l << logn) + k], xm = k == 0 ? 0.0 : X[(l << logn) + n - k];
       const double2 q = d.Q[k];
       const double ck = q.x, sk = -q.y;
-      V[(l << logn) + bitrev(k, logn)] = make_double2(ck * xk + sk * xm, sk * xk - ck * xm);
+      V[swz((l << logn) + bitrev(k, logn))] = make_double2(ck * xk + sk * xm, sk * xk - ck * xm);
     }
     __syncthreads();
   }
   int lh = 0;  // log2 of the half size of the next stage
   if (logn & 1) {  // odd length exponent: one radix-2 stage of half size 1 (twiddle 1)
     for (int e = threadIdx.x; e < (tot >> 1); e += DCT_NT) {
-      const double2 u = V[2 * e], t = V[2 * e + 1];
-      V[2 * e] = cadd(u, t);
-      V[2 * e + 1] = csub(u, t);
+      const int a = swz(2 * e), b = swz(2 * e + 1);
+      const double2 u = V[a], t = V[b];
+      V[a] = cadd(u, t);
+      V[b] = csub(u, t);
     }
     __syncthreads();
     lh = 1;
@@ -156,14 +164,15 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
       const int i0 = (l << logn) + ((q >> lh) << (lh + 2)) + p;
       double2 w1 = d.W[p << (t2 + 1)], w2 = d.W[p << t2];
       if (INV) { w1.y = -w1.y; w2.y = -w2.y; }
-      const double2 a = V[i0], b = cmul(w1, V[i0 + h]), c = V[i0 + 2 * h], dd = cmul(w1, V[i0 + 3 * h]);
+      const int p0 = swz(i0), p1 = swz(i0 + h), p2 = swz(i0 + 2 * h), p3 = swz(i0 + 3 * h);
+      const double2 a = V[p0], b = cmul(w1, V[p1]), c = V[p2], dd = cmul(w1, V[p3]);
       const double2 a1 = cadd(a, b), b1 = csub(a, b);
       const double2 c1 = cmul(w2, cadd(c, dd)), d1 = cmul(w2, csub(c, dd));
       const double2 jd = INV ? make_double2(-d1.y, d1.x) : make_double2(d1.y, -d1.x);
-      V[i0] = cadd(a1, c1);
-      V[i0 + h] = cadd(b1, jd);
-      V[i0 + 2 * h] = csub(a1, c1);
-      V[i0 + 3 * h] = csub(b1, jd);
+      V[p0] = cadd(a1, c1);
+      V[p1] = cadd(b1, jd);
+      V[p2] = csub(a1, c1);
+      V[p3] = csub(b1, jd);
     }
     __syncthreads();
   }
@@ -173,7 +182,7 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
     if (l0 + l >= d.nlines) continue;
     double out;
     if (!INV) {
-      const double2 q = d.Q[j], v = V[(l << logn) + j];
+      const double2 q = d.Q[j], v = V[swz((l << logn) + j)];
       out = q.x * v.x - q.y * v.y;  // Re(Q_j V_j)
       if (d.scale >= 0) {  // z-axis pass: line (i, jy), sample k = j
         const int64_t L = l0 + l;
@@ -183,7 +192,7 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
       }
     } else {
       const int m = (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
-      out = V[(l << logn) + m].x / (double)n;
+      out = V[swz((l << logn) + m)].x / (double)n;
     }
     st_any(dst + base(l) + j * d.stride, out);
   }
