@@ -103,7 +103,10 @@ __device__ __forceinline__ int swz(int i) { return i ^ (((i >> 4) ^ (i >> 8) ^ (
 // one DCT-II (INV = false) or inverse pass along the lines of d, reading src
 // (type TI) and writing dst (type TO); src == dst for the FP64 work array
 // LDS (dynamic, sized by the launch): the block's lines as complex values,
-// then (inverse) their coefficients, read twice.
+// then (inverse) their coefficients, read twice, or (forward) the FFT
+// twiddles of this length, loaded once per block instead of at every step
+// (the inverse keeps them in global memory: the extra LDS would cost it a
+// resident block per CU, which it needs more).
 // The FFT is decimation in time on bit-reversed input; two radix-2 stages
 // (half sizes h and 2h) are done at once as one radix-4 step on four values
 // h apart, so a length-2^m transform takes ceil(m / 2) barriers.
@@ -113,6 +116,10 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
   const int n = d.n, logn = d.logn, lpb = d.lpb, tot = n << d.loglpb;
   double2* V = smem;
   double* X = reinterpret_cast<double*>(smem + tot);
+  double2* Wl = reinterpret_cast<double2*>(X);
+  if (!INV)
+    for (int t = threadIdx.x; t < (n >> 1); t += DCT_NT) Wl[t] = d.W[t];
+  const double2* Wt = INV ? d.W : Wl;
   const int64_t l0 = (int64_t)blockIdx.x << d.loglpb;
   const int64_t fmask = d.nf - 1;
   auto base = [&](int l) -> int64_t {
@@ -162,7 +169,7 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
       const int l = e >> (logn - 2), q = e & ((n >> 2) - 1);
       const int p = q & (h - 1);
       const int i0 = (l << logn) + ((q >> lh) << (lh + 2)) + p;
-      double2 w1 = d.W[p << (t2 + 1)], w2 = d.W[p << t2];
+      double2 w1 = Wt[p << (t2 + 1)], w2 = Wt[p << t2];
       if (INV) { w1.y = -w1.y; w2.y = -w2.y; }
       const int p0 = swz(i0), p1 = swz(i0 + h), p2 = swz(i0 + 2 * h), p3 = swz(i0 + 3 * h);
       const double2 a = V[p0], b = cmul(w1, V[p1]), c = V[p2], dd = cmul(w1, V[p3]);
@@ -293,7 +300,8 @@ hipError_t dct_tables(int n, double2* W, double2* Q, double* lam, hipStream_t st
 
 template <bool INV, typename TI, typename TO>
 static void lines_launch(const void* src, void* dst, const DctLines& d, unsigned blocks, hipStream_t st) {
-  const size_t lds = (size_t)d.n * d.lpb * (sizeof(double2) + (INV ? sizeof(double) : 0));
+  const size_t lds = (size_t)d.n * d.lpb * sizeof(double2) +
+                     (INV ? (size_t)d.n * d.lpb * sizeof(double) : (size_t)(d.n / 2) * sizeof(double2));
   hipLaunchKernelGGL((k_dct_lines<INV, TI, TO>), dim3(blocks), dim3(DCT_NT), lds, st, (const TI*)src, (TO*)dst, d);
 }
 
