@@ -103,10 +103,10 @@ __device__ __forceinline__ int swz(int i) { return i ^ (((i >> 4) ^ (i >> 8) ^ (
 // one DCT-II (INV = false) or inverse pass along the lines of d, reading src
 // (type TI) and writing dst (type TO); src == dst for the FP64 work array
 // LDS (dynamic, sized by the launch): the block's lines as complex values,
-// then (inverse) their coefficients, read twice, or (forward) the FFT
-// twiddles of this length, loaded once per block instead of at every step
-// (the inverse keeps them in global memory: the extra LDS would cost it a
-// resident block per CU, which it needs more).
+// then the FFT twiddles of this length (loaded once per block instead of at
+// every step).  The inverse first keeps its real coefficients in the complex
+// buffer's space; each thread reads the pairs it needs into registers before
+// the buffer is overwritten, so no second buffer costs occupancy.
 // The FFT is decimation in time on bit-reversed input; two radix-2 stages
 // (half sizes h and 2h) are done at once as one radix-4 step on four values
 // h apart, so a length-2^m transform takes ceil(m / 2) barriers.
@@ -115,11 +115,9 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
   extern __shared__ double2 smem[];
   const int n = d.n, logn = d.logn, lpb = d.lpb, tot = n << d.loglpb;
   double2* V = smem;
-  double* X = reinterpret_cast<double*>(smem + tot);
-  double2* Wl = reinterpret_cast<double2*>(X);
-  if (!INV)
-    for (int t = threadIdx.x; t < (n >> 1); t += DCT_NT) Wl[t] = d.W[t];
-  const double2* Wt = INV ? d.W : Wl;
+  double* X = reinterpret_cast<double*>(smem);  // inverse: coefficients, until the twiddle step
+  double2* Wt = smem + tot;
+  for (int t = threadIdx.x; t < (n >> 1); t += DCT_NT) Wt[t] = d.W[t];
   const int64_t l0 = (int64_t)blockIdx.x << d.loglpb;
   const int64_t fmask = d.nf - 1;
   auto base = [&](int l) -> int64_t {
@@ -139,13 +137,26 @@ __global__ void __launch_bounds__(DCT_NT) k_dct_lines(const TI* src, TO* dst, Dc
   }
   __syncthreads();
   if (INV) {
-    // V_k = exp(i pi k / 2n) (X_k - i X_{n-k}) = conj(Q_k) (X_k - i X_{n-k}), X_n = 0
-    for (int e = threadIdx.x; e < tot; e += DCT_NT) {
-      const int l = e >> logn, k = e & (n - 1);
-      const double xk = X[(l << logn) + k], xm = k == 0 ? 0.0 : X[(l << logn) + n - k];
-      const double2 q = d.Q[k];
-      const double ck = q.x, sk = -q.y;
-      V[swz((l << logn) + bitrev(k, logn))] = make_double2(ck * xk + sk * xm, sk * xk - ck * xm);
+    // V_k = exp(i pi k / 2n) (X_k - i X_{n-k}) = conj(Q_k) (X_k - i X_{n-k}), X_n = 0;
+    // all reads of X before the barrier, all writes of V after it
+    constexpr int R = DCT_LDS / DCT_NT;
+    double2 tv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e = threadIdx.x + r * DCT_NT;
+      if (e < tot) {
+        const int l = e >> logn, k = e & (n - 1);
+        const double xk = X[(l << logn) + k], xm = k == 0 ? 0.0 : X[(l << logn) + n - k];
+        const double2 q = d.Q[k];
+        const double ck = q.x, sk = -q.y;
+        tv[r] = make_double2(ck * xk + sk * xm, sk * xk - ck * xm);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e = threadIdx.x + r * DCT_NT;
+      if (e < tot) V[swz(((e >> logn) << logn) + bitrev(e & (n - 1), logn))] = tv[r];
     }
     __syncthreads();
   }
@@ -300,8 +311,7 @@ hipError_t dct_tables(int n, double2* W, double2* Q, double* lam, hipStream_t st
 
 template <bool INV, typename TI, typename TO>
 static void lines_launch(const void* src, void* dst, const DctLines& d, unsigned blocks, hipStream_t st) {
-  const size_t lds = (size_t)d.n * d.lpb * sizeof(double2) +
-                     (INV ? (size_t)d.n * d.lpb * sizeof(double) : (size_t)(d.n / 2) * sizeof(double2));
+  const size_t lds = ((size_t)d.n * d.lpb + (size_t)(d.n / 2)) * sizeof(double2);
   hipLaunchKernelGGL((k_dct_lines<INV, TI, TO>), dim3(blocks), dim3(DCT_NT), lds, st, (const TI*)src, (TO*)dst, d);
 }
 
