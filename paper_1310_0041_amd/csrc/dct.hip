@@ -336,12 +336,11 @@ hipError_t dct_pass(const DctPass& p, hipStream_t st) {
   else { d.n = p.nz; d.stride = pl; d.nf = nx; d.sf = 1; d.ss = nx; d.nlines = nx * ny; }
   d.logn = ilog2(d.n);
   d.adjacent = d.sf == 1;
-  // contiguous lines: about 1024 values per block in a forward pass (more
-  // resident blocks per CU; measured faster) and 2048 in an inverse one
-  // (measured faster); lines of adjacent columns: about 2048, or up to 4096
-  // when they are long (n >= 512), so that the lines of a block still form
-  // runs of 4 or more values in memory
-  const int vals = !d.adjacent ? (p.inverse ? DCT_LDS / 2 : DCT_LDS / 4) : (d.n <= 256 ? DCT_LDS / 2 : DCT_LDS);
+  // values per block, the fastest measured on MI355X: about 1024 in a
+  // forward pass, 2048 in an inverse one.  Long lines of adjacent columns
+  // (n >= 512) keep up to 4096 values, so that the lines of a block still
+  // form runs of 4 or more values in memory.
+  const int vals = (d.adjacent && d.n > 256) ? DCT_LDS : (p.inverse ? DCT_LDS / 2 : DCT_LDS / 4);
   d.lpb = vals / d.n;
   if (d.lpb < 1) d.lpb = 1;
   if (d.lpb > 64) d.lpb = 64;
