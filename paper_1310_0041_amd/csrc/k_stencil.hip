@@ -1,0 +1,429 @@
+// gfx950 finest-level passes of the anisotropic-diffusion (Eq. (1)) and
+// per-slice screened-Poisson (Eq. (2)) solves of Kazhdan et al.,
+// "Gradient-Domain Processing for Large EM Image Stacks": correction-form
+// right-hand side, FP64 canonical residual and refinement update, gauge
+// sums and output.  Layout conventions as in kernels.hip.
+#include "gd_kcommon.h"
+
+namespace gd {
+
+// ------------------------------------------- finest level of AD / SP (Eq. 1, 2)
+//
+// Canonical system of both phases: A = alpha + w_x L_x + w_y L_y + w_z L_z,
+// b = alpha I1 + (w_x L_x + w_y L_y) I0 (AD: alpha = 0; SP: w_z = 0).  In
+// the grid description the caller's y axis is the grid's y axis for a stack
+// and its z axis for a slice (ny = 1); the in-slice weights are then w_x and
+// w_z.  GridDesc::zin flags the slice form.
+// The plain solver iterates on the correction E = x - I0, whose right-hand
+// side is b - A I0 = alpha (I1 - I0) - (cross-slice part of A) I0.
+
+
+// ------------------------------------- correction-form stencil passes
+//
+// Both passes on the finest grid use one z-marching structure (pairs of x
+// per thread, the three planes of one field in an LDS ring for the in-plane
+// neighbours, z neighbours in registers; FP64 arithmetic):
+//
+// KIND 0, right-hand side of the correction E = x - I0.  With F = I0:
+//   b_corr = alpha (I1 - I0) - [stack] w_z L_z I0
+//   ||b||^2 of the canonical system b = alpha I1 + (w_x L_x + w_y L_y) I0
+//   (+ w_z L_z I0 for a slice, whose "z" is its own second axis); the stack
+//   form's cross-slice target is zero (Eq. (1)).  Writes b_corr and a zero
+//   correction.
+// KIND 1, canonical residual b - A x in FP64.  With F = x - I0 (E in MODE 0,
+// x64 - I0 in MODE 1, x64 + s e - I0 in MODE 2, where the refinement's
+// update x64 + s e is also written to x64_out, s = e_scale[grid]) the I0
+// terms of b and A x cancel except across slices:
+//   r = alpha (I1 - I0 - F) - (w_x L_x + w_y L_y + w_z L_z) F - [stack] w_z L_z I0
+//   ||r||^2 per block; r * inv_scale stored when rout is set.
+// L_a v is the Neumann second difference sum over existing neighbours of
+// (v_c - v_n).  Row tiles (TY == 1) serve grids with ny == 1.
+template <typename Tin, typename S, int TX, int TY, int KIND, int MODE>
+__global__ void __launch_bounds__(TX * TY / 2)
+k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+               const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
+               const double* __restrict__ x64, S* __restrict__ out0, S* __restrict__ out1,
+               const double* __restrict__ inv_scale, double* __restrict__ partials,
+               double* __restrict__ x64_out, const double* __restrict__ e_scale) {
+  constexpr bool ROW = (TY == 1);
+  constexpr int NT = TX * TY / 2;
+  constexpr int YO = ROW ? 0 : 1;
+  constexpr int HX = TX + 2, HY = ROW ? 1 : TY + 2;
+  constexpr int NHALO = HX * HY - TX * TY;
+  constexpr int NHR = (NHALO + NT - 1) / NT;
+  static_assert(MODE < 2 || KIND == 1, "the refinement update belongs to the residual pass");
+  __shared__ double X[3][HY][HX];
+  __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
+  const GridDesc& G = grids[t.g];
+  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
+  const bool slice = G.zin != 0;
+  const double alpha = G.alpha, wx = G.wx, wy = ROW ? 0.0 : G.wy, wz = G.wz;
+  const bool cross = !slice && wz != 0.0;  // the stack's cross-slice term of I0
+  const int64_t pl = (int64_t)px * ny;
+  const Tin* I0g = I0 + G.ioff;
+  const Tin* I1g = (I1 && alpha != 0.0) ? I1 + G.ioff : nullptr;
+  const S* Eg = E + G.off;
+  const double* xg = x64 + G.off;
+  const bool ivec = ((G.ioff | G.ipy | G.ipz) & 1) == 0, vec = ((px | G.off) & 1) == 0;
+  const int tid = threadIdx.x;
+  const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
+  const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
+  const int gx = x0 + 2 * pxl, gy = y0 + tyl;
+  const bool rowok = gy < ny;
+  const bool vA = rowok && gx < nx, vB = rowok && gx + 1 < nx;
+  const int lx = 1 + 2 * pxl, ly = YO + tyl;
+  const int64_t own = (int64_t)gy * px + gx, ownu = (int64_t)gy * G.ipy + gx;
+  const bool up = !ROW && gy > 0, dn = !ROW && gy + 1 < ny, o0 = gx > 0, o1 = gx + 2 < nx;
+
+  int hoff[NHR];
+  int64_t hg[NHR], hu[NHR];
+  bool hv[NHR];
+#pragma unroll
+  for (int k = 0; k < NHR; ++k) {
+    const int h = tid + NT * k;
+    int hy = 0, hx = 0;
+    if (ROW) {
+      hx = (h == 0) ? 0 : HX - 1;
+    } else if (h < HX) {
+      hy = 0; hx = h;
+    } else if (h < 2 * HX) {
+      hy = HY - 1; hx = h - HX;
+    } else {
+      const int m = h - 2 * HX;
+      hy = 1 + (m >> 1);
+      hx = (m & 1) ? HX - 1 : 0;
+    }
+    const int cx = x0 - 1 + hx, cy = y0 - YO + hy;
+    hv[k] = h < NHALO && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    hoff[k] = hy * HX + hx;
+    hg[k] = hv[k] ? (int64_t)cy * px + cx : 0;
+    hu[k] = hv[k] ? (int64_t)cy * G.ipy + cx : 0;
+  }
+  // Raw loads of plane q: F's own pair and halo values and (KIND 1) I0's
+  // pair; converted to FP64 only in stash(), after other work has run.
+  using FS = std::conditional_t<KIND == 0, Tin, std::conditional_t<MODE == 0, S, double>>;
+  Raw2<FS> rf;
+  Raw2<Tin> ri;
+  Raw2<S> re;  // MODE 2: the correction e
+  Raw<FS> rh[NHR];
+  Raw<Tin> rhi[NHR];
+  Raw<S> rhe[NHR];
+  const double es = (MODE == 2) ? e_scale[t.g] : 0.0;
+  // loads from clamped addresses without branches around them (masked in stash)
+  auto fetch = [&](int q) {
+    const int qc = min(max(q, 0), nz - 1);
+    const Tin* I0q = I0g + qc * G.ipz;
+    const int64_t po = qc * pl;
+    const int64_t oo = vA ? own : 0, ou = vA ? ownu : 0;
+    if (KIND == 0) {
+      ld_raw2(reinterpret_cast<const FS*>(I0q) + ou, ivec, vB, rf);
+    } else {
+      ld_raw2(I0q + ou, ivec, vB, ri);
+      if (MODE == 0) {
+        ld_raw2(reinterpret_cast<const FS*>(Eg) + po + oo, true, true, rf);
+      } else {
+        ld_raw2(reinterpret_cast<const FS*>(xg) + po + oo, true, true, rf);
+        if (MODE == 2) ld_raw2(Eg + po + oo, true, true, re);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NHR; ++k) {
+      if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0q) + hu[k], rh[k]);
+      else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + po + hg[k], rh[k]);
+      else {
+        ld_raw(reinterpret_cast<const FS*>(xg) + po + hg[k], rh[k]);
+        ld_raw(I0q + hu[k], rhi[k]);
+        if (MODE == 2) ld_raw(Eg + po + hg[k], rhe[k]);
+      }
+    }
+  };
+  // convert the last fetch: F pair (fa, fb), I0 pair (ia, ib); store F's plane
+  double fa = 0, fb = 0, ia = 0, ib = 0;
+  auto stash = [&](int q) {
+    const bool okq = q >= 0 && q < nz, mA = okq && vA, mB = okq && vB;
+    if (KIND == 1) {
+      ia = mA ? raw_a(ri) : 0.0;
+      ib = mB ? raw_b(ri) : 0.0;
+    }
+    fa = mA ? raw_a(rf) : 0.0;
+    fb = mB ? raw_b(rf) : 0.0;
+    if (KIND == 1 && MODE == 2) {  // refinement update x64 + s e, written by the cell's owner
+      fa += mA ? es * raw_a(re) : 0.0;
+      fb += mB ? es * raw_b(re) : 0.0;
+      if (vA && q >= q0 && q < q1) st2(x64_out + G.off + q * pl + own, vec, vB, fa, fb);
+    }
+    if (KIND == 1 && MODE >= 1) {
+      fa -= ia;
+      fb = vB ? fb - ib : 0.0;
+    }
+    double* P = &X[((q % 3) + 3) % 3][0][0];
+    P[ly * HX + lx] = fa;
+    P[ly * HX + lx + 1] = fb;
+#pragma unroll
+    for (int k = 0; k < NHR; ++k)
+      if (tid + NT * k < NHALO) {
+        double v = raw_d(rh[k]);
+        if (KIND == 1 && MODE == 2) v += es * raw_d(rhe[k]);
+        if (KIND == 1 && MODE >= 1) v -= raw_d(rhi[k]);
+        P[hoff[k]] = (okq && hv[k]) ? v : 0.0;
+      }
+  };
+  // I1 pair at plane q (raw), prefetched one plane ahead
+  Raw2<Tin> r1n;
+  auto fetch1 = [&](int q) {  // raw, clamped; used only for k in [q0, q1) with vA / vB
+    if (I1g) ld_raw2(I1g + min(max(q, 0), nz - 1) * G.ipz + (vA ? ownu : 0), ivec, vB, r1n);
+  };
+
+  // registers: F and I0 at k - 1 (m), k (c), k + 1 (p)
+  double fma_ = 0, fmb = 0, fca, fcb, fpa, fpb, ima = 0, imb = 0, ica = 0, icb = 0, ipa = 0, ipb = 0;
+  fetch(q0 - 1);
+  stash(q0 - 1);  // plane q0 - 1 goes to the ring slot of q0 + 2, rewritten before it is read
+  fma_ = fa; fmb = fb; ima = ia; imb = ib;
+  fetch(q0);
+  stash(q0);
+  fca = fa; fcb = fb; ica = ia; icb = ib;
+  fetch(q0 + 1);
+  fetch1(q0);
+  double nrm = 0.0;
+  for (int k = q0; k < q1; ++k) {
+    stash(k + 1);
+    fpa = fa; fpb = fb; ipa = ia; ipb = ib;
+    const Raw2<Tin> r1 = r1n;
+    fetch(k + 2);
+    fetch1(k + 1);
+    __syncthreads();
+    const double v1a = I1g ? raw_a(r1) : 0.0, v1b = I1g ? raw_b(r1) : 0.0;
+    const double* P = &X[k % 3][0][0];
+    const bool zm = k > 0, zp = k < nz - 1;
+    double ra = 0.0, rb = 0.0;
+    // in-plane and z second differences of F; I0's z term for the stack
+    auto lap = [&](double c, double l, bool hl, double rr, bool hr, double u_, double d_, double zm_, double zp_) {
+      double s2 = 0.0;
+      if (hl) s2 += wx * (c - l);
+      if (hr) s2 += wx * (c - rr);
+      if (up) s2 += wy * (c - u_);
+      if (dn) s2 += wy * (c - d_);
+      if (zm) s2 += wz * (c - zm_);
+      if (zp) s2 += wz * (c - zp_);
+      return s2;
+    };
+    if (vA) {
+      const double c = fca;
+      const double lf = lap(c, o0 ? P[ly * HX + lx - 1] : 0.0, o0, fcb, vB, up ? P[(ly - 1) * HX + lx] : 0.0,
+                            dn ? P[(ly + 1) * HX + lx] : 0.0, fma_, fpa);
+      double lzI = 0.0;  // w_z L_z I0 (stack only)
+      if (cross) {
+        const double i0 = KIND == 0 ? fca : ica, im = KIND == 0 ? fma_ : ima, ip = KIND == 0 ? fpa : ipa;
+        if (zm) lzI += wz * (i0 - im);
+        if (zp) lzI += wz * (i0 - ip);
+      }
+      if (KIND == 0) {
+        const double lin = lf - (cross ? lzI : 0.0);  // canonical part of L I0
+        const double bcan = alpha * v1a + lin;
+        nrm += bcan * bcan;
+        ra = alpha * (v1a - c) - lzI;
+      } else {
+        ra = alpha * (v1a - ica - c) - lf - lzI;
+        nrm += ra * ra;
+      }
+    }
+    if (vB) {
+      const double c = fcb;
+      const double lf = lap(c, fca, true, o1 ? P[ly * HX + lx + 2] : 0.0, o1, up ? P[(ly - 1) * HX + lx + 1] : 0.0,
+                            dn ? P[(ly + 1) * HX + lx + 1] : 0.0, fmb, fpb);
+      double lzI = 0.0;
+      if (cross) {
+        const double i0 = KIND == 0 ? fcb : icb, im = KIND == 0 ? fmb : imb, ip = KIND == 0 ? fpb : ipb;
+        if (zm) lzI += wz * (i0 - im);
+        if (zp) lzI += wz * (i0 - ip);
+      }
+      if (KIND == 0) {
+        const double lin = lf - (cross ? lzI : 0.0);
+        const double bcan = alpha * v1b + lin;
+        nrm += bcan * bcan;
+        rb = alpha * (v1b - c) - lzI;
+      } else {
+        rb = alpha * (v1b - icb - c) - lf - lzI;
+        nrm += rb * rb;
+      }
+    }
+    if (vA) {
+      const int64_t v = G.off + k * pl + own;
+      if (KIND == 0) {
+        if (out0) st2(out0 + v, vec, vB, (typename Ty<S>::C)ra, (typename Ty<S>::C)rb);
+        if (out1) st2(out1 + v, vec, vB, (typename Ty<S>::C)0, (typename Ty<S>::C)0);
+      } else if (out0) {
+        const double sc = inv_scale[t.g];
+        st2(out0 + v, vec, vB, (typename Ty<S>::C)(ra * sc), (typename Ty<S>::C)(rb * sc));
+      }
+    }
+    fma_ = fca; fmb = fcb; fca = fpa; fcb = fpb;
+    ima = ica; imb = icb; ica = ipa; icb = ipb;
+  }
+  if (partials) {
+    const double sm = block_sum(nrm, red);
+    if (threadIdx.x == 0) partials[t.bid] = sm;
+  }
+}
+
+template <typename Tin, typename S, int MODE>
+__global__ void __launch_bounds__(256)
+k_sum_shift(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+            const Tin* __restrict__ I0, const S* __restrict__ E, const double* __restrict__ x64,
+            double* __restrict__ partials) {
+  __shared__ double red[4];
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  double s = 0.0;
+  if (i < G.nx && j < G.ny) {
+    const int64_t pl = (int64_t)G.px * G.ny;
+    for (int k = t.z0; k < t.z1; ++k) {
+      const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
+      if (MODE == 0) {
+        s += ld64(E + v);
+      } else {
+        const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
+        s += x64[v] - in_at(I0, u);
+      }
+    }
+  }
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) partials[t.bid] = tot;
+}
+
+template <typename Tin, typename S, typename Tout, int MODE>
+__global__ void __launch_bounds__(256)
+k_finalize(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+           const Tin* __restrict__ I0, const S* __restrict__ E, const double* __restrict__ x64,
+           const double* __restrict__ shift, Tout* __restrict__ out) {
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  if (i >= G.nx || j >= G.ny) return;
+  const int64_t pl = (int64_t)G.px * G.ny;
+  const double sh = shift ? shift[t.g] : 0.0;
+  for (int k = t.z0; k < t.z1; ++k) {
+    const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
+    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
+    const double x = (MODE == 0) ? in_at(I0, u) + ld64(E + v) : x64[v];
+    st64(out + u, x - sh);
+  }
+}
+
+template <typename Tin>
+__global__ void __launch_bounds__(256)
+k_refine_init(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+              const Tin* __restrict__ I0, double* __restrict__ x64) {
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  if (i >= G.nx || j >= G.ny) return;
+  const int64_t pl = (int64_t)G.px * G.ny;
+  for (int k = t.z0; k < t.z1; ++k) {
+    const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
+    x64[G.off + k * pl + (int64_t)j * G.px + i] = in_at(I0, u);
+  }
+}
+
+
+
+// ============================================================ launchers
+
+template <typename TI, typename T, int KIND, int MODE>
+static void corr_stencil_launch(const Geom& g, const void* I0, const void* I1, const void* E, const double* x64,
+                                void* o0, void* o1, const double* inv_scale, double* partials, double* x64o,
+                                const double* escale, hipStream_t st) {
+  if (g.row)
+    hipLaunchKernelGGL((k_corr_stencil<TI, T, SWR_TX, 1, KIND, MODE>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0,
+                       st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0, (const TI*)I1, (const T*)E, x64, (T*)o0,
+                       (T*)o1, inv_scale, partials, x64o, escale);
+  else
+    hipLaunchKernelGGL((k_corr_stencil<TI, T, SW_TX, SW_TY, KIND, MODE>), dim3((unsigned)g.nblocks),
+                       dim3(SW_TX * SW_TY / 2), 0, st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0,
+                       (const TI*)I1, (const T*)E, x64, (T*)o0, (T*)o1, inv_scale, partials, x64o, escale);
+}
+
+hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, const void* I1, void* b,
+                           void* x, double* partials, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L2(TI, T) \
+  corr_stencil_launch<TI, T, 0, 0>(g, I0, I1, nullptr, nullptr, b, x, nullptr, partials, nullptr, nullptr, st)
+#define L1(TI) GD_DISPATCH_S2(s, TI, L2)
+  GD_DISPATCH_S(tin, L1)
+#undef L1
+#undef L2
+  return last();
+}
+
+hipError_t launch_canon_residual(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
+                                 const void* I1, const void* E, const double* x64, void* r_out,
+                                 const double* inv_scale, double* partials, hipStream_t st, double* x64_out,
+                                 const double* e_scale) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L2(TI, T)                                                                                              \
+  if (mode == 0)                                                                                               \
+    corr_stencil_launch<TI, T, 1, 0>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, nullptr, st); \
+  else if (mode == 1)                                                                                          \
+    corr_stencil_launch<TI, T, 1, 1>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, nullptr, st); \
+  else                                                                                                         \
+    corr_stencil_launch<TI, T, 1, 2>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, x64_out, e_scale, st)
+#define L1(TI) GD_DISPATCH_S2(s, TI, L2)
+  GD_DISPATCH_S(tin, L1)
+#undef L1
+#undef L2
+  return last();
+}
+
+hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0, const void* E,
+                            const double* x64, double* partials, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L2(TI, T)                                                                                             \
+  if (mode == 0)                                                                                              \
+    hipLaunchKernelGGL((k_sum_shift<TI, T, 0>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, partials);        \
+  else                                                                                                        \
+    hipLaunchKernelGGL((k_sum_shift<TI, T, 1>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, partials)
+#define L1(TI) GD_DISPATCH_S2(s, TI, L2)
+  GD_DISPATCH_S(tin, L1)
+#undef L1
+#undef L2
+  return last();
+}
+
+template <typename TI, typename T>
+static hipError_t finalize_out(gd_dtype tout, int mode, const Geom& g, const void* I0, const void* E,
+                               const double* x64, const double* shift, void* out, hipStream_t st) {
+#define L(TO)                                                                                                \
+  if (mode == 0)                                                                                             \
+    hipLaunchKernelGGL((k_finalize<TI, T, TO, 0>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, shift, (TO*)out); \
+  else                                                                                                       \
+    hipLaunchKernelGGL((k_finalize<TI, T, TO, 1>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, shift, (TO*)out)
+  GD_DISPATCH_S(tout, L)
+#undef L
+  return hipSuccess;
+}
+
+hipError_t launch_finalize(gd_dtype tin, gd_dtype s, gd_dtype tout, int mode, const Geom& g, const void* I0,
+                           const void* E, const double* x64, const double* shift, void* out, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+#define L2(TI, T) e = finalize_out<TI, T>(tout, mode, g, I0, E, x64, shift, out, st)
+#define L1(TI) GD_DISPATCH_S2(s, TI, L2)
+  GD_DISPATCH_S(tin, L1)
+#undef L1
+#undef L2
+  if (e != hipSuccess) return e;
+  return last();
+}
+
+hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, double* x64, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L(T) hipLaunchKernelGGL(k_refine_init<T>, GD_ARGS(g), (const T*)I0, x64)
+  GD_DISPATCH_S(tin, L)
+#undef L
+  return last();
+}
+
+}  // namespace gd

@@ -1,0 +1,465 @@
+// gfx950 red-black Gauss-Seidel relaxation (Sec. 4.1, multi-coloured GS) of
+// the multigrid solver for the screened anisotropic Poisson systems of
+// Kazhdan et al., "Gradient-Domain Processing for Large EM Image Stacks".
+// Layout and difference-form conventions as in kernels.hip.
+#include "gd_kcommon.h"
+
+namespace gd {
+
+// ------------------------------------------------------- red-black sweep
+//
+// One complete red-black Gauss-Seidel sweep (Sec. 4.1, multi-coloured GS),
+// out of place: reads x_in, writes x_out.  A block owns a TX x TY column of
+// the grid and marches along z.  Thread t owns the x-pair (x0 + 2 (t mod
+// TX/2), y0 + t / (TX/2)) and its two neighbours along x: in every plane one
+// of the pair is red and the other black, and the z-neighbours of a cell are
+// cells of the same column, so each thread keeps its column of planes
+// p-2 .. p+2 in registers and only the in-plane neighbours go through LDS
+// (four planes, with a 2-cell halo ring loaded by the threads in turn).
+//   step p:  barrier | red cells of plane p (own pair and the 1-cell ring
+//            around the tile, from old black values), written to plane p's
+//            LDS buffer | black cells of plane p - 1 (from the new red values
+//            of planes p-2..p: in-plane ones from plane p - 1's buffer,
+//            written in the previous step), plane p - 1 written to memory,
+//            plane p + 2 enters LDS (the buffer plane p - 2 used)
+// One barrier per plane suffices: within a step no buffer is both written
+// and read (red cells of plane p are written, only black cells of plane p
+// and planes p +- 1 are read; plane p - 1 is read; plane p + 2 is written).
+// Recomputing the red ring makes every tile independent of its neighbours,
+// so blocks never exchange data and the sweep equals the sequential
+// definition exactly.  Every thread relaxes its red cell and a ring cell in
+// each plane (a thread without a ring cell relaxes a stand-in and writes it
+// to a slot of its own), so that the LDS reads of both issue together, and
+// the plane parity is a compile-time argument of the unrolled step: the
+// per-parity weights and inverse diagonals stay in registers.  When
+// e_coarse != NULL the up-sampled coarse correction is added to x while it
+// is loaded (fused prolongation).
+// TY == 1 is the row form for grids with ny == 1 (2-D slices).
+
+template <int TX, int TY>
+struct SweepShape {
+  static constexpr bool ROW = (TY == 1);
+  static constexpr int NT = TX * TY / 2;                 // threads: one x-pair each
+  static constexpr int YO = ROW ? 0 : 2;                 // tile row 0 inside the LDS plane
+  static constexpr int HX = TX + 4, HY = ROW ? 1 : TY + 4;
+  static constexpr int NHALO = HX * HY - TX * TY;        // halo cells per plane
+  static constexpr int NHR = (NHALO + NT - 1) / NT;      // halo cells per thread
+  static constexpr int NRING = ROW ? 1 : (TX + 2) + TY;  // red ring-1 cells per plane
+};
+
+// LDS coordinates of halo cell h (everything of the HY x HX plane outside the tile)
+template <int TX, int TY>
+__device__ __forceinline__ void halo_cell(int h, int& hy, int& hx) {
+  using SS = SweepShape<TX, TY>;
+  if constexpr (SS::ROW) {
+    hy = 0;
+    hx = (h < 2) ? h : TX + h;  // 0, 1, TX + 2, TX + 3
+  } else {
+    constexpr int HX = SS::HX;
+    if (h < 2 * HX) { hy = h / HX; hx = h - hy * HX; return; }
+    h -= 2 * HX;
+    if (h < 2 * HX) { hy = TY + 2 + h / HX; hx = h - (h / HX) * HX; return; }
+    h -= 2 * HX;
+    hy = 2 + (h >> 2);
+    const int c = h & 3;
+    hx = (c < 2) ? c : TX + c;  // 0, 1, TX + 2, TX + 3
+  }
+}
+
+// LDS coordinates of the m-th red cell of the 1-cell ring at plane p
+template <int TX, int TY>
+__device__ __forceinline__ void ring_red_cell(int m, int x0, int y0, int p, int& hy, int& hx) {
+  using SS = SweepShape<TX, TY>;
+  if constexpr (SS::ROW) {
+    // cells x0 - 1 and x0 + TX of the single row; exactly one is red
+    hy = 0;
+    hx = ((x0 - 1 + p) & 1) == 0 ? 1 : TX + 2;
+    (void)m; (void)y0;
+  } else {
+    constexpr int HALF = (TX + 2) / 2;
+    if (m < 2 * HALF) {  // top (hy = 1) or bottom (hy = TY + 2) row, hx in 1 .. TX + 2
+      hy = (m < HALF) ? 1 : TY + 2;
+      const int k = (m < HALF) ? m : m - HALF;
+      const int s = (x0 + y0 - 2 + hy + p) & 1;  // parity hx must have
+      hx = (s ? 1 : 2) + 2 * k;
+    } else {  // left (hx = 1) or right (hx = TX + 2) column, hy in 2 .. TY + 1
+      const int k = m - 2 * HALF;
+      const int HC = TY / 2;
+      hx = (k < HC) ? 1 : TX + 2;
+      const int kk = (k < HC) ? k : k - HC;
+      const int s = (x0 - 2 + hx + y0 - 2 + p) & 1;
+      hy = 2 + s + 2 * kk;
+    }
+  }
+}
+
+// Work split of the 1-cell ring and the halo over the waves of a block, so
+// that every wave gets the same share.
+template <int N, int NT>
+struct WaveSplit {
+  static constexpr int NW = NT / 64;
+  static constexpr int PER = (N + NW - 1) / NW;  // items per wave (<= 64 by construction)
+  static __device__ __forceinline__ int item(int tid) {  // -1: none
+    const int w = tid >> 6, l = tid & 63;
+    const int m = w * PER + l;
+    return (l < PER && m < N) ? m : -1;
+  }
+};
+
+// Gauss-Seidel value of one cell in correction form, x + (b - A x) / d:
+// the residual is accumulated from neighbour differences (exact for close
+// values), which keeps the FP32 rounding floor low when x is much larger
+// than b (small alpha).  Neighbours are taken left, right, up, down, z-1,
+// z+1 with explicit fused multiply-adds, so that a ring cell and its owner
+// compute it alike.  inv == 0 (no diagonal) gives 0.
+template <typename C, bool ROW>
+__device__ __forceinline__ C relax(C x, C b, C alpha, C wl, C nl, C wr, C nr, C wu, C nu, C wd, C nd, C wzm, C nzm,
+                                   C wzp, C nzp, C inv) {
+  C r = fmac(-alpha, x, b);
+  r = fmac(wl, nl - x, r);
+  r = fmac(wr, nr - x, r);
+  if (!ROW) {
+    r = fmac(wu, nu - x, r);
+    r = fmac(wd, nd - x, r);
+  }
+  r = fmac(wzm, nzm - x, r);
+  r = fmac(wzp, nzp - x, r);
+  return inv != (C)0 ? fmac(r, inv, x) : (C)0;
+}
+
+template <typename S, int TX, int TY, bool FP, bool VEC>
+__global__ void __launch_bounds__(TX * TY / 2)
+k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+           const S* __restrict__ xin, S* __restrict__ xout, const S* __restrict__ bin,
+           const S* __restrict__ ec, int pmode, int order) {
+  using C = typename Ty<S>::C;
+  using SS = SweepShape<TX, TY>;
+  constexpr int NT = SS::NT, YO = SS::YO, HX = SS::HX, HY = SS::HY, NHR = SS::NHR;
+  constexpr int PLANE = HX * HY;
+  constexpr bool ROW = SS::ROW;
+  using Ring = WaveSplit<SS::NRING, NT>;
+  static_assert(Ring::PER <= 64, "ring share per wave");
+  // four planes, then one slot per thread that takes the masked writes of
+  // threads without a ring cell
+  __shared__ C X[4 * PLANE + NT];
+
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false, order);
+  const GridDesc& G = grids[t.g];
+  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
+  const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
+  const int64_t pl = (int64_t)px * ny;
+  const S* xg = xin + G.off;
+  const S* bg = bin + G.off;
+  S* xo = xout + G.off;
+  const int tid = threadIdx.x;
+  const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
+
+  // ---- own pair (gx, gx + 1) of row gy
+  const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
+  const int gx = x0 + 2 * pxl, gy = y0 + tyl;
+  const bool rowok = gy < ny;
+  const bool vA = rowok && gx < nx, vB = rowok && gx + 1 < nx;
+  const int lo = (YO + tyl) * HX + 2 + 2 * pxl;  // LDS index of gx inside a plane
+  const int own = gy * px + gx;                 // element offset inside a plane (< 2^28)
+  const C wU = (gy > 0) ? wy : (C)0, wD = (gy + 1 < ny) ? wy : (C)0;
+  // per plane parity par = p & 1 the red cell of the pair is at position cp = (gy + par) & 1
+  int offO[2], offY[2];
+  C wO[2], wP[2], wL[2], wR[2], invI[2], invE[2];
+  bool vR[2];
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    const int cp = (gy + par) & 1;
+    offO[par] = cp ? lo + 2 : lo - 1;
+    offY[par] = lo + cp;
+    wO[par] = (cp ? (gx + 2 < nx) : (gx > 0)) ? wx : (C)0;
+    wP[par] = (cp ? true : vB) ? wx : (C)0;
+    vR[par] = cp ? vB : vA;  // the red cell of plane p (and black cell of plane p - 1) exists
+    // left, right, up, down, then z: the order the 1-cell ring uses too, so
+    // that a ring cell and its owner round alike and every tile shape gives
+    // the same values
+    wL[par] = cp ? wP[par] : wO[par];  // left neighbour: the pair partner when the cell is gx + 1
+    wR[par] = cp ? wO[par] : wP[par];
+    const C dxy = alpha + wL[par] + wR[par] + wU + wD;
+    // diagonal inside the z-range and on its first or last plane
+    const C wz1 = nz > 1 ? wz : (C)0;
+    const C di = (dxy + wz1) + wz1, de = dxy + wz1;
+    invI[par] = di > (C)0 ? (C)1 / di : (C)0;
+    invE[par] = de > (C)0 ? (C)1 / de : (C)0;
+  }
+
+  // ---- halo cells of this thread (loaded every plane)
+  int hoff[NHR], hg[NHR];
+  bool hv[NHR], hs[NHR];
+#pragma unroll
+  for (int k = 0; k < NHR; ++k) {
+    int h;
+    if (k < NHR - 1) {
+      h = tid + NT * k;
+    } else {  // last round: spread the remainder over the waves
+      const int m = WaveSplit<SS::NHALO - NT * (NHR - 1), NT>::item(tid);
+      h = m < 0 ? -1 : NT * k + m;
+    }
+    int hy = 0, hx = 0;
+    if (h >= 0) halo_cell<TX, TY>(h, hy, hx);
+    const int cx = x0 - 2 + hx, cy = y0 - YO + hy;
+    hs[k] = h >= 0;
+    hv[k] = h >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    hoff[k] = hy * HX + hx;
+    hg[k] = hv[k] ? cy * px + cx : 0;
+  }
+
+  // ---- ring red cell of this thread, for each plane parity
+  const int rm = Ring::item(tid);
+  int ro[2], rg[2];
+  bool rv[2];
+  C rwl[2], rwr[2], rwu[2], rwd[2], rinvI[2], rinvE[2];
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    int hy = 0, hx = 0;
+    if (rm >= 0) ring_red_cell<TX, TY>(rm, x0, y0, par, hy, hx);
+    const int cx = x0 - 2 + hx, cy = y0 - YO + hy;
+    rv[par] = rm >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    // a thread without a ring cell relaxes its own cell's position as a
+    // stand-in (in-plane neighbours inside the LDS plane) and writes the
+    // result to its dummy slot
+    ro[par] = rm >= 0 ? hy * HX + hx : lo;
+    rg[par] = rv[par] ? cy * px + cx : 0;
+    rwl[par] = cx > 0 ? wx : (C)0;
+    rwr[par] = cx < nx - 1 ? wx : (C)0;
+    rwu[par] = cy > 0 ? wy : (C)0;
+    rwd[par] = cy < ny - 1 ? wy : (C)0;
+    const C dxy = alpha + rwl[par] + rwr[par] + rwu[par] + rwd[par];
+    const C wz1 = nz > 1 ? wz : (C)0;
+    const C di = (dxy + wz1) + wz1, de = dxy + wz1;
+    rinvI[par] = di > (C)0 ? (C)1 / di : (C)0;
+    rinvE[par] = de > (C)0 ? (C)1 / de : (C)0;
+  }
+
+  // ---- plane loads: x pair + halo (registers), b pair, ring b.  Two planes
+  // of x and b are in flight while a plane is relaxed; a loaded value is
+  // first touched one or two planes later, so the loads overlap the updates.
+  // Values are kept raw (storage format) until stash / split: converting a
+  // 16-bit value right after its load would make the wave wait for it there.
+  // The plain loads are issued unconditionally from clamped, always valid
+  // addresses and masked when used: with no branch around them the compiler
+  // can wait for the oldest plane only, keeping the next one in flight.
+  struct XSet {
+    Raw2<S> p;                      // own pair
+    Raw<S> h[NHR];                  // halo cells
+    C ea = 0, eb = 0, eh[NHR] = {};  // fused prolongation (FP)
+  };
+  auto plane_ptr = [&](const S* base, int q) { return base + (int64_t)min(max(q, 0), nz - 1) * pl; };
+  auto fetch_x = [&](int q, XSet& o) {
+    const S* P = plane_ptr(xg, q);
+    if (VEC) {
+      ld_raw2(P + (vA ? own : 0), true, true, o.p);
+    } else {
+      o.p = Raw2<S>();
+      if (vA) ld_raw2(P + own, false, vB, o.p);
+    }
+#pragma unroll
+    for (int k = 0; k < NHR; ++k) ld_raw(P + hg[k], o.h[k]);
+    if (FP) {
+      o.ea = o.eb = (C)0;
+#pragma unroll
+      for (int k = 0; k < NHR; ++k) o.eh[k] = (C)0;
+      if (q >= 0 && q < nz) {
+        if (vA) prolong_pair<S>(ec, G, gx, gy, q, pmode, o.ea, o.eb);
+#pragma unroll
+        for (int k = 0; k < NHR; ++k)
+          if (hv[k]) o.eh[k] = prolong_value<S>(ec, G, x0 - 2 + hoff[k] % HX, y0 - YO + hoff[k] / HX, q, pmode);
+      }
+    }
+  };
+  auto xa = [&](const XSet& o, int q) -> C {
+    const C v = FP ? raw_ca(o.p) + o.ea : raw_ca(o.p);
+    return (q >= 0 && q < nz && vA) ? v : (C)0;
+  };
+  auto xb = [&](const XSet& o, int q) -> C {
+    const C v = FP ? raw_cb(o.p) + o.eb : raw_cb(o.p);
+    return (q >= 0 && q < nz && vB) ? v : (C)0;
+  };
+  auto stash = [&](int q, const XSet& o) {
+    C* P = X + (q & 3) * PLANE;
+    const bool okq = q >= 0 && q < nz;
+    P[lo] = xa(o, q);
+    P[lo + 1] = xb(o, q);
+#pragma unroll
+    for (int k = 0; k < NHR; ++k)
+      if (hs[k]) P[hoff[k]] = (okq && hv[k]) ? (FP ? raw_c(o.h[k]) + o.eh[k] : raw_c(o.h[k])) : (C)0;
+  };
+  // b pair of plane q (memory order, raw; masked by bA / bB)
+  auto fetch_b = [&](int q, Raw2<S>& r) {
+    const S* P = plane_ptr(bg, q);
+    if (VEC) {
+      ld_raw2(P + (vA ? own : 0), true, true, r);
+    } else {
+      r = Raw2<S>();
+      if (vA) ld_raw2(P + own, false, vB, r);
+    }
+  };
+  auto bA = [&](const Raw2<S>& r, int q) -> C { return (q >= 0 && q < nz && vA) ? raw_ca(r) : (C)0; };
+  auto bB = [&](const Raw2<S>& r, int q) -> C { return (q >= 0 && q < nz && vB) ? raw_cb(r) : (C)0; };
+  auto ring_b = [&](int q) -> Raw<S> {
+    Raw<S> r;
+    ld_raw(plane_ptr(bg, q) + rg[q & 1], r);
+    return r;
+  };
+  // pair (in memory order) -> (red, black) of plane q
+  auto split = [&](int q, C a, C b, C& r, C& k) {
+    const bool cp = ((gy + q) & 1) != 0;
+    b = vB ? b : (C)0;
+    r = cp ? b : a;
+    k = cp ? a : b;
+  };
+
+  // column registers (red R / black K of planes p-2 .. p+1), b of planes p-1, p
+  C Rm2 = 0, Km2 = 0, Rm1, Km1, R0, K0, Rp1, Kp1;
+  C bRm1, bKm1, bR0, bK0;
+  // Loads in flight sit in two slots each (plane r in slot (r - pfirst) & 1)
+  // and the loop is unrolled by two, so that no in-flight register is ever
+  // copied: a copy would make the wave wait for the newest loads.
+  XSet S0, S1;
+  Raw2<S> B0, B1;
+  Raw<S> RB0, RB1;
+  const int pfirst = max(q0 - 1, 0);
+  const int plast = (q1 < nz) ? q1 : nz;  // p == nz: black of the last plane only
+  {
+    XSet t0;
+    Raw2<S> tb;
+    fetch_x(pfirst - 1, t0); stash(pfirst - 1, t0); split(pfirst - 1, xa(t0, pfirst - 1), xb(t0, pfirst - 1), Rm1, Km1);
+    fetch_x(pfirst, t0);     stash(pfirst, t0);     split(pfirst, xa(t0, pfirst), xb(t0, pfirst), R0, K0);
+    fetch_x(pfirst + 1, t0); stash(pfirst + 1, t0); split(pfirst + 1, xa(t0, pfirst + 1), xb(t0, pfirst + 1), Rp1, Kp1);
+    fetch_b(pfirst - 1, tb); split(pfirst - 1, bA(tb, pfirst - 1), bB(tb, pfirst - 1), bRm1, bKm1);
+    fetch_b(pfirst, tb);     split(pfirst, bA(tb, pfirst), bB(tb, pfirst), bR0, bK0);
+  }
+  RB0 = ring_b(pfirst);
+  RB1 = ring_b(pfirst + 1);
+  fetch_x(pfirst + 2, S0);
+  fetch_x(pfirst + 3, S1);
+  fetch_b(pfirst + 1, B1);
+  fetch_b(pfirst + 2, B0);
+
+  // one plane step: red of plane p, black of plane p - 1, then plane p + 2
+  // enters LDS and the loads of planes p + 4 (x), p + 3 (b), p + 2 (ring b)
+  // go out into the slots just consumed
+  auto step = [&](auto PC, int p, XSet& XS, Raw2<S>& BS, Raw<S>& RBS) {
+    constexpr int par = decltype(PC)::value;  // p & 1, fixed per unrolled step
+    __syncthreads();
+    if (p < nz) {
+      // ---- red cells of plane p: the pair's red cell and the ring cell,
+      // both computed by every thread (masked), so that their LDS reads
+      // issue together
+      C* P = X + (p & 3) * PLANE;
+      const C* Pm = X + ((p - 1) & 3) * PLANE;
+      const C* Pp = X + ((p + 1) & 3) * PLANE;
+      const C wzm = p > 0 ? wz : (C)0, wzp = p < nz - 1 ? wz : (C)0;
+      const bool edge = p == 0 || p == nz - 1;
+      const bool cp = ((gy + p) & 1) != 0;  // red cell on the pair's right
+      const C vo = P[offO[par]];
+      const C up = ROW ? (C)0 : P[offY[par] - HX], dn = ROW ? (C)0 : P[offY[par] + HX];
+      const int o = ro[par];
+      const C rx = P[o], rl = P[o - 1], rr = P[o + 1];
+      const C ru = ROW ? (C)0 : P[o - HX], rd = ROW ? (C)0 : P[o + HX];
+      const C rzm = Pm[o], rzp = Pp[o];
+      const C nv = relax<C, ROW>(R0, bR0, alpha, wL[par], cp ? K0 : vo, wR[par], cp ? vo : K0, wU, up, wD, dn, wzm, Km1,
+                                 wzp, Kp1, edge ? invE[par] : invI[par]);
+      R0 = vR[par] ? nv : (C)0;
+      P[offY[par]] = R0;
+      const C rb = (p >= 0 && rv[par]) ? raw_c(RBS) : (C)0;
+      const C rn = relax<C, ROW>(rx, rb, alpha, rwl[par], rl, rwr[par], rr, rwu[par], ru, rwd[par], rd, wzm, rzm,
+                                 wzp, rzp, edge ? rinvE[par] : rinvI[par]);
+      *(rv[par] ? P + o : X + 4 * PLANE + tid) = rn;
+    }
+    // no barrier here: the black cells of plane p - 1 read only plane
+    // p - 1's buffer, whose red cells were written in the previous step
+    const int q = p - 1;
+    if (q >= q0 && q < q1) {
+      // ---- black cells of plane q = p - 1 (same position as the red cell of plane p)
+      const C* P = X + (q & 3) * PLANE;
+      const C wzm = q > 0 ? wz : (C)0, wzp = q < nz - 1 ? wz : (C)0;
+      const bool edge = q == 0 || q == nz - 1;
+      const bool cq = ((gy + q) & 1) != 0;  // red position of plane q
+      // the black cell sits on the pair's right when the red one is on its left
+      const C vo = P[offO[par]];
+      const C up = ROW ? (C)0 : P[offY[par] - HX], dn = ROW ? (C)0 : P[offY[par] + HX];
+      const C nv = relax<C, ROW>(Km1, bKm1, alpha, wL[par], cq ? vo : Rm1, wR[par], cq ? Rm1 : vo, wU, up, wD, dn, wzm,
+                                 Rm2, wzp, R0, edge ? invE[par] : invI[par]);
+      Km1 = vR[par] ? nv : (C)0;
+      if (vA) st2(xo + (int64_t)q * pl + own, VEC, vB, cq ? Km1 : Rm1, cq ? Rm1 : Km1);
+    }
+    stash(p + 2, XS);
+    Rm2 = Rm1; Km2 = Km1; Rm1 = R0; Km1 = K0; R0 = Rp1; K0 = Kp1;
+    split(p + 2, xa(XS, p + 2), xb(XS, p + 2), Rp1, Kp1);
+    bRm1 = bR0; bKm1 = bK0;
+    split(p + 1, bA(BS, p + 1), bB(BS, p + 1), bR0, bK0);
+    // next planes (clamped reads past the chunk's end are harmless and keep
+    // the loop free of a branch around the loads)
+    fetch_x(p + 4, XS);
+    fetch_b(p + 3, BS);
+    ld_raw(plane_ptr(bg, p + 2) + rg[par], RBS);  // ring b of plane p + 2 (same parity)
+  };
+  using E0 = std::integral_constant<int, 0>;
+  using E1 = std::integral_constant<int, 1>;
+  int p = pfirst;
+  if ((pfirst & 1) == 0) {
+    for (; p + 1 <= plast; p += 2) {
+      step(E0{}, p, S0, B1, RB0);
+      step(E1{}, p + 1, S1, B0, RB1);
+    }
+    if (p <= plast) step(E0{}, p, S0, B1, RB0);
+  } else {
+    for (; p + 1 <= plast; p += 2) {
+      step(E1{}, p, S0, B1, RB0);
+      step(E0{}, p + 1, S1, B0, RB1);
+    }
+    if (p <= plast) step(E1{}, p, S0, B1, RB0);
+  }
+}
+
+// ============================================================ launchers
+
+template <typename T, bool FP, bool VEC>
+static void sweep_launch3(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
+                          hipStream_t st) {
+  if (g.row) {
+    hipLaunchKernelGGL((k_rb_sweep<T, SWR_TX, 1, FP, VEC>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st,
+                       g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec,
+                       pmode, g.order);
+  } else {
+#define SWEEP_TILE(TX, TY)                                                                                     \
+  hipLaunchKernelGGL((k_rb_sweep<T, TX, TY, FP, VEC>), dim3((unsigned)g.nblocks), dim3(TX * TY / 2), 0, st,    \
+                     g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec, pmode, \
+                     g.order)
+    if (FP || g.tile == 0) {
+      SWEEP_TILE(64, 8);
+    } else if constexpr (!FP) {  // the fused prolongation exists for the 64 x 8 tile only
+      switch (g.tile) {
+        case 1: SWEEP_TILE(128, 8); break;
+        case 2: SWEEP_TILE(64, 16); break;
+        default: SWEEP_TILE(128, 16); break;
+      }
+    }
+#undef SWEEP_TILE
+  }
+}
+
+template <typename T>
+static void sweep_launch(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
+                         hipStream_t st) {
+  // the library's arrays are pair-aligned (g.vec); a caller's odd-width arrays are not
+  if (ec) sweep_launch3<T, true, true>(g, xin, xout, b, ec, pmode, st);
+  else if (g.vec) sweep_launch3<T, false, true>(g, xin, xout, b, ec, pmode, st);
+  else sweep_launch3<T, false, false>(g, xin, xout, b, ec, pmode, st);
+}
+
+hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
+                           const void* ec, int pmode, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L(T) sweep_launch<T>(g, xin, xout, b, ec, pmode, st)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return last();
+}
+
+}  // namespace gd

@@ -12,570 +12,9 @@
 // All stencils are evaluated in difference form, sum_nb w (x_nb - x_c), which
 // keeps the rounding error proportional to the local variation instead of
 // the magnitude of x.
-#include <cstdlib>
-#include <type_traits>
-#include "gd_launch.h"
+#include "gd_kcommon.h"
 
 namespace gd {
-
-// ---------------------------------------------------------------- helpers
-
-// Deterministic block sum of a double (wave shuffles, then the waves in
-// order).  Result valid on thread 0.  `red` must hold blockDim/64 doubles.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
-  return t;
-}
-
-struct Tile {
-  int g, x0, y0, z0, z1;
-  int64_t bid;  // logical block index (per-block partial sums go here)
-};
-
-// Logical block index.  Work-groups go to the 8 XCDs round-robin and each
-// XCD has its own L2.  Order 1 hands XCD x a contiguous run of tiles, so
-// that the halos of neighbouring tiles are fetched into one L2 (used by the
-// relaxation of slice batches); order 0 is the plain order.
-__device__ __forceinline__ int64_t xcd_block(int order = 0) {
-  if (order != 1) return blockIdx.x;
-  // XCD x = b mod 8 takes the contiguous run [x q + min(x, r), ...) of
-  // logical blocks (q = n / 8, r = n mod 8): a bijection of [0, n)
-  const int64_t b = blockIdx.x, n = gridDim.x;
-  const int64_t q = n >> 3, r = n & 7, x = b & 7;
-  return x * q + (x < r ? x : r) + (b >> 3);
-}
-
-// Decode blockIdx.x into (grid, tile, z-range) for tx x ty tiles over the
-// grid's own size (coarse = false) or its child's size (coarse = true).
-__device__ __forceinline__ Tile decode_tile(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0,
-                                            int ngrids, int zlen, int tx_, int ty_, bool coarse,
-                                            int order = 0) {
-  Tile t;
-  const int64_t bid = xcd_block(order);
-  t.bid = bid;
-  t.g = find_grid(block0, ngrids, bid);
-  const GridDesc& G = grids[t.g];
-  const int nx = coarse ? G.cnx : G.nx, ny = coarse ? G.cny : G.ny, nz = coarse ? G.cnz : G.nz;
-  const int64_t local = bid - block0[t.g];
-  const int tx = (nx + tx_ - 1) / tx_, ty = (ny + ty_ - 1) / ty_;
-  const int64_t txy = (int64_t)tx * ty;
-  const int zc = (int)(local / txy);
-  const int r = (int)(local - (int64_t)zc * txy);
-  t.x0 = (r % tx) * tx_;
-  t.y0 = (r / tx) * ty_;
-  t.z0 = zc * zlen;
-  t.z1 = min(t.z0 + zlen, nz);
-  return t;
-}
-
-// Cell-centred linear up-sampling along one axis: the fine cell i of a
-// halved axis takes 3/4 of its parent i/2 and 1/4 of the nearer coarse
-// neighbour; where that neighbour is outside the grid the parent takes weight
-// 1 (mirror boundary).  A kept axis (f == 1) maps i to i with weight 1.
-// two == false means the single index a carries weight 1.
-__device__ __forceinline__ bool lin_idx(int i, int f, int nc, int& a, int& b) {
-  if (f == 1) { a = b = i; return false; }
-  a = i >> 1;
-  b = (i & 1) ? a + 1 : a - 1;
-  if (b < 0 || b >= nc) { b = a; return false; }
-  return true;
-}
-
-template <typename C>
-__device__ __forceinline__ C lin_mix(bool two, C va, C vb) {
-  return two ? (C)0.75 * va + (C)0.25 * vb : va;
-}
-
-// Value of the up-sampled coarse correction at fine cell (i, j, k) of grid G:
-// x first, then y, then z (prolong_pair evaluates the same expression).
-template <typename S>
-__device__ __forceinline__ typename Ty<S>::C prolong_value(const S* __restrict__ ec, const GridDesc& G,
-                                                          int i, int j, int k, int mode) {
-  using C = typename Ty<S>::C;
-  const S* e = ec + G.coff;
-  const int64_t cpl = (int64_t)G.cpx * G.cny;
-  if (mode == 1) {
-    return Ty<S>::ld(e + (int64_t)(k / G.fz) * cpl + (int64_t)(j / G.fy) * G.cpx + (i / G.fx));
-  }
-  int ia, ib, ja, jb, ka, kb;
-  const bool tx = lin_idx(i, G.fx, G.cnx, ia, ib);
-  const bool ty = lin_idx(j, G.fy, G.cny, ja, jb);
-  const bool tz = lin_idx(k, G.fz, G.cnz, ka, kb);
-  auto row = [&](int kk, int jj) {
-    const S* q = e + (int64_t)kk * cpl + (int64_t)jj * G.cpx;
-    return lin_mix<C>(tx, Ty<S>::ld(q + ia), tx ? Ty<S>::ld(q + ib) : (C)0);
-  };
-  auto plane = [&](int kk) { return lin_mix<C>(ty, row(kk, ja), ty ? row(kk, jb) : (C)0); };
-  return lin_mix<C>(tz, plane(ka), tz ? plane(kb) : (C)0);
-}
-
-// The same for the x-pair (i, i + 1), i even, of the library's arrays (child
-// pitch a multiple of 4): the pair shares its coarse rows.
-template <typename S>
-__device__ __forceinline__ void prolong_pair(const S* __restrict__ ec, const GridDesc& G, int i, int j, int k,
-                                             int mode, typename Ty<S>::C& va, typename Ty<S>::C& vb) {
-  using C = typename Ty<S>::C;
-  const S* e = ec + G.coff;
-  const int64_t cpl = (int64_t)G.cpx * G.cny;
-  if (mode == 1) {
-    const S* r = e + (int64_t)(k / G.fz) * cpl + (int64_t)(j / G.fy) * G.cpx;
-    va = Ty<S>::ld(r + i / G.fx);
-    vb = Ty<S>::ld(r + (i + 1) / G.fx);
-    return;
-  }
-  int ja, jb, ka, kb;
-  const bool ty = lin_idx(j, G.fy, G.cny, ja, jb);
-  const bool tz = lin_idx(k, G.fz, G.cnz, ka, kb);
-  int iaA, ibA, iaB, ibB;
-  const bool txA = lin_idx(i, G.fx, G.cnx, iaA, ibA);
-  const bool txB = lin_idx(i + 1, G.fx, G.cnx, iaB, ibB);
-  auto rows = [&](int kk, int jj, C& ra, C& rb) {
-    const S* q = e + (int64_t)kk * cpl + (int64_t)jj * G.cpx;
-    if (G.fx == 1) {
-      ld2(q + i, true, true, ra, rb);  // kept axis: weight 1 on i and i + 1
-    } else {
-      const C c0 = Ty<S>::ld(q + iaA);  // the pair's common parent
-      ra = lin_mix<C>(txA, c0, txA ? Ty<S>::ld(q + ibA) : (C)0);
-      rb = lin_mix<C>(txB, c0, txB ? Ty<S>::ld(q + ibB) : (C)0);
-    }
-  };
-  auto planes = [&](int kk, C& pa, C& pb) {
-    C a0, b0, a1 = 0, b1 = 0;
-    rows(kk, ja, a0, b0);
-    if (ty) rows(kk, jb, a1, b1);
-    pa = lin_mix<C>(ty, a0, a1);
-    pb = lin_mix<C>(ty, b0, b1);
-  };
-  C a0, b0, a1 = 0, b1 = 0;
-  planes(ka, a0, b0);
-  if (tz) planes(kb, a1, b1);
-  va = lin_mix<C>(tz, a0, a1);
-  vb = lin_mix<C>(tz, b0, b1);
-}
-
-// ------------------------------------------------------- red-black sweep
-//
-// One complete red-black Gauss-Seidel sweep (Sec. 4.1, multi-coloured GS),
-// out of place: reads x_in, writes x_out.  A block owns a TX x TY column of
-// the grid and marches along z.  Thread t owns the x-pair (x0 + 2 (t mod
-// TX/2), y0 + t / (TX/2)) and its two neighbours along x: in every plane one
-// of the pair is red and the other black, and the z-neighbours of a cell are
-// cells of the same column, so each thread keeps its column of planes
-// p-2 .. p+2 in registers and only the in-plane neighbours go through LDS
-// (four planes, with a 2-cell halo ring loaded by the threads in turn).
-//   step p:  barrier | red cells of plane p (own pair and the 1-cell ring
-//            around the tile, from old black values), written to plane p's
-//            LDS buffer | black cells of plane p - 1 (from the new red values
-//            of planes p-2..p: in-plane ones from plane p - 1's buffer,
-//            written in the previous step), plane p - 1 written to memory,
-//            plane p + 2 enters LDS (the buffer plane p - 2 used)
-// One barrier per plane suffices: within a step no buffer is both written
-// and read (red cells of plane p are written, only black cells of plane p
-// and planes p +- 1 are read; plane p - 1 is read; plane p + 2 is written).
-// Recomputing the red ring makes every tile independent of its neighbours,
-// so blocks never exchange data and the sweep equals the sequential
-// definition exactly.  Every thread relaxes its red cell and a ring cell in
-// each plane (a thread without a ring cell relaxes a stand-in and writes it
-// to a slot of its own), so that the LDS reads of both issue together, and
-// the plane parity is a compile-time argument of the unrolled step: the
-// per-parity weights and inverse diagonals stay in registers.  When
-// e_coarse != NULL the up-sampled coarse correction is added to x while it
-// is loaded (fused prolongation).
-// TY == 1 is the row form for grids with ny == 1 (2-D slices).
-
-template <int TX, int TY>
-struct SweepShape {
-  static constexpr bool ROW = (TY == 1);
-  static constexpr int NT = TX * TY / 2;                 // threads: one x-pair each
-  static constexpr int YO = ROW ? 0 : 2;                 // tile row 0 inside the LDS plane
-  static constexpr int HX = TX + 4, HY = ROW ? 1 : TY + 4;
-  static constexpr int NHALO = HX * HY - TX * TY;        // halo cells per plane
-  static constexpr int NHR = (NHALO + NT - 1) / NT;      // halo cells per thread
-  static constexpr int NRING = ROW ? 1 : (TX + 2) + TY;  // red ring-1 cells per plane
-};
-
-// LDS coordinates of halo cell h (everything of the HY x HX plane outside the tile)
-template <int TX, int TY>
-__device__ __forceinline__ void halo_cell(int h, int& hy, int& hx) {
-  using SS = SweepShape<TX, TY>;
-  if constexpr (SS::ROW) {
-    hy = 0;
-    hx = (h < 2) ? h : TX + h;  // 0, 1, TX + 2, TX + 3
-  } else {
-    constexpr int HX = SS::HX;
-    if (h < 2 * HX) { hy = h / HX; hx = h - hy * HX; return; }
-    h -= 2 * HX;
-    if (h < 2 * HX) { hy = TY + 2 + h / HX; hx = h - (h / HX) * HX; return; }
-    h -= 2 * HX;
-    hy = 2 + (h >> 2);
-    const int c = h & 3;
-    hx = (c < 2) ? c : TX + c;  // 0, 1, TX + 2, TX + 3
-  }
-}
-
-// LDS coordinates of the m-th red cell of the 1-cell ring at plane p
-template <int TX, int TY>
-__device__ __forceinline__ void ring_red_cell(int m, int x0, int y0, int p, int& hy, int& hx) {
-  using SS = SweepShape<TX, TY>;
-  if constexpr (SS::ROW) {
-    // cells x0 - 1 and x0 + TX of the single row; exactly one is red
-    hy = 0;
-    hx = ((x0 - 1 + p) & 1) == 0 ? 1 : TX + 2;
-    (void)m; (void)y0;
-  } else {
-    constexpr int HALF = (TX + 2) / 2;
-    if (m < 2 * HALF) {  // top (hy = 1) or bottom (hy = TY + 2) row, hx in 1 .. TX + 2
-      hy = (m < HALF) ? 1 : TY + 2;
-      const int k = (m < HALF) ? m : m - HALF;
-      const int s = (x0 + y0 - 2 + hy + p) & 1;  // parity hx must have
-      hx = (s ? 1 : 2) + 2 * k;
-    } else {  // left (hx = 1) or right (hx = TX + 2) column, hy in 2 .. TY + 1
-      const int k = m - 2 * HALF;
-      const int HC = TY / 2;
-      hx = (k < HC) ? 1 : TX + 2;
-      const int kk = (k < HC) ? k : k - HC;
-      const int s = (x0 - 2 + hx + y0 - 2 + p) & 1;
-      hy = 2 + s + 2 * kk;
-    }
-  }
-}
-
-// Work split of the 1-cell ring and the halo over the waves of a block, so
-// that every wave gets the same share.
-template <int N, int NT>
-struct WaveSplit {
-  static constexpr int NW = NT / 64;
-  static constexpr int PER = (N + NW - 1) / NW;  // items per wave (<= 64 by construction)
-  static __device__ __forceinline__ int item(int tid) {  // -1: none
-    const int w = tid >> 6, l = tid & 63;
-    const int m = w * PER + l;
-    return (l < PER && m < N) ? m : -1;
-  }
-};
-
-// Gauss-Seidel value of one cell in correction form, x + (b - A x) / d:
-// the residual is accumulated from neighbour differences (exact for close
-// values), which keeps the FP32 rounding floor low when x is much larger
-// than b (small alpha).  Neighbours are taken left, right, up, down, z-1,
-// z+1 with explicit fused multiply-adds, so that a ring cell and its owner
-// compute it alike.  inv == 0 (no diagonal) gives 0.
-template <typename C>
-__device__ __forceinline__ C fmac(C a, C b, C c) {
-  if constexpr (sizeof(C) == 8) return __builtin_fma(a, b, c);
-  else return __builtin_fmaf(a, b, c);
-}
-template <typename C, bool ROW>
-__device__ __forceinline__ C relax(C x, C b, C alpha, C wl, C nl, C wr, C nr, C wu, C nu, C wd, C nd, C wzm, C nzm,
-                                   C wzp, C nzp, C inv) {
-  C r = fmac(-alpha, x, b);
-  r = fmac(wl, nl - x, r);
-  r = fmac(wr, nr - x, r);
-  if (!ROW) {
-    r = fmac(wu, nu - x, r);
-    r = fmac(wd, nd - x, r);
-  }
-  r = fmac(wzm, nzm - x, r);
-  r = fmac(wzp, nzp - x, r);
-  return inv != (C)0 ? fmac(r, inv, x) : (C)0;
-}
-
-template <typename S, int TX, int TY, bool FP, bool VEC>
-__global__ void __launch_bounds__(TX * TY / 2)
-k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
-           const S* __restrict__ xin, S* __restrict__ xout, const S* __restrict__ bin,
-           const S* __restrict__ ec, int pmode, int order) {
-  using C = typename Ty<S>::C;
-  using SS = SweepShape<TX, TY>;
-  constexpr int NT = SS::NT, YO = SS::YO, HX = SS::HX, HY = SS::HY, NHR = SS::NHR;
-  constexpr int PLANE = HX * HY;
-  constexpr bool ROW = SS::ROW;
-  using Ring = WaveSplit<SS::NRING, NT>;
-  static_assert(Ring::PER <= 64, "ring share per wave");
-  // four planes, then one slot per thread that takes the masked writes of
-  // threads without a ring cell
-  __shared__ C X[4 * PLANE + NT];
-
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false, order);
-  const GridDesc& G = grids[t.g];
-  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
-  const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
-  const int64_t pl = (int64_t)px * ny;
-  const S* xg = xin + G.off;
-  const S* bg = bin + G.off;
-  S* xo = xout + G.off;
-  const int tid = threadIdx.x;
-  const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
-
-  // ---- own pair (gx, gx + 1) of row gy
-  const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
-  const int gx = x0 + 2 * pxl, gy = y0 + tyl;
-  const bool rowok = gy < ny;
-  const bool vA = rowok && gx < nx, vB = rowok && gx + 1 < nx;
-  const int lo = (YO + tyl) * HX + 2 + 2 * pxl;  // LDS index of gx inside a plane
-  const int own = gy * px + gx;                 // element offset inside a plane (< 2^28)
-  const C wU = (gy > 0) ? wy : (C)0, wD = (gy + 1 < ny) ? wy : (C)0;
-  // per plane parity par = p & 1 the red cell of the pair is at position cp = (gy + par) & 1
-  int offO[2], offY[2];
-  C wO[2], wP[2], wL[2], wR[2], invI[2], invE[2];
-  bool vR[2];
-#pragma unroll
-  for (int par = 0; par < 2; ++par) {
-    const int cp = (gy + par) & 1;
-    offO[par] = cp ? lo + 2 : lo - 1;
-    offY[par] = lo + cp;
-    wO[par] = (cp ? (gx + 2 < nx) : (gx > 0)) ? wx : (C)0;
-    wP[par] = (cp ? true : vB) ? wx : (C)0;
-    vR[par] = cp ? vB : vA;  // the red cell of plane p (and black cell of plane p - 1) exists
-    // left, right, up, down, then z: the order the 1-cell ring uses too, so
-    // that a ring cell and its owner round alike and every tile shape gives
-    // the same values
-    wL[par] = cp ? wP[par] : wO[par];  // left neighbour: the pair partner when the cell is gx + 1
-    wR[par] = cp ? wO[par] : wP[par];
-    const C dxy = alpha + wL[par] + wR[par] + wU + wD;
-    // diagonal inside the z-range and on its first or last plane
-    const C wz1 = nz > 1 ? wz : (C)0;
-    const C di = (dxy + wz1) + wz1, de = dxy + wz1;
-    invI[par] = di > (C)0 ? (C)1 / di : (C)0;
-    invE[par] = de > (C)0 ? (C)1 / de : (C)0;
-  }
-
-  // ---- halo cells of this thread (loaded every plane)
-  int hoff[NHR], hg[NHR];
-  bool hv[NHR], hs[NHR];
-#pragma unroll
-  for (int k = 0; k < NHR; ++k) {
-    int h;
-    if (k < NHR - 1) {
-      h = tid + NT * k;
-    } else {  // last round: spread the remainder over the waves
-      const int m = WaveSplit<SS::NHALO - NT * (NHR - 1), NT>::item(tid);
-      h = m < 0 ? -1 : NT * k + m;
-    }
-    int hy = 0, hx = 0;
-    if (h >= 0) halo_cell<TX, TY>(h, hy, hx);
-    const int cx = x0 - 2 + hx, cy = y0 - YO + hy;
-    hs[k] = h >= 0;
-    hv[k] = h >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
-    hoff[k] = hy * HX + hx;
-    hg[k] = hv[k] ? cy * px + cx : 0;
-  }
-
-  // ---- ring red cell of this thread, for each plane parity
-  const int rm = Ring::item(tid);
-  int ro[2], rg[2];
-  bool rv[2];
-  C rwl[2], rwr[2], rwu[2], rwd[2], rinvI[2], rinvE[2];
-#pragma unroll
-  for (int par = 0; par < 2; ++par) {
-    int hy = 0, hx = 0;
-    if (rm >= 0) ring_red_cell<TX, TY>(rm, x0, y0, par, hy, hx);
-    const int cx = x0 - 2 + hx, cy = y0 - YO + hy;
-    rv[par] = rm >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
-    // a thread without a ring cell relaxes its own cell's position as a
-    // stand-in (in-plane neighbours inside the LDS plane) and writes the
-    // result to its dummy slot
-    ro[par] = rm >= 0 ? hy * HX + hx : lo;
-    rg[par] = rv[par] ? cy * px + cx : 0;
-    rwl[par] = cx > 0 ? wx : (C)0;
-    rwr[par] = cx < nx - 1 ? wx : (C)0;
-    rwu[par] = cy > 0 ? wy : (C)0;
-    rwd[par] = cy < ny - 1 ? wy : (C)0;
-    const C dxy = alpha + rwl[par] + rwr[par] + rwu[par] + rwd[par];
-    const C wz1 = nz > 1 ? wz : (C)0;
-    const C di = (dxy + wz1) + wz1, de = dxy + wz1;
-    rinvI[par] = di > (C)0 ? (C)1 / di : (C)0;
-    rinvE[par] = de > (C)0 ? (C)1 / de : (C)0;
-  }
-
-  // ---- plane loads: x pair + halo (registers), b pair, ring b.  Two planes
-  // of x and b are in flight while a plane is relaxed; a loaded value is
-  // first touched one or two planes later, so the loads overlap the updates.
-  // Values are kept raw (storage format) until stash / split: converting a
-  // 16-bit value right after its load would make the wave wait for it there.
-  // The plain loads are issued unconditionally from clamped, always valid
-  // addresses and masked when used: with no branch around them the compiler
-  // can wait for the oldest plane only, keeping the next one in flight.
-  struct XSet {
-    Raw2<S> p;                      // own pair
-    Raw<S> h[NHR];                  // halo cells
-    C ea = 0, eb = 0, eh[NHR] = {};  // fused prolongation (FP)
-  };
-  auto plane_ptr = [&](const S* base, int q) { return base + (int64_t)min(max(q, 0), nz - 1) * pl; };
-  auto fetch_x = [&](int q, XSet& o) {
-    const S* P = plane_ptr(xg, q);
-    if (VEC) {
-      ld_raw2(P + (vA ? own : 0), true, true, o.p);
-    } else {
-      o.p = Raw2<S>();
-      if (vA) ld_raw2(P + own, false, vB, o.p);
-    }
-#pragma unroll
-    for (int k = 0; k < NHR; ++k) ld_raw(P + hg[k], o.h[k]);
-    if (FP) {
-      o.ea = o.eb = (C)0;
-#pragma unroll
-      for (int k = 0; k < NHR; ++k) o.eh[k] = (C)0;
-      if (q >= 0 && q < nz) {
-        if (vA) prolong_pair<S>(ec, G, gx, gy, q, pmode, o.ea, o.eb);
-#pragma unroll
-        for (int k = 0; k < NHR; ++k)
-          if (hv[k]) o.eh[k] = prolong_value<S>(ec, G, x0 - 2 + hoff[k] % HX, y0 - YO + hoff[k] / HX, q, pmode);
-      }
-    }
-  };
-  auto xa = [&](const XSet& o, int q) -> C {
-    const C v = FP ? raw_ca(o.p) + o.ea : raw_ca(o.p);
-    return (q >= 0 && q < nz && vA) ? v : (C)0;
-  };
-  auto xb = [&](const XSet& o, int q) -> C {
-    const C v = FP ? raw_cb(o.p) + o.eb : raw_cb(o.p);
-    return (q >= 0 && q < nz && vB) ? v : (C)0;
-  };
-  auto stash = [&](int q, const XSet& o) {
-    C* P = X + (q & 3) * PLANE;
-    const bool okq = q >= 0 && q < nz;
-    P[lo] = xa(o, q);
-    P[lo + 1] = xb(o, q);
-#pragma unroll
-    for (int k = 0; k < NHR; ++k)
-      if (hs[k]) P[hoff[k]] = (okq && hv[k]) ? (FP ? raw_c(o.h[k]) + o.eh[k] : raw_c(o.h[k])) : (C)0;
-  };
-  // b pair of plane q (memory order, raw; masked by bA / bB)
-  auto fetch_b = [&](int q, Raw2<S>& r) {
-    const S* P = plane_ptr(bg, q);
-    if (VEC) {
-      ld_raw2(P + (vA ? own : 0), true, true, r);
-    } else {
-      r = Raw2<S>();
-      if (vA) ld_raw2(P + own, false, vB, r);
-    }
-  };
-  auto bA = [&](const Raw2<S>& r, int q) -> C { return (q >= 0 && q < nz && vA) ? raw_ca(r) : (C)0; };
-  auto bB = [&](const Raw2<S>& r, int q) -> C { return (q >= 0 && q < nz && vB) ? raw_cb(r) : (C)0; };
-  auto ring_b = [&](int q) -> Raw<S> {
-    Raw<S> r;
-    ld_raw(plane_ptr(bg, q) + rg[q & 1], r);
-    return r;
-  };
-  // pair (in memory order) -> (red, black) of plane q
-  auto split = [&](int q, C a, C b, C& r, C& k) {
-    const bool cp = ((gy + q) & 1) != 0;
-    b = vB ? b : (C)0;
-    r = cp ? b : a;
-    k = cp ? a : b;
-  };
-
-  // column registers (red R / black K of planes p-2 .. p+1), b of planes p-1, p
-  C Rm2 = 0, Km2 = 0, Rm1, Km1, R0, K0, Rp1, Kp1;
-  C bRm1, bKm1, bR0, bK0;
-  // Loads in flight sit in two slots each (plane r in slot (r - pfirst) & 1)
-  // and the loop is unrolled by two, so that no in-flight register is ever
-  // copied: a copy would make the wave wait for the newest loads.
-  XSet S0, S1;
-  Raw2<S> B0, B1;
-  Raw<S> RB0, RB1;
-  const int pfirst = max(q0 - 1, 0);
-  const int plast = (q1 < nz) ? q1 : nz;  // p == nz: black of the last plane only
-  {
-    XSet t0;
-    Raw2<S> tb;
-    fetch_x(pfirst - 1, t0); stash(pfirst - 1, t0); split(pfirst - 1, xa(t0, pfirst - 1), xb(t0, pfirst - 1), Rm1, Km1);
-    fetch_x(pfirst, t0);     stash(pfirst, t0);     split(pfirst, xa(t0, pfirst), xb(t0, pfirst), R0, K0);
-    fetch_x(pfirst + 1, t0); stash(pfirst + 1, t0); split(pfirst + 1, xa(t0, pfirst + 1), xb(t0, pfirst + 1), Rp1, Kp1);
-    fetch_b(pfirst - 1, tb); split(pfirst - 1, bA(tb, pfirst - 1), bB(tb, pfirst - 1), bRm1, bKm1);
-    fetch_b(pfirst, tb);     split(pfirst, bA(tb, pfirst), bB(tb, pfirst), bR0, bK0);
-  }
-  RB0 = ring_b(pfirst);
-  RB1 = ring_b(pfirst + 1);
-  fetch_x(pfirst + 2, S0);
-  fetch_x(pfirst + 3, S1);
-  fetch_b(pfirst + 1, B1);
-  fetch_b(pfirst + 2, B0);
-
-  // one plane step: red of plane p, black of plane p - 1, then plane p + 2
-  // enters LDS and the loads of planes p + 4 (x), p + 3 (b), p + 2 (ring b)
-  // go out into the slots just consumed
-  auto step = [&](auto PC, int p, XSet& XS, Raw2<S>& BS, Raw<S>& RBS) {
-    constexpr int par = decltype(PC)::value;  // p & 1, fixed per unrolled step
-    __syncthreads();
-    if (p < nz) {
-      // ---- red cells of plane p: the pair's red cell and the ring cell,
-      // both computed by every thread (masked), so that their LDS reads
-      // issue together
-      C* P = X + (p & 3) * PLANE;
-      const C* Pm = X + ((p - 1) & 3) * PLANE;
-      const C* Pp = X + ((p + 1) & 3) * PLANE;
-      const C wzm = p > 0 ? wz : (C)0, wzp = p < nz - 1 ? wz : (C)0;
-      const bool edge = p == 0 || p == nz - 1;
-      const bool cp = ((gy + p) & 1) != 0;  // red cell on the pair's right
-      const C vo = P[offO[par]];
-      const C up = ROW ? (C)0 : P[offY[par] - HX], dn = ROW ? (C)0 : P[offY[par] + HX];
-      const int o = ro[par];
-      const C rx = P[o], rl = P[o - 1], rr = P[o + 1];
-      const C ru = ROW ? (C)0 : P[o - HX], rd = ROW ? (C)0 : P[o + HX];
-      const C rzm = Pm[o], rzp = Pp[o];
-      const C nv = relax<C, ROW>(R0, bR0, alpha, wL[par], cp ? K0 : vo, wR[par], cp ? vo : K0, wU, up, wD, dn, wzm, Km1,
-                                 wzp, Kp1, edge ? invE[par] : invI[par]);
-      R0 = vR[par] ? nv : (C)0;
-      P[offY[par]] = R0;
-      const C rb = (p >= 0 && rv[par]) ? raw_c(RBS) : (C)0;
-      const C rn = relax<C, ROW>(rx, rb, alpha, rwl[par], rl, rwr[par], rr, rwu[par], ru, rwd[par], rd, wzm, rzm,
-                                 wzp, rzp, edge ? rinvE[par] : rinvI[par]);
-      *(rv[par] ? P + o : X + 4 * PLANE + tid) = rn;
-    }
-    // no barrier here: the black cells of plane p - 1 read only plane
-    // p - 1's buffer, whose red cells were written in the previous step
-    const int q = p - 1;
-    if (q >= q0 && q < q1) {
-      // ---- black cells of plane q = p - 1 (same position as the red cell of plane p)
-      const C* P = X + (q & 3) * PLANE;
-      const C wzm = q > 0 ? wz : (C)0, wzp = q < nz - 1 ? wz : (C)0;
-      const bool edge = q == 0 || q == nz - 1;
-      const bool cq = ((gy + q) & 1) != 0;  // red position of plane q
-      // the black cell sits on the pair's right when the red one is on its left
-      const C vo = P[offO[par]];
-      const C up = ROW ? (C)0 : P[offY[par] - HX], dn = ROW ? (C)0 : P[offY[par] + HX];
-      const C nv = relax<C, ROW>(Km1, bKm1, alpha, wL[par], cq ? vo : Rm1, wR[par], cq ? Rm1 : vo, wU, up, wD, dn, wzm,
-                                 Rm2, wzp, R0, edge ? invE[par] : invI[par]);
-      Km1 = vR[par] ? nv : (C)0;
-      if (vA) st2(xo + (int64_t)q * pl + own, VEC, vB, cq ? Km1 : Rm1, cq ? Rm1 : Km1);
-    }
-    stash(p + 2, XS);
-    Rm2 = Rm1; Km2 = Km1; Rm1 = R0; Km1 = K0; R0 = Rp1; K0 = Kp1;
-    split(p + 2, xa(XS, p + 2), xb(XS, p + 2), Rp1, Kp1);
-    bRm1 = bR0; bKm1 = bK0;
-    split(p + 1, bA(BS, p + 1), bB(BS, p + 1), bR0, bK0);
-    // next planes (clamped reads past the chunk's end are harmless and keep
-    // the loop free of a branch around the loads)
-    fetch_x(p + 4, XS);
-    fetch_b(p + 3, BS);
-    ld_raw(plane_ptr(bg, p + 2) + rg[par], RBS);  // ring b of plane p + 2 (same parity)
-  };
-  using E0 = std::integral_constant<int, 0>;
-  using E1 = std::integral_constant<int, 1>;
-  int p = pfirst;
-  if ((pfirst & 1) == 0) {
-    for (; p + 1 <= plast; p += 2) {
-      step(E0{}, p, S0, B1, RB0);
-      step(E1{}, p + 1, S1, B0, RB1);
-    }
-    if (p <= plast) step(E0{}, p, S0, B1, RB0);
-  } else {
-    for (; p + 1 <= plast; p += 2) {
-      step(E1{}, p, S0, B1, RB0);
-      step(E0{}, p + 1, S1, B0, RB1);
-    }
-    if (p <= plast) step(E1{}, p, S0, B1, RB0);
-  }
-}
 
 // ------------------------------------------------ residual + restriction
 //
@@ -892,331 +331,6 @@ k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     f1 = fn;
   }
 }
-
-// ------------------------------------------- finest level of AD / SP (Eq. 1, 2)
-//
-// Canonical system of both phases: A = alpha + w_x L_x + w_y L_y + w_z L_z,
-// b = alpha I1 + (w_x L_x + w_y L_y) I0 (AD: alpha = 0; SP: w_z = 0).  In
-// the grid description the caller's y axis is the grid's y axis for a stack
-// and its z axis for a slice (ny = 1); the in-slice weights are then w_x and
-// w_z.  GridDesc::zin flags the slice form.
-// The plain solver iterates on the correction E = x - I0, whose right-hand
-// side is b - A I0 = alpha (I1 - I0) - (cross-slice part of A) I0.
-
-template <typename Tin>
-__device__ __forceinline__ double in_at(const Tin* p, int64_t v) { return ld64(p + v); }
-
-// ------------------------------------- correction-form stencil passes
-//
-// Both passes on the finest grid use one z-marching structure (pairs of x
-// per thread, the three planes of one field in an LDS ring for the in-plane
-// neighbours, z neighbours in registers; FP64 arithmetic):
-//
-// KIND 0, right-hand side of the correction E = x - I0.  With F = I0:
-//   b_corr = alpha (I1 - I0) - [stack] w_z L_z I0
-//   ||b||^2 of the canonical system b = alpha I1 + (w_x L_x + w_y L_y) I0
-//   (+ w_z L_z I0 for a slice, whose "z" is its own second axis); the stack
-//   form's cross-slice target is zero (Eq. (1)).  Writes b_corr and a zero
-//   correction.
-// KIND 1, canonical residual b - A x in FP64.  With F = x - I0 (E in MODE 0,
-// x64 - I0 in MODE 1, x64 + s e - I0 in MODE 2, where the refinement's
-// update x64 + s e is also written to x64_out, s = e_scale[grid]) the I0
-// terms of b and A x cancel except across slices:
-//   r = alpha (I1 - I0 - F) - (w_x L_x + w_y L_y + w_z L_z) F - [stack] w_z L_z I0
-//   ||r||^2 per block; r * inv_scale stored when rout is set.
-// L_a v is the Neumann second difference sum over existing neighbours of
-// (v_c - v_n).  Row tiles (TY == 1) serve grids with ny == 1.
-template <typename Tin, typename S, int TX, int TY, int KIND, int MODE>
-__global__ void __launch_bounds__(TX * TY / 2)
-k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
-               const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
-               const double* __restrict__ x64, S* __restrict__ out0, S* __restrict__ out1,
-               const double* __restrict__ inv_scale, double* __restrict__ partials,
-               double* __restrict__ x64_out, const double* __restrict__ e_scale) {
-  constexpr bool ROW = (TY == 1);
-  constexpr int NT = TX * TY / 2;
-  constexpr int YO = ROW ? 0 : 1;
-  constexpr int HX = TX + 2, HY = ROW ? 1 : TY + 2;
-  constexpr int NHALO = HX * HY - TX * TY;
-  constexpr int NHR = (NHALO + NT - 1) / NT;
-  static_assert(MODE < 2 || KIND == 1, "the refinement update belongs to the residual pass");
-  __shared__ double X[3][HY][HX];
-  __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
-
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
-  const GridDesc& G = grids[t.g];
-  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
-  const bool slice = G.zin != 0;
-  const double alpha = G.alpha, wx = G.wx, wy = ROW ? 0.0 : G.wy, wz = G.wz;
-  const bool cross = !slice && wz != 0.0;  // the stack's cross-slice term of I0
-  const int64_t pl = (int64_t)px * ny;
-  const Tin* I0g = I0 + G.ioff;
-  const Tin* I1g = (I1 && alpha != 0.0) ? I1 + G.ioff : nullptr;
-  const S* Eg = E + G.off;
-  const double* xg = x64 + G.off;
-  const bool ivec = ((G.ioff | G.ipy | G.ipz) & 1) == 0, vec = ((px | G.off) & 1) == 0;
-  const int tid = threadIdx.x;
-  const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
-  const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
-  const int gx = x0 + 2 * pxl, gy = y0 + tyl;
-  const bool rowok = gy < ny;
-  const bool vA = rowok && gx < nx, vB = rowok && gx + 1 < nx;
-  const int lx = 1 + 2 * pxl, ly = YO + tyl;
-  const int64_t own = (int64_t)gy * px + gx, ownu = (int64_t)gy * G.ipy + gx;
-  const bool up = !ROW && gy > 0, dn = !ROW && gy + 1 < ny, o0 = gx > 0, o1 = gx + 2 < nx;
-
-  int hoff[NHR];
-  int64_t hg[NHR], hu[NHR];
-  bool hv[NHR];
-#pragma unroll
-  for (int k = 0; k < NHR; ++k) {
-    const int h = tid + NT * k;
-    int hy = 0, hx = 0;
-    if (ROW) {
-      hx = (h == 0) ? 0 : HX - 1;
-    } else if (h < HX) {
-      hy = 0; hx = h;
-    } else if (h < 2 * HX) {
-      hy = HY - 1; hx = h - HX;
-    } else {
-      const int m = h - 2 * HX;
-      hy = 1 + (m >> 1);
-      hx = (m & 1) ? HX - 1 : 0;
-    }
-    const int cx = x0 - 1 + hx, cy = y0 - YO + hy;
-    hv[k] = h < NHALO && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
-    hoff[k] = hy * HX + hx;
-    hg[k] = hv[k] ? (int64_t)cy * px + cx : 0;
-    hu[k] = hv[k] ? (int64_t)cy * G.ipy + cx : 0;
-  }
-  // Raw loads of plane q: F's own pair and halo values and (KIND 1) I0's
-  // pair; converted to FP64 only in stash(), after other work has run.
-  using FS = std::conditional_t<KIND == 0, Tin, std::conditional_t<MODE == 0, S, double>>;
-  Raw2<FS> rf;
-  Raw2<Tin> ri;
-  Raw2<S> re;  // MODE 2: the correction e
-  Raw<FS> rh[NHR];
-  Raw<Tin> rhi[NHR];
-  Raw<S> rhe[NHR];
-  const double es = (MODE == 2) ? e_scale[t.g] : 0.0;
-  // loads from clamped addresses without branches around them (masked in stash)
-  auto fetch = [&](int q) {
-    const int qc = min(max(q, 0), nz - 1);
-    const Tin* I0q = I0g + qc * G.ipz;
-    const int64_t po = qc * pl;
-    const int64_t oo = vA ? own : 0, ou = vA ? ownu : 0;
-    if (KIND == 0) {
-      ld_raw2(reinterpret_cast<const FS*>(I0q) + ou, ivec, vB, rf);
-    } else {
-      ld_raw2(I0q + ou, ivec, vB, ri);
-      if (MODE == 0) {
-        ld_raw2(reinterpret_cast<const FS*>(Eg) + po + oo, true, true, rf);
-      } else {
-        ld_raw2(reinterpret_cast<const FS*>(xg) + po + oo, true, true, rf);
-        if (MODE == 2) ld_raw2(Eg + po + oo, true, true, re);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NHR; ++k) {
-      if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0q) + hu[k], rh[k]);
-      else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + po + hg[k], rh[k]);
-      else {
-        ld_raw(reinterpret_cast<const FS*>(xg) + po + hg[k], rh[k]);
-        ld_raw(I0q + hu[k], rhi[k]);
-        if (MODE == 2) ld_raw(Eg + po + hg[k], rhe[k]);
-      }
-    }
-  };
-  // convert the last fetch: F pair (fa, fb), I0 pair (ia, ib); store F's plane
-  double fa = 0, fb = 0, ia = 0, ib = 0;
-  auto stash = [&](int q) {
-    const bool okq = q >= 0 && q < nz, mA = okq && vA, mB = okq && vB;
-    if (KIND == 1) {
-      ia = mA ? raw_a(ri) : 0.0;
-      ib = mB ? raw_b(ri) : 0.0;
-    }
-    fa = mA ? raw_a(rf) : 0.0;
-    fb = mB ? raw_b(rf) : 0.0;
-    if (KIND == 1 && MODE == 2) {  // refinement update x64 + s e, written by the cell's owner
-      fa += mA ? es * raw_a(re) : 0.0;
-      fb += mB ? es * raw_b(re) : 0.0;
-      if (vA && q >= q0 && q < q1) st2(x64_out + G.off + q * pl + own, vec, vB, fa, fb);
-    }
-    if (KIND == 1 && MODE >= 1) {
-      fa -= ia;
-      fb = vB ? fb - ib : 0.0;
-    }
-    double* P = &X[((q % 3) + 3) % 3][0][0];
-    P[ly * HX + lx] = fa;
-    P[ly * HX + lx + 1] = fb;
-#pragma unroll
-    for (int k = 0; k < NHR; ++k)
-      if (tid + NT * k < NHALO) {
-        double v = raw_d(rh[k]);
-        if (KIND == 1 && MODE == 2) v += es * raw_d(rhe[k]);
-        if (KIND == 1 && MODE >= 1) v -= raw_d(rhi[k]);
-        P[hoff[k]] = (okq && hv[k]) ? v : 0.0;
-      }
-  };
-  // I1 pair at plane q (raw), prefetched one plane ahead
-  Raw2<Tin> r1n;
-  auto fetch1 = [&](int q) {  // raw, clamped; used only for k in [q0, q1) with vA / vB
-    if (I1g) ld_raw2(I1g + min(max(q, 0), nz - 1) * G.ipz + (vA ? ownu : 0), ivec, vB, r1n);
-  };
-
-  // registers: F and I0 at k - 1 (m), k (c), k + 1 (p)
-  double fma_ = 0, fmb = 0, fca, fcb, fpa, fpb, ima = 0, imb = 0, ica = 0, icb = 0, ipa = 0, ipb = 0;
-  fetch(q0 - 1);
-  stash(q0 - 1);  // plane q0 - 1 goes to the ring slot of q0 + 2, rewritten before it is read
-  fma_ = fa; fmb = fb; ima = ia; imb = ib;
-  fetch(q0);
-  stash(q0);
-  fca = fa; fcb = fb; ica = ia; icb = ib;
-  fetch(q0 + 1);
-  fetch1(q0);
-  double nrm = 0.0;
-  for (int k = q0; k < q1; ++k) {
-    stash(k + 1);
-    fpa = fa; fpb = fb; ipa = ia; ipb = ib;
-    const Raw2<Tin> r1 = r1n;
-    fetch(k + 2);
-    fetch1(k + 1);
-    __syncthreads();
-    const double v1a = I1g ? raw_a(r1) : 0.0, v1b = I1g ? raw_b(r1) : 0.0;
-    const double* P = &X[k % 3][0][0];
-    const bool zm = k > 0, zp = k < nz - 1;
-    double ra = 0.0, rb = 0.0;
-    // in-plane and z second differences of F; I0's z term for the stack
-    auto lap = [&](double c, double l, bool hl, double rr, bool hr, double u_, double d_, double zm_, double zp_) {
-      double s2 = 0.0;
-      if (hl) s2 += wx * (c - l);
-      if (hr) s2 += wx * (c - rr);
-      if (up) s2 += wy * (c - u_);
-      if (dn) s2 += wy * (c - d_);
-      if (zm) s2 += wz * (c - zm_);
-      if (zp) s2 += wz * (c - zp_);
-      return s2;
-    };
-    if (vA) {
-      const double c = fca;
-      const double lf = lap(c, o0 ? P[ly * HX + lx - 1] : 0.0, o0, fcb, vB, up ? P[(ly - 1) * HX + lx] : 0.0,
-                            dn ? P[(ly + 1) * HX + lx] : 0.0, fma_, fpa);
-      double lzI = 0.0;  // w_z L_z I0 (stack only)
-      if (cross) {
-        const double i0 = KIND == 0 ? fca : ica, im = KIND == 0 ? fma_ : ima, ip = KIND == 0 ? fpa : ipa;
-        if (zm) lzI += wz * (i0 - im);
-        if (zp) lzI += wz * (i0 - ip);
-      }
-      if (KIND == 0) {
-        const double lin = lf - (cross ? lzI : 0.0);  // canonical part of L I0
-        const double bcan = alpha * v1a + lin;
-        nrm += bcan * bcan;
-        ra = alpha * (v1a - c) - lzI;
-      } else {
-        ra = alpha * (v1a - ica - c) - lf - lzI;
-        nrm += ra * ra;
-      }
-    }
-    if (vB) {
-      const double c = fcb;
-      const double lf = lap(c, fca, true, o1 ? P[ly * HX + lx + 2] : 0.0, o1, up ? P[(ly - 1) * HX + lx + 1] : 0.0,
-                            dn ? P[(ly + 1) * HX + lx + 1] : 0.0, fmb, fpb);
-      double lzI = 0.0;
-      if (cross) {
-        const double i0 = KIND == 0 ? fcb : icb, im = KIND == 0 ? fmb : imb, ip = KIND == 0 ? fpb : ipb;
-        if (zm) lzI += wz * (i0 - im);
-        if (zp) lzI += wz * (i0 - ip);
-      }
-      if (KIND == 0) {
-        const double lin = lf - (cross ? lzI : 0.0);
-        const double bcan = alpha * v1b + lin;
-        nrm += bcan * bcan;
-        rb = alpha * (v1b - c) - lzI;
-      } else {
-        rb = alpha * (v1b - icb - c) - lf - lzI;
-        nrm += rb * rb;
-      }
-    }
-    if (vA) {
-      const int64_t v = G.off + k * pl + own;
-      if (KIND == 0) {
-        if (out0) st2(out0 + v, vec, vB, (typename Ty<S>::C)ra, (typename Ty<S>::C)rb);
-        if (out1) st2(out1 + v, vec, vB, (typename Ty<S>::C)0, (typename Ty<S>::C)0);
-      } else if (out0) {
-        const double sc = inv_scale[t.g];
-        st2(out0 + v, vec, vB, (typename Ty<S>::C)(ra * sc), (typename Ty<S>::C)(rb * sc));
-      }
-    }
-    fma_ = fca; fmb = fcb; fca = fpa; fcb = fpb;
-    ima = ica; imb = icb; ica = ipa; icb = ipb;
-  }
-  if (partials) {
-    const double sm = block_sum(nrm, red);
-    if (threadIdx.x == 0) partials[t.bid] = sm;
-  }
-}
-
-template <typename Tin, typename S, int MODE>
-__global__ void __launch_bounds__(256)
-k_sum_shift(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
-            const Tin* __restrict__ I0, const S* __restrict__ E, const double* __restrict__ x64,
-            double* __restrict__ partials) {
-  __shared__ double red[4];
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
-  const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
-  double s = 0.0;
-  if (i < G.nx && j < G.ny) {
-    const int64_t pl = (int64_t)G.px * G.ny;
-    for (int k = t.z0; k < t.z1; ++k) {
-      const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
-      if (MODE == 0) {
-        s += ld64(E + v);
-      } else {
-        const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
-        s += x64[v] - in_at(I0, u);
-      }
-    }
-  }
-  const double tot = block_sum(s, red);
-  if (threadIdx.x == 0) partials[t.bid] = tot;
-}
-
-template <typename Tin, typename S, typename Tout, int MODE>
-__global__ void __launch_bounds__(256)
-k_finalize(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
-           const Tin* __restrict__ I0, const S* __restrict__ E, const double* __restrict__ x64,
-           const double* __restrict__ shift, Tout* __restrict__ out) {
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
-  const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
-  if (i >= G.nx || j >= G.ny) return;
-  const int64_t pl = (int64_t)G.px * G.ny;
-  const double sh = shift ? shift[t.g] : 0.0;
-  for (int k = t.z0; k < t.z1; ++k) {
-    const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
-    const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
-    const double x = (MODE == 0) ? in_at(I0, u) + ld64(E + v) : x64[v];
-    st64(out + u, x - sh);
-  }
-}
-
-template <typename Tin>
-__global__ void __launch_bounds__(256)
-k_refine_init(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
-              const Tin* __restrict__ I0, double* __restrict__ x64) {
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
-  const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
-  if (i >= G.nx || j >= G.ny) return;
-  const int64_t pl = (int64_t)G.px * G.ny;
-  for (int k = t.z0; k < t.z1; ++k) {
-    const int64_t u = G.ioff + k * G.ipz + (int64_t)j * G.ipy + i;
-    x64[G.off + k * pl + (int64_t)j * G.px + i] = in_at(I0, u);
-  }
-}
-
-
 // -------------------------------------------------- general system (Sec. 4)
 // (caller's arrays, pitch px = nx)
 template <typename S>
@@ -1755,71 +869,7 @@ k_reduce(const double* __restrict__ partials, const int64_t* __restrict__ block0
 }
 
 // ============================================================ launchers
-
-#define GD_ARGS(geom) dim3((unsigned)(geom).nblocks), dim3(256), 0, st, (geom).grids, (geom).block0, (geom).ngrids, (geom).zlen, (geom).etx
-
-#define GD_DISPATCH_S(s, MACRO)                        \
-  switch (s) {                                         \
-    case GD_F64: MACRO(double); break;                 \
-    case GD_F32: MACRO(float); break;                  \
-    case GD_F16: MACRO(__half); break;                 \
-    case GD_BF16: MACRO(__hip_bfloat16); break;        \
-    default: return hipErrorInvalidValue;              \
-  }
-
-#define GD_DISPATCH_S2(s, T1, MACRO)                   \
-  switch (s) {                                         \
-    case GD_F64: MACRO(T1, double); break;             \
-    case GD_F32: MACRO(T1, float); break;              \
-    case GD_F16: MACRO(T1, __half); break;             \
-    case GD_BF16: MACRO(T1, __hip_bfloat16); break;    \
-    default: return hipErrorInvalidValue;              \
-  }
-
-static hipError_t last() { return hipGetLastError(); }
-
-template <typename T, bool FP, bool VEC>
-static void sweep_launch3(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
-                          hipStream_t st) {
-  if (g.row) {
-    hipLaunchKernelGGL((k_rb_sweep<T, SWR_TX, 1, FP, VEC>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st,
-                       g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec,
-                       pmode, g.order);
-  } else {
-#define SWEEP_TILE(TX, TY)                                                                                     \
-  hipLaunchKernelGGL((k_rb_sweep<T, TX, TY, FP, VEC>), dim3((unsigned)g.nblocks), dim3(TX * TY / 2), 0, st,    \
-                     g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec, pmode, \
-                     g.order)
-    if (FP || g.tile == 0) {
-      SWEEP_TILE(64, 8);
-    } else if constexpr (!FP) {  // the fused prolongation exists for the 64 x 8 tile only
-      switch (g.tile) {
-        case 1: SWEEP_TILE(128, 8); break;
-        case 2: SWEEP_TILE(64, 16); break;
-        default: SWEEP_TILE(128, 16); break;
-      }
-    }
-#undef SWEEP_TILE
-  }
-}
-
-template <typename T>
-static void sweep_launch(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
-                         hipStream_t st) {
-  // the library's arrays are pair-aligned (g.vec); a caller's odd-width arrays are not
-  if (ec) sweep_launch3<T, true, true>(g, xin, xout, b, ec, pmode, st);
-  else if (g.vec) sweep_launch3<T, false, true>(g, xin, xout, b, ec, pmode, st);
-  else sweep_launch3<T, false, false>(g, xin, xout, b, ec, pmode, st);
-}
-
-hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
-                           const void* ec, int pmode, hipStream_t st) {
-  if (g.nblocks == 0) return hipSuccess;
-#define L(T) sweep_launch<T>(g, xin, xout, b, ec, pmode, st)
-  GD_DISPATCH_S(s, L)
-#undef L
-  return last();
-}
+// ============================================================ launchers
 
 template <typename T>
 static void restrict_z_launch(const Geom& g, const void* x, const void* b, void* bc, void* xc, double* partials,
@@ -1864,100 +914,6 @@ hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* ec, void* x
   if (g.nblocks == 0) return hipSuccess;
 #define L(T) hipLaunchKernelGGL(k_prolong_add<T>, GD_ARGS(g), (const T*)ec, (T*)x, mode)
   GD_DISPATCH_S(s, L)
-#undef L
-  return last();
-}
-
-template <typename TI, typename T, int KIND, int MODE>
-static void corr_stencil_launch(const Geom& g, const void* I0, const void* I1, const void* E, const double* x64,
-                                void* o0, void* o1, const double* inv_scale, double* partials, double* x64o,
-                                const double* escale, hipStream_t st) {
-  if (g.row)
-    hipLaunchKernelGGL((k_corr_stencil<TI, T, SWR_TX, 1, KIND, MODE>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0,
-                       st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0, (const TI*)I1, (const T*)E, x64, (T*)o0,
-                       (T*)o1, inv_scale, partials, x64o, escale);
-  else
-    hipLaunchKernelGGL((k_corr_stencil<TI, T, SW_TX, SW_TY, KIND, MODE>), dim3((unsigned)g.nblocks),
-                       dim3(SW_TX * SW_TY / 2), 0, st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0,
-                       (const TI*)I1, (const T*)E, x64, (T*)o0, (T*)o1, inv_scale, partials, x64o, escale);
-}
-
-hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, const void* I1, void* b,
-                           void* x, double* partials, hipStream_t st) {
-  if (g.nblocks == 0) return hipSuccess;
-#define L2(TI, T) \
-  corr_stencil_launch<TI, T, 0, 0>(g, I0, I1, nullptr, nullptr, b, x, nullptr, partials, nullptr, nullptr, st)
-#define L1(TI) GD_DISPATCH_S2(s, TI, L2)
-  GD_DISPATCH_S(tin, L1)
-#undef L1
-#undef L2
-  return last();
-}
-
-hipError_t launch_canon_residual(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
-                                 const void* I1, const void* E, const double* x64, void* r_out,
-                                 const double* inv_scale, double* partials, hipStream_t st, double* x64_out,
-                                 const double* e_scale) {
-  if (g.nblocks == 0) return hipSuccess;
-#define L2(TI, T)                                                                                              \
-  if (mode == 0)                                                                                               \
-    corr_stencil_launch<TI, T, 1, 0>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, nullptr, st); \
-  else if (mode == 1)                                                                                          \
-    corr_stencil_launch<TI, T, 1, 1>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, nullptr, st); \
-  else                                                                                                         \
-    corr_stencil_launch<TI, T, 1, 2>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, x64_out, e_scale, st)
-#define L1(TI) GD_DISPATCH_S2(s, TI, L2)
-  GD_DISPATCH_S(tin, L1)
-#undef L1
-#undef L2
-  return last();
-}
-
-hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0, const void* E,
-                            const double* x64, double* partials, hipStream_t st) {
-  if (g.nblocks == 0) return hipSuccess;
-#define L2(TI, T)                                                                                             \
-  if (mode == 0)                                                                                              \
-    hipLaunchKernelGGL((k_sum_shift<TI, T, 0>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, partials);        \
-  else                                                                                                        \
-    hipLaunchKernelGGL((k_sum_shift<TI, T, 1>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, partials)
-#define L1(TI) GD_DISPATCH_S2(s, TI, L2)
-  GD_DISPATCH_S(tin, L1)
-#undef L1
-#undef L2
-  return last();
-}
-
-template <typename TI, typename T>
-static hipError_t finalize_out(gd_dtype tout, int mode, const Geom& g, const void* I0, const void* E,
-                               const double* x64, const double* shift, void* out, hipStream_t st) {
-#define L(TO)                                                                                                \
-  if (mode == 0)                                                                                             \
-    hipLaunchKernelGGL((k_finalize<TI, T, TO, 0>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, shift, (TO*)out); \
-  else                                                                                                       \
-    hipLaunchKernelGGL((k_finalize<TI, T, TO, 1>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, shift, (TO*)out)
-  GD_DISPATCH_S(tout, L)
-#undef L
-  return hipSuccess;
-}
-
-hipError_t launch_finalize(gd_dtype tin, gd_dtype s, gd_dtype tout, int mode, const Geom& g, const void* I0,
-                           const void* E, const double* x64, const double* shift, void* out, hipStream_t st) {
-  if (g.nblocks == 0) return hipSuccess;
-  hipError_t e = hipSuccess;
-#define L2(TI, T) e = finalize_out<TI, T>(tout, mode, g, I0, E, x64, shift, out, st)
-#define L1(TI) GD_DISPATCH_S2(s, TI, L2)
-  GD_DISPATCH_S(tin, L1)
-#undef L1
-#undef L2
-  if (e != hipSuccess) return e;
-  return last();
-}
-
-hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, double* x64, hipStream_t st) {
-  if (g.nblocks == 0) return hipSuccess;
-#define L(T) hipLaunchKernelGGL(k_refine_init<T>, GD_ARGS(g), (const T*)I0, x64)
-  GD_DISPATCH_S(tin, L)
 #undef L
   return last();
 }
