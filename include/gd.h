@@ -106,6 +106,15 @@ typedef struct {
   double b_norm;          /* ||b||_2 of the canonical system                    */
   double seconds;         /* wall time of the call, host clock                  */
   int levels;             /* multigrid levels (finest = level 0)                */
+  int fallback_used;      /* gd_fcg_solve: 1 when the learned preconditioner was
+                             replaced by the V-cycle (net failed or stopped
+                             reducing the residual); 0 otherwise               */
+  double bytes;           /* algorithmic HBM bytes of the solve's kernels: per
+                             launch, the bytes the kernel must read and write
+                             per cell (e.g. 3 x storage bytes for a sweep)
+                             times the cells it covers, summed on the host; a
+                             slice's report carries its share by cells (0 for
+                             gd_fcg_solve)                                     */
 } gd_solve_report;
 
 /* One slice of a batched screened-Poisson call (Eq. (2) per slice). */
@@ -135,14 +144,20 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
 /* Per-slice screened Poisson, Eq. (2) (Sec. 3.1.2), for a batch of
  * independent 2-D slices of any sizes:
  *   (alpha_i + beta_x L_x + beta_y L_y) I2_i = alpha_i I1_i + (beta_x L_x + beta_y L_y) I0_i.
- * I0, I1, I2 share dtype t and the slice layout `slices` (host array of
- * nslices descriptors; slices must not overlap).  Every slice is iterated
- * until its own relative residual <= rel_tol.  per_slice (host array of
- * nslices, or NULL) receives each slice's final report; rep (or NULL) the
- * batch summary with rel_residual = the largest slice residual.  nslices = 0
- * is an empty batch (GD_OK, nothing touched); nslices < 0, zero-sized
- * slices or alpha <= 0 are GD_ERR_INVALID. */
-gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, gd_dtype t,
+ * I0 (dtype in_t), I1 (dtype i1_t: in_t, GD_F32 or GD_F64) and I2 (dtype
+ * out_t, any) share the slice layout `slices` (host array of nslices
+ * descriptors; slices must not overlap; every array must hold each slice's
+ * span offset + pitch * (ny - 1) + nx).  A wider I1 and I2 let the FP64
+ * result of a refined anisotropic diffusion feed this phase and the refined
+ * result come back without rounding to the 16-bit storage type of I0.
+ * Every slice is iterated until its own relative residual <= rel_tol.
+ * per_slice (host array of nslices, or NULL) receives each slice's final
+ * report; rep (or NULL) the batch summary with rel_residual = the largest
+ * slice residual.  nslices = 0 is an empty batch (GD_OK, nothing touched);
+ * nslices < 0, zero-sized slices, alpha <= 0 or another i1_t are
+ * GD_ERR_INVALID. */
+gd_status gd_screened_poisson_slices(const void* I0, gd_dtype in_t, const void* I1, gd_dtype i1_t,
+                                     void* I2, gd_dtype out_t,
                                      const gd_slice_desc* slices, int64_t nslices,
                                      double beta_x, double beta_y,
                                      const gd_solve_opts* opts, gd_solve_report* rep,
@@ -276,7 +291,10 @@ gd_status gd_mg_error_pairs(gd_hierarchy* h, const void* b, const void* x_star, 
  * forward pass runs in groups of images of at most 2^25 pixels (about 10 GB
  * of activations).  Errors: GD_ERR_INVALID for other shapes. */
 typedef struct gd_net gd_net;
-gd_status gd_net_create(gd_net** n, uint64_t seed);          /* He-normal init from seed */
+/* weights: NULL for He-normal weights from `seed` (zero biases), or a host
+ * array of `count` == gd_net_num_params FP32 master weights in the layout of
+ * gd_net_get_params (copied; count mismatch: GD_ERR_INVALID). */
+gd_status gd_net_create(gd_net** n, const float* weights, int64_t count, uint64_t seed);
 gd_status gd_net_destroy(gd_net* n);
 int64_t gd_net_num_params(const gd_net* n);
 gd_status gd_net_get_params(gd_net* n, float* host, int64_t count);   /* FP32 master weights */
@@ -305,7 +323,7 @@ gd_status gd_net_kernel_time(const gd_net* n, int layer, double* ms, int64_t* la
  * V-cycle without the finest post-smoothing sweeps, then the net on its
  * remaining residual).  x in/out, b in (caller's layout).  When the net
  * fails or stops reducing the residual the iteration restarts with the
- * V-cycle preconditioner (rep->refine_steps = 1 then).  rep->cycles =
+ * V-cycle preconditioner (rep->fallback_used = 1 then).  rep->cycles =
  * iterations, rep->rel_residual = the final true relative residual. */
 gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int precond, double rel_tol,
                        int max_iter, gd_solve_report* rep, void* stream);

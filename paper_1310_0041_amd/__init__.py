@@ -60,6 +60,8 @@ class Report(ctypes.Structure):
         ("b_norm", ctypes.c_double),
         ("seconds", ctypes.c_double),
         ("levels", ctypes.c_int),
+        ("fallback_used", ctypes.c_int),
+        ("bytes", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -85,7 +87,7 @@ _SIGS = {
     "gd_version": (ctypes.c_char_p, []),
     "gd_smooth_z": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, ctypes.POINTER(SolveOpts),
                          ctypes.POINTER(Report), _vp]),
-    "gd_screened_poisson_slices": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(SliceDesc), _i64, _d, _d,
+    "gd_screened_poisson_slices": (_i, [_vp, _i, _vp, _i, _vp, _i, ctypes.POINTER(SliceDesc), _i64, _d, _d,
                                         ctypes.POINTER(SolveOpts), ctypes.POINTER(Report),
                                         ctypes.POINTER(Report), _vp]),
     "gd_dct_solve": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _d, _vp]),
@@ -113,7 +115,7 @@ _SIGS = {
     "gd_sweep_config": (_i, [_i64, _i64, _i64, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i64),
                              ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "gd_mg_error_pairs": (_i, [_vp, _vp, _vp, _i, _vp, _vp, _vp]),
-    "gd_net_create": (_i, [ctypes.POINTER(_vp), ctypes.c_uint64]),
+    "gd_net_create": (_i, [ctypes.POINTER(_vp), _vp, _i64, ctypes.c_uint64]),
     "gd_net_destroy": (_i, [_vp]),
     "gd_net_num_params": (_i64, [_vp]),
     "gd_net_get_params": (_i, [_vp, _vp, _i64]),
@@ -195,6 +197,29 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, shape, dtype, name):
+    """Refuse a tensor the kernels would read or write out of bounds."""
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+        raise ValueError(f"{name} must be {tuple(shape)} {dtype}, got {tuple(t.shape)} {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous GPU tensor")
+    return t
+
+
+_DESC_NP = np.dtype([("offset", "<i8"), ("nx", "<i4"), ("ny", "<i4"), ("pitch", "<i4"), ("alpha", "<f4")])
+
+
+def slice_span(descs):
+    """Elements an array must hold for the slices of ``descs``: the largest
+    offset + pitch * (ny - 1) + nx."""
+    if len(descs) == 0:
+        return 0
+    d = np.frombuffer(descs, dtype=_DESC_NP, count=len(descs))
+    return int((d["offset"] + d["pitch"].astype(np.int64) * (d["ny"].astype(np.int64) - 1) + d["nx"]).max())
+
+
 def _stream():
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
@@ -268,30 +293,44 @@ def make_slice_descs(offsets, nx, ny, alpha, pitch=None):
     return arr
 
 
-def screened_poisson_slices(I0, I1, descs, beta_xy=(1.0, 1.0), opts=None, out=None, check=True, **kw):
+def screened_poisson_slices(I0, I1, descs, beta_xy=(1.0, 1.0), opts=None, out=None, out_dtype=None, check=True,
+                            **kw):
     """Per-slice screened Poisson (Eq. (2)) for a batch of slices described by
-    ``descs`` (from :func:`make_slice_descs`).  Returns (I2, report, per-slice reports)."""
+    ``descs`` (from :func:`make_slice_descs`).  I1 has I0's dtype, float32 or
+    float64; the output (``out``, else a new tensor of ``out_dtype``, default
+    I0's dtype) may have any.  Returns (I2, report, per-slice reports)."""
     lib = load()
-    if I0.dtype != I1.dtype or I0.shape != I1.shape:
-        raise ValueError("I0 and I1 must share dtype and shape")
-    out = _torch().empty_like(I0) if out is None else out
+    torch = _torch()
+    if I1.dtype not in (I0.dtype, torch.float32, torch.float64):
+        raise ValueError("I1 must have I0's dtype, float32 or float64")
+    if I0.shape != I1.shape:
+        raise ValueError("I0 and I1 must share the shape")
+    if out is None:
+        out = torch.empty_like(I0, dtype=out_dtype or I0.dtype)
+    elif out_dtype is not None and out.dtype != out_dtype:
+        raise ValueError("out does not have out_dtype")
+    span = slice_span(descs)
+    for name, t in (("I0", I0), ("I1", I1), ("out", out)):
+        _ptr(t)
+        if t.numel() < span:
+            raise ValueError(f"{name} holds {t.numel()} elements; the slices reach element {span - 1}")
     n = len(descs)
     o = opts or default_opts(**kw)
     rep = Report()
     per = (Report * n)()
-    st = lib.gd_screened_poisson_slices(_ptr(I0), _ptr(I1), _ptr(out), gd_dtype(I0.dtype), descs, n,
-                                        float(beta_xy[0]), float(beta_xy[1]), ctypes.byref(o),
-                                        ctypes.byref(rep), per, _stream())
+    st = lib.gd_screened_poisson_slices(_ptr(I0), gd_dtype(I0.dtype), _ptr(I1), gd_dtype(I1.dtype), _ptr(out),
+                                        gd_dtype(out.dtype), descs, n, float(beta_xy[0]), float(beta_xy[1]),
+                                        ctypes.byref(o), ctypes.byref(rep), per, _stream())
     if check:
         _check(st)
     return out, dict(rep.as_dict(), status=st), [p.as_dict() for p in per]
 
 
-def screened_poisson_stack(I0, I1, alpha=0.01, beta_xy=(1.0, 1.0), opts=None, check=True, **kw):
+def screened_poisson_stack(I0, I1, alpha=0.01, beta_xy=(1.0, 1.0), opts=None, out_dtype=None, check=True, **kw):
     """Eq. (2) for every slice of a [nz][ny][nx] stack."""
     nz, ny, nx = I0.shape
     descs = make_slice_descs(np.arange(nz) * nx * ny, nx, ny, alpha)
-    return screened_poisson_slices(I0, I1, descs, beta_xy, opts=opts, check=check, **kw)
+    return screened_poisson_slices(I0, I1, descs, beta_xy, opts=opts, out_dtype=out_dtype, check=check, **kw)
 
 
 class Hierarchy:
@@ -320,17 +359,24 @@ class Hierarchy:
         return (dims[2], dims[1], dims[0]), tuple(coef)
 
     def rhs(self, V=None, Gx=None, Gy=None, Gz=None):
+        for name, t in (("V", V), ("Gx", Gx), ("Gy", Gy), ("Gz", Gz)):
+            if t is not None:
+                _need(t, self.shape, self.dtype, name)
         b = _torch().empty(self.shape, dtype=self.dtype, device="cuda")
         _check(_lib.gd_rhs_general(self._h, _ptr(V), _ptr(Gx), _ptr(Gy), _ptr(Gz), _ptr(b), _stream()))
         return b
 
     def vcycle(self, x, b, ncycles=1):
+        _need(x, self.shape, self.dtype, "x")
+        _need(b, self.shape, self.dtype, "b")
         rr = ctypes.c_double()
         _check(_lib.gd_vcycle(self._h, _ptr(x), _ptr(b), int(ncycles), ctypes.byref(rr), _stream()))
         return rr.value
 
     def error_pairs(self, b, x_star, cycles):
         """(r_k, e_k) after `cycles` V-cycles from zero: b - A x_k and x_star - x_k."""
+        _need(b, self.shape, self.dtype, "b")
+        _need(x_star, self.shape, self.dtype, "x_star")
         r = _torch().empty_like(b)
         e = _torch().empty_like(b)
         _check(_lib.gd_mg_error_pairs(self._h, _ptr(b), _ptr(x_star), int(cycles), _ptr(r), _ptr(e), _stream()))
@@ -339,6 +385,8 @@ class Hierarchy:
     def fcg(self, x, b, net=None, precond=0, rel_tol=1e-6, max_iter=200, check=True):
         """Flexible CG (x in/out); precond 0 V-cycle, 1 net, 2 V-cycle then net,
         3 net in place of the finest level's post-smoothing."""
+        _need(x, self.shape, _torch().float32, "x")
+        _need(b, self.shape, _torch().float32, "b")
         rep = Report()
         st = _lib.gd_fcg_solve(self._h, net._n if net is not None else None, _ptr(x), _ptr(b), int(precond),
                                float(rel_tol), int(max_iter), ctypes.byref(rep), _stream())
@@ -346,7 +394,6 @@ class Hierarchy:
             _check(st)
         d = rep.as_dict()
         d["iterations"] = d["cycles"]
-        d["fallback_used"] = d["refine_steps"]
         d["status"] = st
         return d
 
@@ -412,10 +459,17 @@ class StreamedHierarchy(Hierarchy):
 class Net:
     """The learned preconditioner (BF16 U-Net run by the library's kernels)."""
 
-    def __init__(self, seed=0):
+    def __init__(self, seed=0, weights=None):
+        """He-normal weights from `seed`, or a copy of `weights` (FP32 master
+        weights in the layout of :meth:`get_params`)."""
         lib = load()
         self._n = ctypes.c_void_p()
-        _check(lib.gd_net_create(ctypes.byref(self._n), int(seed)), net=True)
+        if weights is None:
+            _check(lib.gd_net_create(ctypes.byref(self._n), None, 0, int(seed)), net=True)
+        else:
+            w = np.ascontiguousarray(weights, dtype=np.float32).ravel()
+            _check(lib.gd_net_create(ctypes.byref(self._n), w.ctypes.data_as(ctypes.c_void_p), w.size, int(seed)),
+                   net=True)
 
     @property
     def num_params(self):
@@ -432,12 +486,19 @@ class Net:
 
     def forward(self, r):
         """r: [batch][ny][nx] FP32 on the GPU -> z of the same shape."""
+        _need(r, r.shape, _torch().float32, "r")
+        if r.dim() != 3:
+            raise ValueError("r must be [batch][ny][nx]")
         b, ny, nx = r.shape
         z = _torch().empty_like(r)
         _check(_lib.gd_net_forward(self._n, _ptr(r), _ptr(z), nx, ny, b, _stream()), net=True)
         return z
 
     def gradients(self, r, e):
+        if r.dim() != 3:
+            raise ValueError("r must be [batch][ny][nx]")
+        _need(r, r.shape, _torch().float32, "r")
+        _need(e, r.shape, _torch().float32, "e")
         b, ny, nx = r.shape
         g = np.empty(self.num_params, dtype=np.float32)
         loss = ctypes.c_double()
@@ -446,6 +507,10 @@ class Net:
         return g, loss.value
 
     def train_step(self, r, e, lr=1e-3):
+        if r.dim() != 3:
+            raise ValueError("r must be [batch][ny][nx]")
+        _need(r, r.shape, _torch().float32, "r")
+        _need(e, r.shape, _torch().float32, "e")
         b, ny, nx = r.shape
         loss = ctypes.c_double()
         _check(_lib.gd_net_train_step(self._n, _ptr(r), _ptr(e), nx, ny, b, float(lr), ctypes.byref(loss),

@@ -143,6 +143,12 @@ struct Hier {
   double* x64 = nullptr;     // FP64 iterate of the refinement path
   double* x64b = nullptr;    // its next value (the fused update writes here)
   std::vector<int64_t> cells;  // finest cells per grid
+  std::vector<double> lcells;  // cells of every level (all grids)
+  // Algorithmic HBM bytes of the kernels launched through this hierarchy
+  // (host-side count: the bytes each kernel must read and write per cell,
+  // times the cells it covers; replayed graphs add what their capture counted)
+  double acct = 0.0;
+  void count(int l, double per_cell) { acct += per_cell * lcells[l]; }
   // Hybrid discretisation: per-level table blocks (levels >= 1) on the device
   // Hybrid (hyb) and Linear (lin) discretisations: per-level table blocks on
   // the device (Hybrid: levels >= 1; Linear: every level)
@@ -156,6 +162,7 @@ struct Hier {
   struct Graph {
     hipGraphExec_t exec = nullptr;
     std::vector<std::pair<void*, void*>> from, to;  // (x, xt) of every level before / after
+    double bytes = 0.0;  // algorithmic bytes of one replay
   };
   hipStream_t cap = nullptr;  // private capture stream (default priority)
   std::map<std::string, std::vector<Graph>> graphs;
@@ -294,6 +301,9 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     }
     L.h = cur;
     L.total = off;
+    double lc = 0.0;
+    for (const auto& g : cur) lc += (double)g.nx * g.ny * g.nz;
+    H->lcells.push_back(lc);
     H->lv.push_back(std::move(L));
     if (!more || (max_levels > 0 && (int)H->lv.size() >= max_levels)) break;
     std::vector<GridDesc> nxt(cur.size());
@@ -562,8 +572,32 @@ static void autotune(Hier& H, hipStream_t st) {
 
 // -------------------------------------------------------------- workspace
 
+// Cached hierarchies, keyed by what fixes their structure: the grids'
+// sizes and coupling weights (the weights decide which axes are halved),
+// the storage type and the path.  The screening weight alpha of each grid
+// only scales the level operators, so a new alpha (a new batch of slices
+// with freshly drawn alphas) is written into the cached level descriptors
+// instead of building another hierarchy.  At most kCacheMax hierarchies are
+// kept; the least recently used one is freed first (and all idle ones when
+// a build runs out of device memory).  A lease holds the hierarchy's lock
+// while a solve uses it, so calls of one shape from several threads run one
+// after the other.
+constexpr size_t kCacheMax = 6;
+struct CacheEntry {
+  std::unique_ptr<Hier> H;
+  std::unique_ptr<std::mutex> mu;
+  uint64_t used = 0;
+};
 static std::mutex g_cache_mu;
-static std::map<std::string, std::unique_ptr<Hier>> g_cache;
+static std::map<std::string, CacheEntry> g_cache;
+static uint64_t g_cache_tick = 0;
+
+struct HierLease {
+  Hier* H = nullptr;
+  std::unique_lock<std::mutex> lk;
+  Hier* operator->() const { return H; }
+  Hier& operator*() const { return *H; }
+};
 
 static uint64_t fnv(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
   const unsigned char* c = (const unsigned char*)p;
@@ -571,26 +605,83 @@ static uint64_t fnv(const void* p, size_t n, uint64_t h = 1469598103934665603ull
   return h;
 }
 
-static Hier* get_hier(const char* kind, const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
-                      hipStream_t st, int tile_force) {
+// free idle cached hierarchies (least recently used first) until at most
+// `keep` remain; entries in use are skipped
+static void evict_idle(size_t keep) {
+  while (g_cache.size() > keep) {
+    auto victim = g_cache.end();
+    for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+      if (!it->second.mu->try_lock()) continue;
+      it->second.mu->unlock();
+      if (victim == g_cache.end() || it->second.used < victim->second.used) victim = it;
+    }
+    if (victim == g_cache.end()) return;
+    g_cache.erase(victim);
+  }
+}
+
+// Write each grid's alpha into every level (alpha_c = V alpha per level, as
+// build_hier derives it) and drop captured graphs, which hold launch
+// arguments by value.
+static void set_alphas(Hier& H, const std::vector<GridSpec>& specs, hipStream_t st) {
+  bool changed = false;
+  for (size_t i = 0; i < specs.size(); ++i)
+    if (H.lv[0].h[i].alpha != specs[i].alpha) changed = true;
+  if (!changed) return;
+  HIP_TRY(hipStreamSynchronize(st));
+  for (size_t i = 0; i < specs.size(); ++i) {
+    double a = specs[i].alpha;
+    for (auto& L : H.lv) {
+      GridDesc& g = L.h[i];
+      g.alpha = a;
+      a *= (double)g.fx * g.fy * g.fz;
+    }
+  }
+  for (auto& L : H.lv) HIP_TRY(hipMemcpy(L.d, L.h.data(), L.h.size() * sizeof(GridDesc), hipMemcpyHostToDevice));
+  for (auto* T : {&H.hyb, &H.lin})
+    for (auto& t : *T) t.alpha = H.lv[0].h[0].alpha;
+  for (auto& kv : H.graphs)
+    for (auto& g : kv.second)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  H.graphs.clear();
+}
+
+static HierLease get_hier(const char* kind, const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
+                          hipStream_t st, int tile_force) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  // the descriptors minus the caller's I/O layout decide the hierarchy
+  // sizes and weights decide the hierarchy; alpha and the caller's layout are updated in place
   std::vector<double> sig;
-  for (const auto& g : specs) {
-    sig.insert(sig.end(), {(double)g.nx, (double)g.ny, (double)g.nz, g.alpha, g.wx, g.wy, g.wz});
-  }
+  for (const auto& g : specs) sig.insert(sig.end(), {(double)g.nx, (double)g.ny, (double)g.nz, g.wx, g.wy, g.wz});
   char key[256];
   std::snprintf(key, sizeof key, "%s|d%d|s%d|m%d|t%d|n%zu|h%016llx", kind, dev, (int)s, (int)mixed, tile_force,
                 specs.size(), (unsigned long long)fnv(sig.data(), sig.size() * sizeof(double)));
-  std::lock_guard<std::mutex> lk(g_cache_mu);
-  auto it = g_cache.find(key);
-  if (it == g_cache.end()) {
-    auto H = build_hier(specs, s, mixed, st, tile_force);
-    if (tile_force < 0) autotune(*H, st);
-    it = g_cache.emplace(key, std::move(H)).first;
+  HierLease lease;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it == g_cache.end()) {
+      evict_idle(kCacheMax - 1);
+      std::unique_ptr<Hier> H;
+      try {
+        H = build_hier(specs, s, mixed, st, tile_force);
+      } catch (const HipFail& e) {
+        if (e.e != hipErrorOutOfMemory) throw;
+        evict_idle(0);  // free every idle hierarchy and try once more
+        H = build_hier(specs, s, mixed, st, tile_force);
+      }
+      if (tile_force < 0) autotune(*H, st);
+      CacheEntry ce;
+      ce.H = std::move(H);
+      ce.mu = std::make_unique<std::mutex>();
+      it = g_cache.emplace(key, std::move(ce)).first;
+    }
+    it->second.used = ++g_cache_tick;
+    lease.H = it->second.H.get();
+    lease.lk = std::unique_lock<std::mutex>(*it->second.mu);
   }
-  Hier* H = it->second.get();
+  Hier* H = lease.H;
+  set_alphas(*H, specs, st);
   // the caller's layout may differ between calls of the same shape
   auto& L0 = H->lv[0];
   bool changed = false;
@@ -606,7 +697,7 @@ static Hier* get_hier(const char* kind, const std::vector<GridSpec>& specs, gd_d
     HIP_TRY(hipStreamSynchronize(st));
     HIP_TRY(hipMemcpy(L0.d, L0.h.data(), L0.h.size() * sizeof(GridDesc), hipMemcpyHostToDevice));
   }
-  return H;
+  return lease;
 }
 
 // --------------------------------------------------------------- V-cycle
@@ -766,6 +857,7 @@ struct Cycler {
   // ||b - A x|| of level 0 (FP64 accumulation), r left in the level's spare buffer
   double level0_residual() {
     Level& L = H.lv[0];
+    H.count(0, 3.0 * P());
     if (table_level(0)) {
       HIP_TRY(launch_hyb_residual(H.s, L.h[0], (*T)[0], L.x, L.b, L.xt, st, H.hyb_part));
       HIP_TRY(launch_reduce(H.hyb_part, H.tab_b0, 1, 1, H.dred, st));
@@ -782,8 +874,11 @@ struct Cycler {
     for (auto& p : ev) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   }
 
+  double P() const { return (double)dsize(H.s); }
   void sweep(int l, const void* ec) {
     Level& L = H.lv[l];
+    H.count(l, 3.0 * P());  // read x and b, write x
+    if (ec) H.count(l + 1, P());
     if (hyb && table_level(l)) {  // 27-point level: 8-colour Gauss-Seidel in place
       for (int c = 0; c < 8; ++c) HIP_TRY(launch_hyb_gs8(H.s, L.h[0], (*T)[l], c, L.x, L.b, st));
       return;
@@ -812,6 +907,9 @@ struct Cycler {
   void restrict_to(int l, bool norm) {
     Level& L = H.lv[l];
     Level& C = H.lv[l + 1];
+    H.count(l, 2.0 * P());      // read x and b
+    H.count(l + 1, 2.0 * P());  // write coarse b and x
+    if (hyb) H.count(l, 2.0 * P());  // r written and read again
     if (hyb) {  // residual into the level's spare buffer, then P^T
       if (!table_level(l)) {
         HIP_TRY(launch_hyb_residual7(H.s, L.h[0], L.x, L.b, L.xt, H.hyb_part, st));
@@ -832,11 +930,15 @@ struct Cycler {
     Level& C = H.lv[l + 1];
     const int np = (l == 0 && post0 >= 0) ? post0 : post;
     if (hyb) {
+      H.count(l, 2.0 * P());
+      H.count(l + 1, P());
       HIP_TRY(launch_hyb_prolong(H.s, H.lv[l].h[0], C.x, H.lv[l].x, st));
       smooth(l, np);
     } else if (fuse && np > 0 && H.lv[l].sw.tile == 0) {
       smooth(l, np, C.x);  // prolongation fused into the first sweep's loads
     } else {
+      H.count(l, 2.0 * P());
+      H.count(l + 1, P());
       HIP_TRY(launch_prolong_pair(H.s, H.g_pp(l), C.x, H.lv[l].x, pmode, H.lv[l].keep_x, st));
       smooth(l, np);
     }
@@ -914,6 +1016,7 @@ struct CycleGraphs {
       if (g.from == now) {
         HIP_TRY(hipGraphLaunch(g.exec, st));
         H.set_xstate(g.to);
+        H.acct += g.bytes;
         return;
       }
     }
@@ -923,8 +1026,10 @@ struct CycleGraphs {
     Hier::Graph g;
     g.from = now;
     hipGraph_t graph = nullptr;
+    const double a0 = H.acct;
     HIP_TRY(hipStreamBeginCapture(H.cap, hipStreamCaptureModeThreadLocal));
     piece(H.cap);
+    g.bytes = H.acct - a0;  // the first replay below runs what the capture counted
     HIP_TRY(hipStreamEndCapture(H.cap, &graph));
     g.to = H.xstate();
     hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
@@ -958,19 +1063,25 @@ struct Problem {
   const void* I1;  // SP value target (NULL for AD)
   void* out;
   gd_dtype tin, tout;
-  bool gauge;  // AD: mean(x) = mean(I0)
+  bool gauge;        // AD: mean(x) = mean(I0)
+  gd_dtype t1 = GD_F32;  // I1's type (tin, or F32 / F64)
 };
 
 struct Outcome {
   int cycles = 0, steps = 0;
+  double bytes = 0.0;  // algorithmic HBM bytes of the solve's kernels
   std::vector<double> rel, bnorm;
   bool converged = false, numeric = false;
 };
 
 // ||b|| of the canonical system per grid (and the correction-form rhs when b_out)
+// bytes per cell of reading the caller's inputs (I0, and I1 when given)
+static double in_bytes(const Problem& P) { return (double)dsize(P.tin) + (P.I1 ? (double)dsize(P.t1) : 0.0); }
+
 static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero, std::vector<double>& bn,
                             hipStream_t st) {
-  HIP_TRY(launch_rhs_corr(P.tin, H.s, H.g_rz(0), P.I0, P.I1, b_out, x_zero, H.partials, st));
+  H.count(0, in_bytes(P) + (b_out ? dsize(H.s) : 0) + (x_zero ? dsize(H.s) : 0));
+  HIP_TRY(launch_rhs_corr(P.tin, P.t1, H.s, H.g_rz(0), P.I0, P.I1, b_out, x_zero, H.partials, st));
   HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, H.ngrids, 1, H.dred, st));
   read_dred(H, 1, st);
   bn.resize(H.ngrids);
@@ -978,7 +1089,8 @@ static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero
 }
 
 static std::vector<double> canon_residual(Hier& H, const Problem& P, int mode, void* rout, hipStream_t st) {
-  HIP_TRY(launch_canon_residual(P.tin, H.s, mode, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, rout, H.dscal + H.ngrids,
+  H.count(0, in_bytes(P) + (mode == 0 ? dsize(H.s) : 8.0) + (rout ? dsize(H.s) : 0));
+  HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, mode, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, rout, H.dscal + H.ngrids,
                                 H.partials, st));
   HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, H.ngrids, 1, H.dred, st));
   read_dred(H, 1, st);
@@ -991,7 +1103,10 @@ static double denom(double bn) { return bn > 0.0 ? bn : 1.0; }
 
 static void finish(Hier& H, const Problem& P, int mode, hipStream_t st) {
   const double* shift = nullptr;
+  const double xb = mode == 0 ? (double)dsize(H.s) : 8.0;
+  H.count(0, dsize(P.tin) + xb + dsize(P.tout));
   if (P.gauge) {
+    H.count(0, dsize(P.tin) + xb);
     HIP_TRY(launch_sum_shift(P.tin, H.s, mode, H.g_ew(0), P.I0, H.lv[0].x, H.x64, H.partials, st));
     HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, H.ngrids, 1, H.dred, st));
     read_dred(H, 1, st);
@@ -1022,6 +1137,7 @@ static bool all_below(const std::vector<double>& r, const std::vector<double>& b
 static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
   prep(H, o);
   Outcome R;
+  const double a0 = H.acct;
   canonical_norms(H, P, H.lv[0].b, H.lv[0].x, R.bnorm, st);
   Cycler cy(H, st, o);
   const bool single = H.lv.size() == 1;
@@ -1087,6 +1203,7 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
   cy.harvest();
   finish(H, P, 0, st);
   cy.harvest();
+  R.bytes = H.acct - a0;
   return R;
 }
 
@@ -1099,7 +1216,9 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
 static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
   prep(H, o);
   Outcome R;
+  const double a0 = H.acct;
   canonical_norms(H, P, nullptr, nullptr, R.bnorm, st);
+  H.count(0, dsize(P.tin) + 8.0);
   HIP_TRY(launch_refine_init(P.tin, H.g_ew(0), P.I0, H.x64, st));
   Cycler cy(H, st, o);
   const size_t es = dsize(H.s);
@@ -1127,6 +1246,7 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
       (void)canon_residual(H, P, 1, H.lv[0].b, st);
       first = false;
     }
+    H.count(0, (double)es);
     HIP_TRY(hipMemsetAsync(H.lv[0].x, 0, H.lv[0].total * es, st));
     for (int c = 0; c < o.inner_cycles; ++c) {
       if (graphs_on(o))
@@ -1142,7 +1262,8 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
       H.hpin[n + g] = 1.0 / scale[g];
     }
     HIP_TRY(hipMemcpyAsync(H.dscal, H.hpin, 2 * n * sizeof(double), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_canon_residual(P.tin, H.s, 2, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, H.lv[0].b, H.dscal + n,
+    H.count(0, in_bytes(P) + 8.0 + es + 8.0 + es);  // read x64, e; write x64', scaled r
+    HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, 2, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, H.lv[0].b, H.dscal + n,
                                   H.partials, st, H.x64b, H.dscal));
     HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, n, 1, H.dred, st));
     read_dred(H, 1, st);
@@ -1153,6 +1274,7 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
   HIP_TRY(hipStreamSynchronize(st));
   cy.harvest();
   finish(H, P, 1, st);
+  R.bytes = H.acct - a0;
   return R;
 }
 
@@ -1164,6 +1286,7 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
 static Outcome solve_corr(Hier& H, const gd_solve_opts& o, double bnorm, hipStream_t st) {
   prep(H, o);
   Outcome R;
+  const double a0 = H.acct;
   R.bnorm = {bnorm};
   Cycler cy(H, st, o);
   const bool single = H.lv.size() == 1;
@@ -1202,6 +1325,7 @@ static Outcome solve_corr(Hier& H, const gd_solve_opts& o, double bnorm, hipStre
   }
   HIP_TRY(hipStreamSynchronize(st));
   cy.harvest();
+  R.bytes = H.acct - a0;
   return R;
 }
 
@@ -1235,7 +1359,10 @@ static Outcome solve_linear_ad(Hier& H, const Problem& P, const gd_solve_opts& o
   return R;
 }
 
-static void fill_report(gd_solve_report* rep, const Outcome& R, int g, double secs, int levels) {
+static void fill_report(gd_solve_report* rep, const Outcome& R, int g, double secs, int levels,
+                        double share = 1.0) {
+  rep->fallback_used = 0;
+  rep->bytes = R.bytes * share;
   rep->cycles = R.cycles;
   rep->refine_steps = R.steps;
   rep->rel_residual = R.rel.empty() ? 0.0 : R.rel[g];
@@ -1337,8 +1464,8 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, i
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<GridSpec> g{{nx, ny, nz, 0.0, bx, by, bz, 0, nx, nx * ny}};
-    Hier* H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
-    Problem P{I0, nullptr, I1, in_t, out_t, true};
+    HierLease H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
+    Problem P{I0, nullptr, I1, in_t, out_t, true, in_t};
     Outcome R = o.discretization == 2 ? solve_linear_ad(*H, P, o, bx, by, bz, st)
                 : o.fp64_refine       ? solve_mixed(*H, P, o, st)
                                       : solve_plain(*H, P, o, st);
@@ -1376,7 +1503,7 @@ gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<GridSpec> g{{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}};
-    Hier* H = get_hier("npr", g, o.storage, false, st, o.sweep_tile);
+    HierLease H = get_hier("npr", g, o.storage, false, st, o.sweep_tile);
     Level& L0 = H->lv[0];
     HIP_TRY(launch_npr_rhs(in_t, H->s, H->g_ew(0), I0, lambda, sigma, L0.b, H->partials, st));
     HIP_TRY(launch_reduce(H->partials, L0.ew.d_b0, 1, 2, H->dred, st));
@@ -1394,9 +1521,10 @@ gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
   });
 }
 
-gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, gd_dtype t, const gd_slice_desc* sl,
-                                     int64_t n, double bx, double by, const gd_solve_opts* opts, gd_solve_report* rep,
-                                     gd_solve_report* per, void* stream) {
+gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1, gd_dtype t1, void* I2,
+                                     gd_dtype tout, const gd_slice_desc* sl, int64_t n, double bx, double by,
+                                     const gd_solve_opts* opts, gd_solve_report* rep, gd_solve_report* per,
+                                     void* stream) {
   if (n == 0) {  // an empty batch: nothing to solve
     if (rep) std::memset(rep, 0, sizeof *rep);
     return GD_OK;
@@ -1404,7 +1532,10 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
   if (!I0 || !I1 || !I2 || !sl) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: null pointer");
   if (I2 == I0 || I2 == I1) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: output aliases input");
   if (n < 0 || n > (1 << 24)) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad slice count");
-  if (!valid_dtype(t)) return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad dtype");
+  if (!valid_dtype(t) || !valid_dtype(t1) || !valid_dtype(tout))
+    return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad dtype");
+  if (t1 != t && t1 != GD_F32 && t1 != GD_F64)
+    return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: I1 must have I0's dtype, F32 or F64");
   if (!(bx >= 0.0) || !(by >= 0.0) || !std::isfinite(bx) || !std::isfinite(by))
     return fail(GD_ERR_INVALID, "gd_screened_poisson_slices: bad beta");
   std::vector<GridSpec> g;
@@ -1440,12 +1571,16 @@ gd_status gd_screened_poisson_slices(const void* I0, const void* I1, void* I2, g
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
-    Hier* H = get_hier("sp", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
-    Problem P{I0, I1, I2, t, t, false};
+    HierLease H = get_hier("sp", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
+    Problem P{I0, I1, I2, t, tout, false, t1};
     Outcome R = o.fp64_refine ? solve_mixed(*H, P, o, st) : solve_plain(*H, P, o, st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (per)
-      for (int64_t i = 0; i < n; ++i) fill_report(&per[i], R, (int)i, secs, (int)H->lv.size());
+    if (per) {  // each slice gets its share of the batch's bytes by cells
+      double tot = 0.0;
+      for (int64_t c : H->cells) tot += (double)c;
+      for (int64_t i = 0; i < n; ++i)
+        fill_report(&per[i], R, (int)i, secs, (int)H->lv.size(), (double)H->cells[i] / std::max(tot, 1.0));
+    }
     if (rep) {
       fill_report(rep, R, 0, secs, (int)H->lv.size());
       double worst = 0.0;
@@ -2092,7 +2227,9 @@ gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int
     HIP_TRY(hipStreamSynchronize(st));
     if (rep) {
       rep->cycles = it;
-      rep->refine_steps = fallback;
+      rep->refine_steps = 0;
+      rep->fallback_used = fallback;
+      rep->bytes = 0.0;
       rep->rel_residual = rtrue / den;
       rep->b_norm = bn;
       rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -2283,7 +2420,7 @@ gd_status gd_release_workspace(void) {
     dct_release();
     {
       std::lock_guard<std::mutex> lk(g_cache_mu);
-      g_cache.clear();
+      evict_idle(0);  // hierarchies in use by a running solve stay
     }
     std::lock_guard<std::mutex> lk(g_step_mu);
     for (auto& kv : g_step) {

@@ -50,14 +50,16 @@ hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* e_coarse, v
 // Finest level of the AD/SP systems in correction form: b = alpha (I1 - I0)
 // - w_z L_z I0 (written when b != NULL, x zeroed when x != NULL) and the
 // FP64 squares of the canonical right-hand side alpha I1 + (w_x L_x + w_y L_y) I0.
-hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, const void* I1,
+// I1 (read only when alpha != 0) has type t1: tin, or F32 / F64 on slice
+// (one-line) grids.
+hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype t1, gd_dtype s, const Geom& g, const void* I0, const void* I1,
                            void* b, void* x, double* partials, hipStream_t st);
 // FP64 canonical residual r = b - A x of the AD/SP system for x = I0 + E
 // (mode 0, E packed in `s`), x = x64 (mode 1) or x = x64 + e_scale[g] E
 // (mode 2, the refinement update, also written to x64_out, which must not
 // alias x64).  Per block: sum r^2.  When r_out != NULL also writes
 // r * inv_scale[g] packed in `s`.
-hipError_t launch_canon_residual(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
+hipError_t launch_canon_residual(gd_dtype tin, gd_dtype t1, gd_dtype s, int mode, const Geom& g, const void* I0,
                                  const void* I1, const void* E, const double* x64, void* r_out,
                                  const double* inv_scale, double* partials, hipStream_t st,
                                  double* x64_out = nullptr, const double* e_scale = nullptr);

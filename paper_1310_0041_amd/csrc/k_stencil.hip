@@ -38,10 +38,12 @@ namespace gd {
 //   ||r||^2 per block; r * inv_scale stored when rout is set.
 // L_a v is the Neumann second difference sum over existing neighbours of
 // (v_c - v_n).  Row tiles (TY == 1) serve grids with ny == 1.
-template <typename Tin, typename S, int TX, int TY, int KIND, int MODE>
+// I1 may have a wider type T1 than I0 (the FP64 result of a refined first
+// phase feeding the second).
+template <typename Tin, typename T1, typename S, int TX, int TY, int KIND, int MODE>
 __global__ void __launch_bounds__(TX * TY / 2)
 k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
-               const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
+               const Tin* __restrict__ I0, const T1* __restrict__ I1, const S* __restrict__ E,
                const double* __restrict__ x64, S* __restrict__ out0, S* __restrict__ out1,
                const double* __restrict__ inv_scale, double* __restrict__ partials,
                double* __restrict__ x64_out, const double* __restrict__ e_scale) {
@@ -63,7 +65,7 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   const bool cross = !slice && wz != 0.0;  // the stack's cross-slice term of I0
   const int64_t pl = (int64_t)px * ny;
   const Tin* I0g = I0 + G.ioff;
-  const Tin* I1g = (I1 && alpha != 0.0) ? I1 + G.ioff : nullptr;
+  const T1* I1g = (I1 && alpha != 0.0) ? I1 + G.ioff : nullptr;
   const S* Eg = E + G.off;
   const double* xg = x64 + G.off;
   const bool ivec = ((G.ioff | G.ipy | G.ipz) & 1) == 0, vec = ((px | G.off) & 1) == 0;
@@ -171,7 +173,7 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
       }
   };
   // I1 pair at plane q (raw), prefetched one plane ahead
-  Raw2<Tin> r1n;
+  Raw2<T1> r1n;
   auto fetch1 = [&](int q) {  // raw, clamped; used only for k in [q0, q1) with vA / vB
     if (I1g) ld_raw2(I1g + min(max(q, 0), nz - 1) * G.ipz + (vA ? ownu : 0), ivec, vB, r1n);
   };
@@ -190,7 +192,7 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   for (int k = q0; k < q1; ++k) {
     stash(k + 1);
     fpa = fa; fpb = fb; ipa = ia; ipb = ib;
-    const Raw2<Tin> r1 = r1n;
+    const Raw2<T1> r1 = r1n;
     fetch(k + 2);
     fetch1(k + 1);
     __syncthreads();
@@ -332,48 +334,77 @@ k_refine_init(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 
 // ============================================================ launchers
 
-template <typename TI, typename T, int KIND, int MODE>
-static void corr_stencil_launch(const Geom& g, const void* I0, const void* I1, const void* E, const double* x64,
-                                void* o0, void* o1, const double* inv_scale, double* partials, double* x64o,
-                                const double* escale, hipStream_t st) {
-  if (g.row)
-    hipLaunchKernelGGL((k_corr_stencil<TI, T, SWR_TX, 1, KIND, MODE>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0,
-                       st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0, (const TI*)I1, (const T*)E, x64, (T*)o0,
-                       (T*)o1, inv_scale, partials, x64o, escale);
-  else
-    hipLaunchKernelGGL((k_corr_stencil<TI, T, SW_TX, SW_TY, KIND, MODE>), dim3((unsigned)g.nblocks),
+template <typename TI, typename T1, typename T, int KIND, int MODE>
+static hipError_t corr_stencil_launch2(const Geom& g, const void* I0, const void* I1, const void* E,
+                                       const double* x64, void* o0, void* o1, const double* inv_scale,
+                                       double* partials, double* x64o, const double* escale, hipStream_t st) {
+  if (g.row) {
+    hipLaunchKernelGGL((k_corr_stencil<TI, T1, T, SWR_TX, 1, KIND, MODE>), dim3((unsigned)g.nblocks),
+                       dim3(SWR_TX / 2), 0, st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0, (const T1*)I1,
+                       (const T*)E, x64, (T*)o0, (T*)o1, inv_scale, partials, x64o, escale);
+  } else if constexpr (std::is_same_v<TI, T1>) {
+    hipLaunchKernelGGL((k_corr_stencil<TI, TI, T, SW_TX, SW_TY, KIND, MODE>), dim3((unsigned)g.nblocks),
                        dim3(SW_TX * SW_TY / 2), 0, st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0,
                        (const TI*)I1, (const T*)E, x64, (T*)o0, (T*)o1, inv_scale, partials, x64o, escale);
+  } else {
+    return hipErrorInvalidValue;  // a wider I1 comes with slice (one-line) grids only
+  }
+  return hipSuccess;
 }
 
-hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype s, const Geom& g, const void* I0, const void* I1, void* b,
-                           void* x, double* partials, hipStream_t st) {
+// I1's type: that of I0, or FP32 / FP64
+template <typename TI, typename T, int KIND, int MODE>
+static hipError_t corr_stencil_launch(gd_dtype t1, gd_dtype tin, const Geom& g, const void* I0, const void* I1,
+                                      const void* E, const double* x64, void* o0, void* o1,
+                                      const double* inv_scale, double* partials, double* x64o,
+                                      const double* escale, hipStream_t st) {
+  if (t1 == tin || !I1)
+    return corr_stencil_launch2<TI, TI, T, KIND, MODE>(g, I0, I1, E, x64, o0, o1, inv_scale, partials, x64o, escale,
+                                                       st);
+  if (t1 == GD_F64)
+    return corr_stencil_launch2<TI, double, T, KIND, MODE>(g, I0, I1, E, x64, o0, o1, inv_scale, partials, x64o,
+                                                           escale, st);
+  if (t1 == GD_F32)
+    return corr_stencil_launch2<TI, float, T, KIND, MODE>(g, I0, I1, E, x64, o0, o1, inv_scale, partials, x64o,
+                                                          escale, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype t1, gd_dtype s, const Geom& g, const void* I0, const void* I1,
+                           void* b, void* x, double* partials, hipStream_t st) {
   if (g.nblocks == 0) return hipSuccess;
+  hipError_t e = hipSuccess;
 #define L2(TI, T) \
-  corr_stencil_launch<TI, T, 0, 0>(g, I0, I1, nullptr, nullptr, b, x, nullptr, partials, nullptr, nullptr, st)
+  e = corr_stencil_launch<TI, T, 0, 0>(t1, tin, g, I0, I1, nullptr, nullptr, b, x, nullptr, partials, nullptr, nullptr, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1
 #undef L2
+  if (e != hipSuccess) return e;
   return last();
 }
 
-hipError_t launch_canon_residual(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
+hipError_t launch_canon_residual(gd_dtype tin, gd_dtype t1, gd_dtype s, int mode, const Geom& g, const void* I0,
                                  const void* I1, const void* E, const double* x64, void* r_out,
                                  const double* inv_scale, double* partials, hipStream_t st, double* x64_out,
                                  const double* e_scale) {
   if (g.nblocks == 0) return hipSuccess;
-#define L2(TI, T)                                                                                              \
-  if (mode == 0)                                                                                               \
-    corr_stencil_launch<TI, T, 1, 0>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, nullptr, st); \
-  else if (mode == 1)                                                                                          \
-    corr_stencil_launch<TI, T, 1, 1>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, nullptr, st); \
-  else                                                                                                         \
-    corr_stencil_launch<TI, T, 1, 2>(g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, x64_out, e_scale, st)
+  hipError_t e = hipSuccess;
+#define L2(TI, T)                                                                                               \
+  if (mode == 0)                                                                                                \
+    e = corr_stencil_launch<TI, T, 1, 0>(t1, tin, g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, \
+                                         nullptr, st);                                                          \
+  else if (mode == 1)                                                                                           \
+    e = corr_stencil_launch<TI, T, 1, 1>(t1, tin, g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, \
+                                         nullptr, st);                                                          \
+  else                                                                                                          \
+    e = corr_stencil_launch<TI, T, 1, 2>(t1, tin, g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, x64_out, \
+                                         e_scale, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1
 #undef L2
+  if (e != hipSuccess) return e;
   return last();
 }
 

@@ -387,13 +387,23 @@ extern "C" {
 
 const char* gd_net_last_error(void) { return t_err.c_str(); }
 
-gd_status gd_net_create(gd_net** out, uint64_t seed) {
+gd_status gd_net_create(gd_net** out, const float* weights, int64_t count, uint64_t seed) {
   if (!out) return nfail(GD_ERR_INVALID, "gd_net_create: null handle pointer");
   *out = nullptr;
   return guard([&]() -> gd_status {
     auto N = std::make_unique<gd_net>();
     N->layout();
+    if (weights && count != N->nparam)
+      return nfail(GD_ERR_INVALID, "gd_net_create: weight count " + std::to_string(count) + " != " +
+                                       std::to_string(N->nparam));
     N->alloc_params();
+    if (weights) {  // the caller's FP32 master weights (gd_net_get_params layout)
+      NT_TRY(hipMemcpy(N->master.p, weights, N->nparam * 4, hipMemcpyHostToDevice));
+      N->pack(nullptr);
+      NT_TRY(hipDeviceSynchronize());
+      *out = N.release();
+      return GD_OK;
+    }
     // He-normal weights (Box-Muller on splitmix64), zero biases
     std::vector<float> h(N->nparam, 0.f);
     uint64_t c = seed * 0x2545F4914F6CDD1Dull + 1;

@@ -74,21 +74,27 @@ def test_option_checks(lib):
 
 def test_slice_argument_checks(lib):
     d = gd.make_slice_descs([0, 50], 10, 10, 0.01)
-    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, 2, 1.0, 1.0, None, None, None,
+    assert lib.gd_screened_poisson_slices(P(64), 1, P(128), 1, P(256), 1, d, 2, 1.0, 1.0, None, None, None,
                                           None) == gd.ERR_INVALID  # slices overlap
     d = gd.make_slice_descs([0, 100], 10, 10, 0.0)
-    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, 2, 1.0, 1.0, None, None, None,
+    assert lib.gd_screened_poisson_slices(P(64), 1, P(128), 1, P(256), 1, d, 2, 1.0, 1.0, None, None, None,
                                           None) == gd.ERR_INVALID  # alpha must be > 0
     d = gd.make_slice_descs([0], 10, 10, 0.01, pitch=[5])
-    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, 1, 1.0, 1.0, None, None, None,
+    assert lib.gd_screened_poisson_slices(P(64), 1, P(128), 1, P(256), 1, d, 1, 1.0, 1.0, None, None, None,
                                           None) == gd.ERR_INVALID  # pitch < nx
-    assert lib.gd_screened_poisson_slices(P(64), P(128), P(64), 1, d, 1, 1.0, 1.0, None, None, None,
+    assert lib.gd_screened_poisson_slices(P(64), 1, P(128), 1, P(64), 1, d, 1, 1.0, 1.0, None, None, None,
                                           None) == gd.ERR_INVALID  # aliasing
-    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, -1, 1.0, 1.0, None, None, None,
+    assert lib.gd_screened_poisson_slices(P(64), 1, P(128), 1, P(256), 1, d, -1, 1.0, 1.0, None, None, None,
                                           None) == gd.ERR_INVALID  # negative count
+    d = gd.make_slice_descs([0], 10, 10, 0.01)
+    for t1 in (gd.F16, gd.BF16, 9):  # I1 must have I0's dtype, F32 or F64
+        assert lib.gd_screened_poisson_slices(P(64), gd.F64, P(128), t1, P(256), 1, d, 1, 1.0, 1.0, None, None,
+                                              None, None) == gd.ERR_INVALID
+    assert lib.gd_screened_poisson_slices(P(64), 1, P(128), 1, P(256), 7, d, 1, 1.0, 1.0, None, None, None,
+                                          None) == gd.ERR_INVALID  # bad output dtype
     rep = gd.Report()
     rep.cycles = 7
-    assert lib.gd_screened_poisson_slices(None, None, None, 1, None, 0, 1.0, 1.0, None, ctypes.byref(rep),
+    assert lib.gd_screened_poisson_slices(None, 1, None, 1, None, 1, None, 0, 1.0, 1.0, None, ctypes.byref(rep),
                                           None, None) == gd.OK  # an empty batch touches nothing
     assert rep.cycles == 0
 
@@ -137,7 +143,7 @@ def test_plane_size_limit(lib):
     assert lib.gd_smooth_z(P(64), 1, P(128), 1, 1 << 15, 1 << 14, 2, 1.0, 1.0, 4.0, None, None,
                            None) == gd.ERR_UNSUPPORTED
     d = gd.make_slice_descs([0], 10, 10, 0.01, pitch=[(1 << 28) + 1])
-    assert lib.gd_screened_poisson_slices(P(64), P(128), P(256), 1, d, 1, 1.0, 1.0, None, None, None,
+    assert lib.gd_screened_poisson_slices(P(64), 1, P(128), 1, P(256), 1, d, 1, 1.0, 1.0, None, None, None,
                                           None) == gd.ERR_UNSUPPORTED
 
 
@@ -168,3 +174,65 @@ def test_streamed_hierarchy_argument_checks(lib):
     assert lib.gd_hierarchy_device_bytes(None, None, None) == gd.ERR_INVALID
     assert lib.gd_hierarchy_streamed_levels(None, None) == gd.ERR_INVALID
     assert lib.gd_last_error()
+
+
+def test_binding_refuses_out_of_bounds_slices():
+    """The binding checks dtypes and that every slice lies inside each array
+    before any call reaches the library (the kernels cannot see sizes)."""
+    torch = pytest.importorskip("torch")
+    d = gd.make_slice_descs([0, 100], 10, 10, 0.01)
+    assert gd.slice_span(d) == 200
+    assert gd.slice_span(gd.make_slice_descs([5], 4, 3, 0.01, pitch=[8])) == 5 + 8 * 2 + 4
+
+    class Fake:  # a stand-in GPU tensor: the checks run before any pointer is used
+        def __init__(self, n, dtype):
+            self.shape, self.dtype, self.is_cuda, self._n = (n,), dtype, True, n
+
+        def numel(self):
+            return self._n
+
+        def is_contiguous(self):
+            return True
+
+        def data_ptr(self):
+            return 0
+
+    ok, short = Fake(200, torch.float32), Fake(199, torch.float32)
+    with pytest.raises(ValueError, match="reach"):
+        gd.screened_poisson_slices(ok, Fake(200, torch.float32), d, out=short)
+    with pytest.raises(ValueError, match="reach"):
+        gd.screened_poisson_slices(short, Fake(199, torch.float32), d, out=ok)
+    with pytest.raises(ValueError, match="I1"):
+        gd.screened_poisson_slices(Fake(200, torch.float32), Fake(200, torch.float16), d, out=ok)
+    with pytest.raises(ValueError, match="out_dtype"):
+        gd.screened_poisson_slices(ok, Fake(200, torch.float32), d, out=Fake(200, torch.float16),
+                                   out_dtype=torch.float32)
+
+
+def test_binding_refuses_mismatched_hierarchy_arrays():
+    torch = pytest.importorskip("torch")
+    h = gd.Hierarchy.__new__(gd.Hierarchy)  # checks only: no library call is made
+    h.shape, h.dtype, h._h = (4, 4, 4), torch.float32, None
+    good = torch.zeros(4, 4, 4)
+    with pytest.raises(ValueError):
+        h.vcycle(torch.zeros(4, 4, 5), good)
+    with pytest.raises(ValueError):
+        h.vcycle(good.double(), good)
+    with pytest.raises(ValueError):
+        h.error_pairs(torch.zeros(2, 4, 4), good, 1)
+    with pytest.raises(ValueError):
+        h.rhs(torch.zeros(4, 4, 4, dtype=torch.float16))
+    n = gd.Net.__new__(gd.Net)
+    n._n = None
+    with pytest.raises(ValueError):
+        n.forward(torch.zeros(1, 4, 256, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        n.train_step(torch.zeros(1, 4, 256), torch.zeros(1, 4, 128))
+
+
+def test_net_create_takes_weights(lib):
+    h = ctypes.c_void_p()
+    w = (ctypes.c_float * 3)()
+    # a wrong count is refused before any device work
+    assert lib.gd_net_create(ctypes.byref(h), w, 3, 0) == gd.ERR_INVALID
+    assert lib.gd_net_create(None, None, 0, 0) == gd.ERR_INVALID

@@ -7,6 +7,8 @@
   global input mean; the oracle's own residual on sampled slabs).
 """
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -51,7 +53,10 @@ def test_stack1k_full_against_dct(gd):
 @pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
 def test_stack4k_crop_mixed(gd, dt):
     """The 512x512x32 crop of the 4096x4096x256 stack, solved as its own
-    problem with 16-bit storage and FP64 refinement."""
+    problem with 16-bit storage of the input and the V-cycles and FP64
+    refinement, end to end: the FP64 result of the anisotropic diffusion
+    feeds the screened-Poisson phase, whose refined result comes back in
+    FP64.  Both phases and the pipeline match the FP64 oracle to 1e-6."""
     say("stack4k crop mixed", dt)
     spec = synth.CONFIGS["stack4k"]
     full = synth.make_stack(spec, device="cuda", z_range=(0, 32))
@@ -63,12 +68,17 @@ def test_stack4k_crop_mixed(gd, dt):
     ref1 = osv.ad_dct(a0, BETA)
     assert r1["rel_residual"] <= 5e-8
     assert rel(I1.cpu().numpy(), ref1) <= 1e-6
-    I1q = I1.to(dt)
-    I2, r2, _ = gd.screened_poisson_stack(crop, I1q, 0.01, storage=st, fp64_refine=1, rel_tol=5e-8)
-    ref2 = osv.sp_dct(a0, I1q.double().cpu().numpy(), 0.01)
-    # I2 is returned in the 16-bit input type: compare at its resolution
-    tol = 2e-3 if dt == torch.float16 else 8e-3
-    assert rel(I2.double().cpu().numpy(), ref2) <= tol
+    I2, r2, per = gd.screened_poisson_stack(crop, I1, 0.01, storage=st, fp64_refine=1, rel_tol=5e-8,
+                                            out_dtype=torch.float64)
+    assert I2.dtype == torch.float64 and r2["rel_residual"] <= 5e-8
+    assert max(p["rel_residual"] for p in per) <= 5e-8
+    got = I2.cpu().numpy()
+    # the phase as run (value target: the GPU's own FP64 AD result) ...
+    e_phase = rel(got, osv.sp_dct(a0, I1.cpu().numpy(), 0.01))
+    # ... and the whole pipeline against the oracle's AD then SP
+    e_pipe = rel(got, osv.sp_dct(a0, ref1, 0.01))
+    say(f"AD err {rel(I1.cpu().numpy(), ref1):.2e}; SP err {e_phase:.2e}; pipeline err {e_pipe:.2e}")
+    assert e_phase <= 1e-6 and e_pipe <= 1e-6
     gd.release_workspace()
 
 
@@ -100,41 +110,53 @@ def test_stack4k_full_properties(gd, dt):
     torch.cuda.empty_cache()
 
 
-def test_slices2048_full_sampled(gd):
+def _sp_slice_errors(gd, meta, I2, idx):
+    """Relative error of each slice in `idx` against the FP64 DCT oracle of
+    its own system (slices copied to the host one at a time; the oracle runs
+    in a thread pool, scipy's transforms release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    w, h, a, off = meta["w"], meta["h"], meta["alpha"], meta["offset"]
+
+    def one(i):
+        n = int(w[i]) * int(h[i])
+        sh = (1, int(h[i]), int(w[i]))
+        s0 = meta["I0h"][off[i]:off[i] + n].astype(np.float64).reshape(sh)
+        s1 = meta["I1h"][off[i]:off[i] + n].astype(np.float64).reshape(sh)
+        got = meta["I2h"][off[i]:off[i] + n].astype(np.float64).reshape(sh)
+        return rel(got, osv.sp_dct(s0, s1, float(np.float32(a[i]))))
+
+    meta["I0h"], meta["I1h"], meta["I2h"] = (t.cpu().numpy() for t in (meta["I0"], meta["I1"], I2))
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return np.array(list(ex.map(one, idx)))
+
+
+def test_slices2048_full_all_slices(gd):
     """The 2048 uneven slices of the batched workload, solved as bench.py
-    solves them (one batched solve, FP32, 1e-6 per slice); sampled slices —
-    the smallest, the largest, the most and least screened and a few random
-    ones — against the FP64 DCT oracle of their own systems, and every
-    slice's residual against its own right-hand side."""
-    say("slices2048 full batch, sampled slices vs DCT")
+    solves them (one batched solve, FP32, V(1,2)) to 2e-7 per slice, so that
+    the error bar of 1e-5 holds; every slice against the FP64 DCT oracle of
+    its own system."""
+    say("slices2048 full batch, every slice vs DCT")
     meta = synth.make_slice_batch(device="cuda", dtype=torch.float32)
     descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
-    I2, rep, per = gd.screened_poisson_slices(meta["I0"], meta["I1"], descs, rel_tol=1e-6, pre_smooth=1,
-                                              post_smooth=2)
-    print("batch", rep, flush=True)
-    assert max(p["rel_residual"] for p in per) <= 1e-6
-    w, h, a, off = meta["w"], meta["h"], meta["alpha"], meta["offset"]
-    area = w * h
-    rng = np.random.default_rng(5)
-    pick = {int(np.argmin(area)), int(np.argmax(area)), int(np.argmin(a)), int(np.argmax(a))}
-    pick |= set(int(i) for i in rng.choice(len(w), 4, replace=False))
-    for i in sorted(pick):
-        n = int(area[i])
-        s0 = meta["I0"][off[i]:off[i] + n].double().cpu().numpy().reshape(1, h[i], w[i])
-        s1 = meta["I1"][off[i]:off[i] + n].double().cpu().numpy().reshape(1, h[i], w[i])
-        got = I2[off[i]:off[i] + n].double().cpu().numpy().reshape(1, h[i], w[i])
-        ref = osv.sp_dct(s0, s1, float(np.float32(a[i])))
-        err = rel(got, ref)
-        say(f"slice {i} {w[i]}x{h[i]} alpha {a[i]:.4f}: rel err {err:.2e}")
-        # relative residual 1e-6 with the SP operator's condition (alpha >= 0.001)
-        assert err <= 2e-5
+    I2, rep, per = gd.screened_poisson_slices(meta["I0"], meta["I1"], descs, rel_tol=2e-7, pre_smooth=1,
+                                              post_smooth=2, check=False)
+    print("batch", {k: rep[k] for k in ("cycles", "rel_residual", "status")}, flush=True)
+    res = np.array([p["rel_residual"] for p in per])
+    assert res.max() <= 1e-6
+    err = _sp_slice_errors(gd, meta, I2, range(len(descs)))
+    worst = int(np.argmax(err))
+    say(f"{len(err)} slices: max rel err {err.max():.2e} (slice {worst}, {meta['w'][worst]}x{meta['h'][worst]}, "
+        f"alpha {meta['alpha'][worst]:.4f}), median {np.median(err):.2e}")
+    assert err.max() <= 1e-5
 
 
 def test_learned2k_full_sampled(gd):
     """The learned workload's solve (2048x2048x64 per-slice SP, alpha 0.01)
     by flexible CG with the V-cycle + net preconditioner, as bench.py runs it
-    after training: the true residual reaches 1e-6 and sampled slices agree
-    with the FP64 DCT oracle."""
+    after training: the net stays in use (no fallback to the V-cycle), the
+    true residual reaches 1e-6 and sampled slices agree with the FP64 DCT
+    oracle to 1e-5."""
     say("learned2k full solve, sampled slices vs DCT")
     n, nz, alpha = 2048, 64, 0.01
     spec = synth.StackSpec(n, n, nz, (4.0, 40.0), True, 13100431)
@@ -166,8 +188,9 @@ def test_learned2k_full_sampled(gd):
     net.close()
     print("fcg", rep, flush=True)
     assert rep["rel_residual"] <= 1e-6
+    assert rep["fallback_used"] == 0
     for z in (0, 31, 63):
         ref = osv.dct_solve(b[z:z + 1].double().cpu().numpy(), alpha, (1.0, 1.0, 0.0))
         err = rel(x[z:z + 1].double().cpu().numpy(), ref)
         say(f"slice {z}: rel err {err:.2e}")
-        assert err <= 2e-5
+        assert err <= 1e-5

@@ -252,6 +252,65 @@ def test_sp_batched_mixed_bf16(gd):
         assert rel(out[o:o + w * h].reshape(1, h, w), ref) <= 4e-3
 
 
+@pytest.mark.parametrize("tin,t1,tout,storage,refine", [
+    (torch.bfloat16, torch.float64, torch.float64, "bf16", 1),
+    (torch.float16, torch.float32, torch.float32, "f16", 1),
+    (torch.float32, torch.float64, torch.float64, "f32", 0),
+    (torch.float64, torch.float32, torch.float64, "f64", 0),
+])
+def test_sp_batched_wider_target_and_output(gd, tin, t1, tout, storage, refine):
+    """Eq. (2) with I1 wider than I0 (the refined FP64 or FP32 result of the
+    first phase) and the result returned in its own type: element-wise
+    against the oracle on the same values, at the 1e-6 bar after refinement
+    (1e-5 for the plain FP32 correction)."""
+    say("SP batch wider I1/out", tin, t1, tout, storage, refine)
+    meta = synth.make_slice_batch(nslices=9, lo=20, hi=180, seed=79, dtype=torch.float64)
+    I0 = meta["I0"].to(tin).cuda()
+    I1 = (meta["I1"] + 0.123456789).to(t1).cuda()  # digits beyond I0's precision
+    descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
+    st = {"bf16": gd.BF16, "f16": gd.F16, "f32": gd.F32, "f64": gd.F64}[storage]
+    tol = 2e-7 if refine or storage == "f64" else 1e-6
+    I2, rep, per = gd.screened_poisson_slices(I0, I1, descs, storage=st, fp64_refine=refine, rel_tol=tol,
+                                              out_dtype=tout)
+    assert I2.dtype == tout and rep["rel_residual"] <= tol
+    a0, a1, out = host(I0), host(I1), host(I2)
+    bar = 1e-5 if (storage == "f32" and not refine) else 1e-6
+    for i in range(9):
+        o, w, h = meta["offset"][i], meta["w"][i], meta["h"][i]
+        ref = osv.sp_dct(a0[o:o + w * h].reshape(1, h, w), a1[o:o + w * h].reshape(1, h, w),
+                         float(np.float32(meta["alpha"][i])))
+        assert rel(out[o:o + w * h].reshape(1, h, w), ref) <= bar, i
+        assert per[i]["rel_residual"] <= tol
+        assert per[i]["bytes"] > 0
+    assert abs(sum(p["bytes"] for p in per) - rep["bytes"]) <= 1e-6 * rep["bytes"]
+
+
+def test_sp_new_alphas_reuse_the_hierarchy(gd):
+    """A second batch of the same slice sizes with other alphas reuses the
+    cached hierarchy (no new device memory) and gives what a fresh hierarchy
+    gives, bit for bit."""
+    say("SP new alphas, cached hierarchy")
+    meta = synth.make_slice_batch(nslices=12, lo=40, hi=260, seed=80, dtype=torch.float32)
+    I0, I1 = meta["I0"].cuda(), meta["I1"].cuda()
+    w, h, off = meta["w"], meta["h"], meta["offset"]
+    d1 = gd.make_slice_descs(off, w, h, meta["alpha"])
+    d2 = gd.make_slice_descs(off, w, h, np.random.default_rng(3).uniform(0.001, 0.1, len(w)))
+    gd.release_workspace()
+    gd.screened_poisson_slices(I0, I1, d1)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    cached, _, _ = gd.screened_poisson_slices(I0, I1, d2)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free1 >= free0 - (1 << 20), (free0, free1)
+    gd.release_workspace()
+    fresh, _, _ = gd.screened_poisson_slices(I0, I1, d2)
+    assert torch.equal(cached, fresh)
+    again, _, _ = gd.screened_poisson_slices(I0, I1, d1)  # and back: the first alphas again
+    first, _, _ = gd.screened_poisson_slices(I0, I1, d1)
+    assert torch.equal(again, first)
+
+
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_general_system_hierarchy(gd, dt):
     say("general hierarchy", dt)
