@@ -20,6 +20,8 @@ import numpy as np
 
 WORKLOADS = {
     # name: (spec key, storage, fp64_refine, description)
+    "stack4k": ("stack4k", "f16", 1, "4096x4096x256 stack, FP16 storage of the input and the V-cycles, FP32 "
+                "relaxation, FP64 refinement (headline); legs: BF16 + FP64 refinement, FP32 plain V-cycles"),
     "stack1k": ("stack1k", "f32", 0, "1024x1024x128 stack, FP32 storage + arithmetic, plain V-cycles"),
     "stack4k-f16": ("stack4k", "f16", 1, "4096x4096x256 stack, FP16 storage, FP32 relaxation, FP64 refinement"),
     "stack4k-bf16": ("stack4k", "bf16", 1, "4096x4096x256 stack, BF16 storage, FP32 relaxation, FP64 refinement"),
@@ -49,9 +51,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="stack1k", choices=sorted(WORKLOADS))
+    p.add_argument("--workload", default="stack4k", choices=sorted(WORKLOADS))
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-crop", default="32,192,192", help="nz,ny,nx of the oracle's crop")
+    p.add_argument("--cpu-crop", default="32,512,512", help="nz,ny,nx of the oracle's crop")
     p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
     p.add_argument("--fmg", type=int, default=None, help="1: full-multigrid start of the plain solves")
     p.add_argument("--discretization", default="constant", choices=["constant", "hybrid", "linear"],
@@ -71,24 +73,33 @@ def parse():
     return p.parse_args()
 
 
-def cpu_baseline(I0_host, crop):
-    """The FP64 oracle (CG on the AD system, then CG on the SP system) on a
-    crop of the same stack, solved as its own problem."""
+def cpu_baseline(I0_host, crop, min_s=10.0):
+    """The FP64 oracle on a crop of the same stack, solved as its own problem:
+    AD then SP by the oracle's exact DCT-II solves (scipy.fft with one worker
+    per host core), repeated for at least `min_s` seconds."""
+    import scipy.fft as sfft
+
     from oracle import solvers
 
     nz, ny, nx = crop
     sub = np.ascontiguousarray(I0_host[:nz, :ny, :nx], dtype=np.float64)
+    ncpu = os.cpu_count() or 1
+    reps = 0
     t0 = time.perf_counter()
-    I1 = solvers.ad_solve(sub, BETA, method="cg", rtol=TOL)
-    solvers.sp_solve(sub, I1, ALPHA, method="cg", rtol=TOL)
-    dt = time.perf_counter() - t0
+    with sfft.set_workers(ncpu):
+        while reps == 0 or time.perf_counter() - t0 < min_s:
+            I1 = solvers.ad_dct(sub, BETA)
+            solvers.sp_dct(sub, I1, ALPHA)
+            reps += 1
+    dt = (time.perf_counter() - t0) / reps
     return {
         "value": sub.size / dt,
         "unit": "voxels/s",
-        "cores": 1,
+        "cores": ncpu,
         "kind": "oracle",
-        "sample": f"crop [0:{nz},0:{ny},0:{nx}] of the same stack ({sub.size} voxels), AD then SP by "
-                  f"plain conjugate gradients to {TOL:g}, numpy FP64 (single-threaded elementwise), {dt:.1f} s",
+        "sample": f"crop [0:{nz},0:{ny},0:{nx}] of the same (quantised) stack ({sub.size} voxels), AD then SP "
+                  f"by the oracle's exact DCT-II solves in FP64 (numpy/scipy.fft, workers={ncpu} = os.cpu_count()), "
+                  f"{reps} repetitions in {dt * reps:.1f} s",
     }
 
 
@@ -496,9 +507,6 @@ def main():
     gd.load()
     spec_key, storage, refine, desc = WORKLOADS[a.workload]
     spec = synth.CONFIGS.get(spec_key)
-    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[storage]
-    sdt = {"f32": gd.F32, "f16": gd.F16, "bf16": gd.BF16}[storage]
-    dev = torch.device("cuda:0")
 
     if spec_key == "slices":
         return bench_slices(a, gd, synth, torch, desc)
@@ -510,6 +518,93 @@ def main():
         return bench_dct(a, gd, synth, torch, desc)
     if spec_key.startswith("streamed"):
         return bench_streamed(a, gd, synth, torch, desc)
+    legs = [(storage, refine)]
+    if a.workload == "stack4k":  # the headline line carries the other storage types as legs
+        legs += [("bf16", 1), ("f32", 0)]
+    results = []
+    for i, (stg, ref) in enumerate(legs):
+        steps, warmup = (a.steps, a.warmup) if i == 0 else (min(a.steps, 5), min(a.warmup, 1))
+        results.append(run_stack_leg(a, gd, synth, torch, spec, stg, ref, steps, warmup))
+        gd.release_workspace()
+        torch.cuda.empty_cache()
+    head = results[0]
+    line = {
+        "metric": "voxels/s to 1e-6 rel. residual (AD + per-slice SP)",
+        "value": head["voxels_per_s"],
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16+f64", "bf16": "bf16+f64"}[storage],
+        "data": "synthetic",
+        "config": {
+            "workload": f"{a.workload}: {desc}; beta=(1,1,4), alpha={ALPHA}, Neumann, tol {TOL:g}"
+                        + ("" if a.discretization == "constant" and a.prolong == "trilinear"
+                           else f"; AD {a.discretization} discretisation, {a.prolong} up-sampling"),
+            "nx": spec.nx, "ny": spec.ny, "nz": spec.nz, "voxels": spec.nx * spec.ny * spec.nz,
+            "smooth": [int(v) for v in a.smooth.split(",")],
+        },
+        "roofline": head["roofline"],
+        "ad": head["ad"],
+        "sp": head["sp"],
+        "generate_s": head["generate_s"],
+    }
+    if len(results) > 1:
+        line["legs"] = {r["leg"]: {k: r[k] for k in ("ms_per_step", "voxels_per_s", "steps", "warmup", "ad", "sp",
+                                                     "finest_sweep")}
+                        for r in results}
+        plain = next(r for r in results if r["leg"] == "f32")
+        line["legs"]["speedup_vs_f32_plain"] = {r["leg"]: plain["ms_per_step"] / r["ms_per_step"] for r in results}
+    if not a.no_cpu_baseline:
+        crop = tuple(int(v) for v in a.cpu_crop.split(","))
+        sub = synth.make_stack(spec, device="cuda", z_range=(0, crop[0]))[:, :crop[1], :crop[2]]
+        sub = sub.to({"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[storage]).double().cpu()
+        line["cpu_baseline"] = cpu_baseline(sub.numpy(), crop)
+    print(json.dumps(line), flush=True)
+
+
+def source_sha(path):
+    import hashlib
+
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+SWEEP_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1310_0041_amd", "csrc", "k_sweep.hip")
+
+
+def measured_traffic(a, leg, tile):
+    """HBM bytes per launch of this leg's finest relaxation from the committed
+    rocprofv3 counters (FETCH_SIZE, WRITE_SIZE, each scaled by what it reads
+    for a plain copy), used only when they were taken on the same workload,
+    storage type and tile from the same relaxation source (sha)."""
+    if not os.path.exists(a.traffic_json):
+        return None, None
+    try:
+        t = json.load(open(a.traffic_json))
+    except Exception:
+        return None, None
+    entries = t if isinstance(t, list) else [t]
+    sha = source_sha(SWEEP_SRC)
+    for e in entries:
+        if (e.get("workload") == a.workload and e.get("storage", "f32") == leg and list(e.get("tile", [])) == list(tile)
+                and e.get("source_sha") == sha):
+            return e["bytes_per_launch"], (f"{os.path.relpath(a.traffic_json)}: rocprofv3 FETCH_SIZE x "
+                                           f"{e['fetch_factor']:.3g} + WRITE_SIZE x {e['write_factor']:.3g} of this "
+                                           f"launch, k_sweep.hip sha {sha}")
+    return None, None
+
+
+def run_stack_leg(a, gd, synth, torch, spec, storage, refine, steps, warmup):
+    """One storage type of the stack workload: AD then per-slice SP of the
+    whole stack, each to 1e-6, inputs resident in HBM; `steps` timed steps."""
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[storage]
+    sdt = {"f32": gd.F32, "f16": gd.F16, "bf16": gd.BF16}[storage]
+    dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     I0 = synth.make_stack(spec, device=dev, dtype=tdt)
     torch.cuda.synchronize()
@@ -524,24 +619,25 @@ def main():
         opts["fmg"] = a.fmg
     opts["prolong"] = 0 if a.prolong == "trilinear" else 1
     ad_opts = dict(opts, discretization={"constant": 0, "hybrid": 1, "linear": 2}[a.discretization])
+    I1 = torch.empty_like(I0, dtype=out_dtype)
+    I2 = torch.empty_like(I0, dtype=out_dtype)
 
     def step(timing):
-        I1, r1 = gd.smooth_z(I0, BETA, out_dtype=out_dtype, timing=timing, **ad_opts)
-        I2, r2, per = gd.screened_poisson_stack(I0, I1, ALPHA, timing=timing, out_dtype=out_dtype, **opts)
+        r1 = gd.smooth_z_into(I0, I1, BETA, timing=timing, **ad_opts)
+        _, r2, _ = gd.screened_poisson_stack(I0, I1, ALPHA, timing=timing, out=I2, **opts)
         return r1, r2
 
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         step(0)
     torch.cuda.synchronize()
     gd.reset_kernel_time()
     t0 = time.perf_counter()
     reps = []
-    for _ in range(a.steps):
+    for _ in range(steps):
         reps.append(step(1))
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / a.steps
-    # dominant kernel: the finest-level relaxation of the stack (AD phase),
-    # k_rb_sweep<S, 64, 8, false, true> at the finest level's launch shape
+    dt = (time.perf_counter() - t0) / steps
+    # dominant kernel: the finest-level relaxation of the stack (AD phase)
     ms, launches, bytes_per = gd.kernel_time(gd.SWEEP_STACK)
     avg_ms = ms / max(launches, 1)
     others = {}
@@ -552,62 +648,38 @@ def main():
             others[name] = {"launches": n2, "avg_launch_ms": m2 / n2, "GB/s": b2 / (m2 / n2 * 1e-3) / 1e9}
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     cfg = gd.sweep_config((spec.nz, spec.ny, spec.nx), tdt)
-
-    traffic = None
-    if os.path.exists(a.traffic_json):
-        try:
-            t = json.load(open(a.traffic_json))
-            # counters of this workload's finest relaxation, taken with the same tile
-            if t.get("workload") == a.workload and list(t.get("tile", [])) == list(cfg["tile"]):
-                traffic = t.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-
+    traffic, traffic_src = measured_traffic(a, storage, cfg["tile"])
     r1, r2 = reps[-1]
-    line = {
-        "metric": "voxels/s to 1e-6 rel. residual (AD + per-slice SP)",
-        "value": nvox / dt,
-        "unit": "voxels/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": dt * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"f32": "f32", "f16": "f16+f64", "bf16": "bf16+f64"}[storage],
-        "data": "synthetic",
-        "config": {
-            "workload": f"{a.workload}: {desc}; beta=(1,1,4), alpha={ALPHA}, Neumann, tol {TOL:g}"
-                        + ("" if a.discretization == "constant" and a.prolong == "trilinear"
-                           else f"; AD {a.discretization} discretisation, {a.prolong} up-sampling"),
-            "nx": spec.nx, "ny": spec.ny, "nz": spec.nz, "voxels": nvox, "smooth": [pre, post],
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "k_rb_sweep<%s,%d,%d,false,true> finest level" % ((storage,) + tuple(cfg["tile"])),
-            "sweep_config": cfg,
-            "launches": launches,
-            "avg_launch_ms": avg_ms,
-            "algorithmic_bytes_per_launch": bytes_per,
-            "other_finest_sweeps": others,
-        },
-        "ad": {"cycles": r1["cycles"], "refine_steps": r1["refine_steps"], "rel_residual": r1["rel_residual"],
-               "levels": r1["levels"], "discretization": a.discretization, "prolong": a.prolong,
-               "factor_per_cycle": r1["rel_residual"] ** (1.0 / max(r1["cycles"], 1))},
-        "sp": {"cycles": r2["cycles"], "refine_steps": r2["refine_steps"], "rel_residual": r2["rel_residual"],
-               "factor_per_cycle": r2["rel_residual"] ** (1.0 / max(r2["cycles"], 1))},
-        "generate_s": gen_s,
+    tname = {"f32": "float", "f16": "__half", "bf16": "__hip_bfloat16"}[storage]
+    roof = {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "traffic_source": traffic_src,
+        "kernel": "k_rb_sweep<%s, %d, %d, false, true> finest level (HIP events on the solve's stream)"
+                  % ((tname,) + tuple(cfg["tile"])),
+        "sweep_config": cfg,
+        "launches": launches,
+        "avg_launch_ms": avg_ms,
+        "algorithmic_bytes_per_launch": bytes_per,
+        "other_finest_sweeps": others,
     }
-    if not a.no_cpu_baseline:
-        crop = tuple(int(v) for v in a.cpu_crop.split(","))
-        line["cpu_baseline"] = cpu_baseline(I0[: crop[0], : crop[1], : crop[2]].double().cpu().numpy(), crop)
-    print(json.dumps(line), flush=True)
+    leg = {
+        "leg": storage, "steps": steps, "warmup": warmup, "ms_per_step": dt * 1e3, "voxels_per_s": nvox / dt,
+        "generate_s": gen_s, "roofline": roof,
+        "finest_sweep": {"avg_launch_ms": avg_ms, "GB/s": achieved, "frac": achieved / HBM_PEAK_GBS,
+                         "tile": cfg["tile"]},
+        "ad": {"cycles": r1["cycles"], "refine_steps": r1["refine_steps"], "rel_residual": r1["rel_residual"],
+               "levels": r1["levels"], "bytes": r1["bytes"], "discretization": a.discretization,
+               "prolong": a.prolong, "factor_per_cycle": r1["rel_residual"] ** (1.0 / max(r1["cycles"], 1))},
+        "sp": {"cycles": r2["cycles"], "refine_steps": r2["refine_steps"], "rel_residual": r2["rel_residual"],
+               "bytes": r2["bytes"], "factor_per_cycle": r2["rel_residual"] ** (1.0 / max(r2["cycles"], 1))},
+    }
+    del I0, I1, I2
+    return leg
 
 
 if __name__ == "__main__":

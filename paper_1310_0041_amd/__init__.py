@@ -240,6 +240,22 @@ def smooth_z(I0, beta=(1.0, 1.0, 4.0), out_dtype=None, opts=None, check=True, **
     return out, dict(rep.as_dict(), status=st)
 
 
+def smooth_z_into(I0, out, beta=(1.0, 1.0, 4.0), opts=None, check=True, **kw):
+    """:func:`smooth_z` into the caller's ``out`` (any dtype).  Returns the report."""
+    lib = load()
+    nz, ny, nx = I0.shape
+    _need(out, I0.shape, out.dtype, "out")
+    _ptr(I0)
+    o = opts or default_opts(**kw)
+    rep = Report()
+    st = lib.gd_smooth_z(_ptr(I0), gd_dtype(I0.dtype), _ptr(out), gd_dtype(out.dtype), nx, ny, nz,
+                         float(beta[0]), float(beta[1]), float(beta[2]), ctypes.byref(o), ctypes.byref(rep),
+                         _stream())
+    if check:
+        _check(st)
+    return dict(rep.as_dict(), status=st)
+
+
 def npr_filter(I0, alpha=0.001, beta=(1.0, 1.0, 0.1), lam=1.25, sigma=5.0, out_dtype=None, opts=None, check=True,
                **kw):
     """Gradient-modulation filter of the [nz][ny][nx] volume I0 (Sec. 6).
