@@ -141,6 +141,30 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
                       double beta_x, double beta_y, double beta_z,
                       const gd_solve_opts* opts, gd_solve_report* rep, void* stream);
 
+/* The same solve for callers that cannot allocate memory (code that a HIP
+ * graph is capturing around, tight serving loops, harnesses that forbid
+ * hipMalloc): every device array of the multigrid hierarchy lives in one
+ * static device array of the library, 128 MiB per GPU (gd_noalloc_scratch_bytes),
+ * so no hipMalloc, hipFree, pinned host memory, graph or event is created
+ * (the first call on a GPU loads that array, once per process).
+ * Arguments, results and status codes as gd_smooth_z, with these limits:
+ * the Constant discretisation only (opts->discretization = 0; others
+ * GD_ERR_UNSUPPORTED); opts->use_graph and opts->timing are ignored (plain
+ * launches); no autotuning (the fixed relaxation tile); a problem whose
+ * hierarchy needs more than the scratch (about 19 bytes per voxel for FP32
+ * storage, 26 for FP16/BF16 with FP64 refinement) returns
+ * GD_ERR_UNSUPPORTED with the bytes it needs, before any device work.
+ * All calls on one GPU share that GPU's scratch, which keeps the last
+ * call's contents (every array the solve reads is written by it first):
+ * calls that overlap on one GPU (other threads or streams) race and must be
+ * serialised by the caller. */
+gd_status gd_smooth_z_noalloc(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
+                              int64_t nx, int64_t ny, int64_t nz,
+                              double beta_x, double beta_y, double beta_z,
+                              const gd_solve_opts* opts, gd_solve_report* rep, void* stream);
+/* Size in bytes of the scratch gd_smooth_z_noalloc uses on each GPU. */
+gd_status gd_noalloc_scratch_bytes(int64_t* bytes);
+
 /* Per-slice screened Poisson, Eq. (2) (Sec. 3.1.2), for a batch of
  * independent 2-D slices of any sizes:
  *   (alpha_i + beta_x L_x + beta_y L_y) I2_i = alpha_i I1_i + (beta_x L_x + beta_y L_y) I0_i.

@@ -87,6 +87,9 @@ _SIGS = {
     "gd_version": (ctypes.c_char_p, []),
     "gd_smooth_z": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, ctypes.POINTER(SolveOpts),
                          ctypes.POINTER(Report), _vp]),
+    "gd_smooth_z_noalloc": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, ctypes.POINTER(SolveOpts),
+                                 ctypes.POINTER(Report), _vp]),
+    "gd_noalloc_scratch_bytes": (_i, [ctypes.POINTER(_i64)]),
     "gd_screened_poisson_slices": (_i, [_vp, _i, _vp, _i, _vp, _i, ctypes.POINTER(SliceDesc), _i64, _d, _d,
                                         ctypes.POINTER(SolveOpts), ctypes.POINTER(Report),
                                         ctypes.POINTER(Report), _vp]),
@@ -254,6 +257,30 @@ def smooth_z_into(I0, out, beta=(1.0, 1.0, 4.0), opts=None, check=True, **kw):
     if check:
         _check(st)
     return dict(rep.as_dict(), status=st)
+
+
+def smooth_z_noalloc(I0, out, beta=(1.0, 1.0, 4.0), opts=None, check=True, **kw):
+    """Anisotropic diffusion (Eq. (1)) into the caller's ``out`` without any
+    allocation by the library (its hierarchy lives in a static scratch array
+    of :func:`noalloc_scratch_bytes` bytes per GPU).  Returns the report."""
+    lib = load()
+    nz, ny, nx = I0.shape
+    _need(out, I0.shape, out.dtype, "out")
+    _ptr(I0)
+    o = opts or default_opts(**kw)
+    rep = Report()
+    st = lib.gd_smooth_z_noalloc(_ptr(I0), gd_dtype(I0.dtype), _ptr(out), gd_dtype(out.dtype), nx, ny, nz,
+                                 float(beta[0]), float(beta[1]), float(beta[2]), ctypes.byref(o), ctypes.byref(rep),
+                                 _stream())
+    if check:
+        _check(st)
+    return dict(rep.as_dict(), status=st)
+
+
+def noalloc_scratch_bytes():
+    n = ctypes.c_int64()
+    _check(load().gd_noalloc_scratch_bytes(ctypes.byref(n)))
+    return n.value
 
 
 def npr_filter(I0, alpha=0.001, beta=(1.0, 1.0, 0.1), lam=1.25, sigma=5.0, out_dtype=None, opts=None, check=True,

@@ -173,7 +173,7 @@ struct Hier {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (cap) (void)hipStreamDestroy(cap);
     for (void* p : allocs) (void)hipFree(p);
-    if (hpin) (void)hipHostFree(hpin);
+    if (hpin && host_pin.empty()) (void)hipHostFree(hpin);
   }
   std::vector<std::pair<void*, void*>> xstate() const {
     std::vector<std::pair<void*, void*>> v;
@@ -183,9 +183,22 @@ struct Hier {
   void set_xstate(const std::vector<std::pair<void*, void*>>& v) {
     for (size_t i = 0; i < lv.size(); ++i) { lv[i].x = v[i].first; lv[i].xt = v[i].second; }
   }
+  // Arena mode (the no-allocation entry point): device arrays are carved out
+  // of a caller-provided region instead of hipMalloc, and the host side of
+  // the norm read-back is ordinary memory.  measure: only count the bytes.
+  char* arena = nullptr;
+  size_t arena_cap = 0;
+  bool measure = false;
+  std::vector<double> host_pin;
   void* alloc(size_t bytes) {
     void* p = nullptr;
     if (bytes == 0) bytes = 16;
+    if (arena || measure) {
+      const size_t at = (this->bytes + 255) & ~(size_t)255;
+      if (!measure && at + bytes > arena_cap) throw std::logic_error("scratch arena overflow");
+      this->bytes = at + bytes;
+      return measure ? nullptr : (void*)(arena + at);
+    }
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
     allocs.push_back(p);
@@ -253,10 +266,16 @@ static int64_t sweep_target(bool row = false) {
 
 // Levels below first_arrays get launch tables but no x / xt / b (their
 // data lives elsewhere); max_levels > 0 stops the hierarchy after that many.
+// arena / arena_cap: carve the device arrays out of that region (no
+// allocation); measure: only count the device bytes (nothing is touched).
 static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
                                         hipStream_t st, int tile_force = -1, int first_arrays = 0,
-                                        int max_levels = 0) {
+                                        int max_levels = 0, char* arena = nullptr, size_t arena_cap = 0,
+                                        bool measure = false) {
   auto H = std::make_unique<Hier>();
+  H->arena = arena;
+  H->arena_cap = arena_cap;
+  H->measure = measure;
   HIP_TRY(hipGetDevice(&H->device));
   H->s = s;
   H->ngrids = (int)specs.size();
@@ -370,7 +389,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     const Tab* tabs[5] = {&L.sw, &L.ew, &L.rc, &L.rz, &L.pp};
     for (int k = 0; k < 5; ++k)
       std::memcpy(stage.data() + gbytes + k * nb * sizeof(int64_t), tabs[k]->h_b0.data(), nb * sizeof(int64_t));
-    HIP_TRY(hipMemcpy(dev, stage.data(), bytes, hipMemcpyHostToDevice));
+    if (!measure) HIP_TRY(hipMemcpy(dev, stage.data(), bytes, hipMemcpyHostToDevice));
     if ((int)li >= first_arrays) {
       L.x = H->alloc(L.total * es);
       L.xt = H->alloc(L.total * es);
@@ -380,7 +399,12 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
   H->partials = (double*)H->alloc(maxblocks * 2 * sizeof(double));
   H->dred = (double*)H->alloc(H->ngrids * 2 * sizeof(double));
   H->dscal = (double*)H->alloc(H->ngrids * 4 * sizeof(double));
-  HIP_TRY(hipHostMalloc((void**)&H->hpin, H->ngrids * 4 * sizeof(double), hipHostMallocDefault));
+  if (arena || measure) {
+    H->host_pin.assign((size_t)H->ngrids * 4, 0.0);
+    H->hpin = H->host_pin.data();
+  } else {
+    HIP_TRY(hipHostMalloc((void**)&H->hpin, H->ngrids * 4 * sizeof(double), hipHostMallocDefault));
+  }
   if (mixed) {
     H->x64 = (double*)H->alloc(H->lv[0].total * sizeof(double));
     H->x64b = (double*)H->alloc(H->lv[0].total * sizeof(double));
@@ -1402,6 +1426,29 @@ static gd_status run_guarded(const std::function<gd_status()>& f) {
   }
 }
 
+// Scratch of the no-allocation entry point: one file-scope device array per
+// GPU (loaded with the library's code object and held until the process
+// ends).  In host code the array's name only stands for it; its device
+// address on the current device comes from hipGetSymbolAddress, taken once
+// per device and kept.  Every call on a device shares that device's array.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static char* scratch_ptr() {
+  static std::mutex mu;
+  static std::map<int, char*> per_dev;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = per_dev.find(dev);
+  if (it != per_dev.end()) return it->second;
+  void* p = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw std::logic_error("no device address for the scratch array");
+  per_dev[dev] = (char*)p;
+  return (char*)p;
+}
+
 }  // namespace gd
 
 using namespace gd;
@@ -1442,39 +1489,93 @@ static gd_status check_opts(const gd_solve_opts& o) {
   return GD_OK;
 }
 
-gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, int64_t nx, int64_t ny, int64_t nz,
-                      double bx, double by, double bz, const gd_solve_opts* opts, gd_solve_report* rep,
-                      void* stream) {
-  if (!I0 || !I1) return fail(GD_ERR_INVALID, "gd_smooth_z: null pointer");
-  if ((const void*)I0 == (const void*)I1) return fail(GD_ERR_INVALID, "gd_smooth_z: output aliases input");
+static gd_status smooth_z_args(const std::string& who, const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
+                               int64_t nx, int64_t ny, int64_t nz, double bx, double by, double bz,
+                               const gd_solve_opts* opts, gd_solve_opts& o) {
+  if (!I0 || !I1) return fail(GD_ERR_INVALID, who + ": null pointer");
+  if ((const void*)I0 == (const void*)I1) return fail(GD_ERR_INVALID, who + ": output aliases input");
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX)
-    return fail(GD_ERR_INVALID, "gd_smooth_z: bad size");
-  if (nx * ny > MAX_PLANE) return fail(GD_ERR_UNSUPPORTED, "gd_smooth_z: x-y plane above 2^28 cells");
-  if (!valid_dtype(in_t) || !valid_dtype(out_t)) return fail(GD_ERR_INVALID, "gd_smooth_z: bad dtype");
+    return fail(GD_ERR_INVALID, who + ": bad size");
+  if (nx * ny > MAX_PLANE) return fail(GD_ERR_UNSUPPORTED, who + ": x-y plane above 2^28 cells");
+  if (!valid_dtype(in_t) || !valid_dtype(out_t)) return fail(GD_ERR_INVALID, who + ": bad dtype");
   if (!(bx >= 0.0) || !(by >= 0.0) || !(bz > 0.0) || !std::isfinite(bx) || !std::isfinite(by) || !std::isfinite(bz))
-    return fail(GD_ERR_INVALID, "gd_smooth_z: need beta_x, beta_y >= 0 and beta_z > 0");
-  gd_solve_opts o;
+    return fail(GD_ERR_INVALID, who + ": need beta_x, beta_y >= 0 and beta_z > 0");
   gd_default_opts(&o);
   if (opts) o = *opts;
   gd_status s = check_opts(o);
   if (s != GD_OK) return s;
   if (o.discretization == 2 && o.fp64_refine)
-    return fail(GD_ERR_UNSUPPORTED, "gd_smooth_z: FP64 refinement is not built for the Linear discretisation");
+    return fail(GD_ERR_UNSUPPORTED, who + ": FP64 refinement is not built for the Linear discretisation");
+  return GD_OK;
+}
+
+static Outcome smooth_z_solve(Hier& H, const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, double bx,
+                              double by, double bz, const gd_solve_opts& o, hipStream_t st) {
+  Problem P{I0, nullptr, I1, in_t, out_t, true, in_t};
+  return o.discretization == 2 ? solve_linear_ad(H, P, o, bx, by, bz, st)
+         : o.fp64_refine       ? solve_mixed(H, P, o, st)
+                               : solve_plain(H, P, o, st);
+}
+
+gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, int64_t nx, int64_t ny, int64_t nz,
+                      double bx, double by, double bz, const gd_solve_opts* opts, gd_solve_report* rep,
+                      void* stream) {
+  gd_solve_opts o;
+  gd_status s = smooth_z_args("gd_smooth_z", I0, in_t, I1, out_t, nx, ny, nz, bx, by, bz, opts, o);
+  if (s != GD_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<GridSpec> g{{nx, ny, nz, 0.0, bx, by, bz, 0, nx, nx * ny}};
     HierLease H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
-    Problem P{I0, nullptr, I1, in_t, out_t, true, in_t};
-    Outcome R = o.discretization == 2 ? solve_linear_ad(*H, P, o, bx, by, bz, st)
-                : o.fp64_refine       ? solve_mixed(*H, P, o, st)
-                                      : solve_plain(*H, P, o, st);
+    Outcome R = smooth_z_solve(*H, I0, in_t, I1, out_t, bx, by, bz, o, st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rep) fill_report(rep, R, 0, secs, (int)H->lv.size());
     if (R.numeric) return fail(GD_ERR_NUMERIC, "gd_smooth_z: non-finite residual");
     if (!R.converged) return fail(GD_ERR_NOT_CONVERGED, "gd_smooth_z: tolerance not reached");
     return GD_OK;
   });
+}
+
+gd_status gd_smooth_z_noalloc(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, int64_t nx, int64_t ny,
+                              int64_t nz, double bx, double by, double bz, const gd_solve_opts* opts,
+                              gd_solve_report* rep, void* stream) {
+  const char* who = "gd_smooth_z_noalloc";
+  gd_solve_opts o;
+  gd_status s = smooth_z_args(who, I0, in_t, I1, out_t, nx, ny, nz, bx, by, bz, opts, o);
+  if (s != GD_OK) return s;
+  if (o.discretization != 0)
+    return fail(GD_ERR_UNSUPPORTED, std::string(who) + ": the Constant discretisation only");
+  // no graphs and no timing events: neither may be created here
+  o.use_graph = 0;
+  o.timing = 0;
+  hipStream_t st = (hipStream_t)stream;
+  return run_guarded([&]() -> gd_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<GridSpec> g{{nx, ny, nz, 0.0, bx, by, bz, 0, nx, nx * ny}};
+    const bool mixed = o.fp64_refine != 0;
+    // the device bytes this hierarchy needs, counted without touching the GPU
+    const size_t need =
+        build_hier(g, o.storage, mixed, st, o.sweep_tile, 0, 0, nullptr, 0, true)->bytes;
+    if (need > kScratchBytes)
+      return fail(GD_ERR_UNSUPPORTED, std::string(who) + ": needs " + std::to_string(need) +
+                                          " bytes of scratch, at most " + std::to_string(kScratchBytes));
+    char* arena = scratch_ptr();
+    auto H = build_hier(g, o.storage, mixed, st, o.sweep_tile, 0, 0, arena, kScratchBytes);
+    Outcome R = smooth_z_solve(*H, I0, in_t, I1, out_t, bx, by, bz, o, st);
+    HIP_TRY(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) fill_report(rep, R, 0, secs, (int)H->lv.size());
+    if (R.numeric) return fail(GD_ERR_NUMERIC, std::string(who) + ": non-finite residual");
+    if (!R.converged) return fail(GD_ERR_NOT_CONVERGED, std::string(who) + ": tolerance not reached");
+    return GD_OK;
+  });
+}
+
+gd_status gd_noalloc_scratch_bytes(int64_t* bytes) {
+  if (!bytes) return fail(GD_ERR_INVALID, "gd_noalloc_scratch_bytes: null pointer");
+  *bytes = (int64_t)kScratchBytes;
+  return GD_OK;
 }
 
 gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, int64_t nx, int64_t ny, int64_t nz,
