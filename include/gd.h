@@ -96,6 +96,13 @@ typedef struct {
                            hierarchy calls only, no FP64 refinement).  1 and 2
                            take single-grid solves only (slice batches:
                            GD_ERR_UNSUPPORTED). */
+  int sweep_quad;       /* 1 (default): the relaxation of FP16/BF16 level
+                           arrays, and of FP32 3-D grids, runs in its quad
+                           form (four x cells per thread, one aligned
+                           8/16-byte access per quad); 0: the pair form (two
+                           cells per thread).  Same values bit for bit; FP64,
+                           FP32 slices and the fused prolongation always use
+                           the pair form. */
 } gd_solve_opts;
 
 /* Filled by the solve calls when the pointer is non-NULL. */

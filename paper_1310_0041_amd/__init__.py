@@ -49,6 +49,7 @@ class SolveOpts(ctypes.Structure):
         ("use_graph", ctypes.c_int),
         ("fmg", ctypes.c_int),
         ("discretization", ctypes.c_int),
+        ("sweep_quad", ctypes.c_int),
     ]
 
 

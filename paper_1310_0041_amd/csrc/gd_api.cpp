@@ -113,6 +113,7 @@ struct Tab {  // launch geometry of one kernel family on one level
     g.row = row;
     g.tile = tile;
     g.order = order;
+    g.quad = true;  // level arrays: pitch and offsets multiples of 4
     return g;
   }
 };
@@ -866,12 +867,13 @@ struct Cycler {
   size_t ev_used = 0;
 
   bool fuse;
+  bool quad;  // the relaxation's quad form on the level arrays (FP32 and 16-bit storage)
   int disc;  // 0 Constant; 1 Hybrid (table levels >= 1), 2 Linear (all table levels); B-spline transfers
   bool hyb;  // disc != 0
   const std::vector<HybTables>* T = nullptr;
   Cycler(Hier& h, hipStream_t s, const gd_solve_opts& o)
       : H(h), st(s), pre(o.pre_smooth), post(o.post_smooth), pmode(o.prolong), timing(o.timing != 0),
-        fuse(o.fuse_prolong != 0), disc(o.discretization), hyb(o.discretization != 0) {
+        fuse(o.fuse_prolong != 0), quad(o.sweep_quad != 0), disc(o.discretization), hyb(o.discretization != 0) {
     if (hyb) {
       T = disc == 2 ? &H.lin : &H.hyb;
       if (T->empty()) throw std::logic_error("discretisation tables not built before the cycle");
@@ -919,7 +921,9 @@ struct Cycler {
       if (ev_kind.size() < ev.size()) ev_kind.resize(ev.size());
       ev_kind[ev_used] = (L.row ? 2 : 0) + (ec ? 1 : 0);
     }
-    HIP_TRY(launch_rb_sweep(H.s, H.g_sw(l), L.x, L.xt, L.b, ec, pmode, st));
+    Geom g = H.g_sw(l);
+    g.quad = quad;
+    HIP_TRY(launch_rb_sweep(H.s, g, L.x, L.xt, L.b, ec, pmode, st));
     if (t) HIP_TRY(hipEventRecord(ev[ev_used++].second, st));
     std::swap(L.x, L.xt);
   }
@@ -1070,8 +1074,8 @@ static bool graphs_on(const gd_solve_opts& o) { return o.use_graph != 0 && o.tim
 
 static std::string graph_key(const char* what, const gd_solve_opts& o) {
   char k[128];
-  std::snprintf(k, sizeof k, "%s|%d|%d|%d|%d|%d", what, o.pre_smooth, o.post_smooth, o.prolong, o.fuse_prolong,
-                o.discretization);
+  std::snprintf(k, sizeof k, "%s|%d|%d|%d|%d|%d|%d", what, o.pre_smooth, o.post_smooth, o.prolong, o.fuse_prolong,
+                o.discretization, o.sweep_quad);
   return k;
 }
 
@@ -1473,6 +1477,7 @@ void gd_default_opts(gd_solve_opts* o) {
   o->use_graph = 1;
   o->fmg = 0;
   o->discretization = 0;
+  o->sweep_quad = 1;
 }
 
 const char* gd_last_error(void) { return t_err.c_str(); }
@@ -1482,7 +1487,7 @@ static gd_status check_opts(const gd_solve_opts& o) {
   if (!(o.rel_tol > 0.0) || o.max_cycles < 0 || o.pre_smooth < 0 || o.post_smooth < 0 ||
       o.pre_smooth + o.post_smooth < 1 || !valid_dtype(o.storage) || o.inner_cycles < 1 ||
       (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3 ||
-      o.discretization < 0 || o.discretization > 2)
+      o.discretization < 0 || o.discretization > 2 || o.sweep_quad < 0 || o.sweep_quad > 1)
     return fail(GD_ERR_INVALID, "invalid solver options");
   if (!o.fp64_refine && (o.storage == GD_F16 || o.storage == GD_BF16))
     return fail(GD_ERR_UNSUPPORTED, "16-bit storage needs fp64_refine = 1 (its rounding floor is far above 1e-6)");
@@ -1826,7 +1831,7 @@ static gd_status hier_args(const std::string& who, int64_t nx, int64_t ny, int64
   o.fp64_refine = 0;
   if (!(o.rel_tol > 0.0) || o.pre_smooth < 0 || o.post_smooth < 0 || o.pre_smooth + o.post_smooth < 1 ||
       (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3 || o.discretization < 0 ||
-      o.discretization > 2)
+      o.discretization > 2 || o.sweep_quad < 0 || o.sweep_quad > 1)
     return fail(GD_ERR_INVALID, who + ": invalid options");
   return GD_OK;
 }

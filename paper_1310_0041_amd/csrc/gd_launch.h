@@ -33,6 +33,8 @@ struct Geom {
   bool vec = true;   // every grid's pitch and offset are even (x pairs aligned)
   int tile = 0;      // relaxation tile variant of 3-D grids (SWEEP_TILE_TX / TY)
   int order = 0;     // relaxation block order: 0 plain, 1 contiguous runs per XCD
+  bool quad = false; // the library's own arrays (x pitch and offsets multiples of 4, aligned):
+                     // the relaxation may use its quad form
 };
 
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,

@@ -417,6 +417,392 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
   }
 }
 
+// ------------------------------------------------ red-black sweep, quad form
+//
+// The same sweep with four consecutive x cells per thread (thread t owns
+// gx .. gx + 3, gx = x0 + 4 (t mod TX/4), of row gy = y0 + t / (TX/4)), for
+// the library's own arrays (x pitch and grid offsets multiples of four, so a
+// quad is one aligned 8-byte (16-bit types) or 16-byte (FP32) access) and
+// compute type float.  In every plane two cells of a quad are red and two
+// black: positions c and c + 2 with c = (gy + p) & 1 are the red cells of
+// plane p, and the black cells of planes p - 1 and p + 1 (so the updates of
+// a step, red of plane p and black of plane p - 1, are both at positions c
+// and c + 2).  The plane pipeline, the LDS planes, the recomputed 1-cell red
+// ring and the neighbour order of every update are those of k_rb_sweep, so
+// both forms give the same values bit for bit; the quad form issues half the
+// loads, address computations and conversions per cell.  The LDS plane is
+// TX + 8 wide with the tile at x offset 4, so that a quad is one aligned
+// 16-byte LDS access; the 2-cell halo is loaded in aligned quads (full quads
+// of the two rows above and below the tile, one quad on each side of its
+// rows).
+template <int TX, int TY>
+struct SweepShape4 {
+  static constexpr bool ROW = (TY == 1);
+  static constexpr int NT = TX * TY / 4;                 // threads: one x-quad each
+  static constexpr int YO = ROW ? 0 : 2;                 // tile row 0 inside the LDS plane
+  static constexpr int XO = 4;                           // tile column 0 inside the LDS plane
+  static constexpr int HX = TX + 8, HY = ROW ? 1 : TY + 4;
+  static constexpr int QR = TX / 4 + 2;                  // quads of a full halo row
+  static constexpr int NHQ = ROW ? 2 : 4 * QR + 2 * TY;  // halo quads per plane
+  static constexpr int NHQR = (NHQ + NT - 1) / NT;       // halo quads per thread
+  static constexpr int NRING = ROW ? 1 : (TX + 2) + TY;  // red ring-1 cells per plane
+};
+
+// LDS coordinates (row, first column) of halo quad h
+template <int TX, int TY>
+__device__ __forceinline__ void halo_quad(int h, int& hy, int& hx) {
+  using SS = SweepShape4<TX, TY>;
+  constexpr int QR = SS::QR;
+  if constexpr (SS::ROW) {
+    hy = 0;
+    hx = h == 0 ? 0 : TX + 4;
+  } else {
+    if (h < 2 * QR) { hy = h / QR; hx = 4 * (h - hy * QR); return; }
+    h -= 2 * QR;
+    if (h < 2 * QR) { const int r = h / QR; hy = TY + 2 + r; hx = 4 * (h - r * QR); return; }
+    h -= 2 * QR;
+    hy = 2 + (h >> 1);
+    hx = (h & 1) ? TX + 4 : 0;
+  }
+}
+
+// four consecutive raw values (one aligned access)
+template <typename S> struct Raw4 {
+  using W = std::conditional_t<sizeof(S) == 4, float4, uint2>;
+  W w;
+};
+template <typename S> __device__ __forceinline__ void ld_raw4(const S* p, Raw4<S>& r) {
+  r.w = *reinterpret_cast<const typename Raw4<S>::W*>(p);
+}
+template <typename S> __device__ __forceinline__ float raw4_at(const Raw4<S>& r, int i) {
+  if constexpr (sizeof(S) == 4) {
+    return i == 0 ? r.w.x : i == 1 ? r.w.y : i == 2 ? r.w.z : r.w.w;
+  } else {
+    const uint32_t v = (i < 2) ? r.w.x : r.w.y;
+    return from_bits16f<S>((i & 1) ? (v >> 16) : (v & 0xffffu));
+  }
+}
+template <typename S> __device__ __forceinline__ uint32_t bits16(float v) {
+  S h;
+  Ty<S>::st(&h, v);
+  uint16_t u;
+  __builtin_memcpy(&u, &h, 2);
+  return u;
+}
+template <typename S> __device__ __forceinline__ void st4(S* p, float a, float b, float c, float d) {
+  // the stored value is the rounding of the float the sweep computed and
+  // keeps using: no instruction may fuse the last multiply-add with the
+  // conversion (a mixed-precision FMA would round once, straight to 16 bits)
+  asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+  if constexpr (sizeof(S) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+  } else {
+    *reinterpret_cast<uint2*>(p) =
+        make_uint2(bits16<S>(a) | (bits16<S>(b) << 16), bits16<S>(c) | (bits16<S>(d) << 16));
+  }
+}
+
+template <typename S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY / 4)
+k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+            const S* __restrict__ xin, S* __restrict__ xout, const S* __restrict__ bin, int order) {
+  static_assert(sizeof(S) <= 4, "the quad form computes in float");
+  using C = float;
+  using SS = SweepShape4<TX, TY>;
+  constexpr int NT = SS::NT, YO = SS::YO, XO = SS::XO, HX = SS::HX, HY = SS::HY, NHQR = SS::NHQR;
+  constexpr int PLANE = HX * HY;
+  constexpr bool ROW = SS::ROW;
+  constexpr int QPR = TX / 4;                 // quads per tile row
+  constexpr int RPW = QPR >= 64 ? 1 : 64 / QPR;  // tile rows per wave
+  static_assert(ROW || TY % (2 * RPW) == 0, "waves of rows of one parity");
+  using Ring = WaveSplit<SS::NRING, NT>;
+  static_assert(Ring::PER <= 64, "ring share per wave");
+  // four planes, then one slot per thread that takes the masked writes of
+  // threads without a ring cell
+  __shared__ __align__(16) C X[4 * PLANE + NT];
+
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false, order);
+  const GridDesc& G = grids[t.g];
+  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
+  const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
+  const int64_t pl = (int64_t)px * ny;
+  const S* xg = xin + G.off;
+  const S* bg = bin + G.off;
+  S* xo = xout + G.off;
+  const int tid = threadIdx.x;
+  const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
+
+  // ---- own quad (gx .. gx + 3) of row gy.  The rows of a wave have one
+  // parity (wave w takes rows 2 RPW (w / 2) + (w & 1) + 2 j), so the cells a
+  // step updates (positions c, c + 2, c = (gy + p) & 1) are the same for the
+  // whole wave and the step branches on c uniformly.
+  const int wv = tid >> 6, ln = tid & 63;
+  const int tyl = ROW ? 0 : 2 * RPW * (wv >> 1) + (wv & 1) + 2 * (ln / QPR);
+  const int qxl = ROW ? tid : ln % QPR;
+  const int wpar = __builtin_amdgcn_readfirstlane((y0 + tyl) & 1);  // row parity, uniform per wave
+  const int gx = x0 + 4 * qxl, gy = y0 + tyl;
+  const bool rowok = gy < ny;
+  const bool v0 = rowok && gx < nx, v1 = rowok && gx + 1 < nx, v2 = rowok && gx + 2 < nx,
+             v3 = rowok && gx + 3 < nx;
+  const int lo = (YO + tyl) * HX + XO + 4 * qxl;  // LDS index of gx inside a plane (16-byte aligned)
+  const int own = gy * px + gx;                  // element offset inside a plane (< 2^28)
+  const C wU = (gy > 0) ? wy : (C)0, wD = (gy + 1 < ny) ? wy : (C)0;
+  // per position class k (the updated cells at F = k and S = k + 2): x-weights,
+  // inverse diagonals inside the z-range and on its first or last plane, and
+  // whether the diagonal is non-zero (keep = 0: the cell is set to 0)
+  C wLF[2], wRF[2], wLS[2], wRS[2], invIF[2], invEF[2], invIS[2], invES[2], kIF[2], kEF[2], kIS[2], kES[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int xF = gx + k, xS = gx + k + 2;
+    // weights as the pair form gives them: a neighbour in the grid has w_x
+    wLF[k] = xF > 0 ? wx : (C)0;
+    wRF[k] = xF + 1 < nx ? wx : (C)0;
+    wLS[k] = wx;
+    wRS[k] = xS + 1 < nx ? wx : (C)0;
+    const C wz1 = nz > 1 ? wz : (C)0;
+    const C dF = alpha + wLF[k] + wRF[k] + wU + wD, dS = alpha + wLS[k] + wRS[k] + wU + wD;
+    const C diF = (dF + wz1) + wz1, deF = dF + wz1, diS = (dS + wz1) + wz1, deS = dS + wz1;
+    invIF[k] = diF > (C)0 ? (C)1 / diF : (C)0;
+    invEF[k] = deF > (C)0 ? (C)1 / deF : (C)0;
+    invIS[k] = diS > (C)0 ? (C)1 / diS : (C)0;
+    invES[k] = deS > (C)0 ? (C)1 / deS : (C)0;
+    kIF[k] = diF > (C)0 ? (C)1 : (C)0;
+    kEF[k] = deF > (C)0 ? (C)1 : (C)0;
+    kIS[k] = diS > (C)0 ? (C)1 : (C)0;
+    kES[k] = deS > (C)0 ? (C)1 : (C)0;
+  }
+
+  // ---- halo quads of this thread (loaded every plane)
+  int hoff[NHQR], hg[NHQR], hxs[NHQR];
+  bool hv[NHQR], hs[NHQR];
+#pragma unroll
+  for (int k = 0; k < NHQR; ++k) {
+    const int h = tid + NT * k;
+    int hy = 0, hx = 0;
+    if (h < SS::NHQ) halo_quad<TX, TY>(h, hy, hx);
+    const int cx = x0 - XO + hx, cy = y0 - YO + hy;
+    hs[k] = h < SS::NHQ;
+    hv[k] = hs[k] && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    hoff[k] = hy * HX + hx;
+    hg[k] = hv[k] ? cy * px + cx : 0;
+    hxs[k] = cx;
+  }
+
+  // ---- ring red cell of this thread, for each plane parity (k_rb_sweep's
+  // ring, in this LDS layout)
+  const int rm = Ring::item(tid);
+  int ro[2], rg[2];
+  bool rv[2];
+  C rwl[2], rwr[2], rwu[2], rwd[2], rinvI[2], rinvE[2], rkI[2], rkE[2];
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    int hy = 0, hx = 0;
+    if (rm >= 0) ring_red_cell<TX, TY>(rm, x0, y0, par, hy, hx);
+    hx += XO - 2;  // the pair form's LDS column -> this layout
+    const int cx = x0 - XO + hx, cy = y0 - YO + hy;
+    rv[par] = rm >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    ro[par] = rm >= 0 ? hy * HX + hx : lo;
+    rg[par] = rv[par] ? cy * px + cx : 0;
+    rwl[par] = cx > 0 ? wx : (C)0;
+    rwr[par] = cx < nx - 1 ? wx : (C)0;
+    rwu[par] = cy > 0 ? wy : (C)0;
+    rwd[par] = cy < ny - 1 ? wy : (C)0;
+    const C dxy = alpha + rwl[par] + rwr[par] + rwu[par] + rwd[par];
+    const C wz1 = nz > 1 ? wz : (C)0;
+    const C di = (dxy + wz1) + wz1, de = dxy + wz1;
+    rinvI[par] = di > (C)0 ? (C)1 / di : (C)0;
+    rinvE[par] = de > (C)0 ? (C)1 / de : (C)0;
+    rkI[par] = di > (C)0 ? (C)1 : (C)0;
+    rkE[par] = de > (C)0 ? (C)1 : (C)0;
+  }
+
+  // Gauss-Seidel value in correction form (the neighbour order of relax());
+  // keep = 0 where the diagonal is zero sets the cell to 0 (relax() does that
+  // by a test; the two agree in value)
+  auto gs = [&](C x, C b, C wl, C nl, C wr, C nr, C wu_, C nu, C wd_, C nd, C wzm, C nzm, C wzp, C nzp, C inv,
+                C keep) -> C {
+    C r = fmac(-alpha, x, b);
+    r = fmac(wl, nl - x, r);
+    r = fmac(wr, nr - x, r);
+    if (!ROW) {
+      r = fmac(wu_, nu - x, r);
+      r = fmac(wd_, nd - x, r);
+    }
+    r = fmac(wzm, nzm - x, r);
+    r = fmac(wzp, nzp - x, r);
+    return fmac(r, inv, x * keep);
+  };
+
+  struct XSet {
+    Raw4<S> p;          // own quad
+    Raw4<S> h[NHQR];    // halo quads
+  };
+  // loads from clamped, always valid addresses: a plane outside [0, nz) only
+  // ever enters with a zero z-weight, cells outside the grid are masked to 0
+  auto plane_ptr = [&](const S* base, int q) { return base + (int64_t)min(max(q, 0), nz - 1) * pl; };
+  auto fetch_x = [&](int q, XSet& o) {
+    const S* P = plane_ptr(xg, q);
+    ld_raw4(P + (v0 ? own : 0), o.p);
+#pragma unroll
+    for (int k = 0; k < NHQR; ++k) ld_raw4(P + hg[k], o.h[k]);
+  };
+  auto xq = [&](const Raw4<S>& r, int i, bool v) -> C { return v ? raw4_at(r, i) : (C)0; };
+  auto stash = [&](int q, const XSet& o) {
+    C* P = X + (q & 3) * PLANE;
+    *reinterpret_cast<float4*>(P + lo) = make_float4(xq(o.p, 0, v0), xq(o.p, 1, v1), xq(o.p, 2, v2), xq(o.p, 3, v3));
+#pragma unroll
+    for (int k = 0; k < NHQR; ++k)
+      if (hs[k]) {
+        float4 v;
+        const bool ok = hv[k];
+        v.x = (ok && hxs[k] + 0 < nx) ? raw4_at(o.h[k], 0) : (C)0;
+        v.y = (ok && hxs[k] + 1 < nx) ? raw4_at(o.h[k], 1) : (C)0;
+        v.z = (ok && hxs[k] + 2 < nx) ? raw4_at(o.h[k], 2) : (C)0;
+        v.w = (ok && hxs[k] + 3 < nx) ? raw4_at(o.h[k], 3) : (C)0;
+        *reinterpret_cast<float4*>(P + hoff[k]) = v;
+      }
+  };
+  auto fetch_b = [&](int q, Raw4<S>& r) { ld_raw4(plane_ptr(bg, q) + (v0 ? own : 0), r); };
+  // quad of a plane whose red cells are at c, c + 2 -> red (a, b), black (a, b)
+  auto split = [&](auto CC, const Raw4<S>& r, C& Ra, C& Rb, C& Ka, C& Kb) {
+    constexpr int c = decltype(CC)::value;
+    const C a0 = xq(r, 0, v0), a1 = xq(r, 1, v1), a2 = xq(r, 2, v2), a3 = xq(r, 3, v3);
+    Ra = c ? a1 : a0;
+    Rb = c ? a3 : a2;
+    Ka = c ? a0 : a1;
+    Kb = c ? a2 : a3;
+  };
+  using K0 = std::integral_constant<int, 0>;
+  using K1 = std::integral_constant<int, 1>;
+  auto split_q = [&](int q, const Raw4<S>& r, C& Ra, C& Rb, C& Ka, C& Kb) {
+    if (((wpar + q) & 1) != 0) split(K1{}, r, Ra, Rb, Ka, Kb);
+    else split(K0{}, r, Ra, Rb, Ka, Kb);
+  };
+  auto ring_b = [&](int q) -> Raw<S> {
+    Raw<S> r;
+    ld_raw(plane_ptr(bg, q) + rg[q & 1], r);
+    return r;
+  };
+
+  // column registers: red (a, b) / black (a, b) of planes p-2 .. p+1; b of planes p-1, p
+  C RAm2 = 0, RBm2 = 0, KAm2 = 0, KBm2 = 0;
+  C RAm1, RBm1, KAm1, KBm1, RA0, RB0, KA0, KB0, RAp1, RBp1, KAp1, KBp1;
+  C bRAm1, bRBm1, bKAm1, bKBm1, bRA0, bRB0, bKA0, bKB0;
+  XSet S0, S1;
+  Raw4<S> B0, B1;
+  Raw<S> RB0r, RB1r;
+  const int pfirst = max(q0 - 1, 0);
+  const int plast = (q1 < nz) ? q1 : nz;  // p == nz: black of the last plane only
+  {
+    XSet t0;
+    Raw4<S> tb;
+    fetch_x(pfirst - 1, t0); stash(pfirst - 1, t0); split_q(pfirst - 1, t0.p, RAm1, RBm1, KAm1, KBm1);
+    fetch_x(pfirst, t0);     stash(pfirst, t0);     split_q(pfirst, t0.p, RA0, RB0, KA0, KB0);
+    fetch_x(pfirst + 1, t0); stash(pfirst + 1, t0); split_q(pfirst + 1, t0.p, RAp1, RBp1, KAp1, KBp1);
+    fetch_b(pfirst - 1, tb); split_q(pfirst - 1, tb, bRAm1, bRBm1, bKAm1, bKBm1);
+    fetch_b(pfirst, tb);     split_q(pfirst, tb, bRA0, bRB0, bKA0, bKB0);
+  }
+  RB0r = ring_b(pfirst);
+  RB1r = ring_b(pfirst + 1);
+  fetch_x(pfirst + 2, S0);
+  fetch_x(pfirst + 3, S1);
+  fetch_b(pfirst + 1, B1);
+  fetch_b(pfirst + 2, B0);
+
+  // one plane step for plane parity PAR and updated positions c, c + 2 (CC)
+  auto body = [&](auto PC, auto CC, int p, XSet& XS, Raw4<S>& BS, Raw<S>& RBS) {
+    constexpr int par = decltype(PC)::value;
+    constexpr int c = decltype(CC)::value;
+    constexpr bool EDGE = true;
+    __syncthreads();
+    constexpr int dF = c, dS = c + 2, dO = c ? 4 : -1;  // LDS offsets from lo: F, S, outside neighbour
+    if (p < nz) {
+      // ---- red cells of plane p (F, S) and the ring cell
+      C* P = X + (p & 3) * PLANE;
+      const C* Pm = X + ((p - 1) & 3) * PLANE;
+      const C* Pp = X + ((p + 1) & 3) * PLANE;
+      const C wzm = (!EDGE || p > 0) ? wz : (C)0, wzp = (!EDGE || p < nz - 1) ? wz : (C)0;
+      const bool edge = EDGE && (p == 0 || p == nz - 1);
+      const C out = P[lo + dO];
+      const C upF = ROW ? (C)0 : P[lo + dF - HX], dnF = ROW ? (C)0 : P[lo + dF + HX];
+      const C upS = ROW ? (C)0 : P[lo + dS - HX], dnS = ROW ? (C)0 : P[lo + dS + HX];
+      const int o = ro[par];
+      const C rx = P[o], rl = P[o - 1], rr = P[o + 1];
+      const C ru = ROW ? (C)0 : P[o - HX], rd = ROW ? (C)0 : P[o + HX];
+      const C rzm = Pm[o], rzp = Pp[o];
+      const C nF = gs(RA0, bRA0, wLF[c], c ? KA0 : out, wRF[c], c ? KB0 : KA0, wU, upF, wD, dnF, wzm, KAm1, wzp,
+                      KAp1, edge ? invEF[c] : invIF[c], edge ? kEF[c] : kIF[c]);
+      const C nS = gs(RB0, bRB0, wLS[c], c ? KB0 : KA0, wRS[c], c ? out : KB0, wU, upS, wD, dnS, wzm, KBm1, wzp,
+                      KBp1, edge ? invES[c] : invIS[c], edge ? kES[c] : kIS[c]);
+      RA0 = (c ? v1 : v0) ? nF : (C)0;
+      RB0 = (c ? v3 : v2) ? nS : (C)0;
+      P[lo + dF] = RA0;
+      P[lo + dS] = RB0;
+      const C rb = rv[par] ? raw_c(RBS) : (C)0;
+      const C rn = gs(rx, rb, rwl[par], rl, rwr[par], rr, rwu[par], ru, rwd[par], rd, wzm, rzm, wzp, rzp,
+                      edge ? rinvE[par] : rinvI[par], edge ? rkE[par] : rkI[par]);
+      *(rv[par] ? P + o : X + 4 * PLANE + tid) = rn;
+    }
+    // no barrier here: the black cells of plane p - 1 read only plane
+    // p - 1's buffer, whose red cells were written in the previous step
+    const int q = p - 1;
+    if (q >= q0 && q < q1) {
+      // ---- black cells of plane q = p - 1 (at F, S: the red positions of plane p)
+      const C* P = X + (q & 3) * PLANE;
+      const C wzm = (!EDGE || q > 0) ? wz : (C)0, wzp = (!EDGE || q < nz - 1) ? wz : (C)0;
+      const bool edge = EDGE && (q == 0 || q == nz - 1);
+      const C out = P[lo + dO];
+      const C upF = ROW ? (C)0 : P[lo + dF - HX], dnF = ROW ? (C)0 : P[lo + dF + HX];
+      const C upS = ROW ? (C)0 : P[lo + dS - HX], dnS = ROW ? (C)0 : P[lo + dS + HX];
+      const C nF = gs(KAm1, bKAm1, wLF[c], c ? RAm1 : out, wRF[c], c ? RBm1 : RAm1, wU, upF, wD, dnF, wzm, RAm2,
+                      wzp, RA0, edge ? invEF[c] : invIF[c], edge ? kEF[c] : kIF[c]);
+      const C nS = gs(KBm1, bKBm1, wLS[c], c ? RBm1 : RAm1, wRS[c], c ? out : RBm1, wU, upS, wD, dnS, wzm, RBm2,
+                      wzp, RB0, edge ? invES[c] : invIS[c], edge ? kES[c] : kIS[c]);
+      KAm1 = (c ? v1 : v0) ? nF : (C)0;
+      KBm1 = (c ? v3 : v2) ? nS : (C)0;
+      // memory order of plane q: red at c ^ 1 and (c ^ 1) + 2, black at c and c + 2
+      if (v0) {
+        if (c) st4(xo + (int64_t)q * pl + own, RAm1, KAm1, RBm1, KBm1);
+        else st4(xo + (int64_t)q * pl + own, KAm1, RAm1, KBm1, RBm1);
+      }
+    }
+    stash(p + 2, XS);
+    RAm2 = RAm1; RBm2 = RBm1; KAm2 = KAm1; KBm2 = KBm1;
+    RAm1 = RA0; RBm1 = RB0; KAm1 = KA0; KBm1 = KB0;
+    RA0 = RAp1; RB0 = RBp1; KA0 = KAp1; KB0 = KBp1;
+    // plane p + 2 has plane p's parity: its red cells are at c, c + 2
+    split(CC, XS.p, RAp1, RBp1, KAp1, KBp1);
+    bRAm1 = bRA0; bRBm1 = bRB0; bKAm1 = bKA0; bKBm1 = bKB0;
+    split(std::integral_constant<int, 1 - c>{}, BS, bRA0, bRB0, bKA0, bKB0);  // plane p + 1
+    fetch_x(p + 4, XS);
+    fetch_b(p + 3, BS);
+    ld_raw(plane_ptr(bg, p + 2) + rg[par], RBS);  // ring b of plane p + 2 (same parity)
+  };
+  // The updated positions of a step, c = (gy + p) & 1, are uniform per wave
+  // and alternate with p, so the unrolled pair of steps of the loop has a
+  // fixed (c, 1 - c): one loop per (parity of the first plane, its c).
+  auto loop = [&](auto P0, auto C0) {
+    using P1 = std::integral_constant<int, 1 - decltype(P0)::value>;
+    using C1 = std::integral_constant<int, 1 - decltype(C0)::value>;
+    int p = pfirst;
+    for (; p + 1 <= plast; p += 2) {
+      body(P0, C0, p, S0, B1, RB0r);
+      body(P1{}, C1{}, p + 1, S1, B0, RB1r);
+    }
+    if (p <= plast) body(P0, C0, p, S0, B1, RB0r);
+  };
+  using E0 = std::integral_constant<int, 0>;
+  using E1 = std::integral_constant<int, 1>;
+  const int c0 = (wpar + pfirst) & 1;  // wave-uniform
+  if ((pfirst & 1) == 0) {
+    if (c0) loop(E0{}, K1{});
+    else loop(E0{}, K0{});
+  } else {
+    if (c0) loop(E1{}, K1{});
+    else loop(E1{}, K0{});
+  }
+}
+
 // ============================================================ launchers
 
 template <typename T, bool FP, bool VEC>
@@ -444,9 +830,44 @@ static void sweep_launch3(const Geom& g, const void* xin, void* xout, const void
   }
 }
 
+// The quad form for the library's arrays (float compute types), unless
+// GD_SWEEP_QUAD=0 asks for the pair form (same values either way).
+static bool quad_on() {
+  static const bool v = [] {
+    const char* e = std::getenv("GD_SWEEP_QUAD");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return v;
+}
+
+template <typename T>
+static void sweep_launch4(const Geom& g, const void* xin, void* xout, const void* b, hipStream_t st) {
+#define SWEEP4(TX, TY)                                                                                        \
+  hipLaunchKernelGGL((k_rb_sweep4<T, TX, TY>), dim3((unsigned)g.nblocks), dim3(TX * TY / 4), 0, st, g.grids, \
+                     g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, g.order)
+  if (g.row) {
+    SWEEP4(SWR_TX, 1);
+  } else {
+    switch (g.tile) {
+      case 0: SWEEP4(64, 8); break;
+      case 1: SWEEP4(128, 8); break;
+      case 2: SWEEP4(64, 16); break;
+      default: SWEEP4(128, 16); break;
+    }
+  }
+#undef SWEEP4
+}
+
 template <typename T>
 static void sweep_launch(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
                          hipStream_t st) {
+  // the row form (slices) of FP32 measured no faster in quads: pairs there
+  if constexpr (sizeof(T) <= 4) {
+    if (!ec && g.quad && quad_on() && (sizeof(T) == 2 || !g.row)) {
+      sweep_launch4<T>(g, xin, xout, b, st);
+      return;
+    }
+  }
   // the library's arrays are pair-aligned (g.vec); a caller's odd-width arrays are not
   if (ec) sweep_launch3<T, true, true>(g, xin, xout, b, ec, pmode, st);
   else if (g.vec) sweep_launch3<T, false, true>(g, xin, xout, b, ec, pmode, st);

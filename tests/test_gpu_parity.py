@@ -386,6 +386,33 @@ def test_sweep_tiles_identical(gd, storage):
         assert torch.equal(I1, outs[0][0]) and torch.equal(I2, outs[0][1])
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("shape", [(37, 77, 203), (9, 130, 64), (5, 3, 9), (1, 1, 1), (24, 64, 256)])
+def test_sweep_quad_equals_pair(gd, storage, shape):
+    """The quad form of the relaxation (four x cells per thread) gives the
+    pair form's values bit for bit: AD and SP results after a fixed number
+    of cycles, every tile variant of the stack and the slices' row form,
+    on odd sizes, ragged tile edges and several z-chunks."""
+    import synth
+
+    nz, ny, nx = shape
+    say("quad vs pair", storage, shape)
+    spec = synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100424)
+    I0 = synth.make_stack(spec).to(torch.float32).cuda()
+    kw = dict(rel_tol=1e-9, max_cycles=4, check=False, use_graph=0)
+    if storage != "f32":
+        kw.update(storage=gd.F16 if storage == "f16" else gd.BF16, fp64_refine=1)
+    for tile in range(4):
+        outs = []
+        for quad in (0, 1):
+            I1, r1 = gd.smooth_z(I0, (1.0, 1.0, 4.0), out_dtype=torch.float32, sweep_tile=tile, sweep_quad=quad,
+                                 **kw)
+            I2, r2, _ = gd.screened_poisson_stack(I0, I1, 0.01, sweep_tile=tile, sweep_quad=quad, **kw)
+            outs.append((I1, I2, r1["cycles"], r2["cycles"], r1["rel_residual"], r2["rel_residual"]))
+        assert outs[0][2:] == outs[1][2:], (tile, outs[0][2:], outs[1][2:])
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), tile
+
+
 def test_autotune_choice(gd):
     """A workspace of 2^22 cells is autotuned once; the choice is reported
     and changes nothing in the result."""
