@@ -106,54 +106,65 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   // Raw loads of plane q: F's own pair and halo values and (KIND 1) I0's
   // pair; converted to FP64 only in stash(), after other work has run.
   using FS = std::conditional_t<KIND == 0, Tin, std::conditional_t<MODE == 0, S, double>>;
-  Raw2<FS> rf;
-  Raw2<Tin> ri;
-  Raw2<S> re;  // MODE 2: the correction e
-  Raw<FS> rh[NHR];
-  Raw<Tin> rhi[NHR];
-  Raw<S> rhe[NHR];
+  // Loads of a plane sit in one of two slots: a plane is fetched two planes
+  // ahead of its use, and the loop is unrolled by two so that no slot is
+  // copied (a copy would make the wave wait for the newest loads).
+  struct Pre {
+    Raw2<FS> rf;
+    Raw2<Tin> ri;
+    Raw2<S> re;  // MODE 2: the correction e
+    Raw<FS> rh[NHR];
+    Raw<Tin> rhi[NHR];
+    Raw<S> rhe[NHR];
+    Raw2<T1> r1;  // the I1 pair (alpha != 0)
+  };
   const double es = (MODE == 2) ? e_scale[t.g] : 0.0;
   // loads from clamped addresses without branches around them (masked in stash)
-  auto fetch = [&](int q) {
+  auto fetch = [&](int q, Pre& o) {
     const int qc = min(max(q, 0), nz - 1);
     const Tin* I0q = I0g + qc * G.ipz;
     const int64_t po = qc * pl;
     const int64_t oo = vA ? own : 0, ou = vA ? ownu : 0;
     if (KIND == 0) {
-      ld_raw2(reinterpret_cast<const FS*>(I0q) + ou, ivec, vB, rf);
+      ld_raw2(reinterpret_cast<const FS*>(I0q) + ou, ivec, vB, o.rf);
     } else {
-      ld_raw2(I0q + ou, ivec, vB, ri);
+      ld_raw2(I0q + ou, ivec, vB, o.ri);
       if (MODE == 0) {
-        ld_raw2(reinterpret_cast<const FS*>(Eg) + po + oo, true, true, rf);
+        ld_raw2(reinterpret_cast<const FS*>(Eg) + po + oo, true, true, o.rf);
       } else {
-        ld_raw2(reinterpret_cast<const FS*>(xg) + po + oo, true, true, rf);
-        if (MODE == 2) ld_raw2(Eg + po + oo, true, true, re);
+        ld_raw2(reinterpret_cast<const FS*>(xg) + po + oo, true, true, o.rf);
+        if (MODE == 2) ld_raw2(Eg + po + oo, true, true, o.re);
       }
     }
 #pragma unroll
     for (int k = 0; k < NHR; ++k) {
-      if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0q) + hu[k], rh[k]);
-      else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + po + hg[k], rh[k]);
+      if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0q) + hu[k], o.rh[k]);
+      else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + po + hg[k], o.rh[k]);
       else {
-        ld_raw(reinterpret_cast<const FS*>(xg) + po + hg[k], rh[k]);
-        ld_raw(I0q + hu[k], rhi[k]);
-        if (MODE == 2) ld_raw(Eg + po + hg[k], rhe[k]);
+        ld_raw(reinterpret_cast<const FS*>(xg) + po + hg[k], o.rh[k]);
+        ld_raw(I0q + hu[k], o.rhi[k]);
+        if (MODE == 2) ld_raw(Eg + po + hg[k], o.rhe[k]);
       }
     }
+    // I1 (raw, clamped; used only for planes in [q0, q1) with vA / vB)
+    if (I1g) ld_raw2(I1g + qc * G.ipz + ou, ivec, vB, o.r1);
   };
-  // convert the last fetch: F pair (fa, fb), I0 pair (ia, ib); store F's plane
-  double fa = 0, fb = 0, ia = 0, ib = 0;
-  auto stash = [&](int q) {
+  // convert a slot: F pair (fa, fb), I0 pair (ia, ib), I1 pair (ja, jb);
+  // store F's plane in LDS
+  double fa = 0, fb = 0, ia = 0, ib = 0, ja = 0, jb = 0;
+  auto stash = [&](int q, const Pre& o) {
     const bool okq = q >= 0 && q < nz, mA = okq && vA, mB = okq && vB;
     if (KIND == 1) {
-      ia = mA ? raw_a(ri) : 0.0;
-      ib = mB ? raw_b(ri) : 0.0;
+      ia = mA ? raw_a(o.ri) : 0.0;
+      ib = mB ? raw_b(o.ri) : 0.0;
     }
-    fa = mA ? raw_a(rf) : 0.0;
-    fb = mB ? raw_b(rf) : 0.0;
+    ja = I1g ? raw_a(o.r1) : 0.0;
+    jb = I1g ? raw_b(o.r1) : 0.0;
+    fa = mA ? raw_a(o.rf) : 0.0;
+    fb = mB ? raw_b(o.rf) : 0.0;
     if (KIND == 1 && MODE == 2) {  // refinement update x64 + s e, written by the cell's owner
-      fa += mA ? es * raw_a(re) : 0.0;
-      fb += mB ? es * raw_b(re) : 0.0;
+      fa += mA ? es * raw_a(o.re) : 0.0;
+      fb += mB ? es * raw_b(o.re) : 0.0;
       if (vA && q >= q0 && q < q1) st2(x64_out + G.off + q * pl + own, vec, vB, fa, fb);
     }
     if (KIND == 1 && MODE >= 1) {
@@ -166,37 +177,33 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
 #pragma unroll
     for (int k = 0; k < NHR; ++k)
       if (tid + NT * k < NHALO) {
-        double v = raw_d(rh[k]);
-        if (KIND == 1 && MODE == 2) v += es * raw_d(rhe[k]);
-        if (KIND == 1 && MODE >= 1) v -= raw_d(rhi[k]);
+        double v = raw_d(o.rh[k]);
+        if (KIND == 1 && MODE == 2) v += es * raw_d(o.rhe[k]);
+        if (KIND == 1 && MODE >= 1) v -= raw_d(o.rhi[k]);
         P[hoff[k]] = (okq && hv[k]) ? v : 0.0;
       }
   };
-  // I1 pair at plane q (raw), prefetched one plane ahead
-  Raw2<T1> r1n;
-  auto fetch1 = [&](int q) {  // raw, clamped; used only for k in [q0, q1) with vA / vB
-    if (I1g) ld_raw2(I1g + min(max(q, 0), nz - 1) * G.ipz + (vA ? ownu : 0), ivec, vB, r1n);
-  };
 
-  // registers: F and I0 at k - 1 (m), k (c), k + 1 (p)
+  // registers: F and I0 at k - 1 (m), k (c), k + 1 (p); I1 at k (c) and k + 1 (p)
   double fma_ = 0, fmb = 0, fca, fcb, fpa, fpb, ima = 0, imb = 0, ica = 0, icb = 0, ipa = 0, ipb = 0;
-  fetch(q0 - 1);
-  stash(q0 - 1);  // plane q0 - 1 goes to the ring slot of q0 + 2, rewritten before it is read
+  double jca = 0, jcb = 0, jpa = 0, jpb = 0;
+  Pre A, B;
+  fetch(q0 - 1, A);
+  stash(q0 - 1, A);  // plane q0 - 1 goes to the ring slot of q0 + 2, rewritten before it is read
   fma_ = fa; fmb = fb; ima = ia; imb = ib;
-  fetch(q0);
-  stash(q0);
-  fca = fa; fcb = fb; ica = ia; icb = ib;
-  fetch(q0 + 1);
-  fetch1(q0);
+  fetch(q0, A);
+  stash(q0, A);
+  fca = fa; fcb = fb; ica = ia; icb = ib; jca = ja; jcb = jb;
+  fetch(q0 + 1, A);
+  fetch(q0 + 2, B);
   double nrm = 0.0;
-  for (int k = q0; k < q1; ++k) {
-    stash(k + 1);
-    fpa = fa; fpb = fb; ipa = ia; ipb = ib;
-    const Raw2<T1> r1 = r1n;
-    fetch(k + 2);
-    fetch1(k + 1);
+  // plane k: slot o holds plane k + 1, refilled with plane k + 3
+  auto iter = [&](int k, Pre& o) {
+    stash(k + 1, o);
+    fpa = fa; fpb = fb; ipa = ia; ipb = ib; jpa = ja; jpb = jb;
+    fetch(k + 3, o);
     __syncthreads();
-    const double v1a = I1g ? raw_a(r1) : 0.0, v1b = I1g ? raw_b(r1) : 0.0;
+    const double v1a = jca, v1b = jcb;
     const double* P = &X[k % 3][0][0];
     const bool zm = k > 0, zp = k < nz - 1;
     double ra = 0.0, rb = 0.0;
@@ -263,7 +270,14 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     }
     fma_ = fca; fmb = fcb; fca = fpa; fcb = fpb;
     ima = ica; imb = icb; ica = ipa; icb = ipb;
+    jca = jpa; jcb = jpb;
+  };
+  int k = q0;
+  for (; k + 1 < q1; k += 2) {
+    iter(k, A);
+    iter(k + 1, B);
   }
+  if (k < q1) iter(k, A);
   if (partials) {
     const double sm = block_sum(nrm, red);
     if (threadIdx.x == 0) partials[t.bid] = sm;
