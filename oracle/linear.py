@@ -99,3 +99,76 @@ def relative_residual(x, I0, beta):
     """||b - A x|| / ||b|| of the Linear AD system."""
     b = rhs_ad(I0, beta)
     return float(np.linalg.norm(b - apply(x, 0.0, beta)) / np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------------------
+# per-slice screened Poisson (Eq. (2)) in the same space
+
+
+def _slice_tables(ny, nx):
+    """(M, K) pairs (x, y, z) of one 2-D slice seen as a one-plane grid."""
+    return tables((1, ny, nx))
+
+
+def rhs_sp(I0, I1, alpha, beta_xy=(1.0, 1.0)):
+    """Right-hand side of Eq. (2) per slice with the value target I1 and the
+    gradient target grad I0 both interpolated in the hat-function space:
+    alpha Mx My I1 + (b_x Kx My + b_y Mx Ky) I0."""
+    I0 = grid.as3d(I0)
+    I1 = grid.as3d(I1)
+    out = np.empty(I0.shape)
+    T = _slice_tables(I0.shape[1], I0.shape[2])
+    for z in range(I0.shape[0]):
+        out[z] = (hybrid.apply(I1[z:z + 1], T, alpha, (0.0, 0.0, 0.0))
+                  + hybrid.apply(I0[z:z + 1], T, 0.0, (beta_xy[0], beta_xy[1], 0.0)))[0]
+    return out
+
+
+def apply_sp(x, alpha, beta_xy=(1.0, 1.0)):
+    """The per-slice operator alpha Mx My + b_x Kx My + b_y Mx Ky."""
+    x = grid.as3d(x)
+    out = np.empty(x.shape)
+    T = _slice_tables(x.shape[1], x.shape[2])
+    for z in range(x.shape[0]):
+        out[z] = hybrid.apply(x[z:z + 1], T, alpha, (beta_xy[0], beta_xy[1], 0.0))[0]
+    return out
+
+
+def sp_solve(I0, I1, alpha, beta_xy=(1.0, 1.0), method="cg", rtol=1e-13, maxiter=100000):
+    """Eq. (2) with the Linear discretisation, slice by slice (SPD for
+    alpha > 0): method 'dense' (tiny slices) or 'cg'."""
+    I0 = grid.as3d(I0)
+    I1 = grid.as3d(I1)
+    b = rhs_sp(I0, I1, alpha, beta_xy)
+    x = np.empty(I0.shape)
+    ny, nx = I0.shape[1:]
+    for z in range(I0.shape[0]):
+        if method == "dense":
+            A = hybrid.kron_operator(_slice_tables(ny, nx), alpha, (beta_xy[0], beta_xy[1], 0.0))
+            x[z] = np.linalg.solve(A, b[z].ravel()).reshape(ny, nx)
+            continue
+        xs = np.zeros((1, ny, nx))
+        bz = b[z:z + 1]
+        r = bz - apply_sp(xs, alpha, beta_xy)
+        p = r.copy()
+        rr = float(np.sum(r * r))
+        nb = np.linalg.norm(bz)
+        it = 0
+        while it < maxiter and np.sqrt(rr) > rtol * nb:
+            q = apply_sp(p, alpha, beta_xy)
+            a = rr / float(np.sum(p * q))
+            xs += a * p
+            r -= a * q
+            rn = float(np.sum(r * r))
+            p = r + (rn / rr) * p
+            rr = rn
+            it += 1
+        x[z] = xs[0]
+    return x
+
+
+def sp_relative_residuals(x, I0, I1, alpha, beta_xy=(1.0, 1.0)):
+    """Per-slice ||b - A x|| / ||b|| of the Linear SP system."""
+    b = rhs_sp(I0, I1, alpha, beta_xy)
+    r = b - apply_sp(x, alpha, beta_xy)
+    return np.array([np.linalg.norm(r[z]) / np.linalg.norm(b[z]) for z in range(b.shape[0])])

@@ -101,3 +101,83 @@ def test_tables_are_the_hybrid_level0_with_mass():
     assert np.array_equal(K, hybrid.laplace_1d(5))
     # hats sum to one, so a row sum is the hat's integral: 1 inside, 1/2 at the ends
     assert np.allclose(M.sum(axis=1), [0.5, 1.0, 1.0, 1.0, 0.5]) and np.isclose(M.sum(), 4.0)
+
+
+# ---- per-slice screened Poisson (Eq. (2)) in the same space
+
+
+def test_sp_rhs_by_quadrature():
+    """b_v = integral alpha phi_v I1 + b_x dphi_v/dx dI0/dx + b_y dphi_v/dy dI0/dy
+    over a slice, I0 and I1 interpolated: tensor Gauss quadrature per cell."""
+    ny, nx = 3, 4
+    rng = np.random.default_rng(2)
+    I0 = rng.standard_normal((1, ny, nx))
+    I1 = rng.standard_normal((1, ny, nx))
+    alpha, beta = 0.3, (1.0, 0.5)
+    b = np.zeros((ny, nx))
+    for cy in range(ny - 1):
+        for cx in range(nx - 1):
+            for gy in GP:
+                for gx in GP:
+                    y, x = cy + gy, cx + gx
+                    w = 0.25
+                    hx = np.array([hat(i, x) for i in range(nx)])
+                    hy = np.array([hat(j, y) for j in range(ny)])
+                    dx = np.array([dhat(i, x) for i in range(nx)])
+                    dy = np.array([dhat(j, y) for j in range(ny)])
+                    v1 = hy @ I1[0] @ hx
+                    g0x = hy @ I0[0] @ dx
+                    g0y = dy @ I0[0] @ hx
+                    for j in range(ny):
+                        for i in range(nx):
+                            b[j, i] += w * (alpha * hy[j] * hx[i] * v1 + beta[0] * hy[j] * dx[i] * g0x
+                                            + beta[1] * dy[j] * hx[i] * g0y)
+    assert np.abs(linear.rhs_sp(I0, I1, alpha, beta)[0] - b).max() < 1e-13
+
+
+def _energy_sp(I, I0, I1, alpha, beta):
+    """alpha |I - I1|^2_M + b_x |dI/dx - dI0/dx|^2 + b_y |dI/dy - dI0/dy|^2
+    of one slice with the Kronecker-assembled Gram matrices (independent of
+    the oracle's separable application)."""
+    ny, nx = I.shape
+    Mx, My = linear.mass_1d(nx), linear.mass_1d(ny)
+    Kx, Ky = linear.stiffness_1d(nx), linear.stiffness_1d(ny)
+    M = np.kron(My, Mx)
+    K = beta[0] * np.kron(My, Kx) + beta[1] * np.kron(Ky, Mx)
+    d1 = (I - I1).ravel()
+    d0 = (I - I0).ravel()
+    return alpha * d1 @ M @ d1 + d0 @ K @ d0
+
+
+@pytest.mark.parametrize("shape", [(2, 5, 7), (1, 1, 6), (3, 4, 1)])
+def test_sp_solution_minimises_the_energy(shape):
+    rng = np.random.default_rng(3)
+    I0 = rng.uniform(0, 50, shape)
+    I1 = I0 + rng.standard_normal(shape) * 5
+    alpha, beta = 0.05, (1.0, 0.7)
+    x = linear.sp_solve(I0, I1, alpha, beta, method="dense")
+    xc = linear.sp_solve(I0, I1, alpha, beta, method="cg")
+    assert np.abs(x - xc).max() < 1e-9 * np.abs(x).max()
+    for z in range(shape[0]):
+        e0 = _energy_sp(x[z], I0[z], I1[z], alpha, beta)
+        for _ in range(4):
+            d = rng.standard_normal(x[z].shape) * 1e-3
+            assert _energy_sp(x[z] + d, I0[z], I1[z], alpha, beta) > e0
+    assert linear.sp_relative_residuals(xc, I0, I1, alpha, beta).max() < 1e-12
+
+
+def test_sp_special_cases():
+    rng = np.random.default_rng(4)
+    I0 = rng.uniform(0, 50, (2, 6, 5))
+    # target values equal to the input: the input comes back
+    assert np.abs(linear.sp_solve(I0, I0, 0.01, method="dense") - I0).max() < 1e-10
+    # a per-slice constant offset of the target is reproduced exactly (K kills constants)
+    off = np.array([3.0, -7.0])[:, None, None]
+    assert np.abs(linear.sp_solve(I0, I0 + off, 0.01, method="dense") - (I0 + off)).max() < 1e-9
+    # large alpha: the value target wins
+    I1 = rng.uniform(0, 50, I0.shape)
+    assert np.abs(linear.sp_solve(I0, I1, 1e9, method="dense") - I1).max() < 1e-5
+    # the answer differs from the 7-point (Constant) one
+    from oracle import solvers
+
+    assert np.abs(linear.sp_solve(I0, I1, 0.01, method="dense") - solvers.sp_dct(I0, I1, 0.01)).max() > 1e-3
