@@ -57,8 +57,8 @@ def parse():
     p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
     p.add_argument("--fmg", type=int, default=None, help="1: full-multigrid start of the plain solves")
     p.add_argument("--discretization", default="constant", choices=["constant", "hybrid", "linear"],
-                   help="transfers and coarse operators of the AD solve (Sec. 4.2); the per-slice SP batch "
-                        "always uses the Constant scheme")
+                   help="discretisation of both solves (Sec. 4.2); Hybrid and Linear solve the SP slices one "
+                        "by one")
     p.add_argument("--prolong", default="trilinear", choices=["trilinear", "constant"],
                    help="up-sampling of the Constant scheme: cell-centred trilinear or replication")
     p.add_argument("--inner-cycles", type=int, default=None,
@@ -624,7 +624,7 @@ def run_stack_leg(a, gd, synth, torch, spec, storage, refine, steps, warmup):
 
     def step(timing):
         r1 = gd.smooth_z_into(I0, I1, BETA, timing=timing, **ad_opts)
-        _, r2, _ = gd.screened_poisson_stack(I0, I1, ALPHA, timing=timing, out=I2, **opts)
+        _, r2, _ = gd.screened_poisson_stack(I0, I1, ALPHA, timing=timing, out=I2, **ad_opts)
         return r1, r2
 
     for _ in range(warmup):

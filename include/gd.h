@@ -92,10 +92,11 @@ typedef struct {
                            Galerkin 27-point coarse operators relaxed by
                            8-colour Gauss-Seidel (same answer); 2 "Linear":
                            trilinear B-spline finite elements on every level
-                           (27-point, a different discrete answer; AD and the
-                           hierarchy calls only, no FP64 refinement).  1 and 2
-                           take single-grid solves only (slice batches:
-                           GD_ERR_UNSUPPORTED). */
+                           (27-point, a different discrete answer; no FP64
+                           refinement, not for the gradient-modulation
+                           filter).  Slice batches with 1 or 2 solve every
+                           slice as a one-plane grid of its own, in turn
+                           (slices of one size share a cached hierarchy). */
   int sweep_quad;       /* 1 (default): the relaxation of FP16/BF16 level
                            arrays, and of FP32 3-D grids, runs in its quad
                            form (four x cells per thread, one aligned

@@ -1387,6 +1387,43 @@ static Outcome solve_linear_ad(Hier& H, const Problem& P, const gd_solve_opts& o
   return R;
 }
 
+// SP (Eq. (2)) of one slice with the Linear discretisation: A = alpha Mx My +
+// b_x Kx My + b_y Mx Ky on the slice's hat functions.  In correction form
+// E = I2 - I0 the system is A E = alpha Mx My (I1 - I0); the canonical
+// right-hand side (for the residual's denominator) is alpha Mx My I1 +
+// (b_x Kx My + b_y Mx Ky) I0 = A I0 + alpha Mx My (I1 - I0).  Every product
+// comes from the table residual r = b - A x of suitable x and b.
+static Outcome solve_linear_sp(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
+  prep(H, o);
+  Level& L0 = H.lv[0];
+  const GridDesc& g0 = L0.h[0];
+  const size_t es = dsize(H.s);
+  HybTables Ta = H.lin[0], Tf = H.lin[0];  // alpha Mx My only; the whole operator
+  Ta.w[0] = Ta.w[1] = Ta.w[2] = 0.0;
+  // -alpha M (I1 - I0): x = I1 - I0 against b = 0
+  HIP_TRY(hipMemsetAsync(L0.b, 0, L0.total * es, st));
+  HIP_TRY(launch_load_comb(P.tin, P.t1, H.s, g0, P.I0, P.I1, -1.0, 1.0, L0.x, st));
+  HIP_TRY(launch_hyb_residual(H.s, g0, Ta, L0.x, L0.b, L0.xt, st));
+  // with b = -alpha M (I1 - I0) and x = I0: r = -(canonical right-hand side)
+  HIP_TRY(hipMemcpyAsync(L0.b, L0.xt, L0.total * es, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(launch_load_comb(P.tin, P.t1, H.s, g0, P.I0, nullptr, 1.0, 0.0, L0.x, st));
+  HIP_TRY(launch_hyb_residual(H.s, g0, Tf, L0.x, L0.b, L0.xt, st, H.hyb_part));
+  HIP_TRY(launch_reduce(H.hyb_part, H.tab_b0, 1, 1, H.dred, st));
+  read_dred(H, 1, st);
+  const double bnorm = std::sqrt(H.hpin[0]);
+  // the correction's right-hand side alpha M (I1 - I0): x = I0 - I1 against b = 0
+  HIP_TRY(hipMemsetAsync(L0.b, 0, L0.total * es, st));
+  HIP_TRY(launch_load_comb(P.tin, P.t1, H.s, g0, P.I0, P.I1, 1.0, -1.0, L0.x, st));
+  HIP_TRY(launch_hyb_residual(H.s, g0, Ta, L0.x, L0.b, L0.xt, st));
+  HIP_TRY(hipMemcpyAsync(L0.b, L0.xt, L0.total * es, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * es, st));
+  H.count(0, 3.0 * (double)dsize(P.tin) + 2.0 * (double)dsize(P.t1) + 14.0 * (double)es);
+  Outcome R = solve_corr(H, o, bnorm, st);
+  finish(H, P, 0, st);
+  HIP_TRY(hipStreamSynchronize(st));
+  return R;
+}
+
 static void fill_report(gd_solve_report* rep, const Outcome& R, int g, double secs, int levels,
                         double share = 1.0) {
   rep->fallback_used = 0;
@@ -1672,9 +1709,56 @@ gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1,
   if (opts) o = *opts;
   gd_status s = check_opts(o);
   if (s != GD_OK) return s;
-  if (o.discretization == 2)
-    return fail(GD_ERR_UNSUPPORTED, "gd_screened_poisson_slices: the Linear discretisation is built for the AD solve only");
+  if (o.discretization == 2 && o.fp64_refine)
+    return fail(GD_ERR_UNSUPPORTED, "gd_screened_poisson_slices: FP64 refinement is not built for the Linear discretisation");
   hipStream_t st = (hipStream_t)stream;
+  if (o.discretization != 0) {
+    // Hybrid and Linear (Sec. 4.2): each slice is a one-plane grid of its own
+    // (the 27-point table levels take one grid per hierarchy), solved in turn;
+    // slices of one size share a cached hierarchy
+    return run_guarded([&]() -> gd_status {
+      const auto t0 = std::chrono::steady_clock::now();
+      bool numeric = false, converged = true;
+      double worst = 0.0, bytes = 0.0;
+      int cycles = 0, steps = 0, levels = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        const gd_slice_desc& d = sl[i];
+        // the slice's rows are the grid's z axis (one line per plane), as in
+        // the batched Constant path
+        std::vector<GridSpec> g1{{d.nx, 1, d.ny, (double)d.alpha, bx, 0.0, by, d.offset, d.pitch, d.pitch}};
+        g1[0].zin = 1;
+        HierLease H = get_hier(o.discretization == 1 ? "sp-hybrid" : "sp-linear", g1, o.storage,
+                               o.fp64_refine != 0, st, o.sweep_tile);
+        Problem P{I0, I1, I2, t, tout, false, t1};
+        Outcome R = o.discretization == 2 ? solve_linear_sp(*H, P, o, st)
+                    : o.fp64_refine       ? solve_mixed(*H, P, o, st)
+                                          : solve_plain(*H, P, o, st);
+        if (per) fill_report(&per[i], R, 0, 0.0, (int)H->lv.size());
+        numeric = numeric || R.numeric;
+        converged = converged && R.converged;
+        worst = std::max(worst, R.rel.empty() ? 0.0 : R.rel[0]);
+        cycles = std::max(cycles, R.cycles);
+        steps = std::max(steps, R.steps);
+        levels = std::max(levels, (int)H->lv.size());
+        bytes += R.bytes;
+      }
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (per)
+        for (int64_t i = 0; i < n; ++i) per[i].seconds = secs;
+      if (rep) {
+        std::memset(rep, 0, sizeof *rep);
+        rep->cycles = cycles;
+        rep->refine_steps = steps;
+        rep->rel_residual = worst;
+        rep->seconds = secs;
+        rep->levels = levels;
+        rep->bytes = bytes;
+      }
+      if (numeric) return fail(GD_ERR_NUMERIC, "gd_screened_poisson_slices: non-finite residual");
+      if (!converged) return fail(GD_ERR_NOT_CONVERGED, "gd_screened_poisson_slices: tolerance not reached");
+      return GD_OK;
+    });
+  }
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
     HierLease H = get_hier("sp", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);

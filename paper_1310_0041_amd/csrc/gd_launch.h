@@ -102,6 +102,10 @@ hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T
                                void* r, hipStream_t st, double* partials = nullptr);
 // the caller's input I0 (dtype tin, layout ioff / ipy / ipz of G) into a level array of dtype s
 hipError_t launch_load_input(gd_dtype tin, gd_dtype s, const GridDesc& G, const void* in, void* out, hipStream_t st);
+// out = c0 in0 + c1 in1 (FP64 arithmetic): the caller's inputs (layout ioff /
+// ipy / ipz of G; in1 of type t1 = tin, F32 or F64, or NULL) into a level array
+hipError_t launch_load_comb(gd_dtype tin, gd_dtype t1, gd_dtype s, const GridDesc& G, const void* in0,
+                            const void* in1, double c0, double c1, void* out, hipStream_t st);
 // r = b - A x on the finest (7-point) level of a Hybrid hierarchy, with
 // per-block FP64 sums of r^2 in partials[0 .. hyb_residual7_blocks(G))
 int64_t hyb_residual7_blocks(const GridDesc& G);

@@ -637,6 +637,23 @@ k_load_input(GridDesc G, const Tin* __restrict__ in, S* __restrict__ out) {
     st64(out + G.off + k * pl + (int64_t)j * G.px + i, in_at(in, G.ioff + (int64_t)k * G.ipz + (int64_t)j * G.ipy + i));
 }
 
+// out = c0 in0 + c1 in1 (FP64 arithmetic) from the caller's arrays into a
+// level array; in1 (may be NULL) has the layout of in0
+template <typename Tin, typename T1, typename S>
+__global__ void __launch_bounds__(HBX * HBY)
+k_load_comb(GridDesc G, const Tin* __restrict__ in0, const T1* __restrict__ in1, double c0, double c1,
+            S* __restrict__ out) {
+  const int i = blockIdx.x * HBX + threadIdx.x, j = blockIdx.y * HBY + threadIdx.y;
+  if (i >= G.nx || j >= G.ny) return;
+  const int64_t pl = (int64_t)G.px * G.ny;
+  for (int k = blockIdx.z * HZ; k < min((int)(blockIdx.z + 1) * HZ, G.nz); ++k) {
+    const int64_t u = G.ioff + (int64_t)k * G.ipz + (int64_t)j * G.ipy + i;
+    double v = c0 * in_at(in0, u);
+    if (in1) v += c1 * in_at(in1, u);
+    st64(out + G.off + k * pl + (int64_t)j * G.px + i, v);
+  }
+}
+
 // r = b - A x on the finest (7-point) level, with the FP64 sum of r^2 per
 // block (partials[block], block = x + gx (y + gy z)), summed in a fixed
 // order.  A thread takes HZ7 z-samples; a full chunk is unrolled so that its
@@ -987,6 +1004,38 @@ static void load_input_launch(gd_dtype s, const GridDesc& G, const void* in, voi
     default: break;
   }
 #undef L
+}
+
+template <typename TI, typename T1>
+static hipError_t load_comb_launch(gd_dtype s, const GridDesc& G, const void* in0, const void* in1, double c0,
+                                   double c1, void* out, hipStream_t st) {
+#define L(TT) hipLaunchKernelGGL((k_load_comb<TI, T1, TT>), hyb_grid(G.nx, G.ny, G.nz), dim3(HBX, HBY), 0, st, G, \
+                                 (const TI*)in0, (const T1*)in1, c0, c1, (TT*)out)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return hipSuccess;
+}
+
+hipError_t launch_load_comb(gd_dtype tin, gd_dtype t1, gd_dtype s, const GridDesc& G, const void* in0,
+                            const void* in1, double c0, double c1, void* out, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (!in1 || t1 == tin) {
+#define L(TI) e = load_comb_launch<TI, TI>(s, G, in0, in1, c0, c1, out, st)
+    GD_DISPATCH_S(tin, L)
+#undef L
+  } else if (t1 == GD_F64) {
+#define L(TI) e = load_comb_launch<TI, double>(s, G, in0, in1, c0, c1, out, st)
+    GD_DISPATCH_S(tin, L)
+#undef L
+  } else if (t1 == GD_F32) {
+#define L(TI) e = load_comb_launch<TI, float>(s, G, in0, in1, c0, c1, out, st)
+    GD_DISPATCH_S(tin, L)
+#undef L
+  } else {
+    return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  return last();
 }
 
 hipError_t launch_load_input(gd_dtype tin, gd_dtype s, const GridDesc& G, const void* in, void* out, hipStream_t st) {

@@ -120,11 +120,50 @@ def test_npr_hybrid(gd):
     assert np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
 
 
-def test_slice_batch_hybrid_unsupported(gd):
-    I0 = torch.rand(3, 16, 32, device="cuda")
-    with pytest.raises(gd.GDError) as ei:
-        gd.screened_poisson_stack(I0, I0.clone(), 0.01, discretization=1)
-    assert ei.value.status == gd.ERR_UNSUPPORTED
+def _sp_inputs(shape, seed):
+    nz, ny, nx = shape
+    I0 = synth.make_stack(synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, seed)).numpy()
+    rng = np.random.default_rng(seed)
+    I1 = I0 * rng.uniform(0.8, 1.2, (nz, 1, 1)) + rng.uniform(-20, 20, (nz, 1, 1))
+    return I0, I1
+
+
+@pytest.mark.parametrize("shape", [(5, 33, 47), (1, 64, 96), (3, 1, 40)])
+def test_sp_hybrid_stack(gd, shape):
+    """Eq. (2) with the Hybrid scheme (7-point finest level, B-spline
+    transfers, Galerkin coarse levels): the 7-point answer, so the DCT
+    oracle's, slice by slice."""
+    say("hybrid SP stack", shape)
+    I0, I1 = _sp_inputs(shape, 13100426)
+    out, rep, per = gd.screened_poisson_stack(torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), 0.01,
+                                              storage=gd.F64, rel_tol=1e-10, discretization=1)
+    assert rep["status"] == 0 and max(p["rel_residual"] for p in per) <= 1e-10
+    ref = solvers.sp_dct(I0, I1, 0.01)
+    assert np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
+
+
+def test_sp_hybrid_uneven_batch_fp32_and_mixed(gd):
+    """A batch of uneven slices with per-slice alpha, Hybrid: plain FP32 to
+    1e-6 (error bar 1e-5) and FP16 storage with FP64 refinement (1e-6)."""
+    say("hybrid SP batch")
+    meta = synth.make_slice_batch(nslices=7, lo=20, hi=150, seed=81, dtype=torch.float64)
+    descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
+    a0, a1 = meta["I0"].numpy(), meta["I1"].numpy()
+    for kw, dt, bar in ((dict(), torch.float32, 1e-5),
+                        (dict(storage=gd.F16, fp64_refine=1, rel_tol=5e-8), torch.float16, 1e-6)):
+        I0 = meta["I0"].to(dt)
+        I1 = meta["I1"].to(torch.float32)
+        out, rep, per = gd.screened_poisson_slices(I0.cuda(), I1.cuda(), descs, discretization=1,
+                                                   out_dtype=torch.float64, **kw)
+        assert rep["status"] == 0, rep
+        q0, q1, got = I0.double().numpy(), I1.double().numpy(), out.cpu().numpy()
+        for i in range(7):
+            o, w, h = meta["offset"][i], meta["w"][i], meta["h"][i]
+            ref = solvers.sp_dct(q0[o:o + w * h].reshape(1, h, w), q1[o:o + w * h].reshape(1, h, w),
+                                 float(np.float32(meta["alpha"][i])))
+            err = np.linalg.norm(got[o:o + w * h].reshape(1, h, w) - ref) / np.linalg.norm(ref)
+            assert err <= bar, (i, err, kw)
+            assert per[i]["rel_residual"] <= kw.get("rel_tol", 1e-6)
 
 
 @pytest.mark.parametrize("shape", [(9, 17, 30), (5, 8, 8), (1, 12, 40), (16, 3, 5), (2, 2, 2), (1, 1, 1)])
@@ -179,10 +218,51 @@ def test_linear_ad_solve_fp32(gd):
     assert np.linalg.norm(ref - solvers.ad_dct(I0, beta)) > 1e-4 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("shape", [(4, 24, 37), (1, 50, 64), (2, 1, 30)])
+def test_linear_sp_fp64(gd, shape):
+    """Eq. (2) with the Linear scheme against its own oracle (per-slice CG),
+    FP64: every slice's residual of the Linear system and the answer."""
+    say("linear SP f64", shape)
+    I0, I1 = _sp_inputs(shape, 13100427)
+    out, rep, per = gd.screened_poisson_stack(torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), 0.01,
+                                              storage=gd.F64, rel_tol=1e-10, discretization=2)
+    x = out.cpu().numpy()
+    assert rep["status"] == 0
+    res = linear.sp_relative_residuals(x, I0, I1, 0.01)
+    say("oracle residuals", res, "reported", [p["rel_residual"] for p in per])
+    # the library measures the residual of the correction system in its own
+    # (FP64) arithmetic; the oracle's of I0 + E agrees to a few 1e-11
+    assert res.max() <= 2e-10, res
+    ref = linear.sp_solve(I0, I1, 0.01, method="cg")
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 1e-8
+    # a different answer from the 7-point one
+    assert np.linalg.norm(ref - solvers.sp_dct(I0, I1, 0.01)) > 1e-5 * np.linalg.norm(ref)
+
+
+def test_linear_sp_fp32_uneven(gd):
+    say("linear SP f32 batch")
+    meta = synth.make_slice_batch(nslices=5, lo=16, hi=120, seed=82, dtype=torch.float32)
+    descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
+    out, rep, per = gd.screened_poisson_slices(meta["I0"].cuda(), meta["I1"].cuda(), descs, discretization=2,
+                                               out_dtype=torch.float64, check=False)
+    a0, a1, got = meta["I0"].double().numpy(), meta["I1"].double().numpy(), out.cpu().numpy()
+    for i in range(5):
+        o, w, h = meta["offset"][i], meta["w"][i], meta["h"][i]
+        s0, s1 = a0[o:o + w * h].reshape(1, h, w), a1[o:o + w * h].reshape(1, h, w)
+        al = float(np.float32(meta["alpha"][i]))
+        x = got[o:o + w * h].reshape(1, h, w)
+        # a plain FP32 correction stops at its rounding floor when that is above 1e-6
+        floor = linear.sp_relative_residuals(s0 + (linear.sp_solve(s0, s1, al) - s0).astype(np.float32), s0, s1,
+                                             al)[0]
+        assert linear.sp_relative_residuals(x, s0, s1, al)[0] <= max(1.01e-6, 3.0 * floor)
+        ref = linear.sp_solve(s0, s1, al)
+        assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 1e-5, i
+
+
 def test_linear_unsupported_cases(gd):
     I0 = torch.rand(3, 16, 32, device="cuda") * 100
     with pytest.raises(gd.GDError) as ei:
-        gd.screened_poisson_stack(I0, I0.clone(), 0.01, discretization=2)
+        gd.screened_poisson_stack(I0.half(), I0.float(), 0.01, storage=gd.F16, fp64_refine=1, discretization=2)
     assert ei.value.status == gd.ERR_UNSUPPORTED
     with pytest.raises(gd.GDError) as ei:
         gd.npr_filter(I0, discretization=2)
