@@ -292,6 +292,29 @@ gd_status gd_hierarchy_create_streamed(gd_hierarchy** h, int64_t nx, int64_t ny,
                                        double alpha, double beta_x, double beta_y, double beta_z,
                                        gd_dtype storage, const gd_solve_opts* opts, int64_t slab,
                                        int stream_levels, void* stream);
+/* Anisotropic diffusion, Eq. (1), of a stack that stays in HOST memory (the
+ * paper's setting: the volume does not fit the device; Sec. 4.1 streams
+ * every pass through a window of slices).  I0 (in_t) and I1 (out_t) are
+ * dense [nz][ny][nx] host arrays of the caller (hipHostMalloc memory lets
+ * the copies run at the link's pinned rate).  Every step runs on the GPU in
+ * passes over z-slabs of `slab` planes: the right-hand side of the
+ * correction E = I1 - I0 and the canonical norm (one halo plane per side);
+ * the V-cycles of a streamed hierarchy (as gd_hierarchy_create_streamed
+ * with stream_levels; E and its right-hand side in pinned host arrays of
+ * the library, 2 x storage bytes per voxel); the FP64 canonical residual
+ * after each cycle, itself a streaming pass; the sum of E for the gauge
+ * mean(I1) = mean(I0); and the output I0 + E - mean(E), written back slab
+ * by slab.  Options as gd_smooth_z with plain FP32 or FP64 storage (no
+ * refinement) and the Constant discretisation, others GD_ERR_UNSUPPORTED.
+ * device_budget > 0: the call needs at most that many device bytes (the
+ * streamed hierarchy and the pass windows), or returns GD_ERR_NOMEM before
+ * any pass.  rep->bytes: the HBM bytes of the setup and output passes. */
+gd_status gd_smooth_z_streamed(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
+                               int64_t nx, int64_t ny, int64_t nz,
+                               double beta_x, double beta_y, double beta_z,
+                               const gd_solve_opts* opts, int64_t slab, int stream_levels,
+                               int64_t device_budget, gd_solve_report* rep, void* stream);
+
 /* ncycles V-cycles on A x = b with x (in/out) and b (in) in HOST memory, dense
  * [nz][ny][nx] arrays of the storage dtype, owned by the caller.  Memory
  * from hipHostMalloc lets copies overlap the kernels; pageable memory works

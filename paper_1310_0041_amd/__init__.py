@@ -107,6 +107,8 @@ _SIGS = {
     "gd_hierarchy_create_streamed": (_i, [ctypes.POINTER(_vp), _i64, _i64, _i64, _d, _d, _d, _d, _i,
                                           ctypes.POINTER(SolveOpts), _i64, _i, _vp]),
     "gd_vcycle_streamed": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
+    "gd_smooth_z_streamed": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, ctypes.POINTER(SolveOpts), _i64,
+                                  _i, _i64, ctypes.POINTER(Report), _vp]),
     "gd_hierarchy_device_bytes": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "gd_hierarchy_streamed_levels": (_i, [_vp, ctypes.POINTER(_i)]),
     "gd_rb_sweep": (_i, [_vp, _vp, _vp, _i, _i64, _i64, _i64, _d, _d, _d, _d, _vp]),
@@ -498,6 +500,28 @@ class StreamedHierarchy(Hierarchy):
         _check(_lib.gd_vcycle_streamed(self._h, _host_ptr(x), _host_ptr(b), int(ncycles),
                                        ctypes.byref(rr) if relres else None, _stream()))
         return rr.value if relres else None
+
+
+def smooth_z_streamed(I0, beta=(1.0, 1.0, 4.0), out_dtype=None, slab=32, levels=0, device_budget=0, out=None,
+                      opts=None, check=True, **kw):
+    """Anisotropic diffusion (Eq. (1)) of a stack in HOST memory (CPU
+    tensors, pinned ones copy fastest), streamed through HBM in z-slabs.
+    Returns (I1 on the host, report)."""
+    lib = load()
+    torch = _torch()
+    nz, ny, nx = I0.shape
+    if out is None:
+        out = torch.empty(I0.shape, dtype=out_dtype or I0.dtype, pin_memory=I0.is_pinned())
+    if tuple(out.shape) != tuple(I0.shape):
+        raise ValueError("out must have I0's shape")
+    o = opts or default_opts(**kw)
+    rep = Report()
+    st = lib.gd_smooth_z_streamed(_host_ptr(I0), gd_dtype(I0.dtype), _host_ptr(out), gd_dtype(out.dtype), nx, ny, nz,
+                                  float(beta[0]), float(beta[1]), float(beta[2]), ctypes.byref(o), int(slab),
+                                  int(levels), int(device_budget), ctypes.byref(rep), _stream())
+    if check:
+        _check(st)
+    return out, dict(rep.as_dict(), status=st)
 
 
 class Net:

@@ -2230,6 +2230,32 @@ static void stream_pass(gd_hierarchy& h, int l, bool down, void* xh, const void*
   HIP_TRY(hipStreamWaitEvent(st, S.done_down, 0));
 }
 
+// sum (b - A x)^2 and sum b^2 over the finest level of a streamed hierarchy
+// (x, b in host memory), one streaming pass, every window contributing the
+// planes of its own slab
+static void streamed_residual(gd_hierarchy& h, const void* x, const void* b, double& rr, double& bb,
+                              hipStream_t st) {
+  Hier& H = *h.H;
+  Streamer& S = *h.sm;
+  const GridDesc& g0 = H.lv[0].h[0];
+  const size_t es = dsize(H.s), wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es;
+  const size_t hplane = (size_t)g0.nx * g0.ny * es;
+  rr = bb = 0.0;
+  for (const auto& W : S.lv[0].wins) {
+    Hier& WH = S.lv[0].win(0, W.e - W.a);
+    Level& L = WH.lv[0];
+    const size_t rows = (size_t)g0.ny * (W.e - W.a);
+    HIP_TRY(hipMemcpy2DAsync(L.x, pb, (const char*)x + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpy2DAsync(L.b, pb, (const char*)b + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_general_residual(WH.s, WH.g_ew(0), L.x, L.b, nullptr, WH.partials, st, true,
+                                    (int)(W.z0 - W.a), (int)(W.z1 - W.a)));
+    HIP_TRY(launch_reduce(WH.partials, L.ew.d_b0, 1, 2, WH.dred, st));
+    read_dred(WH, 2, st);
+    rr += WH.hpin[0];
+    bb += WH.hpin[1];
+  }
+}
+
 gd_status gd_vcycle_streamed(gd_hierarchy* h, void* x, const void* b, int ncycles, double* relres, void* stream) {
   if (!h || !x || !b) return fail(GD_ERR_INVALID, "gd_vcycle_streamed: null pointer");
   if (!h->sm) return fail(GD_ERR_INVALID, "gd_vcycle_streamed: the hierarchy keeps its finest level in HBM (gd_vcycle)");
@@ -2249,29 +2275,173 @@ gd_status gd_vcycle_streamed(gd_hierarchy* h, void* x, const void* b, int ncycle
       for (int l = ns - 1; l >= 0; --l) stream_pass(*h, l, false, X(l), B(l), st);
     }
     if (relres) {  // ||b - A x|| / ||b||, every window contributing its own slab's planes
-      const GridDesc& g0 = H.lv[0].h[0];
-      const size_t es = dsize(H.s), wb = (size_t)g0.nx * es, pb = (size_t)g0.px * es;
-      const size_t hplane = (size_t)g0.nx * g0.ny * es;
       double rr = 0.0, bb = 0.0;
-      for (const auto& W : S.lv[0].wins) {
-        Hier& WH = S.lv[0].win(0, W.e - W.a);
-        Level& L = WH.lv[0];
-        const size_t rows = (size_t)g0.ny * (W.e - W.a);
-        HIP_TRY(hipMemcpy2DAsync(L.x, pb, (const char*)x + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpy2DAsync(L.b, pb, (const char*)b + W.a * hplane, wb, wb, rows, hipMemcpyHostToDevice, st));
-        HIP_TRY(launch_general_residual(WH.s, WH.g_ew(0), L.x, L.b, nullptr, WH.partials, st, true,
-                                        (int)(W.z0 - W.a), (int)(W.z1 - W.a)));
-        HIP_TRY(launch_reduce(WH.partials, L.ew.d_b0, 1, 2, WH.dred, st));
-        read_dred(WH, 2, st);
-        rr += WH.hpin[0];
-        bb += WH.hpin[1];
-      }
+      streamed_residual(*h, x, b, rr, bb, st);
       rr = std::sqrt(rr);
       bb = std::sqrt(bb);
       *relres = bb > 0.0 ? rr / bb : rr;
       if (!std::isfinite(*relres)) return fail(GD_ERR_NUMERIC, "gd_vcycle_streamed: non-finite residual");
     }
     HIP_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+  });
+}
+
+// Anisotropic diffusion of a stack kept in host memory (Sec. 4.1: every pass
+// streams the data through a window).  Passes over z-slabs: the right-hand
+// side of the correction E = I1 - I0 (and the canonical norm), the V-cycles
+// of the streamed hierarchy with the residual checked by a streaming pass,
+// the sum of E for the gauge, and the output I0 + E - mean(E) written back
+// slab by slab.  E and its right-hand side live in pinned host arrays of the
+// library; only windows of planes are in HBM.
+gd_status gd_smooth_z_streamed(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, int64_t nx, int64_t ny,
+                               int64_t nz, double bx, double by, double bz, const gd_solve_opts* opts, int64_t slab,
+                               int stream_levels, int64_t device_budget, gd_solve_report* rep, void* stream) {
+  const std::string who = "gd_smooth_z_streamed";
+  gd_solve_opts o;
+  gd_status s0 = smooth_z_args(who, I0, in_t, I1, out_t, nx, ny, nz, bx, by, bz, opts, o);
+  if (s0 != GD_OK) return s0;
+  if (o.fp64_refine || (o.storage != GD_F32 && o.storage != GD_F64))
+    return fail(GD_ERR_UNSUPPORTED, who + ": plain FP32 or FP64 storage only (no refinement)");
+  if (o.discretization != 0) return fail(GD_ERR_UNSUPPORTED, who + ": the Constant discretisation only");
+  if (slab <= 0 || stream_levels < 0 || device_budget < 0) return fail(GD_ERR_INVALID, who + ": bad slab, levels or budget");
+  hipStream_t st = (hipStream_t)stream;
+  gd_hierarchy* hp = nullptr;
+  gd_status sc = gd_hierarchy_create_streamed(&hp, nx, ny, nz, 0.0, bx, by, bz, o.storage, &o, slab, stream_levels,
+                                              stream);
+  if (sc != GD_OK) return sc;
+  std::unique_ptr<gd_hierarchy> h(hp);
+  void* hx = nullptr;
+  void* hb = nullptr;
+  std::vector<void*> dbufs;
+  struct Cleanup {
+    void*& hx;
+    void*& hb;
+    std::vector<void*>& d;
+    ~Cleanup() {
+      if (hx) (void)hipHostFree(hx);
+      if (hb) (void)hipHostFree(hb);
+      for (void* p : d) (void)hipFree(p);
+    }
+  } cleanup{hx, hb, dbufs};
+  return run_guarded([&]() -> gd_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    Hier& H = *h->H;
+    Streamer& S = *h->sm;
+    const size_t es = dsize(o.storage), ei = dsize(in_t), eo = dsize(out_t);
+    const int64_t pln = nx * ny, px = pitch_of(nx);
+    const int64_t sl = S.lv[0].slab;  // planes per slab of the finest level's passes
+    // windows of the setup and output passes: the input with one halo plane
+    // on each side, the right-hand side and the output (dense), E (level pitch)
+    const size_t bi = (size_t)(sl + 2) * pln * ei, bbz = (size_t)sl * pln * es, be = (size_t)sl * px * ny * es,
+                 bo = (size_t)sl * pln * eo;
+    const int64_t nrb = stream_rhs_blocks(nx, ny);
+    auto dalloc = [&](size_t n) {
+      void* p = nullptr;
+      HIP_TRY(hipMalloc(&p, std::max<size_t>(n, 16)));
+      dbufs.push_back(p);
+      return p;
+    };
+    char* wi = (char*)dalloc(bi);
+    char* wbz = (char*)dalloc(bbz);
+    char* we = (char*)dalloc(be);
+    char* wo = (char*)dalloc(bo);
+    double* part = (double*)dalloc((size_t)nrb * sizeof(double));
+    int64_t* b0 = (int64_t*)dalloc(2 * sizeof(int64_t));
+    {
+      const int64_t t[2] = {0, nrb};
+      HIP_TRY(hipMemcpy(b0, t, sizeof t, hipMemcpyHostToDevice));
+    }
+    // slab grids (launch tables only) for the sum and output passes
+    std::map<int64_t, std::unique_ptr<Hier>> sg;
+    auto slab_grid = [&](int64_t planes) -> Hier& {
+      auto it = sg.find(planes);
+      if (it == sg.end())
+        it = sg.emplace(planes, build_hier({{nx, ny, planes, 0.0, bx, by, bz, 0, nx, pln}}, o.storage, false, st, -1,
+                                           1, 1)).first;
+      return *it->second;
+    };
+    int64_t dev = (int64_t)(H.bytes + S.bytes() + bi + bbz + be + bo + nrb * sizeof(double));
+    if (device_budget > 0 && dev > device_budget)
+      return fail(GD_ERR_NOMEM, who + ": needs " + std::to_string(dev) + " device bytes, budget " +
+                                    std::to_string(device_budget));
+    const size_t host = (size_t)nz * pln * es;
+    HIP_TRY(hipHostMalloc(&hx, host, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&hb, host, hipHostMallocDefault));
+    std::memset(hx, 0, host);  // E starts at zero
+    double acct = 0.0;
+    // ---- pass 1: right-hand side of E and the canonical norm
+    double bn2 = 0.0;
+    for (int64_t z0 = 0; z0 < nz; z0 += sl) {
+      const int64_t z1 = std::min(nz, z0 + sl), a = std::max<int64_t>(0, z0 - 1), e = std::min(nz, z1 + 1);
+      HIP_TRY(hipMemcpyAsync(wi, (const char*)I0 + a * pln * ei, (size_t)(e - a) * pln * ei, hipMemcpyHostToDevice,
+                             st));
+      HIP_TRY(launch_stream_rhs(in_t, o.storage, wi, wbz, (int)nx, (int)ny, (int)nz, (int)a, (int)(z0 - a),
+                                (int)(z1 - a), bx, by, bz, part, st));
+      HIP_TRY(launch_reduce(part, b0, 1, 1, H.dred, st));
+      HIP_TRY(hipMemcpyAsync((char*)hb + z0 * pln * es, wbz, (size_t)(z1 - z0) * pln * es, hipMemcpyDeviceToHost, st));
+      read_dred(H, 1, st);
+      bn2 += H.hpin[0];
+      acct += (double)(z1 - z0) * pln * (ei + es);
+    }
+    const double bnorm = std::sqrt(bn2), den = bnorm > 0.0 ? bnorm : 1.0;
+    // ---- V-cycles until the canonical residual (that of E's system) is small enough
+    Outcome R;
+    R.bnorm = {bnorm};
+    double rr = 0.0, bb = 0.0;
+    int batch = std::min(4, std::max(1, o.max_cycles));
+    double best = INFINITY;
+    int stall = 0;
+    for (;;) {
+      gd_status vs = gd_vcycle_streamed(h.get(), hx, hb, batch, nullptr, stream);
+      if (vs != GD_OK) return vs;
+      R.cycles += batch;
+      streamed_residual(*h, hx, hb, rr, bb, st);
+      const double rel = std::sqrt(rr) / den;
+      R.rel = {rel};
+      if (!std::isfinite(rel)) { R.numeric = true; break; }
+      R.converged = rel <= o.rel_tol;
+      stall = rel < 0.7 * best ? 0 : stall + 1;
+      best = std::min(best, rel);
+      if (R.converged || R.cycles >= o.max_cycles || stall >= 3) break;
+      batch = 1;
+    }
+    // ---- pass 3: the gauge, mean(I1) = mean(I0): the sum of E
+    double esum = 0.0;
+    const size_t hplane = (size_t)pln * es, pb = (size_t)px * es, wb = (size_t)nx * es;
+    for (int64_t z0 = 0; z0 < nz; z0 += sl) {
+      const int64_t z1 = std::min(nz, z0 + sl);
+      Hier& G = slab_grid(z1 - z0);
+      HIP_TRY(hipMemcpy2DAsync(we, pb, (const char*)hx + z0 * hplane, wb, wb, (size_t)ny * (z1 - z0),
+                               hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_sum_shift(in_t, o.storage, 0, G.g_ew(0), nullptr, we, nullptr, G.partials, st));
+      HIP_TRY(launch_reduce(G.partials, G.lv[0].ew.d_b0, 1, 1, G.dred, st));
+      read_dred(G, 1, st);
+      esum += G.hpin[0];
+    }
+    // ---- pass 4: the output I0 + E - mean(E), slab by slab
+    H.hpin[0] = esum / ((double)pln * nz);
+    HIP_TRY(hipMemcpyAsync(H.dscal, H.hpin, sizeof(double), hipMemcpyHostToDevice, st));
+    for (int64_t z0 = 0; z0 < nz; z0 += sl) {
+      const int64_t z1 = std::min(nz, z0 + sl);
+      Hier& G = slab_grid(z1 - z0);
+      HIP_TRY(hipMemcpyAsync(wi, (const char*)I0 + z0 * pln * ei, (size_t)(z1 - z0) * pln * ei, hipMemcpyHostToDevice,
+                             st));
+      HIP_TRY(hipMemcpy2DAsync(we, pb, (const char*)hx + z0 * hplane, wb, wb, (size_t)ny * (z1 - z0),
+                               hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_finalize(in_t, o.storage, out_t, 0, G.g_ew(0), wi, we, nullptr, H.dscal, wo, st));
+      HIP_TRY(hipMemcpyAsync((char*)I1 + z0 * pln * eo, wo, (size_t)(z1 - z0) * pln * eo, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      acct += (double)(z1 - z0) * pln * (ei + 2.0 * es + eo);
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) {
+      fill_report(rep, R, 0, secs, (int)H.lv.size());
+      rep->bytes = acct;  // the setup and output passes' bytes (the V-cycles stream through the host link)
+    }
+    if (R.numeric) return fail(GD_ERR_NUMERIC, who + ": non-finite residual");
+    if (!R.converged) return fail(GD_ERR_NOT_CONVERGED, who + ": tolerance not reached");
     return GD_OK;
   });
 }

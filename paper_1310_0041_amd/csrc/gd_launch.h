@@ -106,6 +106,13 @@ hipError_t launch_load_input(gd_dtype tin, gd_dtype s, const GridDesc& G, const 
 // ipy / ipz of G; in1 of type t1 = tin, F32 or F64, or NULL) into a level array
 hipError_t launch_load_comb(gd_dtype tin, gd_dtype t1, gd_dtype s, const GridDesc& G, const void* in0,
                             const void* in1, double c0, double c1, void* out, hipStream_t st);
+// Streamed anisotropic diffusion: b = -b_z L_z I0 of the planes [k0, k1) of a
+// dense window of the caller's input (window plane 0 = global plane z0 of an
+// nzg-plane stack), written dense; per-block FP64 sums of the canonical
+// right-hand side squared in partials[0 .. stream_rhs_blocks(nx, ny))
+int64_t stream_rhs_blocks(int64_t nx, int64_t ny);
+hipError_t launch_stream_rhs(gd_dtype tin, gd_dtype s, const void* I0, void* b, int nx, int ny, int nzg, int z0,
+                             int k0, int k1, double bx, double by, double bz, double* partials, hipStream_t st);
 // r = b - A x on the finest (7-point) level of a Hybrid hierarchy, with
 // per-block FP64 sums of r^2 in partials[0 .. hyb_residual7_blocks(G))
 int64_t hyb_residual7_blocks(const GridDesc& G);

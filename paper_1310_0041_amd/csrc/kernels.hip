@@ -654,6 +654,42 @@ k_load_comb(GridDesc G, const Tin* __restrict__ in0, const T1* __restrict__ in1,
   }
 }
 
+// Right-hand side of the anisotropic diffusion (Eq. (1)) in correction form
+// for the planes [k0, k1) of a window of the caller's input, dense
+// [planes][ny][nx] with window plane 0 at global plane z0 of an nzg-plane
+// stack: b = -b_z L_z I0 (written dense, plane k0 first), the cross-slice
+// term summed z-1 then z+1 as the in-core pass does; per block the FP64 sum
+// of the canonical right-hand side squared, ((b_x L_x + b_y L_y) I0)^2.  L_a
+// is the Neumann second difference over the whole stack.
+template <typename Tin, typename S>
+__global__ void __launch_bounds__(256)
+k_stream_rhs(const Tin* __restrict__ I0, S* __restrict__ b, int nx, int ny, int nzg, int z0, int k0, int k1,
+             double bx, double by, double bz, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  double s = 0.0;
+  if (i < nx && j < ny) {
+    const int64_t pl = (int64_t)nx * ny;
+    for (int k = k0; k < k1; ++k) {
+      const int64_t v = (int64_t)k * pl + (int64_t)j * nx + i;
+      const double c = ld64(I0 + v);
+      double lin = 0.0;
+      if (i > 0) lin += bx * (c - ld64(I0 + v - 1));
+      if (i + 1 < nx) lin += bx * (c - ld64(I0 + v + 1));
+      if (j > 0) lin += by * (c - ld64(I0 + v - nx));
+      if (j + 1 < ny) lin += by * (c - ld64(I0 + v + nx));
+      s += lin * lin;
+      const int gz = z0 + k;
+      double lz = 0.0;
+      if (gz > 0) lz += bz * (c - ld64(I0 + v - pl));
+      if (gz + 1 < nzg) lz += bz * (c - ld64(I0 + v + pl));
+      Ty<S>::st(b + (int64_t)(k - k0) * pl + (int64_t)j * nx + i, (typename Ty<S>::C)(0.0 - lz));
+    }
+  }
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+}
+
 // r = b - A x on the finest (7-point) level, with the FP64 sum of r^2 per
 // block (partials[block], block = x + gx (y + gy z)), summed in a fixed
 // order.  A thread takes HZ7 z-samples; a full chunk is unrolled so that its
@@ -1034,6 +1070,29 @@ hipError_t launch_load_comb(gd_dtype tin, gd_dtype t1, gd_dtype s, const GridDes
   } else {
     return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
+  return last();
+}
+
+template <typename TI>
+static hipError_t stream_rhs_launch(gd_dtype s, const void* I0, void* b, int nx, int ny, int nzg, int z0, int k0,
+                                    int k1, double bx, double by, double bz, double* partials, hipStream_t st) {
+  const dim3 grid((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4));
+#define L(TT) hipLaunchKernelGGL((k_stream_rhs<TI, TT>), grid, dim3(256), 0, st, (const TI*)I0, (TT*)b, nx, ny, nzg, \
+                                 z0, k0, k1, bx, by, bz, partials)
+  GD_DISPATCH_S(s, L)
+#undef L
+  return hipSuccess;
+}
+
+int64_t stream_rhs_blocks(int64_t nx, int64_t ny) { return ((nx + 63) / 64) * ((ny + 3) / 4); }
+
+hipError_t launch_stream_rhs(gd_dtype tin, gd_dtype s, const void* I0, void* b, int nx, int ny, int nzg, int z0,
+                             int k0, int k1, double bx, double by, double bz, double* partials, hipStream_t st) {
+  hipError_t e = hipSuccess;
+#define L(TI) e = stream_rhs_launch<TI>(s, I0, b, nx, ny, nzg, z0, k0, k1, bx, by, bz, partials, st)
+  GD_DISPATCH_S(tin, L)
+#undef L
   if (e != hipSuccess) return e;
   return last();
 }

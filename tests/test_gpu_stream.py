@@ -166,3 +166,69 @@ def test_automatic_choice_keeps_short_coarse_levels_resident(gd):
     hs2 = gd.StreamedHierarchy((40, 33, 47), 0.0, (1.0, 1.0, 4.0), torch.float32, 8, 8)
     assert hs2.streamed_levels() == 2
     assert hs.device_bytes()[0] < hs2.device_bytes()[0]
+
+
+@pytest.mark.parametrize("shape,slab,dt,storage", [
+    ((70, 80, 96), 16, torch.float32, "f32"),
+    ((41, 33, 57), 8, torch.float16, "f32"),
+    ((30, 24, 40), 64, torch.float64, "f64"),
+])
+def test_smooth_z_streamed_end_to_end(gd, shape, slab, dt, storage):
+    """The anisotropic diffusion of a stack held in host memory, every pass
+    streamed through HBM (right-hand side, V-cycles, residual, gauge,
+    output): the same answer as the in-core gd_smooth_z and the oracle's."""
+    import synth
+
+    say("streamed AD end to end", shape, slab, dt, storage)
+    nz, ny, nx = shape
+    I0 = synth.make_stack(synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100428)).to(dt)
+    beta = (1.0, 1.0, 4.0)
+    kw = dict(storage=gd.F64, rel_tol=1e-10) if storage == "f64" else dict(rel_tol=1e-6, check=False)
+    out, rep = gd.smooth_z_streamed(I0.pin_memory(), beta, out_dtype=torch.float64, slab=slab, **kw)
+    incore, rin = gd.smooth_z(I0.cuda(), beta, out_dtype=torch.float64, **kw)
+    say(f"streamed: status {rep['status']} cycles {rep['cycles']} res {rep['rel_residual']:.3g}; "
+        f"in core: status {rin['status']} cycles {rin['cycles']} res {rin['rel_residual']:.3g}")
+    a0 = I0.double().numpy()
+    ref = osv.ad_dct(a0, beta)
+    x = out.numpy()
+    res = om.relative_residual(x, og_rhs(a0, beta), 0.0, beta)
+    assert abs(x.mean() - a0.mean()) <= 1e-9 * max(1.0, abs(a0.mean()))
+    if storage == "f64":
+        assert rep["status"] == 0 and res <= 1.01e-10
+        assert rel(x, ref) <= 1e-7 and rel(x, incore.cpu().numpy()) <= 1e-8
+    else:
+        # the plain FP32 correction reaches 1e-6 or stops at its rounding floor, as in core
+        assert rep["status"] in (0, gd.ERR_NOT_CONVERGED) and res <= max(1.01e-6, 1.01 * rep["rel_residual"])
+        assert rel(x, ref) <= 1e-5 and rel(x, incore.cpu().numpy()) <= 2e-6
+    assert rep["bytes"] > 0
+
+
+def og_rhs(I0, beta):
+    from oracle import grid as og
+
+    return og.rhs_ad(I0, beta)
+
+
+def test_smooth_z_streamed_within_a_device_budget(gd):
+    """A long stack whose in-core hierarchy needs more device memory than the
+    budget given: the streamed solve stays within it and matches the oracle;
+    a budget below what the streamed solve needs is refused up front."""
+    import synth
+
+    say("streamed AD under a device budget")
+    shape = (1024, 64, 64)
+    nz, ny, nx = shape
+    hc = gd.Hierarchy(shape, 0.0, (1.0, 1.0, 4.0), torch.float32)
+    incore_bytes, _ = hc.device_bytes()
+    hc.close()
+    budget = incore_bytes // 2
+    I0 = synth.make_stack(synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100429)).float().pin_memory()
+    out, rep = gd.smooth_z_streamed(I0, (1.0, 1.0, 4.0), out_dtype=torch.float64, slab=16, device_budget=budget,
+                                    check=False)
+    say(f"in-core hierarchy {incore_bytes} B, budget {budget} B; status {rep['status']}, cycles {rep['cycles']}")
+    assert rep["status"] in (0, gd.ERR_NOT_CONVERGED)
+    a0 = I0.double().numpy()
+    assert rel(out.numpy(), osv.ad_dct(a0, (1.0, 1.0, 4.0))) <= 1e-5
+    with pytest.raises(gd.GDError) as ei:
+        gd.smooth_z_streamed(I0, (1.0, 1.0, 4.0), slab=16, device_budget=1 << 20)
+    assert ei.value.status == gd.ERR_NOMEM
