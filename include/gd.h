@@ -315,6 +315,20 @@ gd_status gd_smooth_z_streamed(const void* I0, gd_dtype in_t, void* I1, gd_dtype
                                const gd_solve_opts* opts, int64_t slab, int stream_levels,
                                int64_t device_budget, gd_solve_report* rep, void* stream);
 
+/* Per-slice screened Poisson, Eq. (2), of a stack held in HOST memory: the
+ * slices are independent, so batches of `slab` consecutive slices are
+ * uploaded, solved in HBM as one batch (gd_screened_poisson_slices, same
+ * options, alpha for every slice) and written back.  I0 (in_t), I1 (i1_t:
+ * in_t, F32 or F64) and I2 (out_t) are dense [nz][ny][nx] host arrays of
+ * the caller.  per_slice (nz reports, or NULL) and rep as
+ * gd_screened_poisson_slices.  device_budget > 0: GD_ERR_NOMEM up front if
+ * the slab buffers and the batch's hierarchy need more device bytes. */
+gd_status gd_screened_poisson_streamed(const void* I0, gd_dtype in_t, const void* I1, gd_dtype i1_t,
+                                       void* I2, gd_dtype out_t, int64_t nx, int64_t ny, int64_t nz,
+                                       double alpha, double beta_x, double beta_y,
+                                       const gd_solve_opts* opts, int64_t slab, int64_t device_budget,
+                                       gd_solve_report* rep, gd_solve_report* per_slice, void* stream);
+
 /* ncycles V-cycles on A x = b with x (in/out) and b (in) in HOST memory, dense
  * [nz][ny][nx] arrays of the storage dtype, owned by the caller.  Memory
  * from hipHostMalloc lets copies overlap the kernels; pageable memory works

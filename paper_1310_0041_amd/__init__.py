@@ -107,6 +107,9 @@ _SIGS = {
     "gd_hierarchy_create_streamed": (_i, [ctypes.POINTER(_vp), _i64, _i64, _i64, _d, _d, _d, _d, _i,
                                           ctypes.POINTER(SolveOpts), _i64, _i, _vp]),
     "gd_vcycle_streamed": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
+    "gd_screened_poisson_streamed": (_i, [_vp, _i, _vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d,
+                                          ctypes.POINTER(SolveOpts), _i64, _i64, ctypes.POINTER(Report),
+                                          ctypes.POINTER(Report), _vp]),
     "gd_smooth_z_streamed": (_i, [_vp, _i, _vp, _i, _i64, _i64, _i64, _d, _d, _d, ctypes.POINTER(SolveOpts), _i64,
                                   _i, _i64, ctypes.POINTER(Report), _vp]),
     "gd_hierarchy_device_bytes": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
@@ -522,6 +525,30 @@ def smooth_z_streamed(I0, beta=(1.0, 1.0, 4.0), out_dtype=None, slab=32, levels=
     if check:
         _check(st)
     return out, dict(rep.as_dict(), status=st)
+
+
+def screened_poisson_streamed(I0, I1, alpha=0.01, beta_xy=(1.0, 1.0), out_dtype=None, slab=16, device_budget=0,
+                              out=None, opts=None, check=True, **kw):
+    """Eq. (2) for every slice of a [nz][ny][nx] stack in HOST memory, in
+    batches of `slab` slices through HBM.  Returns (I2 on the host, report,
+    per-slice reports)."""
+    lib = load()
+    torch = _torch()
+    nz, ny, nx = I0.shape
+    if tuple(I1.shape) != tuple(I0.shape):
+        raise ValueError("I0 and I1 must share the shape")
+    if out is None:
+        out = torch.empty(I0.shape, dtype=out_dtype or I0.dtype, pin_memory=I0.is_pinned())
+    o = opts or default_opts(**kw)
+    rep = Report()
+    per = (Report * nz)()
+    st = lib.gd_screened_poisson_streamed(_host_ptr(I0), gd_dtype(I0.dtype), _host_ptr(I1), gd_dtype(I1.dtype),
+                                          _host_ptr(out), gd_dtype(out.dtype), nx, ny, nz, float(alpha),
+                                          float(beta_xy[0]), float(beta_xy[1]), ctypes.byref(o), int(slab),
+                                          int(device_budget), ctypes.byref(rep), per, _stream())
+    if check:
+        _check(st)
+    return out, dict(rep.as_dict(), status=st), [p.as_dict() for p in per]
 
 
 class Net:

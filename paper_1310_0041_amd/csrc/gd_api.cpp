@@ -2446,6 +2446,88 @@ gd_status gd_smooth_z_streamed(const void* I0, gd_dtype in_t, void* I1, gd_dtype
   });
 }
 
+// Per-slice screened Poisson (Eq. (2)) of a stack held in host memory: the
+// slices are independent, so batches of `slab` consecutive slices are
+// uploaded, solved as one batch in HBM and written back.
+gd_status gd_screened_poisson_streamed(const void* I0, gd_dtype in_t, const void* I1, gd_dtype i1_t, void* I2,
+                                       gd_dtype out_t, int64_t nx, int64_t ny, int64_t nz, double alpha, double bx,
+                                       double by, const gd_solve_opts* opts, int64_t slab, int64_t device_budget,
+                                       gd_solve_report* rep, gd_solve_report* per_slice, void* stream) {
+  const std::string who = "gd_screened_poisson_streamed";
+  if (!I0 || !I1 || !I2) return fail(GD_ERR_INVALID, who + ": null pointer");
+  if (I2 == I0 || I2 == I1) return fail(GD_ERR_INVALID, who + ": output aliases input");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX || nx * ny > MAX_PLANE)
+    return fail(GD_ERR_INVALID, who + ": bad size");
+  if (!valid_dtype(in_t) || !valid_dtype(i1_t) || !valid_dtype(out_t) ||
+      (i1_t != in_t && i1_t != GD_F32 && i1_t != GD_F64))
+    return fail(GD_ERR_INVALID, who + ": bad dtype (I1: I0's, F32 or F64)");
+  if (!(alpha > 0.0) || !std::isfinite(alpha) || slab <= 0 || device_budget < 0)
+    return fail(GD_ERR_INVALID, who + ": need alpha > 0, slab > 0 and a budget >= 0");
+  gd_solve_opts o;
+  gd_default_opts(&o);
+  if (opts) o = *opts;
+  gd_status sc = check_opts(o);
+  if (sc != GD_OK) return sc;
+  hipStream_t st = (hipStream_t)stream;
+  void* d[3] = {nullptr, nullptr, nullptr};
+  struct Free {
+    void** d;
+    ~Free() {
+      for (int i = 0; i < 3; ++i)
+        if (d[i]) (void)hipFree(d[i]);
+    }
+  } fr{d};
+  return run_guarded([&]() -> gd_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t sl = std::min(slab, nz), pln = nx * ny;
+    const size_t ei = dsize(in_t), e1 = dsize(i1_t), eo = dsize(out_t);
+    std::vector<GridSpec> specs;
+    for (int64_t i = 0; i < sl; ++i) {
+      GridSpec g{nx, 1, ny, alpha, bx, 0.0, by, i * pln, nx, nx};
+      g.zin = 1;
+      specs.push_back(g);
+    }
+    const size_t hier = o.discretization != 0 ? 0
+                        : build_hier(specs, o.storage, o.fp64_refine != 0, st, -1, 0, 0, nullptr, 0, true)->bytes;
+    const size_t need = hier + (size_t)sl * pln * (ei + e1 + eo);
+    if (device_budget > 0 && (int64_t)need > device_budget)
+      return fail(GD_ERR_NOMEM, who + ": needs " + std::to_string(need) + " device bytes, budget " +
+                                    std::to_string(device_budget));
+    HIP_TRY(hipMalloc(&d[0], (size_t)sl * pln * ei));
+    HIP_TRY(hipMalloc(&d[1], (size_t)sl * pln * e1));
+    HIP_TRY(hipMalloc(&d[2], (size_t)sl * pln * eo));
+    std::vector<gd_slice_desc> descs(sl);
+    for (int64_t i = 0; i < sl; ++i) descs[i] = gd_slice_desc{i * pln, (int32_t)nx, (int32_t)ny, (int32_t)nx, (float)alpha};
+    std::vector<gd_solve_report> per(sl);
+    gd_solve_report sum{};
+    bool numeric = false, converged = true;
+    for (int64_t z0 = 0; z0 < nz; z0 += sl) {
+      const int64_t n = std::min(sl, nz - z0);
+      HIP_TRY(hipMemcpyAsync(d[0], (const char*)I0 + z0 * pln * ei, (size_t)n * pln * ei, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(d[1], (const char*)I1 + z0 * pln * e1, (size_t)n * pln * e1, hipMemcpyHostToDevice, st));
+      gd_solve_report r{};
+      const gd_status s2 = gd_screened_poisson_slices(d[0], in_t, d[1], i1_t, d[2], out_t, descs.data(), n, bx, by,
+                                                      &o, &r, per.data(), stream);
+      if (s2 == GD_ERR_NUMERIC) numeric = true;
+      else if (s2 == GD_ERR_NOT_CONVERGED) converged = false;
+      else if (s2 != GD_OK) return s2;
+      HIP_TRY(hipMemcpyAsync((char*)I2 + z0 * pln * eo, d[2], (size_t)n * pln * eo, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (per_slice) std::memcpy(per_slice + z0, per.data(), (size_t)n * sizeof(gd_solve_report));
+      sum.cycles = std::max(sum.cycles, r.cycles);
+      sum.refine_steps = std::max(sum.refine_steps, r.refine_steps);
+      sum.rel_residual = std::max(sum.rel_residual, r.rel_residual);
+      sum.levels = std::max(sum.levels, r.levels);
+      sum.bytes += r.bytes;
+    }
+    sum.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = sum;
+    if (numeric) return fail(GD_ERR_NUMERIC, who + ": non-finite residual");
+    if (!converged) return fail(GD_ERR_NOT_CONVERGED, who + ": tolerance not reached");
+    return GD_OK;
+  });
+}
+
 gd_status gd_hierarchy_device_bytes(const gd_hierarchy* h, int64_t* bytes, int64_t* window_planes) {
   if (!h || !bytes) return fail(GD_ERR_INVALID, "gd_hierarchy_device_bytes: null pointer");
   size_t b = h->H->bytes;

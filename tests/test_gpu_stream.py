@@ -232,3 +232,25 @@ def test_smooth_z_streamed_within_a_device_budget(gd):
     with pytest.raises(gd.GDError) as ei:
         gd.smooth_z_streamed(I0, (1.0, 1.0, 4.0), slab=16, device_budget=1 << 20)
     assert ei.value.status == gd.ERR_NOMEM
+
+
+@pytest.mark.parametrize("slab,refine", [(5, 0), (64, 0), (7, 1)])
+def test_screened_poisson_streamed(gd, slab, refine):
+    """Eq. (2) of a stack held in host memory, in batches of slices through
+    HBM: every slice against the DCT oracle and the in-core solve."""
+    import synth
+
+    say("streamed SP", slab, refine)
+    shape = (23, 48, 72)
+    nz, ny, nx = shape
+    I0 = synth.make_stack(synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100430))
+    I1 = osv.ad_dct(I0.numpy(), (1.0, 1.0, 4.0))
+    kw = dict(storage=gd.F16, fp64_refine=1, rel_tol=1e-7) if refine else dict()
+    I0t = (I0.half() if refine else I0.float()).pin_memory()
+    I1t = torch.from_numpy(I1).float().pin_memory()
+    out, rep, per = gd.screened_poisson_streamed(I0t, I1t, 0.01, out_dtype=torch.float64, slab=slab, **kw)
+    assert rep["status"] == 0 and max(p["rel_residual"] for p in per) <= kw.get("rel_tol", 1e-6)
+    ref = osv.sp_dct(I0t.double().numpy(), I1t.double().numpy(), 0.01)
+    assert rel(out.numpy(), ref) <= (1e-6 if refine else 1e-5)
+    incore, _, _ = gd.screened_poisson_stack(I0t.cuda(), I1t.cuda(), 0.01, out_dtype=torch.float64, **kw)
+    assert rel(out.numpy(), incore.cpu().numpy()) <= (1e-6 if refine else 2e-6)
