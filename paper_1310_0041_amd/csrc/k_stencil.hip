@@ -78,6 +78,10 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   const int lx = 1 + 2 * pxl, ly = YO + tyl;
   const int64_t own = (int64_t)gy * px + gx, ownu = (int64_t)gy * G.ipy + gx;
   const bool up = !ROW && gy > 0, dn = !ROW && gy + 1 < ny, o0 = gx > 0, o1 = gx + 2 < nx;
+  // x and in-plane y weights of the pair's cells (0 where the neighbour is
+  // outside the grid)
+  const double wlA = o0 ? wx : 0.0, wrA = vB ? wx : 0.0, wlB = wx, wrB = o1 ? wx : 0.0;
+  const double wu = up ? wy : 0.0, wd = dn ? wy : 0.0;
 
   int hoff[NHR];
   int64_t hg[NHR], hu[NHR];
@@ -205,57 +209,66 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     __syncthreads();
     const double v1a = jca, v1b = jcb;
     const double* P = &X[k % 3][0][0];
-    const bool zm = k > 0, zp = k < nz - 1;
-    double ra = 0.0, rb = 0.0;
-    // in-plane and z second differences of F; I0's z term for the stack
-    auto lap = [&](double c, double l, bool hl, double rr, bool hr, double u_, double d_, double zm_, double zp_) {
+    // every term is computed: a neighbour outside the grid has weight 0 and
+    // a finite (zero) value in LDS, so no branch or mask is needed until the
+    // norm and the stores
+    const double wzm = k > 0 ? wz : 0.0, wzp = k < nz - 1 ? wz : 0.0;
+    // in-plane and z second differences of F (left, right, up, down, z-1,
+    // z+1); I0's z term for the stack
+    auto lap = [&](double c, double wl, double l, double wr, double rr, double u_, double d_, double zm_,
+                   double zp_) {
       double s2 = 0.0;
-      if (hl) s2 += wx * (c - l);
-      if (hr) s2 += wx * (c - rr);
-      if (up) s2 += wy * (c - u_);
-      if (dn) s2 += wy * (c - d_);
-      if (zm) s2 += wz * (c - zm_);
-      if (zp) s2 += wz * (c - zp_);
+      s2 += wl * (c - l);
+      s2 += wr * (c - rr);
+      if (!ROW) {
+        s2 += wu * (c - u_);
+        s2 += wd * (c - d_);
+      }
+      s2 += wzm * (c - zm_);
+      s2 += wzp * (c - zp_);
       return s2;
     };
-    if (vA) {
+    const int lo_ = ly * HX + lx;
+    const double uA = ROW ? 0.0 : P[lo_ - HX], uB = ROW ? 0.0 : P[lo_ - HX + 1];
+    const double dA = ROW ? 0.0 : P[lo_ + HX], dB = ROW ? 0.0 : P[lo_ + HX + 1];
+    const double lA = P[lo_ - 1], rB = P[lo_ + 2];
+    double ra, rb;
+    {
       const double c = fca;
-      const double lf = lap(c, o0 ? P[ly * HX + lx - 1] : 0.0, o0, fcb, vB, up ? P[(ly - 1) * HX + lx] : 0.0,
-                            dn ? P[(ly + 1) * HX + lx] : 0.0, fma_, fpa);
+      const double lf = lap(c, wlA, lA, wrA, fcb, uA, dA, fma_, fpa);
       double lzI = 0.0;  // w_z L_z I0 (stack only)
       if (cross) {
         const double i0 = KIND == 0 ? fca : ica, im = KIND == 0 ? fma_ : ima, ip = KIND == 0 ? fpa : ipa;
-        if (zm) lzI += wz * (i0 - im);
-        if (zp) lzI += wz * (i0 - ip);
+        lzI += wzm * (i0 - im);
+        lzI += wzp * (i0 - ip);
       }
       if (KIND == 0) {
         const double lin = lf - (cross ? lzI : 0.0);  // canonical part of L I0
         const double bcan = alpha * v1a + lin;
-        nrm += bcan * bcan;
+        nrm += vA ? bcan * bcan : 0.0;
         ra = alpha * (v1a - c) - lzI;
       } else {
         ra = alpha * (v1a - ica - c) - lf - lzI;
-        nrm += ra * ra;
+        nrm += vA ? ra * ra : 0.0;
       }
     }
-    if (vB) {
+    {
       const double c = fcb;
-      const double lf = lap(c, fca, true, o1 ? P[ly * HX + lx + 2] : 0.0, o1, up ? P[(ly - 1) * HX + lx + 1] : 0.0,
-                            dn ? P[(ly + 1) * HX + lx + 1] : 0.0, fmb, fpb);
+      const double lf = lap(c, wlB, fca, wrB, rB, uB, dB, fmb, fpb);
       double lzI = 0.0;
       if (cross) {
         const double i0 = KIND == 0 ? fcb : icb, im = KIND == 0 ? fmb : imb, ip = KIND == 0 ? fpb : ipb;
-        if (zm) lzI += wz * (i0 - im);
-        if (zp) lzI += wz * (i0 - ip);
+        lzI += wzm * (i0 - im);
+        lzI += wzp * (i0 - ip);
       }
       if (KIND == 0) {
         const double lin = lf - (cross ? lzI : 0.0);
         const double bcan = alpha * v1b + lin;
-        nrm += bcan * bcan;
+        nrm += vB ? bcan * bcan : 0.0;
         rb = alpha * (v1b - c) - lzI;
       } else {
         rb = alpha * (v1b - icb - c) - lf - lzI;
-        nrm += rb * rb;
+        nrm += vB ? rb * rb : 0.0;
       }
     }
     if (vA) {
