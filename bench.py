@@ -642,7 +642,8 @@ def run_stack_leg(a, gd, synth, torch, spec, storage, refine, steps, warmup):
     avg_ms = ms / max(launches, 1)
     others = {}
     for name, v in (("stack_fused_prolong", gd.SWEEP_STACK_PROLONG), ("slice", gd.SWEEP_SLICE),
-                    ("slice_fused_prolong", gd.SWEEP_SLICE_PROLONG)):
+                    ("slice_fused_prolong", gd.SWEEP_SLICE_PROLONG), ("stack_from_zero", gd.SWEEP_STACK_ZERO),
+                    ("slice_from_zero", gd.SWEEP_SLICE_ZERO)):
         m2, n2, b2 = gd.kernel_time(v)
         if n2:
             others[name] = {"launches": n2, "avg_launch_ms": m2 / n2, "GB/s": b2 / (m2 / n2 * 1e-3) / 1e9}

@@ -427,8 +427,10 @@ gd_status gd_prolong_add(const void* e_coarse, void* x, gd_dtype s,
  * launches of one variant since the last reset, recorded by solves run with
  * opts->timing = 1.  variant: 0 stack grid, 1 stack grid with the coarse
  * correction added on load, 2 slice (one-line) grids, 3 slice grids with the
- * correction.  bytes_per_launch: algorithmic bytes of one launch (read x and
- * b, write x: 3 * storage bytes per voxel of the finest level). */
+ * correction, 4 stack grid and 5 slice grids starting from a zero iterate
+ * (the first sweep of a refinement step's V-cycle, which does not read x).
+ * bytes_per_launch: algorithmic bytes of one launch (read x and b, write x:
+ * 3 * storage bytes per voxel of the finest level; 2 * for variants 4, 5). */
 gd_status gd_get_kernel_time(int variant, double* total_ms, int64_t* launches, double* bytes_per_launch);
 void gd_reset_kernel_time(void);
 

@@ -666,7 +666,7 @@ def prolong_add(e_coarse, x, c, mode=0):
     return x
 
 
-SWEEP_STACK, SWEEP_STACK_PROLONG, SWEEP_SLICE, SWEEP_SLICE_PROLONG = 0, 1, 2, 3
+SWEEP_STACK, SWEEP_STACK_PROLONG, SWEEP_SLICE, SWEEP_SLICE_PROLONG, SWEEP_STACK_ZERO, SWEEP_SLICE_ZERO = 0, 1, 2, 3, 4, 5
 
 
 def kernel_time(variant=SWEEP_STACK):

@@ -65,11 +65,15 @@ static bool valid_dtype(int t) { return t >= GD_F64 && t <= GD_BF16; }
 
 // ------------------------------------------------------------- timing
 
+// finest-level relaxation launches by kind: 0 stack grid, 1 stack with the
+// correction added on load, 2 slices, 3 slices with the correction, 4 stack
+// starting from zero, 5 slices starting from zero
+constexpr int kTimerKinds = 6;
 struct KernelTimer {
   std::mutex mu;
-  double total_ms[4] = {0, 0, 0, 0};
-  int64_t launches[4] = {0, 0, 0, 0};
-  double bytes[4] = {0, 0, 0, 0};
+  double total_ms[kTimerKinds] = {};
+  int64_t launches[kTimerKinds] = {};
+  double bytes[kTimerKinds] = {};
 };
 static KernelTimer g_timer;
 
@@ -901,9 +905,12 @@ struct Cycler {
   }
 
   double P() const { return (double)dsize(H.s); }
+  bool x0_zero = false;  // level 0's x is zero before its next sweep (which then does not read it)
   void sweep(int l, const void* ec) {
     Level& L = H.lv[l];
-    H.count(l, 3.0 * P());  // read x and b, write x
+    const bool xz = l == 0 && x0_zero;
+    if (l == 0) x0_zero = false;
+    H.count(l, (xz ? 2.0 : 3.0) * P());  // read x and b, write x
     if (ec) H.count(l + 1, P());
     if (hyb && table_level(l)) {  // 27-point level: 8-colour Gauss-Seidel in place
       for (int c = 0; c < 8; ++c) HIP_TRY(launch_hyb_gs8(H.s, L.h[0], (*T)[l], c, L.x, L.b, st));
@@ -919,11 +926,11 @@ struct Cycler {
       }
       HIP_TRY(hipEventRecord(ev[ev_used].first, st));
       if (ev_kind.size() < ev.size()) ev_kind.resize(ev.size());
-      ev_kind[ev_used] = (L.row ? 2 : 0) + (ec ? 1 : 0);
+      ev_kind[ev_used] = xz ? 4 + (L.row ? 1 : 0) : (L.row ? 2 : 0) + (ec ? 1 : 0);
     }
     Geom g = H.g_sw(l);
     g.quad = quad;
-    HIP_TRY(launch_rb_sweep(H.s, g, L.x, L.xt, L.b, ec, pmode, st));
+    HIP_TRY(launch_rb_sweep(H.s, g, L.x, L.xt, L.b, ec, pmode, st, xz));
     if (t) HIP_TRY(hipEventRecord(ev[ev_used++].second, st));
     std::swap(L.x, L.xt);
   }
@@ -1003,8 +1010,8 @@ struct Cycler {
   // collect HIP-event times of finest-level sweeps (after a stream sync)
   void harvest() {
     if (!timing || ev_used == 0) return;
-    double tot[4] = {0, 0, 0, 0};
-    int64_t cnt[4] = {0, 0, 0, 0};
+    double tot[kTimerKinds] = {};
+    int64_t cnt[kTimerKinds] = {};
     for (size_t i = 0; i < ev_used; ++i) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ev[i].first, ev[i].second));
@@ -1014,11 +1021,11 @@ struct Cycler {
     double cells = 0.0;
     for (int64_t c : H.cells) cells += (double)c;
     std::lock_guard<std::mutex> lk(g_timer.mu);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kTimerKinds; ++k) {
       if (!cnt[k]) continue;
       g_timer.total_ms[k] += tot[k];
       g_timer.launches[k] += cnt[k];
-      g_timer.bytes[k] = 3.0 * (double)dsize(H.s) * cells;
+      g_timer.bytes[k] = (k >= 4 ? 2.0 : 3.0) * (double)dsize(H.s) * cells;
     }
     ev_used = 0;
   }
@@ -1258,6 +1265,9 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
     return q > 0.0 ? q : 1.0;
   };
   bool first = true;
+  Geom g0sw = H.g_sw(0);
+  g0sw.quad = o.sweep_quad != 0;
+  const bool zstart = o.pre_smooth > 0 && o.discretization == 0 && sweep_starts_from_zero_ok(H.s, g0sw);
   for (;;) {
     bool bad = false;
     R.converged = all_below(r, R.bnorm, o.rel_tol, bad);
@@ -1274,13 +1284,24 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
       (void)canon_residual(H, P, 1, H.lv[0].b, st);
       first = false;
     }
-    H.count(0, (double)es);
-    HIP_TRY(hipMemsetAsync(H.lv[0].x, 0, H.lv[0].total * es, st));
+    // the V-cycles start from zero: the first level-0 sweep skips reading x
+    // where its form allows (otherwise x is cleared)
+    if (!zstart) {
+      H.count(0, (double)es);
+      HIP_TRY(hipMemsetAsync(H.lv[0].x, 0, H.lv[0].total * es, st));
+    }
     for (int c = 0; c < o.inner_cycles; ++c) {
-      if (graphs_on(o))
-        CycleGraphs(H, graph_key("full", o)).run(st, [&](hipStream_t cs) { Cycler(H, cs, o).full(0); });
-      else
+      const bool z = zstart && c == 0;
+      if (graphs_on(o)) {
+        CycleGraphs(H, graph_key(z ? "full-zero" : "full", o)).run(st, [&](hipStream_t cs) {
+          Cycler c2(H, cs, o);
+          c2.x0_zero = z;
+          c2.full(0);
+        });
+      } else {
+        cy.x0_zero = z;
         cy.full(0);
+      }
       R.cycles++;
     }
     // x64' = x64 + scale e; r = b - A x64'; L0.b = r / rms(previous r)
@@ -2817,7 +2838,7 @@ gd_status gd_prolong_add(const void* ec, void* x, gd_dtype s, int64_t nx, int64_
 }
 
 gd_status gd_get_kernel_time(int variant, double* total_ms, int64_t* launches, double* bytes) {
-  if (variant < 0 || variant > 3) return fail(GD_ERR_INVALID, "gd_get_kernel_time: variant must be 0..3");
+  if (variant < 0 || variant >= kTimerKinds) return fail(GD_ERR_INVALID, "gd_get_kernel_time: variant must be 0..5");
   std::lock_guard<std::mutex> lk(g_timer.mu);
   if (total_ms) *total_ms = g_timer.total_ms[variant];
   if (launches) *launches = g_timer.launches[variant];
@@ -2827,7 +2848,7 @@ gd_status gd_get_kernel_time(int variant, double* total_ms, int64_t* launches, d
 
 void gd_reset_kernel_time(void) {
   std::lock_guard<std::mutex> lk(g_timer.mu);
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kTimerKinds; ++k) {
     g_timer.total_ms[k] = 0.0;
     g_timer.launches[k] = 0;
   }

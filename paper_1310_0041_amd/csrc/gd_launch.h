@@ -37,8 +37,11 @@ struct Geom {
                      // the relaxation may use its quad form
 };
 
+// xzero: x_in is all zero (not read; the quad form only, see
+// sweep_starts_from_zero_ok)
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
-                           const void* e_coarse, int prolong_mode, hipStream_t st);
+                           const void* e_coarse, int prolong_mode, hipStream_t st, bool xzero = false);
+bool sweep_starts_from_zero_ok(gd_dtype s, const Geom& g);
 // Residual + restriction (tiles as the relaxation, zlen even); per-block
 // sum r^2 into partials when non-NULL, coarse x zeroed when non-NULL.
 hipError_t launch_restrict_z(gd_dtype s, const Geom& g, const void* x, const void* b, void* b_coarse,

@@ -502,7 +502,9 @@ template <typename S> __device__ __forceinline__ void st4(S* p, float a, float b
   }
 }
 
-template <typename S, int TX, int TY>
+// ZX: the input iterate is zero (the first sweep of a V-cycle started from
+// zero): x is not read, the sweep starts from zeros.
+template <typename S, int TX, int TY, bool ZX>
 __global__ void __launch_bounds__(TX * TY / 4)
 k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
             const S* __restrict__ xin, S* __restrict__ xout, const S* __restrict__ bin, int order) {
@@ -641,10 +643,15 @@ k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
   // ever enters with a zero z-weight, cells outside the grid are masked to 0
   auto plane_ptr = [&](const S* base, int q) { return base + (int64_t)min(max(q, 0), nz - 1) * pl; };
   auto fetch_x = [&](int q, XSet& o) {
-    const S* P = plane_ptr(xg, q);
-    ld_raw4(P + (v0 ? own : 0), o.p);
+    if constexpr (ZX) {
+      __builtin_memset(&o, 0, sizeof o);
+      (void)q;
+    } else {
+      const S* P = plane_ptr(xg, q);
+      ld_raw4(P + (v0 ? own : 0), o.p);
 #pragma unroll
-    for (int k = 0; k < NHQR; ++k) ld_raw4(P + hg[k], o.h[k]);
+      for (int k = 0; k < NHQR; ++k) ld_raw4(P + hg[k], o.h[k]);
+    }
   };
   auto xq = [&](const Raw4<S>& r, int i, bool v) -> C { return v ? raw4_at(r, i) : (C)0; };
   auto stash = [&](int q, const XSet& o) {
@@ -840,10 +847,10 @@ static bool quad_on() {
   return v;
 }
 
-template <typename T>
+template <typename T, bool ZX>
 static void sweep_launch4(const Geom& g, const void* xin, void* xout, const void* b, hipStream_t st) {
-#define SWEEP4(TX, TY)                                                                                        \
-  hipLaunchKernelGGL((k_rb_sweep4<T, TX, TY>), dim3((unsigned)g.nblocks), dim3(TX * TY / 4), 0, st, g.grids, \
+#define SWEEP4(TX, TY)                                                                                            \
+  hipLaunchKernelGGL((k_rb_sweep4<T, TX, TY, ZX>), dim3((unsigned)g.nblocks), dim3(TX * TY / 4), 0, st, g.grids, \
                      g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, g.order)
   if (g.row) {
     SWEEP4(SWR_TX, 1);
@@ -858,13 +865,22 @@ static void sweep_launch4(const Geom& g, const void* xin, void* xout, const void
 #undef SWEEP4
 }
 
+static bool quad_form(size_t es, const Geom& g, const void* ec) {
+  // the row form (slices) of FP32 measured no faster in quads: pairs there
+  return es <= 4 && !ec && g.quad && quad_on() && (es == 2 || !g.row);
+}
+
+bool sweep_starts_from_zero_ok(gd_dtype s, const Geom& g) {
+  return s != GD_F64 && quad_form(s == GD_F32 ? 4 : 2, g, nullptr);
+}
+
 template <typename T>
 static void sweep_launch(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
-                         hipStream_t st) {
-  // the row form (slices) of FP32 measured no faster in quads: pairs there
+                         bool xzero, hipStream_t st) {
   if constexpr (sizeof(T) <= 4) {
-    if (!ec && g.quad && quad_on() && (sizeof(T) == 2 || !g.row)) {
-      sweep_launch4<T>(g, xin, xout, b, st);
+    if (quad_form(sizeof(T), g, ec)) {
+      if (xzero) sweep_launch4<T, true>(g, xin, xout, b, st);
+      else sweep_launch4<T, false>(g, xin, xout, b, st);
       return;
     }
   }
@@ -875,9 +891,10 @@ static void sweep_launch(const Geom& g, const void* xin, void* xout, const void*
 }
 
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
-                           const void* ec, int pmode, hipStream_t st) {
+                           const void* ec, int pmode, hipStream_t st, bool xzero) {
   if (g.nblocks == 0) return hipSuccess;
-#define L(T) sweep_launch<T>(g, xin, xout, b, ec, pmode, st)
+  if (xzero && !sweep_starts_from_zero_ok(s, g)) return hipErrorInvalidValue;
+#define L(T) sweep_launch<T>(g, xin, xout, b, ec, pmode, xzero, st)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();
