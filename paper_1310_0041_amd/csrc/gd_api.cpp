@@ -1113,14 +1113,20 @@ struct Outcome {
 // bytes per cell of reading the caller's inputs (I0, and I1 when given)
 static double in_bytes(const Problem& P) { return (double)dsize(P.tin) + (P.I1 ? (double)dsize(P.t1) : 0.0); }
 
+// (one pass; r0, when given, receives the norm of the correction-form
+// right-hand side, which is the canonical residual of x = I0)
 static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero, std::vector<double>& bn,
-                            hipStream_t st) {
+                            hipStream_t st, std::vector<double>* r0 = nullptr) {
   H.count(0, in_bytes(P) + (b_out ? dsize(H.s) : 0) + (x_zero ? dsize(H.s) : 0));
   HIP_TRY(launch_rhs_corr(P.tin, P.t1, H.s, H.g_rz(0), P.I0, P.I1, b_out, x_zero, H.partials, st));
-  HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, H.ngrids, 1, H.dred, st));
-  read_dred(H, 1, st);
+  HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, H.ngrids, 2, H.dred, st));
+  read_dred(H, 2, st);
   bn.resize(H.ngrids);
-  for (int g = 0; g < H.ngrids; ++g) bn[g] = std::sqrt(H.hpin[g]);
+  for (int g = 0; g < H.ngrids; ++g) bn[g] = std::sqrt(H.hpin[2 * g]);
+  if (r0) {
+    r0->resize(H.ngrids);
+    for (int g = 0; g < H.ngrids; ++g) (*r0)[g] = std::sqrt(H.hpin[2 * g + 1]);
+  }
 }
 
 static std::vector<double> canon_residual(Hier& H, const Problem& P, int mode, void* rout, hipStream_t st) {
@@ -1243,28 +1249,44 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
 }
 
 // Mixed path: FP64 iterate x64 (starting at I0), V-cycles in the storage
-// type on the residual scaled to unit RMS.  One fused pass per refinement
-// step applies the update x64 + s e (into the second FP64 buffer), computes
-// the FP64 canonical residual of the result and writes it, scaled by the
-// RMS of the residual before it (so that it is of order one), as the next
-// right-hand side.
+// type on the residual scaled to unit RMS.  The right-hand-side pass writes
+// the correction-form b, which is the residual of x64 = I0, and its norm;
+// in FP16 storage it is scaled by a power of two (exact) when its RMS is far
+// from one.  One fused pass per refinement step applies the update x64 + s e
+// (into the second FP64 buffer; the first update reads I0 in place of
+// x64), computes the FP64 canonical residual of the result and writes it,
+// scaled by the RMS of the residual before it (so that it is of order one),
+// as the next right-hand side.
 static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
   prep(H, o);
   Outcome R;
   const double a0 = H.acct;
-  canonical_norms(H, P, nullptr, nullptr, R.bnorm, st);
-  H.count(0, dsize(P.tin) + 8.0);
-  HIP_TRY(launch_refine_init(P.tin, H.g_ew(0), P.I0, H.x64, st));
+  std::vector<double> r;
+  canonical_norms(H, P, H.lv[0].b, nullptr, R.bnorm, st, &r);
   Cycler cy(H, st, o);
   const size_t es = dsize(H.s);
   const int n = H.ngrids;
-  std::vector<double> r = canon_residual(H, P, 1, nullptr, st);
-  std::vector<double> scale(n, 1.0);  // scale of the right-hand side in L0.b
   auto rms = [&](int g, const std::vector<double>& v) {
     const double q = v[g] / std::sqrt((double)H.cells[g]);
     return q > 0.0 ? q : 1.0;
   };
-  bool first = true;
+  std::vector<double> scale(n, 1.0);  // scale of the right-hand side in L0.b
+  if (H.s == GD_F16) {
+    bool any = false;
+    for (int g = 0; g < n; ++g) {
+      const double e = std::round(std::log2(rms(g, r)));
+      if (e < -2.0 || e > 4.0) {
+        scale[g] = std::ldexp(1.0, (int)e);
+        any = true;
+      }
+      H.hpin[3 * n + g] = 1.0 / scale[g];  // a slot the steps below leave alone while the copy is pending
+    }
+    if (any) {
+      HIP_TRY(hipMemcpyAsync(H.dscal + 3 * n, H.hpin + 3 * n, n * sizeof(double), hipMemcpyHostToDevice, st));
+      H.count(0, 2.0 * es);
+      HIP_TRY(launch_scale_level(H.s, H.g_ew(0), H.lv[0].b, H.dscal + 3 * n, st));
+    }
+  }
   Geom g0sw = H.g_sw(0);
   g0sw.quad = o.sweep_quad != 0;
   const bool zstart = o.pre_smooth > 0 && o.discretization == 0 && sweep_starts_from_zero_ok(H.s, g0sw);
@@ -1275,15 +1297,6 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
     for (int g = 0; g < n; ++g) R.rel[g] = r[g] / denom(R.bnorm[g]);
     if (bad) { R.numeric = true; break; }
     if (R.converged || R.steps >= o.max_cycles) break;
-    if (first) {  // scaled copy of the initial residual
-      for (int g = 0; g < n; ++g) {
-        scale[g] = rms(g, r);
-        H.hpin[n + g] = 1.0 / scale[g];
-      }
-      HIP_TRY(hipMemcpyAsync(H.dscal + n, H.hpin + n, n * sizeof(double), hipMemcpyHostToDevice, st));
-      (void)canon_residual(H, P, 1, H.lv[0].b, st);
-      first = false;
-    }
     // the V-cycles start from zero: the first level-0 sweep skips reading x
     // where its form allows (otherwise x is cleared)
     if (!zstart) {
@@ -1304,21 +1317,27 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
       }
       R.cycles++;
     }
-    // x64' = x64 + scale e; r = b - A x64'; L0.b = r / rms(previous r)
+    // x64' = x64 + scale e (x64 = I0 before the first update); r = b - A x64';
+    // L0.b = r / rms(previous r)
     for (int g = 0; g < n; ++g) {
       H.hpin[g] = scale[g];
       scale[g] = rms(g, r);
       H.hpin[n + g] = 1.0 / scale[g];
     }
     HIP_TRY(hipMemcpyAsync(H.dscal, H.hpin, 2 * n * sizeof(double), hipMemcpyHostToDevice, st));
-    H.count(0, in_bytes(P) + 8.0 + es + 8.0 + es);  // read x64, e; write x64', scaled r
-    HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, 2, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, H.lv[0].b, H.dscal + n,
-                                  H.partials, st, H.x64b, H.dscal));
+    const int mode = R.steps == 0 ? 3 : 2;
+    H.count(0, in_bytes(P) + (mode == 2 ? 8.0 : 0.0) + es + 8.0 + es);  // read x64, e; write x64', scaled r
+    HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, mode, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, H.lv[0].b,
+                                  H.dscal + n, H.partials, st, H.x64b, H.dscal));
     HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, n, 1, H.dred, st));
     read_dred(H, 1, st);
     for (int g = 0; g < n; ++g) r[g] = std::sqrt(H.hpin[g]);
     std::swap(H.x64, H.x64b);
     R.steps++;
+  }
+  if (R.steps == 0) {  // x64 = I0 for the output
+    H.count(0, dsize(P.tin) + 8.0);
+    HIP_TRY(launch_refine_init(P.tin, H.g_ew(0), P.I0, H.x64, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
   cy.harvest();

@@ -53,8 +53,9 @@ hipError_t launch_prolong_pair(gd_dtype s, const Geom& g, const void* e_coarse, 
 hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* e_coarse, void* x, int mode,
                               hipStream_t st);
 // Finest level of the AD/SP systems in correction form: b = alpha (I1 - I0)
-// - w_z L_z I0 (written when b != NULL, x zeroed when x != NULL) and the
-// FP64 squares of the canonical right-hand side alpha I1 + (w_x L_x + w_y L_y) I0.
+// - w_z L_z I0 (written when b != NULL, x zeroed when x != NULL) and per
+// block two FP64 sums (partials[2 block], [2 block + 1]): the squares of the
+// canonical right-hand side alpha I1 + (w_x L_x + w_y L_y) I0 and of b.
 // I1 (read only when alpha != 0) has type t1: tin, or F32 / F64 on slice
 // (one-line) grids.
 hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype t1, gd_dtype s, const Geom& g, const void* I0, const void* I1,
@@ -62,12 +63,15 @@ hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype t1, gd_dtype s, const Geom& g,
 // FP64 canonical residual r = b - A x of the AD/SP system for x = I0 + E
 // (mode 0, E packed in `s`), x = x64 (mode 1) or x = x64 + e_scale[g] E
 // (mode 2, the refinement update, also written to x64_out, which must not
-// alias x64).  Per block: sum r^2.  When r_out != NULL also writes
+// alias x64), or x = I0 + e_scale[g] E (mode 3: the first update, x64 not
+// read).  Per block: sum r^2.  When r_out != NULL also writes
 // r * inv_scale[g] packed in `s`.
 hipError_t launch_canon_residual(gd_dtype tin, gd_dtype t1, gd_dtype s, int mode, const Geom& g, const void* I0,
                                  const void* I1, const void* E, const double* x64, void* r_out,
                                  const double* inv_scale, double* partials, hipStream_t st,
                                  double* x64_out = nullptr, const double* e_scale = nullptr);
+// v *= f[g] on the cells of grid g of a level array (per-voxel tiles)
+hipError_t launch_scale_level(gd_dtype s, const Geom& g, void* v, const double* f, hipStream_t st);
 // Per block: sum (x - I0) for x = I0 + E (mode 0) or x64 (mode 1).
 hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
                             const void* E, const double* x64, double* partials, hipStream_t st);

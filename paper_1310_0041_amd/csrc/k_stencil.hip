@@ -31,7 +31,8 @@ namespace gd {
 //   form's cross-slice target is zero (Eq. (1)).  Writes b_corr and a zero
 //   correction.
 // KIND 1, canonical residual b - A x in FP64.  With F = x - I0 (E in MODE 0,
-// x64 - I0 in MODE 1, x64 + s e - I0 in MODE 2, where the refinement's
+// x64 - I0 in MODE 1, x64 + s e - I0 in MODE 2, I0 + s e - I0 in MODE 3 (the
+// first refinement update, from x64 = I0 without reading it), where the refinement's
 // update x64 + s e is also written to x64_out, s = e_scale[grid]) the I0
 // terms of b and A x cancel except across slices:
 //   r = alpha (I1 - I0 - F) - (w_x L_x + w_y L_y + w_z L_z) F - [stack] w_z L_z I0
@@ -54,8 +55,10 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   constexpr int NHALO = HX * HY - TX * TY;
   constexpr int NHR = (NHALO + NT - 1) / NT;
   static_assert(MODE < 2 || KIND == 1, "the refinement update belongs to the residual pass");
+  constexpr bool UPD = MODE >= 2;  // the refinement update x64' = (x64 or I0) + s e
   __shared__ double X[3][HY][HX];
   __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+  __shared__ double red2[NT / 64 > 0 ? NT / 64 : 1];
 
   const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
@@ -109,20 +112,20 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   }
   // Raw loads of plane q: F's own pair and halo values and (KIND 1) I0's
   // pair; converted to FP64 only in stash(), after other work has run.
-  using FS = std::conditional_t<KIND == 0, Tin, std::conditional_t<MODE == 0, S, double>>;
+  using FS = std::conditional_t<KIND == 0, Tin, std::conditional_t<MODE == 0 || MODE == 3, S, double>>;
   // Loads of a plane sit in one of two slots: a plane is fetched two planes
   // ahead of its use, and the loop is unrolled by two so that no slot is
   // copied (a copy would make the wave wait for the newest loads).
   struct Pre {
     Raw2<FS> rf;
     Raw2<Tin> ri;
-    Raw2<S> re;  // MODE 2: the correction e
+    Raw2<S> re;  // MODE 2, 3: the correction e
     Raw<FS> rh[NHR];
     Raw<Tin> rhi[NHR];
     Raw<S> rhe[NHR];
     Raw2<T1> r1;  // the I1 pair (alpha != 0)
   };
-  const double es = (MODE == 2) ? e_scale[t.g] : 0.0;
+  const double es = UPD ? e_scale[t.g] : 0.0;
   // loads from clamped addresses without branches around them (masked in stash)
   auto fetch = [&](int q, Pre& o) {
     const int qc = min(max(q, 0), nz - 1);
@@ -135,6 +138,8 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
       ld_raw2(I0q + ou, ivec, vB, o.ri);
       if (MODE == 0) {
         ld_raw2(reinterpret_cast<const FS*>(Eg) + po + oo, true, true, o.rf);
+      } else if (MODE == 3) {
+        ld_raw2(Eg + po + oo, true, true, o.re);
       } else {
         ld_raw2(reinterpret_cast<const FS*>(xg) + po + oo, true, true, o.rf);
         if (MODE == 2) ld_raw2(Eg + po + oo, true, true, o.re);
@@ -144,7 +149,10 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     for (int k = 0; k < NHR; ++k) {
       if (KIND == 0) ld_raw(reinterpret_cast<const FS*>(I0q) + hu[k], o.rh[k]);
       else if (MODE == 0) ld_raw(reinterpret_cast<const FS*>(Eg) + po + hg[k], o.rh[k]);
-      else {
+      else if (MODE == 3) {
+        ld_raw(I0q + hu[k], o.rhi[k]);
+        ld_raw(Eg + po + hg[k], o.rhe[k]);
+      } else {
         ld_raw(reinterpret_cast<const FS*>(xg) + po + hg[k], o.rh[k]);
         ld_raw(I0q + hu[k], o.rhi[k]);
         if (MODE == 2) ld_raw(Eg + po + hg[k], o.rhe[k]);
@@ -164,9 +172,14 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     }
     ja = I1g ? raw_a(o.r1) : 0.0;
     jb = I1g ? raw_b(o.r1) : 0.0;
-    fa = mA ? raw_a(o.rf) : 0.0;
-    fb = mB ? raw_b(o.rf) : 0.0;
-    if (KIND == 1 && MODE == 2) {  // refinement update x64 + s e, written by the cell's owner
+    if (MODE == 3) {  // x64 = I0 before the first update
+      fa = ia;
+      fb = ib;
+    } else {
+      fa = mA ? raw_a(o.rf) : 0.0;
+      fb = mB ? raw_b(o.rf) : 0.0;
+    }
+    if (KIND == 1 && UPD) {  // refinement update x64 + s e, written by the cell's owner
       fa += mA ? es * raw_a(o.re) : 0.0;
       fb += mB ? es * raw_b(o.re) : 0.0;
       if (vA && q >= q0 && q < q1) st2(x64_out + G.off + q * pl + own, vec, vB, fa, fb);
@@ -181,8 +194,8 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
 #pragma unroll
     for (int k = 0; k < NHR; ++k)
       if (tid + NT * k < NHALO) {
-        double v = raw_d(o.rh[k]);
-        if (KIND == 1 && MODE == 2) v += es * raw_d(o.rhe[k]);
+        double v = MODE == 3 ? raw_d(o.rhi[k]) : raw_d(o.rh[k]);
+        if (KIND == 1 && UPD) v += es * raw_d(o.rhe[k]);
         if (KIND == 1 && MODE >= 1) v -= raw_d(o.rhi[k]);
         P[hoff[k]] = (okq && hv[k]) ? v : 0.0;
       }
@@ -200,7 +213,7 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   fca = fa; fcb = fb; ica = ia; icb = ib; jca = ja; jcb = jb;
   fetch(q0 + 1, A);
   fetch(q0 + 2, B);
-  double nrm = 0.0;
+  double nrm = 0.0, nrm2 = 0.0;  // KIND 0: sum b^2 (canonical) and sum b_corr^2
   // plane k: slot o holds plane k + 1, refilled with plane k + 3
   auto iter = [&](int k, Pre& o) {
     stash(k + 1, o);
@@ -247,6 +260,7 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
         const double bcan = alpha * v1a + lin;
         nrm += vA ? bcan * bcan : 0.0;
         ra = alpha * (v1a - c) - lzI;
+        nrm2 += vA ? ra * ra : 0.0;
       } else {
         ra = alpha * (v1a - ica - c) - lf - lzI;
         nrm += vA ? ra * ra : 0.0;
@@ -266,6 +280,7 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
         const double bcan = alpha * v1b + lin;
         nrm += vB ? bcan * bcan : 0.0;
         rb = alpha * (v1b - c) - lzI;
+        nrm2 += vB ? rb * rb : 0.0;
       } else {
         rb = alpha * (v1b - icb - c) - lf - lzI;
         nrm += vB ? rb * rb : 0.0;
@@ -293,7 +308,15 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   if (k < q1) iter(k, A);
   if (partials) {
     const double sm = block_sum(nrm, red);
-    if (threadIdx.x == 0) partials[t.bid] = sm;
+    if (KIND == 0) {
+      const double sm2 = block_sum(nrm2, red2);
+      if (threadIdx.x == 0) {
+        partials[2 * t.bid] = sm;
+        partials[2 * t.bid + 1] = sm2;
+      }
+    } else if (threadIdx.x == 0) {
+      partials[t.bid] = sm;
+    }
   }
 }
 
@@ -358,6 +381,22 @@ k_refine_init(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 }
 
 
+// v *= f[grid] on the cells of a level array (the scale of a right-hand side)
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_scale_level(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
+              S* __restrict__ v, const double* __restrict__ f) {
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
+  const GridDesc& G = grids[t.g];
+  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
+  if (i >= G.nx || j >= G.ny) return;
+  const int64_t pl = (int64_t)G.px * G.ny;
+  const double c = f[t.g];
+  for (int k = t.z0; k < t.z1; ++k) {
+    S* p = v + G.off + k * pl + (int64_t)j * G.px + i;
+    st64(p, ld64(p) * c);
+  }
+}
 
 // ============================================================ launchers
 
@@ -424,8 +463,11 @@ hipError_t launch_canon_residual(gd_dtype tin, gd_dtype t1, gd_dtype s, int mode
   else if (mode == 1)                                                                                           \
     e = corr_stencil_launch<TI, T, 1, 1>(t1, tin, g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, nullptr, \
                                          nullptr, st);                                                          \
-  else                                                                                                          \
+  else if (mode == 2)                                                                                           \
     e = corr_stencil_launch<TI, T, 1, 2>(t1, tin, g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, x64_out, \
+                                         e_scale, st);                                                          \
+  else                                                                                                          \
+    e = corr_stencil_launch<TI, T, 1, 3>(t1, tin, g, I0, I1, E, x64, r_out, nullptr, inv_scale, partials, x64_out, \
                                          e_scale, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
@@ -480,6 +522,14 @@ hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, doubl
   if (g.nblocks == 0) return hipSuccess;
 #define L(T) hipLaunchKernelGGL(k_refine_init<T>, GD_ARGS(g), (const T*)I0, x64)
   GD_DISPATCH_S(tin, L)
+#undef L
+  return last();
+}
+
+hipError_t launch_scale_level(gd_dtype s, const Geom& g, void* v, const double* f, hipStream_t st) {
+  if (g.nblocks == 0) return hipSuccess;
+#define L(T) hipLaunchKernelGGL(k_scale_level<T>, GD_ARGS(g), (T*)v, f)
+  GD_DISPATCH_S(s, L)
 #undef L
   return last();
 }
