@@ -590,8 +590,9 @@ def measured_traffic(a, leg, tile):
         return None, None
     entries = t if isinstance(t, list) else [t]
     sha = source_sha(SWEEP_SRC)
+    spec_key = WORKLOADS[a.workload][0]  # the input (stack4k-f16 is the stack4k input's FP16 leg)
     for e in entries:
-        if (e.get("workload") == a.workload and e.get("storage", "f32") == leg and list(e.get("tile", [])) == list(tile)
+        if (e.get("workload") == spec_key and e.get("storage", "f32") == leg and list(e.get("tile", [])) == list(tile)
                 and e.get("source_sha") == sha):
             return e["bytes_per_launch"], (f"{os.path.relpath(a.traffic_json)}: rocprofv3 FETCH_SIZE x "
                                            f"{e['fetch_factor']:.3g} + WRITE_SIZE x {e['write_factor']:.3g} of this "
@@ -660,7 +661,7 @@ def run_stack_leg(a, gd, synth, torch, spec, storage, refine, steps, warmup):
         "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
         "traffic_source": traffic_src,
-        "kernel": "k_rb_sweep<%s, %d, %d, false, true> finest level (HIP events on the solve's stream)"
+        "kernel": "k_rb_sweep4<%s, %d, %d, false> finest level (HIP events on the solve's stream)"
                   % ((tname,) + tuple(cfg["tile"])),
         "sweep_config": cfg,
         "launches": launches,

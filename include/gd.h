@@ -76,7 +76,10 @@ typedef struct {
                            post-smoothing sweep instead of a separate pass    */
   int sweep_tile;       /* relaxation tile of 3-D grids: -1 automatic (the
                            autotuned or default choice), 0: 64x8, 1: 128x8,
-                           2: 64x16, 3: 128x16.  Results do not depend on it. */
+                           2: 64x16, 3: 128x16; 4: 256x8 and 5: 256x12 with
+                           FP32/FP16/BF16 storage and sweep_quad = 1 only
+                           (GD_ERR_INVALID otherwise).  Results do not depend
+                           on it. */
   int use_graph;        /* 1 (default): the repeated part of each V-cycle is
                            captured once into a HIP graph and replayed; 0:
                            plain launches.  Same results either way; timing = 1

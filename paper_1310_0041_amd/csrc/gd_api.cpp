@@ -90,7 +90,7 @@ static int32_t pitch_of(int64_t nx) { return (int32_t)((nx + 3) & ~(int64_t)3); 
 
 // Block order of relaxation launches (0 plain, 1 a contiguous run of tiles
 // per XCD): GD_SWEEP_ORDER=0/1 fixes it, otherwise -1 here and the slice
-// autotuner times both (3-D grids keep the plain order).
+// autotuner times both (3-D grids keep the plain order unless it is set).
 static int sweep_order_env() {
   static const int v = [] {
     const char* e = std::getenv("GD_SWEEP_ORDER");
@@ -129,6 +129,7 @@ struct Level {
   bool row = false;  // every grid has ny == 1
   bool keep_x = false;  // every grid keeps x on the way to the next level (f_x == 1)
   Tab sw, ew, rc, rz, pp;  // relaxation, per-voxel, child-cell, z-marching restriction, prolongation tiles
+  Tab cs;                  // quad-form finest-level stencil passes (3-D grids)
   void* x = nullptr;
   void* xt = nullptr;
   void* b = nullptr;
@@ -215,6 +216,8 @@ struct Hier {
   Geom g_rc(int l) const { return lv[l].rc.geom(lv[l].d, ngrids, lv[l].row); }
   Geom g_rz(int l) const { return lv[l].rz.geom(lv[l].d, ngrids, lv[l].row); }
   Geom g_pp(int l) const { return lv[l].pp.geom(lv[l].d, ngrids, lv[l].row); }
+  Geom g_cs(int l) const { return lv[l].cs.geom(lv[l].d, ngrids, lv[l].row); }
+  bool quad_opt = true;  // the caller's sweep_quad option of the running solve
 };
 
 static void coarsen_factors(const GridDesc& g, int f[3]) {
@@ -253,6 +256,16 @@ static int sweep_tile() {
     const char* e = std::getenv("GD_SWEEP_TILE");
     const int t = e ? std::atoi(e) : 2;
     return (t >= 0 && t < 4) ? t : 2;
+  }();
+  return v;
+}
+
+// Tile of the quad-form stencil passes (GD_STENCIL_TILE: 0 128 x 8, the
+// default; 1 64 x 16).
+static int stencil4_tile() {
+  static const int v = [] {
+    const char* e = std::getenv("GD_STENCIL_TILE");
+    return (e && std::atoi(e) == 1) ? 1 : 0;
   }();
   return v;
 }
@@ -368,20 +381,25 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
       build_tab(L.rc, L.h, EWR_TX, 1, true, 8192);
       build_tab(L.rz, L.h, SWR_TX, 1, false, 4096, true);
       build_tab(L.pp, L.h, SWR_TX, 1, false, li == 0 ? 8192 : 4096);
+      build_tab(L.cs, L.h, SWR_TX, 1, false, 4096);  // not used: rows take the pair form
     } else {
       const int v = tile_force >= 0 ? tile_force : sweep_tile();
       build_tab(L.sw, L.h, SWEEP_TILE_TX[v], SWEEP_TILE_TY[v], false, tgt);
       L.sw.tile = v;
+      L.sw.order = sweep_order_env() == 1 ? 1 : 0;
       build_tab(L.ew, L.h, EW_TX, EW_TY, false, 8192);
       build_tab(L.rc, L.h, EW_TX, EW_TY, true, 8192);
       build_tab(L.rz, L.h, SW_TX, SW_TY, false, 2048, true);
       build_tab(L.pp, L.h, SW_TX, SW_TY, false, li == 0 ? 4096 : 2048);
+      const int c4 = stencil4_tile();
+      build_tab(L.cs, L.h, CS4_TX[c4], CS4_TY[c4], false, 2048);
+      L.cs.tile = c4;
     }
     maxblocks = std::max({maxblocks, L.sw.h_b0.back(), L.ew.h_b0.back(), L.rc.h_b0.back(), L.rz.h_b0.back(),
-                          L.pp.h_b0.back()});
+                          L.pp.h_b0.back(), L.cs.h_b0.back()});
     const size_t nb = (size_t)H->ngrids + 1;
     const size_t gbytes = L.h.size() * sizeof(GridDesc);
-    const size_t bytes = gbytes + 5 * nb * sizeof(int64_t);
+    const size_t bytes = gbytes + 6 * nb * sizeof(int64_t);
     char* dev = (char*)H->alloc(bytes);
     L.d = (GridDesc*)dev;
     L.sw.d_b0 = (int64_t*)(dev + gbytes);
@@ -389,10 +407,11 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     L.rc.d_b0 = L.ew.d_b0 + nb;
     L.rz.d_b0 = L.rc.d_b0 + nb;
     L.pp.d_b0 = L.rz.d_b0 + nb;
+    L.cs.d_b0 = L.pp.d_b0 + nb;
     stage.resize(bytes);
     std::memcpy(stage.data(), L.h.data(), gbytes);
-    const Tab* tabs[5] = {&L.sw, &L.ew, &L.rc, &L.rz, &L.pp};
-    for (int k = 0; k < 5; ++k)
+    const Tab* tabs[6] = {&L.sw, &L.ew, &L.rc, &L.rz, &L.pp, &L.cs};
+    for (int k = 0; k < 6; ++k)
       std::memcpy(stage.data() + gbytes + k * nb * sizeof(int64_t), tabs[k]->h_b0.data(), nb * sizeof(int64_t));
     if (!measure) HIP_TRY(hipMemcpy(dev, stage.data(), bytes, hipMemcpyHostToDevice));
     if ((int)li >= first_arrays) {
@@ -536,7 +555,8 @@ static void autotune_rows(Hier& H, hipStream_t st) {
   set_row_tabs(H, best.target, best.order);
 }
 
-static void autotune(Hier& H, hipStream_t st) {
+// wide: the quad form's wide tiles (4, 5) are candidates
+static void autotune(Hier& H, hipStream_t st, bool wide) {
   Level& L = H.lv[0];
   if (!autotune_on()) return;
   if (L.row) {
@@ -566,11 +586,12 @@ static void autotune(Hier& H, hipStream_t st) {
   TuneChoice best;
   best.ms = 1e30;
   const int64_t targets[4] = {1024, 2048, 4096, 8192};
-  for (int tile = 0; tile < 4; ++tile) {
+  for (int tile = 0; tile < (wide ? kSweepTiles : kPairTiles); ++tile) {
     for (int64_t target : targets) {
       Tab t;
       build_tab(t, L.h, SWEEP_TILE_TX[tile], SWEEP_TILE_TY[tile], false, target);
       t.tile = tile;
+      t.order = L.sw.order;
       HIP_TRY(hipMemcpyAsync(d_b0, t.h_b0.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice, st));
       t.d_b0 = d_b0;
       const Geom geo = t.geom(L.d, 1, false);
@@ -676,15 +697,16 @@ static void set_alphas(Hier& H, const std::vector<GridSpec>& specs, hipStream_t 
 }
 
 static HierLease get_hier(const char* kind, const std::vector<GridSpec>& specs, gd_dtype s, bool mixed,
-                          hipStream_t st, int tile_force) {
+                          hipStream_t st, int tile_force, bool quad) {
+  const bool wide = sweep_wide_tiles_ok(s, quad);  // the autotuner may pick a quad-only tile
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   // sizes and weights decide the hierarchy; alpha and the caller's layout are updated in place
   std::vector<double> sig;
   for (const auto& g : specs) sig.insert(sig.end(), {(double)g.nx, (double)g.ny, (double)g.nz, g.wx, g.wy, g.wz});
   char key[256];
-  std::snprintf(key, sizeof key, "%s|d%d|s%d|m%d|t%d|n%zu|h%016llx", kind, dev, (int)s, (int)mixed, tile_force,
-                specs.size(), (unsigned long long)fnv(sig.data(), sig.size() * sizeof(double)));
+  std::snprintf(key, sizeof key, "%s|d%d|s%d|m%d|t%d|w%d|n%zu|h%016llx", kind, dev, (int)s, (int)mixed, tile_force,
+                (int)wide, specs.size(), (unsigned long long)fnv(sig.data(), sig.size() * sizeof(double)));
   HierLease lease;
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -699,7 +721,7 @@ static HierLease get_hier(const char* kind, const std::vector<GridSpec>& specs, 
         evict_idle(0);  // free every idle hierarchy and try once more
         H = build_hier(specs, s, mixed, st, tile_force);
       }
-      if (tile_force < 0) autotune(*H, st);
+      if (tile_force < 0) autotune(*H, st, wide);
       CacheEntry ce;
       ce.H = std::move(H);
       ce.mu = std::make_unique<std::mutex>();
@@ -856,6 +878,7 @@ static void ensure_tables(Hier& H, int disc) {
 
 static void prep(Hier& H, const gd_solve_opts& o) {
   if (o.discretization == 1 || o.discretization == 2) ensure_tables(H, o.discretization);
+  H.quad_opt = o.sweep_quad != 0;
 }
 
 static void read_dred(Hier& H, int ncomp, hipStream_t st);
@@ -1109,6 +1132,22 @@ struct Outcome {
   bool converged = false, numeric = false;
 };
 
+// Launch geometry of the finest-level stencil passes: the quad form on 3-D
+// grids when the caller's inputs allow aligned 4-element accesses (offsets
+// and pitches multiples of 4, base addresses aligned) and the solve asks
+// for quad forms; otherwise the pair form on the restriction's tiles.
+static Geom stencil_geom(const Hier& H, const Problem& P) {
+  const Level& L = H.lv[0];
+  auto aligned = [](const void* p, gd_dtype t) { return ((uintptr_t)p % (4 * dsize(t))) == 0; };
+  const char* env = std::getenv("GD_STENCIL_QUAD");  // 0: the pair form (same values)
+  bool q = H.quad_opt && !(env && std::atoi(env) == 0) && !L.row && aligned(P.I0, P.tin) &&
+           (!P.I1 || (P.t1 == P.tin && aligned(P.I1, P.t1)));
+  for (const auto& g : L.h) q = q && ((g.ioff | g.ipy | g.ipz) & 3) == 0;
+  Geom g = q ? H.g_cs(0) : H.g_rz(0);
+  g.stencil4 = q;
+  return g;
+}
+
 // ||b|| of the canonical system per grid (and the correction-form rhs when b_out)
 // bytes per cell of reading the caller's inputs (I0, and I1 when given)
 static double in_bytes(const Problem& P) { return (double)dsize(P.tin) + (P.I1 ? (double)dsize(P.t1) : 0.0); }
@@ -1116,10 +1155,11 @@ static double in_bytes(const Problem& P) { return (double)dsize(P.tin) + (P.I1 ?
 // (one pass; r0, when given, receives the norm of the correction-form
 // right-hand side, which is the canonical residual of x = I0)
 static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero, std::vector<double>& bn,
-                            hipStream_t st, std::vector<double>* r0 = nullptr) {
+                            hipStream_t st, std::vector<double>* r0 = nullptr, const double* inv_scale = nullptr) {
   H.count(0, in_bytes(P) + (b_out ? dsize(H.s) : 0) + (x_zero ? dsize(H.s) : 0));
-  HIP_TRY(launch_rhs_corr(P.tin, P.t1, H.s, H.g_rz(0), P.I0, P.I1, b_out, x_zero, H.partials, st));
-  HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, H.ngrids, 2, H.dred, st));
+  const Geom g = stencil_geom(H, P);
+  HIP_TRY(launch_rhs_corr(P.tin, P.t1, H.s, g, P.I0, P.I1, b_out, x_zero, H.partials, st, inv_scale));
+  HIP_TRY(launch_reduce(H.partials, g.block0, H.ngrids, 2, H.dred, st));
   read_dred(H, 2, st);
   bn.resize(H.ngrids);
   for (int g = 0; g < H.ngrids; ++g) bn[g] = std::sqrt(H.hpin[2 * g]);
@@ -1131,9 +1171,10 @@ static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero
 
 static std::vector<double> canon_residual(Hier& H, const Problem& P, int mode, void* rout, hipStream_t st) {
   H.count(0, in_bytes(P) + (mode == 0 ? dsize(H.s) : 8.0) + (rout ? dsize(H.s) : 0));
-  HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, mode, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, rout, H.dscal + H.ngrids,
+  const Geom g = stencil_geom(H, P);
+  HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, mode, g, P.I0, P.I1, H.lv[0].x, H.x64, rout, H.dscal + H.ngrids,
                                 H.partials, st));
-  HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, H.ngrids, 1, H.dred, st));
+  HIP_TRY(launch_reduce(H.partials, g.block0, H.ngrids, 1, H.dred, st));
   read_dred(H, 1, st);
   std::vector<double> r(H.ngrids);
   for (int g = 0; g < H.ngrids; ++g) r[g] = std::sqrt(H.hpin[g]);
@@ -1249,43 +1290,41 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
 }
 
 // Mixed path: FP64 iterate x64 (starting at I0), V-cycles in the storage
-// type on the residual scaled to unit RMS.  The right-hand-side pass writes
-// the correction-form b, which is the residual of x64 = I0, and its norm;
-// in FP16 storage it is scaled by a power of two (exact) when its RMS is far
-// from one.  One fused pass per refinement step applies the update x64 + s e
-// (into the second FP64 buffer; the first update reads I0 in place of
-// x64), computes the FP64 canonical residual of the result and writes it,
-// scaled by the RMS of the residual before it (so that it is of order one),
-// as the next right-hand side.
+// type on the residual scaled to unit RMS (by a power of two).  The
+// right-hand-side pass writes the correction-form b, which is the residual
+// of x64 = I0, and its norm (in FP16 storage, whose range is narrow, a first
+// pass takes the norm and a second writes b already scaled).  One fused pass
+// per refinement step applies the update x64 + s e (into the second FP64
+// buffer; the first update reads I0 in place of x64), computes the FP64
+// canonical residual of the result and writes it, scaled by the RMS of the
+// residual before it (so that it is of order one), as the next right-hand
+// side.
 static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
   prep(H, o);
   Outcome R;
   const double a0 = H.acct;
-  std::vector<double> r;
-  canonical_norms(H, P, H.lv[0].b, nullptr, R.bnorm, st, &r);
   Cycler cy(H, st, o);
   const size_t es = dsize(H.s);
   const int n = H.ngrids;
+  // the power of two nearest the RMS of a residual: scaling by it is exact,
+  // so the stored right-hand side does not depend on the last bits of the
+  // norm (which depend on the order of its sums)
   auto rms = [&](int g, const std::vector<double>& v) {
     const double q = v[g] / std::sqrt((double)H.cells[g]);
-    return q > 0.0 ? q : 1.0;
+    return (q > 0.0 && std::isfinite(q)) ? std::ldexp(1.0, (int)std::lround(std::log2(q))) : 1.0;
   };
+  std::vector<double> r;
   std::vector<double> scale(n, 1.0);  // scale of the right-hand side in L0.b
   if (H.s == GD_F16) {
-    bool any = false;
+    canonical_norms(H, P, nullptr, nullptr, R.bnorm, st, &r);
     for (int g = 0; g < n; ++g) {
-      const double e = std::round(std::log2(rms(g, r)));
-      if (e < -2.0 || e > 4.0) {
-        scale[g] = std::ldexp(1.0, (int)e);
-        any = true;
-      }
-      H.hpin[3 * n + g] = 1.0 / scale[g];  // a slot the steps below leave alone while the copy is pending
+      scale[g] = rms(g, r);
+      H.hpin[3 * n + g] = 1.0 / scale[g];  // a slot the steps below leave alone
     }
-    if (any) {
-      HIP_TRY(hipMemcpyAsync(H.dscal + 3 * n, H.hpin + 3 * n, n * sizeof(double), hipMemcpyHostToDevice, st));
-      H.count(0, 2.0 * es);
-      HIP_TRY(launch_scale_level(H.s, H.g_ew(0), H.lv[0].b, H.dscal + 3 * n, st));
-    }
+    HIP_TRY(hipMemcpyAsync(H.dscal + 3 * n, H.hpin + 3 * n, n * sizeof(double), hipMemcpyHostToDevice, st));
+    canonical_norms(H, P, H.lv[0].b, nullptr, R.bnorm, st, &r, H.dscal + 3 * n);
+  } else {
+    canonical_norms(H, P, H.lv[0].b, nullptr, R.bnorm, st, &r);
   }
   Geom g0sw = H.g_sw(0);
   g0sw.quad = o.sweep_quad != 0;
@@ -1327,9 +1366,10 @@ static Outcome solve_mixed(Hier& H, const Problem& P, const gd_solve_opts& o, hi
     HIP_TRY(hipMemcpyAsync(H.dscal, H.hpin, 2 * n * sizeof(double), hipMemcpyHostToDevice, st));
     const int mode = R.steps == 0 ? 3 : 2;
     H.count(0, in_bytes(P) + (mode == 2 ? 8.0 : 0.0) + es + 8.0 + es);  // read x64, e; write x64', scaled r
-    HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, mode, H.g_rz(0), P.I0, P.I1, H.lv[0].x, H.x64, H.lv[0].b,
+    const Geom gs = stencil_geom(H, P);
+    HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, mode, gs, P.I0, P.I1, H.lv[0].x, H.x64, H.lv[0].b,
                                   H.dscal + n, H.partials, st, H.x64b, H.dscal));
-    HIP_TRY(launch_reduce(H.partials, H.lv[0].rz.d_b0, n, 1, H.dred, st));
+    HIP_TRY(launch_reduce(H.partials, gs.block0, n, 1, H.dred, st));
     read_dred(H, 1, st);
     for (int g = 0; g < n; ++g) r[g] = std::sqrt(H.hpin[g]);
     std::swap(H.x64, H.x64b);
@@ -1563,9 +1603,11 @@ const char* gd_version(void) { return "gdstack 0.1 gfx950"; }
 static gd_status check_opts(const gd_solve_opts& o) {
   if (!(o.rel_tol > 0.0) || o.max_cycles < 0 || o.pre_smooth < 0 || o.post_smooth < 0 ||
       o.pre_smooth + o.post_smooth < 1 || !valid_dtype(o.storage) || o.inner_cycles < 1 ||
-      (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3 ||
+      (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile >= kSweepTiles ||
       o.discretization < 0 || o.discretization > 2 || o.sweep_quad < 0 || o.sweep_quad > 1)
     return fail(GD_ERR_INVALID, "invalid solver options");
+  if (o.sweep_tile >= kPairTiles && !sweep_wide_tiles_ok(o.storage, o.sweep_quad != 0))
+    return fail(GD_ERR_INVALID, "sweep_tile 4 and 5 need the quad relaxation (FP32/FP16/BF16 storage, sweep_quad = 1)");
   if (!o.fp64_refine && (o.storage == GD_F16 || o.storage == GD_BF16))
     return fail(GD_ERR_UNSUPPORTED, "16-bit storage needs fp64_refine = 1 (its rounding floor is far above 1e-6)");
   return GD_OK;
@@ -1609,7 +1651,7 @@ gd_status gd_smooth_z(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t, i
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<GridSpec> g{{nx, ny, nz, 0.0, bx, by, bz, 0, nx, nx * ny}};
-    HierLease H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
+    HierLease H = get_hier("ad", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile, o.sweep_quad != 0);
     Outcome R = smooth_z_solve(*H, I0, in_t, I1, out_t, bx, by, bz, o, st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rep) fill_report(rep, R, 0, secs, (int)H->lv.size());
@@ -1686,7 +1728,7 @@ gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<GridSpec> g{{nx, ny, nz, alpha, bx, by, bz, 0, nx, nx * ny}};
-    HierLease H = get_hier("npr", g, o.storage, false, st, o.sweep_tile);
+    HierLease H = get_hier("npr", g, o.storage, false, st, o.sweep_tile, o.sweep_quad != 0);
     Level& L0 = H->lv[0];
     HIP_TRY(launch_npr_rhs(in_t, H->s, H->g_ew(0), I0, lambda, sigma, L0.b, H->partials, st));
     HIP_TRY(launch_reduce(H->partials, L0.ew.d_b0, 1, 2, H->dred, st));
@@ -1768,7 +1810,7 @@ gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1,
         std::vector<GridSpec> g1{{d.nx, 1, d.ny, (double)d.alpha, bx, 0.0, by, d.offset, d.pitch, d.pitch}};
         g1[0].zin = 1;
         HierLease H = get_hier(o.discretization == 1 ? "sp-hybrid" : "sp-linear", g1, o.storage,
-                               o.fp64_refine != 0, st, o.sweep_tile);
+                               o.fp64_refine != 0, st, o.sweep_tile, o.sweep_quad != 0);
         Problem P{I0, I1, I2, t, tout, false, t1};
         Outcome R = o.discretization == 2 ? solve_linear_sp(*H, P, o, st)
                     : o.fp64_refine       ? solve_mixed(*H, P, o, st)
@@ -1801,7 +1843,7 @@ gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1,
   }
   return run_guarded([&]() -> gd_status {
     const auto t0 = std::chrono::steady_clock::now();
-    HierLease H = get_hier("sp", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile);
+    HierLease H = get_hier("sp", g, o.storage, o.fp64_refine != 0, st, o.sweep_tile, o.sweep_quad != 0);
     Problem P{I0, I1, I2, t, tout, false, t1};
     Outcome R = o.fp64_refine ? solve_mixed(*H, P, o, st) : solve_plain(*H, P, o, st);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -39,15 +39,27 @@ template <> struct Ty<float> {
   static __device__ __forceinline__ float ld(const float* p) { return *p; }
   static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
 };
+// A 16-bit store rounds the FP32 value it is given.  A value computed in
+// FP64 and cast to float first is thus rounded twice; the empty asm keeps the
+// compiler from folding the two roundings into one (it does so for some
+// call sites and not others, which made equal expressions store different
+// values) and from fusing the last multiply-add into a mixed-precision FMA
+// that rounds once to 16 bits.
 template <> struct Ty<__half> {
   using C = float;
   static __device__ __forceinline__ float ld(const __half* p) { return __half2float(*p); }
-  static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
+  static __device__ __forceinline__ void st(__half* p, float v) {
+    asm volatile("" : "+v"(v));
+    *p = __float2half_rn(v);
+  }
 };
 template <> struct Ty<__hip_bfloat16> {
   using C = float;
   static __device__ __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
-  static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+  static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) {
+    asm volatile("" : "+v"(v));
+    *p = __float2bfloat16(v);
+  }
 };
 
 // Two consecutive values (p aligned to two elements when vec).

@@ -14,11 +14,13 @@ constexpr int SW_TX = 64, SW_TY = 8;   // relaxation tile of 3-D grids, 256 thre
 constexpr int SWR_TX = 256;            // relaxation tile of one-line grids (2-D slices), 128 threads
 constexpr int EW_TX = 64, EW_TY = 4;   // per-voxel kernels on 3-D grids: 256 threads
 constexpr int EWR_TX = 256;            // per-voxel kernels on one-line grids
-// Relaxation tile variants of 3-D grids (one x-pair per thread): 0: 64 x 8,
-// 1: 128 x 8, 2: 64 x 16, 3: 128 x 16.  Wider and taller tiles re-read a
-// smaller share of halo cells per voxel.
-constexpr int SWEEP_TILE_TX[4] = {64, 128, 64, 128};
-constexpr int SWEEP_TILE_TY[4] = {8, 8, 16, 16};
+// Relaxation tile variants of 3-D grids: 0: 64 x 8, 1: 128 x 8, 2: 64 x 16,
+// 3: 128 x 16, and for the quad form only 4: 256 x 8, 5: 256 x 12.  Wider
+// and taller tiles re-read a smaller share of halo cells per voxel (at
+// 1024 threads, 256 x 16, the registers of a thread no longer fit).
+constexpr int kSweepTiles = 6, kPairTiles = 4;
+constexpr int SWEEP_TILE_TX[kSweepTiles] = {64, 128, 64, 128, 256, 256};
+constexpr int SWEEP_TILE_TY[kSweepTiles] = {8, 8, 16, 16, 8, 12};
 
 // A launch over the grids of one level: blocks [block0[g], block0[g+1])
 // belong to grid g; each block covers one (x, y) tile and `zlen` planes.
@@ -35,13 +37,21 @@ struct Geom {
   int order = 0;     // relaxation block order: 0 plain, 1 contiguous runs per XCD
   bool quad = false; // the library's own arrays (x pitch and offsets multiples of 4, aligned):
                      // the relaxation may use its quad form
+  bool stencil4 = false;  // the finest-level stencil passes in their quad form (tiles
+                          // CS4_TX[tile] x CS4_TY[tile]; 3-D grids, quad-aligned inputs)
 };
+// Tiles of the quad-form finest-level stencil passes of 3-D grids.
+constexpr int CS4_TX[2] = {128, 64};
+constexpr int CS4_TY[2] = {8, 16};
 
 // xzero: x_in is all zero (not read; the quad form only, see
 // sweep_starts_from_zero_ok)
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
                            const void* e_coarse, int prolong_mode, hipStream_t st, bool xzero = false);
 bool sweep_starts_from_zero_ok(gd_dtype s, const Geom& g);
+// the relaxation of the library's 3-D arrays in storage s takes the quad
+// form (quad: the caller's sweep_quad option), so the wide tiles 4 and 5 exist
+bool sweep_wide_tiles_ok(gd_dtype s, bool quad);
 // Residual + restriction (tiles as the relaxation, zlen even); per-block
 // sum r^2 into partials when non-NULL, coarse x zeroed when non-NULL.
 hipError_t launch_restrict_z(gd_dtype s, const Geom& g, const void* x, const void* b, void* b_coarse,
@@ -53,13 +63,14 @@ hipError_t launch_prolong_pair(gd_dtype s, const Geom& g, const void* e_coarse, 
 hipError_t launch_prolong_add(gd_dtype s, const Geom& g, const void* e_coarse, void* x, int mode,
                               hipStream_t st);
 // Finest level of the AD/SP systems in correction form: b = alpha (I1 - I0)
-// - w_z L_z I0 (written when b != NULL, x zeroed when x != NULL) and per
+// - w_z L_z I0 (written when b != NULL, times inv_scale[g] when that is
+// given, a power of two; x zeroed when x != NULL) and per
 // block two FP64 sums (partials[2 block], [2 block + 1]): the squares of the
 // canonical right-hand side alpha I1 + (w_x L_x + w_y L_y) I0 and of b.
 // I1 (read only when alpha != 0) has type t1: tin, or F32 / F64 on slice
 // (one-line) grids.
 hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype t1, gd_dtype s, const Geom& g, const void* I0, const void* I1,
-                           void* b, void* x, double* partials, hipStream_t st);
+                           void* b, void* x, double* partials, hipStream_t st, const double* inv_scale = nullptr);
 // FP64 canonical residual r = b - A x of the AD/SP system for x = I0 + E
 // (mode 0, E packed in `s`), x = x64 (mode 1) or x = x64 + e_scale[g] E
 // (mode 2, the refinement update, also written to x64_out, which must not
@@ -70,8 +81,6 @@ hipError_t launch_canon_residual(gd_dtype tin, gd_dtype t1, gd_dtype s, int mode
                                  const void* I1, const void* E, const double* x64, void* r_out,
                                  const double* inv_scale, double* partials, hipStream_t st,
                                  double* x64_out = nullptr, const double* e_scale = nullptr);
-// v *= f[g] on the cells of grid g of a level array (per-voxel tiles)
-hipError_t launch_scale_level(gd_dtype s, const Geom& g, void* v, const double* f, hipStream_t st);
 // Per block: sum (x - I0) for x = I0 + E (mode 0) or x64 (mode 1).
 hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
                             const void* E, const double* x64, double* partials, hipStream_t st);

@@ -180,8 +180,10 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
       fb = mB ? raw_b(o.rf) : 0.0;
     }
     if (KIND == 1 && UPD) {  // refinement update x64 + s e, written by the cell's owner
-      fa += mA ? es * raw_a(o.re) : 0.0;
-      fb += mB ? es * raw_b(o.re) : 0.0;
+      // one fused multiply-add, as for the halo copies of the same cell
+      // (other tiles must see the value this tile stores)
+      fa = mA ? __builtin_fma(es, raw_a(o.re), fa) : fa;
+      fb = mB ? __builtin_fma(es, raw_b(o.re), fb) : fb;
       if (vA && q >= q0 && q < q1) st2(x64_out + G.off + q * pl + own, vec, vB, fa, fb);
     }
     if (KIND == 1 && MODE >= 1) {
@@ -195,7 +197,7 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     for (int k = 0; k < NHR; ++k)
       if (tid + NT * k < NHALO) {
         double v = MODE == 3 ? raw_d(o.rhi[k]) : raw_d(o.rh[k]);
-        if (KIND == 1 && UPD) v += es * raw_d(o.rhe[k]);
+        if (KIND == 1 && UPD) v = __builtin_fma(es, raw_d(o.rhe[k]), v);
         if (KIND == 1 && MODE >= 1) v -= raw_d(o.rhi[k]);
         P[hoff[k]] = (okq && hv[k]) ? v : 0.0;
       }
@@ -289,7 +291,8 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     if (vA) {
       const int64_t v = G.off + k * pl + own;
       if (KIND == 0) {
-        if (out0) st2(out0 + v, vec, vB, (typename Ty<S>::C)ra, (typename Ty<S>::C)rb);
+        const double sc = inv_scale ? inv_scale[t.g] : 1.0;  // a power of two (exact)
+        if (out0) st2(out0 + v, vec, vB, (typename Ty<S>::C)(ra * sc), (typename Ty<S>::C)(rb * sc));
         if (out1) st2(out1 + v, vec, vB, (typename Ty<S>::C)0, (typename Ty<S>::C)0);
       } else if (out0) {
         const double sc = inv_scale[t.g];
@@ -299,6 +302,324 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
     fma_ = fca; fmb = fcb; fca = fpa; fcb = fpb;
     ima = ica; imb = icb; ica = ipa; icb = ipb;
     jca = jpa; jcb = jpb;
+  };
+  int k = q0;
+  for (; k + 1 < q1; k += 2) {
+    iter(k, A);
+    iter(k + 1, B);
+  }
+  if (k < q1) iter(k, A);
+  if (partials) {
+    const double sm = block_sum(nrm, red);
+    if (KIND == 0) {
+      const double sm2 = block_sum(nrm2, red2);
+      if (threadIdx.x == 0) {
+        partials[2 * t.bid] = sm;
+        partials[2 * t.bid + 1] = sm2;
+      }
+    } else if (threadIdx.x == 0) {
+      partials[t.bid] = sm;
+    }
+  }
+}
+
+// ------------------------------------- quad form of the same passes
+//
+// The passes above on 3-D grids with four consecutive x cells per thread,
+// for caller arrays whose offset and pitches are multiples of four (one
+// aligned access per quad) and the library's level arrays.  Every cell is
+// computed by the expressions of the pair form in the same order, so both
+// forms store the same values; the per-block norm partials are the same
+// terms summed in another order.  The LDS plane is TX + 8 wide with the tile
+// at x offset 4 (aligned quads): the halo is the full quad rows above and
+// below the tile and one quad on each side of its rows.
+
+template <typename T> struct Q4 {  // four consecutive raw values
+  using W = std::conditional_t<sizeof(T) == 8, double2, std::conditional_t<sizeof(T) == 4, float4, uint2>>;
+  W w[sizeof(T) == 8 ? 2 : 1];
+};
+template <typename T> __device__ __forceinline__ void ld_q4(const T* p, Q4<T>& r) {
+  if constexpr (sizeof(T) == 8) {
+    r.w[0] = reinterpret_cast<const double2*>(p)[0];
+    r.w[1] = reinterpret_cast<const double2*>(p)[1];
+  } else {
+    r.w[0] = *reinterpret_cast<const typename Q4<T>::W*>(p);
+  }
+}
+template <typename T> __device__ __forceinline__ double q4_d(const Q4<T>& r, int i) {
+  if constexpr (sizeof(T) == 8) {
+    const double2 v = r.w[i >> 1];
+    return (i & 1) ? v.y : v.x;
+  } else if constexpr (sizeof(T) == 4) {
+    const float4 v = r.w[0];
+    return (double)(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w);
+  } else {
+    const uint32_t v = (i < 2) ? r.w[0].x : r.w[0].y;
+    return from_bits16<T>((i & 1) ? (v >> 16) : (v & 0xffffu));
+  }
+}
+// four values of the compute type Ty<S>::C into an aligned quad of S
+template <typename S, typename C>
+__device__ __forceinline__ void st_q4(S* p, C a, C b, C c, C d) {
+  if constexpr (sizeof(S) == 8) {
+    reinterpret_cast<double2*>(p)[0] = make_double2((double)a, (double)b);
+    reinterpret_cast<double2*>(p)[1] = make_double2((double)c, (double)d);
+  } else if constexpr (sizeof(S) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4((float)a, (float)b, (float)c, (float)d);
+  } else {
+    S h[4];
+    Ty<S>::st(&h[0], a);
+    Ty<S>::st(&h[1], b);
+    Ty<S>::st(&h[2], c);
+    Ty<S>::st(&h[3], d);
+    uint16_t u[4];
+    __builtin_memcpy(u, h, 8);
+    *reinterpret_cast<uint2*>(p) = make_uint2((uint32_t)u[0] | ((uint32_t)u[1] << 16),
+                                              (uint32_t)u[2] | ((uint32_t)u[3] << 16));
+  }
+}
+
+template <typename Tin, typename S, int TX, int TY, int KIND, int MODE>
+__global__ void __launch_bounds__(TX * TY / 4)
+k_corr_stencil4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
+                const Tin* __restrict__ I0, const Tin* __restrict__ I1, const S* __restrict__ E,
+                const double* __restrict__ x64, S* __restrict__ out0, S* __restrict__ out1,
+                const double* __restrict__ inv_scale, double* __restrict__ partials,
+                double* __restrict__ x64_out, const double* __restrict__ e_scale) {
+  constexpr int NT = TX * TY / 4, QPR = TX / 4;
+  constexpr int XO = 4, HX = TX + 8, HY = TY + 2;
+  constexpr int QR = TX / 4 + 2;        // quads of a full halo row
+  constexpr int NHQ = 2 * QR + 2 * TY;  // halo quads per plane
+  constexpr int NHQR = (NHQ + NT - 1) / NT;
+  static_assert(MODE < 2 || KIND == 1, "the refinement update belongs to the residual pass");
+  static_assert(NT % 64 == 0, "whole waves");
+  constexpr bool UPD = MODE >= 2;
+  using C = typename Ty<S>::C;
+  __shared__ __align__(16) double X[3][HY * HX];
+  __shared__ double red[NT / 64];
+  __shared__ double red2[NT / 64];
+
+  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
+  const GridDesc& G = grids[t.g];
+  const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
+  const double alpha = G.alpha, wx = G.wx, wy = G.wy, wz = G.wz;
+  const bool cross = G.zin == 0 && wz != 0.0;  // the stack's cross-slice term of I0
+  const int64_t pl = (int64_t)px * ny;
+  const Tin* I0g = I0 + G.ioff;
+  const Tin* I1g = (I1 && alpha != 0.0) ? I1 + G.ioff : nullptr;
+  const S* Eg = E + G.off;
+  const double* xg = x64 + G.off;
+  const int tid = threadIdx.x;
+  const int x0 = t.x0, y0 = t.y0, q0 = t.z0, q1 = t.z1;
+  const int tyl = tid / QPR, qxl = tid - tyl * QPR;
+  const int gx = x0 + 4 * qxl, gy = y0 + tyl;
+  const bool rowok = gy < ny;
+  bool v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = rowok && gx + j < nx;
+  const int lo = (1 + tyl) * HX + XO + 4 * qxl;
+  const int64_t own = (int64_t)gy * px + gx, ownu = (int64_t)gy * G.ipy + gx;
+  // x and in-plane y weights of the quad's cells (0 where the neighbour is
+  // outside the grid), as the pair form gives them
+  double wl[4], wr[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    wl[j] = gx + j > 0 ? wx : 0.0;
+    wr[j] = gx + j + 1 < nx ? wx : 0.0;
+  }
+  const double wu = gy > 0 ? wy : 0.0, wd = gy + 1 < ny ? wy : 0.0;
+
+  int hoff[NHQR], hx0[NHQR];
+  int64_t hg[NHQR], hu[NHQR];
+  bool hs[NHQR], hq[NHQR];
+#pragma unroll
+  for (int k = 0; k < NHQR; ++k) {
+    const int h = tid + NT * k;
+    int hy = 0, hx = 0;
+    if (h < QR) {
+      hx = 4 * h;
+    } else if (h < 2 * QR) {
+      hy = HY - 1;
+      hx = 4 * (h - QR);
+    } else {
+      const int m = h - 2 * QR;
+      hy = 1 + (m >> 1);
+      hx = (m & 1) ? TX + XO : 0;
+    }
+    const int cx = x0 - XO + hx, cy = y0 - 1 + hy;  // cx is a multiple of 4
+    hs[k] = h < NHQ;
+    hq[k] = hs[k] && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    hoff[k] = hy * HX + hx;
+    hg[k] = hq[k] ? (int64_t)cy * px + cx : 0;
+    hu[k] = hq[k] ? (int64_t)cy * G.ipy + cx : 0;
+    hx0[k] = cx;
+  }
+  using FS = std::conditional_t<KIND == 0, Tin, std::conditional_t<MODE == 0 || MODE == 3, S, double>>;
+  struct Pre {
+    Q4<FS> rf;
+    Q4<Tin> ri;
+    Q4<S> re;  // MODE 2, 3: the correction e
+    Q4<FS> rh[NHQR];
+    Q4<Tin> rhi[NHQR];
+    Q4<S> rhe[NHQR];
+    Q4<Tin> r1;  // I1 (alpha != 0)
+  };
+  const double es = UPD ? e_scale[t.g] : 0.0;
+  // loads from clamped addresses without branches around them (masked in stash)
+  auto fetch = [&](int q, Pre& o) {
+    const int qc = min(max(q, 0), nz - 1);
+    const Tin* I0q = I0g + qc * G.ipz;
+    const int64_t po = qc * pl;
+    const int64_t oo = v[0] ? own : 0, ou = v[0] ? ownu : 0;
+    if (KIND == 0) {
+      ld_q4(reinterpret_cast<const FS*>(I0q) + ou, o.rf);
+    } else {
+      ld_q4(I0q + ou, o.ri);
+      if (MODE == 0) {
+        ld_q4(reinterpret_cast<const FS*>(Eg) + po + oo, o.rf);
+      } else if (MODE == 3) {
+        ld_q4(Eg + po + oo, o.re);
+      } else {
+        ld_q4(reinterpret_cast<const FS*>(xg) + po + oo, o.rf);
+        if (MODE == 2) ld_q4(Eg + po + oo, o.re);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NHQR; ++k) {
+      if (KIND == 0) ld_q4(reinterpret_cast<const FS*>(I0q) + hu[k], o.rh[k]);
+      else if (MODE == 0) ld_q4(reinterpret_cast<const FS*>(Eg) + po + hg[k], o.rh[k]);
+      else if (MODE == 3) {
+        ld_q4(I0q + hu[k], o.rhi[k]);
+        ld_q4(Eg + po + hg[k], o.rhe[k]);
+      } else {
+        ld_q4(reinterpret_cast<const FS*>(xg) + po + hg[k], o.rh[k]);
+        ld_q4(I0q + hu[k], o.rhi[k]);
+        if (MODE == 2) ld_q4(Eg + po + hg[k], o.rhe[k]);
+      }
+    }
+    if (I1g) ld_q4(I1g + qc * G.ipz + ou, o.r1);
+  };
+  // convert a slot: F (f), I0 (i), I1 (jv) of the quad; store F's plane in LDS
+  double f[4], i4[4], jv[4];
+  auto stash = [&](int q, const Pre& o) {
+    const bool okq = q >= 0 && q < nz;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool m = okq && v[j];
+      i4[j] = (KIND == 1 && m) ? q4_d(o.ri, j) : 0.0;
+      jv[j] = I1g ? q4_d(o.r1, j) : 0.0;
+      if (MODE == 3) f[j] = i4[j];  // x64 = I0 before the first update
+      else f[j] = m ? q4_d(o.rf, j) : 0.0;
+      if (KIND == 1 && UPD) f[j] = m ? __builtin_fma(es, q4_d(o.re, j), f[j]) : f[j];  // as for the halo copies
+    }
+    if (KIND == 1 && UPD && v[0] && q >= q0 && q < q1) {
+      double* xo = x64_out + G.off + q * pl + own;
+      reinterpret_cast<double2*>(xo)[0] = make_double2(f[0], f[1]);
+      reinterpret_cast<double2*>(xo)[1] = make_double2(f[2], f[3]);
+    }
+    if (KIND == 1 && MODE >= 1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) f[j] -= i4[j];
+    }
+    double* P = X[((q % 3) + 3) % 3];
+    reinterpret_cast<double2*>(P + lo)[0] = make_double2(f[0], f[1]);
+    reinterpret_cast<double2*>(P + lo)[1] = make_double2(f[2], f[3]);
+#pragma unroll
+    for (int k = 0; k < NHQR; ++k)
+      if (hs[k]) {
+        double hv4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          double vv = MODE == 3 ? q4_d(o.rhi[k], j) : q4_d(o.rh[k], j);
+          if (KIND == 1 && UPD) vv = __builtin_fma(es, q4_d(o.rhe[k], j), vv);
+          if (KIND == 1 && MODE >= 1) vv -= q4_d(o.rhi[k], j);
+          hv4[j] = (okq && hq[k] && hx0[k] + j < nx) ? vv : 0.0;
+        }
+        reinterpret_cast<double2*>(P + hoff[k])[0] = make_double2(hv4[0], hv4[1]);
+        reinterpret_cast<double2*>(P + hoff[k])[1] = make_double2(hv4[2], hv4[3]);
+      }
+  };
+
+  // registers: F and I0 at k - 1 (m), k (c), k + 1 (p); I1 at k (c) and k + 1 (p)
+  double fm[4], fc[4], fp[4], im[4], ic[4], ip[4], jc[4], jp[4];
+  Pre A, B;
+  fetch(q0 - 1, A);
+  stash(q0 - 1, A);  // plane q0 - 1 goes to the ring slot of q0 + 2, rewritten before it is read
+#pragma unroll
+  for (int j = 0; j < 4; ++j) { fm[j] = f[j]; im[j] = i4[j]; }
+  fetch(q0, A);
+  stash(q0, A);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) { fc[j] = f[j]; ic[j] = i4[j]; jc[j] = jv[j]; }
+  fetch(q0 + 1, A);
+  fetch(q0 + 2, B);
+  double nrm = 0.0, nrm2 = 0.0;  // KIND 0: sum b^2 (canonical) and sum b_corr^2
+  // plane k: slot o holds plane k + 1, refilled with plane k + 3
+  auto iter = [&](int k, Pre& o) {
+    stash(k + 1, o);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { fp[j] = f[j]; ip[j] = i4[j]; jp[j] = jv[j]; }
+    fetch(k + 3, o);
+    __syncthreads();
+    const double* P = X[k % 3];
+    const double wzm = k > 0 ? wz : 0.0, wzp = k < nz - 1 ? wz : 0.0;
+    auto lap = [&](double c, double wl_, double l, double wr_, double rr, double u_, double d_, double zm_,
+                   double zp_) {
+      double s2 = 0.0;
+      s2 += wl_ * (c - l);
+      s2 += wr_ * (c - rr);
+      s2 += wu * (c - u_);
+      s2 += wd * (c - d_);
+      s2 += wzm * (c - zm_);
+      s2 += wzp * (c - zp_);
+      return s2;
+    };
+    const double2 u01 = reinterpret_cast<const double2*>(P + lo - HX)[0];
+    const double2 u23 = reinterpret_cast<const double2*>(P + lo - HX)[1];
+    const double2 d01 = reinterpret_cast<const double2*>(P + lo + HX)[0];
+    const double2 d23 = reinterpret_cast<const double2*>(P + lo + HX)[1];
+    const double uu[4] = {u01.x, u01.y, u23.x, u23.y}, dd[4] = {d01.x, d01.y, d23.x, d23.y};
+    const double lft = P[lo - 1], rgt = P[lo + 4];
+    double r4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double c = fc[j];
+      const double l = j == 0 ? lft : fc[j - 1], rr = j == 3 ? rgt : fc[j + 1];
+      const double lf = lap(c, wl[j], l, wr[j], rr, uu[j], dd[j], fm[j], fp[j]);
+      double lzI = 0.0;  // w_z L_z I0 (stack only)
+      if (cross) {
+        const double i0 = KIND == 0 ? fc[j] : ic[j], im_ = KIND == 0 ? fm[j] : im[j], ip_ = KIND == 0 ? fp[j] : ip[j];
+        lzI += wzm * (i0 - im_);
+        lzI += wzp * (i0 - ip_);
+      }
+      if (KIND == 0) {
+        const double lin = lf - (cross ? lzI : 0.0);  // canonical part of L I0
+        const double bcan = alpha * jc[j] + lin;
+        nrm += v[j] ? bcan * bcan : 0.0;
+        r4[j] = alpha * (jc[j] - c) - lzI;
+        nrm2 += v[j] ? r4[j] * r4[j] : 0.0;
+      } else {
+        r4[j] = alpha * (jc[j] - ic[j] - c) - lf - lzI;
+        nrm += v[j] ? r4[j] * r4[j] : 0.0;
+      }
+    }
+    if (v[0]) {
+      const int64_t vo = G.off + k * pl + own;
+      if (KIND == 0) {
+        const double sc = inv_scale ? inv_scale[t.g] : 1.0;  // a power of two (exact)
+        if (out0) st_q4<S, C>(out0 + vo, (C)(r4[0] * sc), (C)(r4[1] * sc), (C)(r4[2] * sc), (C)(r4[3] * sc));
+        if (out1) st_q4<S, C>(out1 + vo, (C)0, (C)0, (C)0, (C)0);
+      } else if (out0) {
+        const double sc = inv_scale[t.g];
+        st_q4<S, C>(out0 + vo, (C)(r4[0] * sc), (C)(r4[1] * sc), (C)(r4[2] * sc), (C)(r4[3] * sc));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      fm[j] = fc[j]; fc[j] = fp[j];
+      im[j] = ic[j]; ic[j] = ip[j];
+      jc[j] = jp[j];
+    }
   };
   int k = q0;
   for (; k + 1 < q1; k += 2) {
@@ -381,29 +702,27 @@ k_refine_init(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
 }
 
 
-// v *= f[grid] on the cells of a level array (the scale of a right-hand side)
-template <typename S>
-__global__ void __launch_bounds__(256)
-k_scale_level(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
-              S* __restrict__ v, const double* __restrict__ f) {
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
-  const GridDesc& G = grids[t.g];
-  const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
-  if (i >= G.nx || j >= G.ny) return;
-  const int64_t pl = (int64_t)G.px * G.ny;
-  const double c = f[t.g];
-  for (int k = t.z0; k < t.z1; ++k) {
-    S* p = v + G.off + k * pl + (int64_t)j * G.px + i;
-    st64(p, ld64(p) * c);
-  }
-}
-
 // ============================================================ launchers
 
 template <typename TI, typename T1, typename T, int KIND, int MODE>
 static hipError_t corr_stencil_launch2(const Geom& g, const void* I0, const void* I1, const void* E,
                                        const double* x64, void* o0, void* o1, const double* inv_scale,
                                        double* partials, double* x64o, const double* escale, hipStream_t st) {
+  if (g.stencil4) {  // quad form: 3-D grids, I1 of I0's type, the quad table of the level
+    if constexpr (std::is_same_v<TI, T1>) {
+      if (g.row) return hipErrorInvalidValue;
+#define CS4(TX, TY)                                                                                             \
+  hipLaunchKernelGGL((k_corr_stencil4<TI, T, TX, TY, KIND, MODE>), dim3((unsigned)g.nblocks), dim3(TX * TY / 4), 0, \
+                     st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0, (const TI*)I1, (const T*)E, x64,     \
+                     (T*)o0, (T*)o1, inv_scale, partials, x64o, escale)
+      if (g.tile == 0) CS4(128, 8);
+      else CS4(64, 16);
+#undef CS4
+      return hipSuccess;
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (g.row) {
     hipLaunchKernelGGL((k_corr_stencil<TI, T1, T, SWR_TX, 1, KIND, MODE>), dim3((unsigned)g.nblocks),
                        dim3(SWR_TX / 2), 0, st, g.grids, g.block0, g.ngrids, g.zlen, (const TI*)I0, (const T1*)I1,
@@ -437,11 +756,11 @@ static hipError_t corr_stencil_launch(gd_dtype t1, gd_dtype tin, const Geom& g, 
 }
 
 hipError_t launch_rhs_corr(gd_dtype tin, gd_dtype t1, gd_dtype s, const Geom& g, const void* I0, const void* I1,
-                           void* b, void* x, double* partials, hipStream_t st) {
+                           void* b, void* x, double* partials, hipStream_t st, const double* inv_scale) {
   if (g.nblocks == 0) return hipSuccess;
   hipError_t e = hipSuccess;
 #define L2(TI, T) \
-  e = corr_stencil_launch<TI, T, 0, 0>(t1, tin, g, I0, I1, nullptr, nullptr, b, x, nullptr, partials, nullptr, nullptr, st)
+  e = corr_stencil_launch<TI, T, 0, 0>(t1, tin, g, I0, I1, nullptr, nullptr, b, x, inv_scale, partials, nullptr, nullptr, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1
@@ -522,14 +841,6 @@ hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, doubl
   if (g.nblocks == 0) return hipSuccess;
 #define L(T) hipLaunchKernelGGL(k_refine_init<T>, GD_ARGS(g), (const T*)I0, x64)
   GD_DISPATCH_S(tin, L)
-#undef L
-  return last();
-}
-
-hipError_t launch_scale_level(gd_dtype s, const Geom& g, void* v, const double* f, hipStream_t st) {
-  if (g.nblocks == 0) return hipSuccess;
-#define L(T) hipLaunchKernelGGL(k_scale_level<T>, GD_ARGS(g), (T*)v, f)
-  GD_DISPATCH_S(s, L)
 #undef L
   return last();
 }

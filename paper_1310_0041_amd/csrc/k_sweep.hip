@@ -813,12 +813,14 @@ k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
 // ============================================================ launchers
 
 template <typename T, bool FP, bool VEC>
-static void sweep_launch3(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
+static hipError_t sweep_launch3(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
                           hipStream_t st) {
   if (g.row) {
     hipLaunchKernelGGL((k_rb_sweep<T, SWR_TX, 1, FP, VEC>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 2), 0, st,
                        g.grids, g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, (const T*)ec,
                        pmode, g.order);
+  } else if (g.tile >= kPairTiles) {
+    return hipErrorInvalidValue;  // the wide tiles exist in the quad form only
   } else {
 #define SWEEP_TILE(TX, TY)                                                                                     \
   hipLaunchKernelGGL((k_rb_sweep<T, TX, TY, FP, VEC>), dim3((unsigned)g.nblocks), dim3(TX * TY / 2), 0, st,    \
@@ -835,6 +837,7 @@ static void sweep_launch3(const Geom& g, const void* xin, void* xout, const void
     }
 #undef SWEEP_TILE
   }
+  return hipSuccess;
 }
 
 // The quad form for the library's arrays (float compute types), unless
@@ -859,7 +862,9 @@ static void sweep_launch4(const Geom& g, const void* xin, void* xout, const void
       case 0: SWEEP4(64, 8); break;
       case 1: SWEEP4(128, 8); break;
       case 2: SWEEP4(64, 16); break;
-      default: SWEEP4(128, 16); break;
+      case 3: SWEEP4(128, 16); break;
+      case 4: SWEEP4(256, 8); break;
+      default: SWEEP4(256, 12); break;
     }
   }
 #undef SWEEP4
@@ -874,29 +879,33 @@ bool sweep_starts_from_zero_ok(gd_dtype s, const Geom& g) {
   return s != GD_F64 && quad_form(s == GD_F32 ? 4 : 2, g, nullptr);
 }
 
+bool sweep_wide_tiles_ok(gd_dtype s, bool quad) { return s != GD_F64 && quad && quad_on(); }
+
 template <typename T>
-static void sweep_launch(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
-                         bool xzero, hipStream_t st) {
+static hipError_t sweep_launch(const Geom& g, const void* xin, void* xout, const void* b, const void* ec, int pmode,
+                               bool xzero, hipStream_t st) {
   if constexpr (sizeof(T) <= 4) {
     if (quad_form(sizeof(T), g, ec)) {
       if (xzero) sweep_launch4<T, true>(g, xin, xout, b, st);
       else sweep_launch4<T, false>(g, xin, xout, b, st);
-      return;
+      return hipSuccess;
     }
   }
   // the library's arrays are pair-aligned (g.vec); a caller's odd-width arrays are not
-  if (ec) sweep_launch3<T, true, true>(g, xin, xout, b, ec, pmode, st);
-  else if (g.vec) sweep_launch3<T, false, true>(g, xin, xout, b, ec, pmode, st);
-  else sweep_launch3<T, false, false>(g, xin, xout, b, ec, pmode, st);
+  if (ec) return sweep_launch3<T, true, true>(g, xin, xout, b, ec, pmode, st);
+  if (g.vec) return sweep_launch3<T, false, true>(g, xin, xout, b, ec, pmode, st);
+  return sweep_launch3<T, false, false>(g, xin, xout, b, ec, pmode, st);
 }
 
 hipError_t launch_rb_sweep(gd_dtype s, const Geom& g, const void* xin, void* xout, const void* b,
                            const void* ec, int pmode, hipStream_t st, bool xzero) {
   if (g.nblocks == 0) return hipSuccess;
   if (xzero && !sweep_starts_from_zero_ok(s, g)) return hipErrorInvalidValue;
-#define L(T) sweep_launch<T>(g, xin, xout, b, ec, pmode, xzero, st)
+  hipError_t e = hipSuccess;
+#define L(T) e = sweep_launch<T>(g, xin, xout, b, ec, pmode, xzero, st)
   GD_DISPATCH_S(s, L)
 #undef L
+  if (e != hipSuccess) return e;
   return last();
 }
 

@@ -199,6 +199,29 @@ def test_ad_mixed_refinement(gd, storage):
     assert rel(host(I1), ref) <= 1e-6
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("factor", [2.0 ** 10, 2.0 ** -10])
+def test_mixed_refinement_power_of_two_invariant(gd, storage, factor):
+    """16-bit storage with FP64 refinement covers the range of the input:
+    the right-hand side and every refinement residual are scaled by powers
+    of two, so scaling I0 by 2^k scales the AD and SP results by exactly 2^k
+    (bit for bit), for inputs up to 2.6e5 (far beyond FP16's 65504) and
+    down to 2.5e-1."""
+    say("mixed 2^k invariance", storage, factor)
+    st = {"f16": gd.F16, "bf16": gd.BF16}[storage]
+    spec = synth.StackSpec(128, 40, 12, (4.0, 40.0), True, 13100427)
+    I0 = synth.make_stack(spec).to(torch.float32).cuda()
+    kw = dict(storage=st, fp64_refine=1, out_dtype=torch.float32)
+    a1, ra = gd.smooth_z(I0, BETA, **kw)
+    b1, rb = gd.smooth_z(I0 * factor, BETA, **kw)
+    assert ra["refine_steps"] == rb["refine_steps"]
+    assert torch.equal(b1, a1 * factor)
+    a2, ra2, _ = gd.screened_poisson_stack(I0, a1, 0.01, storage=st, fp64_refine=1)
+    b2, rb2, _ = gd.screened_poisson_stack(I0 * factor, b1, 0.01, storage=st, fp64_refine=1)
+    assert ra2["refine_steps"] == rb2["refine_steps"]
+    assert torch.equal(b2, a2 * factor)
+
+
 @pytest.mark.parametrize("shape", [(8, 256, 256), (3, 37, 130), (2, 1, 1)])
 def test_sp_stack_plain_fp32(gd, shape):
     say("SP stack f32", shape)
@@ -366,8 +389,8 @@ def test_deterministic(gd):
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_sweep_tiles_identical(gd, storage):
     """Every relaxation tile computes the same values: the AD and SP results
-    agree bit for bit across the four tile variants (odd sizes, several
-    z-chunks and ragged tile edges)."""
+    agree bit for bit across the six tile variants (the two wide ones in the
+    quad form only; odd sizes, several z-chunks and ragged tile edges)."""
     import synth
 
     spec = synth.StackSpec(203, 77, 37, (4.0, 40.0), True, 13100422)
@@ -377,7 +400,7 @@ def test_sweep_tiles_identical(gd, storage):
     if storage == "f16":
         kw.update(storage=gd.F16, fp64_refine=1)
     outs = []
-    for tile in range(4):
+    for tile in range(6):
         I1, r1 = gd.smooth_z(I0, (1.0, 1.0, 4.0), out_dtype=torch.float32, sweep_tile=tile, **kw)
         I2, r2, _ = gd.screened_poisson_stack(I0, I1, 0.01, sweep_tile=tile, **kw)
         outs.append((I1, I2, r1["cycles"], r2["cycles"]))
@@ -387,12 +410,15 @@ def test_sweep_tiles_identical(gd, storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("shape", [(37, 77, 203), (9, 130, 64), (5, 3, 9), (1, 1, 1), (24, 64, 256)])
+@pytest.mark.parametrize("shape", [(37, 77, 203), (9, 130, 64), (5, 3, 9), (1, 1, 1), (24, 64, 256), (7, 13, 132)])
 def test_sweep_quad_equals_pair(gd, storage, shape):
-    """The quad form of the relaxation (four x cells per thread) gives the
-    pair form's values bit for bit: AD and SP results after a fixed number
-    of cycles, every tile variant of the stack and the slices' row form,
-    on odd sizes, ragged tile edges and several z-chunks."""
+    """The quad forms of the relaxation and of the finest-level stencil
+    passes (four x cells per thread; the stencil passes where the input's
+    width is a multiple of four) give the pair forms' values bit for bit:
+    AD and SP results after a fixed number of cycles, every tile variant of
+    the stack and the slices' row form, on odd sizes, ragged tile edges and
+    several z-chunks.  The residual norms are the same sums taken in another
+    order (equal to 1e-12)."""
     import synth
 
     nz, ny, nx = shape
@@ -409,8 +435,24 @@ def test_sweep_quad_equals_pair(gd, storage, shape):
                                  **kw)
             I2, r2, _ = gd.screened_poisson_stack(I0, I1, 0.01, sweep_tile=tile, sweep_quad=quad, **kw)
             outs.append((I1, I2, r1["cycles"], r2["cycles"], r1["rel_residual"], r2["rel_residual"]))
-        assert outs[0][2:] == outs[1][2:], (tile, outs[0][2:], outs[1][2:])
+        assert outs[0][2:4] == outs[1][2:4], (tile, outs[0][2:], outs[1][2:])
+        for a, b in zip(outs[0][4:], outs[1][4:]):
+            assert abs(a - b) <= 1e-12 * max(abs(a), 1e-300), (tile, a, b)
         assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), tile
+
+
+def test_wide_tiles_need_the_quad_form(gd):
+    """The 256-wide tiles exist in the quad form only: asking for them with
+    FP64 storage or with the pair form is refused before any launch."""
+    I0 = dev(np.random.default_rng(3).uniform(0, 255, (6, 20, 30)))
+    for tile in (4, 5):
+        with pytest.raises(RuntimeError, match="sweep_tile 4 and 5"):
+            gd.smooth_z(I0, BETA, sweep_tile=tile, storage=gd.F64)
+        with pytest.raises(RuntimeError, match="sweep_tile 4 and 5"):
+            gd.smooth_z(I0.float(), BETA, sweep_tile=tile, sweep_quad=0)
+    J, rep = gd.smooth_z(I0.float(), BETA, sweep_tile=4)
+    K, _ = gd.smooth_z(I0.float(), BETA, sweep_tile=0)
+    assert torch.equal(J, K)
 
 
 def test_autotune_choice(gd):
