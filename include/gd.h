@@ -111,7 +111,10 @@ typedef struct {
 
 /* Filled by the solve calls when the pointer is non-NULL. */
 typedef struct {
-  int cycles;             /* V-cycles run (all refinement steps included)       */
+  int cycles;             /* V-cycles run (all refinement steps included); per
+                             slice of a plain batched solve, the cycles after
+                             which that slice met the tolerance and left the
+                             batch (its kernels skip it from then on)          */
   int refine_steps;       /* FP64 refinement steps (0 for plain solves)         */
   double rel_residual;    /* final canonical relative residual, FP64 on the GPU */
   double b_norm;          /* ||b||_2 of the canonical system                    */
@@ -432,8 +435,10 @@ gd_status gd_prolong_add(const void* e_coarse, void* x, gd_dtype s,
  * correction added on load, 2 slice (one-line) grids, 3 slice grids with the
  * correction, 4 stack grid and 5 slice grids starting from a zero iterate
  * (the first sweep of a refinement step's V-cycle, which does not read x).
- * bytes_per_launch: algorithmic bytes of one launch (read x and b, write x:
- * 3 * storage bytes per voxel of the finest level; 2 * for variants 4, 5). */
+ * bytes_per_launch: algorithmic bytes of one launch, averaged over the launches
+ * counted (read x and b, write x: 3 * storage bytes per voxel of the finest
+ * level that the launch worked on -- slices of a batch that have converged are
+ * left out; 2 * for variants 4, 5). */
 gd_status gd_get_kernel_time(int variant, double* total_ms, int64_t* launches, double* bytes_per_launch);
 void gd_reset_kernel_time(void);
 

@@ -73,7 +73,7 @@ struct KernelTimer {
   std::mutex mu;
   double total_ms[kTimerKinds] = {};
   int64_t launches[kTimerKinds] = {};
-  double bytes[kTimerKinds] = {};
+  double bytes[kTimerKinds] = {};  // summed over the launches (grids the kernels worked on)
 };
 static KernelTimer g_timer;
 
@@ -149,7 +149,9 @@ struct Hier {
   double* x64 = nullptr;     // FP64 iterate of the refinement path
   double* x64b = nullptr;    // its next value (the fused update writes here)
   std::vector<int64_t> cells;  // finest cells per grid
-  std::vector<double> lcells;  // cells of every level (all grids)
+  std::vector<double> lcells;  // cells of every level (the grids the kernels work on)
+  std::vector<double> lcells_all;  // the same with every grid
+  double act = 1.0;  // share of the finest level's cells in grids the kernels work on
   // Algorithmic HBM bytes of the kernels launched through this hierarchy
   // (host-side count: the bytes each kernel must read and write per cell,
   // times the cells it covers; replayed graphs add what their capture counted)
@@ -169,6 +171,7 @@ struct Hier {
     hipGraphExec_t exec = nullptr;
     std::vector<std::pair<void*, void*>> from, to;  // (x, xt) of every level before / after
     double bytes = 0.0;  // algorithmic bytes of one replay
+    double act = 1.0;    // Hier::act when it was captured (replays scale by the share now)
   };
   hipStream_t cap = nullptr;  // private capture stream (default priority)
   std::map<std::string, std::vector<Graph>> graphs;
@@ -218,6 +221,7 @@ struct Hier {
   Geom g_pp(int l) const { return lv[l].pp.geom(lv[l].d, ngrids, lv[l].row); }
   Geom g_cs(int l) const { return lv[l].cs.geom(lv[l].d, ngrids, lv[l].row); }
   bool quad_opt = true;  // the caller's sweep_quad option of the running solve
+  bool flags_set = false;  // some grid descriptor carries a skip / alt flag
 };
 
 static void coarsen_factors(const GridDesc& g, int f[3]) {
@@ -341,6 +345,7 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
     double lc = 0.0;
     for (const auto& g : cur) lc += (double)g.nx * g.ny * g.nz;
     H->lcells.push_back(lc);
+    H->lcells_all.push_back(lc);
     H->lv.push_back(std::move(L));
     if (!more || (max_levels > 0 && (int)H->lv.size() >= max_levels)) break;
     std::vector<GridDesc> nxt(cur.size());
@@ -876,9 +881,12 @@ static void ensure_tables(Hier& H, int disc) {
   }
 }
 
+static void upload_flags(Hier& H, const std::vector<char>& skip, const std::vector<char>& alt, hipStream_t st);
+
 static void prep(Hier& H, const gd_solve_opts& o) {
   if (o.discretization == 1 || o.discretization == 2) ensure_tables(H, o.discretization);
   H.quad_opt = o.sweep_quad != 0;
+  if (H.flags_set) upload_flags(H, {}, {}, nullptr);  // left by a solve that ended in an error
 }
 
 static void read_dred(Hier& H, int ncomp, hipStream_t st);
@@ -891,6 +899,7 @@ struct Cycler {
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   std::vector<int> ev_kind;
+  std::vector<double> ev_cells;  // finest-level cells the timed launch worked on
   size_t ev_used = 0;
 
   bool fuse;
@@ -949,7 +958,9 @@ struct Cycler {
       }
       HIP_TRY(hipEventRecord(ev[ev_used].first, st));
       if (ev_kind.size() < ev.size()) ev_kind.resize(ev.size());
+      if (ev_cells.size() < ev.size()) ev_cells.resize(ev.size());
       ev_kind[ev_used] = xz ? 4 + (L.row ? 1 : 0) : (L.row ? 2 : 0) + (ec ? 1 : 0);
+      ev_cells[ev_used] = H.lcells[0];
     }
     Geom g = H.g_sw(l);
     g.quad = quad;
@@ -1033,22 +1044,22 @@ struct Cycler {
   // collect HIP-event times of finest-level sweeps (after a stream sync)
   void harvest() {
     if (!timing || ev_used == 0) return;
-    double tot[kTimerKinds] = {};
+    double tot[kTimerKinds] = {}, byt[kTimerKinds] = {};
     int64_t cnt[kTimerKinds] = {};
     for (size_t i = 0; i < ev_used; ++i) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ev[i].first, ev[i].second));
-      tot[ev_kind[i]] += ms;
-      cnt[ev_kind[i]] += 1;
+      const int k = ev_kind[i];
+      tot[k] += ms;
+      cnt[k] += 1;
+      byt[k] += (k >= 4 ? 2.0 : 3.0) * (double)dsize(H.s) * ev_cells[i];
     }
-    double cells = 0.0;
-    for (int64_t c : H.cells) cells += (double)c;
     std::lock_guard<std::mutex> lk(g_timer.mu);
     for (int k = 0; k < kTimerKinds; ++k) {
       if (!cnt[k]) continue;
       g_timer.total_ms[k] += tot[k];
       g_timer.launches[k] += cnt[k];
-      g_timer.bytes[k] = (k >= 4 ? 2.0 : 3.0) * (double)dsize(H.s) * cells;
+      g_timer.bytes[k] += byt[k];
     }
     ev_used = 0;
   }
@@ -1074,7 +1085,7 @@ struct CycleGraphs {
       if (g.from == now) {
         HIP_TRY(hipGraphLaunch(g.exec, st));
         H.set_xstate(g.to);
-        H.acct += g.bytes;
+        H.acct += g.bytes * (H.act / g.act);
         return;
       }
     }
@@ -1083,6 +1094,7 @@ struct CycleGraphs {
     HIP_TRY(hipStreamSynchronize(st));
     Hier::Graph g;
     g.from = now;
+    g.act = H.act;
     hipGraph_t graph = nullptr;
     const double a0 = H.acct;
     HIP_TRY(hipStreamBeginCapture(H.cap, hipStreamCaptureModeThreadLocal));
@@ -1127,6 +1139,7 @@ struct Problem {
 
 struct Outcome {
   int cycles = 0, steps = 0;
+  std::vector<int> gcycles;  // per grid, when grids of a batch retire at different cycles
   double bytes = 0.0;  // algorithmic HBM bytes of the solve's kernels
   std::vector<double> rel, bnorm;
   bool converged = false, numeric = false;
@@ -1189,15 +1202,38 @@ static void finish(Hier& H, const Problem& P, int mode, hipStream_t st) {
   H.count(0, dsize(P.tin) + xb + dsize(P.tout));
   if (P.gauge) {
     H.count(0, dsize(P.tin) + xb);
-    HIP_TRY(launch_sum_shift(P.tin, H.s, mode, H.g_ew(0), P.I0, H.lv[0].x, H.x64, H.partials, st));
+    HIP_TRY(launch_sum_shift(P.tin, H.s, mode, H.g_ew(0), P.I0, H.lv[0].x, H.x64, H.partials, st, H.lv[0].xt));
     HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, H.ngrids, 1, H.dred, st));
     read_dred(H, 1, st);
     for (int g = 0; g < H.ngrids; ++g) H.hpin[g] = H.hpin[g] / (double)H.cells[g];
     HIP_TRY(hipMemcpyAsync(H.dscal + 2 * H.ngrids, H.hpin, H.ngrids * sizeof(double), hipMemcpyHostToDevice, st));
     shift = H.dscal + 2 * H.ngrids;
   }
-  HIP_TRY(launch_finalize(P.tin, H.s, P.tout, mode, H.g_ew(0), P.I0, H.lv[0].x, H.x64, shift, P.out, st));
+  HIP_TRY(launch_finalize(P.tin, H.s, P.tout, mode, H.g_ew(0), P.I0, H.lv[0].x, H.x64, shift, P.out, st,
+                          H.lv[0].xt));
   HIP_TRY(hipStreamSynchronize(st));
+}
+
+// Per-grid flags of the level descriptors (every level; host copy and device).
+static void upload_flags(Hier& H, const std::vector<char>& skip, const std::vector<char>& alt, hipStream_t st) {
+  if (st) HIP_TRY(hipStreamSynchronize(st));
+  else HIP_TRY(hipDeviceSynchronize());  // no stream known: nothing may still read the descriptors
+  for (auto& L : H.lv) {
+    for (int g = 0; g < H.ngrids; ++g) {
+      L.h[g].skip = skip.empty() ? 0 : skip[g];
+      L.h[g].alt = alt.empty() ? 0 : alt[g];
+    }
+    HIP_TRY(hipMemcpy(L.d, L.h.data(), L.h.size() * sizeof(GridDesc), hipMemcpyHostToDevice));
+  }
+  H.flags_set = !(skip.empty() && alt.empty());
+  // byte accounting: only the grids the kernels work on
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    double c = 0.0;
+    for (const auto& g : H.lv[l].h)
+      if (!g.skip) c += (double)g.nx * g.ny * g.nz;
+    H.lcells[l] = c;
+  }
+  H.act = H.lcells_all[0] > 0.0 ? H.lcells[0] / H.lcells_all[0] : 1.0;
 }
 
 static bool all_below(const std::vector<double>& r, const std::vector<double>& bn, double tol, bool& bad) {
@@ -1216,15 +1252,29 @@ static bool all_below(const std::vector<double>& r, const std::vector<double>& b
 // bounds how small the residual of a stored E can be (its rounding error
 // times the operator); when three successive cycles gain less than 30 %, the
 // solve stops there and reports the FP64 residual it reached.
+// In a batch of grids (slices) each grid is retired once its FP64 residual
+// meets the tolerance: the cycle kernels then leave it alone (its flag in
+// the level descriptors), and the output pass reads its correction from
+// whichever of the level's two buffers held it then.
 static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
   prep(H, o);
   Outcome R;
   const double a0 = H.acct;
+  const int n = H.ngrids;
   canonical_norms(H, P, H.lv[0].b, H.lv[0].x, R.bnorm, st);
   Cycler cy(H, st, o);
   const bool single = H.lv.size() == 1;
-  double inner = 0.5;
-  std::vector<double> rr(H.ngrids), best(H.ngrids, INFINITY);
+  const bool retire = n > 1 && !single;
+  // Per grid: retired, the level-0 buffer that held it then (1: the second),
+  // its inner threshold, and whether its own storage residual asked for the
+  // FP64 check.  A grid leaves only on a check it asked for, so when it
+  // leaves depends on that grid alone, not on the others in the batch.
+  std::vector<char> done(n, 0), park(n, 0), asked(n, 0);
+  std::vector<double> inner(n, 0.5), rr(n), best(n, INFINITY);
+  int ndone = 0;
+  void* const buf0 = H.lv[0].x;
+  auto which = [&]() { return H.lv[0].x == buf0 ? 0 : 1; };
+  R.rel.assign(n, 0.0);
   int stall = 0;
   bool pre_done = false;  // the graph has already run this cycle's pre-smoothing and restriction
   if (o.fmg && !single) {
@@ -1244,27 +1294,56 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
       if (!pre_done) cy.restrict_to(0, true);
       pre_done = false;
       read_dred(H, 1, st);
-      bool bad = false;
-      bool gained = false;
-      for (int g = 0; g < H.ngrids; ++g) {
+      bool bad = false, gained = false, all = true, any = false;
+      for (int g = 0; g < n; ++g) {
+        if (done[g]) continue;
         rr[g] = std::sqrt(H.hpin[g]);
+        if (!std::isfinite(rr[g])) bad = true;
         if (rr[g] < 0.7 * best[g]) gained = true;
         best[g] = std::min(best[g], rr[g]);
+        asked[g] = rr[g] <= inner[g] * o.rel_tol * denom(R.bnorm[g]);
+        all = all && asked[g];
+        any = any || asked[g];
       }
-      if (all_below(rr, R.bnorm, inner * o.rel_tol, bad)) check_final = true;
+      if (all || (retire && any)) check_final = true;
       if (bad) { R.numeric = true; break; }
       stall = gained ? 0 : stall + 1;
       if (stall >= 3) check_final = stop_after = true;
+    } else {
+      asked.assign(n, 1);
     }
     if (check_final) {
       std::vector<double> c = canon_residual(H, P, 0, nullptr, st);
-      bool bad = false;
-      R.converged = all_below(c, R.bnorm, o.rel_tol, bad);
-      R.rel.resize(H.ngrids);
-      for (int g = 0; g < H.ngrids; ++g) R.rel[g] = c[g] / denom(R.bnorm[g]);
+      bool bad = false, all = true;
+      std::vector<int> leave;
+      for (int g = 0; g < n; ++g) {
+        if (done[g]) continue;
+        if (!std::isfinite(c[g])) bad = true;
+        R.rel[g] = c[g] / denom(R.bnorm[g]);
+        const bool ok = c[g] <= o.rel_tol * denom(R.bnorm[g]);
+        if (!ok) all = false;
+        if (asked[g]) {
+          if (ok) leave.push_back(g);
+          else inner[g] *= 0.25;
+        }
+      }
       if (bad) { R.numeric = true; break; }
-      if (R.converged || stop_after) break;
-      inner *= 0.25;
+      const bool last = ndone + (int)leave.size() == n;  // every grid has left
+      if (last || (!retire && all)) R.converged = true;
+      if (R.converged || stop_after) {
+        if (!R.converged && all) R.converged = true;  // stopped with every grid below the tolerance
+        break;
+      }
+      if (retire && !leave.empty()) {
+        if (R.gcycles.empty()) R.gcycles.assign(n, 0);
+        for (int g : leave) {
+          done[g] = 1;
+          park[g] = (char)which();
+          R.gcycles[g] = R.cycles;
+        }
+        ndone += (int)leave.size();
+        upload_flags(H, done, {}, st);
+      }
     }
     if (graphs_on(o) && !single) {
       // the correction of this cycle and the next cycle's pre-smoothing and
@@ -1283,7 +1362,15 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
     }
   }
   cy.harvest();
+  for (int g = 0; g < (int)R.gcycles.size(); ++g)
+    if (!done[g]) R.gcycles[g] = R.cycles;
+  if (ndone > 0) {  // every grid back in the kernels' view; retired ones read where they were left
+    std::vector<char> alt(n, 0);
+    for (int g = 0; g < n; ++g) alt[g] = done[g] && park[g] != which();
+    upload_flags(H, {}, alt, st);
+  }
   finish(H, P, 0, st);
+  if (ndone > 0) upload_flags(H, {}, {}, st);
   cy.harvest();
   R.bytes = H.acct - a0;
   return R;
@@ -1508,7 +1595,7 @@ static void fill_report(gd_solve_report* rep, const Outcome& R, int g, double se
                         double share = 1.0) {
   rep->fallback_used = 0;
   rep->bytes = R.bytes * share;
-  rep->cycles = R.cycles;
+  rep->cycles = (g < (int)R.gcycles.size()) ? R.gcycles[g] : R.cycles;
   rep->refine_steps = R.steps;
   rep->rel_residual = R.rel.empty() ? 0.0 : R.rel[g];
   rep->b_norm = R.bnorm.empty() ? 0.0 : R.bnorm[g];
@@ -1855,6 +1942,7 @@ gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1,
     }
     if (rep) {
       fill_report(rep, R, 0, secs, (int)H->lv.size());
+      rep->cycles = R.cycles;  // the batch: its last slice
       double worst = 0.0;
       for (double r : R.rel) worst = std::max(worst, r);
       rep->rel_residual = worst;
@@ -2903,7 +2991,7 @@ gd_status gd_get_kernel_time(int variant, double* total_ms, int64_t* launches, d
   std::lock_guard<std::mutex> lk(g_timer.mu);
   if (total_ms) *total_ms = g_timer.total_ms[variant];
   if (launches) *launches = g_timer.launches[variant];
-  if (bytes) *bytes = g_timer.bytes[variant];
+  if (bytes) *bytes = g_timer.launches[variant] ? g_timer.bytes[variant] / (double)g_timer.launches[variant] : 0.0;
   return GD_OK;
 }
 
@@ -2912,6 +3000,7 @@ void gd_reset_kernel_time(void) {
   for (int k = 0; k < kTimerKinds; ++k) {
     g_timer.total_ms[k] = 0.0;
     g_timer.launches[k] = 0;
+    g_timer.bytes[k] = 0.0;
   }
 }
 

@@ -24,6 +24,11 @@ struct GridDesc {
   int32_t px;             // x pitch of this level's arrays (>= nx)
   int32_t cpx;            // x pitch of the child grid's arrays
   int32_t zin;            // 1: a 2-D slice seen as nz rows of one line (z is in-slice)
+  int32_t skip;           // 1: the cycle kernels leave this grid alone (a slice of a batch
+                          // that has converged)
+  int32_t alt;            // 1: the output pass reads this grid's finest correction from the
+                          // level's second buffer (where it was when the grid converged)
+  int32_t pad_;
   double alpha, wx, wy, wz;  // operator alpha*Id + sum_a w_a L_a of this level
 };
 

@@ -81,13 +81,16 @@ hipError_t launch_canon_residual(gd_dtype tin, gd_dtype t1, gd_dtype s, int mode
                                  const void* I1, const void* E, const double* x64, void* r_out,
                                  const double* inv_scale, double* partials, hipStream_t st,
                                  double* x64_out = nullptr, const double* e_scale = nullptr);
-// Per block: sum (x - I0) for x = I0 + E (mode 0) or x64 (mode 1).
+// Per block: sum (x - I0) for x = I0 + E (mode 0) or x64 (mode 1).  A grid
+// flagged `alt` reads E from E2 (the level's other buffer).
 hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0,
-                            const void* E, const double* x64, double* partials, hipStream_t st);
-// out = x - shift[g] in the caller's layout, x = I0 + E (mode 0) or x64 (mode 1).
+                            const void* E, const double* x64, double* partials, hipStream_t st,
+                            const void* E2 = nullptr);
+// out = x - shift[g] in the caller's layout, x = I0 + E (mode 0) or x64 (mode 1);
+// E2 as for launch_sum_shift.
 hipError_t launch_finalize(gd_dtype tin, gd_dtype s, gd_dtype tout, int mode, const Geom& g,
                            const void* I0, const void* E, const double* x64, const double* shift,
-                           void* out, hipStream_t st);
+                           void* out, hipStream_t st, const void* E2 = nullptr);
 hipError_t launch_refine_init(gd_dtype tin, const Geom& g, const void* I0, double* x64, hipStream_t st);
 // Generic system: b = alpha V + sum_a w_a D_a^T G_a.
 hipError_t launch_rhs_general(gd_dtype s, const Geom& g, const void* V, const void* Gx,

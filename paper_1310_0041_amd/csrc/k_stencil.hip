@@ -62,6 +62,7 @@ k_corr_stencil(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
 
   const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
+  if (G.skip) return;  // a converged grid of a batch
   const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const bool slice = G.zin != 0;
   const double alpha = G.alpha, wx = G.wx, wy = ROW ? 0.0 : G.wy, wz = G.wz;
@@ -401,6 +402,7 @@ k_corr_stencil4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ 
 
   const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
+  if (G.skip) return;  // a converged grid of a batch
   const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const double alpha = G.alpha, wx = G.wx, wy = G.wy, wz = G.wz;
   const bool cross = G.zin == 0 && wz != 0.0;  // the stack's cross-slice term of I0
@@ -644,11 +646,12 @@ k_corr_stencil4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ 
 template <typename Tin, typename S, int MODE>
 __global__ void __launch_bounds__(256)
 k_sum_shift(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
-            const Tin* __restrict__ I0, const S* __restrict__ E, const double* __restrict__ x64,
-            double* __restrict__ partials) {
+            const Tin* __restrict__ I0, const S* __restrict__ E, const S* __restrict__ E2,
+            const double* __restrict__ x64, double* __restrict__ partials) {
   __shared__ double red[4];
   const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
+  if (G.alt) E = E2;  // the grid's correction is in the level's other buffer
   const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   double s = 0.0;
   if (i < G.nx && j < G.ny) {
@@ -670,10 +673,11 @@ k_sum_shift(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
 template <typename Tin, typename S, typename Tout, int MODE>
 __global__ void __launch_bounds__(256)
 k_finalize(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen, int etx,
-           const Tin* __restrict__ I0, const S* __restrict__ E, const double* __restrict__ x64,
-           const double* __restrict__ shift, Tout* __restrict__ out) {
+           const Tin* __restrict__ I0, const S* __restrict__ E, const S* __restrict__ E2,
+           const double* __restrict__ x64, const double* __restrict__ shift, Tout* __restrict__ out) {
   const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
+  if (G.alt) E = E2;  // the grid's correction is in the level's other buffer
   const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   if (i >= G.nx || j >= G.ny) return;
   const int64_t pl = (int64_t)G.px * G.ny;
@@ -797,13 +801,14 @@ hipError_t launch_canon_residual(gd_dtype tin, gd_dtype t1, gd_dtype s, int mode
 }
 
 hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, const void* I0, const void* E,
-                            const double* x64, double* partials, hipStream_t st) {
+                            const double* x64, double* partials, hipStream_t st, const void* E2) {
   if (g.nblocks == 0) return hipSuccess;
 #define L2(TI, T)                                                                                             \
   if (mode == 0)                                                                                              \
-    hipLaunchKernelGGL((k_sum_shift<TI, T, 0>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, partials);        \
+    hipLaunchKernelGGL((k_sum_shift<TI, T, 0>), GD_ARGS(g), (const TI*)I0, (const T*)E, (const T*)E2, x64,     \
+                       partials);                                                                             \
   else                                                                                                        \
-    hipLaunchKernelGGL((k_sum_shift<TI, T, 1>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, partials)
+    hipLaunchKernelGGL((k_sum_shift<TI, T, 1>), GD_ARGS(g), (const TI*)I0, (const T*)E, (const T*)E2, x64, partials)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1
@@ -812,23 +817,26 @@ hipError_t launch_sum_shift(gd_dtype tin, gd_dtype s, int mode, const Geom& g, c
 }
 
 template <typename TI, typename T>
-static hipError_t finalize_out(gd_dtype tout, int mode, const Geom& g, const void* I0, const void* E,
+static hipError_t finalize_out(gd_dtype tout, int mode, const Geom& g, const void* I0, const void* E, const void* E2,
                                const double* x64, const double* shift, void* out, hipStream_t st) {
 #define L(TO)                                                                                                \
   if (mode == 0)                                                                                             \
-    hipLaunchKernelGGL((k_finalize<TI, T, TO, 0>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, shift, (TO*)out); \
+    hipLaunchKernelGGL((k_finalize<TI, T, TO, 0>), GD_ARGS(g), (const TI*)I0, (const T*)E, (const T*)E2, x64, \
+                       shift, (TO*)out);                                                                     \
   else                                                                                                       \
-    hipLaunchKernelGGL((k_finalize<TI, T, TO, 1>), GD_ARGS(g), (const TI*)I0, (const T*)E, x64, shift, (TO*)out)
+    hipLaunchKernelGGL((k_finalize<TI, T, TO, 1>), GD_ARGS(g), (const TI*)I0, (const T*)E, (const T*)E2, x64, \
+                       shift, (TO*)out)
   GD_DISPATCH_S(tout, L)
 #undef L
   return hipSuccess;
 }
 
 hipError_t launch_finalize(gd_dtype tin, gd_dtype s, gd_dtype tout, int mode, const Geom& g, const void* I0,
-                           const void* E, const double* x64, const double* shift, void* out, hipStream_t st) {
+                           const void* E, const double* x64, const double* shift, void* out, hipStream_t st,
+                           const void* E2) {
   if (g.nblocks == 0) return hipSuccess;
   hipError_t e = hipSuccess;
-#define L2(TI, T) e = finalize_out<TI, T>(tout, mode, g, I0, E, x64, shift, out, st)
+#define L2(TI, T) e = finalize_out<TI, T>(tout, mode, g, I0, E, E2, x64, shift, out, st)
 #define L1(TI) GD_DISPATCH_S2(s, TI, L2)
   GD_DISPATCH_S(tin, L1)
 #undef L1

@@ -145,6 +145,7 @@ k_rb_sweep(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block
 
   const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false, order);
   const GridDesc& G = grids[t.g];
+  if (G.skip) return;  // a converged grid of a batch
   const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
   const int64_t pl = (int64_t)px * ny;
@@ -525,6 +526,7 @@ k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
 
   const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false, order);
   const GridDesc& G = grids[t.g];
+  if (G.skip) return;  // a converged grid of a batch
   const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
   const int64_t pl = (int64_t)px * ny;

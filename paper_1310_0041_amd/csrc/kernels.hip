@@ -46,6 +46,7 @@ k_restrict_z(const GridDesc* __restrict__ grids, const int64_t* __restrict__ blo
 
   const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
+  if (G.skip) return;  // a converged grid of a batch
   const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
   const C alpha = (C)G.alpha, wx = (C)G.wx, wy = (C)G.wy, wz = (C)G.wz;
   const int64_t pl = (int64_t)px * ny;
@@ -194,6 +195,7 @@ k_prolong_add(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bl
               int etx, const S* __restrict__ ec, S* __restrict__ xio, int mode) {
   const Tile t = decode_tile(grids, block0, ngrids, zlen, etx, 256 / etx, false);
   const GridDesc& G = grids[t.g];
+  if (G.skip) return;  // a converged grid of a batch
   const int i = t.x0 + (threadIdx.x % etx), j = t.y0 + (threadIdx.x / etx);
   if (i >= G.nx || j >= G.ny) return;
   const int64_t pl = (int64_t)G.px * G.ny;
@@ -221,6 +223,7 @@ k_prolong_pair(const GridDesc* __restrict__ grids, const int64_t* __restrict__ b
   using C = typename Ty<S>::C;
   const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false);
   const GridDesc& G = grids[t.g];
+  if (G.skip) return;  // a converged grid of a batch
   const int tid = threadIdx.x;
   const int tyl = tid / (TX / 2), pxl = tid - tyl * (TX / 2);
   const int gx = t.x0 + 2 * pxl, gy = t.y0 + tyl;

@@ -133,13 +133,15 @@ def _sp_slice_errors(gd, meta, I2, idx):
 
 def test_slices2048_full_all_slices(gd):
     """The 2048 uneven slices of the batched workload, solved as bench.py
-    solves them (one batched solve, FP32, V(1,2)) to 2e-7 per slice, so that
-    the error bar of 1e-5 holds; every slice against the FP64 DCT oracle of
-    its own system."""
+    solves them (one batched solve, FP32, V(1,2)) to 5e-8 per slice (each
+    slice leaves the batch at its own tolerance, and the smoothest modes of
+    the small-alpha slices amplify the residual about 100 times), so that the
+    error bar of 1e-5 holds; every slice against the FP64 DCT oracle of its
+    own system."""
     say("slices2048 full batch, every slice vs DCT")
     meta = synth.make_slice_batch(device="cuda", dtype=torch.float32)
     descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
-    I2, rep, per = gd.screened_poisson_slices(meta["I0"], meta["I1"], descs, rel_tol=2e-7, pre_smooth=1,
+    I2, rep, per = gd.screened_poisson_slices(meta["I0"], meta["I1"], descs, rel_tol=5e-8, pre_smooth=1,
                                               post_smooth=2, check=False)
     print("batch", {k: rep[k] for k in ("cycles", "rel_residual", "status")}, flush=True)
     res = np.array([p["rel_residual"] for p in per])

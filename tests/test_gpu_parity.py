@@ -229,9 +229,12 @@ def test_sp_stack_plain_fp32(gd, shape):
     rng = np.random.default_rng(4)
     I0 = host(dev(rng.uniform(0, 255, shape)))
     I1 = host(dev(I0 + rng.uniform(-20, 20, (nz, 1, 1)) + rng.standard_normal(shape)))
-    I2, rep, per = gd.screened_poisson_stack(dev(I0), dev(I1), 0.01)
-    assert rep["rel_residual"] <= 1e-6
-    assert all(p["rel_residual"] <= 1e-6 for p in per)
+    # each slice stops once it meets the tolerance; the error bar of 1e-5
+    # needs its residual well below 1e-6 on this white-noise input (its
+    # smoothest modes amplify the residual about 150 times)
+    I2, rep, per = gd.screened_poisson_stack(dev(I0), dev(I1), 0.01, rel_tol=5e-8)
+    assert rep["rel_residual"] <= 5e-8
+    assert all(p["rel_residual"] <= 5e-8 for p in per)
     assert rel(host(I2), osv.sp_dct(I0, I1, 0.01)) <= 1e-5
 
 
@@ -253,8 +256,55 @@ def test_sp_batched_uneven_slices(gd):
         s1 = a1[o:o + w * h].reshape(1, h, w)
         alpha = float(np.float32(meta["alpha"][i]))
         ref = osv.sp_dct(s0, s1, alpha)
-        assert rel(out[o:o + w * h].reshape(1, h, w), ref) <= 1e-5, i
+        # each slice stops once it meets the tolerance; the operator's smallest
+        # eigenvalue is alpha, so ||x - x*|| <= ||r|| / alpha bounds the error
+        bnorm = np.linalg.norm(og.rhs_sp(s0, s1, alpha))
+        bar = max(1e-5, 1.01 * per[i]["rel_residual"] * bnorm / (alpha * np.linalg.norm(ref)))
+        assert rel(out[o:o + w * h].reshape(1, h, w), ref) <= bar, i
         assert per[i]["rel_residual"] <= 1e-6
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_sp_batch_retires_converged_slices(gd, use_graph):
+    """A batch whose slices converge at very different rates (alpha 0.5 next
+    to 0.001): each slice leaves the cycle once its FP64 residual meets the
+    tolerance, its result stays where it was (whichever of the level's two
+    buffers held it) and matches the DCT; the per-slice reports give the
+    cycle at which each slice left (fewer for the fast ones); a second call on
+    the cached hierarchy returns the same bits (the flags are cleared)."""
+    say("SP batch retire", use_graph)
+    meta = synth.make_slice_batch(nslices=12, lo=40, hi=260, seed=91, dtype=torch.float32)
+    alpha = np.where(np.arange(12) % 3 == 0, 0.5, np.where(np.arange(12) % 3 == 1, 0.02, 0.001))
+    descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], alpha)
+    I0, I1 = meta["I0"].cuda(), meta["I1"].cuda()
+    I2, rep, per = gd.screened_poisson_slices(I0, I1, descs, use_graph=use_graph)
+    assert rep["rel_residual"] <= 1e-6
+    res = np.array([p["rel_residual"] for p in per])
+    assert (res <= 1e-6).all()
+    a0 = meta["I0"].double().numpy()
+    a1 = meta["I1"].double().numpy()
+    out = host(I2)
+    for i in range(12):
+        o, w, h = meta["offset"][i], meta["w"][i], meta["h"][i]
+        s0, s1 = a0[o:o + w * h].reshape(1, h, w), a1[o:o + w * h].reshape(1, h, w)
+        al = float(np.float32(alpha[i]))
+        ref = osv.sp_dct(s0, s1, al)
+        # error bound from the slice's own residual: ||x - x*|| <= ||r|| / alpha
+        bar = max(1e-5, 1.01 * res[i] * np.linalg.norm(og.rhs_sp(s0, s1, al)) / (al * np.linalg.norm(ref)))
+        assert rel(out[o:o + w * h].reshape(1, h, w), ref) <= bar, i
+    # the fast slices (alpha 0.5) left the batch while the slow ones went on
+    cyc = np.array([p["cycles"] for p in per])
+    assert cyc.max() == rep["cycles"] and cyc[0::3].max() < cyc.max() and cyc[0::3].max() <= cyc[2::3].min(), cyc
+    J2, rep2, per2 = gd.screened_poisson_slices(I0, I1, descs, use_graph=use_graph)
+    assert torch.equal(I2, J2) and rep2["cycles"] == rep["cycles"]
+    # a slice's result does not depend on the rest of the batch: the slow
+    # slices alone give the same bits
+    k = np.arange(2, 12, 3)
+    sub = gd.make_slice_descs(meta["offset"][k], meta["w"][k], meta["h"][k], alpha[k])
+    K2, _, perk = gd.screened_poisson_slices(I0, I1, sub, use_graph=use_graph, out=torch.zeros_like(I0))
+    for j, i in enumerate(k):
+        o, w, h = meta["offset"][i], meta["w"][i], meta["h"][i]
+        assert torch.equal(K2[o:o + w * h], I2[o:o + w * h]) and perk[j]["cycles"] == per[i]["cycles"]
 
 
 def test_sp_batched_mixed_bf16(gd):
@@ -292,7 +342,8 @@ def test_sp_batched_wider_target_and_output(gd, tin, t1, tout, storage, refine):
     I1 = (meta["I1"] + 0.123456789).to(t1).cuda()  # digits beyond I0's precision
     descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
     st = {"bf16": gd.BF16, "f16": gd.F16, "f32": gd.F32, "f64": gd.F64}[storage]
-    tol = 2e-7
+    # (plain FP64 storage: each slice stops at its tolerance, so the 1e-6 error bar needs a tight one)
+    tol = 2e-7 if refine else 1e-9
     I2, rep, per = gd.screened_poisson_slices(I0, I1, descs, storage=st, fp64_refine=refine, rel_tol=tol,
                                               out_dtype=tout)
     assert I2.dtype == tout and rep["rel_residual"] <= tol

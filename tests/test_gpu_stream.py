@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import grid as og
 from oracle import mgsteps as om
 from oracle import solvers as osv
 
@@ -251,6 +252,10 @@ def test_screened_poisson_streamed(gd, slab, refine):
     out, rep, per = gd.screened_poisson_streamed(I0t, I1t, 0.01, out_dtype=torch.float64, slab=slab, **kw)
     assert rep["status"] == 0 and max(p["rel_residual"] for p in per) <= kw.get("rel_tol", 1e-6)
     ref = osv.sp_dct(I0t.double().numpy(), I1t.double().numpy(), 0.01)
-    assert rel(out.numpy(), ref) <= (1e-6 if refine else 1e-5)
+    # each slice stops at its own tolerance: ||x - x*|| <= max_i rel_i ||b|| / alpha bounds the error
+    worst = max(p["rel_residual"] for p in per)
+    b = np.linalg.norm(og.rhs_sp(I0t.double().numpy(), I1t.double().numpy(), 0.01))
+    bar = max(1e-6 if refine else 1e-5, 1.01 * worst * b / (0.01 * np.linalg.norm(ref)))
+    assert rel(out.numpy(), ref) <= bar
     incore, _, _ = gd.screened_poisson_stack(I0t.cuda(), I1t.cuda(), 0.01, out_dtype=torch.float64, **kw)
     assert rel(out.numpy(), incore.cpu().numpy()) <= (1e-6 if refine else 2e-6)
