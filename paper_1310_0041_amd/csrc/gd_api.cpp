@@ -100,6 +100,34 @@ static int sweep_order_env() {
   return v;
 }
 
+// The quad relaxation of a one-grid 3-D level runs as two launches, its
+// interior tiles (uniform weights) and its edge tiles (GD_SWEEP_SPLIT=0: one
+// launch over all tiles).  Counts as in the kernels' decode.
+static bool split_on() {
+  static const bool v = [] {
+    const char* e = std::getenv("GD_SWEEP_SPLIT");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return v;
+}
+static void set_split(Geom& g, const GridDesc& G) {
+  g.n_int = g.n_edge = 0;
+  if (!split_on()) return;
+  const int TX = SWEEP_TILE_TX[g.tile], TY = SWEEP_TILE_TY[g.tile];
+  const int64_t ntx = (G.nx + TX - 1) / TX, nty = (G.ny + TY - 1) / TY;
+  const int64_t nix = std::max<int64_t>(0, (G.nx - 4) / TX - 1), niy = std::max<int64_t>(0, (G.ny - 2) / TY - 1);
+  const int64_t chunks = (G.nz + g.zlen - 1) / g.zlen;
+  if (nix * niy == 0) return;
+  g.n_int = nix * niy * chunks;
+  // the edge tiles are few: shorter z-chunks give their launch enough blocks
+  // to fill the chip instead of a tail of long columns (values do not depend
+  // on the chunking)
+  const int64_t et = ntx * nty - nix * niy;
+  const int64_t ce = std::min<int64_t>(G.nz, std::max<int64_t>(chunks, (4096 + et - 1) / et));
+  g.zlen_edge = (int)((G.nz + ce - 1) / ce);
+  g.n_edge = et * ((G.nz + g.zlen_edge - 1) / g.zlen_edge);
+}
+
 struct Tab {  // launch geometry of one kernel family on one level
   int64_t* d_b0 = nullptr;
   std::vector<int64_t> h_b0;
@@ -214,7 +242,11 @@ struct Hier {
     this->bytes += bytes;
     return p;
   }
-  Geom g_sw(int l) const { return lv[l].sw.geom(lv[l].d, ngrids, lv[l].row); }
+  Geom g_sw(int l) const {
+    Geom g = lv[l].sw.geom(lv[l].d, ngrids, lv[l].row);
+    if (ngrids == 1 && !lv[l].row) set_split(g, lv[l].h[0]);
+    return g;
+  }
   Geom g_ew(int l) const { return lv[l].ew.geom(lv[l].d, ngrids, lv[l].row); }
   Geom g_rc(int l) const { return lv[l].rc.geom(lv[l].d, ngrids, lv[l].row); }
   Geom g_rz(int l) const { return lv[l].rz.geom(lv[l].d, ngrids, lv[l].row); }
@@ -599,7 +631,8 @@ static void autotune(Hier& H, hipStream_t st, bool wide) {
       t.order = L.sw.order;
       HIP_TRY(hipMemcpyAsync(d_b0, t.h_b0.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice, st));
       t.d_b0 = d_b0;
-      const Geom geo = t.geom(L.d, 1, false);
+      Geom geo = t.geom(L.d, 1, false);
+      set_split(geo, g);
       HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));  // warm-up
       HIP_TRY(hipEventRecord(e0, st));
       for (int r = 0; r < 3; ++r) HIP_TRY(launch_rb_sweep(H.s, geo, L.x, L.xt, L.b, nullptr, 0, st));

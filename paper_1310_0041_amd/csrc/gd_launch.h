@@ -37,6 +37,9 @@ struct Geom {
   int order = 0;     // relaxation block order: 0 plain, 1 contiguous runs per XCD
   bool quad = false; // the library's own arrays (x pitch and offsets multiples of 4, aligned):
                      // the relaxation may use its quad form
+  int64_t n_int = 0, n_edge = 0;  // quad relaxation of a one-grid 3-D level: blocks of its interior and
+                                  // edge tiles (n_int 0: one launch over the tile table)
+  int zlen_edge = 1;              // z-chunk of the edge tiles' launch
   bool stencil4 = false;  // the finest-level stencil passes in their quad form (tiles
                           // CS4_TX[tile] x CS4_TY[tile]; 3-D grids, quad-aligned inputs)
 };

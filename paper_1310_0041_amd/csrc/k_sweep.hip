@@ -503,12 +503,68 @@ template <typename S> __device__ __forceinline__ void st4(S* p, float a, float b
   }
 }
 
+// Split launch of a one-grid 3-D level: the tiles whose cells, ring and halo
+// all lie inside the grid (interior) and the others (the edge ring of tiles).
+// Interior tiles are those with tx >= 1, ty >= 1, (tx + 1) TX + 4 <= nx and
+// (ty + 1) TY + 2 <= ny.
+struct SplitTiles {
+  int ntx, nty, txh, tyh, nix, niy;
+  __device__ __forceinline__ SplitTiles(int nx, int ny, int TX, int TY) {
+    ntx = (nx + TX - 1) / TX;
+    nty = (ny + TY - 1) / TY;
+    txh = (nx - 4) / TX;
+    tyh = (ny - 2) / TY;
+    nix = max(0, txh - 1);
+    niy = max(0, tyh - 1);
+  }
+};
+// MAP 1: block -> interior tile; MAP 2: block -> edge tile (rows above and
+// below the interior band, then the tiles left and right of it)
+template <int TX, int TY, int MAP>
+__device__ __forceinline__ Tile decode_split(const GridDesc* __restrict__ grids, int zlen) {
+  const GridDesc& G = grids[0];
+  const SplitTiles s(G.nx, G.ny, TX, TY);
+  const int64_t per = MAP == 1 ? (int64_t)s.nix * s.niy : (int64_t)s.ntx * s.nty - (int64_t)s.nix * s.niy;
+  const int64_t b = blockIdx.x;
+  const int zc = (int)(b / per);
+  int r = (int)(b - (int64_t)zc * per), tx, ty;
+  if (MAP == 1) {
+    ty = 1 + r / s.nix;
+    tx = 1 + r % s.nix;
+  } else if (r < s.ntx) {  // tile row 0
+    ty = 0;
+    tx = r;
+  } else if ((r -= s.ntx) < s.niy * (1 + s.ntx - s.txh)) {  // left and right of the interior band
+    const int m = 1 + s.ntx - s.txh;
+    ty = 1 + r / m;
+    const int k = r % m;
+    tx = k == 0 ? 0 : s.txh + k - 1;
+  } else {  // tile rows below the interior band
+    r -= s.niy * (1 + s.ntx - s.txh);
+    ty = 1 + s.niy + r / s.ntx;
+    tx = r % s.ntx;
+  }
+  Tile t;
+  t.g = 0;
+  t.bid = b;
+  t.x0 = tx * TX;
+  t.y0 = ty * TY;
+  t.z0 = zc * zlen;
+  t.z1 = min(t.z0 + zlen, G.nz);
+  return t;
+}
+
 // ZX: the input iterate is zero (the first sweep of a V-cycle started from
 // zero): x is not read, the sweep starts from zeros.
-template <typename S, int TX, int TY, bool ZX>
+// MAP 0: the level's tile table; MAP 1: interior tiles of a one-grid level
+// (every weight the same, no masks: the per-cell weights, inverse diagonals
+// and validity flags fold into uniform values, which frees registers for
+// more waves per CU); MAP 2: its edge tiles (the general body).
+template <typename S, int TX, int TY, bool ZX, int MAP>
 __global__ void __launch_bounds__(TX * TY / 4)
 k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ block0, int ngrids, int zlen,
             const S* __restrict__ xin, S* __restrict__ xout, const S* __restrict__ bin, int order) {
+  constexpr bool INT = MAP == 1;
   static_assert(sizeof(S) <= 4, "the quad form computes in float");
   using C = float;
   using SS = SweepShape4<TX, TY>;
@@ -524,7 +580,8 @@ k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
   // threads without a ring cell
   __shared__ __align__(16) C X[4 * PLANE + NT];
 
-  const Tile t = decode_tile(grids, block0, ngrids, zlen, TX, TY, false, order);
+  const Tile t = MAP == 0 ? decode_tile(grids, block0, ngrids, zlen, TX, TY, false, order)
+                           : decode_split<TX, TY, MAP>(grids, zlen);
   const GridDesc& G = grids[t.g];
   if (G.skip) return;  // a converged grid of a batch
   const int nx = G.nx, ny = G.ny, nz = G.nz, px = G.px;
@@ -545,12 +602,12 @@ k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
   const int qxl = ROW ? tid : ln % QPR;
   const int wpar = __builtin_amdgcn_readfirstlane((y0 + tyl) & 1);  // row parity, uniform per wave
   const int gx = x0 + 4 * qxl, gy = y0 + tyl;
-  const bool rowok = gy < ny;
-  const bool v0 = rowok && gx < nx, v1 = rowok && gx + 1 < nx, v2 = rowok && gx + 2 < nx,
-             v3 = rowok && gx + 3 < nx;
+  const bool rowok = INT || gy < ny;
+  const bool v0 = INT || (rowok && gx < nx), v1 = INT || (rowok && gx + 1 < nx), v2 = INT || (rowok && gx + 2 < nx),
+             v3 = INT || (rowok && gx + 3 < nx);
   const int lo = (YO + tyl) * HX + XO + 4 * qxl;  // LDS index of gx inside a plane (16-byte aligned)
   const int own = gy * px + gx;                  // element offset inside a plane (< 2^28)
-  const C wU = (gy > 0) ? wy : (C)0, wD = (gy + 1 < ny) ? wy : (C)0;
+  const C wU = (INT || gy > 0) ? wy : (C)0, wD = (INT || gy + 1 < ny) ? wy : (C)0;
   // per position class k (the updated cells at F = k and S = k + 2): x-weights,
   // inverse diagonals inside the z-range and on its first or last plane, and
   // whether the diagonal is non-zero (keep = 0: the cell is set to 0)
@@ -559,10 +616,10 @@ k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
   for (int k = 0; k < 2; ++k) {
     const int xF = gx + k, xS = gx + k + 2;
     // weights as the pair form gives them: a neighbour in the grid has w_x
-    wLF[k] = xF > 0 ? wx : (C)0;
-    wRF[k] = xF + 1 < nx ? wx : (C)0;
+    wLF[k] = (INT || xF > 0) ? wx : (C)0;
+    wRF[k] = (INT || xF + 1 < nx) ? wx : (C)0;
     wLS[k] = wx;
-    wRS[k] = xS + 1 < nx ? wx : (C)0;
+    wRS[k] = (INT || xS + 1 < nx) ? wx : (C)0;
     const C wz1 = nz > 1 ? wz : (C)0;
     const C dF = alpha + wLF[k] + wRF[k] + wU + wD, dS = alpha + wLS[k] + wRS[k] + wU + wD;
     const C diF = (dF + wz1) + wz1, deF = dF + wz1, diS = (dS + wz1) + wz1, deS = dS + wz1;
@@ -586,7 +643,7 @@ k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
     if (h < SS::NHQ) halo_quad<TX, TY>(h, hy, hx);
     const int cx = x0 - XO + hx, cy = y0 - YO + hy;
     hs[k] = h < SS::NHQ;
-    hv[k] = hs[k] && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    hv[k] = hs[k] && (INT || (cx >= 0 && cx < nx && cy >= 0 && cy < ny));
     hoff[k] = hy * HX + hx;
     hg[k] = hv[k] ? cy * px + cx : 0;
     hxs[k] = cx;
@@ -604,13 +661,13 @@ k_rb_sweep4(const GridDesc* __restrict__ grids, const int64_t* __restrict__ bloc
     if (rm >= 0) ring_red_cell<TX, TY>(rm, x0, y0, par, hy, hx);
     hx += XO - 2;  // the pair form's LDS column -> this layout
     const int cx = x0 - XO + hx, cy = y0 - YO + hy;
-    rv[par] = rm >= 0 && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    rv[par] = rm >= 0 && (INT || (cx >= 0 && cx < nx && cy >= 0 && cy < ny));
     ro[par] = rm >= 0 ? hy * HX + hx : lo;
     rg[par] = rv[par] ? cy * px + cx : 0;
-    rwl[par] = cx > 0 ? wx : (C)0;
-    rwr[par] = cx < nx - 1 ? wx : (C)0;
-    rwu[par] = cy > 0 ? wy : (C)0;
-    rwd[par] = cy < ny - 1 ? wy : (C)0;
+    rwl[par] = (INT || cx > 0) ? wx : (C)0;
+    rwr[par] = (INT || cx < nx - 1) ? wx : (C)0;
+    rwu[par] = (INT || cy > 0) ? wy : (C)0;
+    rwd[par] = (INT || cy < ny - 1) ? wy : (C)0;
     const C dxy = alpha + rwl[par] + rwr[par] + rwu[par] + rwd[par];
     const C wz1 = nz > 1 ? wz : (C)0;
     const C di = (dxy + wz1) + wz1, de = dxy + wz1;
@@ -852,24 +909,35 @@ static bool quad_on() {
   return v;
 }
 
-template <typename T, bool ZX>
-static void sweep_launch4(const Geom& g, const void* xin, void* xout, const void* b, hipStream_t st) {
-#define SWEEP4(TX, TY)                                                                                            \
-  hipLaunchKernelGGL((k_rb_sweep4<T, TX, TY, ZX>), dim3((unsigned)g.nblocks), dim3(TX * TY / 4), 0, st, g.grids, \
-                     g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, g.order)
-  if (g.row) {
-    SWEEP4(SWR_TX, 1);
+template <typename T, bool ZX, int TX, int TY>
+static void sweep_launch4t(const Geom& g, const void* xin, void* xout, const void* b, hipStream_t st) {
+#define SWEEP4(MAP, NB, ZL)                                                                                      \
+  hipLaunchKernelGGL((k_rb_sweep4<T, TX, TY, ZX, MAP>), dim3((unsigned)(NB)), dim3(TX * TY / 4), 0, st, g.grids, \
+                     g.block0, g.ngrids, ZL, (const T*)xin, (T*)xout, (const T*)b, g.order)
+  if (g.n_int > 0) {  // one-grid level: interior tiles, then the edge tiles
+    SWEEP4(1, g.n_int, g.zlen);
+    if (g.n_edge > 0) SWEEP4(2, g.n_edge, g.zlen_edge);
   } else {
-    switch (g.tile) {
-      case 0: SWEEP4(64, 8); break;
-      case 1: SWEEP4(128, 8); break;
-      case 2: SWEEP4(64, 16); break;
-      case 3: SWEEP4(128, 16); break;
-      case 4: SWEEP4(256, 8); break;
-      default: SWEEP4(256, 12); break;
-    }
+    SWEEP4(0, g.nblocks, g.zlen);
   }
 #undef SWEEP4
+}
+
+template <typename T, bool ZX>
+static void sweep_launch4(const Geom& g, const void* xin, void* xout, const void* b, hipStream_t st) {
+  if (g.row) {
+    hipLaunchKernelGGL((k_rb_sweep4<T, SWR_TX, 1, ZX, 0>), dim3((unsigned)g.nblocks), dim3(SWR_TX / 4), 0, st, g.grids,
+                       g.block0, g.ngrids, g.zlen, (const T*)xin, (T*)xout, (const T*)b, g.order);
+    return;
+  }
+  switch (g.tile) {
+    case 0: sweep_launch4t<T, ZX, 64, 8>(g, xin, xout, b, st); break;
+    case 1: sweep_launch4t<T, ZX, 128, 8>(g, xin, xout, b, st); break;
+    case 2: sweep_launch4t<T, ZX, 64, 16>(g, xin, xout, b, st); break;
+    case 3: sweep_launch4t<T, ZX, 128, 16>(g, xin, xout, b, st); break;
+    case 4: sweep_launch4t<T, ZX, 256, 8>(g, xin, xout, b, st); break;
+    default: sweep_launch4t<T, ZX, 256, 12>(g, xin, xout, b, st); break;
+  }
 }
 
 static bool quad_form(size_t es, const Geom& g, const void* ec) {

@@ -461,15 +461,18 @@ def test_sweep_tiles_identical(gd, storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("shape", [(37, 77, 203), (9, 130, 64), (5, 3, 9), (1, 1, 1), (24, 64, 256), (7, 13, 132)])
+@pytest.mark.parametrize("shape", [(37, 77, 203), (9, 130, 64), (5, 3, 9), (1, 1, 1), (24, 64, 256), (7, 13, 132),
+                                   (9, 41, 801)])
 def test_sweep_quad_equals_pair(gd, storage, shape):
     """The quad forms of the relaxation and of the finest-level stencil
     passes (four x cells per thread; the stencil passes where the input's
     width is a multiple of four) give the pair forms' values bit for bit:
     AD and SP results after a fixed number of cycles, every tile variant of
     the stack and the slices' row form, on odd sizes, ragged tile edges and
-    several z-chunks.  The residual norms are the same sums taken in another
-    order (equal to 1e-12)."""
+    several z-chunks; 801 x 41 has interior tiles for every tile variant, so
+    its stack runs the split launch (interior tiles with uniform weights,
+    then the edge tiles).  The residual norms are the same sums taken in
+    another order (equal to 1e-12)."""
     import synth
 
     nz, ny, nx = shape
