@@ -46,6 +46,16 @@ TOL = 1e-6
 HBM_PEAK_GBS = 8000.0
 
 
+def smooth_split(a, storage="f32", refine=0):
+    """(pre, post) sweeps per V-cycle: --smooth, or with "auto" what the
+    library picks for the storage path (V(2,3) for 16-bit storage with FP64
+    refinement, V(1,2) otherwise)."""
+    if a.smooth != "auto":
+        pre, post = (int(v) for v in a.smooth.split(","))
+        return pre, post
+    return (2, 3) if refine and storage in ("f16", "bf16") else (1, 2)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -54,7 +64,9 @@ def parse():
     p.add_argument("--workload", default="stack4k", choices=sorted(WORKLOADS))
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-crop", default="32,512,512", help="nz,ny,nx of the oracle's crop")
-    p.add_argument("--smooth", default="1,2", help="pre,post red-black sweeps per V-cycle")
+    p.add_argument("--smooth", default="auto",
+                   help="pre,post red-black sweeps per V-cycle; auto: the library's choice per storage path "
+                        "(V(2,3) for 16-bit storage with FP64 refinement, V(1,2) otherwise)")
     p.add_argument("--fmg", type=int, default=None, help="1: full-multigrid start of the plain solves")
     p.add_argument("--discretization", default="constant", choices=["constant", "hybrid", "linear"],
                    help="discretisation of both solves (Sec. 4.2); Hybrid and Linear solve the SP slices one "
@@ -112,7 +124,7 @@ def bench_slices(a, gd, synth, torch, desc):
     descs = gd.make_slice_descs(meta["offset"], meta["w"], meta["h"], meta["alpha"])
     I0, I1 = meta["I0"], meta["I1"]
     npx = I0.numel()
-    pre, post = (int(v) for v in a.smooth.split(","))
+    pre, post = smooth_split(a)
     opts = dict(rel_tol=TOL, pre_smooth=pre, post_smooth=post)
     out = torch.empty_like(I0)
     for _ in range(a.warmup):
@@ -323,7 +335,7 @@ def bench_streamed(a, gd, synth, torch, desc):
     I0 = synth.make_stack(spec, device=torch.device("cuda:0"), dtype=torch.float32)
     shape = tuple(I0.shape)
     nvox = I0.numel()
-    pre, post = (int(v) for v in a.smooth.split(","))
+    pre, post = smooth_split(a)
     kw = dict(pre_smooth=pre, post_smooth=post)
     # right-hand side of Eq. (1): G = (d I0 / dx, d I0 / dy, 0) on the faces
     gx = torch.zeros_like(I0)
@@ -436,7 +448,7 @@ def bench_npr(a, gd, synth, torch, desc):
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     nvox = I0.numel()
-    pre, post = (int(v) for v in a.smooth.split(","))
+    pre, post = smooth_split(a)
     opts = dict(rel_tol=TOL, pre_smooth=pre, post_smooth=post)
 
     def step(timing):
@@ -546,7 +558,7 @@ def main():
                         + ("" if a.discretization == "constant" and a.prolong == "trilinear"
                            else f"; AD {a.discretization} discretisation, {a.prolong} up-sampling"),
             "nx": spec.nx, "ny": spec.ny, "nz": spec.nz, "voxels": spec.nx * spec.ny * spec.nz,
-            "smooth": [int(v) for v in a.smooth.split(",")],
+            "smooth": list(smooth_split(a, storage, refine)),
         },
         "roofline": head["roofline"],
         "ad": head["ad"],
@@ -554,8 +566,8 @@ def main():
         "generate_s": head["generate_s"],
     }
     if len(results) > 1:
-        line["legs"] = {r["leg"]: {k: r[k] for k in ("ms_per_step", "voxels_per_s", "steps", "warmup", "ad", "sp",
-                                                     "finest_sweep")}
+        line["legs"] = {r["leg"]: {k: r[k] for k in ("ms_per_step", "voxels_per_s", "steps", "warmup", "smooth", "ad",
+                                                     "sp", "finest_sweep")}
                         for r in results}
         plain = next(r for r in results if r["leg"] == "f32")
         line["legs"]["speedup_vs_f32_plain"] = {r["leg"]: plain["ms_per_step"] / r["ms_per_step"] for r in results}
@@ -612,7 +624,7 @@ def run_stack_leg(a, gd, synth, torch, spec, storage, refine, steps, warmup):
     gen_s = time.perf_counter() - t0
     nvox = I0.numel()
     out_dtype = torch.float32  # I1 and I2 in FP32 (16-bit storage covers the input and the V-cycles)
-    pre, post = (int(v) for v in a.smooth.split(","))
+    pre, post = smooth_split(a, storage, refine)
     opts = dict(storage=sdt, fp64_refine=refine, rel_tol=TOL, pre_smooth=pre, post_smooth=post)
     if a.inner_cycles is not None:
         opts["inner_cycles"] = a.inner_cycles
@@ -671,6 +683,7 @@ def run_stack_leg(a, gd, synth, torch, spec, storage, refine, steps, warmup):
     }
     leg = {
         "leg": storage, "steps": steps, "warmup": warmup, "ms_per_step": dt * 1e3, "voxels_per_s": nvox / dt,
+        "smooth": [pre, post],
         "generate_s": gen_s, "roofline": roof,
         "finest_sweep": {"avg_launch_ms": avg_ms, "GB/s": achieved, "frac": achieved / HBM_PEAK_GBS,
                          "tile": cfg["tile"]},

@@ -62,8 +62,12 @@ typedef struct {
   double rel_tol;       /* stop when ||b - A x||_2 / ||b||_2 <= rel_tol (canonical
                            system, x0 = 0 convention of the Table 1 caption)   */
   int max_cycles;       /* V-cycles (plain) or refinement steps (mixed)        */
-  int pre_smooth;       /* red-black GS sweeps before restriction              */
-  int post_smooth;      /* red-black GS sweeps after prolongation              */
+  int pre_smooth;       /* red-black GS sweeps before restriction; -1 (the
+                           default): automatic, 2 for FP16/BF16 storage with
+                           fp64_refine = 1, else 1                            */
+  int post_smooth;      /* red-black GS sweeps after prolongation; -1 (the
+                           default): automatic, 3 for FP16/BF16 storage with
+                           fp64_refine = 1, else 2                            */
   gd_dtype storage;     /* storage of the multigrid arrays: F64/F32 (plain) or
                            F16/BF16/F32 (with fp64_refine)                      */
   int fp64_refine;      /* 1: FP64 outer iterative refinement around V-cycles

@@ -1702,8 +1702,8 @@ void gd_default_opts(gd_solve_opts* o) {
   if (!o) return;
   o->rel_tol = 1e-6;
   o->max_cycles = 50;
-  o->pre_smooth = 2;
-  o->post_smooth = 2;
+  o->pre_smooth = -1;  // automatic (auto_smooth)
+  o->post_smooth = -1;
   o->storage = GD_F32;
   o->fp64_refine = 0;
   o->inner_cycles = 1;
@@ -1719,6 +1719,16 @@ void gd_default_opts(gd_solve_opts* o) {
 
 const char* gd_last_error(void) { return t_err.c_str(); }
 const char* gd_version(void) { return "gdstack 0.1 gfx950"; }
+
+// Sweeps per V-cycle left automatic (-1): V(2, 3) for 16-bit storage with
+// FP64 refinement (a stronger cycle saves refinement passes, which cost an
+// FP64 pass over the finest level each), V(1, 2) otherwise; the fastest
+// splits to 1e-6 measured on the 4096^2 x 256 stack.
+static void auto_smooth(gd_solve_opts& o) {
+  const bool mixed16 = o.fp64_refine && (o.storage == GD_F16 || o.storage == GD_BF16);
+  if (o.pre_smooth == -1) o.pre_smooth = mixed16 ? 2 : 1;
+  if (o.post_smooth == -1) o.post_smooth = mixed16 ? 3 : 2;
+}
 
 static gd_status check_opts(const gd_solve_opts& o) {
   if (!(o.rel_tol > 0.0) || o.max_cycles < 0 || o.pre_smooth < 0 || o.post_smooth < 0 ||
@@ -1746,6 +1756,7 @@ static gd_status smooth_z_args(const std::string& who, const void* I0, gd_dtype 
     return fail(GD_ERR_INVALID, who + ": need beta_x, beta_y >= 0 and beta_z > 0");
   gd_default_opts(&o);
   if (opts) o = *opts;
+  auto_smooth(o);
   gd_status s = check_opts(o);
   if (s != GD_OK) return s;
   if (o.discretization == 2 && o.fp64_refine)
@@ -1839,6 +1850,7 @@ gd_status gd_npr_filter(const void* I0, gd_dtype in_t, void* I1, gd_dtype out_t,
   gd_solve_opts o;
   gd_default_opts(&o);
   if (opts) o = *opts;
+  auto_smooth(o);
   gd_status s = check_opts(o);
   if (s != GD_OK) return s;
   if (o.fp64_refine) return fail(GD_ERR_UNSUPPORTED, "gd_npr_filter: FP64 refinement is not built for this filter");
@@ -1909,6 +1921,7 @@ gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1,
   gd_solve_opts o;
   gd_default_opts(&o);
   if (opts) o = *opts;
+  auto_smooth(o);
   gd_status s = check_opts(o);
   if (s != GD_OK) return s;
   if (o.discretization == 2 && o.fp64_refine)
@@ -2116,6 +2129,7 @@ static gd_status hier_args(const std::string& who, int64_t nx, int64_t ny, int64
   if (opts) o = *opts;
   o.storage = s;
   o.fp64_refine = 0;
+  auto_smooth(o);
   if (!(o.rel_tol > 0.0) || o.pre_smooth < 0 || o.post_smooth < 0 || o.pre_smooth + o.post_smooth < 1 ||
       (o.prolong != 0 && o.prolong != 1) || o.sweep_tile < -1 || o.sweep_tile > 3 || o.discretization < 0 ||
       o.discretization > 2 || o.sweep_quad < 0 || o.sweep_quad > 1)
@@ -2669,6 +2683,7 @@ gd_status gd_screened_poisson_streamed(const void* I0, gd_dtype in_t, const void
   gd_solve_opts o;
   gd_default_opts(&o);
   if (opts) o = *opts;
+  auto_smooth(o);
   gd_status sc = check_opts(o);
   if (sc != GD_OK) return sc;
   hipStream_t st = (hipStream_t)stream;
