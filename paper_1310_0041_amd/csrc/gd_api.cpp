@@ -285,13 +285,14 @@ static void build_tab(Tab& t, const std::vector<GridDesc>& grids, int TX, int TY
   }
 }
 
-// Relaxation tile variant of 3-D grids (GD_SWEEP_TILE, 0..3; 64 x 16 by
-// default, the fastest of the four on MI355X for 1024^2 x 128 FP32 stacks).
+// Relaxation tile variant of 3-D grids when the autotuner does not choose
+// (GD_SWEEP_TILE, 0..5, the wide ones 4 and 5 where the quad form applies;
+// 64 x 16 by default).
 static int sweep_tile() {
   static int v = [] {
     const char* e = std::getenv("GD_SWEEP_TILE");
     const int t = e ? std::atoi(e) : 2;
-    return (t >= 0 && t < 4) ? t : 2;
+    return (t >= 0 && t < kSweepTiles) ? t : 2;
   }();
   return v;
 }
@@ -420,7 +421,8 @@ static std::unique_ptr<Hier> build_hier(const std::vector<GridSpec>& specs, gd_d
       build_tab(L.pp, L.h, SWR_TX, 1, false, li == 0 ? 8192 : 4096);
       build_tab(L.cs, L.h, SWR_TX, 1, false, 4096);  // not used: rows take the pair form
     } else {
-      const int v = tile_force >= 0 ? tile_force : sweep_tile();
+      int v = tile_force >= 0 ? tile_force : sweep_tile();
+      if (v >= kPairTiles && !sweep_wide_tiles_ok(s, true)) v = kPairTiles - 1;  // a quad-only tile
       build_tab(L.sw, L.h, SWEEP_TILE_TX[v], SWEEP_TILE_TY[v], false, tgt);
       L.sw.tile = v;
       L.sw.order = sweep_order_env() == 1 ? 1 : 0;
