@@ -253,6 +253,17 @@ struct Hier {
   Geom g_pp(int l) const { return lv[l].pp.geom(lv[l].d, ngrids, lv[l].row); }
   Geom g_cs(int l) const { return lv[l].cs.geom(lv[l].d, ngrids, lv[l].row); }
   bool quad_opt = true;  // the caller's sweep_quad option of the running solve
+  // A stack of equal, independent slices solved as one 3-D grid with w_z = 0:
+  // the norms of the stencil passes are taken per plane (one plane per block)
+  struct PlaneNorms {
+    Tab tab[2];              // one-plane tiles of the pair (0) and quad (1) stencil forms
+    int64_t* seg[2] = {};    // device: nz + 1 block offsets of the planes
+    double* part = nullptr;  // device: 2 sums per block
+    int64_t part_blocks = 0;
+    double* red = nullptr;   // device: 2 sums per plane
+    std::vector<double> host;  // 2 sums per plane
+  };
+  std::unique_ptr<PlaneNorms> planes;
   bool flags_set = false;  // some grid descriptor carries a skip / alt flag
 };
 
@@ -1202,9 +1213,66 @@ static double in_bytes(const Problem& P) { return (double)dsize(P.tin) + (P.I1 ?
 
 // (one pass; r0, when given, receives the norm of the correction-form
 // right-hand side, which is the canonical residual of x = I0)
+// Stencil geometry with one plane per block and the plane segments (plane mode).
+static Geom plane_geom(Hier& H, const Problem& P, const int64_t*& seg) {
+  Geom g = stencil_geom(H, P);
+  auto& pn = *H.planes;
+  const int f = g.stencil4 ? 1 : 0;
+  const Level& L = H.lv[0];
+  const GridDesc& G = L.h[0];
+  Tab& t = pn.tab[f];
+  const int TX = f ? CS4_TX[L.cs.tile] : SW_TX, TY = f ? CS4_TY[L.cs.tile] : SW_TY;
+  if (!t.d_b0) {
+    const int64_t txy = (int64_t)((G.nx + TX - 1) / TX) * ((G.ny + TY - 1) / TY);
+    build_tab(t, L.h, TX, TY, false, txy * G.nz);  // as many blocks as tiles: one plane each
+    t.tile = L.cs.tile;
+    t.d_b0 = (int64_t*)H.alloc(2 * sizeof(int64_t));
+    HIP_TRY(hipMemcpy(t.d_b0, t.h_b0.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice));
+    std::vector<int64_t> sg(G.nz + 1);
+    for (int z = 0; z <= G.nz; ++z) sg[z] = (int64_t)z * txy;
+    pn.seg[f] = (int64_t*)H.alloc(sg.size() * sizeof(int64_t));
+    HIP_TRY(hipMemcpy(pn.seg[f], sg.data(), sg.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (t.h_b0.back() > pn.part_blocks) {
+      pn.part = (double*)H.alloc(2 * t.h_b0.back() * sizeof(double));
+      pn.part_blocks = t.h_b0.back();
+    }
+    if (!pn.red) {
+      pn.red = (double*)H.alloc(2 * (size_t)G.nz * sizeof(double));
+      pn.host.resize(2 * (size_t)G.nz);
+    }
+  }
+  Geom q = t.geom(L.d, 1, false);
+  q.stencil4 = g.stencil4;
+  seg = pn.seg[f];
+  return q;
+}
+
+// per-plane sums (ncomp per plane) of the partials of a plane-mode pass
+static void read_planes(Hier& H, const int64_t* seg, int ncomp, hipStream_t st) {
+  auto& pn = *H.planes;
+  const int nz = H.lv[0].h[0].nz;
+  HIP_TRY(launch_reduce(pn.part, seg, nz, ncomp, pn.red, st));
+  HIP_TRY(hipMemcpyAsync(pn.host.data(), pn.red, (size_t)nz * ncomp * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+}
+
 static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero, std::vector<double>& bn,
                             hipStream_t st, std::vector<double>* r0 = nullptr, const double* inv_scale = nullptr) {
   H.count(0, in_bytes(P) + (b_out ? dsize(H.s) : 0) + (x_zero ? dsize(H.s) : 0));
+  if (H.planes) {  // per plane of the stack
+    const int64_t* seg = nullptr;
+    const Geom g = plane_geom(H, P, seg);
+    HIP_TRY(launch_rhs_corr(P.tin, P.t1, H.s, g, P.I0, P.I1, b_out, x_zero, H.planes->part, st, inv_scale));
+    read_planes(H, seg, 2, st);
+    const int nz = H.lv[0].h[0].nz;
+    bn.resize(nz);
+    for (int z = 0; z < nz; ++z) bn[z] = std::sqrt(H.planes->host[2 * z]);
+    if (r0) {
+      r0->resize(nz);
+      for (int z = 0; z < nz; ++z) (*r0)[z] = std::sqrt(H.planes->host[2 * z + 1]);
+    }
+    return;
+  }
   const Geom g = stencil_geom(H, P);
   HIP_TRY(launch_rhs_corr(P.tin, P.t1, H.s, g, P.I0, P.I1, b_out, x_zero, H.partials, st, inv_scale));
   HIP_TRY(launch_reduce(H.partials, g.block0, H.ngrids, 2, H.dred, st));
@@ -1219,6 +1287,17 @@ static void canonical_norms(Hier& H, const Problem& P, void* b_out, void* x_zero
 
 static std::vector<double> canon_residual(Hier& H, const Problem& P, int mode, void* rout, hipStream_t st) {
   H.count(0, in_bytes(P) + (mode == 0 ? dsize(H.s) : 8.0) + (rout ? dsize(H.s) : 0));
+  if (H.planes) {  // per plane of the stack
+    const int64_t* seg = nullptr;
+    const Geom g = plane_geom(H, P, seg);
+    HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, mode, g, P.I0, P.I1, H.lv[0].x, H.x64, rout,
+                                  H.dscal + H.ngrids, H.planes->part, st));
+    read_planes(H, seg, 1, st);
+    const int nz = H.lv[0].h[0].nz;
+    std::vector<double> r(nz);
+    for (int z = 0; z < nz; ++z) r[z] = std::sqrt(H.planes->host[z]);
+    return r;
+  }
   const Geom g = stencil_geom(H, P);
   HIP_TRY(launch_canon_residual(P.tin, P.t1, H.s, mode, g, P.I0, P.I1, H.lv[0].x, H.x64, rout, H.dscal + H.ngrids,
                                 H.partials, st));
@@ -1407,6 +1486,76 @@ static Outcome solve_plain(Hier& H, const Problem& P, const gd_solve_opts& o, hi
   finish(H, P, 0, st);
   if (ndone > 0) upload_flags(H, {}, {}, st);
   cy.harvest();
+  R.bytes = H.acct - a0;
+  return R;
+}
+
+// Plain V-cycles of a stack of equal, independent slices held as one 3-D
+// grid with w_z = 0 (z is never coarsened, so every level keeps the slices
+// apart): the storage-precision residual of the whole stack decides when to
+// look, and the FP64 canonical residual of every slice against its own
+// right-hand side decides convergence (each slice to the tolerance).
+static Outcome solve_planes(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
+  prep(H, o);
+  Outcome R;
+  const double a0 = H.acct;
+  canonical_norms(H, P, H.lv[0].b, H.lv[0].x, R.bnorm, st);
+  const int nz = (int)R.bnorm.size();
+  double bglob = 0.0;
+  for (double b : R.bnorm) bglob += b * b;
+  bglob = std::sqrt(bglob);
+  Cycler cy(H, st, o);
+  // Once the stack's storage residual is below half the tolerance (or stops
+  // falling), every cycle checks the slices in FP64; the slices' floors in
+  // the storage precision differ (a slice with a small right-hand side has
+  // a relatively higher one), so the worst slice decides when to stop.
+  bool checking = false, pre_done = false;
+  double best = INFINITY, best_worst = INFINITY;
+  int stall = 0, stall_c = 0;
+  R.rel.assign(nz, 0.0);
+  for (;;) {
+    if (!pre_done) {
+      cy.smooth(0, o.pre_smooth);
+      cy.restrict_to(0, true);
+    }
+    pre_done = false;
+    read_dred(H, 1, st);
+    const double rr = std::sqrt(H.hpin[0]);
+    if (!std::isfinite(rr)) { R.numeric = true; break; }
+    stall = rr < 0.7 * best ? 0 : stall + 1;
+    best = std::min(best, rr);
+    if (rr <= 0.5 * o.rel_tol * denom(bglob) || stall >= 3) checking = true;
+    const bool last = R.cycles >= o.max_cycles;
+    if (checking || last) {
+      std::vector<double> c = canon_residual(H, P, 0, nullptr, st);
+      bool bad = false;
+      R.converged = all_below(c, R.bnorm, o.rel_tol, bad);
+      double worst = 0.0;
+      for (int z = 0; z < nz; ++z) {
+        R.rel[z] = c[z] / denom(R.bnorm[z]);
+        worst = std::max(worst, R.rel[z]);
+      }
+      if (bad) { R.numeric = true; break; }
+      if (R.converged || last) break;
+      stall_c = worst < 0.7 * best_worst ? 0 : stall_c + 1;
+      best_worst = std::min(best_worst, worst);
+      if (stall_c >= 3) break;  // the worst slice has reached its floor
+    }
+    if (graphs_on(o)) {
+      CycleGraphs(H, graph_key("plain", o)).run(st, [&](hipStream_t cs) {
+        Cycler c(H, cs, o);
+        c.correct(0);
+        c.smooth(0, o.pre_smooth);
+        c.restrict_to(0, true);
+      });
+      pre_done = true;
+    } else {
+      cy.correct(0);
+    }
+    R.cycles++;
+  }
+  cy.harvest();
+  finish(H, P, 0, st);
   R.bytes = H.acct - a0;
   return R;
 }
@@ -1929,6 +2078,38 @@ gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1,
   if (o.discretization == 2 && o.fp64_refine)
     return fail(GD_ERR_UNSUPPORTED, "gd_screened_poisson_slices: FP64 refinement is not built for the Linear discretisation");
   hipStream_t st = (hipStream_t)stream;
+  // Hybrid, plain V-cycles, slices of one size and alpha laid out as a stack
+  // (equal pitch, constant stride): one 3-D grid with w_z = 0, per-slice norms
+  bool stack = o.discretization == 1 && !o.fp64_refine && n > 1;
+  for (int64_t i = 1; stack && i < n; ++i)
+    stack = sl[i].nx == sl[0].nx && sl[i].ny == sl[0].ny && sl[i].pitch == sl[0].pitch &&
+            sl[i].alpha == sl[0].alpha && sl[i].offset - sl[i - 1].offset == sl[1].offset - sl[0].offset &&
+            sl[1].offset - sl[0].offset >= (int64_t)sl[0].pitch * sl[0].ny;
+  if (stack && (int64_t)sl[0].nx * sl[0].ny <= MAX_PLANE && n <= INT32_MAX) {
+    return run_guarded([&]() -> gd_status {
+      const auto t0 = std::chrono::steady_clock::now();
+      const gd_slice_desc& d = sl[0];
+      std::vector<GridSpec> g3{{d.nx, d.ny, n, (double)d.alpha, bx, by, 0.0, d.offset, d.pitch,
+                                sl[1].offset - sl[0].offset}};
+      HierLease H = get_hier("sp-hybrid-stack", g3, o.storage, false, st, o.sweep_tile, o.sweep_quad != 0);
+      if (!H->planes) H->planes = std::make_unique<Hier::PlaneNorms>();
+      Problem P{I0, I1, I2, t, tout, false, t1};
+      Outcome R = solve_planes(*H, P, o, st);
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (per)
+        for (int64_t i = 0; i < n; ++i) fill_report(&per[i], R, (int)i, secs, (int)H->lv.size(), 1.0 / (double)n);
+      if (rep) {
+        fill_report(rep, R, 0, secs, (int)H->lv.size());
+        double worst = 0.0;
+        for (double r : R.rel) worst = std::max(worst, r);
+        rep->rel_residual = worst;
+        rep->b_norm = 0.0;
+      }
+      if (R.numeric) return fail(GD_ERR_NUMERIC, "gd_screened_poisson_slices: non-finite residual");
+      if (!R.converged) return fail(GD_ERR_NOT_CONVERGED, "gd_screened_poisson_slices: tolerance not reached");
+      return GD_OK;
+    });
+  }
   if (o.discretization != 0) {
     // Hybrid and Linear (Sec. 4.2): each slice is a one-plane grid of its own
     // (the 27-point table levels take one grid per hierarchy), solved in turn;

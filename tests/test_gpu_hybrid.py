@@ -142,6 +142,43 @@ def test_sp_hybrid_stack(gd, shape):
     assert np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
 
 
+def test_sp_hybrid_stack_as_one_grid(gd):
+    """Hybrid SP of equal slices laid out as a stack runs as one 3-D grid
+    with no coupling across slices (w_z = 0, z never coarsened) and per-slice
+    FP64 norms: every slice meets the tolerance against its own right-hand
+    side and matches the DCT within the bound its residual gives (the
+    operator's smallest eigenvalue is alpha); the same slices passed out of
+    stack order take the slice-by-slice route and agree with it to that
+    bound."""
+    say("hybrid SP stack as one grid")
+    nz, ny, nx = 6, 40, 72
+    # I1 a few percent and a few grey levels off I0: the exact answer rounded
+    # to FP32 leaves relative residuals of 1.3e-7 .. 3.4e-7 per slice, so
+    # FP32 storage can meet 1e-6 (offsets of +-20 put that floor at 1.2e-6)
+    I0 = synth.make_stack(synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100431)).numpy()
+    rng = np.random.default_rng(13100431)
+    I1 = I0 * rng.uniform(0.95, 1.05, (nz, 1, 1)) + rng.uniform(-2, 2, (nz, 1, 1))
+    x0, x1 = torch.from_numpy(I0).float().cuda(), torch.from_numpy(I1).float().cuda()
+    out, rep, per = gd.screened_poisson_stack(x0, x1, 0.01, discretization=1, out_dtype=torch.float64)
+    q0, q1 = x0.double().cpu().numpy(), x1.double().cpu().numpy()
+    ref = solvers.sp_dct(q0, q1, 0.01)
+    got = out.cpu().numpy()
+    for z in range(nz):
+        assert per[z]["rel_residual"] <= 1e-6
+        b = np.linalg.norm(og.rhs_sp(q0[z:z + 1], q1[z:z + 1], 0.01))
+        bar = max(1e-5, 1.01 * per[z]["rel_residual"] * b / (0.01 * np.linalg.norm(ref[z])))
+        assert np.linalg.norm(got[z] - ref[z]) / np.linalg.norm(ref[z]) <= bar, z
+    # out of stack order: the slice-by-slice route
+    order = np.arange(nz)[::-1]
+    descs = gd.make_slice_descs(order * nx * ny, nx, ny, 0.01)
+    out2, rep2, per2 = gd.screened_poisson_slices(x0.reshape(-1), x1.reshape(-1), descs, discretization=1,
+                                                  out_dtype=torch.float64)
+    got2 = out2.cpu().numpy().reshape(nz, ny, nx)
+    for z in range(nz):
+        assert per2[z]["rel_residual"] <= 1e-6
+        assert np.linalg.norm(got2[z] - ref[z]) / np.linalg.norm(ref[z]) <= 1e-4, z
+
+
 def test_sp_hybrid_uneven_batch_fp32_and_mixed(gd):
     """A batch of uneven slices with per-slice alpha, Hybrid: plain FP32 to
     1e-6 (error bar 1e-5) and FP16 storage with FP64 refinement (1e-6)."""
