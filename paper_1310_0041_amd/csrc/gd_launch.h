@@ -117,6 +117,11 @@ struct HybTables {
 // one colour (0..7) of an 8-colour Gauss-Seidel sweep of a table level, in place
 hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int colour, void* x, const void* b,
                           hipStream_t st);
+// one whole 8-colour sweep of a table level from xin into xout (two launches,
+// one per z-parity of the planes; same values as the eight colour launches);
+// xin and xout must not overlap
+hipError_t launch_hyb_gs8z(gd_dtype s, const GridDesc& G, const HybTables& T, const void* xin, void* xout,
+                           const void* b, hipStream_t st);
 // r = b - A x on a table level; with partials, per-block FP64 sums of r^2
 // in partials[0 .. hyb_residual_blocks(G))
 int64_t hyb_residual_blocks(const GridDesc& G);

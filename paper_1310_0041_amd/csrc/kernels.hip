@@ -530,45 +530,74 @@ __device__ __forceinline__ double bsp_weight(int f, int c, int n, int nc, bool h
   return 0.0;
 }
 
-// sum over the 27 neighbours of (row of A at (i, j, k)) . x, and the diagonal.
+// sum over the 27 neighbours of (row of A at (i, j, k)) . x, and the diagonal,
+// with fetch(qx, qy, qz) giving the current value of sample (qx, qy, qz) and
+// tab(a, r, p) row r of axis a's table at sample p.
 // Branch-free: a neighbour outside the grid is read at a clamped index and
 // weighted by its table entry, which is 0 (the first sample has no lower and
-// the last no upper coupling on every level), so all 27 loads issue at once.
-template <typename S>
-__device__ __forceinline__ void hyb_row(const HybAxes& A, const GridDesc& G, const S* __restrict__ x, int i, int j,
-                                        int k, double& ax, double& diag) {
+// the last no upper coupling on every level), so all 27 reads issue at once.
+// Every table-level relaxation goes through this one body, so they agree
+// bit for bit whatever memory the values come from.
+template <typename TB, typename F>
+__device__ __forceinline__ void hyb_row_f(const HybAxes& A, const GridDesc& G, int i, int j, int k, TB&& tab,
+                                          F&& fetch, double& ax, double& diag) {
+  // Every multiply-add is written out: left to the compiler, the choice of
+  // which product joins an add differs between call sites, and the 27-point
+  // coefficients are short sums of larger products (the finite-element
+  // stencils cancel), so it moved them by ~1e-11 relative.
+#pragma clang fp contract(off)
   const int n[3] = {G.nx, G.ny, G.nz}, c[3] = {i, j, k};
   double m[3][3], kk[3][3];  // [axis][offset + 1]
   int q[3][3];               // clamped neighbour index [axis][offset + 1]
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double* T = A.t[a];
     const int na = n[a], p = c[a];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      m[a][d] = T[d * na + p];
-      kk[a][d] = T[(3 + d) * na + p];
+      m[a][d] = tab(a, d, p);
+      kk[a][d] = tab(a, 3 + d, p);
       q[a][d] = min(max(p + d - 1, 0), na - 1);
     }
   }
-  const int64_t pl = (int64_t)G.px * G.ny;
-  const S* base = x + G.off;
-  double s = 0.0;
+  // x-axis factors alpha M_x + w_x K_x
+  double px_[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) px_[d] = __builtin_fma(A.w[0], kk[0][d], A.alpha * m[0][d]);
+  // one partial sum per neighbour plane (three independent chains of nine
+  // multiply-adds instead of one of 27), added in a fixed order
+  double s[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) {
-      const double myz = m[1][dy] * m[2][dz], kyz = kk[1][dy] * m[2][dz], mkz = m[1][dy] * kk[2][dz];
-      const S* row = base + q[2][dz] * pl + (int64_t)q[1][dy] * G.px;
+      const double myz = m[1][dy] * m[2][dz];
+      const double yz = __builtin_fma(A.w[2], m[1][dy] * kk[2][dz], A.w[1] * (kk[1][dy] * m[2][dz]));
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
-        const double coef = (A.alpha * m[0][dx] + A.w[0] * kk[0][dx]) * myz + m[0][dx] * (A.w[1] * kyz + A.w[2] * mkz);
-        s += coef * ld64(row + q[0][dx]);
+        const double coef = __builtin_fma(m[0][dx], yz, px_[dx] * myz);
+        s[dz] = __builtin_fma(coef, fetch(q[0][dx], q[1][dy], q[2][dz]), s[dz]);
       }
     }
-  ax = s;
-  diag = (A.alpha * m[0][1] + A.w[0] * kk[0][1]) * m[1][1] * m[2][1] +
-         m[0][1] * (A.w[1] * kk[1][1] * m[2][1] + A.w[2] * m[1][1] * kk[2][1]);
+  ax = (s[0] + s[1]) + s[2];
+  diag = __builtin_fma(m[0][1], __builtin_fma(A.w[2], m[1][1] * kk[2][1], A.w[1] * (kk[1][1] * m[2][1])),
+                       px_[1] * (m[1][1] * m[2][1]));
+}
+
+// the same with the values in a level array x
+template <typename S>
+__device__ __forceinline__ void hyb_row(const HybAxes& A, const GridDesc& G, const S* __restrict__ x, int i, int j,
+                                        int k, double& ax, double& diag) {
+  const int64_t pl = (int64_t)G.px * G.ny;
+  const S* base = x + G.off;
+  const int n[3] = {G.nx, G.ny, G.nz};
+  hyb_row_f(A, G, i, j, k, [&](int a, int r, int p) { return A.t[a][r * n[a] + p]; },
+            [&](int qx, int qy, int qz) { return ld64(base + qz * pl + (int64_t)qy * G.px + qx); }, ax, diag);
+}
+
+// the Gauss-Seidel update of one sample from its row (a zero diagonal, a
+// sample with no coupling at all, is set to 0)
+__device__ __forceinline__ double hyb_update(double xc, double bv, double ax, double d) {
+  return d != 0.0 ? xc + (bv - ax) / d : 0.0;
 }
 
 // Table-level kernels run on a 3-D launch: a block is 64 x 4 samples of one
@@ -592,8 +621,123 @@ k_hyb_gs8(GridDesc G, HybAxes A, int colour, S* __restrict__ x, const S* __restr
     double ax, d;
     hyb_row(A, G, x, i, j, k, ax, d);
     const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
-    const double xc = ld64(x + v);
-    st64(x + v, d != 0.0 ? xc + (ld64(b + v) - ax) / d : 0.0);
+    st64(x + v, hyb_update(ld64(x + v), ld64(b + v), ax, d));
+  }
+}
+
+// The same sweep in two launches, one per z-parity ck of the planes.  The
+// 8-colour order (colours 0..3 on every even plane before colours 4..7 on
+// the odd ones) means: an even plane reads its odd neighbour planes as they
+// were before the sweep, an odd plane reads its even neighbours as they are
+// after it, and within a plane the four colours (x, y parity (0,0), (1,0),
+// (0,1), (1,1)) follow each other.  A block owns an HGX x HGY tile of a run
+// of planes of its parity; the plane's window (tile plus a ring of HGR) and
+// the two neighbour planes sit in LDS, and the four colours run in turn on
+// the tile widened by 3, 2, 1 and 0 samples (a colour reads the colours
+// before it up to one sample away), so the tile's new values need no other
+// block.  Reads come from xin (this parity's planes, before the sweep) and
+// xnb (the neighbour planes: xin for ck = 0, xout for ck = 1); the tile's
+// new values go to xout.  Every update is hyb_row_f / hyb_update on the
+// values the colour launches would read, so the result is theirs bit for bit.
+constexpr int HGX = 64, HGY = 16, HGR = 4, HGZ = 4;  // tile, ring, planes of a parity per block
+constexpr int HGWX = HGX + 2 * HGR, HGWY = HGY + 2 * HGR;
+constexpr int HGT = 256;
+
+// LDS cell of a window: the storage type, 16-bit ones as raw bits (their
+// types have constructors, which __shared__ arrays may not have); values go
+// in and out through st64 / ld64, so they round exactly as stores to a level
+template <typename S> struct HybLds { using T = S; };
+template <> struct HybLds<__half> { using T = uint16_t; };
+template <> struct HybLds<__hip_bfloat16> { using T = uint16_t; };
+template <typename S>
+__device__ __forceinline__ double hl_ld(typename HybLds<S>::T w) {
+  const S v = __builtin_bit_cast(S, w);
+  return ld64(&v);
+}
+template <typename S>
+__device__ __forceinline__ typename HybLds<S>::T hl_st(double v) {
+  S t;
+  st64(&t, v);
+  return __builtin_bit_cast(typename HybLds<S>::T, t);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(HGT)
+k_hyb_gs8z(GridDesc G, HybAxes A, int ck, const S* xin, const S* xnb, S* xout, const S* __restrict__ b) {
+  using LT = typename HybLds<S>::T;
+  __shared__ __align__(16) LT W[3][HGWY][HGWX];  // plane slots: the tile's plane and its two neighbours
+  __shared__ double TXs[6][HGWX], TYs[6][HGWY];  // the x and y tables over the window
+  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int ntx = (nx + HGX - 1) / HGX;
+  const int x0 = (int)(blockIdx.x % ntx) * HGX, y0 = (int)(blockIdx.x / ntx) * HGY;
+  const int wx0 = x0 - HGR, wy0 = y0 - HGR;  // grid coordinates of the window's corner
+  const int64_t pl = (int64_t)G.px * ny;
+  const int mz = (nz - ck + 1) / 2;
+  const int kk0 = blockIdx.y * HGZ, kk1 = min(kk0 + HGZ, mz);
+  const int tid = threadIdx.x;
+  for (int m = tid; m < 6 * HGWX; m += HGT) {
+    const int r = m / HGWX, w = m - r * HGWX, g = wx0 + w;
+    if (g >= 0 && g < nx) TXs[r][w] = A.t[0][r * nx + g];
+  }
+  for (int m = tid; m < 6 * HGWY; m += HGT) {
+    const int r = m / HGWY, w = m - r * HGWY, g = wy0 + w;
+    if (g >= 0 && g < ny) TYs[r][w] = A.t[1][r * ny + g];
+  }
+  // the window of plane k of src into slot sl (samples outside the grid are never read)
+  auto load = [&](int sl, const S* src, int k) {
+    const LT* p = reinterpret_cast<const LT*>(src + G.off + k * pl);
+    for (int m = tid; m < HGWX * HGWY; m += HGT) {
+      const int wy = m / HGWX, wx = m - wy * HGWX;
+      const int gx = wx0 + wx, gy = wy0 + wy;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) W[sl][wy][wx] = p[(int64_t)gy * G.px + gx];
+    }
+  };
+  int lo = 1, hi = 2;
+  constexpr int cen = 0;
+  for (int kk = kk0; kk < kk1; ++kk) {
+    const int k = 2 * kk + ck;
+    if (kk > kk0) {
+      __syncthreads();  // the previous plane's reads of every slot are done
+      const int t = lo;  // plane k - 1 is the previous plane's k + 1
+      lo = hi;
+      hi = t;
+    } else if (k > 0) {
+      load(lo, xnb, k - 1);
+    }
+    load(cen, xin, k);
+    if (k + 1 < nz) load(hi, xnb, k + 1);
+    __syncthreads();
+    const int ls = k > 0 ? lo : cen, hs = k + 1 < nz ? hi : cen;  // clamped planes read the tile's own
+    auto fetch = [&](int qx, int qy, int qz) {
+      const int sl = qz == k ? cen : (qz < k ? ls : hs);
+      return hl_ld<S>(W[sl][qy - wy0][qx - wx0]);
+    };
+    auto tab = [&](int a, int r, int p) {
+      return a == 0 ? TXs[r][p - wx0] : (a == 1 ? TYs[r][p - wy0] : A.t[2][r * nz + p]);
+    };
+    const S* bk = b + G.off + k * pl;
+#pragma unroll 1
+    for (int ph = 0; ph < 4; ++ph) {
+      const int pi = ph & 1, pj = ph >> 1, r = 3 - ph;  // colour (pi, pj) on the tile widened by r
+      const int xa = max(x0 - r, 0), xb = min(x0 + HGX + r, nx), ya = max(y0 - r, 0), yb = min(y0 + HGY + r, ny);
+      const int ia = xa + ((xa & 1) ^ pi), ja = ya + ((ya & 1) ^ pj);
+      const int nu = xb > ia ? (xb - ia + 1) / 2 : 0, nv = yb > ja ? (yb - ja + 1) / 2 : 0;
+      for (int m = tid; m < nu * nv; m += HGT) {
+        const int v = m / nu, u = m - v * nu;
+        const int i = ia + 2 * u, j = ja + 2 * v;
+        double ax, d;
+        hyb_row_f(A, G, i, j, k, tab, fetch, ax, d);
+        LT& c = W[cen][j - wy0][i - wx0];
+        c = hl_st<S>(hyb_update(hl_ld<S>(c), ld64(bk + (int64_t)j * G.px + i), ax, d));
+      }
+      __syncthreads();
+    }
+    LT* o = reinterpret_cast<LT*>(xout + G.off + k * pl);
+    for (int m = tid; m < HGX * HGY; m += HGT) {
+      const int ty = m / HGX, tx = m - ty * HGX;
+      const int gx = x0 + tx, gy = y0 + ty;
+      if (gx < nx && gy < ny) o[(int64_t)gy * G.px + gx] = W[cen][gy - wy0][gx - wx0];
+    }
   }
 }
 
@@ -1013,6 +1157,25 @@ hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int
                                  (const TT*)b)
   GD_DISPATCH_S(s, L)
 #undef L
+  return last();
+}
+
+hipError_t launch_hyb_gs8z(gd_dtype s, const GridDesc& G, const HybTables& T, const void* xin, void* xout,
+                           const void* b, hipStream_t st) {
+  if ((int64_t)G.nx * G.ny * G.nz == 0) return hipSuccess;
+  HybAxes A{{T.t[0], T.t[1], T.t[2]}, T.alpha, {T.w[0], T.w[1], T.w[2]}};
+  const int64_t tiles = (int64_t)((G.nx + HGX - 1) / HGX) * ((G.ny + HGY - 1) / HGY);
+  for (int ck = 0; ck < 2; ++ck) {
+    const int64_t mz = (G.nz - ck + 1) / 2;
+    if (mz == 0) continue;
+    const dim3 grid((unsigned)tiles, (unsigned)((mz + HGZ - 1) / HGZ));
+    // even planes read their neighbours before the sweep (xin), odd ones after it (xout)
+    const void* nb = ck == 0 ? xin : xout;
+#define L(TT) hipLaunchKernelGGL(k_hyb_gs8z<TT>, grid, dim3(HGT), 0, st, G, A, ck, (const TT*)xin, (const TT*)nb, \
+                                 (TT*)xout, (const TT*)b)
+    GD_DISPATCH_S(s, L)
+#undef L
+  }
   return last();
 }
 

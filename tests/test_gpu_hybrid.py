@@ -203,6 +203,69 @@ def test_sp_hybrid_uneven_batch_fp32_and_mixed(gd):
             assert per[i]["rel_residual"] <= kw.get("rel_tol", 1e-6)
 
 
+@pytest.mark.parametrize("disc", [1, 2])
+@pytest.mark.parametrize("storage,dt", [("F32", torch.float32), ("F64", torch.float64), ("F16", torch.float16)])
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_table_relaxation_by_plane_parity_equals_colour_launches(gd, monkeypatch, disc, storage, dt, use_graph):
+    """The table levels' 8-colour Gauss-Seidel sweep as two launches (even
+    planes, then odd planes; each block's four in-plane colours on a tile
+    widened by 3, 2, 1, 0 samples in LDS) gives the eight in-place colour
+    launches' values bit for bit: whole solves, several 64 x 16 tiles with
+    ragged edges, odd and single-plane grids, with and without graph replay
+    (GD_HYB_COLOURS forces one form; by default the size of a level picks it)."""
+    if disc == 2 and storage == "F16":
+        pytest.skip("the Linear discretisation has no FP64 refinement")
+    for shape in [(9, 40, 150), (2, 37, 70), (6, 1, 45), (13, 17, 66), (1, 37, 70)]:
+        say("table relaxation by plane parity", disc, storage, use_graph, shape)
+        rng = np.random.default_rng(1310)
+        I0 = torch.from_numpy(rng.uniform(0, 60, shape)).to(dt).cuda()
+        kw = dict(storage=getattr(gd, storage), discretization=disc, use_graph=use_graph, rel_tol=1e-6, check=False,
+                  out_dtype=torch.float64)
+        if storage == "F16":
+            kw["fp64_refine"] = 1
+        if shape[0] > 1:  # (one plane: the AD right-hand side is zero, no cycle runs)
+            monkeypatch.setenv("GD_HYB_COLOURS", "1")
+            ref, rep_ref = gd.smooth_z(I0, (1.0, 1.0, 4.0), **kw)
+            monkeypatch.setenv("GD_HYB_COLOURS", "2")
+            got, rep = gd.smooth_z(I0, (1.0, 1.0, 4.0), **kw)
+            assert rep["cycles"] == rep_ref["cycles"] and rep["cycles"] > 0
+            assert torch.equal(got.view(torch.int64), ref.view(torch.int64)), shape
+        # two V-cycles of the hierarchy call on a random system
+        if disc == 1 or storage != "F16":
+            x0 = torch.from_numpy(rng.standard_normal(shape)).to(dt)
+            b = torch.from_numpy(rng.standard_normal(shape)).to(dt)
+            outs = []
+            for env in ("1", "2"):
+                monkeypatch.setenv("GD_HYB_COLOURS", env)
+                h = gd.Hierarchy(shape, 0.01, (1.0, 1.0, 0.5), dt, discretization=disc, pre_smooth=2, post_smooth=3)
+                x = x0.clone().cuda()
+                h.vcycle(x, b.cuda(), 2)
+                h.close()
+                outs.append(x.cpu())
+            assert torch.equal(outs[0].view(torch.int16 if dt == torch.float16 else torch.int32 if dt == torch.float32
+                                            else torch.int64),
+                               outs[1].view(torch.int16 if dt == torch.float16 else torch.int32 if dt == torch.float32
+                                            else torch.int64)), shape
+
+
+@pytest.mark.parametrize("disc,shape", [(2, (16, 256, 256)), (1, (32, 256, 300))])
+def test_table_relaxation_default_choice(gd, monkeypatch, disc, shape):
+    """Levels of at least 8 rows and 2^20 samples take the plane-parity form
+    by default (Linear: level 0 here; Hybrid: the z-halved level 1), the rest
+    the colour launches: the mix gives the colour launches' answer bit for
+    bit."""
+    say("table relaxation default choice", disc, shape)
+    rng = np.random.default_rng(1311)
+    I0 = torch.from_numpy(rng.uniform(0, 60, shape)).float().cuda()
+    kw = dict(discretization=disc, rel_tol=1e-6, check=False, out_dtype=torch.float64)
+    monkeypatch.setenv("GD_HYB_COLOURS", "1")
+    ref, rep_ref = gd.smooth_z(I0, (1.0, 1.0, 4.0), **kw)
+    monkeypatch.setenv("GD_HYB_COLOURS", "0")
+    got, rep = gd.smooth_z(I0, (1.0, 1.0, 4.0), **kw)
+    assert rep["cycles"] == rep_ref["cycles"] and rep["cycles"] > 0
+    assert torch.equal(got.view(torch.int64), ref.view(torch.int64))
+
+
 @pytest.mark.parametrize("shape", [(9, 17, 30), (5, 8, 8), (1, 12, 40), (16, 3, 5), (2, 2, 2), (1, 1, 1)])
 @pytest.mark.parametrize("alpha,w", SYSTEMS)
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
