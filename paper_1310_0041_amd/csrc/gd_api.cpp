@@ -265,6 +265,10 @@ struct Hier {
   };
   std::unique_ptr<PlaneNorms> planes;
   bool flags_set = false;  // some grid descriptor carries a skip / alt flag
+  // level l (>= 1) holds a stale x that counts as zero: the restriction into
+  // it did not clear x, and its next relaxation starts from zero (kept here,
+  // not in a Cycler, because captured cycle pieces end with that restriction)
+  std::vector<char> czero;
 };
 
 static void coarsen_factors(const GridDesc& g, int f[3]) {
@@ -1006,8 +1010,10 @@ struct Cycler {
   bool x0_zero = false;  // level 0's x is zero before its next sweep (which then does not read it)
   void sweep(int l, const void* ec) {
     Level& L = H.lv[l];
-    const bool xz = l == 0 && x0_zero;
+    if (H.czero.size() < H.lv.size()) H.czero.assign(H.lv.size(), 0);
+    const bool xz = l == 0 ? x0_zero : H.czero[l] != 0;
     if (l == 0) x0_zero = false;
+    else H.czero[l] = 0;
     H.count(l, (xz ? 2.0 : 3.0) * P());  // read x and b, write x
     if (ec) H.count(l + 1, P());
     if (hyb && table_level(l)) {  // 27-point level: 8-colour Gauss-Seidel
@@ -1043,12 +1049,23 @@ struct Cycler {
     for (int i = 0; i < n; ++i) sweep(l, i == 0 ? ec : nullptr);
   }
   // residual of level l restricted into level l + 1 (its x zeroed);
-  // with `norm`, per-grid sum r^2 lands in H.dred
-  void restrict_to(int l, bool norm) {
+  // with `norm`, per-grid sum r^2 lands in H.dred.  lazy: level l + 1 is
+  // relaxed next (a V-cycle's descent), so where that relaxation can start
+  // from zero without reading x, x is left as it is and flagged instead
+  void restrict_to(int l, bool norm, bool lazy = true) {
     Level& L = H.lv[l];
     Level& C = H.lv[l + 1];
-    H.count(l, 2.0 * P());      // read x and b
-    H.count(l + 1, 2.0 * P());  // write coarse b and x
+    if (H.czero.size() < H.lv.size()) H.czero.assign(H.lv.size(), 0);
+    const int last = (int)H.lv.size() - 1;
+    bool lz = false;
+    if (lazy && !hyb && (pre > 0 || l + 1 == last)) {
+      Geom gc = H.g_sw(l + 1);
+      gc.quad = quad;
+      lz = sweep_starts_from_zero_ok(H.s, gc);
+    }
+    H.czero[l + 1] = lz ? 1 : 0;
+    H.count(l, 2.0 * P());                   // read x and b
+    H.count(l + 1, (lz ? 1.0 : 2.0) * P());  // write coarse b (and x)
     if (hyb) H.count(l, 2.0 * P());  // r written and read again
     if (hyb) {  // residual into the level's spare buffer, then P^T
       if (!table_level(l)) {
@@ -1061,7 +1078,7 @@ struct Cycler {
       HIP_TRY(launch_hyb_restrict(H.s, L.h[0], L.xt, C.b, C.x, st));
       return;
     }
-    HIP_TRY(launch_restrict_z(H.s, H.g_rz(l), L.x, L.b, C.b, C.x, norm ? H.partials : nullptr, st));
+    HIP_TRY(launch_restrict_z(H.s, H.g_rz(l), L.x, L.b, C.b, lz ? nullptr : C.x, norm ? H.partials : nullptr, st));
     if (norm) HIP_TRY(launch_reduce(H.partials, L.rz.d_b0, H.ngrids, 1, H.dred, st));
   }
   // coarse-grid correction of level l (levels l+1 .. bottom), then post-smoothing
@@ -1098,7 +1115,7 @@ struct Cycler {
   // coarse solution interpolated as the initial guess and one V-cycle run
   void fmg() {
     const int last = (int)H.lv.size() - 1;
-    for (int l = 0; l < last; ++l) restrict_to(l, false);  // x = 0: r = b
+    for (int l = 0; l < last; ++l) restrict_to(l, false, false);  // x = 0: r = b
     smooth(last, 1);
     for (int l = last - 1; l >= 0; --l) {
       if (hyb) HIP_TRY(launch_hyb_prolong(H.s, H.lv[l].h[0], H.lv[l + 1].x, H.lv[l].x, st));
