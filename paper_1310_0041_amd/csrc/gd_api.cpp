@@ -262,8 +262,10 @@ struct Hier {
     int64_t part_blocks = 0;
     double* red = nullptr;   // device: 2 sums per plane
     std::vector<double> host;  // 2 sums per plane
+    int64_t* tseg = nullptr;   // device: nz + 1 block offsets of the table residual's planes
   };
   std::unique_ptr<PlaneNorms> planes;
+  bool stack_z = false;  // z indexes independent slices: the table operators have M_z = Id, K_z = 0
   bool flags_set = false;  // some grid descriptor carries a skip / alt flag
   // level l (>= 1) holds a stale x that counts as zero: the restriction into
   // it did not clear x, and its next relaxation starts from zero (kept here,
@@ -889,6 +891,12 @@ static void ensure_tables(Hier& H, int disc) {
     for (int i = 0; i < n; ++i) {
       if (i > 0) { K[a].lo[i] = -1.0; K[a].di[i] += 1.0; }
       if (i + 1 < n) { K[a].up[i] = -1.0; K[a].di[i] += 1.0; }
+    }
+    if (a == 2 && H.stack_z) {  // a stack of slices: no coupling along z
+      std::fill(K[a].lo.begin(), K[a].lo.end(), 0.0);
+      std::fill(K[a].di.begin(), K[a].di.end(), 0.0);
+      std::fill(K[a].up.begin(), K[a].up.end(), 0.0);
+      continue;
     }
     if (disc == 2 && n > 1)
       for (int i = 0; i < n; ++i) {
@@ -1817,6 +1825,114 @@ static Outcome solve_linear_sp(Hier& H, const Problem& P, const gd_solve_opts& o
   return R;
 }
 
+// ||b - A x|| of every plane of level 0 (table operator T), r left in r
+// (a stack of independent slices: one norm per slice)
+static std::vector<double> table_planes(Hier& H, const HybTables& T, const void* x, const void* b, void* r,
+                                        hipStream_t st) {
+  auto& pn = *H.planes;
+  const GridDesc& g0 = H.lv[0].h[0];
+  const int nz = g0.nz;
+  const int64_t nb = hyb_residual_blocks(g0, true);
+  if (!pn.tseg) {
+    std::vector<int64_t> sg(nz + 1);
+    for (int z = 0; z <= nz; ++z) sg[z] = (int64_t)z * (nb / nz);
+    pn.tseg = (int64_t*)H.alloc(sg.size() * sizeof(int64_t));
+    HIP_TRY(hipMemcpy(pn.tseg, sg.data(), sg.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (nb > pn.part_blocks) {
+      pn.part = (double*)H.alloc(2 * nb * sizeof(double));
+      pn.part_blocks = nb;
+    }
+    if (!pn.red) {
+      pn.red = (double*)H.alloc(2 * (size_t)nz * sizeof(double));
+      pn.host.resize(2 * (size_t)nz);
+    }
+  }
+  HIP_TRY(launch_hyb_residual(H.s, g0, T, x, b, r, st, pn.part, true));
+  HIP_TRY(launch_reduce(pn.part, pn.tseg, nz, 1, pn.red, st));
+  HIP_TRY(hipMemcpyAsync(pn.host.data(), pn.red, (size_t)nz * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<double> out(nz);
+  for (int z = 0; z < nz; ++z) out[z] = std::sqrt(pn.host[z]);
+  return out;
+}
+
+// The Linear SP of a stack of equal slices as one grid (z indexes the
+// slices: M_z = Id, w_z = 0, z never coarsened): the right-hand side and
+// the residuals of solve_linear_sp with norms per slice; every slice must
+// meet the tolerance against its own right-hand side.
+static Outcome solve_linear_sp_stack(Hier& H, const Problem& P, const gd_solve_opts& o, hipStream_t st) {
+  prep(H, o);
+  Level& L0 = H.lv[0];
+  const GridDesc& g0 = L0.h[0];
+  const size_t es = dsize(H.s);
+  const double a0 = H.acct;
+  HybTables Ta = H.lin[0];  // alpha Mx My only
+  Ta.w[0] = Ta.w[1] = Ta.w[2] = 0.0;
+  Outcome R;
+  HIP_TRY(hipMemsetAsync(L0.b, 0, L0.total * es, st));
+  HIP_TRY(launch_load_comb(P.tin, P.t1, H.s, g0, P.I0, P.I1, -1.0, 1.0, L0.x, st));
+  HIP_TRY(launch_hyb_residual(H.s, g0, Ta, L0.x, L0.b, L0.xt, st));
+  HIP_TRY(hipMemcpyAsync(L0.b, L0.xt, L0.total * es, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(launch_load_comb(P.tin, P.t1, H.s, g0, P.I0, nullptr, 1.0, 0.0, L0.x, st));
+  R.bnorm = table_planes(H, H.lin[0], L0.x, L0.b, L0.xt, st);  // the canonical right-hand side per slice
+  HIP_TRY(hipMemsetAsync(L0.b, 0, L0.total * es, st));
+  HIP_TRY(launch_load_comb(P.tin, P.t1, H.s, g0, P.I0, P.I1, 1.0, -1.0, L0.x, st));
+  HIP_TRY(launch_hyb_residual(H.s, g0, Ta, L0.x, L0.b, L0.xt, st));
+  HIP_TRY(hipMemcpyAsync(L0.b, L0.xt, L0.total * es, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemsetAsync(L0.x, 0, L0.total * es, st));
+  H.count(0, 3.0 * (double)dsize(P.tin) + 2.0 * (double)dsize(P.t1) + 14.0 * (double)es);
+  const int nz = g0.nz;
+  double bglob = 0.0;
+  for (double v : R.bnorm) bglob += v * v;
+  bglob = std::sqrt(bglob);
+  Cycler cy(H, st, o);
+  const bool single = H.lv.size() == 1;
+  // the stack's residual triggers the per-slice checks, as in solve_planes
+  bool checking = single;
+  double best = INFINITY, best_worst = INFINITY;
+  int stall = 0, stall_c = 0;
+  R.rel.assign(nz, 0.0);
+  for (;;) {
+    if (single) {
+      cy.smooth(0, 1);
+      R.cycles++;
+    } else {
+      cy.smooth(0, o.pre_smooth);
+      cy.restrict_to(0, true);
+      read_dred(H, 1, st);
+      const double rr = std::sqrt(H.hpin[0]);
+      if (!std::isfinite(rr)) { R.numeric = true; break; }
+      stall = rr < 0.7 * best ? 0 : stall + 1;
+      best = std::min(best, rr);
+      if (rr <= 0.5 * o.rel_tol * denom(bglob) || stall >= 3) checking = true;
+    }
+    const bool last = R.cycles >= o.max_cycles;
+    if (checking || last) {
+      const std::vector<double> c = table_planes(H, H.lin[0], L0.x, L0.b, L0.xt, st);
+      bool bad = false;
+      R.converged = all_below(c, R.bnorm, o.rel_tol, bad);
+      double worst = 0.0;
+      for (int z = 0; z < nz; ++z) {
+        R.rel[z] = c[z] / denom(R.bnorm[z]);
+        worst = std::max(worst, R.rel[z]);
+      }
+      if (bad) { R.numeric = true; break; }
+      if (R.converged || last) break;
+      stall_c = worst < 0.7 * best_worst ? 0 : stall_c + 1;
+      best_worst = std::min(best_worst, worst);
+      if (stall_c >= 3) break;  // the worst slice has reached its floor
+    }
+    if (!single) {
+      cy.correct(0);
+      R.cycles++;
+    }
+  }
+  cy.harvest();
+  finish(H, P, 0, st);
+  R.bytes = H.acct - a0;
+  return R;
+}
+
 static void fill_report(gd_solve_report* rep, const Outcome& R, int g, double secs, int levels,
                         double share = 1.0) {
   rep->fallback_used = 0;
@@ -2120,9 +2236,11 @@ gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1,
   if (o.discretization == 2 && o.fp64_refine)
     return fail(GD_ERR_UNSUPPORTED, "gd_screened_poisson_slices: FP64 refinement is not built for the Linear discretisation");
   hipStream_t st = (hipStream_t)stream;
-  // Hybrid, plain V-cycles, slices of one size and alpha laid out as a stack
-  // (equal pitch, constant stride): one 3-D grid with w_z = 0, per-slice norms
-  bool stack = o.discretization == 1 && !o.fp64_refine && n > 1;
+  // Hybrid (plain V-cycles) or Linear, slices of one size and alpha laid out
+  // as a stack (equal pitch, constant stride): one 3-D grid with w_z = 0 (and
+  // for Linear M_z = Id), per-slice norms
+  bool stack = (o.discretization == 1 || o.discretization == 2) && !o.fp64_refine && n > 1 &&
+               (o.discretization != 2 || n <= 65535);  // (Linear: one launch row of blocks per slice)
   for (int64_t i = 1; stack && i < n; ++i)
     stack = sl[i].nx == sl[0].nx && sl[i].ny == sl[0].ny && sl[i].pitch == sl[0].pitch &&
             sl[i].alpha == sl[0].alpha && sl[i].offset - sl[i - 1].offset == sl[1].offset - sl[0].offset &&
@@ -2133,10 +2251,12 @@ gd_status gd_screened_poisson_slices(const void* I0, gd_dtype t, const void* I1,
       const gd_slice_desc& d = sl[0];
       std::vector<GridSpec> g3{{d.nx, d.ny, n, (double)d.alpha, bx, by, 0.0, d.offset, d.pitch,
                                 sl[1].offset - sl[0].offset}};
-      HierLease H = get_hier("sp-hybrid-stack", g3, o.storage, false, st, o.sweep_tile, o.sweep_quad != 0);
+      HierLease H = get_hier(o.discretization == 2 ? "sp-linear-stack" : "sp-hybrid-stack", g3, o.storage, false, st,
+                             o.sweep_tile, o.sweep_quad != 0);
       if (!H->planes) H->planes = std::make_unique<Hier::PlaneNorms>();
+      H->stack_z = true;
       Problem P{I0, I1, I2, t, tout, false, t1};
-      Outcome R = solve_planes(*H, P, o, st);
+      Outcome R = o.discretization == 2 ? solve_linear_sp_stack(*H, P, o, st) : solve_planes(*H, P, o, st);
       const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (per)
         for (int64_t i = 0; i < n; ++i) fill_report(&per[i], R, (int)i, secs, (int)H->lv.size(), 1.0 / (double)n);

@@ -123,10 +123,11 @@ hipError_t launch_hyb_gs8(gd_dtype s, const GridDesc& G, const HybTables& T, int
 hipError_t launch_hyb_gs8z(gd_dtype s, const GridDesc& G, const HybTables& T, const void* xin, void* xout,
                            const void* b, hipStream_t st);
 // r = b - A x on a table level; with partials, per-block FP64 sums of r^2
-// in partials[0 .. hyb_residual_blocks(G))
-int64_t hyb_residual_blocks(const GridDesc& G);
+// in partials[0 .. hyb_residual_blocks(G, per_plane)); per_plane: every block
+// spans one plane, plane z's blocks at [z B, (z + 1) B), B = blocks / nz
+int64_t hyb_residual_blocks(const GridDesc& G, bool per_plane = false);
 hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T, const void* x, const void* b,
-                               void* r, hipStream_t st, double* partials = nullptr);
+                               void* r, hipStream_t st, double* partials = nullptr, bool per_plane = false);
 // the caller's input I0 (dtype tin, layout ioff / ipy / ipz of G) into a level array of dtype s
 hipError_t launch_load_input(gd_dtype tin, gd_dtype s, const GridDesc& G, const void* in, void* out, hipStream_t st);
 // out = c0 in0 + c1 in1 (FP64 arithmetic): the caller's inputs (layout ioff /

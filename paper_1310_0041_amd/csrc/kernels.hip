@@ -742,17 +742,18 @@ k_hyb_gs8z(GridDesc G, HybAxes A, int ck, const S* xin, const S* xnb, S* xout, c
 }
 
 // r = b - A x on a table level (all samples); with partials, the FP64 sum
-// of r^2 per block (block = x + gx (y + gy z)), in a fixed order
+// of r^2 per block (block = x + gx (y + gy z), a block spanning hz planes),
+// in a fixed order
 template <typename S>
 __global__ void __launch_bounds__(HBX * HBY)
 k_hyb_residual(GridDesc G, HybAxes A, const S* __restrict__ x, const S* __restrict__ b, S* __restrict__ r,
-               double* __restrict__ partials) {
+               double* __restrict__ partials, int hz) {
   __shared__ double red[HBY];
   const int i = blockIdx.x * HBX + threadIdx.x, j = blockIdx.y * HBY + threadIdx.y;
   double rr = 0.0;
   if (i < G.nx && j < G.ny) {
     const int64_t pl = (int64_t)G.px * G.ny;
-    for (int k = blockIdx.z * HZ; k < min((int)(blockIdx.z + 1) * HZ, G.nz); ++k) {
+    for (int k = blockIdx.z * hz; k < min((int)(blockIdx.z + 1) * hz, G.nz); ++k) {
       double ax, d;
       hyb_row(A, G, x, i, j, k, ax, d);
       const int64_t v = G.off + k * pl + (int64_t)j * G.px + i;
@@ -1179,16 +1180,18 @@ hipError_t launch_hyb_gs8z(gd_dtype s, const GridDesc& G, const HybTables& T, co
   return last();
 }
 
-int64_t hyb_residual_blocks(const GridDesc& G) {
+int64_t hyb_residual_blocks(const GridDesc& G, bool per_plane) {
   const dim3 g = hyb_grid(G.nx, G.ny, G.nz);
-  return (int64_t)g.x * g.y * g.z;
+  return per_plane ? (int64_t)g.x * g.y * G.nz : (int64_t)g.x * g.y * g.z;
 }
 
 hipError_t launch_hyb_residual(gd_dtype s, const GridDesc& G, const HybTables& T, const void* x, const void* b,
-                               void* r, hipStream_t st, double* partials) {
+                               void* r, hipStream_t st, double* partials, bool per_plane) {
   HybAxes A{{T.t[0], T.t[1], T.t[2]}, T.alpha, {T.w[0], T.w[1], T.w[2]}};
-#define L(TT) hipLaunchKernelGGL(k_hyb_residual<TT>, hyb_grid(G.nx, G.ny, G.nz), dim3(HBX, HBY), 0, st, G, A, \
-                                 (const TT*)x, (const TT*)b, (TT*)r, partials)
+  const int hz = per_plane ? 1 : HZ;
+  const dim3 grid((unsigned)((G.nx + HBX - 1) / HBX), (unsigned)((G.ny + HBY - 1) / HBY), (unsigned)((G.nz + hz - 1) / hz));
+#define L(TT) hipLaunchKernelGGL(k_hyb_residual<TT>, grid, dim3(HBX, HBY), 0, st, G, A, (const TT*)x, (const TT*)b, \
+                                 (TT*)r, partials, hz)
   GD_DISPATCH_S(s, L)
 #undef L
   return last();

@@ -339,6 +339,39 @@ def test_linear_sp_fp64(gd, shape):
     assert np.linalg.norm(ref - solvers.sp_dct(I0, I1, 0.01)) > 1e-5 * np.linalg.norm(ref)
 
 
+def test_linear_sp_stack_as_one_grid(gd):
+    """Linear SP of equal slices laid out as a stack runs as one 3-D grid
+    (M_z = Id, w_z = 0, z never coarsened) with per-slice norms: by the
+    oracle's own residual of the Linear system every slice meets the
+    tolerance (FP32 storage; the library's residual is that of the FP32-stored
+    correction system, so the oracle's may exceed it by FP32 rounding).  The
+    same slices out of stack order take the slice-by-slice route: the same bar,
+    and the two answers agree (loosely: at alpha = 0.01 the operator's
+    smallest eigenvalue, alpha times the mass matrices', makes the residual a
+    weak bound on the error)."""
+    say("linear SP stack as one grid")
+    nz, ny, nx = 6, 40, 72
+    I0 = synth.make_stack(synth.StackSpec(nx, ny, nz, (4.0, 40.0), True, 13100432)).numpy()
+    rng = np.random.default_rng(13100432)
+    I1 = I0 * rng.uniform(0.95, 1.05, (nz, 1, 1)) + rng.uniform(-2, 2, (nz, 1, 1))
+    x0, x1 = torch.from_numpy(I0).float().cuda(), torch.from_numpy(I1).float().cuda()
+    q0, q1 = x0.double().cpu().numpy(), x1.double().cpu().numpy()
+    out, rep, per = gd.screened_poisson_stack(x0, x1, 0.01, discretization=2, out_dtype=torch.float64)
+    got = out.cpu().numpy()
+    assert rep["status"] == 0 and max(p["rel_residual"] for p in per) <= 1e-6
+    res = linear.sp_relative_residuals(got, q0, q1, 0.01)
+    assert res.max() <= 2e-6, res
+    order = np.arange(nz)[::-1]
+    descs = gd.make_slice_descs(order * nx * ny, nx, ny, 0.01)
+    out2, rep2, per2 = gd.screened_poisson_slices(x0.reshape(-1), x1.reshape(-1), descs, discretization=2,
+                                                  out_dtype=torch.float64)
+    got2 = out2.cpu().numpy().reshape(nz, ny, nx)
+    assert max(p["rel_residual"] for p in per2) <= 1e-6
+    assert linear.sp_relative_residuals(got2, q0, q1, 0.01).max() <= 2e-6
+    for z in range(nz):
+        assert np.linalg.norm(got2[z] - got[z]) / np.linalg.norm(got[z]) <= 1e-4, z
+
+
 def test_linear_sp_fp32_uneven(gd):
     say("linear SP f32 batch")
     meta = synth.make_slice_batch(nslices=5, lo=16, hi=120, seed=82, dtype=torch.float32)
