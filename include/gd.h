@@ -101,9 +101,16 @@ typedef struct {
                            trilinear B-spline finite elements on every level
                            (27-point, a different discrete answer; no FP64
                            refinement, not for the gradient-modulation
-                           filter).  Slice batches with 1 or 2 solve every
-                           slice as a one-plane grid of its own, in turn
-                           (slices of one size share a cached hierarchy). */
+                           filter).  Slice batches with 1 or 2: slices of
+                           one size and alpha laid out as a stack (equal
+                           pitch, constant offset step of at least pitch*ny)
+                           are solved as one 3-D grid with no coupling along
+                           the stack (w_z = 0; for 2 also M_z = Id), each
+                           slice checked against its own right-hand side
+                           (Hybrid with FP64 refinement excluded); other
+                           batches solve every slice as a one-plane grid of
+                           its own, in turn (slices of one size share a
+                           cached hierarchy). */
   int sweep_quad;       /* 1 (default): the relaxation of FP16/BF16 level
                            arrays, and of FP32 3-D grids, runs in its quad
                            form (four x cells per thread, one aligned
@@ -194,8 +201,10 @@ gd_status gd_noalloc_scratch_bytes(int64_t* bytes);
  * result come back without rounding to the 16-bit storage type of I0.
  * Every slice is iterated until its own relative residual <= rel_tol.
  * per_slice (host array of nslices, or NULL) receives each slice's final
- * report; rep (or NULL) the batch summary with rel_residual = the largest
- * slice residual.  nslices = 0 is an empty batch (GD_OK, nothing touched);
+ * report (its cycles: those it took before leaving the batch, or for a
+ * Hybrid / Linear stack solved as one grid those of the whole stack); rep
+ * (or NULL) the batch summary with rel_residual = the largest slice
+ * residual.  nslices = 0 is an empty batch (GD_OK, nothing touched);
  * nslices < 0, zero-sized slices, alpha <= 0 or another i1_t are
  * GD_ERR_INVALID. */
 gd_status gd_screened_poisson_slices(const void* I0, gd_dtype in_t, const void* I1, gd_dtype i1_t,
