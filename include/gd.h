@@ -138,8 +138,9 @@ typedef struct {
                              launch, the bytes the kernel must read and write
                              per cell (e.g. 3 x storage bytes for a sweep)
                              times the cells it covers, summed on the host; a
-                             slice's report carries its share by cells (0 for
-                             gd_fcg_solve)                                     */
+                             slice's report carries its share by cells; for
+                             gd_fcg_solve the V-cycles and Krylov vector
+                             kernels, not the net's convolutions           */
 } gd_solve_report;
 
 /* One slice of a batched screened-Poisson call (Eq. (2) per slice). */

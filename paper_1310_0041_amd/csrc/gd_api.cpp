@@ -2445,6 +2445,7 @@ static void mg_apply(gd_hierarchy* h, const void* r, void* z, hipStream_t st, bo
   if (no_post) cy.post0 = 0;
   cy.full(0);
   HIP_TRY(hipMemcpy2DAsync(z, wb, L0.x, pb, wb, rows, hipMemcpyDeviceToDevice, st));
+  H.count(0, 4.0 * (double)es);  // r in, x cleared, z out (the cycle counts itself)
 }
 
 static double reduce1(Hier& H, hipStream_t st) {
@@ -3163,7 +3164,9 @@ gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int
     const Geom g = H.g_ew(0);
     int mode = precond, fallback = 0, it = 0;
     double bn = 0.0, rn = 0.0;
+    const double a0 = H.acct;  // algorithmic bytes: V-cycles and vector kernels (4 B a value), not the net
     auto residual = [&]() {  // r = b - A x, returns ||r||, sets ||b||
+      H.count(0, 12.0);
       HIP_TRY(launch_general_residual(H.s, g, x, b, r, H.partials, st));
       HIP_TRY(launch_reduce(H.partials, H.lv[0].ew.d_b0, 1, 2, H.dred, st));
       read_dred(H, 2, st);
@@ -3177,6 +3180,7 @@ gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int
         if (gd_net_forward(net, (const float*)r, (float*)z, g0.nx, g0.ny, g0.nz, st) != GD_OK) return false;
       } else if (m == 2 || m == 3) {
         // z += net(r - A z); q still holds A p of this iteration and must survive
+        H.count(0, 24.0);  // the residual and the sum
         HIP_TRY(launch_general_residual(H.s, g, z, r, t, H.partials, st));
         if (gd_net_forward(net, (const float*)t, (float*)u, g0.nx, g0.ny, g0.nz, st) != GD_OK) return false;
         set_coef(H, 1.0, 1.0, st);
@@ -3200,8 +3204,10 @@ gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int
       if (restart) {
         if (!precondition(mode)) { mode = 0; fallback = 1; precondition(0); }
         HIP_TRY(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, st));
+        H.count(0, 8.0);
         restart = false;
       }
+      H.count(0, 8.0 + 8.0 + 24.0);  // q = A p with p.q, p.r, the x and r update
       HIP_TRY(launch_apply_dot(H.s, g, p, q, H.partials, st));
       const double pq = reduce1(H, st);
       HIP_TRY(launch_dot(H.s, g, p, r, H.partials, st));
@@ -3223,6 +3229,7 @@ gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int
       }
       if (rn <= rel_tol * den) continue;
       if (!precondition(mode)) { mode = 0; fallback = 1; restart = true; continue; }
+      H.count(0, 8.0 + 12.0);  // z.q, p = z + beta p
       HIP_TRY(launch_dot(H.s, g, z, q, H.partials, st));
       const double zq = reduce1(H, st);
       set_coef(H, 1.0, -zq / pq, st);
@@ -3234,7 +3241,7 @@ gd_status gd_fcg_solve(gd_hierarchy* h, gd_net* net, void* x, const void* b, int
       rep->cycles = it;
       rep->refine_steps = 0;
       rep->fallback_used = fallback;
-      rep->bytes = 0.0;
+      rep->bytes = H.acct - a0;
       rep->rel_residual = rtrue / den;
       rep->b_norm = bn;
       rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

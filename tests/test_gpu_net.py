@@ -206,6 +206,8 @@ def test_fcg_solution_matches_oracle(gd, trained, precond):
     rep = h.fcg(x, b, net=net, precond=precond, rel_tol=1e-6, max_iter=300, check=False)
     h.close()
     assert rep["status"] == 0 and rep["rel_residual"] <= 1e-6, rep
+    # algorithmic bytes: at least a residual pass and one iteration's vector kernels (4 B a value)
+    assert rep["bytes"] >= (12 + 40) * x.numel(), rep
     ref = solvers.dct_solve(bnp, ALPHA, (1.0, 1.0, 0.0))
     err = np.linalg.norm(x.double().cpu().numpy() - ref) / np.linalg.norm(ref)
     assert err < 2e-5, err
